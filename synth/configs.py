@@ -1,0 +1,166 @@
+"""The five synthetic workloads: group, einsum strings, signs, block sizes, value laws.
+
+Pure data.  A tensor with cyclic (or product-of-cyclic) group symmetry is
+described by its sign string (coefficient +1 or -1 per mode), its total charge
+Z, and its block (inner) dimension per mode; every mode has |G| sectors.  The
+stored array is the standard reduced form: sector axes of modes 0..N-2, then
+the inner axes of all N modes, row-major (the layout of the paper's API
+example, Sec. 3).  Values come from ``synth.philox`` keyed by
+(seed, tensor id).
+
+Workloads (shapes taken from the paper's coupled-cluster and tensor-network
+contractions, Sec. 4 and Table 2):
+
+* ``plain_z4``      w_abij = sum_kl u_abkl v_klij, Z_4, every block dim 4.
+* ``ccd_ladder_z8`` w_abij = sum_cd V_abcd T_cdij, Z_8, virtual 24, occupied 6.
+* ``mps_env_z2z3``  E'_{a'b'c'} = E_abc A_{a s a'} W_{b s s' b'} A_{c s' c'},
+                    Z_2 x Z_3, bond 64, MPO bond 4, physical 2, contracted
+                    pairwise left to right.
+* ``ccd_ladder_z16`` the ladder at Z_16, virtual 32, occupied 8.
+* ``mps_env_grad``  the environment chain at bond 128 with L = <E', R>.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+from .philox import DIST_NORMAL, DIST_UNIFORM
+
+DEFAULT_SEED = 20070805
+
+
+@dataclass(frozen=True)
+class Operand:
+    name: str
+    modes: str            # one letter per mode, einsum order
+    signs: str            # '+' / '-' per mode
+    charge: int           # total charge Z as a flattened group element
+    dims: tuple           # block dimension per mode
+    dist: int = DIST_UNIFORM
+    scale: float = 1.0
+    tensor_id: int = 0
+
+    @property
+    def order(self) -> int:
+        return len(self.modes)
+
+
+@dataclass(frozen=True)
+class Contraction:
+    einsum: str           # "u,v->w" over mode letters
+    u: str                # operand names
+    v: str
+    w: str
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    group: tuple          # cyclic factor orders, e.g. (8,) or (2, 3)
+    operands: dict        # name -> Operand (inputs and derived outputs)
+    steps: tuple          # Contraction steps, executed in order
+    inputs: tuple         # names of generated inputs
+    output: str
+    seed: int = DEFAULT_SEED
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def group_size(self) -> int:
+        g = 1
+        for o in self.group:
+            g *= o
+        return g
+
+    def reduced_shape(self, name: str) -> tuple:
+        op = self.operands[name]
+        return (self.group_size,) * (op.order - 1) + tuple(op.dims)
+
+
+def _ladder(name, G, nv, no, cid):
+    ops = {
+        "V": Operand("V", "abcd", "++--", 0, (nv, nv, nv, nv), DIST_NORMAL, 1.0, cid * 16 + 0),
+        "T": Operand("T", "cdij", "++--", 0, (nv, nv, no, no), DIST_NORMAL, 1e-2, cid * 16 + 1),
+        "W": Operand("W", "abij", "++--", 0, (nv, nv, no, no)),
+    }
+    return Workload(name, (G,), ops, (Contraction("abcd,cdij->abij", "V", "T", "W"),),
+                    ("V", "T"), "W")
+
+
+def plain_z4() -> Workload:
+    n = 4
+    ops = {
+        "u": Operand("u", "abkl", "++--", 0, (n, n, n, n), DIST_UNIFORM, 1.0, 0),
+        "v": Operand("v", "klij", "++--", 0, (n, n, n, n), DIST_UNIFORM, 1.0, 1),
+        "w": Operand("w", "abij", "++--", 0, (n, n, n, n)),
+    }
+    return Workload("plain_z4", (4,), ops, (Contraction("abkl,klij->abij", "u", "v", "w"),),
+                    ("u", "v"), "w")
+
+
+def ccd_ladder_z8() -> Workload:
+    return _ladder("ccd_ladder_z8", 8, 24, 6, 1)
+
+
+def ccd_ladder_z16() -> Workload:
+    return _ladder("ccd_ladder_z16", 16, 32, 8, 3)
+
+
+def _mps_env(name, bond, cid, with_r):
+    """E (a-,b-,c-), A (a+,s+,A-), W (b+,s-,S-,B-); every charge 0.
+
+    Every contracted pair carries opposite signs.  The intermediates are
+    T1_{bcsA} (-,-,+,-), T2_{cASB} (-,-,-,-) and E'_{ABC} (-,-,-).
+    """
+    nb, nw, ns = bond, 4, 2
+    ops = {
+        "E": Operand("E", "abc", "---", 0, (nb, nw, nb), DIST_UNIFORM, 1.0, cid * 16 + 0),
+        "A": Operand("A", "asA", "++-", 0, (nb, ns, nb), DIST_UNIFORM, 1.0, cid * 16 + 1),
+        "W": Operand("W", "bsSB", "+---", 0, (nw, ns, ns, nw), DIST_UNIFORM, 1.0, cid * 16 + 2),
+        "T1": Operand("T1", "bcsA", "--+-", 0, (nw, nb, ns, nb)),
+        "T2": Operand("T2", "cASB", "----", 0, (nb, nb, ns, nw)),
+        "Ep": Operand("Ep", "ABC", "---", 0, (nb, nw, nb)),
+    }
+    inputs = ("E", "A", "W")
+    if with_r:
+        ops["R"] = Operand("R", "ABC", "---", 0, (nb, nw, nb), DIST_NORMAL, 1.0, cid * 16 + 3)
+        inputs = inputs + ("R",)
+    steps = (
+        Contraction("abc,asA->bcsA", "E", "A", "T1"),
+        Contraction("bcsA,bsSB->cASB", "T1", "W", "T2"),
+        Contraction("cASB,cSC->ABC", "T2", "A", "Ep"),
+    )
+    return Workload(name, (2, 3), ops, steps, inputs, "Ep")
+
+
+def mps_env_z2z3() -> Workload:
+    return _mps_env("mps_env_z2z3", 64, 2, False)
+
+
+def mps_env_grad() -> Workload:
+    return _mps_env("mps_env_grad", 128, 4, True)
+
+
+ALL = {
+    "plain_z4": plain_z4,
+    "ccd_ladder_z8": ccd_ladder_z8,
+    "mps_env_z2z3": mps_env_z2z3,
+    "ccd_ladder_z16": ccd_ladder_z16,
+    "mps_env_grad": mps_env_grad,
+}
+
+
+def get(name: str) -> Workload:
+    return ALL[name]()
+
+
+def scaled(wl: Workload, dims_map: dict) -> Workload:
+    """A copy of a workload with some block dimensions replaced (for small test cases).
+
+    ``dims_map`` maps a mode letter to its new block dimension; every operand
+    carrying that letter changes consistently.
+    """
+    ops = {}
+    for k, op in wl.operands.items():
+        dims = tuple(dims_map.get(m, d) for m, d in zip(op.modes, op.dims))
+        ops[k] = Operand(op.name, op.modes, op.signs, op.charge, dims, op.dist, op.scale, op.tensor_id)
+    return Workload(wl.name + "_scaled", wl.group, ops, wl.steps, wl.inputs, wl.output, wl.seed,
+                    dict(wl.extra))

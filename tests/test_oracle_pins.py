@@ -1,0 +1,442 @@
+"""Pins of the CPU oracle against things other than its own formulas (no GPU).
+
+Each test ties the oracle to the paper's printed maps, a brute-force search, a
+textbook identity, a library routine or a closed form.  The "planted mistake"
+tests at the end show that plausible bugs in the oracle fail these pins.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from synth import philox
+
+RNG = np.random.default_rng(12345)
+
+
+# ---------------------------------------------------------------------------
+# Input generator
+# ---------------------------------------------------------------------------
+def test_philox_known_answers(golden_dir):
+    rows = [ln.split() for ln in open(os.path.join(golden_dir, "philox4x32_10_kat.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        vals = [int(x, 16) for x in r]
+        out = philox.philox4x32_10(*vals[:6])
+        assert [int(o) for o in out] == vals[6:]
+
+
+def test_uniform_values_exact_and_in_range():
+    e = np.arange(0, 20000, dtype=np.int64)
+    x = philox.values_at(e, 7, 3, philox.DIST_UNIFORM)
+    assert x.min() >= -1.0 and x.max() < 1.0
+    # exactness: recompute from the raw words with Python integers
+    for i in (0, 1, 12345, 19999):
+        w = philox.philox4x32_10(i & 0xFFFFFFFF, i >> 32, 0, 0, 7, 3)
+        k = ((int(w[1]) << 32) | int(w[0])) >> 11
+        assert x[i] == k / 2.0 ** 52 - 1.0
+    assert abs(x.mean()) < 0.02 and abs(x.var() - 1.0 / 3.0) < 0.01
+
+
+def test_normal_values_exact_moments():
+    e = np.arange(0, 50000, dtype=np.int64)
+    x = philox.values_at(e, 11, 5, philox.DIST_NORMAL)
+    for i in (0, 7, 49999):
+        s = 0
+        for d in range(3):
+            s += sum(int(v) for v in philox.philox4x32_10(i, 0, d, 0, 11, 5))
+        assert x[i] == s / 2.0 ** 32 - 6.0
+    assert abs(x.mean()) < 0.02 and abs(x.var() - 1.0) < 0.03
+    y = philox.values_at(e[:100], 11, 5, philox.DIST_NORMAL, 1e-2)
+    assert np.array_equal(y, x[:100] * np.float64(1e-2))
+
+
+# ---------------------------------------------------------------------------
+# Group arithmetic
+# ---------------------------------------------------------------------------
+def test_cyclic_group_is_addition_mod_g():
+    for G in (1, 2, 5, 8):
+        g = O.Group(G)
+        for a in range(G):
+            for b in range(G):
+                assert g.add(a, b) == (a + b) % G
+                assert g.sub(a, b) == (a - b) % G
+            assert g.neg(a) == (-a) % G
+
+
+def test_z2xz3_isomorphic_to_z6_by_crt():
+    g = O.Group((2, 3))
+    phi = {e: (3 * g.digits(e)[0] + 4 * g.digits(e)[1]) % 6 for e in range(6)}
+    assert sorted(phi.values()) == list(range(6))
+    for a in range(6):
+        for b in range(6):
+            assert phi[g.add(a, b)] == (phi[a] + phi[b]) % 6
+            assert phi[g.neg(a)] == (-phi[a]) % 6
+
+
+def test_implicit_sector_is_the_unique_brute_force_solution():
+    for orders in ((3,), (4,), (2, 3), (2, 2)):
+        g = O.Group(orders)
+        G = g.size
+        for N in (1, 2, 3, 4):
+            for _ in range(10):
+                signs = tuple(int(s) for s in RNG.choice([-1, 1], N))
+                Z = int(RNG.integers(G))
+                sym = O.Sym(signs, Z, (1,) * N, g)
+                for pos in range(N):
+                    known = tuple(int(x) for x in RNG.integers(G, size=N - 1))
+                    sols = []
+                    for cand in range(G):
+                        secs = list(known)
+                        secs.insert(pos, cand)
+                        # brute-force rule check, digit by digit
+                        ok = all(sum(c * g.digits(s)[f] for c, s in zip(signs, secs)) % orders[f]
+                                 == g.digits(Z)[f] for f in range(len(orders)))
+                        if ok:
+                            sols.append(cand)
+                    assert sols == [O.implicit_sector(sym, known, position=pos)]
+
+
+# ---------------------------------------------------------------------------
+# The paper's worked example (Sec. 2.1) at G = 3
+# ---------------------------------------------------------------------------
+def _example_rows(golden_dir, kind):
+    out = []
+    for ln in open(os.path.join(golden_dir, "sec21_example_maps_z3.txt")):
+        p = ln.split()
+        if p and p[0] == kind:
+            k = p.index("->")
+            out.append(([int(x) for x in p[1:k]], [int(x) for x in p[k + 1:]]))
+    return out
+
+
+def test_standard_form_maps_of_the_example(golden_dir):
+    g = O.Group(3)
+    w = O.Sym.make("++--", 0, (1, 1, 1, 1), g)
+    rows = _example_rows(golden_dir, "std")
+    assert len(rows) == 27
+    for (A, I, J), (B,) in rows:
+        assert O.implicit_sector(w, (A, I, J), position=1) == B
+    for (A, B, I, K), (J, L) in _example_rows(golden_dir, "alg1"):
+        assert O.implicit_sector(w, (A, B, I)) == J        # w's last mode
+        assert O.implicit_sector(w, (A, B, K)) == L        # u_abkl has the same rule
+
+
+def test_aligned_form_maps_of_the_example(golden_dir):
+    """Alignment deltas reproduce Sec. 2.1's maps with Q_alg = -Q_example (Q = sum c^U_K K)."""
+    g = O.Group(3)
+    su = O.Sym.make("++--", 0, (1, 1, 1, 1), g)
+    sv = O.Sym.make("++--", 0, (1, 1, 1, 1), g)
+    d1, d2, d3 = O.alignment_deltas("abkl,klij->abij", su, sv)
+    rows = _example_rows(golden_dir, "aligned")
+    assert len(rows) == 81
+    for (Q, A, J, L), (B, I, K) in rows:
+        q = (-Q) % 3
+        assert d1[A, B, q] == 1 and d1[A].sum(axis=0)[q] == 1     # B = Q - A, unique
+        assert d3[I, J, q] == 1 and d3[:, J, q].sum() == 1         # I = Q - J, unique
+        assert d2[K, L, q] == 1 and d2[:, L, q].sum() == 1         # K = Q - L, unique
+
+
+def test_footnote_rank3_reduced_form():
+    """Sec. 2.1 footnote: r_{i,I,j,J,k} = t_{i,I,j,J,k,I+J} for I + J - K == 0."""
+    G, n = 3, 2
+    g = O.Group(G)
+    sym = O.Sym.make("++-", 0, (n, n, n), g)
+    T = np.zeros((G * n,) * 3)
+    for I, J, K in itertools.product(range(G), repeat=3):
+        if (I + J - K) % G == 0:
+            T[I * n:(I + 1) * n, J * n:(J + 1) * n, K * n:(K + 1) * n] = RNG.standard_normal((n, n, n))
+    R, zero_ok = O.reduce_full(T, sym)
+    assert zero_ok
+    for I, J in itertools.product(range(G), repeat=2):
+        K = (I + J) % G
+        assert np.array_equal(R[I, J], T[I * n:(I + 1) * n, J * n:(J + 1) * n, K * n:(K + 1) * n])
+    assert np.array_equal(O.expand(R, sym), T)
+
+
+# ---------------------------------------------------------------------------
+# The five forms agree; brute force on tiny inputs
+# ---------------------------------------------------------------------------
+def _random_case(rng, orders, s, t, v, nmax=2, sigma=None):
+    g = O.Group(orders)
+    G = g.size
+    letters = iter("abcdefghijklmnop")
+    I = [next(letters) for _ in range(s)]
+    K = [next(letters) for _ in range(v)]
+    J = [next(letters) for _ in range(t)]
+    tu = list(I + K)
+    rng.shuffle(tu)
+    tv = list(K + J)
+    rng.shuffle(tv)
+    tw = list(I + J)
+    rng.shuffle(tw)
+    dims = {m: int(rng.integers(1, nmax + 1)) for m in I + K + J}
+    sign_u = {m: int(rng.choice([-1, 1])) for m in tu}
+    sigma = int(rng.choice([-1, 1])) if sigma is None else sigma
+    sign_v = {m: (sigma * sign_u[m] if m in K else int(rng.choice([-1, 1]))) for m in tv}
+    su = O.Sym(tuple(sign_u[m] for m in tu), int(rng.integers(G)), tuple(dims[m] for m in tu), g)
+    sv = O.Sym(tuple(sign_v[m] for m in tv), int(rng.integers(G)), tuple(dims[m] for m in tv), g)
+    sub = f"{''.join(tu)},{''.join(tv)}->{''.join(tw)}"
+    Ru = rng.standard_normal(su.reduced_shape())
+    Rv = rng.standard_normal(sv.reduced_shape())
+    return sub, Ru, su, Rv, sv
+
+
+@pytest.mark.parametrize("orders", [(2,), (3,), (2, 2)])
+@pytest.mark.parametrize("stv", [(1, 1, 1), (2, 1, 1), (1, 2, 1), (1, 1, 2), (2, 1, 2)])
+def test_forms_agree_with_brute_force(orders, stv):
+    rng = np.random.default_rng(hash((orders, stv)) % 2 ** 32)
+    s, t, v = stv
+    for sigma in (-1, 1):
+        sub, Ru, su, Rv, sv = _random_case(rng, orders, s, t, v, sigma=sigma)
+        Rb, swb, zb = O.contract_bruteforce(sub, Ru, su, Rv, sv)
+        assert zb, "brute-force output violates the derived conservation rule"
+        Rd, swd, zd = O.contract_dense(sub, Ru, su, Rv, sv)
+        Rk, swk = O.contract_blocks(sub, Ru, su, Rv, sv)
+        Ra, swa, *_ = O.contract_irrep_aligned(sub, Ru, su, Rv, sv)
+        assert zd
+        for R in (Rd, Rk, Ra):
+            np.testing.assert_allclose(R, Rb, rtol=1e-13, atol=1e-13)
+        # every allowed block is generically nonzero: the derived rule is not too strict
+        Wf = O.expand(Rb, swb)
+        nz = 0
+        for secs in itertools.product(range(su.group.size), repeat=swb.order):
+            if O.allowed(swb, secs):
+                sl = tuple(slice(S * n, (S + 1) * n) for S, n in zip(secs, swb.dims))
+                nz += int(np.any(Wf[sl] != 0))
+        assert nz == su.group.size ** (swb.order - 1)
+
+
+def test_larger_random_contractions_dense_blocks_aligned():
+    rng = np.random.default_rng(99)
+    for orders, stv in (((4,), (2, 2, 2)), ((2, 3), (2, 2, 1)), ((5,), (1, 3, 2)), ((3,), (3, 1, 2))):
+        sub, Ru, su, Rv, sv = _random_case(rng, orders, *stv, nmax=3)
+        Rd, sw, zd = O.contract_dense(sub, Ru, su, Rv, sv)
+        Rk, _ = O.contract_blocks(sub, Ru, su, Rv, sv)
+        Ra, _, Ual, Val, Wal = O.contract_irrep_aligned(sub, Ru, su, Rv, sv)
+        assert zd
+        np.testing.assert_allclose(Rk, Rd, rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(Ra, Rd, rtol=1e-12, atol=1e-12)
+        G, M, Kd, N = O.aligned_shape(sub, su, sv)
+        assert Ual.shape == (G, M, Kd) and Val.shape == (G, Kd, N) and Wal.shape == (G, M, N)
+        # the alignment is a bijection of stored elements: same multiset of values
+        assert np.array_equal(np.sort(Ual.ravel()), np.sort(np.asarray(Ru).ravel()))
+        assert np.array_equal(np.sort(Val.ravel()), np.sort(np.asarray(Rv).ravel()))
+
+
+def test_sampled_form_matches_dense():
+    rng = np.random.default_rng(5)
+    sub, Ru, su, Rv, sv = _random_case(rng, (4,), 2, 2, 2, nmax=3)
+    Rd, sw, _ = O.contract_dense(sub, Ru, su, Rv, sv)
+    Wf = O.expand(Rd, sw)
+    pos = np.stack([rng.integers(0, d, 40) for d in Wf.shape], axis=1)
+    got = O.sample_contract(sub, su, sv, O.reduced_value_fn(Ru, su), O.reduced_value_fn(Rv, sv), pos)
+    np.testing.assert_allclose(got, Wf[tuple(pos.T)], rtol=1e-12, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Special cases that reduce to textbook or library routines
+# ---------------------------------------------------------------------------
+def test_trivial_group_is_plain_einsum():
+    rng = np.random.default_rng(3)
+    g = O.Group(1)
+    su = O.Sym.make("+-+", 0, (3, 4, 5), g)
+    sv = O.Sym.make("-+", 0, (5, 2), g)
+    Ru = rng.standard_normal(su.reduced_shape())
+    Rv = rng.standard_normal(sv.reduced_shape())
+    sub = "abk,kj->ajb"
+    ref = np.einsum(sub, Ru.reshape(3, 4, 5), Rv.reshape(5, 2))
+    for R in (O.contract_dense(sub, Ru, su, Rv, sv)[0], O.contract_blocks(sub, Ru, su, Rv, sv)[0],
+              O.contract_irrep_aligned(sub, Ru, su, Rv, sv)[0]):
+        np.testing.assert_allclose(R.reshape(ref.shape), ref, rtol=1e-13, atol=1e-13)
+
+
+def test_matrix_product_is_block_diagonal_gemm():
+    import scipy.linalg
+    rng = np.random.default_rng(4)
+    G, n = 5, 3
+    g = O.Group(G)
+    su = O.Sym.make("+-", 0, (n, n), g)
+    sv = O.Sym.make("+-", 0, (n, n), g)
+    Ru = rng.standard_normal(su.reduced_shape())
+    Rv = rng.standard_normal(sv.reduced_shape())
+    ref = scipy.linalg.block_diag(*Ru) @ scipy.linalg.block_diag(*Rv)
+    for R, sw in (O.contract_dense("ij,jk->ik", Ru, su, Rv, sv)[:2],
+                  O.contract_blocks("ij,jk->ik", Ru, su, Rv, sv),
+                  O.contract_irrep_aligned("ij,jk->ik", Ru, su, Rv, sv)[:2]):
+        np.testing.assert_allclose(O.expand(R, sw), ref, rtol=1e-13, atol=1e-13)
+
+
+def test_product_group_equals_z6_after_crt_relabelling():
+    rng = np.random.default_rng(6)
+    g23, g6 = O.Group((2, 3)), O.Group(6)
+    phi = np.array([(3 * g23.digits(e)[0] + 4 * g23.digits(e)[1]) % 6 for e in range(6)])
+    sub = "abc,asA->bcsA"
+    su = O.Sym.make("---", 2, (2, 1, 2), g23)
+    sv = O.Sym.make("++-", 5, (2, 1, 2), g23)
+    Ru = rng.standard_normal(su.reduced_shape())
+    Rv = rng.standard_normal(sv.reduced_shape())
+
+    def relabel(R, order):
+        out = np.empty_like(R)
+        for secs in itertools.product(range(6), repeat=order - 1):
+            out[tuple(phi[list(secs)])] = R[secs]
+        return out
+
+    su6 = O.Sym(su.signs, int(phi[su.charge]), su.dims, g6)
+    sv6 = O.Sym(sv.signs, int(phi[sv.charge]), sv.dims, g6)
+    W23, sw23 = O.contract_blocks(sub, Ru, su, Rv, sv)
+    W6, sw6 = O.contract_blocks(sub, relabel(Ru, 3), su6, relabel(Rv, 3), sv6)
+    assert sw6.charge == phi[sw23.charge]
+    np.testing.assert_allclose(W6, relabel(W23, 4), rtol=1e-13, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# Costs (paper Sec. 2.1, Alg. 2 li:contra, Table 1)
+# ---------------------------------------------------------------------------
+def test_flop_counts_closed_forms():
+    for G, n in ((4, 4), (8, 3), (3, 5)):
+        g = O.Group(G)
+        s4 = O.Sym.make("++--", 0, (n,) * 4, g)
+        assert O.flop_count("abkl,klij->abij", s4, s4) == 2 * n ** 6 * G ** 4     # Sec. 2.1
+        s2 = O.Sym.make("+-", 0, (n, n), g)
+        assert O.flop_count("ij,jk->ik", s2, s2) == 2 * G * n ** 3                 # Table 1, MM
+        s3 = O.Sym.make("++-", 0, (n, n, n), g)
+        s3v = O.Sym.make("+--", 0, (n, n, n), g)
+        assert O.flop_count("ijk,klm->ijlm", s3, s3v) == 2 * G ** 3 * n ** 5       # Table 1, MPS
+    # plain_z4 workload: 2 n^6 G^4 = 2 097 152
+    s = O.Sym.make("++--", 0, (4,) * 4, O.Group(4))
+    assert O.flop_count("abkl,klij->abij", s, s) == 2_097_152
+
+
+def test_flop_count_equals_brute_force_count_of_nonzero_terms():
+    rng = np.random.default_rng(8)
+    for orders, stv in (((3,), (1, 1, 1)), ((2,), (2, 1, 2)), ((2, 2), (1, 2, 1)), ((3,), (2, 2, 1))):
+        sub, Ru, su, Rv, sv = _random_case(rng, orders, *stv)
+        tu, tv, tw, I, K, J = O.parse_einsum(sub)
+        size = {}
+        for t, sym in ((tu, su), (tv, sv)):
+            for p, m in enumerate(t):
+                size[m] = sym.group.size * sym.dims[p]
+        count = 0
+        for wi in itertools.product(*[range(size[m]) for m in tw]):
+            idx = dict(zip(tw, wi))
+            for ki in itertools.product(*[range(size[m]) for m in K]):
+                idx.update(zip(K, ki))
+                cu = tuple(idx[m] // su.dims[p] for p, m in enumerate(tu))
+                cv = tuple(idx[m] // sv.dims[p] for p, m in enumerate(tv))
+                count += O.allowed(su, cu) and O.allowed(sv, cv)
+        assert 2 * count == O.flop_count(sub, su, sv)
+
+
+# ---------------------------------------------------------------------------
+# Workload definitions are consistent with the derived output rule
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", list(synth.configs.ALL))
+def test_workload_output_signs_are_the_derived_ones(name):
+    wl = synth.configs.get(name)
+    g = O.Group(wl.group)
+    for st in wl.steps:
+        ou, ov, ow = (wl.operands[x] for x in (st.u, st.v, st.w))
+        su = O.Sym.make(ou.signs, ou.charge, ou.dims, g)
+        sv = O.Sym.make(ov.signs, ov.charge, ov.dims, g)
+        sw = O.Sym.make(ow.signs, ow.charge, ow.dims, g)
+        assert O.same_symmetry(O.output_symmetry(st.einsum, su, sv), sw)
+
+
+# ---------------------------------------------------------------------------
+# bfloat16 rounding against the library conversion
+# ---------------------------------------------------------------------------
+def test_bf16_round_matches_torch():
+    import torch
+    x = np.concatenate([RNG.standard_normal(20000), RNG.standard_normal(2000) * 1e-30,
+                        RNG.standard_normal(2000) * 1e30]).astype(np.float32)
+    # ties: values exactly half-way between two bf16 numbers
+    ties = (np.arange(1, 2000, dtype=np.uint32) << 16 | np.uint32(0x8000)).view(np.float32)
+    x = np.concatenate([x, ties, -ties])
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+    assert np.array_equal(O.bf16_round(x), ref)
+    hi, lo = O.bf16_split(x[:20000])
+    assert np.array_equal(O.bf16_round(hi), hi) and np.array_equal(O.bf16_round(lo), lo)
+    err = np.abs(x[:20000].astype(np.float64) - hi - lo) / np.abs(x[:20000])
+    assert err.max() <= 2.0 ** -16
+
+
+# ---------------------------------------------------------------------------
+# Planted mistakes: each must make at least one pin fail
+# ---------------------------------------------------------------------------
+def _pins_pass(monkeypatch_ctx=None):
+    rng = np.random.default_rng(77)
+    try:
+        for orders, stv in (((3,), (1, 1, 1)), ((2, 2), (2, 1, 1)), ((3,), (1, 2, 2))):
+            for sigma in (-1, 1):
+                sub, Ru, su, Rv, sv = _random_case(rng, orders, *stv, sigma=sigma)
+                Rb, _, zb = O.contract_bruteforce(sub, Ru, su, Rv, sv)
+                Rd, _, zd = O.contract_dense(sub, Ru, su, Rv, sv)
+                Rk, _ = O.contract_blocks(sub, Ru, su, Rv, sv)
+                Ra, *_ = O.contract_irrep_aligned(sub, Ru, su, Rv, sv)
+                if not (zb and zd):
+                    return False
+                for R in (Rd, Rk, Ra):
+                    if not np.allclose(R, Rb, rtol=1e-12, atol=1e-12):
+                        return False
+    except (AssertionError, ValueError, IndexError):
+        return False
+    return True
+
+
+def test_pins_pass_unmodified():
+    assert _pins_pass()
+
+
+def test_planted_sign_error_in_output_rule_is_caught(monkeypatch):
+    import oracle.symcontract as S
+    real = S.output_symmetry
+
+    def wrong(sub, su, sv):
+        w = real(sub, su, sv)
+        return S.Sym(w.signs, w.group.add(w.charge, 1), w.dims, w.group)   # Z^U + sigma Z^V + 1
+    monkeypatch.setattr(S, "output_symmetry", wrong)
+    assert not _pins_pass()
+
+
+def test_planted_dropped_coefficient_in_implicit_sector_is_caught(monkeypatch):
+    import oracle.symcontract as S
+
+    def wrong(sym, known, position=None):
+        g = sym.group
+        p = sym.order - 1 if position is None else position
+        others = [c for m, c in enumerate(sym.signs) if m != p]
+        return g.sub(sym.charge, g.total(others, known))      # forgets to multiply by c_p
+    monkeypatch.setattr(S, "implicit_sector", wrong)
+    assert not _pins_pass()
+
+
+def test_planted_wrong_q_sign_in_delta3_is_caught(monkeypatch):
+    import oracle.symcontract as S
+    real = S.alignment_deltas
+
+    def wrong(sub, su, sv):
+        d1, d2, d3 = real(sub, su, sv)
+        tu, tv, tw, I, K, J = S.parse_einsum(sub)
+        d3w = S.kron_delta(su.group, [sv.signs[tv.index(m)] for m in J], +1, sv.charge)  # ignores sigma
+        return d1, d2, d3w
+    monkeypatch.setattr(S, "alignment_deltas", wrong)
+    assert not _pins_pass()
+
+
+def test_planted_transposed_block_product_is_caught(monkeypatch):
+    import oracle.symcontract as S
+    real_einsum = np.einsum
+
+    def wrong(*args, **kw):
+        out = real_einsum(*args, **kw)
+        if isinstance(args[0], str) and "->" in args[0] and out.ndim >= 2 and out.shape[0] == out.shape[1]:
+            out = np.swapaxes(out, 0, 1)
+        return out
+    monkeypatch.setattr(S.np, "einsum", wrong)
+    assert not _pins_pass()
