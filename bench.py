@@ -1,0 +1,193 @@
+"""Throughput of the irrep-alignment contraction on one MI355X.
+
+One step = the whole hot path on one batch of synthetic input already resident
+in HBM: align V_abcd, align T_cdij, one sector-batched FP64 product, unalign
+W_abij -- the coupled-cluster particle-particle ladder w_abij = sum_cd
+V_abcd T_cdij with Z_8 symmetry, virtual block 24, occupied block 6.
+
+Prints one JSON line: effective GFLOP/s (algorithmic flops of allowed blocks
+only, 2 |G| M K N, divided by the measured step time), the roofline of the
+dominant kernel (the sector product; its duration from HIP events the library
+records around each launch on the stream it launches on), and the CPU oracle's
+rate on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--extra PATH]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0}     # dense MFMA TFLOP/s, MI355X
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "ccd_ladder_z8"
+
+
+def source_digest(*rel):
+    h = hashlib.sha256()
+    for r in rel:
+        with open(os.path.join(ROOT, r), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def gemm_traffic(kernel_key, digest):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if still current."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(kernel_key)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_digest") != digest:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(wl, budget_s=12.0):
+    """Loop-over-blocks oracle on a sample of V's stored blocks, timed on the host cores."""
+    import numpy as np
+    import oracle as O
+    import synth
+    from synth import philox
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:  # noqa: BLE001
+        cores = os.cpu_count() or 1
+    st = wl.steps[0]
+    g = O.Group(wl.group)
+    ou, ov = wl.operands[st.u], wl.operands[st.v]
+    su = O.Sym.make(ou.signs, ou.charge, ou.dims, g)
+    sv = O.Sym.make(ov.signs, ov.charge, ov.dims, g)
+    G = g.size
+    Rv = synth.host_input(wl, st.v)                       # T: 10.6 M elements
+    Ru = np.zeros(wl.reduced_shape(st.u))
+    blk = int(np.prod(ou.dims))
+    all_blocks = [(a, b, c) for a in range(G) for b in range(G) for c in range(G)]
+    done_blocks, flops_per_block = 0, 2 * blk * int(np.prod(ov.dims[2:])) * G
+    elapsed = 0.0
+    i = 0
+    while i < len(all_blocks) and elapsed < budget_s:
+        batch = all_blocks[i:i + 8]
+        for b in batch:                                   # generate the sampled V blocks
+            lin = np.ravel_multi_index(b, (G, G, G)) * blk
+            Ru[b] = philox.values_at(np.arange(lin, lin + blk), wl.seed, ou.tensor_id, ou.dist,
+                                     ou.scale).reshape(ou.dims)
+        t0 = time.perf_counter()
+        O.contract_blocks(st.einsum, Ru, su, Rv, sv, u_blocks=batch)
+        elapsed += time.perf_counter() - t0
+        done_blocks += len(batch)
+        i += len(batch)
+    gflops = done_blocks * flops_per_block / elapsed / 1e9
+    return {"value": round(gflops, 3), "unit": "GFLOP/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"loop-over-blocks oracle (numpy FP64) over {done_blocks} of {len(all_blocks)} "
+                      f"stored blocks of V_abcd against all of T_cdij, {elapsed:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--extra", default="", help="write per-kernel details to this JSON file")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the contraction is benchmarked on a single MI355X "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2007_08056_amd as P
+    import synth
+    import synth.gpu as SG
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    wl = synth.configs.get(WORKLOAD)
+    st = wl.steps[0]
+    ou, ov, ow = (wl.operands[x] for x in (st.u, st.v, st.w))
+    u = P.SymTensor(SG.device_input(wl, st.u, device=dev), ou.signs, ou.charge, wl.group)
+    v = P.SymTensor(SG.device_input(wl, st.v, device=dev), ov.signs, ov.charge, wl.group)
+    w = P.output_like(st.einsum, u, v)
+    info = P.plan(st.einsum, u, v, "f64", w)
+    ws = torch.empty(info.workspace_bytes, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        P.contract_into(st.einsum, u, v, w, "f64", ws)
+    torch.cuda.synchronize()
+    P.read_timing(0)
+    P.set_timing(0, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        P.contract_into(st.einsum, u, v, w, "f64", ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    P.set_timing(0, False)
+    ms, launches = P.read_timing(0)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = info.flops / (ms_step * 1e-3) / 1e9
+
+    gemm_ms = ms[2] / max(1, launches[2])
+    achieved = info.flops / (gemm_ms * 1e-3) / 1e12
+    digest = source_digest("paper_2007_08056_amd/csrc/gemm.hip")
+    traffic = gemm_traffic("sector_gemm_f64_ccd_ladder_z8", digest)
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["f64"], "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK["f64"], 4), "traffic": traffic}
+
+    extra = {
+        "kernel_ms_per_launch": {name: (ms[i] / launches[i] if launches[i] else None)
+                                 for i, name in enumerate(("align_u", "align_v", "sector_gemm", "unalign_w"))},
+        "shape": {"batch": info.group_size, "m": info.m, "k": info.k, "n": info.n},
+        "flops": info.flops,
+        "bytes_u": info.elems_u * 8, "bytes_v": info.elems_v * 8, "bytes_w": info.elems_w * 8,
+        "gemm_source_digest": digest,
+    }
+    xf = extra["kernel_ms_per_launch"]
+    for key, nbytes in (("align_u", 2 * info.elems_u * 8), ("align_v", 2 * info.elems_v * 8),
+                        ("unalign_w", 2 * info.elems_w * 8)):
+        if xf[key]:
+            extra[key + "_GBs"] = nbytes / (xf[key] * 1e-3) / 1e9
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(wl)
+
+    line = {
+        "metric": "effective GFLOP/s of symmetric contraction (fwd) vs FP64 plain",
+        "value": round(value, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded Philox4x32-10, N(0,1) V, 1e-2 N(0,1) T)",
+        "config": {"workload": "ccd_ladder_z8: w_abij = sum_cd V_abcd T_cdij, Z_8, virtual block 24, "
+                               "occupied block 6, FP64; aligned product 8 x (4608 x 4608 x 288)",
+                   "group": "Z_8", "einsum": st.einsum, "flops_per_step": info.flops},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    if args.extra:
+        with open(args.extra, "w") as f:
+            json.dump(extra, f, indent=1)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,212 @@
+/*
+ * symtensor.h -- C ABI of the irreducible-representation-alignment contraction
+ * for tensors with cyclic-group (Z_G) or product-of-cyclic-group symmetry,
+ * built for AMD Instinct MI355X (gfx950).
+ *
+ * The method (Gao, Helms, Chan, Solomonik, "Automatic transformation of
+ * irreducible representations for efficient contraction of tensors with cyclic
+ * group symmetry"):
+ *   (a) each operand's standard reduced form is remapped into an aligned
+ *       reduced form indexed by an auxiliary sector Q (Sec. 2.1 "aligned"
+ *       maps; Alg. 2, step li:rf);
+ *   (b) one dense product per Q value contracts the aligned forms (Sec. 2.1,
+ *       einsum "AQL,LQJ->AQJ"; Alg. 2, step li:contra);
+ *   (c) the aligned output is remapped to the standard reduced form of W
+ *       (Alg. 2, final step).
+ *
+ * Tensor model (Sec. 2.2, Eq. symtsr).  An order-N operand has modes
+ * m = 0..N-1, each with |G| sectors and a block (inner) dimension n_m.  With
+ * coefficients c_m in {+1,-1} (the sign string) and a total charge Z, element
+ * (I_0 i_0, ..., I_{N-1} i_{N-1}) may be nonzero only if
+ * sum_m c_m I_m == Z in G.  G = Z_{g_1} x ... x Z_{g_f}; a group element is an
+ * int in [0,|G|), mixed radix with the first factor most significant, added
+ * component-wise.  The STANDARD REDUCED FORM is the row-major array
+ *     [|G|]^(N-1) x n_0 x n_1 x ... x n_{N-1}
+ * holding the sectors of modes 0..N-2 and every in-block index; the sector of
+ * mode N-1 is the one the rule implies (layout of the API example, Sec. 3).
+ *
+ * Contractions (Eq. ctr).  "tu,tv->tw" with one letter per mode.  Letters of
+ * tu also in tw form I (s modes), of tu also in tv form K (v contracted
+ * modes), of tv also in tw form J (t modes).  Every letter sits in exactly two
+ * terms; s, t, v >= 1.  The contracted modes must carry the same coefficient
+ * ratio sigma = c^V_k / c^U_k for every k (sigma = +1 is Alg. 2's assumption;
+ * sigma = -1 is the worked example of Sec. 2.1).  The output's rule is then
+ * c^W = (c^U_I, -sigma c^V_J) in tw order and Z^W = Z^U - sigma Z^V (proof of
+ * Sec. 2.3); (c^W, Z^W) and (-c^W, -Z^W) are the same rule and both are
+ * accepted.
+ *
+ * ALIGNED LAYOUTS (produced by step (a), consumed by (b), fixed by this ABI).
+ * Group orders: I and K in tu order, J in tv order.  The implicit (unstored)
+ * sector of each group is its last mode.  Q = sum_{k in K} c^U_k K_k.
+ *   U_al[Q][I stored sectors][I inner][K stored sectors][K inner]  -> (|G|, M, Kd)
+ *   V_al[Q][K stored sectors][K inner][J stored sectors][J inner]  -> (|G|, Kd, N)
+ *   W_al[Q][I stored sectors][I inner][J stored sectors][J inner]  -> (|G|, M, N)
+ * with M = |G|^(s-1) prod n_I, Kd = |G|^(v-1) prod n_K, N = |G|^(t-1) prod n_J.
+ * Implicit sectors: last I from sum c^U_I I + Q == Z^U; last K from
+ * sum c^U_K K == Q; last J from sum c^V_J J + sigma Q == Z^V.
+ * Per compute mode the aligned buffers hold:
+ *   SYMT_COMPUTE_F64    U_al f64 (|G|,M,Kd) row-major; V_al f64 (|G|,Kd,N); W_al f64 (|G|,M,N)
+ *   SYMT_COMPUTE_F32    the same shapes in f32
+ *   SYMT_COMPUTE_BF16X3 U_al = two bf16 planes hi then lo, each (|G|,M,Kd);
+ *                       V_al = two bf16 planes hi then lo, each (|G|,N,Kd) (Kd fastest);
+ *                       W_al f64 (|G|,M,N).
+ *   hi = bf16(x), lo = bf16(x - hi), x taken in binary32, both rounded to
+ *   nearest even; the product is hi*hi + hi*lo + lo*hi with binary32
+ *   accumulation (two accumulators) and a binary64 sum of the two at the end.
+ *
+ * Execution and ownership.  Every device buffer (operand data, workspace,
+ * aligned buffers) is allocated and owned by the caller.  A context holds only
+ * host state; it allocates no device memory.  Functions taking a stream
+ * (a hipStream_t passed as void*, NULL = the null stream) enqueue their
+ * kernels on it and return without synchronising.  All validation happens on
+ * the host before the first launch: on any error no kernel is launched and no
+ * output byte is written.  A kernel fault surfaces at the caller's next
+ * synchronisation.  A context must not be used by two threads at once.
+ *
+ * Return values: SYMT_OK (0) or one of the negative codes below; the detail of
+ * the last failure on a context is in symtensor_last_error().
+ */
+#ifndef SYMTENSOR_H
+#define SYMTENSOR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SYMT_MAX_FACTORS 4   /* cyclic factors of G */
+#define SYMT_MAX_ORDER 12    /* modes per operand */
+
+enum {
+  SYMT_OK = 0,
+  SYMT_EINVAL = -1,        /* null pointer, negative or mismatched sizes, bad group */
+  SYMT_EEINSUM = -2,       /* malformed subscripts, repeated letter in a term, a letter in
+                              all three terms or in only one, s, t or v = 0 */
+  SYMT_ESYM = -3,          /* mixed sign ratio over contracted modes, W's rule differs from the
+                              derived one, bad sign string or charge */
+  SYMT_EDTYPE = -4,        /* unsupported storage dtype / compute mode pair */
+  SYMT_EWORKSPACE = -5,    /* workspace or aligned buffer too small */
+  SYMT_EALIAS = -6,        /* output overlaps an input */
+  SYMT_EUNSUPPORTED = -7,  /* valid request outside this library's support */
+  SYMT_EHIP = -8           /* HIP runtime error (launch, device query) */
+};
+
+typedef enum { SYMT_F64 = 0, SYMT_F32 = 1 } symt_dtype;
+typedef enum {
+  SYMT_COMPUTE_F64 = 0,    /* binary64 MFMA products */
+  SYMT_COMPUTE_F32 = 1,    /* binary32 MFMA products, binary32 accumulation */
+  SYMT_COMPUTE_BF16X3 = 2  /* split-bfloat16 three-term products (see above) */
+} symt_compute;
+
+/* G = Z_order[0] x ... x Z_order[nfactors-1]; 1 <= nfactors <= SYMT_MAX_FACTORS. */
+typedef struct {
+  int32_t nfactors;
+  int32_t order[SYMT_MAX_FACTORS];
+} symt_group;
+
+/* One operand.  `signs` holds nmodes characters '+' / '-' (c_m, einsum-term
+ * order); `charge` is Z in [0,|G|); `dims` holds the nmodes block sizes n_m
+ * (each >= 0); `data` is a device pointer to the standard reduced form in
+ * `dtype`, or NULL when the tensor has no elements or is only being planned. */
+typedef struct {
+  int32_t nmodes;
+  const char* signs;
+  int32_t charge;
+  const int64_t* dims;
+  int32_t dtype;           /* symt_dtype */
+  void* data;
+} symt_tensor;
+
+/* Result of planning one contraction (host-only, no device needed). */
+typedef struct {
+  int32_t s, t, v;                 /* modes of I, J, K */
+  int32_t sigma;                   /* c^V_k / c^U_k */
+  int32_t group_size;              /* |G| = batch of the aligned product */
+  int64_t m, k, n;                 /* aligned product shape per Q */
+  int64_t elems_u, elems_v, elems_w;
+  double flops;                    /* 2 |G| m k n: multiply-adds of allowed blocks only */
+  size_t bytes_u_al, bytes_v_al, bytes_w_al;  /* aligned buffer sizes for this compute mode */
+  size_t workspace_bytes;          /* what symtensor_contract needs */
+  char w_signs[SYMT_MAX_ORDER + 1];/* derived output sign string (tw order), NUL-terminated */
+  int32_t w_charge;                /* derived output charge */
+} symt_plan_info;
+
+typedef struct symt_ctx symt_ctx;
+
+/* Create a context bound to HIP device `device` (it becomes current on the
+ * calling thread).  *out receives the context; SYMT_EHIP if the device does
+ * not exist. */
+int symtensor_create(symt_ctx** out, int device);
+
+/* Destroy a context; NULL is a no-op.  Does not synchronise any stream. */
+int symtensor_destroy(symt_ctx* ctx);
+
+/* Validate a contraction and report its shapes, flops, derived output rule and
+ * workspace size (Alg. 2 steps li:coeff to li:delta).  Host-only: operand
+ * `data` pointers are not read.  `w` may be NULL, in which case only the
+ * derived rule is reported.  `compute` is a symt_compute. */
+int symtensor_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
+                   const symt_tensor* v, const symt_tensor* w, int32_t compute,
+                   symt_plan_info* info);
+
+/* Workspace bytes needed by symtensor_contract (same as info.workspace_bytes). */
+int symtensor_workspace_size(const char* einsum, const symt_group* group, const symt_tensor* u,
+                             const symt_tensor* v, const symt_tensor* w, int32_t compute,
+                             size_t* bytes);
+
+/* W = contraction of U and V (Eq. ctr), written over w->data in W's standard
+ * reduced form: steps (a), (b), (c) above, enqueued on `stream`.  `workspace`
+ * is a caller-owned device buffer of at least info.workspace_bytes bytes
+ * holding U_al, V_al and W_al (256-byte aligned sub-buffers, in that order).
+ * w->data must not overlap u->data, v->data or the workspace (SYMT_EALIAS).
+ * Storage dtypes: SYMT_COMPUTE_F64 takes any mix of F64/F32 operands
+ * (converted exactly to binary64); SYMT_COMPUTE_F32 and BF16X3 take any mix,
+ * F64 inputs being rounded to binary32 first. */
+int symtensor_contract(symt_ctx* ctx, const char* einsum, const symt_group* group,
+                       const symt_tensor* u, const symt_tensor* v, const symt_tensor* w,
+                       int32_t compute, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Step (a) alone: write the aligned form of U (operand = 0) or V (operand = 1)
+ * for this contraction into the caller's device buffer `aligned`
+ * (at least info.bytes_u_al / bytes_v_al bytes), in the layout of the compute
+ * mode (see ALIGNED LAYOUTS).  Pure data movement for F64/F32: bit-exact. */
+int symtensor_align(symt_ctx* ctx, const char* einsum, const symt_group* group,
+                    const symt_tensor* u, const symt_tensor* v, const symt_tensor* w,
+                    int32_t compute, int32_t operand, void* aligned, size_t aligned_bytes,
+                    void* stream);
+
+/* Step (c) alone: read the aligned output W_al (layout of the compute mode,
+ * info.bytes_w_al bytes) and write W's standard reduced form to w->data. */
+int symtensor_unalign(symt_ctx* ctx, const char* einsum, const symt_group* group,
+                      const symt_tensor* u, const symt_tensor* v, const symt_tensor* w,
+                      int32_t compute, const void* aligned_w, void* stream);
+
+/* Step (b) alone: c[q] = a[q] b[q] for q < batch over the aligned layouts of
+ * the compute mode (a: batch x m x k, b: batch x k x n, or for BF16X3 the hi/lo
+ * planes with b stored batch x n x k; c: batch x m x n in f64 for F64 and
+ * BF16X3, f32 for F32).  c must not overlap a or b. */
+int symtensor_sector_gemm(symt_ctx* ctx, int32_t compute, int64_t batch, int64_t m, int64_t k,
+                          int64_t n, const void* a, const void* b, void* c, void* stream);
+
+/* Per-step timing: when enabled, symtensor_contract records a HIP event
+ * pair around each of its kernel launches on the caller's stream.
+ * symtensor_read_timing synchronises on those events and returns the summed
+ * milliseconds and launch counts per step: [0] align U, [1] align V,
+ * [2] sector product, [3] unalign W, then clears them. */
+int symtensor_set_timing(symt_ctx* ctx, int32_t enable);
+int symtensor_read_timing(symt_ctx* ctx, double ms[4], int64_t launches[4]);
+
+/* Static description of a status code. */
+const char* symtensor_status_string(int status);
+
+/* Detail of the last failure on this context ("" if none); valid until the
+ * next call on the context.  NULL ctx -> the detail of the last failure of a
+ * context-free call (symtensor_plan, symtensor_workspace_size) on this thread. */
+const char* symtensor_last_error(const symt_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SYMTENSOR_H */

@@ -291,12 +291,14 @@ def contract_dense(sub, Ru, su: Sym, Rv, sv: Sym):
 # ----------------------------------------------------------------------------
 # Form 2: loop over symmetry blocks (Alg. 1, any s, t, v)
 # ----------------------------------------------------------------------------
-def contract_blocks(sub, Ru, su: Sym, Rv, sv: Sym):
+def contract_blocks(sub, Ru, su: Sym, Rv, sv: Sym, u_blocks=None):
     """Loop over every stored block of U and every free J-sector choice.
 
     For each stored block of U the sectors of all U modes follow from U's rule;
     the sectors of J except its last one are looped over, and the last one
     follows from V's rule (the role of J = A+B-I and L = A+B-K in Alg. 1).
+    ``u_blocks`` optionally restricts the outer loop to the listed stored
+    sector tuples of U (a sample of the full loop).
     """
     tu, tv, tw, I, K, J = check_operands(sub, su, sv)
     sw = output_symmetry(sub, su, sv)
@@ -306,7 +308,9 @@ def contract_blocks(sub, Ru, su: Sym, Rv, sv: Sym):
     Rv = np.asarray(Rv, dtype=np.float64)
     Rw = np.zeros(sw.reduced_shape(), dtype=np.float64)
     inner_sub = sub.replace(" ", "")
-    for ustored in itertools.product(range(G), repeat=su.order - 1):
+    outer = itertools.product(range(G), repeat=su.order - 1) if u_blocks is None else u_blocks
+    for ustored in outer:
+        ustored = tuple(ustored)
         usec = full_sectors(su, ustored)
         sec = {m: usec[p] for p, m in enumerate(tu)}
         for jfree in itertools.product(range(G), repeat=len(J) - 1):

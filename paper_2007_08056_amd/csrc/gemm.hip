@@ -1,0 +1,421 @@
+// Sector-batched dense product of the aligned forms (Alg. 2, step li:contra;
+// the einsum "AQL,LQJ->AQJ" of Sec. 2.1): for every auxiliary sector Q,
+// C[Q] (M x N) = A[Q] (M x K) * B[Q] (K x N), all slices the same shape.
+//
+// gfx950 MFMA kernels, one workgroup per (Q, BM x BN) output tile:
+//   * f64: v_mfma_f64_16x16x4_f64, f32: v_mfma_f32_16x16x4_f32.  A and B
+//     tiles are staged through LDS in double buffers (A as [m][k], B as
+//     [k][n], both padded), one barrier per K step.
+//   * split-bf16: A = Ahi + Alo and B = Bhi + Blo (bf16 planes, B stored
+//     [Q][N][K]); v_mfma_f32_16x16x32_bf16 forms Ahi*Bhi in one binary32
+//     accumulator and Ahi*Blo + Alo*Bhi in a second; the epilogue adds the two
+//     in binary64 and stores binary64.
+// Workgroups are dispatched round-robin over the 8 XCDs; the tile order is
+// remapped so that each XCD receives a contiguous run of tiles (the N tiles
+// of one M panel land on the same XCD and share its L2).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "plan.hpp"
+
+namespace symt {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ int64_t xcd_remap(int64_t wg, int64_t n) {
+  const int64_t per = n / 8;
+  if (wg >= per * 8) return wg;
+  return (wg % 8) * per + wg / 8;
+}
+
+template <typename T>
+struct Mfma;
+// Accumulator layouts (lane l, item r, column l % 16): the f64 16x16x4 form
+// holds row l/16 + 4r, the f32 16x16x4 and bf16 16x16x32 forms row 4(l/16) + r.
+template <>
+struct Mfma<double> {
+  using Acc = d4;
+  static __device__ __forceinline__ Acc run(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <>
+struct Mfma<float> {
+  using Acc = f4;
+  static __device__ __forceinline__ Acc run(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+template <typename T, int V>
+struct alignas(sizeof(T) * V) VecT {
+  T v[V];
+};
+
+// ---------------------------------------------------------------------------
+// f64 / f32: C = A B, A [Q][M][K], B [Q][K][N], C [Q][M][N], row-major.
+// V: elements per global vector access (16 bytes, or 1 when K or N is odd).
+// ---------------------------------------------------------------------------
+template <typename T, int BM, int BN, int BK, int WM, int WN, int V>
+__global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
+                                                       const T* __restrict__ B,
+                                                       T* __restrict__ C, int M, int N, int K,
+                                                       int tiles_m, int tiles_n, int64_t ntiles) {
+  constexpr int NT = 64 * WM * WN;
+  constexpr int PAD = 16 / sizeof(T);
+  constexpr int TM = BM / WM / 16;
+  constexpr int TN = BN / WN / 16;
+  static_assert(TM * WM * 16 == BM && TN * WN * 16 == BN, "tile shape");
+  static_assert(BK % 4 == 0, "BK");
+  constexpr int LA = (BM * BK / V + NT - 1) / NT;   // vector loads per thread, A tile
+  constexpr int LB = (BK * BN / V + NT - 1) / NT;   // vector loads per thread, B tile
+  using Acc = typename Mfma<T>::Acc;
+
+  __shared__ T As[2][BM][BK + PAD];
+  __shared__ T Bs[2][BK][BN + PAD];
+
+  const int64_t tile = xcd_remap(blockIdx.x, ntiles);
+  const int tn = static_cast<int>(tile % tiles_n);
+  const int64_t t2 = tile / tiles_n;
+  const int tm = static_cast<int>(t2 % tiles_m);
+  const int64_t q = t2 / tiles_m;
+  const T* Aq = A + q * static_cast<int64_t>(M) * K;
+  const T* Bq = B + q * static_cast<int64_t>(K) * N;
+  T* Cq = C + q * static_cast<int64_t>(M) * N;
+  const int m0 = tm * BM, n0 = tn * BN;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm0 = (wave / WN) * (BM / WM);
+  const int wn0 = (wave % WN) * (BN / WN);
+
+  VecT<T, V> ra[LA], rb[LB];
+  auto load_tiles = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < LA; ++i) {
+      const int e = (tid + i * NT) * V;              // element index inside the BM x BK tile
+      const int r = e / BK, c = e % BK;
+      const int gr = m0 + r, gc = k0 + c;
+      if (e < BM * BK && gr < M && gc < K)
+        ra[i] = *reinterpret_cast<const VecT<T, V>*>(Aq + static_cast<int64_t>(gr) * K + gc);
+      else
+#pragma unroll
+        for (int j = 0; j < V; ++j) ra[i].v[j] = T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      const int e = (tid + i * NT) * V;              // element index inside the BK x BN tile
+      const int r = e / BN, c = e % BN;
+      const int gr = k0 + r, gc = n0 + c;
+      if (e < BK * BN && gr < K && gc < N)
+        rb[i] = *reinterpret_cast<const VecT<T, V>*>(Bq + static_cast<int64_t>(gr) * N + gc);
+      else
+#pragma unroll
+        for (int j = 0; j < V; ++j) rb[i].v[j] = T(0);
+    }
+  };
+  auto store_tiles = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < LA; ++i) {
+      const int e = (tid + i * NT) * V;
+      if (e < BM * BK) *reinterpret_cast<VecT<T, V>*>(&As[buf][e / BK][e % BK]) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      const int e = (tid + i * NT) * V;
+      if (e < BK * BN) *reinterpret_cast<VecT<T, V>*>(&Bs[buf][e / BN][e % BN]) = rb[i];
+    }
+  };
+
+  Acc acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = Acc{};
+
+  const int nk = (K + BK - 1) / BK;
+  load_tiles(0);
+  store_tiles(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load_tiles((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      T a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a[i] = As[buf][wm0 + i * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) b[j] = Bs[buf][kk + (lane >> 4)][wn0 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<T>::run(a[i], b[j], acc[i][j]);
+    }
+    if (kt + 1 < nk) store_tiles(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int col = n0 + wn0 + j * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm0 + i * 16 + Mfma<T>::row(lane, r);
+        if (row < M && col < N) Cq[static_cast<int64_t>(row) * N + col] = acc[i][j][r];
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// split-bf16: A planes [Q][M][K], B planes [Q][N][K] (K fastest), C f64.
+// ---------------------------------------------------------------------------
+template <int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf16x3(
+    const uint16_t* __restrict__ Ahi, const uint16_t* __restrict__ Alo,
+    const uint16_t* __restrict__ Bhi, const uint16_t* __restrict__ Blo, double* __restrict__ C,
+    int M, int N, int K, int tiles_m, int tiles_n, int64_t ntiles) {
+  constexpr int NT = 64 * WM * WN;
+  constexpr int V = 8;                // bf16 per 16-byte access
+  constexpr int LDK = BK + 8;         // padded row (keeps 16-byte alignment)
+  constexpr int TM = BM / WM / 16;
+  constexpr int TN = BN / WN / 16;
+  static_assert(TM * WM * 16 == BM && TN * WN * 16 == BN, "tile shape");
+  static_assert(BK % 32 == 0, "BK");
+  constexpr int LA = (BM * BK / V + NT - 1) / NT;
+  constexpr int LB = (BN * BK / V + NT - 1) / NT;
+
+  __shared__ uint16_t Ash[2][BM][LDK], Asl[2][BM][LDK];
+  __shared__ uint16_t Bsh[2][BN][LDK], Bsl[2][BN][LDK];
+
+  const int64_t tile = xcd_remap(blockIdx.x, ntiles);
+  const int tn = static_cast<int>(tile % tiles_n);
+  const int64_t t2 = tile / tiles_n;
+  const int tm = static_cast<int>(t2 % tiles_m);
+  const int64_t q = t2 / tiles_m;
+  const int64_t offA = q * static_cast<int64_t>(M) * K;
+  const int64_t offB = q * static_cast<int64_t>(N) * K;
+  double* Cq = C + q * static_cast<int64_t>(M) * N;
+  const int m0 = tm * BM, n0 = tn * BN;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm0 = (wave / WN) * (BM / WM);
+  const int wn0 = (wave % WN) * (BN / WN);
+
+  using V8 = VecT<uint16_t, 8>;
+  V8 rah[LA], ral[LA], rbh[LB], rbl[LB];
+  auto load_tiles = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < LA; ++i) {
+      const int e = (tid + i * NT) * V;
+      const int r = e / BK, c = e % BK;
+      const int gr = m0 + r, gc = k0 + c;
+      if (e < BM * BK && gr < M && gc < K) {
+        const int64_t o = offA + static_cast<int64_t>(gr) * K + gc;
+        rah[i] = *reinterpret_cast<const V8*>(Ahi + o);
+        ral[i] = *reinterpret_cast<const V8*>(Alo + o);
+      } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j) rah[i].v[j] = ral[i].v[j] = 0;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      const int e = (tid + i * NT) * V;
+      const int r = e / BK, c = e % BK;
+      const int gr = n0 + r, gc = k0 + c;
+      if (e < BN * BK && gr < N && gc < K) {
+        const int64_t o = offB + static_cast<int64_t>(gr) * K + gc;
+        rbh[i] = *reinterpret_cast<const V8*>(Bhi + o);
+        rbl[i] = *reinterpret_cast<const V8*>(Blo + o);
+      } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j) rbh[i].v[j] = rbl[i].v[j] = 0;
+      }
+    }
+  };
+  auto store_tiles = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < LA; ++i) {
+      const int e = (tid + i * NT) * V;
+      if (e < BM * BK) {
+        *reinterpret_cast<V8*>(&Ash[buf][e / BK][e % BK]) = rah[i];
+        *reinterpret_cast<V8*>(&Asl[buf][e / BK][e % BK]) = ral[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      const int e = (tid + i * NT) * V;
+      if (e < BN * BK) {
+        *reinterpret_cast<V8*>(&Bsh[buf][e / BK][e % BK]) = rbh[i];
+        *reinterpret_cast<V8*>(&Bsl[buf][e / BK][e % BK]) = rbl[i];
+      }
+    }
+  };
+
+  f4 acc_hh[TM][TN], acc_x[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc_hh[i][j] = acc_x[i][j] = f4{};
+
+  const int nk = (K + BK - 1) / BK;
+  load_tiles(0);
+  store_tiles(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load_tiles((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 32) {
+      // operand layout of the 16x16x32 bf16 MFMA: lane l holds row (or column)
+      // l%16 and the 8 consecutive k values starting at 8*(l/16).
+      bf8 ah[TM], al[TM], bh[TN], bl[TN];
+      const int kof = kk + 8 * (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int r = wm0 + i * 16 + (lane & 15);
+        ah[i] = *reinterpret_cast<const bf8*>(&Ash[buf][r][kof]);
+        al[i] = *reinterpret_cast<const bf8*>(&Asl[buf][r][kof]);
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int r = wn0 + j * 16 + (lane & 15);
+        bh[j] = *reinterpret_cast<const bf8*>(&Bsh[buf][r][kof]);
+        bl[j] = *reinterpret_cast<const bf8*>(&Bsl[buf][r][kof]);
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          acc_hh[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc_hh[i][j], 0, 0, 0);
+          acc_x[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc_x[i][j], 0, 0, 0);
+          acc_x[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc_x[i][j], 0, 0, 0);
+        }
+    }
+    if (kt + 1 < nk) store_tiles(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int col = n0 + wn0 + j * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm0 + i * 16 + 4 * (lane >> 4) + r;
+        if (row < M && col < N)
+          Cq[static_cast<int64_t>(row) * N + col] =
+              static_cast<double>(acc_hh[i][j][r]) + static_cast<double>(acc_x[i][j][r]);
+      }
+    }
+}
+
+template <typename T, int BM, int BN, int BK, int WM, int WN>
+hipError_t launch_fp(int vec, int64_t batch, int M, int N, int K, const void* A, const void* B,
+                     void* C, hipStream_t s) {
+  const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
+  const int64_t ntiles = batch * tiles_m * tiles_n;
+  const dim3 grid(static_cast<unsigned>(ntiles)), block(64 * WM * WN);
+  const T* a = static_cast<const T*>(A);
+  const T* b = static_cast<const T*>(B);
+  T* c = static_cast<T*>(C);
+  if (vec > 1)
+    hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, 16 / sizeof(T)>), grid, block, 0, s, a, b, c,
+                       M, N, K, tiles_m, tiles_n, ntiles);
+  else
+    hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, 1>), grid, block, 0, s, a, b, c, M, N, K,
+                       tiles_m, tiles_n, ntiles);
+  return hipGetLastError();
+}
+
+template <int BM, int BN, int BK, int WM, int WN>
+hipError_t launch_bf16x3(int64_t batch, int M, int N, int K, const void* A, const void* B, void* C,
+                         hipStream_t s) {
+  const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
+  const int64_t ntiles = batch * tiles_m * tiles_n;
+  const dim3 grid(static_cast<unsigned>(ntiles)), block(64 * WM * WN);
+  const uint16_t* a = static_cast<const uint16_t*>(A);
+  const uint16_t* b = static_cast<const uint16_t*>(B);
+  const int64_t pa = batch * static_cast<int64_t>(M) * K;
+  const int64_t pb = batch * static_cast<int64_t>(N) * K;
+  hipLaunchKernelGGL((k_gemm_bf16x3<BM, BN, BK, WM, WN>), grid, block, 0, s, a, a + pa, b, b + pb,
+                     static_cast<double*>(C), M, N, K, tiles_m, tiles_n, ntiles);
+  return hipGetLastError();
+}
+
+// Padded work of a tiling (smaller is better), used to pick a tile shape.
+double padded(int64_t M, int64_t N, int bm, int bn) {
+  return static_cast<double>((M + bm - 1) / bm * bm) * static_cast<double>((N + bn - 1) / bn * bn);
+}
+
+}  // namespace
+
+int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t n, const void* A,
+                       const void* B, void* C, hipStream_t stream, std::string* err) {
+  if (batch == 0 || m == 0 || n == 0) return SYMT_OK;
+  if (m > INT32_MAX || n > INT32_MAX || k > INT32_MAX) {
+    if (err) *err = "sector product dimension above 2^31-1";
+    return SYMT_EUNSUPPORTED;
+  }
+  const int M = static_cast<int>(m), N = static_cast<int>(n), K = static_cast<int>(k);
+  hipError_t e = hipSuccess;
+  if (compute == SYMT_COMPUTE_BF16X3) {
+    if (K % 8 != 0) {
+      if (err) *err = "split-bf16 product needs the contracted extent to be a multiple of 8";
+      return SYMT_EUNSUPPORTED;
+    }
+    if (N <= 64)
+      e = launch_bf16x3<128, 64, 64, 4, 1>(batch, M, N, K, A, B, C, stream);
+    else
+      e = launch_bf16x3<128, 128, 64, 2, 2>(batch, M, N, K, A, B, C, stream);
+  } else {
+    const bool f64 = compute == SYMT_COMPUTE_F64;
+    const int vw = f64 ? 2 : 4;
+    const int vec = (K % vw == 0 && N % vw == 0) ? vw : 1;
+    // candidate tiles: (128,128), (128,96), (128,64), (128,48)
+    const double c128 = padded(M, N, 128, 128), c96 = padded(M, N, 128, 96),
+                 c64 = padded(M, N, 128, 64), c48 = padded(M, N, 128, 48);
+    double best = c128;
+    int pick = 0;
+    if (c96 < best) { best = c96; pick = 1; }
+    if (c64 < best) { best = c64; pick = 2; }
+    if (c48 < best) { best = c48; pick = 3; }
+    if (f64) {
+      switch (pick) {
+        case 0: e = launch_fp<double, 128, 128, 16, 2, 2>(vec, batch, M, N, K, A, B, C, stream); break;
+        case 1: e = launch_fp<double, 128, 96, 16, 2, 2>(vec, batch, M, N, K, A, B, C, stream); break;
+        case 2: e = launch_fp<double, 128, 64, 16, 2, 2>(vec, batch, M, N, K, A, B, C, stream); break;
+        default: e = launch_fp<double, 128, 48, 16, 4, 1>(vec, batch, M, N, K, A, B, C, stream); break;
+      }
+    } else {
+      switch (pick) {
+        case 0: e = launch_fp<float, 128, 128, 16, 2, 2>(vec, batch, M, N, K, A, B, C, stream); break;
+        case 1: e = launch_fp<float, 128, 96, 16, 2, 2>(vec, batch, M, N, K, A, B, C, stream); break;
+        case 2: e = launch_fp<float, 128, 64, 16, 2, 2>(vec, batch, M, N, K, A, B, C, stream); break;
+        default: e = launch_fp<float, 128, 48, 16, 4, 1>(vec, batch, M, N, K, A, B, C, stream); break;
+      }
+    }
+  }
+  if (e != hipSuccess) {
+    if (err) *err = std::string("sector product launch: ") + hipGetErrorString(e);
+    return SYMT_EHIP;
+  }
+  return SYMT_OK;
+}
+
+}  // namespace symt

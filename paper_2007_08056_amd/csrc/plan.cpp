@@ -1,0 +1,442 @@
+// Host planner: einsum parsing, mode classification, the derived output rule,
+// aligned shapes and the transform descriptors (Alg. 2, steps li:coeff,
+// li:delta and the index maps of li:rf and the final step).
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+
+namespace symt {
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+namespace {
+
+constexpr int64_t kInt64Max = INT64_MAX;
+
+bool mul_ok(int64_t a, int64_t b, int64_t* out) {
+  if (a < 0 || b < 0) return false;
+  if (a != 0 && b > kInt64Max / a) return false;
+  *out = a * b;
+  return true;
+}
+
+int fail(std::string* err, int code, const char* fmt, const char* a = "", const char* b = "") {
+  if (err) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, fmt, a, b);
+    *err = buf;
+  }
+  return code;
+}
+
+int gsub(const GroupDesc& g, int a, int b);
+int gadd(const GroupDesc& g, int a, int b) {
+  int r = 0, mul = 1;
+  for (int f = g.nf - 1; f >= 0; --f) {
+    const int o = g.ord[f];
+    const int da = a % o, db = b % o;
+    a /= o;
+    b /= o;
+    r += ((da + db) % o) * mul;
+    mul *= o;
+  }
+  return r;
+}
+int gneg(const GroupDesc& g, int a) {
+  int r = 0, mul = 1;
+  for (int f = g.nf - 1; f >= 0; --f) {
+    const int o = g.ord[f];
+    const int da = a % o;
+    a /= o;
+    r += ((o - da) % o) * mul;
+    mul *= o;
+  }
+  return r;
+}
+int gsub(const GroupDesc& g, int a, int b) { return gadd(g, a, gneg(g, b)); }
+int gtimes(const GroupDesc& g, int c, int a) { return c >= 0 ? a : gneg(g, a); }
+
+int read_group(const symt_group* grp, GroupDesc* g, std::string* err) {
+  if (!grp) return fail(err, SYMT_EINVAL, "group is NULL");
+  if (grp->nfactors < 1 || grp->nfactors > SYMT_MAX_FACTORS)
+    return fail(err, SYMT_EINVAL, "group must have 1..%s cyclic factors", "4");
+  g->nf = grp->nfactors;
+  int64_t size = 1;
+  for (int f = 0; f < g->nf; ++f) {
+    if (grp->order[f] < 1) return fail(err, SYMT_EINVAL, "group factor orders must be >= 1");
+    g->ord[f] = grp->order[f];
+    size *= grp->order[f];
+    if (size > (1 << 20)) return fail(err, SYMT_EUNSUPPORTED, "group order above 2^20");
+  }
+  for (int f = g->nf; f < SYMT_MAX_FACTORS; ++f) g->ord[f] = 1;
+  g->size = static_cast<int32_t>(size);
+  return SYMT_OK;
+}
+
+int read_operand(const symt_tensor* t, const GroupDesc& g, OperandDesc* o, const char* name,
+                 std::string* err) {
+  if (!t) return fail(err, SYMT_EINVAL, "operand %s is NULL", name);
+  if (t->nmodes < 1 || t->nmodes > kMaxOrder)
+    return fail(err, SYMT_EINVAL, "operand %s: order must be 1..12", name);
+  if (!t->signs) return fail(err, SYMT_ESYM, "operand %s: sign string is NULL", name);
+  if (!t->dims) return fail(err, SYMT_EINVAL, "operand %s: dims is NULL", name);
+  o->n = t->nmodes;
+  for (int m = 0; m < o->n; ++m) {
+    const char c = t->signs[m];
+    if (c == '+') o->sign[m] = 1;
+    else if (c == '-') o->sign[m] = -1;
+    else return fail(err, SYMT_ESYM, "operand %s: sign string must be '+'/'-' per mode", name);
+  }
+  if (t->signs[o->n] != '\0')
+    return fail(err, SYMT_ESYM, "operand %s: sign string longer than its order", name);
+  if (t->charge < 0 || t->charge >= g.size)
+    return fail(err, SYMT_ESYM, "operand %s: charge outside [0,|G|)", name);
+  o->charge = t->charge;
+  if (t->dtype != SYMT_F64 && t->dtype != SYMT_F32)
+    return fail(err, SYMT_EDTYPE, "operand %s: dtype must be SYMT_F64 or SYMT_F32", name);
+  o->dtype = t->dtype;
+  o->data = t->data;
+  int64_t e = 1;
+  for (int m = 0; m < o->n - 1; ++m)
+    if (!mul_ok(e, g.size, &e)) return fail(err, SYMT_EINVAL, "operand %s: size overflows", name);
+  for (int m = 0; m < o->n; ++m) {
+    if (t->dims[m] < 0) return fail(err, SYMT_EINVAL, "operand %s: negative block dimension", name);
+    o->dims[m] = t->dims[m];
+    if (!mul_ok(e, t->dims[m], &e)) return fail(err, SYMT_EINVAL, "operand %s: size overflows", name);
+  }
+  o->elems = e;
+  return SYMT_OK;
+}
+
+bool is_letter(char c) { return (c >= 'a' && c <= 'z') || (c >= 'A' && c <= 'Z'); }
+
+}  // namespace
+
+AlignedLayout aligned_layout(int32_t compute, int operand) {
+  // The split-bf16 product reads both factors along the contracted index, so
+  // V's aligned form keeps that index fastest.
+  if (compute == SYMT_COMPUTE_BF16X3 && operand == 1) return kColMajor;
+  return kRowMajor;
+}
+
+int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
+              const symt_tensor* v, const symt_tensor* w, int32_t compute, Plan* p,
+              std::string* err) {
+  if (!einsum || !p) return fail(err, SYMT_EINVAL, "einsum or plan is NULL");
+  int rc = read_group(group, &p->g, err);
+  if (rc) return rc;
+  if (compute < SYMT_COMPUTE_F64 || compute > SYMT_COMPUTE_BF16X3)
+    return fail(err, SYMT_EDTYPE, "unknown compute mode");
+  p->compute = compute;
+
+  // ---- parse "tu,tv->tw"
+  std::string s(einsum);
+  const size_t comma = s.find(',');
+  const size_t arrow = s.find("->");
+  if (comma == std::string::npos || arrow == std::string::npos || comma > arrow ||
+      s.find(',', comma + 1) != std::string::npos || s.find("->", arrow + 2) != std::string::npos)
+    return fail(err, SYMT_EEINSUM, "einsum must read \"u,v->w\"");
+  p->tu = s.substr(0, comma);
+  p->tv = s.substr(comma + 1, arrow - comma - 1);
+  p->tw = s.substr(arrow + 2);
+  for (const std::string* t : {&p->tu, &p->tv, &p->tw}) {
+    if (t->empty() || t->size() > static_cast<size_t>(kMaxOrder))
+      return fail(err, SYMT_EEINSUM, "einsum term empty or longer than 12 modes");
+    for (size_t i = 0; i < t->size(); ++i) {
+      if (!is_letter((*t)[i])) return fail(err, SYMT_EEINSUM, "einsum letters must be a-z/A-Z");
+      if (t->find((*t)[i], i + 1) != std::string::npos)
+        return fail(err, SYMT_EEINSUM, "letter repeated inside one einsum term");
+    }
+  }
+  const std::string &tu = p->tu, &tv = p->tv, &tw = p->tw;
+  std::string I, K, J;
+  for (char c : tu) {
+    const bool inv = tv.find(c) != std::string::npos, inw = tw.find(c) != std::string::npos;
+    if (inv && inw) return fail(err, SYMT_EEINSUM, "a letter in all three terms is a batch index");
+    if (!inv && !inw) return fail(err, SYMT_EEINSUM, "a letter of u appears nowhere else");
+    (inw ? I : K).push_back(c);
+  }
+  for (char c : tv) {
+    const bool inu = tu.find(c) != std::string::npos, inw = tw.find(c) != std::string::npos;
+    if (!inu && !inw) return fail(err, SYMT_EEINSUM, "a letter of v appears nowhere else");
+    if (!inu) J.push_back(c);
+  }
+  for (char c : tw)
+    if (tu.find(c) == std::string::npos && tv.find(c) == std::string::npos)
+      return fail(err, SYMT_EEINSUM, "a letter of the output appears in no input");
+  if (tw.size() != I.size() + J.size())
+    return fail(err, SYMT_EEINSUM, "output term must hold exactly the uncontracted letters");
+  p->s = static_cast<int32_t>(I.size());
+  p->v = static_cast<int32_t>(K.size());
+  p->t = static_cast<int32_t>(J.size());
+  if (p->s == 0 || p->t == 0 || p->v == 0)
+    return fail(err, SYMT_EEINSUM, "s, t and v must all be >= 1 (no outer products or vectors)");
+
+  // ---- operands
+  if ((rc = read_operand(u, p->g, &p->U, "u", err))) return rc;
+  if ((rc = read_operand(v, p->g, &p->V, "v", err))) return rc;
+  if (p->U.n != static_cast<int>(tu.size()) || p->V.n != static_cast<int>(tv.size()))
+    return fail(err, SYMT_EINVAL, "operand order differs from its einsum term");
+  for (int i = 0; i < p->s; ++i) p->posI_u[i] = static_cast<int32_t>(tu.find(I[i]));
+  for (int i = 0; i < p->v; ++i) {
+    p->posK_u[i] = static_cast<int32_t>(tu.find(K[i]));
+    p->posK_v[i] = static_cast<int32_t>(tv.find(K[i]));
+  }
+  for (int i = 0; i < p->t; ++i) p->posJ_v[i] = static_cast<int32_t>(tv.find(J[i]));
+  for (int i = 0; i < p->s; ++i) p->posI_w[i] = static_cast<int32_t>(tw.find(I[i]));
+  for (int i = 0; i < p->t; ++i) p->posJ_w[i] = static_cast<int32_t>(tw.find(J[i]));
+
+  // ---- contracted modes: equal block sizes and one sign ratio
+  int sigma = 0;
+  for (int i = 0; i < p->v; ++i) {
+    if (p->U.dims[p->posK_u[i]] != p->V.dims[p->posK_v[i]])
+      return fail(err, SYMT_EINVAL, "contracted mode '%s' has different block sizes",
+                  std::string(1, K[i]).c_str());
+    const int r = p->U.sign[p->posK_u[i]] * p->V.sign[p->posK_v[i]];
+    if (sigma == 0) sigma = r;
+    else if (r != sigma)
+      return fail(err, SYMT_ESYM, "contracted modes carry mixed sign ratios c^V/c^U");
+  }
+  p->sigma = sigma;
+
+  // ---- derived output rule: c^W = (c^U_I, -sigma c^V_J), Z^W = Z^U - sigma Z^V
+  for (size_t m = 0; m < tw.size(); ++m) {
+    const char c = tw[m];
+    const size_t pu = tu.find(c);
+    p->w_sign[m] = (pu != std::string::npos) ? p->U.sign[pu] : -sigma * p->V.sign[tv.find(c)];
+  }
+  p->w_charge = gsub(p->g, p->U.charge, gtimes(p->g, sigma, p->V.charge));
+
+  // ---- output descriptor
+  p->has_w = (w != nullptr);
+  if (w) {
+    if ((rc = read_operand(w, p->g, &p->W, "w", err))) return rc;
+    if (p->W.n != static_cast<int>(tw.size()))
+      return fail(err, SYMT_EINVAL, "output order differs from its einsum term");
+    for (size_t m = 0; m < tw.size(); ++m) {
+      const char c = tw[m];
+      const size_t pu = tu.find(c);
+      const int64_t d = (pu != std::string::npos) ? p->U.dims[pu] : p->V.dims[tv.find(c)];
+      if (p->W.dims[m] != d) return fail(err, SYMT_EINVAL, "output block sizes differ from inputs'");
+    }
+    bool same = p->W.charge == p->w_charge, flipped = p->W.charge == gneg(p->g, p->w_charge);
+    for (size_t m = 0; m < tw.size(); ++m) {
+      same = same && p->W.sign[m] == p->w_sign[m];
+      flipped = flipped && p->W.sign[m] == -p->w_sign[m];
+    }
+    if (!same && !flipped)
+      return fail(err, SYMT_ESYM, "output signs/charge differ from the rule implied by u and v");
+  } else {
+    p->W = OperandDesc{};
+    p->W.n = static_cast<int32_t>(tw.size());
+    int64_t e = 1;
+    for (int m = 0; m < p->W.n - 1; ++m) mul_ok(e, p->g.size, &e);
+    for (size_t m = 0; m < tw.size(); ++m) {
+      const char c = tw[m];
+      const size_t pu = tu.find(c);
+      p->W.dims[m] = (pu != std::string::npos) ? p->U.dims[pu] : p->V.dims[tv.find(c)];
+      p->W.sign[m] = p->w_sign[m];
+      if (!mul_ok(e, p->W.dims[m], &e)) return fail(err, SYMT_EINVAL, "output size overflows");
+    }
+    p->W.charge = p->w_charge;
+    p->W.dtype = SYMT_F64;
+    p->W.elems = e;
+  }
+
+  // ---- aligned shapes M = G^(s-1) n_I, Kd = G^(v-1) n_K, N = G^(t-1) n_J
+  p->nI = p->nK = p->nJ = 1;
+  for (int i = 0; i < p->s; ++i) mul_ok(p->nI, p->U.dims[p->posI_u[i]], &p->nI);
+  for (int i = 0; i < p->v; ++i) mul_ok(p->nK, p->U.dims[p->posK_u[i]], &p->nK);
+  for (int i = 0; i < p->t; ++i) mul_ok(p->nJ, p->V.dims[p->posJ_v[i]], &p->nJ);
+  int64_t gs = 1, gt = 1, gv = 1;
+  for (int i = 1; i < p->s; ++i) mul_ok(gs, p->g.size, &gs);
+  for (int i = 1; i < p->t; ++i) mul_ok(gt, p->g.size, &gt);
+  for (int i = 1; i < p->v; ++i) mul_ok(gv, p->g.size, &gv);
+  if (!mul_ok(gs, p->nI, &p->M) || !mul_ok(gv, p->nK, &p->Kd) || !mul_ok(gt, p->nJ, &p->N))
+    return fail(err, SYMT_EINVAL, "aligned shape overflows");
+  if (p->M > INT32_MAX || p->N > INT32_MAX || p->Kd > INT32_MAX)
+    return fail(err, SYMT_EUNSUPPORTED, "aligned matrix dimension above 2^31-1");
+  p->flops = 2.0 * p->g.size * static_cast<double>(p->M) * static_cast<double>(p->Kd) *
+             static_cast<double>(p->N);
+
+  // ---- buffer sizes for the compute mode
+  const size_t eu = static_cast<size_t>(p->U.elems), ev = static_cast<size_t>(p->V.elems),
+               ew = static_cast<size_t>(p->W.elems);
+  switch (compute) {
+    case SYMT_COMPUTE_F64: p->bytes_u_al = 8 * eu; p->bytes_v_al = 8 * ev; p->bytes_w_al = 8 * ew; break;
+    case SYMT_COMPUTE_F32: p->bytes_u_al = 4 * eu; p->bytes_v_al = 4 * ev; p->bytes_w_al = 4 * ew; break;
+    default: p->bytes_u_al = 4 * eu; p->bytes_v_al = 4 * ev; p->bytes_w_al = 8 * ew; break;
+  }
+  p->workspace = round_up(p->bytes_u_al, 256) + round_up(p->bytes_v_al, 256) +
+                 round_up(p->bytes_w_al, 256);
+  return SYMT_OK;
+}
+
+XformParams make_xform(const Plan& p, int operand, bool to_aligned, int in_bytes, int out_bytes,
+                       bool out_is_split) {
+  XformParams x;
+  std::memset(&x, 0, sizeof x);
+  x.g = p.g;
+  const OperandDesc& X = operand == 0 ? p.U : operand == 1 ? p.V : p.W;
+  x.order = X.n;
+
+  // Sector groups: rows (I for U and W, K for V), columns (K for U, J for V and W).
+  SectorGroup& R = x.row;
+  SectorGroup& C = x.col;
+  const int G = p.g.size;
+  if (operand == 0) {
+    R.count = p.s;
+    for (int i = 0; i < p.s; ++i) { R.pos[i] = p.posI_u[i]; R.coef[i] = p.U.sign[p.posI_u[i]]; }
+    R.alpha = -1; R.beta = p.U.charge;                 // delta(1): sum c^U_I I + Q == Z^U
+    C.count = p.v;
+    for (int i = 0; i < p.v; ++i) { C.pos[i] = p.posK_u[i]; C.coef[i] = p.U.sign[p.posK_u[i]]; }
+    C.alpha = 1; C.beta = 0;                           // delta(2): sum c^U_K K == Q
+  } else if (operand == 1) {
+    R.count = p.v;
+    for (int i = 0; i < p.v; ++i) { R.pos[i] = p.posK_v[i]; R.coef[i] = p.U.sign[p.posK_u[i]]; }
+    R.alpha = 1; R.beta = 0;                           // delta(2), U's coefficients
+    C.count = p.t;
+    for (int i = 0; i < p.t; ++i) { C.pos[i] = p.posJ_v[i]; C.coef[i] = p.V.sign[p.posJ_v[i]]; }
+    C.alpha = -p.sigma; C.beta = p.V.charge;           // delta(3): sum c^V_J J + sigma Q == Z^V
+  } else {
+    R.count = p.s;
+    for (int i = 0; i < p.s; ++i) { R.pos[i] = p.posI_w[i]; R.coef[i] = p.U.sign[p.posI_u[i]]; }
+    R.alpha = -1; R.beta = p.U.charge;
+    C.count = p.t;
+    for (int i = 0; i < p.t; ++i) { C.pos[i] = p.posJ_w[i]; C.coef[i] = p.V.sign[p.posJ_v[i]]; }
+    C.alpha = -p.sigma; C.beta = p.V.charge;
+  }
+  x.gpow_row = 1;
+  for (int i = 1; i < R.count; ++i) x.gpow_row *= G;
+  x.gpow_col = 1;
+  for (int i = 1; i < C.count; ++i) x.gpow_col *= G;
+  x.nblocks = x.gpow_row * x.gpow_col * G;
+  x.blk_elems = 1;
+  for (int m = 0; m < X.n; ++m) x.blk_elems *= X.dims[m];
+  int64_t nR = 1, nC = 1;
+  for (int i = 0; i < R.count; ++i) nR *= X.dims[R.pos[i]];
+  for (int i = 0; i < C.count; ++i) nC *= X.dims[C.pos[i]];
+  const int64_t rows_tot = x.gpow_row * nR, cols_tot = x.gpow_col * nC;
+  const AlignedLayout lay = aligned_layout(p.compute, operand);
+  x.q_stride = rows_tot * cols_tot;
+  x.plane = static_cast<int64_t>(G) * rows_tot * cols_tot;
+  const int64_t row_unit = lay == kRowMajor ? cols_tot : 1;   // aligned stride of one row
+  const int64_t col_unit = lay == kRowMajor ? 1 : rows_tot;   // aligned stride of one column
+  x.rs_stride = nR * row_unit;
+  x.cs_stride = nC * col_unit;
+  x.to_aligned = to_aligned ? 1 : 0;
+
+  // Inner dims in aligned order with both strides.
+  int64_t std_stride[kMaxOrder];
+  {
+    int64_t acc = 1;
+    for (int m = X.n - 1; m >= 0; --m) { std_stride[m] = acc; acc *= X.dims[m]; }
+  }
+  int nd = 0;
+  int64_t size[kMaxDims], s_std[kMaxDims], s_al[kMaxDims];
+  {
+    int64_t acc = 1;
+    int64_t tmp_al[kMaxOrder];
+    for (int i = R.count - 1; i >= 0; --i) { tmp_al[i] = acc * row_unit; acc *= X.dims[R.pos[i]]; }
+    for (int i = 0; i < R.count; ++i) {
+      size[nd] = X.dims[R.pos[i]]; s_std[nd] = std_stride[R.pos[i]]; s_al[nd] = tmp_al[i]; ++nd;
+    }
+    acc = 1;
+    for (int i = C.count - 1; i >= 0; --i) { tmp_al[i] = acc * col_unit; acc *= X.dims[C.pos[i]]; }
+    for (int i = 0; i < C.count; ++i) {
+      size[nd] = X.dims[C.pos[i]]; s_std[nd] = std_stride[C.pos[i]]; s_al[nd] = tmp_al[i]; ++nd;
+    }
+  }
+  // Drop unit dims, then merge neighbours that nest the same way in both layouts.
+  int md = 0;
+  int64_t msize[kMaxDims], mstd[kMaxDims], mal[kMaxDims];
+  for (int d = 0; d < nd; ++d) {
+    if (size[d] == 1) continue;
+    if (md > 0 && mstd[md - 1] == s_std[d] * size[d] && mal[md - 1] == s_al[d] * size[d]) {
+      msize[md - 1] *= size[d];
+      mstd[md - 1] = s_std[d];
+      mal[md - 1] = s_al[d];
+      continue;
+    }
+    msize[md] = size[d]; mstd[md] = s_std[d]; mal[md] = s_al[d]; ++md;
+  }
+  if (md == 0) { msize[0] = 1; mstd[0] = 1; mal[0] = 1; md = 1; }
+  const int64_t* ss = to_aligned ? mstd : mal;
+  const int64_t* ds = to_aligned ? mal : mstd;
+
+  // Choose the copy run / transpose pair.
+  int run = -1;
+  for (int d = 0; d < md; ++d)
+    if (ss[d] == 1 && ds[d] == 1) run = d;
+  int a = 0, b = 0;
+  for (int d = 1; d < md; ++d) {
+    if (ss[d] < ss[a]) a = d;
+    if (ds[d] < ds[b]) b = d;
+  }
+  if (run < 0 && a == b) run = a;
+  x.mode = run >= 0 ? 0 : 1;
+  if (x.mode == 0) a = run;
+  x.run = a;
+  x.run_len = msize[a];
+  x.run_ss = ss[a];
+  x.run_ds = ds[a];
+  if (x.mode == 1) {
+    x.tdim = b;
+    x.t_len = msize[b];
+    x.t_ss = ss[b];
+    x.t_ds = ds[b];
+  }
+  // Batch dims: the rest, ordered so that the last one has the smallest dst stride.
+  int order_idx[kMaxDims];
+  int nb = 0;
+  for (int d = 0; d < md; ++d)
+    if (d != a && !(x.mode == 1 && d == b)) order_idx[nb++] = d;
+  std::sort(order_idx, order_idx + nb, [&](int l, int r) { return ds[l] > ds[r]; });
+  x.nbatch = nb;
+  x.rows = 1;
+  for (int i = 0; i < nb; ++i) {
+    const int d = order_idx[i];
+    x.bsize[i] = msize[d];
+    x.bss[i] = ss[d];
+    x.bds[i] = ds[d];
+    x.rows *= msize[d];
+  }
+
+  if (x.mode == 0) {
+    // Vector width: 16-byte accesses where every offset stays a multiple of it.
+    int vec = 1;
+    if (x.run_ss == 1 && x.run_ds == 1) {
+      const int out_unit = out_is_split ? 2 : out_bytes;
+      for (int cand : {4, 2}) {
+        if (cand * in_bytes > 16 || cand * out_unit > 16) continue;
+        bool ok = x.run_len % cand == 0 && x.blk_elems % cand == 0 && x.q_stride % cand == 0 &&
+                  x.rs_stride % cand == 0 && x.cs_stride % cand == 0 && x.plane % cand == 0;
+        for (int i = 0; i < nb && ok; ++i) ok = x.bss[i] % cand == 0 && x.bds[i] % cand == 0;
+        if (ok) { vec = cand; break; }
+      }
+    }
+    x.vec = vec;
+    const int64_t vecs = (x.run_len + vec - 1) / vec;
+    int lanes = 1, lg = 0;
+    while (lanes < 64 && lanes < vecs) { lanes *= 2; ++lg; }
+    x.lanes_per_row = lanes;
+    x.lanes_log2 = lg;
+    int64_t rpt = std::max<int64_t>(1, 32768 / std::max<int64_t>(1, x.run_len * in_bytes));
+    rpt = std::max<int64_t>(rpt, 256 / lanes);
+    rpt = std::min<int64_t>(rpt, 256);
+    rpt = std::min<int64_t>(rpt, x.rows);
+    x.rows_per_tile = std::max<int64_t>(rpt, 1);
+    x.tiles_per_block = (x.rows + x.rows_per_tile - 1) / x.rows_per_tile;
+  } else {
+    x.vec = 1;
+    x.tiles_run = static_cast<int32_t>((x.run_len + 63) / 64);
+    x.tiles_t = static_cast<int32_t>((x.t_len + 63) / 64);
+    x.rows_per_tile = 1;
+    x.tiles_per_block = x.rows * x.tiles_run * x.tiles_t;
+  }
+  return x;
+}
+
+}  // namespace symt

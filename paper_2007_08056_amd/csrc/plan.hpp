@@ -1,0 +1,118 @@
+// Host-side plan of one symmetric contraction and the POD descriptors handed to
+// the transform and sector-product kernels.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "symtensor.h"
+
+namespace symt {
+
+constexpr int kMaxOrder = SYMT_MAX_ORDER;
+constexpr int kMaxDims = SYMT_MAX_ORDER + 1;
+
+struct GroupDesc {
+  int32_t nf;                       // number of cyclic factors
+  int32_t ord[SYMT_MAX_FACTORS];    // factor orders, first most significant
+  int32_t size;                     // |G|
+};
+
+// One sector group of an aligned operand (rows or columns of its matrix form).
+// The sectors S[pos[i]] of the group's modes obey
+//     sum_i coef[i] * S[pos[i]] == alpha * Q + beta      (in G)
+// which is one of the three generalized Kronecker deltas of Alg. 2
+// (delta(1) on I, delta(2) on K, delta(3) on J).  The last listed mode is the
+// implicit one; the others are stored, first most significant.
+struct SectorGroup {
+  int32_t count;
+  int32_t pos[kMaxOrder];
+  int32_t coef[kMaxOrder];
+  int32_t alpha;
+  int32_t beta;
+};
+
+// Layout variants of an aligned matrix (|G|, rows, cols).
+enum AlignedLayout : int32_t {
+  kRowMajor = 0,     // [Q][row][col]
+  kColMajor = 1      // [Q][col][row]  (row index fastest)
+};
+
+// Element types the transform moves between.
+enum XType : int32_t { kXF64 = 0, kXF32 = 1, kXBF16Split = 2 };
+
+// Everything one transform launch needs; passed to the kernel by value.
+struct XformParams {
+  GroupDesc g;
+  int32_t order;                    // modes of the operand
+  SectorGroup row, col;
+  int64_t gpow_row, gpow_col;       // |G|^(count-1) of each group
+  int64_t nblocks;                  // |G|^(order-1) blocks (bijection std <-> aligned)
+  int64_t blk_elems;                // elements per block (product of inner dims)
+  int64_t q_stride, rs_stride, cs_stride;  // aligned block base = Q*q + Rs*rs + Cs*cs
+  int64_t plane;                    // elements between the hi and lo bf16 planes
+  int32_t to_aligned;               // 1: standard -> aligned, 0: aligned -> standard
+  // inner dims after merging; src / dst strides already oriented by direction
+  int32_t mode;                     // 0 copy (one run dim), 1 tiled transpose
+  int32_t run;                      // copy: run dim; transpose: src-fast dim
+  int32_t tdim;                     // transpose: dst-fast dim
+  int64_t run_len;                  // size[run]
+  int64_t run_ss, run_ds;           // strides of the run dim
+  int64_t t_len, t_ss, t_ds;        // size/strides of the dst-fast dim (transpose)
+  int32_t nbatch;                   // remaining dims ("rows")
+  int64_t bsize[kMaxDims];
+  int64_t bss[kMaxDims];
+  int64_t bds[kMaxDims];
+  int64_t rows;                     // product of bsize
+  int64_t rows_per_tile;            // copy: rows per workgroup
+  int64_t tiles_per_block;          // workgroups per block
+  int32_t lanes_per_row;            // copy: power of two <= 64
+  int32_t lanes_log2;
+  int32_t vec;                      // elements per thread access along the run (1, 2, 4)
+  int32_t tiles_run, tiles_t;       // transpose: tiles along run and tdim
+};
+
+struct OperandDesc {
+  int32_t n;                        // order
+  int32_t sign[kMaxOrder];          // +1 / -1
+  int32_t charge;
+  int64_t dims[kMaxOrder];
+  int32_t dtype;
+  void* data;
+  int64_t elems;                    // elements of the standard reduced form
+};
+
+struct Plan {
+  GroupDesc g;
+  std::string tu, tv, tw;
+  int32_t s = 0, t = 0, v = 0, sigma = 0;
+  int32_t posI_u[kMaxOrder], posK_u[kMaxOrder], posK_v[kMaxOrder], posJ_v[kMaxOrder];
+  int32_t posI_w[kMaxOrder], posJ_w[kMaxOrder];
+  int64_t nI = 1, nK = 1, nJ = 1;
+  int64_t M = 0, Kd = 0, N = 0;
+  OperandDesc U, V, W;
+  bool has_w = false;
+  int32_t w_sign[kMaxOrder];        // derived
+  int32_t w_charge = 0;             // derived
+  int32_t compute = 0;
+  size_t bytes_u_al = 0, bytes_v_al = 0, bytes_w_al = 0, workspace = 0;
+  double flops = 0.0;
+};
+
+// Parse and validate; returns a SYMT_* status and fills `err` on failure.
+int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
+              const symt_tensor* v, const symt_tensor* w, int32_t compute, Plan* plan,
+              std::string* err);
+
+// Transform descriptor for operand 0 (U), 1 (V) or 2 (W) in the given direction.
+// `in_type` / `out_type` are the element types of the source and destination.
+XformParams make_xform(const Plan& p, int operand, bool to_aligned, int in_elem_bytes,
+                       int out_elem_bytes, bool out_is_split);
+
+// Aligned layout used for an operand under a compute mode.
+AlignedLayout aligned_layout(int32_t compute, int operand);
+
+size_t round_up(size_t x, size_t a);
+
+}  // namespace symt

@@ -1,0 +1,356 @@
+// C ABI of the irrep-alignment contraction: contexts, validation, workspace
+// layout and the three-step launch sequence (align U, align V, sector
+// product, unalign W).  Declarations and contracts are in include/symtensor.h.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "plan.hpp"
+#include "symtensor.h"
+
+namespace symt {
+int launch_xform(const XformParams& p, bool in_f64, int out, const void* src, void* dst,
+                 hipStream_t stream, std::string* err);
+int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t n, const void* A,
+                       const void* B, void* C, hipStream_t stream, std::string* err);
+}  // namespace symt
+
+using symt::Plan;
+
+struct symt_ctx {
+  int device = 0;
+  std::string last_error;
+  bool timing = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[4];
+};
+
+namespace {
+
+thread_local std::string g_free_error;
+
+int ctx_fail(symt_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->last_error = msg;
+  else g_free_error = msg;
+  return code;
+}
+
+size_t elem_bytes(int dtype) { return dtype == SYMT_F64 ? 8 : 4; }
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  if (!a || !b || na == 0 || nb == 0) return false;
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return x < y + nb && y < x + na;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+hipEvent_t take_event(symt_ctx* ctx) {
+  if (!ctx->pool.empty()) {
+    hipEvent_t e = ctx->pool.back();
+    ctx->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Runs `fn` on the stream, bracketed by a timing event pair when timing is on.
+template <typename F>
+int timed(symt_ctx* ctx, int step, hipStream_t s, F&& fn) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (ctx->timing) {
+    a = take_event(ctx);
+    b = take_event(ctx);
+    if (a && b) (void)hipEventRecord(a, s);
+  }
+  const int rc = fn();
+  if (a && b) {
+    (void)hipEventRecord(b, s);
+    ctx->pending[step].emplace_back(a, b);
+  }
+  return rc;
+}
+
+int out_kind_aligned(int compute) {
+  return compute == SYMT_COMPUTE_F64 ? 0 : compute == SYMT_COMPUTE_F32 ? 1 : 2;
+}
+int aligned_elem_bytes(int compute) {
+  return compute == SYMT_COMPUTE_F64 ? 8 : compute == SYMT_COMPUTE_F32 ? 4 : 2;
+}
+
+// Align operand 0 (U) or 1 (V) from its standard form into `dst`.
+int do_align(symt_ctx* ctx, const Plan& p, int operand, void* dst, hipStream_t s) {
+  const symt::OperandDesc& X = operand == 0 ? p.U : p.V;
+  if (X.elems == 0) return SYMT_OK;
+  const int kind = out_kind_aligned(p.compute);
+  symt::XformParams x = symt::make_xform(p, operand, true, static_cast<int>(elem_bytes(X.dtype)),
+                                         aligned_elem_bytes(p.compute), kind == 2);
+  if (!aligned16(X.data) || !aligned16(dst)) x.vec = 1;
+  std::string err;
+  const int rc = timed(ctx, operand, s, [&] {
+    return symt::launch_xform(x, X.dtype == SYMT_F64, kind, X.data, dst, s, &err);
+  });
+  return rc ? ctx_fail(ctx, rc, err) : SYMT_OK;
+}
+
+int do_unalign(symt_ctx* ctx, const Plan& p, const void* wal, hipStream_t s) {
+  if (p.W.elems == 0) return SYMT_OK;
+  const bool in_f64 = p.compute != SYMT_COMPUTE_F32;
+  symt::XformParams x = symt::make_xform(p, 2, false, in_f64 ? 8 : 4,
+                                         static_cast<int>(elem_bytes(p.W.dtype)), false);
+  if (!aligned16(wal) || !aligned16(p.W.data)) x.vec = 1;
+  std::string err;
+  const int rc = timed(ctx, 3, s, [&] {
+    return symt::launch_xform(x, in_f64, p.W.dtype == SYMT_F64 ? 0 : 1, wal, p.W.data, s, &err);
+  });
+  return rc ? ctx_fail(ctx, rc, err) : SYMT_OK;
+}
+
+int do_gemm(symt_ctx* ctx, int compute, int64_t batch, int64_t m, int64_t k, int64_t n,
+            const void* a, const void* b, void* c, hipStream_t s) {
+  std::string err;
+  const int rc = timed(ctx, 2, s, [&] {
+    return symt::launch_sector_gemm(compute, batch, m, k, n, a, b, c, s, &err);
+  });
+  return rc ? ctx_fail(ctx, rc, err) : SYMT_OK;
+}
+
+int plan_for(symt_ctx* ctx, const char* einsum, const symt_group* group, const symt_tensor* u,
+             const symt_tensor* v, const symt_tensor* w, int32_t compute, Plan* p) {
+  std::string err;
+  const int rc = symt::make_plan(einsum, group, u, v, w, compute, p, &err);
+  return rc ? ctx_fail(ctx, rc, err) : SYMT_OK;
+}
+
+int check_data(symt_ctx* ctx, const symt::OperandDesc& X, const char* name) {
+  if (X.elems > 0 && !X.data)
+    return ctx_fail(ctx, SYMT_EINVAL, std::string("operand ") + name + " data is NULL");
+  return SYMT_OK;
+}
+
+int set_device(symt_ctx* ctx) {
+  const hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return ctx_fail(ctx, SYMT_EHIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+  return SYMT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int symtensor_create(symt_ctx** out, int device) {
+  if (!out) return ctx_fail(nullptr, SYMT_EINVAL, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || device < 0 || device >= count)
+    return ctx_fail(nullptr, SYMT_EHIP, "no such HIP device");
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return ctx_fail(nullptr, SYMT_EHIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+  symt_ctx* c = new symt_ctx;
+  c->device = device;
+  *out = c;
+  return SYMT_OK;
+}
+
+int symtensor_destroy(symt_ctx* ctx) {
+  if (!ctx) return SYMT_OK;
+  for (auto& v : ctx->pending)
+    for (auto& pr : v) {
+      hipEventDestroy(pr.first);
+      hipEventDestroy(pr.second);
+    }
+  for (hipEvent_t e : ctx->pool) hipEventDestroy(e);
+  delete ctx;
+  return SYMT_OK;
+}
+
+int symtensor_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
+                   const symt_tensor* v, const symt_tensor* w, int32_t compute,
+                   symt_plan_info* info) {
+  if (!info) return ctx_fail(nullptr, SYMT_EINVAL, "info is NULL");
+  Plan p;
+  int rc = plan_for(nullptr, einsum, group, u, v, w, compute, &p);
+  if (rc) return rc;
+  std::memset(info, 0, sizeof *info);
+  info->s = p.s;
+  info->t = p.t;
+  info->v = p.v;
+  info->sigma = p.sigma;
+  info->group_size = p.g.size;
+  info->m = p.M;
+  info->k = p.Kd;
+  info->n = p.N;
+  info->elems_u = p.U.elems;
+  info->elems_v = p.V.elems;
+  info->elems_w = p.W.elems;
+  info->flops = p.flops;
+  info->bytes_u_al = p.bytes_u_al;
+  info->bytes_v_al = p.bytes_v_al;
+  info->bytes_w_al = p.bytes_w_al;
+  info->workspace_bytes = p.workspace;
+  for (size_t m = 0; m < p.tw.size(); ++m) info->w_signs[m] = p.w_sign[m] > 0 ? '+' : '-';
+  info->w_signs[p.tw.size()] = '\0';
+  info->w_charge = p.w_charge;
+  return SYMT_OK;
+}
+
+int symtensor_workspace_size(const char* einsum, const symt_group* group, const symt_tensor* u,
+                             const symt_tensor* v, const symt_tensor* w, int32_t compute,
+                             size_t* bytes) {
+  if (!bytes) return ctx_fail(nullptr, SYMT_EINVAL, "bytes is NULL");
+  Plan p;
+  const int rc = plan_for(nullptr, einsum, group, u, v, w, compute, &p);
+  if (rc) return rc;
+  *bytes = p.workspace;
+  return SYMT_OK;
+}
+
+int symtensor_contract(symt_ctx* ctx, const char* einsum, const symt_group* group,
+                       const symt_tensor* u, const symt_tensor* v, const symt_tensor* w,
+                       int32_t compute, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!ctx) return ctx_fail(nullptr, SYMT_EINVAL, "context is NULL");
+  if (!w) return ctx_fail(ctx, SYMT_EINVAL, "output descriptor is NULL");
+  Plan p;
+  int rc = plan_for(ctx, einsum, group, u, v, w, compute, &p);
+  if (rc) return rc;
+  if ((rc = check_data(ctx, p.U, "u")) || (rc = check_data(ctx, p.V, "v")) ||
+      (rc = check_data(ctx, p.W, "w")))
+    return rc;
+  if (p.W.elems == 0) return SYMT_OK;
+  if (workspace_bytes < p.workspace || (p.workspace > 0 && !workspace))
+    return ctx_fail(ctx, SYMT_EWORKSPACE, "workspace smaller than symtensor_workspace_size()");
+  const size_t wb = static_cast<size_t>(p.W.elems) * elem_bytes(p.W.dtype);
+  if (overlaps(p.W.data, wb, p.U.data, static_cast<size_t>(p.U.elems) * elem_bytes(p.U.dtype)) ||
+      overlaps(p.W.data, wb, p.V.data, static_cast<size_t>(p.V.elems) * elem_bytes(p.V.dtype)) ||
+      overlaps(p.W.data, wb, workspace, p.workspace))
+    return ctx_fail(ctx, SYMT_EALIAS, "output overlaps an input or the workspace");
+  if (p.compute == SYMT_COMPUTE_BF16X3 && p.Kd % 8 != 0)
+    return ctx_fail(ctx, SYMT_EUNSUPPORTED,
+                    "split-bf16 product needs the aligned contracted extent to be a multiple of 8");
+  if (p.compute == SYMT_COMPUTE_BF16X3 && !aligned16(workspace))
+    return ctx_fail(ctx, SYMT_EUNSUPPORTED, "split-bf16 workspace must be 16-byte aligned");
+  if ((rc = set_device(ctx))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(workspace);
+  void* ual = base;
+  void* val = base + symt::round_up(p.bytes_u_al, 256);
+  void* wal = base + symt::round_up(p.bytes_u_al, 256) + symt::round_up(p.bytes_v_al, 256);
+  if ((rc = do_align(ctx, p, 0, ual, s))) return rc;
+  if ((rc = do_align(ctx, p, 1, val, s))) return rc;
+  if ((rc = do_gemm(ctx, p.compute, p.g.size, p.M, p.Kd, p.N, ual, val, wal, s))) return rc;
+  if ((rc = do_unalign(ctx, p, wal, s))) return rc;
+  return SYMT_OK;
+}
+
+int symtensor_align(symt_ctx* ctx, const char* einsum, const symt_group* group,
+                    const symt_tensor* u, const symt_tensor* v, const symt_tensor* w,
+                    int32_t compute, int32_t operand, void* aligned, size_t aligned_bytes,
+                    void* stream) {
+  if (!ctx) return ctx_fail(nullptr, SYMT_EINVAL, "context is NULL");
+  if (operand != 0 && operand != 1) return ctx_fail(ctx, SYMT_EINVAL, "operand must be 0 (u) or 1 (v)");
+  Plan p;
+  int rc = plan_for(ctx, einsum, group, u, v, w, compute, &p);
+  if (rc) return rc;
+  const symt::OperandDesc& X = operand == 0 ? p.U : p.V;
+  if ((rc = check_data(ctx, X, operand == 0 ? "u" : "v"))) return rc;
+  const size_t need = operand == 0 ? p.bytes_u_al : p.bytes_v_al;
+  if (aligned_bytes < need || (need > 0 && !aligned))
+    return ctx_fail(ctx, SYMT_EWORKSPACE, "aligned buffer too small");
+  if (overlaps(aligned, need, X.data, static_cast<size_t>(X.elems) * elem_bytes(X.dtype)))
+    return ctx_fail(ctx, SYMT_EALIAS, "aligned buffer overlaps the operand");
+  if ((rc = set_device(ctx))) return rc;
+  return do_align(ctx, p, operand, aligned, static_cast<hipStream_t>(stream));
+}
+
+int symtensor_unalign(symt_ctx* ctx, const char* einsum, const symt_group* group,
+                      const symt_tensor* u, const symt_tensor* v, const symt_tensor* w,
+                      int32_t compute, const void* aligned_w, void* stream) {
+  if (!ctx) return ctx_fail(nullptr, SYMT_EINVAL, "context is NULL");
+  if (!w) return ctx_fail(ctx, SYMT_EINVAL, "output descriptor is NULL");
+  Plan p;
+  int rc = plan_for(ctx, einsum, group, u, v, w, compute, &p);
+  if (rc) return rc;
+  if ((rc = check_data(ctx, p.W, "w"))) return rc;
+  if (p.W.elems > 0 && !aligned_w) return ctx_fail(ctx, SYMT_EINVAL, "aligned_w is NULL");
+  if (overlaps(p.W.data, static_cast<size_t>(p.W.elems) * elem_bytes(p.W.dtype), aligned_w,
+               p.bytes_w_al))
+    return ctx_fail(ctx, SYMT_EALIAS, "output overlaps the aligned buffer");
+  if ((rc = set_device(ctx))) return rc;
+  return do_unalign(ctx, p, aligned_w, static_cast<hipStream_t>(stream));
+}
+
+int symtensor_sector_gemm(symt_ctx* ctx, int32_t compute, int64_t batch, int64_t m, int64_t k,
+                          int64_t n, const void* a, const void* b, void* c, void* stream) {
+  if (!ctx) return ctx_fail(nullptr, SYMT_EINVAL, "context is NULL");
+  if (compute < SYMT_COMPUTE_F64 || compute > SYMT_COMPUTE_BF16X3)
+    return ctx_fail(ctx, SYMT_EDTYPE, "unknown compute mode");
+  if (batch < 0 || m < 0 || k < 0 || n < 0) return ctx_fail(ctx, SYMT_EINVAL, "negative size");
+  const size_t ea = compute == SYMT_COMPUTE_F64 ? 8 : compute == SYMT_COMPUTE_F32 ? 4 : 4;
+  const size_t ec = compute == SYMT_COMPUTE_F32 ? 4 : 8;
+  const size_t na = static_cast<size_t>(batch) * m * k * ea, nb = static_cast<size_t>(batch) * k * n * ea,
+               nc = static_cast<size_t>(batch) * m * n * ec;
+  if (nc == 0) return SYMT_OK;
+  if (!c || (na && !a) || (nb && !b)) return ctx_fail(ctx, SYMT_EINVAL, "NULL buffer");
+  if (overlaps(c, nc, a, na) || overlaps(c, nc, b, nb))
+    return ctx_fail(ctx, SYMT_EALIAS, "c overlaps a or b");
+  if (compute == SYMT_COMPUTE_BF16X3 && (k % 8 != 0 || !aligned16(a) || !aligned16(b)))
+    return ctx_fail(ctx, SYMT_EUNSUPPORTED, "split-bf16 product needs k % 8 == 0 and 16-byte aligned planes");
+  if (compute != SYMT_COMPUTE_BF16X3 && (!aligned16(a) || !aligned16(b) || !aligned16(c)))
+    return ctx_fail(ctx, SYMT_EUNSUPPORTED, "sector product buffers must be 16-byte aligned");
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  return do_gemm(ctx, compute, batch, m, k, n, a, b, c, static_cast<hipStream_t>(stream));
+}
+
+int symtensor_set_timing(symt_ctx* ctx, int32_t enable) {
+  if (!ctx) return ctx_fail(nullptr, SYMT_EINVAL, "context is NULL");
+  ctx->timing = enable != 0;
+  return SYMT_OK;
+}
+
+int symtensor_read_timing(symt_ctx* ctx, double ms[4], int64_t launches[4]) {
+  if (!ctx || !ms || !launches) return ctx_fail(ctx, SYMT_EINVAL, "NULL argument");
+  for (int i = 0; i < 4; ++i) {
+    ms[i] = 0.0;
+    launches[i] = 0;
+    for (auto& pr : ctx->pending[i]) {
+      float t = 0.f;
+      if (hipEventSynchronize(pr.second) == hipSuccess &&
+          hipEventElapsedTime(&t, pr.first, pr.second) == hipSuccess) {
+        ms[i] += t;
+        ++launches[i];
+      }
+      ctx->pool.push_back(pr.first);
+      ctx->pool.push_back(pr.second);
+    }
+    ctx->pending[i].clear();
+  }
+  return SYMT_OK;
+}
+
+const char* symtensor_status_string(int status) {
+  switch (status) {
+    case SYMT_OK: return "ok";
+    case SYMT_EINVAL: return "invalid argument";
+    case SYMT_EEINSUM: return "invalid einsum subscripts";
+    case SYMT_ESYM: return "inconsistent symmetry";
+    case SYMT_EDTYPE: return "unsupported dtype or compute mode";
+    case SYMT_EWORKSPACE: return "workspace too small";
+    case SYMT_EALIAS: return "output overlaps an input";
+    case SYMT_EUNSUPPORTED: return "unsupported request";
+    case SYMT_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char* symtensor_last_error(const symt_ctx* ctx) {
+  return ctx ? ctx->last_error.c_str() : g_free_error.c_str();
+}
+
+}  // extern "C"

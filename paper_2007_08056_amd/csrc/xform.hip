@@ -1,0 +1,211 @@
+// Reduced-form transforms of the irrep-alignment method (Alg. 2, step li:rf
+// for the inputs and the final step for the output).
+//
+// The aligned form of an operand and its standard reduced form hold the same
+// blocks in a different arrangement: each aligned block (Q, stored row
+// sectors, stored column sectors) is exactly one stored block of the standard
+// form, because the generalized Kronecker deltas fix the two implicit sectors
+// from Q.  So the transform is a block permutation plus one fixed permutation
+// of the in-block indices -- constant work per element, the structured route
+// the paper contrasts with dense delta contractions.  Each workgroup works
+// inside one block; the block's two base offsets are computed once per
+// workgroup from the group arithmetic.  Inside the block either
+//   * copy mode: one run of elements is contiguous in both layouts; every
+//     thread moves 16-byte vectors along it, rows indexed through LDS, or
+//   * transpose mode: the source- and destination-contiguous dims differ;
+//     a 64 x 64 tile is read along the first into LDS and written along the
+//     second.
+// Element conversions (f64 <-> f32, f32 -> bf16 hi/lo pair) are fused.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "plan.hpp"
+#include "xform_index.hpp"
+
+namespace symt {
+
+namespace {
+
+template <typename T, int V>
+struct alignas(sizeof(T) * V) VecT {
+  T v[V];
+};
+
+// bfloat16 by round-to-nearest-even on the binary32 bit pattern (finite inputs).
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float bf16_as_f32(uint16_t h) {
+  return __uint_as_float(static_cast<uint32_t>(h) << 16);
+}
+
+// OUT: 0 -> f64, 1 -> f32, 2 -> bf16 hi plane at off, lo plane at off + plane.
+template <int OUT, int V>
+__device__ __forceinline__ void store_vec(void* dst, int64_t off, int64_t plane, const double (&x)[V]) {
+  if constexpr (OUT == 0) {
+    VecT<double, V> o;
+#pragma unroll
+    for (int i = 0; i < V; ++i) o.v[i] = x[i];
+    *reinterpret_cast<VecT<double, V>*>(static_cast<double*>(dst) + off) = o;
+  } else if constexpr (OUT == 1) {
+    VecT<float, V> o;
+#pragma unroll
+    for (int i = 0; i < V; ++i) o.v[i] = static_cast<float>(x[i]);
+    *reinterpret_cast<VecT<float, V>*>(static_cast<float*>(dst) + off) = o;
+  } else {
+    VecT<uint16_t, V> h, l;
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      const float f = static_cast<float>(x[i]);
+      const uint16_t hb = bf16_rne(f);
+      h.v[i] = hb;
+      l.v[i] = bf16_rne(f - bf16_as_f32(hb));
+    }
+    uint16_t* d = static_cast<uint16_t*>(dst);
+    *reinterpret_cast<VecT<uint16_t, V>*>(d + off) = h;
+    *reinterpret_cast<VecT<uint16_t, V>*>(d + off + plane) = l;
+  }
+}
+
+template <typename Tin, int OUT, int V>
+__global__ __launch_bounds__(256) void k_xform_copy(const Tin* __restrict__ src,
+                                                    void* __restrict__ dst, const XformParams p) {
+  __shared__ int64_t soff[256];
+  __shared__ int64_t doff[256];
+  const int64_t wg = blockIdx.x;
+  const int64_t blk = wg / p.tiles_per_block;
+  const int64_t tile = wg - blk * p.tiles_per_block;
+  int64_t sb, ab;
+  block_bases(p, blk, sb, ab);
+  const int64_t src_base = p.to_aligned ? sb : ab;
+  const int64_t dst_base = p.to_aligned ? ab : sb;
+  const int64_t r0 = tile * p.rows_per_tile;
+  const int64_t left = p.rows - r0;
+  const int nr = static_cast<int>(left < p.rows_per_tile ? left : p.rows_per_tile);
+  for (int r = threadIdx.x; r < nr; r += blockDim.x) {
+    int64_t rem = r0 + r, so = 0, dof = 0;
+    for (int i = p.nbatch - 1; i >= 0; --i) {
+      const int64_t qd = rem / p.bsize[i];
+      const int64_t d = rem - qd * p.bsize[i];
+      rem = qd;
+      so += d * p.bss[i];
+      dof += d * p.bds[i];
+    }
+    soff[r] = src_base + so;
+    doff[r] = dst_base + dof;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & (p.lanes_per_row - 1);
+  const int sub = threadIdx.x >> p.lanes_log2;
+  const int rpp = blockDim.x >> p.lanes_log2;
+  const int64_t step = static_cast<int64_t>(p.lanes_per_row) * V;
+  for (int r = sub; r < nr; r += rpp) {
+    const int64_t s0 = soff[r], d0 = doff[r];
+    for (int64_t c = static_cast<int64_t>(lane) * V; c < p.run_len; c += step) {
+      double x[V];
+      if constexpr (V == 1) {
+        x[0] = static_cast<double>(src[s0 + c * p.run_ss]);
+        store_vec<OUT, 1>(dst, d0 + c * p.run_ds, p.plane, x);
+      } else {
+        const VecT<Tin, V> in = *reinterpret_cast<const VecT<Tin, V>*>(src + s0 + c);
+#pragma unroll
+        for (int i = 0; i < V; ++i) x[i] = static_cast<double>(in.v[i]);
+        store_vec<OUT, V>(dst, d0 + c, p.plane, x);
+      }
+    }
+  }
+}
+
+template <typename Tin, int OUT>
+__global__ __launch_bounds__(256) void k_xform_transpose(const Tin* __restrict__ src,
+                                                         void* __restrict__ dst,
+                                                         const XformParams p) {
+  __shared__ double tile[64][65];
+  const int64_t wg = blockIdx.x;
+  const int64_t blk = wg / p.tiles_per_block;
+  int64_t rem = wg - blk * p.tiles_per_block;
+  const int64_t tb = rem % p.tiles_t;
+  rem /= p.tiles_t;
+  const int64_t ta = rem % p.tiles_run;
+  int64_t row = rem / p.tiles_run;
+  int64_t sb, ab;
+  block_bases(p, blk, sb, ab);
+  int64_t so = p.to_aligned ? sb : ab;
+  int64_t dof = p.to_aligned ? ab : sb;
+  for (int i = p.nbatch - 1; i >= 0; --i) {
+    const int64_t qd = row / p.bsize[i];
+    const int64_t d = row - qd * p.bsize[i];
+    row = qd;
+    so += d * p.bss[i];
+    dof += d * p.bds[i];
+  }
+  const int x = threadIdx.x & 63;
+  const int y = threadIdx.x >> 6;
+  for (int j = y; j < 64; j += 4) {
+    const int64_t ia = ta * 64 + x, ib = tb * 64 + j;
+    if (ia < p.run_len && ib < p.t_len)
+      tile[j][x] = static_cast<double>(src[so + ia * p.run_ss + ib * p.t_ss]);
+  }
+  __syncthreads();
+  for (int j = y; j < 64; j += 4) {
+    const int64_t ia = ta * 64 + j, ib = tb * 64 + x;
+    if (ia < p.run_len && ib < p.t_len) {
+      double v[1] = {tile[x][j]};
+      store_vec<OUT, 1>(dst, dof + ia * p.run_ds + ib * p.t_ds, p.plane, v);
+    }
+  }
+}
+
+template <typename Tin, int OUT>
+hipError_t launch_typed(const XformParams& p, const void* src, void* dst, hipStream_t stream) {
+  const int64_t nwg = p.nblocks * p.tiles_per_block;
+  const dim3 grid(static_cast<unsigned>(nwg)), block(256);
+  const Tin* s = static_cast<const Tin*>(src);
+  if (p.mode == 1) {
+    hipLaunchKernelGGL((k_xform_transpose<Tin, OUT>), grid, block, 0, stream, s, dst, p);
+  } else if (p.vec == 4) {
+    if constexpr (sizeof(Tin) * 4 <= 16 && (OUT != 0))
+      hipLaunchKernelGGL((k_xform_copy<Tin, OUT, 4>), grid, block, 0, stream, s, dst, p);
+    else
+      hipLaunchKernelGGL((k_xform_copy<Tin, OUT, 1>), grid, block, 0, stream, s, dst, p);
+  } else if (p.vec == 2) {
+    hipLaunchKernelGGL((k_xform_copy<Tin, OUT, 2>), grid, block, 0, stream, s, dst, p);
+  } else {
+    hipLaunchKernelGGL((k_xform_copy<Tin, OUT, 1>), grid, block, 0, stream, s, dst, p);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// in_f64: source elements are binary64 (else binary32); out: 0 f64, 1 f32, 2 bf16 split.
+int launch_xform(const XformParams& p, bool in_f64, int out, const void* src, void* dst,
+                 hipStream_t stream, std::string* err) {
+  const int64_t nwg = p.nblocks * p.tiles_per_block;
+  if (nwg == 0) return SYMT_OK;
+  if (nwg > INT32_MAX) {
+    if (err) *err = "transform needs more than 2^31-1 workgroups";
+    return SYMT_EUNSUPPORTED;
+  }
+  hipError_t e;
+  if (in_f64) {
+    e = out == 0 ? launch_typed<double, 0>(p, src, dst, stream)
+        : out == 1 ? launch_typed<double, 1>(p, src, dst, stream)
+                   : launch_typed<double, 2>(p, src, dst, stream);
+  } else {
+    e = out == 0 ? launch_typed<float, 0>(p, src, dst, stream)
+        : out == 1 ? launch_typed<float, 1>(p, src, dst, stream)
+                   : launch_typed<float, 2>(p, src, dst, stream);
+  }
+  if (e != hipSuccess) {
+    if (err) *err = std::string("transform launch: ") + hipGetErrorString(e);
+    return SYMT_EHIP;
+  }
+  return SYMT_OK;
+}
+
+}  // namespace symt

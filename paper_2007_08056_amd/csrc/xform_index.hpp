@@ -1,0 +1,81 @@
+// Index arithmetic of the reduced-form transforms, shared by the kernels and
+// host-side checks: group operations on flattened elements, the implicit
+// sector of a sector group (one generalized Kronecker delta of Alg. 2), and
+// the two base offsets of one block in the standard and aligned layouts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "plan.hpp"
+
+namespace symt {
+
+__host__ __device__ inline int dg_add(const GroupDesc& g, int a, int b) {
+  if (g.nf == 1) {
+    const int s = a + b;
+    return s >= g.size ? s - g.size : s;
+  }
+  int r = 0, mul = 1;
+  for (int f = g.nf - 1; f >= 0; --f) {
+    const int o = g.ord[f];
+    const int da = a % o, db = b % o;
+    a /= o;
+    b /= o;
+    const int s = da + db;
+    r += (s >= o ? s - o : s) * mul;
+    mul *= o;
+  }
+  return r;
+}
+
+__host__ __device__ inline int dg_neg(const GroupDesc& g, int a) {
+  if (g.nf == 1) return a == 0 ? 0 : g.size - a;
+  int r = 0, mul = 1;
+  for (int f = g.nf - 1; f >= 0; --f) {
+    const int o = g.ord[f];
+    const int da = a % o;
+    a /= o;
+    r += (da == 0 ? 0 : o - da) * mul;
+    mul *= o;
+  }
+  return r;
+}
+
+__host__ __device__ inline int dg_times(const GroupDesc& g, int c, int a) {
+  return c >= 0 ? a : dg_neg(g, a);
+}
+
+// Sectors of one group's modes: the stored ones are the digits of `digits`
+// (base |G|, first most significant); the last one solves the group's delta.
+__host__ __device__ inline void fill_sectors(const GroupDesc& g, const SectorGroup& sg,
+                                             int64_t digits, int q, int* S) {
+  int acc = 0;
+  for (int i = sg.count - 2; i >= 0; --i) {
+    const int d = static_cast<int>(digits % g.size);
+    digits /= g.size;
+    S[sg.pos[i]] = d;
+    acc = dg_add(g, acc, dg_times(g, sg.coef[i], d));
+  }
+  const int rhs = dg_add(g, dg_times(g, sg.alpha, q), sg.beta);
+  S[sg.pos[sg.count - 1]] = dg_times(g, sg.coef[sg.count - 1], dg_add(g, rhs, dg_neg(g, acc)));
+}
+
+// Aligned block index -> (standard-form element offset, aligned element offset).
+__host__ __device__ inline void block_bases(const XformParams& p, int64_t blk, int64_t& std_base,
+                                            int64_t& al_base) {
+  const int64_t cs = blk % p.gpow_col;
+  const int64_t t = blk / p.gpow_col;
+  const int64_t rs = t % p.gpow_row;
+  const int q = static_cast<int>(t / p.gpow_row);
+  int S[kMaxOrder];
+  fill_sectors(p.g, p.row, rs, q, S);
+  fill_sectors(p.g, p.col, cs, q, S);
+  int64_t sb = 0;
+  for (int m = 0; m < p.order - 1; ++m) sb = sb * p.g.size + S[m];
+  std_base = sb * p.blk_elems;
+  al_base = q * p.q_stride + rs * p.rs_stride + cs * p.cs_stride;
+}
+
+}  // namespace symt

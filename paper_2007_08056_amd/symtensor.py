@@ -1,0 +1,251 @@
+"""Python front end: symmetric tensors on torch device memory and the contraction.
+
+``SymTensor`` pairs a standard reduced form (a torch tensor of shape
+[|G|]*(N-1) + [n_0, ..., n_{N-1}], the layout of the paper's API example,
+Sec. 3) with its symmetry label (sign string, total charge, group).
+``einsum(subscripts, u, v)`` contracts two of them through the HIP library:
+align both operands, one sector-batched product, unalign the result
+(Alg. 2).  It is differentiable: the backward pass is two more contractions
+of the same kind (dU = dW . V over the J modes, dV = U . dW over the I
+modes), whose aligned operands are recomputed from the saved standard forms
+rather than stored.
+
+PyTorch supplies device memory and the current HIP stream; no arithmetic of
+the method happens in Python.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+_DTYPE_CODE = {torch.float64: L.SYMT_F64, torch.float32: L.SYMT_F32}
+
+
+def _group_tuple(group):
+    return tuple(int(o) for o in (group if isinstance(group, (tuple, list)) else (group,)))
+
+
+def group_size(group) -> int:
+    g = 1
+    for o in _group_tuple(group):
+        g *= o
+    return g
+
+
+@dataclass
+class SymTensor:
+    """A tensor with cyclic (or product-of-cyclic) group symmetry, stored reduced."""
+    data: torch.Tensor
+    signs: str
+    charge: int
+    group: tuple
+
+    def __post_init__(self):
+        self.group = _group_tuple(self.group)
+        n = len(self.signs)
+        G = group_size(self.group)
+        if self.data.dim() != 2 * n - 1 or any(int(s) != G for s in self.data.shape[: n - 1]):
+            raise ValueError(f"reduced form must have shape [{G}]*{n - 1} + dims, got {tuple(self.data.shape)}")
+        if self.data.dtype not in _DTYPE_CODE:
+            raise TypeError("reduced form must be float64 or float32")
+        self.charge = int(self.charge) % G
+
+    @property
+    def dims(self):
+        n = len(self.signs)
+        return tuple(int(d) for d in self.data.shape[n - 1:])
+
+    @property
+    def order(self):
+        return len(self.signs)
+
+    def desc(self, data=None) -> L.TensorDesc:
+        d = self.data if data is None else data
+        return L.TensorDesc(self.signs, self.charge, self.dims, _DTYPE_CODE[d.dtype],
+                            d.data_ptr() if d.numel() else None)
+
+
+def _check_dense(t: torch.Tensor):
+    if not t.is_cuda:
+        raise ValueError("operand data must live on a HIP device")
+    if not t.is_contiguous():
+        raise ValueError("operand data must be contiguous")
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def plan(subscripts: str, u: SymTensor, v: SymTensor, compute: str = "f64", w: SymTensor | None = None):
+    """Shapes, flops, workspace and derived output rule of a contraction (host only)."""
+    if u.group != v.group:
+        raise ValueError("operands use different groups")
+    g = L.make_group(u.group)
+    return L.plan(subscripts, g, u.desc(), v.desc(), w.desc() if w is not None else None,
+                  L.COMPUTE[compute])
+
+
+def output_like(subscripts: str, u: SymTensor, v: SymTensor, dtype=None) -> SymTensor:
+    """A zero-filled output with the derived sign string and charge."""
+    info = plan(subscripts, u, v)
+    tu, rest = subscripts.split(",")
+    tv, tw = rest.split("->")
+    dims = []
+    for m in tw:
+        dims.append(u.dims[tu.index(m)] if m in tu else v.dims[tv.index(m)])
+    G = group_size(u.group)
+    shape = [G] * (len(tw) - 1) + dims
+    dtype = dtype or u.data.dtype
+    data = torch.zeros(shape, dtype=dtype, device=u.data.device)
+    return SymTensor(data, info.w_signs.decode(), info.w_charge, u.group)
+
+
+def contract_into(subscripts: str, u: SymTensor, v: SymTensor, w: SymTensor, compute: str = "f64",
+                  workspace: torch.Tensor | None = None):
+    """w.data <- contraction of u and v (no autograd); returns w."""
+    for t in (u.data, v.data, w.data):
+        _check_dense(t)
+    dev = u.data.device
+    g = L.make_group(u.group)
+    du, dv, dw = u.desc(), v.desc(), w.desc()
+    info = L.plan(subscripts, g, du, dv, dw, L.COMPUTE[compute])
+    if workspace is None or workspace.numel() < info.workspace_bytes:
+        workspace = torch.empty(max(1, info.workspace_bytes), dtype=torch.uint8, device=dev)
+    ctx = L.context(dev.index or 0)
+    L.check(L.LIB.symtensor_contract(ctx, subscripts.encode(), ctypes.byref(g), du.ref, dv.ref,
+                                     dw.ref, L.COMPUTE[compute], ctypes.c_void_p(workspace.data_ptr()),
+                                     workspace.numel(), ctypes.c_void_p(_stream(dev))), ctx)
+    return w
+
+
+def _swap(subscripts):
+    tu, rest = subscripts.split(",")
+    tv, tw = rest.split("->")
+    return tu, tv, tw
+
+
+class _Contract(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, subscripts, meta_u, meta_v, meta_w, compute, ud, vd):
+        u = SymTensor(ud, *meta_u)
+        v = SymTensor(vd, *meta_v)
+        w = SymTensor(torch.empty(meta_w[3], dtype=ud.dtype, device=ud.device), *meta_w[:3])
+        contract_into(subscripts, u, v, w, compute)
+        ctx.save_for_backward(ud, vd)
+        ctx.meta = (subscripts, meta_u, meta_v, meta_w, compute)
+        return w.data
+
+    @staticmethod
+    def backward(ctx, gw):
+        subscripts, meta_u, meta_v, meta_w, compute = ctx.meta
+        ud, vd = ctx.saved_tensors
+        tu, tv, tw = _swap(subscripts)
+        dW = SymTensor(gw.contiguous().to(ud.dtype), *meta_w[:3])
+        gu = gv = None
+        if ctx.needs_input_grad[5]:
+            # dU[I,K] = sum_J dW[I,J] V[K,J]; the derived rule of (dW, V) is U's.
+            out = SymTensor(torch.empty_like(ud), *meta_u)
+            contract_into(f"{tw},{tv}->{tu}", dW, SymTensor(vd, *meta_v), out, compute)
+            gu = out.data
+        if ctx.needs_input_grad[6]:
+            # dV[K,J] = sum_I U[I,K] dW[I,J]; the derived rule of (U, dW) is V's up to a global sign.
+            out = SymTensor(torch.empty_like(vd), *meta_v)
+            contract_into(f"{tu},{tw}->{tv}", SymTensor(ud, *meta_u), dW, out, compute)
+            gv = out.data
+        return None, None, None, None, None, gu, gv
+
+
+def einsum(subscripts: str, u: SymTensor, v: SymTensor, compute: str = "f64") -> SymTensor:
+    """W = contraction of u and v (Eq. ctr), differentiable with respect to u.data and v.data."""
+    if u.group != v.group:
+        raise ValueError("operands use different groups")
+    if compute not in L.COMPUTE:
+        raise ValueError(f"compute must be one of {list(L.COMPUTE)}")
+    info = plan(subscripts, u, v, compute)
+    tu, tv, tw = _swap(subscripts)
+    dims = [u.dims[tu.index(m)] if m in tu else v.dims[tv.index(m)] for m in tw]
+    G = group_size(u.group)
+    shape = tuple([G] * (len(tw) - 1) + dims)
+    meta_u = (u.signs, u.charge, u.group)
+    meta_v = (v.signs, v.charge, v.group)
+    meta_w = (info.w_signs.decode(), info.w_charge, u.group, shape)
+    wd = _Contract.apply(subscripts, meta_u, meta_v, meta_w, compute, u.data, v.data)
+    return SymTensor(wd, meta_w[0], meta_w[1], u.group)
+
+
+# ---------------------------------------------------------------------------
+# The three steps on their own (tests, profiling)
+# ---------------------------------------------------------------------------
+def align(subscripts: str, u: SymTensor, v: SymTensor, operand: int, compute: str = "f64") -> torch.Tensor:
+    """Aligned form of u (operand 0) or v (operand 1) in the compute mode's layout.
+
+    f64 / f32: a (|G|, M, K) or (|G|, K, N) tensor.  bf16x3: an int16 tensor of
+    raw bf16 bits, (2, |G|, M, K) for u and (2, |G|, N, K) for v (hi plane first).
+    """
+    dev = u.data.device
+    g = L.make_group(u.group)
+    du, dv = u.desc(), v.desc()
+    info = L.plan(subscripts, g, du, dv, None, L.COMPUTE[compute])
+    G, M, K, N = info.group_size, info.m, info.k, info.n
+    if compute == "f64":
+        out = torch.empty((G, M, K) if operand == 0 else (G, K, N), dtype=torch.float64, device=dev)
+    elif compute == "f32":
+        out = torch.empty((G, M, K) if operand == 0 else (G, K, N), dtype=torch.float32, device=dev)
+    else:
+        out = torch.empty((2, G, M, K) if operand == 0 else (2, G, N, K), dtype=torch.int16, device=dev)
+    ctx = L.context(dev.index or 0)
+    nbytes = out.numel() * out.element_size()
+    L.check(L.LIB.symtensor_align(ctx, subscripts.encode(), ctypes.byref(g), du.ref, dv.ref, None,
+                                  L.COMPUTE[compute], int(operand),
+                                  ctypes.c_void_p(out.data_ptr()) if nbytes else None, nbytes,
+                                  ctypes.c_void_p(_stream(dev))), ctx)
+    return out
+
+
+def unalign(subscripts: str, u: SymTensor, v: SymTensor, w: SymTensor, aligned_w: torch.Tensor,
+            compute: str = "f64") -> SymTensor:
+    dev = u.data.device
+    g = L.make_group(u.group)
+    ctx = L.context(dev.index or 0)
+    du, dv, dw = u.desc(), v.desc(), w.desc()
+    L.check(L.LIB.symtensor_unalign(ctx, subscripts.encode(), ctypes.byref(g), du.ref, dv.ref, dw.ref,
+                                    L.COMPUTE[compute], ctypes.c_void_p(aligned_w.data_ptr()),
+                                    ctypes.c_void_p(_stream(dev))), ctx)
+    return w
+
+
+def sector_gemm(a: torch.Tensor, b: torch.Tensor, compute: str = "f64", c: torch.Tensor | None = None):
+    """c[q] = a[q] b[q] on the aligned layouts (see include/symtensor.h)."""
+    dev = a.device
+    if compute == "bf16x3":
+        _, batch, m, k = a.shape
+        n = b.shape[2]
+        cdt = torch.float64
+    else:
+        batch, m, k = a.shape
+        n = b.shape[2]
+        cdt = a.dtype
+    if c is None:
+        c = torch.empty((batch, m, n), dtype=cdt, device=dev)
+    ctx = L.context(dev.index or 0)
+    L.check(L.LIB.symtensor_sector_gemm(ctx, L.COMPUTE[compute], batch, m, k, n,
+                                        ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                                        ctypes.c_void_p(c.data_ptr()), ctypes.c_void_p(_stream(dev))), ctx)
+    return c
+
+
+def set_timing(device, enable: bool):
+    L.check(L.LIB.symtensor_set_timing(L.context(device), int(bool(enable))))
+
+
+def read_timing(device):
+    """Summed milliseconds and launches per step: align U, align V, product, unalign W."""
+    ms = (ctypes.c_double * 4)()
+    n = (ctypes.c_int64 * 4)()
+    ctx = L.context(device)
+    L.check(L.LIB.symtensor_read_timing(ctx, ms, n), ctx)
+    return list(ms), list(n)

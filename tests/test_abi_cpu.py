@@ -1,0 +1,178 @@
+"""C-ABI checks that need no GPU: symbols, planner results, error codes."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from paper_2007_08056_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "symtensor.h")).read()
+    declared = set(re.findall(r"\b(symtensor_\w+)\s*\(", header))
+    assert declared == set(L.EXPORTED)
+    lib = ctypes.CDLL(L.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def _desc(signs, charge, dims, dtype=L.SYMT_F64):
+    return L.TensorDesc(signs, charge, dims, dtype, None)
+
+
+def _plan(sub, group, u, v, w=None, compute=0):
+    info = L.SymtPlanInfo()
+    rc = L.LIB.symtensor_plan(sub.encode(), ctypes.byref(L.make_group(group)), u.ref, v.ref,
+                              w.ref if w is not None else None, compute, ctypes.byref(info))
+    return rc, info
+
+
+@pytest.mark.parametrize("name", list(synth.configs.ALL))
+def test_plan_matches_oracle_on_workloads(name):
+    wl = synth.configs.get(name)
+    g = O.Group(wl.group)
+    for st in wl.steps:
+        ou, ov, ow = (wl.operands[x] for x in (st.u, st.v, st.w))
+        su = O.Sym.make(ou.signs, ou.charge, ou.dims, g)
+        sv = O.Sym.make(ov.signs, ov.charge, ov.dims, g)
+        rc, info = _plan(st.einsum, wl.group, _desc(ou.signs, ou.charge, ou.dims),
+                         _desc(ov.signs, ov.charge, ov.dims), _desc(ow.signs, ow.charge, ow.dims))
+        assert rc == 0, L.last_error()
+        G, M, K, N = O.aligned_shape(st.einsum, su, sv)
+        assert (info.group_size, info.m, info.k, info.n) == (G, M, K, N)
+        assert info.flops == O.flop_count(st.einsum, su, sv)
+        sw = O.output_symmetry(st.einsum, su, sv)
+        assert info.w_signs.decode() == sw.sign_string() and info.w_charge == sw.charge
+        assert info.elems_u == np.prod(su.reduced_shape())
+        assert info.workspace_bytes >= 8 * (info.elems_u + info.elems_v + info.elems_w)
+
+
+def test_plan_matches_oracle_on_random_contractions():
+    rng = np.random.default_rng(2)
+    letters = "abcdefghij"
+    for _ in range(200):
+        orders = [(2,), (3,), (4,), (2, 3), (2, 2, 2)][rng.integers(5)]
+        g = O.Group(orders)
+        s, t, v = (int(x) for x in rng.integers(1, 4, 3))
+        ls = list(letters[: s + t + v])
+        I, K, J = ls[:s], ls[s:s + v], ls[s + v:]
+        tu = list(I + K); rng.shuffle(tu)
+        tv = list(K + J); rng.shuffle(tv)
+        tw = list(I + J); rng.shuffle(tw)
+        dims = {m: int(rng.integers(0, 4)) for m in ls}
+        cu = {m: int(rng.choice([-1, 1])) for m in tu}
+        sigma = int(rng.choice([-1, 1]))
+        cv = {m: (sigma * cu[m] if m in K else int(rng.choice([-1, 1]))) for m in tv}
+        su = O.Sym(tuple(cu[m] for m in tu), int(rng.integers(g.size)), tuple(dims[m] for m in tu), g)
+        sv = O.Sym(tuple(cv[m] for m in tv), int(rng.integers(g.size)), tuple(dims[m] for m in tv), g)
+        sub = f"{''.join(tu)},{''.join(tv)}->{''.join(tw)}"
+        rc, info = _plan(sub, orders, _desc(su.sign_string(), su.charge, su.dims),
+                         _desc(sv.sign_string(), sv.charge, sv.dims))
+        assert rc == 0, L.last_error()
+        assert (info.group_size, info.m, info.k, info.n) == O.aligned_shape(sub, su, sv)
+        assert info.sigma == sigma and (info.s, info.t, info.v) == (s, t, v)
+        sw = O.output_symmetry(sub, su, sv)
+        assert info.w_signs.decode() == sw.sign_string() and info.w_charge == sw.charge
+        # the globally flipped rule is accepted as W, anything else is not
+        flip = "".join("+" if c == "-" else "-" for c in sw.sign_string())
+        rc2, _ = _plan(sub, orders, _desc(su.sign_string(), su.charge, su.dims),
+                       _desc(sv.sign_string(), sv.charge, sv.dims),
+                       _desc(flip, g.neg(sw.charge), sw.dims))
+        assert rc2 == 0
+        if g.size > 2:
+            rc3, _ = _plan(sub, orders, _desc(su.sign_string(), su.charge, su.dims),
+                           _desc(sv.sign_string(), sv.charge, sv.dims),
+                           _desc(sw.sign_string(), g.add(sw.charge, 1), sw.dims))
+            assert rc3 == L.SYMT_ESYM
+
+
+U4 = ("++--", 0, (2, 2, 2, 2))
+
+
+@pytest.mark.parametrize("sub,code", [
+    ("abkl,klij", L.SYMT_EEINSUM),            # no arrow
+    ("abkl,klij->abij,x", L.SYMT_EEINSUM),
+    ("aakl,klij->abij", L.SYMT_EEINSUM),      # repeated letter
+    ("abkl,klaj->abj", L.SYMT_EEINSUM),       # 'a' in all three terms (batch)
+    ("abkl,klij->abi", L.SYMT_EEINSUM),       # 'j' only in v (trace)
+    ("abkl,klij->abijx", L.SYMT_EEINSUM),     # output letter in no input
+    ("ab1l,klij->abij", L.SYMT_EEINSUM),      # not a letter
+    ("abkl,abkl->", L.SYMT_EEINSUM),          # full contraction: s = t = 0
+])
+def test_einsum_errors(sub, code):
+    rc, _ = _plan(sub, 4, _desc(*U4), _desc(*U4))
+    assert rc == code, L.last_error()
+
+
+def test_symmetry_and_size_errors():
+    good = _desc(*U4)
+    assert _plan("abkl,klij->abij", 4, good, good)[0] == 0
+    # mixed sign ratio over the two contracted modes
+    assert _plan("abkl,klij->abij", 4, good, _desc("+---", 0, (2, 2, 2, 2)))[0] == L.SYMT_ESYM
+    # output rule not the derived one
+    assert _plan("abkl,klij->abij", 4, good, good, _desc("++-+", 0, (2, 2, 2, 2)))[0] == L.SYMT_ESYM
+    assert _plan("abkl,klij->abij", 4, good, good, _desc("++--", 1, (2, 2, 2, 2)))[0] == L.SYMT_ESYM
+    # flipped output rule is the same rule
+    assert _plan("abkl,klij->abij", 4, good, good, _desc("--++", 0, (2, 2, 2, 2)))[0] == 0
+    # bad sign characters / length, charge out of range
+    assert _plan("abkl,klij->abij", 4, _desc("++-x", 0, (2, 2, 2, 2)), good)[0] == L.SYMT_ESYM
+    assert _plan("abkl,klij->abij", 4, _desc("++-", 0, (2, 2, 2)), good)[0] == L.SYMT_EINVAL
+    assert _plan("abkl,klij->abij", 4, _desc("++--", 4, (2, 2, 2, 2)), good)[0] == L.SYMT_ESYM
+    # contracted block sizes differ
+    assert _plan("abkl,klij->abij", 4, good, _desc("++--", 0, (3, 2, 2, 2)))[0] == L.SYMT_EINVAL
+    # output block sizes differ
+    assert _plan("abkl,klij->abij", 4, good, good, _desc("++--", 0, (2, 2, 2, 3)))[0] == L.SYMT_EINVAL
+    # negative dims, bad dtype, bad compute, bad group
+    assert _plan("abkl,klij->abij", 4, _desc("++--", 0, (2, -1, 2, 2)), good)[0] == L.SYMT_EINVAL
+    assert _plan("abkl,klij->abij", 4, _desc("++--", 0, (2, 2, 2, 2), dtype=7), good)[0] == L.SYMT_EDTYPE
+    assert _plan("abkl,klij->abij", 4, good, good, compute=9)[0] == L.SYMT_EDTYPE
+    assert _plan("abkl,klij->abij", (0,), good, good)[0] == L.SYMT_EINVAL
+    bad = L.SymtGroup()
+    bad.nfactors = 5
+    info = L.SymtPlanInfo()
+    assert L.LIB.symtensor_plan(b"abkl,klij->abij", ctypes.byref(bad), good.ref, good.ref, None, 0,
+                                ctypes.byref(info)) == L.SYMT_EINVAL
+
+
+def test_null_arguments():
+    info = L.SymtPlanInfo()
+    g = L.make_group(4)
+    good = _desc(*U4)
+    assert L.LIB.symtensor_plan(None, ctypes.byref(g), good.ref, good.ref, None, 0, ctypes.byref(info)) == L.SYMT_EINVAL
+    assert L.LIB.symtensor_plan(b"abkl,klij->abij", None, good.ref, good.ref, None, 0, ctypes.byref(info)) == L.SYMT_EINVAL
+    assert L.LIB.symtensor_plan(b"abkl,klij->abij", ctypes.byref(g), None, good.ref, None, 0, ctypes.byref(info)) == L.SYMT_EINVAL
+    assert L.LIB.symtensor_plan(b"abkl,klij->abij", ctypes.byref(g), good.ref, good.ref, None, 0, None) == L.SYMT_EINVAL
+    assert L.last_error() != ""
+    # context-taking calls reject a NULL context before touching the device
+    assert L.LIB.symtensor_contract(None, b"abkl,klij->abij", ctypes.byref(g), good.ref, good.ref, good.ref,
+                                    0, None, 0, None) == L.SYMT_EINVAL
+    assert L.LIB.symtensor_sector_gemm(None, 0, 1, 1, 1, 1, None, None, None, None) == L.SYMT_EINVAL
+    assert L.LIB.symtensor_destroy(None) == 0
+
+
+def test_workspace_sizes_per_compute_mode():
+    u = _desc("++--", 0, (3, 3, 3, 3))
+    v = _desc("++--", 0, (3, 3, 2, 2))
+    sizes = {}
+    for name, code in L.COMPUTE.items():
+        s = ctypes.c_size_t()
+        assert L.LIB.symtensor_workspace_size(b"abcd,cdij->abij", ctypes.byref(L.make_group(4)), u.ref,
+                                              v.ref, None, code, ctypes.byref(s)) == 0
+        sizes[name] = s.value
+    eu, ev, ew = 4 ** 3 * 81, 4 ** 3 * 36, 4 ** 3 * 36
+    r = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    assert sizes["f64"] == r(8 * eu) + r(8 * ev) + r(8 * ew)
+    assert sizes["f32"] == r(4 * eu) + r(4 * ev) + r(4 * ew)
+    assert sizes["bf16x3"] == r(4 * eu) + r(4 * ev) + r(8 * ew)
+
+
+def test_status_strings():
+    for code in range(-8, 1):
+        assert L.status_string(code) not in ("", "unknown status")
+    assert L.status_string(-99) == "unknown status"

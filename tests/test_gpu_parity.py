@@ -1,0 +1,289 @@
+"""GPU parity of every step of the HIP path against the CPU oracle (MI355X).
+
+Each test prints what names its case before touching the GPU.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from synth import philox
+from tests import gpu_helpers as H
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2007_08056_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def SG():
+    import synth.gpu as SG
+    return SG
+
+
+def _sym_tensor(P, R: np.ndarray, sym: O.Sym, dtype=torch.float64):
+    return P.SymTensor(torch.from_numpy(np.ascontiguousarray(R)).to(DEV, dtype), sym.sign_string(),
+                       sym.charge, sym.group.orders)
+
+
+# ---------------------------------------------------------------------------
+# synthetic inputs: GPU generator == NumPy generator, bit for bit
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dist,scale", [(philox.DIST_UNIFORM, 1.0), (philox.DIST_NORMAL, 1.0),
+                                        (philox.DIST_NORMAL, 1e-2)])
+def test_generator_bit_exact(SG, dist, scale):
+    say(f"generator dist={dist} scale={scale}")
+    first = (1 << 33) + 12345
+    n = 100_003
+    ref = philox.values_at(np.arange(first, first + n, dtype=np.int64), 99, 7, dist, scale)
+    t = torch.empty(n, dtype=torch.float64, device=DEV)
+    SG.fill_(t, 99, 7, dist, scale, first=first)
+    assert np.array_equal(H.to_np(t), ref)
+    t32 = torch.empty(n, dtype=torch.float32, device=DEV)
+    SG.fill_(t32, 99, 7, dist, scale, first=first)
+    assert np.array_equal(H.to_np(t32), ref.astype(np.float32))
+
+
+# ---------------------------------------------------------------------------
+# step (b) alone: sector-batched products
+# ---------------------------------------------------------------------------
+GEMM_SHAPES = [(1, 16, 4, 16), (3, 64, 64, 64), (2, 130, 50, 70), (4, 200, 96, 288), (1, 1, 1, 1),
+               (2, 257, 33, 47), (6, 300, 48, 48), (1, 128, 128, 128), (5, 17, 0, 9)]
+
+
+@pytest.mark.parametrize("shape", GEMM_SHAPES)
+@pytest.mark.parametrize("compute", ["f64", "f32"])
+def test_sector_gemm_fp(P, shape, compute):
+    say(f"sector_gemm {compute} {shape}")
+    b, m, k, n = shape
+    rng = np.random.default_rng(m * 1000 + n)
+    A = rng.standard_normal((b, m, k))
+    B = rng.standard_normal((b, k, n))
+    dt = torch.float64 if compute == "f64" else torch.float32
+    a = torch.from_numpy(A).to(DEV, dt)
+    bb = torch.from_numpy(B).to(DEV, dt)
+    C = H.to_np(P.sector_gemm(a, bb, compute))
+    A = H.to_np(a).astype(np.float64)
+    B = H.to_np(bb).astype(np.float64)
+    ref = np.matmul(A, B)
+    absb = np.matmul(np.abs(A), np.abs(B))
+    fac = 2 * H.gamma(max(k, 1), H.U64) if compute == "f64" else 1.05 * H.gamma(max(k, 1), H.U32)
+    assert np.all(np.abs(C - ref) <= fac * absb + 1e-300), compute
+
+
+@pytest.mark.parametrize("shape", [(1, 16, 32, 16), (3, 64, 64, 64), (2, 130, 56, 70), (4, 200, 96, 288),
+                                   (2, 257, 40, 47), (6, 300, 48, 48), (1, 128, 256, 128)])
+def test_sector_gemm_bf16x3(P, shape):
+    say(f"sector_gemm bf16x3 {shape}")
+    b, m, k, n = shape
+    rng = np.random.default_rng(m * 7 + n)
+    A = rng.standard_normal((b, m, k)).astype(np.float32)
+    B = rng.standard_normal((b, k, n)).astype(np.float32)
+    ah, al = O.bf16_split(A)
+    bh, bl = O.bf16_split(np.ascontiguousarray(np.swapaxes(B, 1, 2)))   # [b][n][k]
+    bits = lambda x: (x.view(np.uint32) >> 16).astype(np.uint16).view(np.int16)  # noqa: E731
+    a = torch.from_numpy(np.stack([bits(ah), bits(al)])).to(DEV)
+    bb = torch.from_numpy(np.stack([bits(bh), bits(bl)])).to(DEV)
+    C = H.to_np(P.sector_gemm(a, bb, "bf16x3"))
+    ah64, al64 = ah.astype(np.float64), al.astype(np.float64)
+    bh64 = np.swapaxes(bh, 1, 2).astype(np.float64)
+    bl64 = np.swapaxes(bl, 1, 2).astype(np.float64)
+    ref = np.matmul(ah64, bh64) + np.matmul(ah64, bl64) + np.matmul(al64, bh64)
+    absb = (np.matmul(np.abs(ah64), np.abs(bh64)) + np.matmul(np.abs(ah64), np.abs(bl64))
+            + np.matmul(np.abs(al64), np.abs(bh64)))
+    assert np.all(np.abs(C - ref) <= 1.1 * H.gamma(k, H.U32) * absb)
+    # and the three-term product is within the split bound of the binary32 product
+    full = np.matmul(A.astype(np.float64), B.astype(np.float64))
+    absf = np.matmul(np.abs(A.astype(np.float64)), np.abs(B.astype(np.float64)))
+    assert np.all(np.abs(C - full) <= (3.1 * H.U_BF16_PAIR + 1.1 * H.gamma(k, H.U32)) * absf)
+
+
+# ---------------------------------------------------------------------------
+# steps (a) and (c) alone: bit-exact against Alg. 2 with dense deltas
+# ---------------------------------------------------------------------------
+ALIGN_CASES = [((4,), 2, 2, 2), ((3,), 1, 1, 1), ((2, 3), 2, 2, 1), ((5,), 1, 3, 2), ((2,), 3, 1, 2),
+               ((2, 2), 2, 1, 2), ((1,), 2, 2, 2), ((8,), 1, 1, 1), ((3,), 3, 2, 2)]
+
+
+def _bf16_planes_of(x64):
+    hi, lo = O.bf16_split(x64.astype(np.float32))
+    return (hi.view(np.uint32) >> 16).astype(np.uint16), (lo.view(np.uint32) >> 16).astype(np.uint16)
+
+
+@pytest.mark.parametrize("case", ALIGN_CASES)
+def test_align_and_unalign_bit_exact(P, case):
+    orders, ns, nt, nv = case
+    rng = np.random.default_rng(abs(hash(case)) % 2 ** 32)
+    for rep in range(3):
+        sub, su, sv = H.random_case(rng, orders, ns, nt, nv, nmax=4)
+        say(f"align {sub} G={orders} rep={rep} dims_u={su.dims} dims_v={sv.dims}")
+        Ru = rng.standard_normal(su.reduced_shape())
+        Rv = rng.standard_normal(sv.reduced_shape())
+        u = _sym_tensor(P, Ru, su)
+        v = _sym_tensor(P, Rv, sv)
+        Ual = O.align_u(sub, Ru, su, sv)
+        Val = O.align_v(sub, Rv, su, sv)
+        assert np.array_equal(H.to_np(P.align(sub, u, v, 0, "f64")), Ual)
+        assert np.array_equal(H.to_np(P.align(sub, u, v, 1, "f64")), Val)
+        assert np.array_equal(H.to_np(P.align(sub, u, v, 0, "f32")), Ual.astype(np.float32))
+        # f32 storage in, f32 aligned out
+        u32 = P.SymTensor(u.data.float(), u.signs, u.charge, u.group)
+        assert np.array_equal(H.to_np(P.align(sub, u32, v, 0, "f32")), Ual.astype(np.float32))
+        # split bf16 planes: U as (2, G, M, K); V transposed (2, G, N, K)
+        gu = H.to_np(P.align(sub, u, v, 0, "bf16x3")).view(np.uint16)
+        hi, lo = _bf16_planes_of(Ual)
+        assert np.array_equal(gu[0], hi) and np.array_equal(gu[1], lo)
+        gv = H.to_np(P.align(sub, u, v, 1, "bf16x3")).view(np.uint16)
+        hi, lo = _bf16_planes_of(np.ascontiguousarray(np.swapaxes(Val, 1, 2)))
+        assert np.array_equal(gv[0], hi) and np.array_equal(gv[1], lo)
+        # step (c): random aligned output -> standard form of W
+        Wal = rng.standard_normal(np.matmul(Ual, Val).shape)
+        ref, sw = O.unalign_w(sub, Wal, su, sv)
+        w = P.output_like(sub, u, v)
+        P.unalign(sub, u, v, w, torch.from_numpy(Wal).to(DEV), "f64")
+        assert np.array_equal(H.to_np(w.data), ref)
+        w32 = P.output_like(sub, u, v, dtype=torch.float32)
+        P.unalign(sub, u, v, w32, torch.from_numpy(Wal).to(DEV, torch.float32), "f32")
+        assert np.array_equal(H.to_np(w32.data), ref.astype(np.float32))
+
+
+# ---------------------------------------------------------------------------
+# whole path on random contractions
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ALIGN_CASES)
+def test_contract_random_vs_oracle(P, case):
+    orders, ns, nt, nv = case
+    rng = np.random.default_rng(abs(hash(case)) % 2 ** 31 + 1)
+    for rep in range(2):
+        sub, su, sv = H.random_case(rng, orders, ns, nt, nv, nmax=5)
+        say(f"contract {sub} G={orders} rep={rep}")
+        Ru = rng.standard_normal(su.reduced_shape())
+        Rv = rng.standard_normal(sv.reduced_shape())
+        ref, sw = O.contract_blocks(sub, Ru, su, Rv, sv)
+        absref, _ = O.contract_blocks(sub, np.abs(Ru), su, np.abs(Rv), sv)
+        k = H.contracted_extent(sub, su)
+        u = _sym_tensor(P, Ru, su)
+        vv = _sym_tensor(P, Rv, sv)
+        for compute in ("f64", "f32", "bf16x3"):
+            info = P.plan(sub, u, vv, compute)
+            if compute == "bf16x3" and info.k % 8:
+                continue
+            w = P.output_like(sub, u, vv)
+            P.contract_into(sub, u, vv, w, compute)
+            got = H.to_np(w.data)
+            assert w.signs == sw.sign_string() and w.charge == sw.charge
+            assert np.all(np.abs(got - ref) <= H.bound_factor(compute, k) * absref + 1e-300), compute
+            if compute == "f64":
+                assert H.rel_err(got, ref) <= 1e-12
+                # zero pattern of the full tensor is identical
+                assert np.array_equal(O.expand(got, sw) == 0, O.expand(ref, sw) == 0)
+
+
+def test_degenerate_shapes(P):
+    rng = np.random.default_rng(11)
+    g = O.Group(3)
+    # an empty contracted block dim: W is all zeros
+    su = O.Sym.make("+-", 0, (3, 0), g)
+    sv = O.Sym.make("+-", 0, (0, 2), g)
+    say("degenerate: empty contracted dim")
+    u = _sym_tensor(P, np.zeros(su.reduced_shape()), su)
+    v = _sym_tensor(P, np.zeros(sv.reduced_shape()), sv)
+    w = P.output_like("ij,jk->ik", u, v)
+    w.data.fill_(7.0)
+    P.contract_into("ij,jk->ik", u, v, w)
+    assert np.all(H.to_np(w.data) == 0.0)
+    # an empty output
+    su = O.Sym.make("+-", 0, (0, 2), g)
+    sv = O.Sym.make("+-", 0, (2, 2), g)
+    say("degenerate: empty output")
+    u = _sym_tensor(P, np.zeros(su.reduced_shape()), su)
+    v = _sym_tensor(P, rng.standard_normal(sv.reduced_shape()), sv)
+    w = P.output_like("ij,jk->ik", u, v)
+    P.contract_into("ij,jk->ik", u, v, w)
+    assert w.data.numel() == 0
+    # the trivial group is a plain product
+    say("degenerate: trivial group")
+    g1 = O.Group(1)
+    su = O.Sym.make("++-", 0, (5, 3, 7), g1)
+    sv = O.Sym.make("+-", 0, (7, 4), g1)
+    Ru, Rv = rng.standard_normal(su.reduced_shape()), rng.standard_normal(sv.reduced_shape())
+    w = P.output_like("abk,kc->acb", _sym_tensor(P, Ru, su), _sym_tensor(P, Rv, sv))
+    P.contract_into("abk,kc->acb", _sym_tensor(P, Ru, su), _sym_tensor(P, Rv, sv), w)
+    ref = np.einsum("abk,kc->acb", Ru.reshape(5, 3, 7), Rv.reshape(7, 4))
+    np.testing.assert_allclose(H.to_np(w.data).reshape(ref.shape), ref, rtol=1e-13, atol=1e-13)
+
+
+def test_misaligned_views_take_the_scalar_path(P):
+    rng = np.random.default_rng(12)
+    g = O.Group(4)
+    su = O.Sym.make("++--", 1, (2, 3, 2, 2), g)
+    sv = O.Sym.make("++--", 2, (2, 2, 3, 1), g)
+    Ru, Rv = rng.standard_normal(su.reduced_shape()), rng.standard_normal(sv.reduced_shape())
+    say("misaligned views")
+    # views starting one element into a larger buffer: 8-byte but not 16-byte aligned
+    bu = torch.zeros(Ru.size + 1, dtype=torch.float64, device=DEV)
+    bu[1:] = torch.from_numpy(Ru.ravel()).to(DEV)
+    bv = torch.zeros(Rv.size + 1, dtype=torch.float64, device=DEV)
+    bv[1:] = torch.from_numpy(Rv.ravel()).to(DEV)
+    u = P.SymTensor(bu[1:].view(su.reduced_shape()), "++--", 1, (4,))
+    v = P.SymTensor(bv[1:].view(sv.reduced_shape()), "++--", 2, (4,))
+    bw = torch.zeros(1 + int(np.prod(O.output_symmetry("abkl,klij->abij", su, sv).reduced_shape())),
+                     dtype=torch.float64, device=DEV)
+    sw = O.output_symmetry("abkl,klij->abij", su, sv)
+    w = P.SymTensor(bw[1:].view(sw.reduced_shape()), sw.sign_string(), sw.charge, (4,))
+    P.contract_into("abkl,klij->abij", u, v, w)
+    ref, _ = O.contract_blocks("abkl,klij->abij", Ru, su, Rv, sv)
+    assert H.rel_err(H.to_np(w.data), ref) <= 1e-13
+
+
+def test_error_paths_on_device(P):
+    from paper_2007_08056_amd import _lib as L
+    rng = np.random.default_rng(13)
+    g = O.Group(4)
+    su = O.Sym.make("++--", 0, (2, 2, 2, 2), g)
+    u = _sym_tensor(P, rng.standard_normal(su.reduced_shape()), su)
+    v = _sym_tensor(P, rng.standard_normal(su.reduced_shape()), su)
+    w = P.output_like("abkl,klij->abij", u, v)
+    say("errors: workspace too small")
+    with pytest.raises(L.SymtError) as e:
+        info = P.plan("abkl,klij->abij", u, v)
+        ws = torch.empty(info.workspace_bytes - 1, dtype=torch.uint8, device=DEV)
+        import ctypes
+        gg = L.make_group(4)
+        L.check(L.LIB.symtensor_contract(L.context(0), b"abkl,klij->abij", ctypes.byref(gg), u.desc().ref,
+                                         v.desc().ref, w.desc().ref, 0, ctypes.c_void_p(ws.data_ptr()),
+                                         ws.numel(), None), L.context(0))
+    assert e.value.code == L.SYMT_EWORKSPACE
+    say("errors: output aliases an input")
+    w_alias = P.SymTensor(u.data, "++--", 0, (4,))
+    with pytest.raises(L.SymtError) as e:
+        P.contract_into("abkl,klij->abij", u, v, w_alias)
+    assert e.value.code == L.SYMT_EALIAS
+    say("errors: mixed signs")
+    v_bad = P.SymTensor(v.data, "+---", 0, (4,))
+    with pytest.raises(L.SymtError) as e:
+        P.contract_into("abkl,klij->abij", u, v_bad, w)
+    assert e.value.code == L.SYMT_ESYM
+    # nothing was written by the failed calls
+    before = w.data.clone()
+    with pytest.raises(L.SymtError):
+        P.contract_into("abkl,klij->abij", u, v_bad, w)
+    torch.cuda.synchronize()
+    assert torch.equal(before, w.data)
