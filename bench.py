@@ -100,6 +100,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--extra", default="", help="write per-kernel details to this JSON file")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="also run one plain elementwise kernel that reads and writes 256 MiB "
+                         "(the reference for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the contraction is benchmarked on a single MI355X "
@@ -123,6 +126,12 @@ def main():
     ws = torch.empty(info.workspace_bytes, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
+    if args.calibrate:
+        x = torch.ones(32 * 2 ** 20, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        del x, y
     for _ in range(args.warmup):
         P.contract_into(st.einsum, u, v, w, "f64", ws)
     torch.cuda.synchronize()

@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
+#include <cstring>
 #include <string>
 
 #include "plan.hpp"
@@ -358,9 +360,53 @@ hipError_t launch_bf16x3(int64_t batch, int M, int N, int K, const void* A, cons
   return hipGetLastError();
 }
 
-// Padded work of a tiling (smaller is better), used to pick a tile shape.
-double padded(int64_t M, int64_t N, int bm, int bn) {
-  return static_cast<double>((M + bm - 1) / bm * bm) * static_cast<double>((N + bn - 1) / bn * bn);
+// One f64/f32 tile configuration.
+struct FpTile {
+  const char* name;
+  int bm, bn;
+};
+constexpr FpTile kFpTiles[] = {
+    {"128x128", 128, 128}, {"128x96", 128, 96}, {"128x64", 128, 64}, {"128x48", 128, 48},
+    {"144x96", 144, 96},   {"96x96", 96, 96},   {"256x96", 256, 96}, {"192x96", 192, 96},
+};
+constexpr int kNumFpTiles = sizeof(kFpTiles) / sizeof(kFpTiles[0]);
+
+template <typename T>
+hipError_t launch_fp_tile(int idx, int vec, int64_t batch, int M, int N, int K, const void* A,
+                          const void* B, void* C, hipStream_t s) {
+  switch (idx) {
+    case 0: return launch_fp<T, 128, 128, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s);
+    case 1: return launch_fp<T, 128, 96, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s);
+    case 2: return launch_fp<T, 128, 64, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s);
+    case 3: return launch_fp<T, 128, 48, 16, 4, 1>(vec, batch, M, N, K, A, B, C, s);
+    case 4: return launch_fp<T, 144, 96, 16, 3, 2>(vec, batch, M, N, K, A, B, C, s);
+    case 5: return launch_fp<T, 96, 96, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s);
+    case 6: return launch_fp<T, 256, 96, 16, 4, 2>(vec, batch, M, N, K, A, B, C, s);
+    default: return launch_fp<T, 192, 96, 16, 3, 2>(vec, batch, M, N, K, A, B, C, s);
+  }
+}
+
+// Estimated cost of a tiling in units of one (BM x BN) tile's work: padded work,
+// rounded up to whole waves of tiles over the 256 compute units (each tile is
+// assumed to run on one CU at a time).
+double tile_cost(int64_t batch, int64_t M, int64_t N, int bm, int bn) {
+  const int64_t tiles = batch * ((M + bm - 1) / bm) * ((N + bn - 1) / bn);
+  const int64_t waves = (tiles + 255) / 256;
+  return static_cast<double>(waves) * bm * bn;
+}
+
+int pick_fp_tile(int64_t batch, int64_t M, int64_t N) {
+  const char* forced = std::getenv("SYMT_GEMM_TILE");
+  if (forced)
+    for (int i = 0; i < kNumFpTiles; ++i)
+      if (std::strcmp(forced, kFpTiles[i].name) == 0) return i;
+  int best = 0;
+  double best_cost = 0;
+  for (int i = 0; i < 4; ++i) {
+    const double c = tile_cost(batch, M, N, kFpTiles[i].bm, kFpTiles[i].bn);
+    if (i == 0 || c < best_cost) { best = i; best_cost = c; }
+  }
+  return best;
 }
 
 }  // namespace
@@ -387,29 +433,9 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
     const bool f64 = compute == SYMT_COMPUTE_F64;
     const int vw = f64 ? 2 : 4;
     const int vec = (K % vw == 0 && N % vw == 0) ? vw : 1;
-    // candidate tiles: (128,128), (128,96), (128,64), (128,48)
-    const double c128 = padded(M, N, 128, 128), c96 = padded(M, N, 128, 96),
-                 c64 = padded(M, N, 128, 64), c48 = padded(M, N, 128, 48);
-    double best = c128;
-    int pick = 0;
-    if (c96 < best) { best = c96; pick = 1; }
-    if (c64 < best) { best = c64; pick = 2; }
-    if (c48 < best) { best = c48; pick = 3; }
-    if (f64) {
-      switch (pick) {
-        case 0: e = launch_fp<double, 128, 128, 16, 2, 2>(vec, batch, M, N, K, A, B, C, stream); break;
-        case 1: e = launch_fp<double, 128, 96, 16, 2, 2>(vec, batch, M, N, K, A, B, C, stream); break;
-        case 2: e = launch_fp<double, 128, 64, 16, 2, 2>(vec, batch, M, N, K, A, B, C, stream); break;
-        default: e = launch_fp<double, 128, 48, 16, 4, 1>(vec, batch, M, N, K, A, B, C, stream); break;
-      }
-    } else {
-      switch (pick) {
-        case 0: e = launch_fp<float, 128, 128, 16, 2, 2>(vec, batch, M, N, K, A, B, C, stream); break;
-        case 1: e = launch_fp<float, 128, 96, 16, 2, 2>(vec, batch, M, N, K, A, B, C, stream); break;
-        case 2: e = launch_fp<float, 128, 64, 16, 2, 2>(vec, batch, M, N, K, A, B, C, stream); break;
-        default: e = launch_fp<float, 128, 48, 16, 4, 1>(vec, batch, M, N, K, A, B, C, stream); break;
-      }
-    }
+    const int tile = pick_fp_tile(batch, M, N);
+    e = f64 ? launch_fp_tile<double>(tile, vec, batch, M, N, K, A, B, C, stream)
+            : launch_fp_tile<float>(tile, vec, batch, M, N, K, A, B, C, stream);
   }
   if (e != hipSuccess) {
     if (err) *err = std::string("sector product launch: ") + hipGetErrorString(e);
