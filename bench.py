@@ -148,6 +148,21 @@ def main():
     ms_step = (t1 - t0) * 1e3 / args.steps
     value = info.flops / (ms_step * 1e-3) / 1e9
 
+    # the three separate steps on the same inputs: per-transform HBM rates
+    wsteps = P.output_like(st.einsum, u, v)
+    for _ in range(2):
+        P.contract_into(st.einsum, u, v, wsteps, "f64", steps=True)
+    torch.cuda.synchronize()
+    P.read_timing(0)
+    P.set_timing(0, True)
+    for _ in range(5):
+        P.contract_into(st.einsum, u, v, wsteps, "f64", steps=True)
+    torch.cuda.synchronize()
+    P.set_timing(0, False)
+    ms_s, launches_s = P.read_timing(0)
+    same = bool(torch.equal(wsteps.data, w.data))
+    del wsteps
+
     gemm_ms = ms[2] / max(1, launches[2])
     achieved = info.flops / (gemm_ms * 1e-3) / 1e12
     digest = source_digest("paper_2007_08056_amd/csrc/gemm.hip")
@@ -156,14 +171,20 @@ def main():
                 "frac": round(achieved / PEAK["f64"], 4), "traffic": traffic}
 
     extra = {
+        "fused": bool(info.fused),
         "kernel_ms_per_launch": {name: (ms[i] / launches[i] if launches[i] else None)
-                                 for i, name in enumerate(("align_u", "align_v", "sector_gemm", "unalign_w"))},
+                                 for i, name in enumerate(("offset_tables" if info.fused else "align_u",
+                                                           "align_v", "sector_gemm", "unalign_w"))},
+        "steps_kernel_ms_per_launch": {name: (ms_s[i] / launches_s[i] if launches_s[i] else None)
+                                       for i, name in enumerate(("align_u", "align_v", "sector_gemm",
+                                                                 "unalign_w"))},
+        "steps_result_identical_to_fused": same,
         "shape": {"batch": info.group_size, "m": info.m, "k": info.k, "n": info.n},
         "flops": info.flops,
         "bytes_u": info.elems_u * 8, "bytes_v": info.elems_v * 8, "bytes_w": info.elems_w * 8,
         "gemm_source_digest": digest,
     }
-    xf = extra["kernel_ms_per_launch"]
+    xf = extra["steps_kernel_ms_per_launch"]
     for key, nbytes in (("align_u", 2 * info.elems_u * 8), ("align_v", 2 * info.elems_v * 8),
                         ("unalign_w", 2 * info.elems_w * 8)):
         if xf[key]:

@@ -54,6 +54,18 @@
  *   nearest even; the product is hi*hi + hi*lo + lo*hi with binary32
  *   accumulation (two accumulators) and a binary64 sum of the two at the end.
  *
+ * FUSED PRODUCT.  The standard-form offset of aligned element (Q, r, c) of any
+ * operand splits as R(Q, r) + C(Q, c) (the block index and the in-block offset
+ * are linear in the sectors and indices, and each implicit sector belongs to one
+ * sector group).  When compute is F64 or F32, u is stored in the compute type,
+ * w (if given) too, u's last v modes are exactly its contracted modes and their
+ * block size is a multiple of 16, symtensor_contract builds the four offset
+ * tables of U and W in the workspace and runs one product that reads A straight
+ * from u's standard form and writes C straight into w's, so U_al and W_al are
+ * never materialised; only V is aligned.  The workspace then holds V_al and the
+ * tables (info.fused = 1) and is much smaller.  Results are identical in value
+ * to the three-step path up to the product's summation order, which is the same.
+ *
  * Execution and ownership.  Every device buffer (operand data, workspace,
  * aligned buffers) is allocated and owned by the caller.  A context holds only
  * host state; it allocates no device memory.  Functions taking a stream
@@ -100,6 +112,11 @@ typedef enum {
   SYMT_COMPUTE_BF16X3 = 2  /* split-bfloat16 three-term products (see above) */
 } symt_compute;
 
+/* OR-ed into a compute argument of symtensor_plan / workspace_size / contract:
+ * run the three separate steps (align U, align V, product, unalign W) even
+ * where the fused product applies (see FUSED PRODUCT). */
+#define SYMT_FLAG_STEPS 0x100
+
 /* G = Z_order[0] x ... x Z_order[nfactors-1]; 1 <= nfactors <= SYMT_MAX_FACTORS. */
 typedef struct {
   int32_t nfactors;
@@ -131,6 +148,7 @@ typedef struct {
   size_t workspace_bytes;          /* what symtensor_contract needs */
   char w_signs[SYMT_MAX_ORDER + 1];/* derived output sign string (tw order), NUL-terminated */
   int32_t w_charge;                /* derived output charge */
+  int32_t fused;                   /* 1 if symtensor_contract will run the fused product */
 } symt_plan_info;
 
 typedef struct symt_ctx symt_ctx;
@@ -158,8 +176,10 @@ int symtensor_workspace_size(const char* einsum, const symt_group* group, const 
 
 /* W = contraction of U and V (Eq. ctr), written over w->data in W's standard
  * reduced form: steps (a), (b), (c) above, enqueued on `stream`.  `workspace`
- * is a caller-owned device buffer of at least info.workspace_bytes bytes
- * holding U_al, V_al and W_al (256-byte aligned sub-buffers, in that order).
+ * is a caller-owned, 16-byte aligned device buffer of at least
+ * info.workspace_bytes bytes holding U_al, V_al and W_al (256-byte aligned
+ * sub-buffers, in that order), or for the fused product V_al and the offset
+ * tables.
  * w->data must not overlap u->data, v->data or the workspace (SYMT_EALIAS).
  * Storage dtypes: SYMT_COMPUTE_F64 takes any mix of F64/F32 operands
  * (converted exactly to binary64); SYMT_COMPUTE_F32 and BF16X3 take any mix,

@@ -29,6 +29,7 @@ SYMT_EHIP = -8
 SYMT_F64 = 0
 SYMT_F32 = 1
 COMPUTE = {"f64": 0, "f32": 1, "bf16x3": 2}
+SYMT_FLAG_STEPS = 0x100
 
 EXPORTED = (
     "symtensor_create", "symtensor_destroy", "symtensor_plan", "symtensor_workspace_size",
@@ -53,7 +54,7 @@ class SymtPlanInfo(ctypes.Structure):
                 ("elems_u", c_int64), ("elems_v", c_int64), ("elems_w", c_int64),
                 ("flops", c_double), ("bytes_u_al", c_size_t), ("bytes_v_al", c_size_t),
                 ("bytes_w_al", c_size_t), ("workspace_bytes", c_size_t),
-                ("w_signs", c_char * (SYMT_MAX_ORDER + 1)), ("w_charge", c_int32)]
+                ("w_signs", c_char * (SYMT_MAX_ORDER + 1)), ("w_charge", c_int32), ("fused", c_int32)]
 
 
 class SymtError(RuntimeError):

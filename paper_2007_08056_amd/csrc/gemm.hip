@@ -66,13 +66,27 @@ struct alignas(sizeof(T) * V) VecT {
 // f64 / f32: C = A B, A [Q][M][K], B [Q][K][N], C [Q][M][N], row-major.
 // V: elements per global vector access (16 bytes, or 1 when K or N is odd).
 // ---------------------------------------------------------------------------
-template <typename T, int BM, int BN, int BK, int WM, int WN, int V>
+// Fused forms (FA / FC): A is read straight from U's standard reduced form,
+// element (q, m, k) at ra[q*M + m] + ca[q*K + k], and C is written straight
+// into W's standard reduced form at rc[q*M + m] + cc[q*N + n] (separable offset
+// tables).  FA needs every BK-aligned run of K to be contiguous in U.
+template <typename T, int BM, int BN, int BK, int WM, int WN, int V, bool FA, bool FC>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
                                                        const T* __restrict__ B,
                                                        T* __restrict__ C, int M, int N, int K,
-                                                       int tiles_m, int tiles_n, int64_t ntiles) {
+                                                       int tiles_m, int tiles_n, int64_t ntiles,
+                                                       const int64_t* __restrict__ ra,
+                                                       const int64_t* __restrict__ ca,
+                                                       const int64_t* __restrict__ rc,
+                                                       const int64_t* __restrict__ cc) {
   constexpr int NT = 64 * WM * WN;
   constexpr int PAD = 16 / sizeof(T);
+  // B rows: a fragment read touches 16 consecutive n at 4 consecutive k; pad each
+  // row so that the 4 rows start 16 * sizeof(T) bytes apart modulo the 256-byte
+  // bank cycle, which keeps the four 16-lane groups on disjoint banks.
+  constexpr int ROWB = BN * static_cast<int>(sizeof(T));
+  constexpr int SHIFT = 16 * static_cast<int>(sizeof(T));
+  constexpr int PADB = ((SHIFT - ROWB % 256 + 256) % 256) / static_cast<int>(sizeof(T));
   constexpr int TM = BM / WM / 16;
   constexpr int TN = BN / WN / 16;
   static_assert(TM * WM * 16 == BM && TN * WN * 16 == BN, "tile shape");
@@ -82,16 +96,16 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
   using Acc = typename Mfma<T>::Acc;
 
   __shared__ T As[2][BM][BK + PAD];
-  __shared__ T Bs[2][BK][BN + PAD];
+  __shared__ T Bs[2][BK][BN + PADB];
 
   const int64_t tile = xcd_remap(blockIdx.x, ntiles);
   const int tn = static_cast<int>(tile % tiles_n);
   const int64_t t2 = tile / tiles_n;
   const int tm = static_cast<int>(t2 % tiles_m);
   const int64_t q = t2 / tiles_m;
-  const T* Aq = A + q * static_cast<int64_t>(M) * K;
+  const T* Aq = A + (FA ? 0 : q * static_cast<int64_t>(M) * K);
   const T* Bq = B + q * static_cast<int64_t>(K) * N;
-  T* Cq = C + q * static_cast<int64_t>(M) * N;
+  T* Cq = C + (FC ? 0 : q * static_cast<int64_t>(M) * N);
   const int m0 = tm * BM, n0 = tn * BN;
 
   const int tid = threadIdx.x;
@@ -100,18 +114,28 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
   const int wm0 = (wave / WN) * (BM / WM);
   const int wn0 = (wave % WN) * (BN / WN);
 
-  VecT<T, V> ra[LA], rb[LB];
+  // Fused A: the standard-form offset of each of this thread's tile rows.
+  int64_t arow[LA];
+#pragma unroll
+  for (int i = 0; i < LA; ++i) {
+    const int e = (tid + i * NT) * V;
+    const int gr = m0 + e / BK;
+    arow[i] = (FA && e < BM * BK && gr < M) ? ra[q * M + gr] : static_cast<int64_t>(gr) * K;
+  }
+
+  VecT<T, V> ra_[LA], rb[LB];
   auto load_tiles = [&](int k0) {
+    const int64_t acol = FA ? ca[q * K + k0] : k0;
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
       const int e = (tid + i * NT) * V;              // element index inside the BM x BK tile
       const int r = e / BK, c = e % BK;
       const int gr = m0 + r, gc = k0 + c;
       if (e < BM * BK && gr < M && gc < K)
-        ra[i] = *reinterpret_cast<const VecT<T, V>*>(Aq + static_cast<int64_t>(gr) * K + gc);
+        ra_[i] = *reinterpret_cast<const VecT<T, V>*>(Aq + arow[i] + acol + c);
       else
 #pragma unroll
-        for (int j = 0; j < V; ++j) ra[i].v[j] = T(0);
+        for (int j = 0; j < V; ++j) ra_[i].v[j] = T(0);
     }
 #pragma unroll
     for (int i = 0; i < LB; ++i) {
@@ -129,7 +153,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
       const int e = (tid + i * NT) * V;
-      if (e < BM * BK) *reinterpret_cast<VecT<T, V>*>(&As[buf][e / BK][e % BK]) = ra[i];
+      if (e < BM * BK) *reinterpret_cast<VecT<T, V>*>(&As[buf][e / BK][e % BK]) = ra_[i];
     }
 #pragma unroll
     for (int i = 0; i < LB; ++i) {
@@ -168,16 +192,20 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
   }
 
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int j = 0; j < TN; ++j) {
+    const int col = n0 + wn0 + j * 16 + (lane & 15);
+    const int64_t ccol = (FC && col < N) ? cc[q * N + col] : col;
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int col = n0 + wn0 + j * 16 + (lane & 15);
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm0 + i * 16 + Mfma<T>::row(lane, r);
-        if (row < M && col < N) Cq[static_cast<int64_t>(row) * N + col] = acc[i][j][r];
+        if (row < M && col < N) {
+          const int64_t crow = FC ? rc[q * M + row] : static_cast<int64_t>(row) * N;
+          Cq[crow + ccol] = acc[i][j][r];
+        }
       }
-    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -329,19 +357,27 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf16x3(
 
 template <typename T, int BM, int BN, int BK, int WM, int WN>
 hipError_t launch_fp(int vec, int64_t batch, int M, int N, int K, const void* A, const void* B,
-                     void* C, hipStream_t s) {
+                     void* C, hipStream_t s, const FusedTables* f) {
   const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
   const int64_t ntiles = batch * tiles_m * tiles_n;
   const dim3 grid(static_cast<unsigned>(ntiles)), block(64 * WM * WN);
   const T* a = static_cast<const T*>(A);
   const T* b = static_cast<const T*>(B);
   T* c = static_cast<T*>(C);
-  if (vec > 1)
-    hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, 16 / sizeof(T)>), grid, block, 0, s, a, b, c,
-                       M, N, K, tiles_m, tiles_n, ntiles);
-  else
-    hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, 1>), grid, block, 0, s, a, b, c, M, N, K,
-                       tiles_m, tiles_n, ntiles);
+  constexpr int VV = 16 / sizeof(T);
+  if (f && f->vec > 1) {
+    hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, VV, true, true>), grid, block, 0, s, a, b, c,
+                       M, N, K, tiles_m, tiles_n, ntiles, f->ra, f->ca, f->rc, f->cc);
+  } else if (f) {
+    hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, 1, true, true>), grid, block, 0, s, a, b, c,
+                       M, N, K, tiles_m, tiles_n, ntiles, f->ra, f->ca, f->rc, f->cc);
+  } else if (vec > 1) {
+    hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, VV, false, false>), grid, block, 0, s, a, b,
+                       c, M, N, K, tiles_m, tiles_n, ntiles, nullptr, nullptr, nullptr, nullptr);
+  } else {
+    hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, 1, false, false>), grid, block, 0, s, a, b, c,
+                       M, N, K, tiles_m, tiles_n, ntiles, nullptr, nullptr, nullptr, nullptr);
+  }
   return hipGetLastError();
 }
 
@@ -367,22 +403,27 @@ struct FpTile {
 };
 constexpr FpTile kFpTiles[] = {
     {"128x128", 128, 128}, {"128x96", 128, 96}, {"128x64", 128, 64}, {"128x48", 128, 48},
-    {"144x96", 144, 96},   {"96x96", 96, 96},   {"256x96", 256, 96}, {"192x96", 192, 96},
+    {"96x96", 96, 96},     {"256x96", 256, 96}, {"128x128k32", 128, 128}, {"128x48k32", 128, 48},
+    {"96x96k32", 96, 96},  {"256x128", 256, 128}, {"128x256", 128, 256}, {"64x96", 64, 96},
 };
 constexpr int kNumFpTiles = sizeof(kFpTiles) / sizeof(kFpTiles[0]);
 
 template <typename T>
 hipError_t launch_fp_tile(int idx, int vec, int64_t batch, int M, int N, int K, const void* A,
-                          const void* B, void* C, hipStream_t s) {
+                          const void* B, void* C, hipStream_t s, const FusedTables* f) {
   switch (idx) {
-    case 0: return launch_fp<T, 128, 128, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s);
-    case 1: return launch_fp<T, 128, 96, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s);
-    case 2: return launch_fp<T, 128, 64, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s);
-    case 3: return launch_fp<T, 128, 48, 16, 4, 1>(vec, batch, M, N, K, A, B, C, s);
-    case 4: return launch_fp<T, 144, 96, 16, 3, 2>(vec, batch, M, N, K, A, B, C, s);
-    case 5: return launch_fp<T, 96, 96, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s);
-    case 6: return launch_fp<T, 256, 96, 16, 4, 2>(vec, batch, M, N, K, A, B, C, s);
-    default: return launch_fp<T, 192, 96, 16, 3, 2>(vec, batch, M, N, K, A, B, C, s);
+    case 0: return launch_fp<T, 128, 128, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s, f);
+    case 1: return launch_fp<T, 128, 96, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s, f);
+    case 2: return launch_fp<T, 128, 64, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s, f);
+    case 3: return launch_fp<T, 128, 48, 16, 4, 1>(vec, batch, M, N, K, A, B, C, s, f);
+    case 4: return launch_fp<T, 96, 96, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s, f);
+    case 5: return launch_fp<T, 256, 96, 16, 4, 2>(vec, batch, M, N, K, A, B, C, s, f);
+    case 6: return launch_fp<T, 128, 128, 32, 2, 2>(vec, batch, M, N, K, A, B, C, s, f);
+    case 7: return launch_fp<T, 128, 48, 32, 4, 1>(vec, batch, M, N, K, A, B, C, s, f);
+    case 8: return launch_fp<T, 96, 96, 32, 2, 2>(vec, batch, M, N, K, A, B, C, s, f);
+    case 9: return launch_fp<T, 256, 128, 16, 4, 2>(vec, batch, M, N, K, A, B, C, s, f);
+    case 10: return launch_fp<T, 128, 256, 16, 2, 4>(vec, batch, M, N, K, A, B, C, s, f);
+    default: return launch_fp<T, 64, 96, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s, f);
   }
 }
 
@@ -412,7 +453,8 @@ int pick_fp_tile(int64_t batch, int64_t M, int64_t N) {
 }  // namespace
 
 int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t n, const void* A,
-                       const void* B, void* C, hipStream_t stream, std::string* err) {
+                       const void* B, void* C, hipStream_t stream, std::string* err,
+                       const FusedTables* fused) {
   if (batch == 0 || m == 0 || n == 0) return SYMT_OK;
   if (m > INT32_MAX || n > INT32_MAX || k > INT32_MAX) {
     if (err) *err = "sector product dimension above 2^31-1";
@@ -434,8 +476,8 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
     const int vw = f64 ? 2 : 4;
     const int vec = (K % vw == 0 && N % vw == 0) ? vw : 1;
     const int tile = pick_fp_tile(batch, M, N);
-    e = f64 ? launch_fp_tile<double>(tile, vec, batch, M, N, K, A, B, C, stream)
-            : launch_fp_tile<float>(tile, vec, batch, M, N, K, A, B, C, stream);
+    e = f64 ? launch_fp_tile<double>(tile, vec, batch, M, N, K, A, B, C, stream, fused)
+            : launch_fp_tile<float>(tile, vec, batch, M, N, K, A, B, C, stream, fused);
   }
   if (e != hipSuccess) {
     if (err) *err = std::string("sector product launch: ") + hipGetErrorString(e);

@@ -127,6 +127,8 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   if (!einsum || !p) return fail(err, SYMT_EINVAL, "einsum or plan is NULL");
   int rc = read_group(group, &p->g, err);
   if (rc) return rc;
+  const bool force_steps = (compute & kForceSteps) != 0;
+  compute &= ~kForceSteps;
   if (compute < SYMT_COMPUTE_F64 || compute > SYMT_COMPUTE_BF16X3)
     return fail(err, SYMT_EDTYPE, "unknown compute mode");
   p->compute = compute;
@@ -271,7 +273,88 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   }
   p->workspace = round_up(p->bytes_u_al, 256) + round_up(p->bytes_v_al, 256) +
                  round_up(p->bytes_w_al, 256);
+
+  // ---- fused product: A read from U's standard form along contiguous K runs
+  // (U's last v modes are its contracted modes and their block holds whole
+  // K-depths), C written straight into W's standard form.
+  const int want = compute == SYMT_COMPUTE_F64 ? SYMT_F64 : SYMT_F32;
+  bool trailing_k = true;
+  for (int i = 0; i < p->v; ++i) trailing_k = trailing_k && p->posK_u[i] == p->U.n - p->v + i;
+  const int vw = compute == SYMT_COMPUTE_F64 ? 2 : 4;
+  p->fused = !force_steps && compute != SYMT_COMPUTE_BF16X3 && p->U.dtype == want &&
+             (!w || p->W.dtype == want) && trailing_k && p->nK % kFpBK == 0 && p->N % vw == 0 &&
+             p->M > 0 && p->N > 0 && p->Kd > 0 && p->U.elems > 0;
+  if (p->fused) {
+    const size_t G = static_cast<size_t>(p->g.size);
+    p->bytes_tables = round_up(8 * G * p->M, 256) * 2 + round_up(8 * G * p->Kd, 256) +
+                      round_up(8 * G * p->N, 256);
+    p->workspace = round_up(p->bytes_v_al, 256) + p->bytes_tables;
+  }
   return SYMT_OK;
+}
+
+namespace {
+// Sector groups of an operand (rows, cols) with their deltas; shared by the
+// transform and offset-table descriptors.
+void sector_groups(const Plan& p, int operand, SectorGroup* R, SectorGroup* C) {
+  if (operand == 0) {
+    R->count = p.s;
+    for (int i = 0; i < p.s; ++i) { R->pos[i] = p.posI_u[i]; R->coef[i] = p.U.sign[p.posI_u[i]]; }
+    R->alpha = -1; R->beta = p.U.charge;                 // delta(1): sum c^U_I I + Q == Z^U
+    C->count = p.v;
+    for (int i = 0; i < p.v; ++i) { C->pos[i] = p.posK_u[i]; C->coef[i] = p.U.sign[p.posK_u[i]]; }
+    C->alpha = 1; C->beta = 0;                           // delta(2): sum c^U_K K == Q
+  } else if (operand == 1) {
+    R->count = p.v;
+    for (int i = 0; i < p.v; ++i) { R->pos[i] = p.posK_v[i]; R->coef[i] = p.U.sign[p.posK_u[i]]; }
+    R->alpha = 1; R->beta = 0;                           // delta(2), U's coefficients
+    C->count = p.t;
+    for (int i = 0; i < p.t; ++i) { C->pos[i] = p.posJ_v[i]; C->coef[i] = p.V.sign[p.posJ_v[i]]; }
+    C->alpha = -p.sigma; C->beta = p.V.charge;           // delta(3): sum c^V_J J + sigma Q == Z^V
+  } else {
+    R->count = p.s;
+    for (int i = 0; i < p.s; ++i) { R->pos[i] = p.posI_w[i]; R->coef[i] = p.U.sign[p.posI_u[i]]; }
+    R->alpha = -1; R->beta = p.U.charge;
+    C->count = p.t;
+    for (int i = 0; i < p.t; ++i) { C->pos[i] = p.posJ_w[i]; C->coef[i] = p.V.sign[p.posJ_v[i]]; }
+    C->alpha = -p.sigma; C->beta = p.V.charge;
+  }
+}
+}  // namespace
+
+OffsetParams make_offsets(const Plan& p, int operand, bool rows) {
+  OffsetParams o;
+  std::memset(&o, 0, sizeof o);
+  o.g = p.g;
+  SectorGroup R, C;
+  sector_groups(p, operand, &R, &C);
+  o.grp = rows ? R : C;
+  const OperandDesc& X = operand == 0 ? p.U : operand == 1 ? p.V : p.W;
+  int64_t std_stride[kMaxOrder];
+  int64_t acc = 1;
+  for (int m = X.n - 1; m >= 0; --m) { std_stride[m] = acc; acc *= X.dims[m]; }
+  const int64_t blk = acc;
+  // weight of mode m's sector in the block index: |G|^(N-2-m) blocks; the last
+  // mode's sector is not stored and contributes nothing.
+  int64_t wsec[kMaxOrder];
+  int64_t w = blk;
+  for (int m = X.n - 1; m >= 0; --m) {
+    if (m == X.n - 1) { wsec[m] = 0; continue; }
+    wsec[m] = w;
+    w *= p.g.size;
+  }
+  o.gpow = 1;
+  for (int i = 1; i < o.grp.count; ++i) o.gpow *= p.g.size;
+  o.n_inner = 1;
+  for (int i = 0; i < o.grp.count; ++i) {
+    const int m = o.grp.pos[i];
+    o.dim[i] = X.dims[m];
+    o.stride[i] = std_stride[m];
+    o.weight[i] = wsec[m];
+    o.n_inner *= X.dims[m];
+  }
+  o.count = o.gpow * o.n_inner;
+  return o;
 }
 
 XformParams make_xform(const Plan& p, int operand, bool to_aligned, int in_bytes, int out_bytes,
@@ -286,28 +369,7 @@ XformParams make_xform(const Plan& p, int operand, bool to_aligned, int in_bytes
   SectorGroup& R = x.row;
   SectorGroup& C = x.col;
   const int G = p.g.size;
-  if (operand == 0) {
-    R.count = p.s;
-    for (int i = 0; i < p.s; ++i) { R.pos[i] = p.posI_u[i]; R.coef[i] = p.U.sign[p.posI_u[i]]; }
-    R.alpha = -1; R.beta = p.U.charge;                 // delta(1): sum c^U_I I + Q == Z^U
-    C.count = p.v;
-    for (int i = 0; i < p.v; ++i) { C.pos[i] = p.posK_u[i]; C.coef[i] = p.U.sign[p.posK_u[i]]; }
-    C.alpha = 1; C.beta = 0;                           // delta(2): sum c^U_K K == Q
-  } else if (operand == 1) {
-    R.count = p.v;
-    for (int i = 0; i < p.v; ++i) { R.pos[i] = p.posK_v[i]; R.coef[i] = p.U.sign[p.posK_u[i]]; }
-    R.alpha = 1; R.beta = 0;                           // delta(2), U's coefficients
-    C.count = p.t;
-    for (int i = 0; i < p.t; ++i) { C.pos[i] = p.posJ_v[i]; C.coef[i] = p.V.sign[p.posJ_v[i]]; }
-    C.alpha = -p.sigma; C.beta = p.V.charge;           // delta(3): sum c^V_J J + sigma Q == Z^V
-  } else {
-    R.count = p.s;
-    for (int i = 0; i < p.s; ++i) { R.pos[i] = p.posI_w[i]; R.coef[i] = p.U.sign[p.posI_u[i]]; }
-    R.alpha = -1; R.beta = p.U.charge;
-    C.count = p.t;
-    for (int i = 0; i < p.t; ++i) { C.pos[i] = p.posJ_w[i]; C.coef[i] = p.V.sign[p.posJ_v[i]]; }
-    C.alpha = -p.sigma; C.beta = p.V.charge;
-  }
+  sector_groups(p, operand, &R, &C);
   x.gpow_row = 1;
   for (int i = 1; i < R.count; ++i) x.gpow_row *= G;
   x.gpow_col = 1;

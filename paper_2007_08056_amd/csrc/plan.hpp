@@ -73,6 +73,32 @@ struct XformParams {
   int32_t tiles_run, tiles_t;       // transpose: tiles along run and tdim
 };
 
+// Offsets of one sector group of an aligned operand inside its standard
+// reduced form.  The standard-form offset of aligned element (Q, r, c) splits
+// as R(Q, r) + C(Q, c): the block index and the in-block offset are both
+// linear in the sectors and in-block indices, and every sector (stored or
+// implicit) belongs to exactly one group.  One OffsetParams describes R or C.
+struct OffsetParams {
+  GroupDesc g;
+  SectorGroup grp;                  // the group's modes, coefficients and delta
+  int64_t gpow;                     // |G|^(count-1): stored sector combinations
+  int64_t n_inner;                  // product of the group's inner dims
+  int64_t count;                    // entries per Q = gpow * n_inner
+  int64_t dim[kMaxOrder];           // inner dims of the group's modes (group order)
+  int64_t stride[kMaxOrder];        // their standard-form strides
+  int64_t weight[kMaxOrder];        // standard-form offset of one unit of each mode's sector
+};
+
+// Device pointers of the four offset tables of the fused product: rows and
+// columns of U (A operand) and of W (output), each |G| x (rows or columns).
+struct FusedTables {
+  const int64_t* ra;
+  const int64_t* ca;
+  const int64_t* rc;
+  const int64_t* cc;
+  int32_t vec;                      // 1: U is not 16-byte aligned, load A one element at a time
+};
+
 struct OperandDesc {
   int32_t n;                        // order
   int32_t sign[kMaxOrder];          // +1 / -1
@@ -96,7 +122,9 @@ struct Plan {
   int32_t w_sign[kMaxOrder];        // derived
   int32_t w_charge = 0;             // derived
   int32_t compute = 0;
+  bool fused = false;               // A read from U's standard form, C written to W's
   size_t bytes_u_al = 0, bytes_v_al = 0, bytes_w_al = 0, workspace = 0;
+  size_t bytes_tables = 0;          // fused: the four offset tables
   double flops = 0.0;
 };
 
@@ -105,10 +133,18 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
               const symt_tensor* v, const symt_tensor* w, int32_t compute, Plan* plan,
               std::string* err);
 
+// Bit of the compute argument that forces the three separate steps.
+constexpr int32_t kForceSteps = 0x100;
+// K-depth of every f64/f32 product tile (the fused path needs contiguous runs of it).
+constexpr int kFpBK = 16;
+
 // Transform descriptor for operand 0 (U), 1 (V) or 2 (W) in the given direction.
 // `in_type` / `out_type` are the element types of the source and destination.
 XformParams make_xform(const Plan& p, int operand, bool to_aligned, int in_elem_bytes,
                        int out_elem_bytes, bool out_is_split);
+
+// Row (rows = true) or column offset table of operand 0 (U), 1 (V) or 2 (W).
+OffsetParams make_offsets(const Plan& p, int operand, bool rows);
 
 // Aligned layout used for an operand under a compute mode.
 AlignedLayout aligned_layout(int32_t compute, int operand);

@@ -15,7 +15,9 @@ namespace symt {
 int launch_xform(const XformParams& p, bool in_f64, int out, const void* src, void* dst,
                  hipStream_t stream, std::string* err);
 int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t n, const void* A,
-                       const void* B, void* C, hipStream_t stream, std::string* err);
+                       const void* B, void* C, hipStream_t stream, std::string* err,
+                       const FusedTables* fused = nullptr);
+int launch_offsets(const OffsetParams& p, int64_t* out, hipStream_t stream, std::string* err);
 }  // namespace symt
 
 using symt::Plan;
@@ -112,12 +114,37 @@ int do_unalign(symt_ctx* ctx, const Plan& p, const void* wal, hipStream_t s) {
 }
 
 int do_gemm(symt_ctx* ctx, int compute, int64_t batch, int64_t m, int64_t k, int64_t n,
-            const void* a, const void* b, void* c, hipStream_t s) {
+            const void* a, const void* b, void* c, hipStream_t s,
+            const symt::FusedTables* fused = nullptr) {
   std::string err;
   const int rc = timed(ctx, 2, s, [&] {
-    return symt::launch_sector_gemm(compute, batch, m, k, n, a, b, c, s, &err);
+    return symt::launch_sector_gemm(compute, batch, m, k, n, a, b, c, s, &err, fused);
   });
   return rc ? ctx_fail(ctx, rc, err) : SYMT_OK;
+}
+
+// Fused path: offset tables of U's rows and columns and of W's rows and
+// columns, V aligned, then one product that reads U and writes W in place.
+int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s) {
+  using symt::round_up;
+  const size_t G = static_cast<size_t>(p.g.size);
+  void* val = base;
+  int64_t* ra = reinterpret_cast<int64_t*>(base + round_up(p.bytes_v_al, 256));
+  int64_t* ca = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(ra) + round_up(8 * G * p.M, 256));
+  int64_t* rc = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(ca) + round_up(8 * G * p.Kd, 256));
+  int64_t* cc = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(rc) + round_up(8 * G * p.M, 256));
+  std::string err;
+  int rc_ = timed(ctx, 0, s, [&] {
+    int r = symt::launch_offsets(symt::make_offsets(p, 0, true), ra, s, &err);
+    if (!r) r = symt::launch_offsets(symt::make_offsets(p, 0, false), ca, s, &err);
+    if (!r) r = symt::launch_offsets(symt::make_offsets(p, 2, true), rc, s, &err);
+    if (!r) r = symt::launch_offsets(symt::make_offsets(p, 2, false), cc, s, &err);
+    return r;
+  });
+  if (rc_) return ctx_fail(ctx, rc_, err);
+  if ((rc_ = do_align(ctx, p, 1, val, s))) return rc_;
+  symt::FusedTables f{ra, ca, rc, cc, aligned16(p.U.data) ? 2 : 1};
+  return do_gemm(ctx, p.compute, p.g.size, p.M, p.Kd, p.N, p.U.data, val, p.W.data, s, &f);
 }
 
 int plan_for(symt_ctx* ctx, const char* einsum, const symt_group* group, const symt_tensor* u,
@@ -197,6 +224,7 @@ int symtensor_plan(const char* einsum, const symt_group* group, const symt_tenso
   for (size_t m = 0; m < p.tw.size(); ++m) info->w_signs[m] = p.w_sign[m] > 0 ? '+' : '-';
   info->w_signs[p.tw.size()] = '\0';
   info->w_charge = p.w_charge;
+  info->fused = p.fused ? 1 : 0;
   return SYMT_OK;
 }
 
@@ -233,11 +261,12 @@ int symtensor_contract(symt_ctx* ctx, const char* einsum, const symt_group* grou
   if (p.compute == SYMT_COMPUTE_BF16X3 && p.Kd % 8 != 0)
     return ctx_fail(ctx, SYMT_EUNSUPPORTED,
                     "split-bf16 product needs the aligned contracted extent to be a multiple of 8");
-  if (p.compute == SYMT_COMPUTE_BF16X3 && !aligned16(workspace))
-    return ctx_fail(ctx, SYMT_EUNSUPPORTED, "split-bf16 workspace must be 16-byte aligned");
+  if (p.workspace > 0 && !aligned16(workspace))
+    return ctx_fail(ctx, SYMT_EUNSUPPORTED, "workspace must be 16-byte aligned");
   if ((rc = set_device(ctx))) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(workspace);
+  if (p.fused) return do_fused(ctx, p, base, s);
   void* ual = base;
   void* val = base + symt::round_up(p.bytes_u_al, 256);
   void* wal = base + symt::round_up(p.bytes_u_al, 256) + symt::round_up(p.bytes_v_al, 256);

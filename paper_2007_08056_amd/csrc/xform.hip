@@ -180,7 +180,31 @@ hipError_t launch_typed(const XformParams& p, const void* src, void* dst, hipStr
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_offsets(int64_t* __restrict__ out, const OffsetParams p,
+                                                 int64_t total) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int q = static_cast<int>(i / p.count);
+    out[i] = group_offset(p, q, i - q * p.count);
+  }
+}
+
 }  // namespace
+
+// Offset table of one sector group for every auxiliary sector: out[q * count + i].
+int launch_offsets(const OffsetParams& p, int64_t* out, hipStream_t stream, std::string* err) {
+  const int64_t total = p.count * p.g.size;
+  if (total == 0) return SYMT_OK;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_offsets, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, out, p, total);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    if (err) *err = std::string("offset table launch: ") + hipGetErrorString(e);
+    return SYMT_EHIP;
+  }
+  return SYMT_OK;
+}
 
 // in_f64: source elements are binary64 (else binary32); out: 0 f64, 1 f32, 2 bf16 split.
 int launch_xform(const XformParams& p, bool in_f64, int out, const void* src, void* dst,

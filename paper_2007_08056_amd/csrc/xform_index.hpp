@@ -78,4 +78,21 @@ __host__ __device__ inline void block_bases(const XformParams& p, int64_t blk, i
   al_base = q * p.q_stride + rs * p.rs_stride + cs * p.cs_stride;
 }
 
+// Entry i of an offset table for auxiliary sector q: the group's stored sectors
+// are the digits of i / n_inner, its in-block indices those of i % n_inner
+// (row-major in group order); the implicit sector solves the group's delta.
+__host__ __device__ inline int64_t group_offset(const OffsetParams& p, int q, int64_t i) {
+  int64_t digits = i / p.n_inner;
+  int64_t inner = i - digits * p.n_inner;
+  int S[kMaxOrder];
+  fill_sectors(p.g, p.grp, digits, q, S);
+  int64_t off = 0;
+  for (int j = p.grp.count - 1; j >= 0; --j) {
+    const int64_t d = inner % p.dim[j];
+    inner /= p.dim[j];
+    off += d * p.stride[j] + static_cast<int64_t>(S[p.grp.pos[j]]) * p.weight[j];
+  }
+  return off;
+}
+
 }  // namespace symt

@@ -80,13 +80,18 @@ def _stream(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
-def plan(subscripts: str, u: SymTensor, v: SymTensor, compute: str = "f64", w: SymTensor | None = None):
+def _code(compute: str, steps: bool) -> int:
+    return L.COMPUTE[compute] | (L.SYMT_FLAG_STEPS if steps else 0)
+
+
+def plan(subscripts: str, u: SymTensor, v: SymTensor, compute: str = "f64", w: SymTensor | None = None,
+         steps: bool = False):
     """Shapes, flops, workspace and derived output rule of a contraction (host only)."""
     if u.group != v.group:
         raise ValueError("operands use different groups")
     g = L.make_group(u.group)
     return L.plan(subscripts, g, u.desc(), v.desc(), w.desc() if w is not None else None,
-                  L.COMPUTE[compute])
+                  _code(compute, steps))
 
 
 def output_like(subscripts: str, u: SymTensor, v: SymTensor, dtype=None) -> SymTensor:
@@ -105,19 +110,24 @@ def output_like(subscripts: str, u: SymTensor, v: SymTensor, dtype=None) -> SymT
 
 
 def contract_into(subscripts: str, u: SymTensor, v: SymTensor, w: SymTensor, compute: str = "f64",
-                  workspace: torch.Tensor | None = None):
-    """w.data <- contraction of u and v (no autograd); returns w."""
+                  workspace: torch.Tensor | None = None, steps: bool = False):
+    """w.data <- contraction of u and v (no autograd); returns w.
+
+    ``steps=True`` runs the three separate steps even where the fused product
+    applies (include/symtensor.h, FUSED PRODUCT).
+    """
     for t in (u.data, v.data, w.data):
         _check_dense(t)
     dev = u.data.device
     g = L.make_group(u.group)
     du, dv, dw = u.desc(), v.desc(), w.desc()
-    info = L.plan(subscripts, g, du, dv, dw, L.COMPUTE[compute])
+    code = _code(compute, steps)
+    info = L.plan(subscripts, g, du, dv, dw, code)
     if workspace is None or workspace.numel() < info.workspace_bytes:
         workspace = torch.empty(max(1, info.workspace_bytes), dtype=torch.uint8, device=dev)
     ctx = L.context(dev.index or 0)
     L.check(L.LIB.symtensor_contract(ctx, subscripts.encode(), ctypes.byref(g), du.ref, dv.ref,
-                                     dw.ref, L.COMPUTE[compute], ctypes.c_void_p(workspace.data_ptr()),
+                                     dw.ref, code, ctypes.c_void_p(workspace.data_ptr()),
                                      workspace.numel(), ctypes.c_void_p(_stream(dev))), ctx)
     return w
 

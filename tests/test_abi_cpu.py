@@ -50,7 +50,22 @@ def test_plan_matches_oracle_on_workloads(name):
         sw = O.output_symmetry(st.einsum, su, sv)
         assert info.w_signs.decode() == sw.sign_string() and info.w_charge == sw.charge
         assert info.elems_u == np.prod(su.reduced_shape())
-        assert info.workspace_bytes >= 8 * (info.elems_u + info.elems_v + info.elems_w)
+        tu = st.einsum.split(",")[0]
+        tv = st.einsum.split(",")[1].split("->")[0]
+        k_modes = [m for m in tu if m in tv]
+        trailing = tu.endswith("".join(k_modes))
+        nK = int(np.prod([ou.dims[tu.index(m)] for m in k_modes]))
+        assert info.fused == int(trailing and nK % 16 == 0)
+        G = info.group_size
+        if info.fused:
+            # V aligned plus four offset tables of U and W
+            assert info.workspace_bytes >= 8 * info.elems_v + 8 * G * (2 * info.m + info.k + info.n)
+            assert info.workspace_bytes < 8 * (info.elems_u + info.elems_v + info.elems_w)
+        rc, steps = _plan(st.einsum, wl.group, _desc(ou.signs, ou.charge, ou.dims),
+                          _desc(ov.signs, ov.charge, ov.dims), _desc(ow.signs, ow.charge, ow.dims),
+                          compute=L.SYMT_FLAG_STEPS)
+        assert rc == 0 and steps.fused == 0
+        assert steps.workspace_bytes >= 8 * (info.elems_u + info.elems_v + info.elems_w)
 
 
 def test_plan_matches_oracle_on_random_contractions():
@@ -132,6 +147,7 @@ def test_symmetry_and_size_errors():
     assert _plan("abkl,klij->abij", 4, _desc("++--", 0, (2, -1, 2, 2)), good)[0] == L.SYMT_EINVAL
     assert _plan("abkl,klij->abij", 4, _desc("++--", 0, (2, 2, 2, 2), dtype=7), good)[0] == L.SYMT_EDTYPE
     assert _plan("abkl,klij->abij", 4, good, good, compute=9)[0] == L.SYMT_EDTYPE
+    assert _plan("abkl,klij->abij", 4, good, good, compute=0x200)[0] == L.SYMT_EDTYPE
     assert _plan("abkl,klij->abij", (0,), good, good)[0] == L.SYMT_EINVAL
     bad = L.SymtGroup()
     bad.nfactors = 5

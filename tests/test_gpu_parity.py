@@ -287,3 +287,52 @@ def test_error_paths_on_device(P):
         P.contract_into("abkl,klij->abij", u, v_bad, w)
     torch.cuda.synchronize()
     assert torch.equal(before, w.data)
+
+
+# ---------------------------------------------------------------------------
+# fused product: A read from U's standard form, C written into W's
+# ---------------------------------------------------------------------------
+FUSED_CASES = [
+    ("abkl,klij->abij", (4,), "++--", "++--", (3, 5, 4, 4), (4, 4, 2, 3)),
+    ("abkl,klij->abji", (3,), "+-+-", "-+++", (2, 7, 8, 2), (8, 2, 4, 1)),
+    ("ak,kb->ab", (5,), "+-", "++", (33, 16), (16, 20)),
+    ("ak,kb->ba", (2, 3), "--", "-+", (17, 32), (32, 8)),
+    ("xykcd,kcdz->zxy", (2,), "+-+--", "-++-", (3, 3, 2, 2, 4), (2, 2, 4, 8)),
+    ("abcd,cdij->abij", (8,), "++--", "++--", (5, 6, 4, 4), (4, 4, 3, 2)),
+]
+
+
+@pytest.mark.parametrize("case", FUSED_CASES)
+@pytest.mark.parametrize("compute", ["f64", "f32"])
+def test_fused_product_equals_steps_and_oracle(P, case, compute):
+    sub, orders, cu, cv, du, dv = case
+    rng = np.random.default_rng(len(sub) * 31 + sum(du))
+    g = O.Group(orders)
+    su = O.Sym.make(cu, int(rng.integers(g.size)), du, g)
+    sv = O.Sym.make(cv, int(rng.integers(g.size)), dv, g)
+    say(f"fused {sub} G={orders} {compute}")
+    Ru = rng.standard_normal(su.reduced_shape())
+    Rv = rng.standard_normal(sv.reduced_shape())
+    dt = torch.float64 if compute == "f64" else torch.float32
+    u = _sym_tensor(P, Ru, su, dt)
+    v = _sym_tensor(P, Rv, sv, dt)
+    assert P.plan(sub, u, v, compute).fused == 1
+    assert P.plan(sub, u, v, compute, steps=True).fused == 0
+    w_f = P.output_like(sub, u, v, dtype=dt)
+    w_s = P.output_like(sub, u, v, dtype=dt)
+    P.contract_into(sub, u, v, w_f, compute)
+    P.contract_into(sub, u, v, w_s, compute, steps=True)
+    assert torch.equal(w_f.data, w_s.data)
+    ref, sw = O.contract_blocks(sub, H.to_np(u.data).astype(np.float64), su,
+                                H.to_np(v.data).astype(np.float64), sv)
+    absref, _ = O.contract_blocks(sub, np.abs(Ru), su, np.abs(Rv), sv)
+    k = H.contracted_extent(sub, su)
+    fac = 2 * H.gamma(k, H.U64) if compute == "f64" else 1.05 * H.gamma(k, H.U32) + H.gamma(k, H.U64)
+    assert np.all(np.abs(H.to_np(w_f.data) - ref) <= fac * absref + 1e-300)
+    # U starting 8 bytes into a buffer: the fused product loads A one element at a time
+    buf = torch.zeros(u.data.numel() + 1, dtype=dt, device=DEV)
+    buf[1:] = u.data.reshape(-1)
+    u_off = P.SymTensor(buf[1:].view(u.data.shape), u.signs, u.charge, u.group)
+    w_o = P.output_like(sub, u, v, dtype=dt)
+    P.contract_into(sub, u_off, v, w_o, compute)
+    assert torch.equal(w_o.data, w_s.data)
