@@ -209,6 +209,158 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
 }
 
 // ---------------------------------------------------------------------------
+// f64 / f32 with direct global->LDS loads (global_load_lds_dwordx4) into an
+// S-stage LDS ring: tile k+S-1 streams into LDS while tile k is multiplied, so
+// S-1 K-steps of latency are hidden without staging registers; one barrier per
+// K-step.  A rows are 128 bytes (BK = 128 / sizeof(T)), 8 chunks of 16 bytes.
+// Lane i of a wave load writes LDS slot i of its 1 KB block, so each lane picks
+// the global chunk that belongs in its slot: A slot (r, c) holds chunk
+// c ^ ((r >> 1) & 7), B slot (k, c) holds chunk c ^ ((k & 1) << 3), which keeps
+// the MFMA fragment reads free of bank conflicts.  Needs K % BK == 0; rows and
+// columns past M and N are clamped on load and never stored.
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(1))) void* gptr_t;
+typedef __attribute__((address_space(3))) void* lptr_t;
+__device__ __forceinline__ void lds_dma16(const void* g, void* lds) {
+  __builtin_amdgcn_global_load_lds((gptr_t)(g), (lptr_t)(lds), 16, 0, 0);
+}
+
+// s_waitcnt with vmcnt <= n and the other counters untouched (gfx9 encoding).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+template <typename T, int BM, int BN, int WM, int WN, int S, bool FA, bool FC>
+__global__ __launch_bounds__(64 * WM * WN) void k_gemm_dma(
+    const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C, int M, int N, int K,
+    int tiles_m, int tiles_n, int64_t ntiles, const int64_t* __restrict__ ra,
+    const int64_t* __restrict__ ca, const int64_t* __restrict__ rc, const int64_t* __restrict__ cc) {
+  constexpr int NW = WM * WN;
+  constexpr int NT = 64 * NW;
+  constexpr int VE = 16 / sizeof(T);              // elements per 16-byte chunk
+  constexpr int BK = 128 / sizeof(T);             // one 128-byte A row per K-step
+  constexpr int TM = BM / WM / 16;
+  constexpr int TN = BN / WN / 16;
+  constexpr int BCH = BN / VE;                    // chunks per B row
+  constexpr int A_LOADS = BM * 8 / NT;            // 16-byte loads per thread per stage
+  constexpr int B_LOADS = BK * BCH / NT;
+  static_assert(TM * WM * 16 == BM && TN * WN * 16 == BN, "tile shape");
+  static_assert(A_LOADS * NT == BM * 8 && B_LOADS * NT == BK * BCH, "loads must divide evenly");
+  static_assert(BCH % 16 == 0, "B rows must hold a multiple of 16 chunks");
+  constexpr int STAGE = BM * 128 + BK * BN * static_cast<int>(sizeof(T));   // bytes per stage
+  __shared__ __attribute__((aligned(1024))) char smem[S * STAGE];
+
+  const int64_t tile = xcd_remap(blockIdx.x, ntiles);
+  const int tn = static_cast<int>(tile % tiles_n);
+  const int64_t t2 = tile / tiles_n;
+  const int tm = static_cast<int>(t2 % tiles_m);
+  const int64_t q = t2 / tiles_m;
+  const T* Aq = A + (FA ? 0 : q * static_cast<int64_t>(M) * K);
+  const T* Bq = B + q * static_cast<int64_t>(K) * N;
+  T* Cq = C + (FC ? 0 : q * static_cast<int64_t>(M) * N);
+  const int m0 = tm * BM, n0 = tn * BN;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm0 = (wave / WN) * (BM / WM);
+  const int wn0 = (wave % WN) * (BN / WN);
+
+  // Global source of each of this thread's loads (row base, chunk), fixed across K-steps.
+  int64_t a_src[A_LOADS];
+  int a_chunk[A_LOADS];
+#pragma unroll
+  for (int i = 0; i < A_LOADS; ++i) {
+    const int slot = tid + i * NT;                // A slot = row * 8 + position
+    const int r = slot >> 3, c = slot & 7;
+    const int gr = min(m0 + r, M - 1);
+    a_src[i] = FA ? ra[q * M + gr] : static_cast<int64_t>(gr) * K;
+    a_chunk[i] = c ^ ((r >> 1) & 7);
+  }
+  int64_t b_src[B_LOADS];
+#pragma unroll
+  for (int i = 0; i < B_LOADS; ++i) {
+    const int slot = tid + i * NT;                // B slot = k * BCH + position
+    const int k = slot / BCH, c = slot % BCH;
+    const int gch = c ^ ((k & 1) << 3);
+    const int gn = min(n0 + gch * VE, N - VE);
+    b_src[i] = static_cast<int64_t>(k) * N + gn;
+  }
+  auto issue = [&](int kt, int stage) {
+    const int k0 = kt * BK;
+    const int64_t acol = FA ? ca[q * K + k0] : k0;
+    char* base = smem + stage * STAGE;
+#pragma unroll
+    for (int i = 0; i < A_LOADS; ++i)
+      lds_dma16(Aq + a_src[i] + acol + a_chunk[i] * VE, base + (i * NT + wave * 64) * 16);
+#pragma unroll
+    for (int i = 0; i < B_LOADS; ++i)
+      lds_dma16(Bq + b_src[i] + static_cast<int64_t>(k0) * N, base + BM * 128 + (i * NT + wave * 64) * 16);
+  };
+
+  using Acc = typename Mfma<T>::Acc;
+  Acc acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = Acc{};
+
+  const int nk = K / BK;
+#pragma unroll
+  for (int s = 0; s < S - 1; ++s)
+    if (s < nk) issue(s, s);
+  for (int kt = 0; kt < nk; ++kt) {
+    // tile kt has landed once at most (S-2) later tiles' loads are outstanding
+    if (kt + S - 2 < nk) wait_vmcnt<(S - 2) * (A_LOADS + B_LOADS)>();
+    else wait_vmcnt<0>();
+    // a plain barrier: the explicit wait above already covers this wave's loads of
+    // tile kt, and a workgroup fence here would drain the loads still in flight
+    asm volatile("s_barrier" ::: "memory");
+    if (kt + S - 1 < nk) issue(kt + S - 1, (kt + S - 1) % S);
+    const char* base = smem + (kt % S) * STAGE;
+    const T* As = reinterpret_cast<const T*>(base);
+    const T* Bs = reinterpret_cast<const T*>(base + BM * 128);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int k = kk + (lane >> 4);
+      T a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int m = wm0 + i * 16 + (lane & 15);
+        a[i] = As[m * BK + ((k / VE) ^ ((m >> 1) & 7)) * VE + k % VE];
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int n = wn0 + j * 16 + (lane & 15);
+        b[j] = Bs[k * BN + ((n / VE) ^ ((k & 1) << 3)) * VE + n % VE];
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<T>::run(a[i], b[j], acc[i][j]);
+    }
+  }
+
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int col = n0 + wn0 + j * 16 + (lane & 15);
+    const int64_t ccol = (FC && col < N) ? cc[q * N + col] : col;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm0 + i * 16 + Mfma<T>::row(lane, r);
+        if (row < M && col < N) {
+          const int64_t crow = FC ? rc[q * M + row] : static_cast<int64_t>(row) * N;
+          Cq[crow + ccol] = acc[i][j][r];
+        }
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // split-bf16: A planes [Q][M][K], B planes [Q][N][K] (K fastest), C f64.
 // ---------------------------------------------------------------------------
 template <int BM, int BN, int BK, int WM, int WN>
@@ -396,15 +548,45 @@ hipError_t launch_bf16x3(int64_t batch, int M, int N, int K, const void* A, cons
   return hipGetLastError();
 }
 
-// One f64/f32 tile configuration.
+template <typename T, int BM, int BN, int WM, int WN, int S>
+hipError_t launch_dma(int64_t batch, int M, int N, int K, const void* A, const void* B, void* C,
+                      hipStream_t s, const FusedTables* f) {
+  // B rows must hold a multiple of 16 chunks of 16 bytes (the swizzle works in
+  // halves of a bank cycle); other shapes are never selected for this type.
+  if constexpr ((BN * sizeof(T) / 16) % 16 != 0) {
+    return hipErrorInvalidValue;
+  } else {
+  const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
+  const int64_t ntiles = batch * tiles_m * tiles_n;
+  const dim3 grid(static_cast<unsigned>(ntiles)), block(64 * WM * WN);
+  const T* a = static_cast<const T*>(A);
+  const T* b = static_cast<const T*>(B);
+  T* c = static_cast<T*>(C);
+  if (f)
+    hipLaunchKernelGGL((k_gemm_dma<T, BM, BN, WM, WN, S, true, true>), grid, block, 0, s, a, b, c, M,
+                       N, K, tiles_m, tiles_n, ntiles, f->ra, f->ca, f->rc, f->cc);
+  else
+    hipLaunchKernelGGL((k_gemm_dma<T, BM, BN, WM, WN, S, false, false>), grid, block, 0, s, a, b, c,
+                       M, N, K, tiles_m, tiles_n, ntiles, nullptr, nullptr, nullptr, nullptr);
+  return hipGetLastError();
+  }
+}
+
+// One f64/f32 tile configuration.  dma: direct global->LDS loads into an
+// S-stage ring (needs K to be a multiple of the 128-byte K-depth and N a
+// multiple of 16 bytes).
 struct FpTile {
   const char* name;
   int bm, bn;
+  bool dma;
+  double eff;     // measured f64 MFMA efficiency on a large, evenly tiled product
 };
 constexpr FpTile kFpTiles[] = {
-    {"128x128", 128, 128}, {"128x96", 128, 96}, {"128x64", 128, 64}, {"128x48", 128, 48},
-    {"96x96", 96, 96},     {"256x96", 256, 96}, {"128x128k32", 128, 128}, {"128x48k32", 128, 48},
-    {"96x96k32", 96, 96},  {"256x128", 256, 128}, {"128x256", 128, 256}, {"64x96", 64, 96},
+    {"128x128", 128, 128, false, 0.80},  {"128x96", 128, 96, false, 0.76},
+    {"128x64", 128, 64, false, 0.77},    {"128x48", 128, 48, false, 0.72},
+    {"96x96", 96, 96, false, 0.72},      {"64x96", 64, 96, false, 0.71},
+    {"d128x128s2", 128, 128, true, 0.84}, {"d128x96s2", 128, 96, true, 0.79},
+    {"d128x64s3", 128, 64, true, 0.77},  {"d96x96s3", 96, 96, true, 0.74},
 };
 constexpr int kNumFpTiles = sizeof(kFpTiles) / sizeof(kFpTiles[0]);
 
@@ -417,35 +599,38 @@ hipError_t launch_fp_tile(int idx, int vec, int64_t batch, int M, int N, int K, 
     case 2: return launch_fp<T, 128, 64, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s, f);
     case 3: return launch_fp<T, 128, 48, 16, 4, 1>(vec, batch, M, N, K, A, B, C, s, f);
     case 4: return launch_fp<T, 96, 96, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s, f);
-    case 5: return launch_fp<T, 256, 96, 16, 4, 2>(vec, batch, M, N, K, A, B, C, s, f);
-    case 6: return launch_fp<T, 128, 128, 32, 2, 2>(vec, batch, M, N, K, A, B, C, s, f);
-    case 7: return launch_fp<T, 128, 48, 32, 4, 1>(vec, batch, M, N, K, A, B, C, s, f);
-    case 8: return launch_fp<T, 96, 96, 32, 2, 2>(vec, batch, M, N, K, A, B, C, s, f);
-    case 9: return launch_fp<T, 256, 128, 16, 4, 2>(vec, batch, M, N, K, A, B, C, s, f);
-    case 10: return launch_fp<T, 128, 256, 16, 2, 4>(vec, batch, M, N, K, A, B, C, s, f);
-    default: return launch_fp<T, 64, 96, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s, f);
+    case 5: return launch_fp<T, 64, 96, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s, f);
+    case 6: return launch_dma<T, 128, 128, 2, 2, 2>(batch, M, N, K, A, B, C, s, f);
+    case 7: return launch_dma<T, 128, 96, 2, 2, 2>(batch, M, N, K, A, B, C, s, f);
+    case 8: return launch_dma<T, 128, 64, 2, 2, 3>(batch, M, N, K, A, B, C, s, f);
+    default: return launch_dma<T, 96, 96, 2, 2, 3>(batch, M, N, K, A, B, C, s, f);
   }
 }
 
-// Estimated cost of a tiling in units of one (BM x BN) tile's work: padded work,
-// rounded up to whole waves of tiles over the 256 compute units (each tile is
-// assumed to run on one CU at a time).
-double tile_cost(int64_t batch, int64_t M, int64_t N, int bm, int bn) {
-  const int64_t tiles = batch * ((M + bm - 1) / bm) * ((N + bn - 1) / bn);
+// Estimated time of a tiling: padded tile work, rounded up to whole waves of
+// tiles over the 256 compute units, divided by the tile's measured efficiency.
+double tile_cost(int64_t batch, int64_t M, int64_t N, const FpTile& t) {
+  const int64_t tiles = batch * ((M + t.bm - 1) / t.bm) * ((N + t.bn - 1) / t.bn);
   const int64_t waves = (tiles + 255) / 256;
-  return static_cast<double>(waves) * bm * bn;
+  return static_cast<double>(waves) * t.bm * t.bn / t.eff;
 }
 
-int pick_fp_tile(int64_t batch, int64_t M, int64_t N) {
+// aligned: A and B start on 16-byte boundaries (required by the DMA tiles).
+int pick_fp_tile(int64_t batch, int64_t M, int64_t N, int64_t K, int elem, bool aligned) {
+  auto usable = [&](const FpTile& t) {
+    if (!t.dma) return true;
+    return aligned && K % (128 / elem) == 0 && N % (16 / elem) == 0 && (t.bn * elem / 16) % 16 == 0;
+  };
   const char* forced = std::getenv("SYMT_GEMM_TILE");
   if (forced)
     for (int i = 0; i < kNumFpTiles; ++i)
-      if (std::strcmp(forced, kFpTiles[i].name) == 0) return i;
-  int best = 0;
+      if (std::strcmp(forced, kFpTiles[i].name) == 0 && usable(kFpTiles[i])) return i;
+  int best = -1;
   double best_cost = 0;
-  for (int i = 0; i < 4; ++i) {
-    const double c = tile_cost(batch, M, N, kFpTiles[i].bm, kFpTiles[i].bn);
-    if (i == 0 || c < best_cost) { best = i; best_cost = c; }
+  for (int i = 0; i < kNumFpTiles; ++i) {
+    if (!usable(kFpTiles[i])) continue;
+    const double c = tile_cost(batch, M, N, kFpTiles[i]);
+    if (best < 0 || c < best_cost) { best = i; best_cost = c; }
   }
   return best;
 }
@@ -475,7 +660,9 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
     const bool f64 = compute == SYMT_COMPUTE_F64;
     const int vw = f64 ? 2 : 4;
     const int vec = (K % vw == 0 && N % vw == 0) ? vw : 1;
-    const int tile = pick_fp_tile(batch, M, N);
+    const bool aligned = (reinterpret_cast<uintptr_t>(A) & 15) == 0 &&
+                         (reinterpret_cast<uintptr_t>(B) & 15) == 0 && (!fused || fused->vec > 1);
+    const int tile = pick_fp_tile(batch, M, N, K, f64 ? 8 : 4, aligned);
     e = f64 ? launch_fp_tile<double>(tile, vec, batch, M, N, K, A, B, C, stream, fused)
             : launch_fp_tile<float>(tile, vec, batch, M, N, K, A, B, C, stream, fused);
   }

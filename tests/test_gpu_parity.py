@@ -336,3 +336,23 @@ def test_fused_product_equals_steps_and_oracle(P, case, compute):
     w_o = P.output_like(sub, u, v, dtype=dt)
     P.contract_into(sub, u_off, v, w_o, compute)
     assert torch.equal(w_o.data, w_s.data)
+
+
+@pytest.mark.parametrize("tile", ["d128x128s2", "d128x96s2", "d128x64s3", "d96x96s3", "128x48", "64x96"])
+@pytest.mark.parametrize("compute", ["f64", "f32"])
+def test_sector_gemm_every_tile_on_ragged_shapes(P, tile, compute, monkeypatch):
+    """Each tile shape, forced, on shapes that leave partial tiles in M and N."""
+    monkeypatch.setenv("SYMT_GEMM_TILE", tile)
+    for shape in ((2, 130, 64, 68), (3, 257, 96, 196), (1, 16, 32, 4)):
+        b, m, k, n = shape
+        say(f"sector_gemm tile={tile} {compute} {shape}")
+        rng = np.random.default_rng(m + n + k)
+        dt = torch.float64 if compute == "f64" else torch.float32
+        a = torch.from_numpy(rng.standard_normal((b, m, k))).to(DEV, dt)
+        bb = torch.from_numpy(rng.standard_normal((b, k, n))).to(DEV, dt)
+        C = H.to_np(P.sector_gemm(a, bb, compute))
+        A64, B64 = H.to_np(a).astype(np.float64), H.to_np(bb).astype(np.float64)
+        ref = np.matmul(A64, B64)
+        absb = np.matmul(np.abs(A64), np.abs(B64))
+        fac = 2 * H.gamma(k, H.U64) if compute == "f64" else 1.05 * H.gamma(k, H.U32)
+        assert np.all(np.abs(C - ref) <= fac * absb), (tile, compute, shape)
