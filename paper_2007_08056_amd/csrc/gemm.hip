@@ -364,7 +364,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_dma(
 // split-bf16: A planes [Q][M][K], B planes [Q][N][K] (K fastest), C f64.
 // ---------------------------------------------------------------------------
 template <int BM, int BN, int BK, int WM, int WN>
-__global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf16x3(
+__global__ __launch_bounds__(64 * WM * WN, (WM * WN == 4 && BK == 32) ? 2 : 1) void k_gemm_bf16x3(
     const uint16_t* __restrict__ Ahi, const uint16_t* __restrict__ Alo,
     const uint16_t* __restrict__ Bhi, const uint16_t* __restrict__ Blo, double* __restrict__ C,
     int M, int N, int K, int tiles_m, int tiles_n, int64_t ntiles) {
@@ -465,7 +465,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf16x3(
     for (int kk = 0; kk < BK; kk += 32) {
       // operand layout of the 16x16x32 bf16 MFMA: lane l holds row (or column)
       // l%16 and the 8 consecutive k values starting at 8*(l/16).
-      bf8 ah[TM], al[TM], bh[TN], bl[TN];
+      // A fragments stay in registers for the whole K-step; B fragments are
+      // read one column tile at a time to keep register pressure down.
+      bf8 ah[TM], al[TM];
       const int kof = kk + 8 * (lane >> 4);
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
@@ -476,17 +478,18 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf16x3(
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const int r = wn0 + j * 16 + (lane & 15);
-        bh[j] = *reinterpret_cast<const bf8*>(&Bsh[buf][r][kof]);
-        bl[j] = *reinterpret_cast<const bf8*>(&Bsl[buf][r][kof]);
-      }
+        const bf8 bh = *reinterpret_cast<const bf8*>(&Bsh[buf][r][kof]);
+        const bf8 bl = *reinterpret_cast<const bf8*>(&Bsl[buf][r][kof]);
+        // the two updates of each cross accumulator are TM products apart
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          acc_hh[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc_hh[i][j], 0, 0, 0);
-          acc_x[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc_x[i][j], 0, 0, 0);
-          acc_x[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc_x[i][j], 0, 0, 0);
+        for (int i = 0; i < TM; ++i) {
+          acc_hh[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc_hh[i][j], 0, 0, 0);
+          acc_x[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc_x[i][j], 0, 0, 0);
         }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+          acc_x[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc_x[i][j], 0, 0, 0);
+      }
     }
     if (kt + 1 < nk) store_tiles(buf ^ 1);
     __syncthreads();
@@ -652,10 +655,20 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
       if (err) *err = "split-bf16 product needs the contracted extent to be a multiple of 8";
       return SYMT_EUNSUPPORTED;
     }
-    if (N <= 64)
-      e = launch_bf16x3<128, 64, 64, 4, 1>(batch, M, N, K, A, B, C, stream);
+    const char* forced = std::getenv("SYMT_GEMM_TILE");
+    const std::string f = forced ? forced : "";
+    if (f == "b128x128k64") e = launch_bf16x3<128, 128, 64, 2, 2>(batch, M, N, K, A, B, C, stream);
+    else if (f == "b128x128k32") e = launch_bf16x3<128, 128, 32, 2, 2>(batch, M, N, K, A, B, C, stream);
+    else if (f == "b256x128k32") e = launch_bf16x3<256, 128, 32, 4, 2>(batch, M, N, K, A, B, C, stream);
+    else if (f == "b128x256k32") e = launch_bf16x3<128, 256, 32, 2, 4>(batch, M, N, K, A, B, C, stream);
+    else if (f == "b128x64k32") e = launch_bf16x3<128, 64, 32, 4, 1>(batch, M, N, K, A, B, C, stream);
+    else if (f == "b64x64k32") e = launch_bf16x3<64, 64, 32, 2, 2>(batch, M, N, K, A, B, C, stream);
+    else if (N <= 64)
+      e = launch_bf16x3<128, 64, 32, 4, 1>(batch, M, N, K, A, B, C, stream);
+    else if (N >= 1024 && M >= 1024)
+      e = launch_bf16x3<128, 256, 32, 2, 4>(batch, M, N, K, A, B, C, stream);
     else
-      e = launch_bf16x3<128, 128, 64, 2, 2>(batch, M, N, K, A, B, C, stream);
+      e = launch_bf16x3<128, 128, 32, 2, 2>(batch, M, N, K, A, B, C, stream);
   } else {
     const bool f64 = compute == SYMT_COMPUTE_F64;
     const int vw = f64 ? 2 : 4;
