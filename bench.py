@@ -11,7 +11,12 @@ dominant kernel (the sector product; its duration from HIP events the library
 records around each launch on the stream it launches on), and the CPU oracle's
 rate on a bounded sample of the same workload.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--extra PATH]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--extra PATH] [--all]
+
+Where the layout allows (here it does), one step runs the fused product: A is
+read straight from V_abcd's standard form and C written straight into W_abij's,
+so only T_cdij is aligned (include/symtensor.h, FUSED PRODUCT); the three
+separate steps are timed too and reported in the --extra file.
 """
 from __future__ import annotations
 
@@ -93,6 +98,54 @@ def cpu_baseline(wl, budget_s=12.0):
                       f"stored blocks of V_abcd against all of T_cdij, {elapsed:.1f} s"}
 
 
+def chain_flops(wl, compute):
+    """Algorithmic flops of a workload's contraction chain (host-only planning)."""
+    from paper_2007_08056_amd import _lib as L
+    total = 0.0
+    for st in wl.steps:
+        ou, ov = wl.operands[st.u], wl.operands[st.v]
+        info = L.plan(st.einsum, L.make_group(wl.group),
+                      L.TensorDesc(ou.signs, ou.charge, ou.dims, L.SYMT_F64, None),
+                      L.TensorDesc(ov.signs, ov.charge, ov.dims, L.SYMT_F64, None), None, L.COMPUTE[compute])
+        total += info.flops
+    return total
+
+
+def time_workload(P, SG, wl, compute, steps, warmup, grad=False):
+    """ms per step and effective TFLOP/s of a workload's contraction chain (optionally fwd+bwd).
+
+    With grad, the backward of every step is two contractions of the forward's
+    size (dU and dV), so the step does three times the forward's flops.
+    """
+    import torch
+    dt = torch.float64 if compute == "f64" else torch.float32
+    t = {}
+    for name in wl.inputs:
+        op = wl.operands[name]
+        d = SG.device_input(wl, name, dtype=dt, device="cuda:0")
+        if grad and name != "R":
+            d.requires_grad_(True)
+        t[name] = P.SymTensor(d, op.signs, op.charge, wl.group)
+    flops = chain_flops(wl, compute) * (3.0 if grad else 1.0)
+
+    def step():
+        cur = dict(t)
+        for st in wl.steps:
+            cur[st.w] = P.einsum(st.einsum, cur[st.u], cur[st.v], compute)
+        if grad:
+            (cur[wl.output].data * cur["R"].data).sum().backward()
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    return {"ms_per_step": round(ms, 4), "tflops": round(flops / (ms * 1e-3) / 1e12, 2),
+            "flops_per_step": flops}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +153,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--extra", default="", help="write per-kernel details to this JSON file")
+    ap.add_argument("--all", action="store_true",
+                    help="also time every workload in every precision (written to --extra)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run one plain elementwise kernel that reads and writes 256 MiB "
                          "(the reference for scaling HBM byte counters)")
@@ -189,6 +244,24 @@ def main():
                         ("unalign_w", 2 * info.elems_w * 8)):
         if xf[key]:
             extra[key + "_GBs"] = nbytes / (xf[key] * 1e-3) / 1e9
+
+    if args.all:
+        import synth as S
+        table = {}
+        for name, computes, grad in (("plain_z4", ("f64",), False), ("ccd_ladder_z8", ("f32", "bf16x3"), False),
+                                     ("mps_env_z2z3", ("f64", "f32", "bf16x3"), False),
+                                     ("ccd_ladder_z16", ("f64", "f32", "bf16x3"), False),
+                                     ("mps_env_grad", ("f64", "f32"), False),
+                                     ("mps_env_grad", ("f64", "f32"), True)):
+            wlx = S.configs.get(name)
+            for c in computes:
+                n_steps = 3 if name == "ccd_ladder_z16" else 10
+                r = time_workload(P, SG, wlx, c, n_steps, 2, grad)
+                key = f"{name}/{c}" + ("/fwd+bwd" if grad else "")
+                table[key] = r
+                print(f"{key}: {r['ms_per_step']:.3f} ms, {r['tflops']:.1f} TFLOP/s", file=sys.stderr, flush=True)
+                torch.cuda.empty_cache()
+        extra["workloads"] = table
 
     cpu = None
     if not args.no_cpu:

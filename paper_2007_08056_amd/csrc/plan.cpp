@@ -428,7 +428,7 @@ XformParams make_xform(const Plan& p, int operand, bool to_aligned, int in_bytes
   const int64_t* ss = to_aligned ? mstd : mal;
   const int64_t* ds = to_aligned ? mal : mstd;
 
-  // Choose the copy run / transpose pair.
+  // Copy mode when one dim is the fastest in both layouts, else tiled transpose.
   int run = -1;
   for (int d = 0; d < md; ++d)
     if (ss[d] == 1 && ds[d] == 1) run = d;
@@ -439,22 +439,54 @@ XformParams make_xform(const Plan& p, int operand, bool to_aligned, int in_bytes
   }
   if (run < 0 && a == b) run = a;
   x.mode = run >= 0 ? 0 : 1;
-  if (x.mode == 0) a = run;
-  x.run = a;
-  x.run_len = msize[a];
-  x.run_ss = ss[a];
-  x.run_ds = ds[a];
-  if (x.mode == 1) {
-    x.tdim = b;
-    x.t_len = msize[b];
-    x.t_ss = ss[b];
-    x.t_ds = ds[b];
+  bool in_tile[kMaxDims] = {};
+  x.na = x.nb = 0;
+  x.run = run;
+  if (x.mode == 0) {
+    in_tile[run] = true;
+    x.run_len = msize[run];
+    x.run_ss = ss[run];
+    x.run_ds = ds[run];
+  } else {
+    // A: dims by increasing source stride until 64 elements (reads coalesce
+    // along it); B: the remaining dims by increasing destination stride until
+    // 64 elements (writes coalesce along it).  Tiny dims are merged this way
+    // so that one 64 x 64 tile stays full whatever the in-block shape.
+    int by[kMaxDims];
+    for (int d = 0; d < md; ++d) by[d] = d;
+    std::sort(by, by + md, [&](int l, int r) { return ss[l] < ss[r]; });
+    int64_t pa = 1;
+    for (int i = 0; i < md && pa < 64; ++i) {
+      const int d = by[i];
+      x.asize[x.na] = msize[d]; x.ass[x.na] = ss[d]; x.ads[x.na] = ds[d]; ++x.na;
+      pa *= msize[d];
+      in_tile[d] = true;
+    }
+    std::sort(by, by + md, [&](int l, int r) { return ds[l] < ds[r]; });
+    int64_t pb = 1;
+    for (int i = 0; i < md && pb < 64; ++i) {
+      const int d = by[i];
+      if (in_tile[d]) continue;
+      x.tsize[x.nb] = msize[d]; x.tss[x.nb] = ss[d]; x.tds[x.nb] = ds[d]; ++x.nb;
+      pb *= msize[d];
+      in_tile[d] = true;
+    }
+    if (x.nb == 0 && x.na > 1) {
+      // Every dim went to A: give its slowest one to B so both sides stay parallel.
+      --x.na;
+      x.tsize[0] = x.asize[x.na]; x.tss[0] = x.ass[x.na]; x.tds[0] = x.ads[x.na]; x.nb = 1;
+      pb = x.tsize[0];
+      pa = 1;
+      for (int i = 0; i < x.na; ++i) pa *= x.asize[i];
+    }
+    x.run_len = pa;
+    x.t_len = pb;
   }
   // Batch dims: the rest, ordered so that the last one has the smallest dst stride.
   int order_idx[kMaxDims];
   int nb = 0;
   for (int d = 0; d < md; ++d)
-    if (d != a && !(x.mode == 1 && d == b)) order_idx[nb++] = d;
+    if (!in_tile[d]) order_idx[nb++] = d;
   std::sort(order_idx, order_idx + nb, [&](int l, int r) { return ds[l] > ds[r]; });
   x.nbatch = nb;
   x.rows = 1;

@@ -55,11 +55,16 @@ struct XformParams {
   int32_t to_aligned;               // 1: standard -> aligned, 0: aligned -> standard
   // inner dims after merging; src / dst strides already oriented by direction
   int32_t mode;                     // 0 copy (one run dim), 1 tiled transpose
-  int32_t run;                      // copy: run dim; transpose: src-fast dim
-  int32_t tdim;                     // transpose: dst-fast dim
-  int64_t run_len;                  // size[run]
-  int64_t run_ss, run_ds;           // strides of the run dim
-  int64_t t_len, t_ss, t_ds;        // size/strides of the dst-fast dim (transpose)
+  int32_t run;                      // copy: run dim
+  int64_t run_len;                  // copy: size[run]; transpose: elements of the A index
+  int64_t run_ss, run_ds;           // copy: strides of the run dim
+  int64_t t_len;                    // transpose: elements of the B index
+  // Transpose tile indices, each a mixed-radix merge of dims listed fastest
+  // first: A (read along, smallest source strides) and B (written along,
+  // smallest destination strides among the rest).
+  int32_t na, nb;
+  int64_t asize[kMaxDims], ass[kMaxDims], ads[kMaxDims];
+  int64_t tsize[kMaxDims], tss[kMaxDims], tds[kMaxDims];
   int32_t nbatch;                   // remaining dims ("rows")
   int64_t bsize[kMaxDims];
   int64_t bss[kMaxDims];

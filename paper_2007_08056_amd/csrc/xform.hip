@@ -13,8 +13,10 @@
 //   * copy mode: one run of elements is contiguous in both layouts; every
 //     thread moves 16-byte vectors along it, rows indexed through LDS, or
 //   * transpose mode: the source- and destination-contiguous dims differ;
-//     a 64 x 64 tile is read along the first into LDS and written along the
-//     second.
+//     a 64 x 64 tile is read into LDS along index A (the source-fastest dims,
+//     merged until 64 elements) and written along index B (the
+//     destination-fastest of the rest), so in-block dims as small as 2 still
+//     fill the tile.
 // Element conversions (f64 <-> f32, f32 -> bf16 hi/lo pair) are fused.
 #include <hip/hip_runtime.h>
 
@@ -120,11 +122,26 @@ __global__ __launch_bounds__(256) void k_xform_copy(const Tin* __restrict__ src,
   }
 }
 
+// Offsets (source, destination) of entry i of a mixed-radix tile index.
+__device__ __forceinline__ void tile_offsets(int64_t i, int n, const int64_t* size, const int64_t* ss,
+                                             const int64_t* ds, int64_t& so, int64_t& dof) {
+  so = 0;
+  dof = 0;
+  for (int k = 0; k < n; ++k) {
+    const int64_t q = i / size[k];
+    const int64_t c = i - q * size[k];
+    i = q;
+    so += c * ss[k];
+    dof += c * ds[k];
+  }
+}
+
 template <typename Tin, int OUT>
 __global__ __launch_bounds__(256) void k_xform_transpose(const Tin* __restrict__ src,
                                                          void* __restrict__ dst,
                                                          const XformParams p) {
   __shared__ double tile[64][65];
+  __shared__ int64_t a_src[64], a_dst[64], b_src[64], b_dst[64];
   const int64_t wg = blockIdx.x;
   const int64_t blk = wg / p.tiles_per_block;
   int64_t rem = wg - blk * p.tiles_per_block;
@@ -143,19 +160,29 @@ __global__ __launch_bounds__(256) void k_xform_transpose(const Tin* __restrict__
     so += d * p.bss[i];
     dof += d * p.bds[i];
   }
-  const int x = threadIdx.x & 63;
-  const int y = threadIdx.x >> 6;
-  for (int j = y; j < 64; j += 4) {
-    const int64_t ia = ta * 64 + x, ib = tb * 64 + j;
-    if (ia < p.run_len && ib < p.t_len)
-      tile[j][x] = static_cast<double>(src[so + ia * p.run_ss + ib * p.t_ss]);
+  const int64_t a0 = ta * 64, b0 = tb * 64;
+  const int na = static_cast<int>(p.run_len - a0 < 64 ? p.run_len - a0 : 64);
+  const int nb = static_cast<int>(p.t_len - b0 < 64 ? p.t_len - b0 : 64);
+  const int t = threadIdx.x;
+  if (t < 64) {
+    if (t < na) tile_offsets(a0 + t, p.na, p.asize, p.ass, p.ads, a_src[t], a_dst[t]);
+  } else if (t < 128) {
+    const int u = t - 64;
+    if (u < nb) tile_offsets(b0 + u, p.nb, p.tsize, p.tss, p.tds, b_src[u], b_dst[u]);
   }
   __syncthreads();
-  for (int j = y; j < 64; j += 4) {
-    const int64_t ia = ta * 64 + j, ib = tb * 64 + x;
-    if (ia < p.run_len && ib < p.t_len) {
+  const int x = t & 63;
+  const int y = t >> 6;
+  if (x < na) {
+    const int64_t sx = so + a_src[x];
+    for (int j = y; j < nb; j += 4) tile[j][x] = static_cast<double>(src[sx + b_src[j]]);
+  }
+  __syncthreads();
+  if (x < nb) {
+    const int64_t dx = dof + b_dst[x];
+    for (int j = y; j < na; j += 4) {
       double v[1] = {tile[x][j]};
-      store_vec<OUT, 1>(dst, dof + ia * p.run_ds + ib * p.t_ds, p.plane, v);
+      store_vec<OUT, 1>(dst, dx + a_dst[j], p.plane, v);
     }
   }
 }

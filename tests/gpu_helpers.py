@@ -92,8 +92,11 @@ def contracted_extent(sub, su: O.Sym) -> int:
     return math.prod(su.group.size * su.dims[tu.index(k)] for k in K)
 
 
-def random_case(rng, orders, s, t, v, nmax=3, nmin=1, sigma=None):
-    """A random contraction (subscripts and both operand symmetries) with s, t, v modes."""
+def random_case(rng, orders, s, t, v, nmax=3, nmin=1, sigma=None, dim_choices=None):
+    """A random contraction (subscripts and both operand symmetries) with s, t, v modes.
+
+    Block dims are uniform in [nmin, nmax], or drawn from ``dim_choices``.
+    """
     g = O.Group(orders)
     letters = iter("abcdefghijklmnop")
     I = [next(letters) for _ in range(s)]
@@ -102,7 +105,10 @@ def random_case(rng, orders, s, t, v, nmax=3, nmin=1, sigma=None):
     tu = list(I + K); rng.shuffle(tu)
     tv = list(K + J); rng.shuffle(tv)
     tw = list(I + J); rng.shuffle(tw)
-    dims = {m: int(rng.integers(nmin, nmax + 1)) for m in I + K + J}
+    if dim_choices is None:
+        dims = {m: int(rng.integers(nmin, nmax + 1)) for m in I + K + J}
+    else:
+        dims = {m: int(rng.choice(dim_choices)) for m in I + K + J}
     cu = {m: int(rng.choice([-1, 1])) for m in tu}
     sigma = int(rng.choice([-1, 1])) if sigma is None else sigma
     cv = {m: (sigma * cu[m] if m in K else int(rng.choice([-1, 1]))) for m in tv}

@@ -164,6 +164,70 @@ def test_align_and_unalign_bit_exact(P, case):
         assert np.array_equal(H.to_np(w32.data), ref.astype(np.float32))
 
 
+# In-block shapes whose fastest dims are tiny or odd: the transpose tile is
+# then a mixed-radix merge of several dims on each side, with ragged tiles.
+RAGGED_DIMS = (1, 2, 3, 5, 7, 9, 13, 17, 33, 65, 70)
+RAGGED_CASES = [((2, 3), 2, 2, 2), ((3,), 1, 2, 2), ((2,), 2, 1, 3), ((4,), 3, 1, 1), ((1,), 2, 2, 2)]
+
+
+def _check_align_unalign(P, sub, su, sv, rng):
+    Ru = rng.standard_normal(su.reduced_shape())
+    Rv = rng.standard_normal(sv.reduced_shape())
+    u = _sym_tensor(P, Ru, su)
+    v = _sym_tensor(P, Rv, sv)
+    Ual = O.align_u(sub, Ru, su, sv)
+    Val = O.align_v(sub, Rv, su, sv)
+    assert np.array_equal(H.to_np(P.align(sub, u, v, 0, "f64")), Ual)
+    assert np.array_equal(H.to_np(P.align(sub, u, v, 1, "f64")), Val)
+    assert np.array_equal(H.to_np(P.align(sub, u, v, 0, "f32")), Ual.astype(np.float32))
+    gu = H.to_np(P.align(sub, u, v, 0, "bf16x3")).view(np.uint16)
+    hi, lo = _bf16_planes_of(Ual)
+    assert np.array_equal(gu[0], hi) and np.array_equal(gu[1], lo)
+    gv = H.to_np(P.align(sub, u, v, 1, "bf16x3")).view(np.uint16)
+    hi, lo = _bf16_planes_of(np.ascontiguousarray(np.swapaxes(Val, 1, 2)))
+    assert np.array_equal(gv[0], hi) and np.array_equal(gv[1], lo)
+    Wal = rng.standard_normal((Ual.shape[0], Ual.shape[1], Val.shape[2]))
+    ref, _ = O.unalign_w(sub, Wal, su, sv)
+    w = P.output_like(sub, u, v)
+    P.unalign(sub, u, v, w, torch.from_numpy(Wal).to(DEV), "f64")
+    assert np.array_equal(H.to_np(w.data), ref)
+    w32 = P.output_like(sub, u, v, dtype=torch.float32)
+    P.unalign(sub, u, v, w32, torch.from_numpy(Wal).to(DEV, torch.float32), "f32")
+    assert np.array_equal(H.to_np(w32.data), ref.astype(np.float32))
+
+
+@pytest.mark.parametrize("case", RAGGED_CASES)
+def test_align_unalign_ragged_inner_dims(P, case):
+    orders, ns, nt, nv = case
+    rng = np.random.default_rng(abs(hash(("ragged",) + case)) % 2 ** 32)
+    G = int(np.prod(orders))
+    done = 0
+    while done < 3:
+        sub, su, sv = H.random_case(rng, orders, ns, nt, nv, dim_choices=RAGGED_DIMS)
+        tu, rest = sub.split(",")
+        tv, tw = rest.split("->")
+        dims = dict(zip(tu, su.dims)) | dict(zip(tv, sv.dims))
+        sizes = [G ** (len(x) - 1) * int(np.prod([dims[m] for m in x])) for x in (tu, tv, tw)]
+        if max(sizes) > 300000:
+            continue
+        say(f"ragged align {sub} G={orders} dims_u={su.dims} dims_v={sv.dims}")
+        _check_align_unalign(P, sub, su, sv, rng)
+        done += 1
+
+
+@pytest.mark.parametrize("sub,cu,du,cv,dv", [
+    # environment steps of an MPS with physical dim 2 and MPO bond 4 (bond 33)
+    ("bcsA,bsSB->cASB", (-1, -1, 1, -1), (4, 33, 2, 33), (1, -1, -1, -1), (4, 2, 2, 4)),
+    ("cASB,cSC->ABC", (-1, -1, -1, -1), (33, 33, 2, 4), (1, 1, -1), (33, 2, 33)),
+    ("abc,asA->bcsA", (-1, -1, -1), (33, 4, 33), (1, 1, -1), (33, 2, 33)),
+])
+def test_align_unalign_mps_environment_shapes(P, sub, cu, du, cv, dv):
+    g = O.Group((2, 3))
+    su, sv = O.Sym(cu, 0, du, g), O.Sym(cv, 0, dv, g)
+    say(f"mps-shape align {sub}")
+    _check_align_unalign(P, sub, su, sv, np.random.default_rng(5))
+
+
 # ---------------------------------------------------------------------------
 # whole path on random contractions
 # ---------------------------------------------------------------------------
