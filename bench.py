@@ -149,8 +149,8 @@ def time_workload(P, SG, wl, compute, steps, warmup, grad=False):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--extra", default="", help="write per-kernel details to this JSON file")
     ap.add_argument("--all", action="store_true",

@@ -179,7 +179,8 @@ int symtensor_workspace_size(const char* einsum, const symt_group* group, const 
  * is a caller-owned, 16-byte aligned device buffer of at least
  * info.workspace_bytes bytes holding U_al, V_al and W_al (256-byte aligned
  * sub-buffers, in that order), or for the fused product V_al and the offset
- * tables.
+ * tables; then, where the product runs stream-K (see symtensor_sector_gemm),
+ * the pieces of the tiles it cuts.
  * w->data must not overlap u->data, v->data or the workspace (SYMT_EALIAS).
  * Storage dtypes: SYMT_COMPUTE_F64 takes any mix of F64/F32 operands
  * (converted exactly to binary64); SYMT_COMPUTE_F32 and BF16X3 take any mix,
@@ -206,9 +207,24 @@ int symtensor_unalign(symt_ctx* ctx, const char* einsum, const symt_group* group
 /* Step (b) alone: c[q] = a[q] b[q] for q < batch over the aligned layouts of
  * the compute mode (a: batch x m x k, b: batch x k x n, or for BF16X3 the hi/lo
  * planes with b stored batch x n x k; c: batch x m x n in f64 for F64 and
- * BF16X3, f32 for F32).  c must not overlap a or b. */
+ * BF16X3, f32 for F32).  c must not overlap a, b or the workspace
+ * (SYMT_EALIAS).
+ * `workspace` (caller-owned device memory, 16-byte aligned, may be NULL) lets
+ * an F64 / F32 product run stream-K where the launch model prefers it: a fixed
+ * set of persistent workgroups takes equal shares of all tiles' K-iterations,
+ * so the last wave of tiles no longer idles most of the device; tiles cut
+ * between two workgroups are stored here as pieces and summed afterwards in K
+ * order (the result does not depend on scheduling).  With a NULL or smaller
+ * workspace the product runs one workgroup per tile.  The two launches differ
+ * only in floating-point summation order. */
 int symtensor_sector_gemm(symt_ctx* ctx, int32_t compute, int64_t batch, int64_t m, int64_t k,
-                          int64_t n, const void* a, const void* b, void* c, void* stream);
+                          int64_t n, const void* a, const void* b, void* c, void* workspace,
+                          size_t workspace_bytes, void* stream);
+
+/* Workspace bytes with which symtensor_sector_gemm may run stream-K for this
+ * shape (0: the model keeps one workgroup per tile).  Host-only. */
+int symtensor_sector_gemm_workspace_size(int32_t compute, int64_t batch, int64_t m, int64_t k,
+                                         int64_t n, size_t* bytes);
 
 /* Per-step timing: when enabled, symtensor_contract records a HIP event
  * pair around each of its kernel launches on the caller's stream.

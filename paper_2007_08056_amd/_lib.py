@@ -34,8 +34,8 @@ SYMT_FLAG_STEPS = 0x100
 EXPORTED = (
     "symtensor_create", "symtensor_destroy", "symtensor_plan", "symtensor_workspace_size",
     "symtensor_contract", "symtensor_align", "symtensor_unalign", "symtensor_sector_gemm",
-    "symtensor_set_timing", "symtensor_read_timing", "symtensor_status_string",
-    "symtensor_last_error",
+    "symtensor_sector_gemm_workspace_size", "symtensor_set_timing", "symtensor_read_timing",
+    "symtensor_status_string", "symtensor_last_error",
 )
 
 
@@ -65,7 +65,7 @@ class SymtError(RuntimeError):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_2007_08056_amd.build`")
+        raise ImportError(f"{LIB_PATH} is missing; build it with `python paper_2007_08056_amd/build.py`")
     lib = ctypes.CDLL(LIB_PATH)
     p_tensor = POINTER(SymtTensor)
     p_group = POINTER(SymtGroup)
@@ -82,7 +82,9 @@ def _load():
     lib.symtensor_unalign.argtypes = [c_void_p, c_char_p, p_group, p_tensor, p_tensor, p_tensor,
                                       c_int32, c_void_p, c_void_p]
     lib.symtensor_sector_gemm.argtypes = [c_void_p, c_int32, c_int64, c_int64, c_int64, c_int64,
-                                          c_void_p, c_void_p, c_void_p, c_void_p]
+                                          c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+    lib.symtensor_sector_gemm_workspace_size.argtypes = [c_int32, c_int64, c_int64, c_int64, c_int64,
+                                                         POINTER(c_size_t)]
     lib.symtensor_set_timing.argtypes = [c_void_p, c_int32]
     lib.symtensor_read_timing.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int64)]
     lib.symtensor_status_string.argtypes = [c_int]

@@ -4,7 +4,7 @@
   of include/symtensor.h).
 * ``synth/libsynthgen.so`` -- the GPU twin of the seeded input generator.
 
-Usage: ``python -m paper_2007_08056_amd.build`` (always recompiles).
+Usage: ``python paper_2007_08056_amd/build.py`` (always recompiles).
 """
 from __future__ import annotations
 

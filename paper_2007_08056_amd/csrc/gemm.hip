@@ -15,6 +15,8 @@
 // of one M panel land on the same XCD and share its L2).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
@@ -232,35 +234,40 @@ __device__ __forceinline__ void wait_vmcnt() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-template <typename T, int BM, int BN, int WM, int WN, int S, bool FA, bool FC>
-__global__ __launch_bounds__(64 * WM * WN) void k_gemm_dma(
-    const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C, int M, int N, int K,
-    int tiles_m, int tiles_n, int64_t ntiles, const int64_t* __restrict__ ra,
-    const int64_t* __restrict__ ca, const int64_t* __restrict__ rc, const int64_t* __restrict__ cc) {
-  constexpr int NW = WM * WN;
-  constexpr int NT = 64 * NW;
-  constexpr int VE = 16 / sizeof(T);              // elements per 16-byte chunk
-  constexpr int BK = 128 / sizeof(T);             // one 128-byte A row per K-step
-  constexpr int TM = BM / WM / 16;
-  constexpr int TN = BN / WN / 16;
-  constexpr int BCH = BN / VE;                    // chunks per B row
-  constexpr int A_LOADS = BM * 8 / NT;            // 16-byte loads per thread per stage
-  constexpr int B_LOADS = BK * BCH / NT;
+// Geometry of a global-to-LDS tile: BM x BN outputs, K-steps of one 128-byte
+// A row, S LDS stages, WM x WN waves.
+template <typename T, int BM, int BN, int WM, int WN, int S>
+struct DmaTile {
+  static constexpr int NW = WM * WN;
+  static constexpr int NT = 64 * NW;
+  static constexpr int VE = 16 / sizeof(T);                  // elements per 16-byte chunk
+  static constexpr int BK = 128 / sizeof(T);                 // one 128-byte A row per K-step
+  static constexpr int TM = BM / WM / 16;
+  static constexpr int TN = BN / WN / 16;
+  static constexpr int BCH = BN / VE;                        // chunks per B row
+  static constexpr int A_LOADS = BM * 8 / NT;                // 16-byte loads per thread per stage
+  static constexpr int B_LOADS = BK * BCH / NT;
+  static constexpr int STAGE = BM * 128 + BK * BN * static_cast<int>(sizeof(T));   // bytes per stage
   static_assert(TM * WM * 16 == BM && TN * WN * 16 == BN, "tile shape");
   static_assert(A_LOADS * NT == BM * 8 && B_LOADS * NT == BK * BCH, "loads must divide evenly");
   static_assert(BCH % 16 == 0, "B rows must hold a multiple of 16 chunks");
-  constexpr int STAGE = BM * 128 + BK * BN * static_cast<int>(sizeof(T));   // bytes per stage
-  __shared__ __attribute__((aligned(1024))) char smem[S * STAGE];
+  using Acc = typename Mfma<T>::Acc;
+};
 
-  const int64_t tile = xcd_remap(blockIdx.x, ntiles);
-  const int tn = static_cast<int>(tile % tiles_n);
-  const int64_t t2 = tile / tiles_n;
-  const int tm = static_cast<int>(t2 % tiles_m);
-  const int64_t q = t2 / tiles_m;
+// Accumulates K-steps [kt0, kt1) of the tile at (q, m0, n0) into acc (which the
+// caller zeroes).  Every wave leaves with its own loads drained; LDS may still
+// be read by other waves, so a caller that reuses smem barriers first.
+template <typename T, int BM, int BN, int WM, int WN, int S, bool FA>
+__device__ __forceinline__ void dma_tile_accumulate(
+    const T* __restrict__ A, const T* __restrict__ B, int M, int N, int K, int64_t q, int m0, int n0,
+    int kt0, int kt1, const int64_t* __restrict__ ra, const int64_t* __restrict__ ca, char* smem,
+    typename DmaTile<T, BM, BN, WM, WN, S>::Acc (&acc)[DmaTile<T, BM, BN, WM, WN, S>::TM]
+                                                      [DmaTile<T, BM, BN, WM, WN, S>::TN]) {
+  using D = DmaTile<T, BM, BN, WM, WN, S>;
+  constexpr int NT = D::NT, VE = D::VE, BK = D::BK, TM = D::TM, TN = D::TN, BCH = D::BCH;
+  constexpr int A_LOADS = D::A_LOADS, B_LOADS = D::B_LOADS, STAGE = D::STAGE;
   const T* Aq = A + (FA ? 0 : q * static_cast<int64_t>(M) * K);
   const T* Bq = B + q * static_cast<int64_t>(K) * N;
-  T* Cq = C + (FC ? 0 : q * static_cast<int64_t>(M) * N);
-  const int m0 = tm * BM, n0 = tn * BN;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -300,26 +307,19 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_dma(
       lds_dma16(Bq + b_src[i] + static_cast<int64_t>(k0) * N, base + BM * 128 + (i * NT + wave * 64) * 16);
   };
 
-  using Acc = typename Mfma<T>::Acc;
-  Acc acc[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = Acc{};
-
-  const int nk = K / BK;
+  const int nk = kt1 - kt0;
 #pragma unroll
   for (int s = 0; s < S - 1; ++s)
-    if (s < nk) issue(s, s);
-  for (int kt = 0; kt < nk; ++kt) {
-    // tile kt has landed once at most (S-2) later tiles' loads are outstanding
-    if (kt + S - 2 < nk) wait_vmcnt<(S - 2) * (A_LOADS + B_LOADS)>();
+    if (s < nk) issue(kt0 + s, s);
+  for (int it = 0; it < nk; ++it) {
+    // step it has landed once at most (S-2) later steps' loads are outstanding
+    if (it + S - 2 < nk) wait_vmcnt<(S - 2) * (A_LOADS + B_LOADS)>();
     else wait_vmcnt<0>();
     // a plain barrier: the explicit wait above already covers this wave's loads of
-    // tile kt, and a workgroup fence here would drain the loads still in flight
+    // step it, and a workgroup fence here would drain the loads still in flight
     asm volatile("s_barrier" ::: "memory");
-    if (kt + S - 1 < nk) issue(kt + S - 1, (kt + S - 1) % S);
-    const char* base = smem + (kt % S) * STAGE;
+    if (it + S - 1 < nk) issue(kt0 + it + S - 1, (it + S - 1) % S);
+    const char* base = smem + (it % S) * STAGE;
     const T* As = reinterpret_cast<const T*>(base);
     const T* Bs = reinterpret_cast<const T*>(base + BM * 128);
 #pragma unroll
@@ -342,7 +342,18 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_dma(
         for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<T>::run(a[i], b[j], acc[i][j]);
     }
   }
+}
 
+// Writes a finished tile: C[q] row-major, or scattered through W's offset tables.
+template <typename T, int BM, int BN, int WM, int WN, int TM, int TN, bool FC, typename Acc>
+__device__ __forceinline__ void store_tile(T* __restrict__ C, int M, int N, int64_t q, int m0, int n0,
+                                           const int64_t* __restrict__ rc,
+                                           const int64_t* __restrict__ cc, const Acc (&acc)[TM][TN]) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wm0 = (wave / WN) * (BM / WM);
+  const int wn0 = (wave % WN) * (BN / WN);
+  T* Cq = C + (FC ? 0 : q * static_cast<int64_t>(M) * N);
 #pragma unroll
   for (int j = 0; j < TN; ++j) {
     const int col = n0 + wn0 + j * 16 + (lane & 15);
@@ -358,6 +369,129 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_dma(
         }
       }
   }
+}
+
+// Piece of a cut tile in accumulator order: element ((wave*TM + i)*TN + j)*4 + r
+// of lane l sits at 64 * that + l, so stores and the fixup's loads coalesce.
+template <int TM, int TN, typename T, typename Acc>
+__device__ __forceinline__ void store_piece(T* __restrict__ piece, const Acc (&acc)[TM][TN]) {
+  const int lane = threadIdx.x & 63;
+  T* pw = piece + (threadIdx.x >> 6) * (TM * TN * 4 * 64) + lane;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) pw[((i * TN + j) * 4 + r) * 64] = acc[i][j][r];
+}
+
+// Stream-K partition: persistent workgroup w owns K-iterations [bound(w), bound(w+1))
+// of the concatenation of all tiles (tile-major, nk iterations each).
+__device__ __forceinline__ int64_t sk_bound(int64_t w, int64_t total, int P) {
+  return w * total / P;
+}
+
+// Sector product on global-to-LDS tiles.  SK = false: one workgroup per tile
+// (XCD-aware order).  SK = true: gridDim.x persistent workgroups take equal
+// shares of all K-iterations; a tile one of them covers whole is written as
+// usual, the pieces of a cut tile go to `part` for k_sk_fixup.
+template <typename T, int BM, int BN, int WM, int WN, int S, bool FA, bool FC, bool SK>
+__global__ __launch_bounds__(64 * WM * WN) void k_gemm_dma(
+    const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C, int M, int N, int K,
+    int tiles_m, int tiles_n, int64_t ntiles, const int64_t* __restrict__ ra,
+    const int64_t* __restrict__ ca, const int64_t* __restrict__ rc, const int64_t* __restrict__ cc,
+    T* __restrict__ part) {
+  using D = DmaTile<T, BM, BN, WM, WN, S>;
+  constexpr int TM = D::TM, TN = D::TN;
+  __shared__ __attribute__((aligned(1024))) char smem[S * D::STAGE];
+  typename D::Acc acc[TM][TN];
+  const int nk = K / D::BK;
+  if constexpr (!SK) {
+    const int64_t tile = xcd_remap(blockIdx.x, ntiles);
+    const int tn = static_cast<int>(tile % tiles_n);
+    const int64_t t2 = tile / tiles_n;
+    const int tm = static_cast<int>(t2 % tiles_m);
+    const int64_t q = t2 / tiles_m;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = typename D::Acc{};
+    dma_tile_accumulate<T, BM, BN, WM, WN, S, FA>(A, B, M, N, K, q, tm * BM, tn * BN, 0, nk, ra, ca,
+                                                  smem, acc);
+    store_tile<T, BM, BN, WM, WN, TM, TN, FC>(C, M, N, q, tm * BM, tn * BN, rc, cc, acc);
+  } else {
+    const int P = static_cast<int>(gridDim.x);
+    const int b = static_cast<int>(blockIdx.x);
+    // Neighbouring shares run on one XCD (workgroups are dealt round-robin to
+    // the 8 XCDs), so tiles sharing A rows meet in the same L2.
+    const int w = (P % 8 == 0) ? (b % 8) * (P / 8) + b / 8 : b;
+    const int64_t total = ntiles * nk;
+    int64_t it = sk_bound(w, total, P);
+    const int64_t end = sk_bound(w + 1, total, P);
+    const int64_t first = it / nk;
+    while (it < end) {
+      const int64_t tile = it / nk;
+      const int kt0 = static_cast<int>(it - tile * nk);
+      const int kt1 = static_cast<int>(min(static_cast<int64_t>(nk), kt0 + (end - it)));
+      const int tn = static_cast<int>(tile % tiles_n);
+      const int64_t t2 = tile / tiles_n;
+      const int tm = static_cast<int>(t2 % tiles_m);
+      const int64_t q = t2 / tiles_m;
+      __syncthreads();      // the previous piece's LDS reads are done before new loads land
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = typename D::Acc{};
+      dma_tile_accumulate<T, BM, BN, WM, WN, S, FA>(A, B, M, N, K, q, tm * BM, tn * BN, kt0, kt1, ra,
+                                                    ca, smem, acc);
+      if (kt0 == 0 && kt1 == nk)
+        store_tile<T, BM, BN, WM, WN, TM, TN, FC>(C, M, N, q, tm * BM, tn * BN, rc, cc, acc);
+      else
+        store_piece<TM, TN>(part + (2 * static_cast<int64_t>(w) + (tile == first ? 0 : 1)) * (BM * BN), acc);
+      it += kt1 - kt0;
+    }
+  }
+}
+
+// Sums the pieces of every tile that stream-K cut, in increasing K order (so
+// the result does not depend on scheduling), and writes the tile.  One
+// workgroup per tile; tiles covered whole by one workgroup return at once.
+template <typename T, int BM, int BN, int WM, int WN, bool FC>
+__global__ __launch_bounds__(64 * WM * WN) void k_sk_fixup(
+    const T* __restrict__ part, T* __restrict__ C, int M, int N, int nk, int tiles_m, int tiles_n,
+    int64_t ntiles, int P, const int64_t* __restrict__ rc, const int64_t* __restrict__ cc) {
+  constexpr int TM = BM / WM / 16, TN = BN / WN / 16;
+  using Acc = typename Mfma<T>::Acc;
+  const int64_t tile = blockIdx.x;
+  const int64_t total = ntiles * nk;
+  const int64_t x0 = tile * nk, x1 = x0 + nk;
+  // last workgroup whose share starts at or before x0 (its share is not empty)
+  int64_t w = ((x0 + 1) * P - 1) / total;
+  if (sk_bound(w + 1, total, P) >= x1) return;
+  Acc acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = Acc{};
+  const int lane = threadIdx.x & 63;
+  for (; w < P; ++w) {
+    const int64_t b0 = sk_bound(w, total, P), b1 = sk_bound(w + 1, total, P);
+    if (b0 >= x1) break;
+    if (b1 == b0) continue;
+    const T* pw = part + (2 * w + (b0 / nk == tile ? 0 : 1)) * (BM * BN) +
+                  (threadIdx.x >> 6) * (TM * TN * 4 * 64) + lane;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[i][j][r] += pw[((i * TN + j) * 4 + r) * 64];
+  }
+  const int tn = static_cast<int>(tile % tiles_n);
+  const int64_t t2 = tile / tiles_n;
+  const int tm = static_cast<int>(t2 % tiles_m);
+  const int64_t q = t2 / tiles_m;
+  store_tile<T, BM, BN, WM, WN, TM, TN, FC>(C, M, N, q, tm * BM, tn * BN, rc, cc, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -551,9 +685,23 @@ hipError_t launch_bf16x3(int64_t batch, int M, int N, int K, const void* A, cons
   return hipGetLastError();
 }
 
+// Compute units of the current device (cached per device).
+int device_cus() {
+  static std::atomic<int> cus[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  int n = cus[dev].load(std::memory_order_relaxed);
+  if (n == 0) {
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
+    cus[dev].store(n, std::memory_order_relaxed);
+  }
+  return n;
+}
+
+// part / part_bytes: stream-K piece buffer (nullptr: one workgroup per tile).
 template <typename T, int BM, int BN, int WM, int WN, int S>
 hipError_t launch_dma(int64_t batch, int M, int N, int K, const void* A, const void* B, void* C,
-                      hipStream_t s, const FusedTables* f) {
+                      hipStream_t s, const FusedTables* f, void* part, size_t part_bytes) {
   // B rows must hold a multiple of 16 chunks of 16 bytes (the swizzle works in
   // halves of a bank cycle); other shapes are never selected for this type.
   if constexpr ((BN * sizeof(T) / 16) % 16 != 0) {
@@ -561,16 +709,57 @@ hipError_t launch_dma(int64_t batch, int M, int N, int K, const void* A, const v
   } else {
   const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
   const int64_t ntiles = batch * tiles_m * tiles_n;
-  const dim3 grid(static_cast<unsigned>(ntiles)), block(64 * WM * WN);
+  const dim3 block(64 * WM * WN);
   const T* a = static_cast<const T*>(A);
   const T* b = static_cast<const T*>(B);
   T* c = static_cast<T*>(C);
+  const int64_t* ra = f ? f->ra : nullptr;
+  const int64_t* ca = f ? f->ca : nullptr;
+  const int64_t* rc = f ? f->rc : nullptr;
+  const int64_t* cc = f ? f->cc : nullptr;
+  const int nk = K / DmaTile<T, BM, BN, WM, WN, S>::BK;
+  int P = 0;
+  if (part) {
+    // resident workgroups per CU of this instantiation (fused or not), cached
+    static std::atomic<int> occupancy[2];
+    int occ = occupancy[f ? 1 : 0].load(std::memory_order_relaxed);
+    if (occ == 0) {
+      auto kern = f ? k_gemm_dma<T, BM, BN, WM, WN, S, true, true, true>
+                    : k_gemm_dma<T, BM, BN, WM, WN, S, false, false, true>;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64 * WM * WN, 0) != hipSuccess || occ < 1)
+        occ = 1;
+      occupancy[f ? 1 : 0].store(occ, std::memory_order_relaxed);
+    }
+    const int64_t slots = static_cast<int64_t>(device_cus()) * occ;
+    const int64_t by_work = ntiles * nk / kSkMinIters;
+    P = static_cast<int>(std::min<int64_t>({static_cast<int64_t>(kSkSlots), slots, by_work}));
+    if (P < 1 || 2 * static_cast<size_t>(P) * BM * BN * sizeof(T) > part_bytes) P = 0;
+  }
+  T* pt = static_cast<T*>(part);
+  if (P > 0) {
+    if (f)
+      hipLaunchKernelGGL((k_gemm_dma<T, BM, BN, WM, WN, S, true, true, true>), dim3(P), block, 0, s, a,
+                         b, c, M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt);
+    else
+      hipLaunchKernelGGL((k_gemm_dma<T, BM, BN, WM, WN, S, false, false, true>), dim3(P), block, 0, s,
+                         a, b, c, M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (f)
+      hipLaunchKernelGGL((k_sk_fixup<T, BM, BN, WM, WN, true>), dim3(static_cast<unsigned>(ntiles)),
+                         block, 0, s, pt, c, M, N, nk, tiles_m, tiles_n, ntiles, P, rc, cc);
+    else
+      hipLaunchKernelGGL((k_sk_fixup<T, BM, BN, WM, WN, false>), dim3(static_cast<unsigned>(ntiles)),
+                         block, 0, s, pt, c, M, N, nk, tiles_m, tiles_n, ntiles, P, rc, cc);
+    return hipGetLastError();
+  }
+  const dim3 grid(static_cast<unsigned>(ntiles));
   if (f)
-    hipLaunchKernelGGL((k_gemm_dma<T, BM, BN, WM, WN, S, true, true>), grid, block, 0, s, a, b, c, M,
-                       N, K, tiles_m, tiles_n, ntiles, f->ra, f->ca, f->rc, f->cc);
+    hipLaunchKernelGGL((k_gemm_dma<T, BM, BN, WM, WN, S, true, true, false>), grid, block, 0, s, a, b,
+                       c, M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt);
   else
-    hipLaunchKernelGGL((k_gemm_dma<T, BM, BN, WM, WN, S, false, false>), grid, block, 0, s, a, b, c,
-                       M, N, K, tiles_m, tiles_n, ntiles, nullptr, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL((k_gemm_dma<T, BM, BN, WM, WN, S, false, false, false>), grid, block, 0, s, a,
+                       b, c, M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt);
   return hipGetLastError();
   }
 }
@@ -578,24 +767,11 @@ hipError_t launch_dma(int64_t batch, int M, int N, int K, const void* A, const v
 // One f64/f32 tile configuration.  dma: direct global->LDS loads into an
 // S-stage ring (needs K to be a multiple of the 128-byte K-depth and N a
 // multiple of 16 bytes).
-struct FpTile {
-  const char* name;
-  int bm, bn;
-  bool dma;
-  double eff;     // measured f64 MFMA efficiency on a large, evenly tiled product
-};
-constexpr FpTile kFpTiles[] = {
-    {"128x128", 128, 128, false, 0.80},  {"128x96", 128, 96, false, 0.76},
-    {"128x64", 128, 64, false, 0.77},    {"128x48", 128, 48, false, 0.72},
-    {"96x96", 96, 96, false, 0.72},      {"64x96", 64, 96, false, 0.71},
-    {"d128x128s2", 128, 128, true, 0.84}, {"d128x96s2", 128, 96, true, 0.79},
-    {"d128x64s3", 128, 64, true, 0.77},  {"d96x96s3", 96, 96, true, 0.74},
-};
-constexpr int kNumFpTiles = sizeof(kFpTiles) / sizeof(kFpTiles[0]);
-
+// Dispatch order = the tile table of choose_fp_gemm.
 template <typename T>
 hipError_t launch_fp_tile(int idx, int vec, int64_t batch, int M, int N, int K, const void* A,
-                          const void* B, void* C, hipStream_t s, const FusedTables* f) {
+                          const void* B, void* C, hipStream_t s, const FusedTables* f, void* part,
+                          size_t part_bytes) {
   switch (idx) {
     case 0: return launch_fp<T, 128, 128, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s, f);
     case 1: return launch_fp<T, 128, 96, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s, f);
@@ -603,46 +779,18 @@ hipError_t launch_fp_tile(int idx, int vec, int64_t batch, int M, int N, int K, 
     case 3: return launch_fp<T, 128, 48, 16, 4, 1>(vec, batch, M, N, K, A, B, C, s, f);
     case 4: return launch_fp<T, 96, 96, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s, f);
     case 5: return launch_fp<T, 64, 96, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s, f);
-    case 6: return launch_dma<T, 128, 128, 2, 2, 2>(batch, M, N, K, A, B, C, s, f);
-    case 7: return launch_dma<T, 128, 96, 2, 2, 2>(batch, M, N, K, A, B, C, s, f);
-    case 8: return launch_dma<T, 128, 64, 2, 2, 3>(batch, M, N, K, A, B, C, s, f);
-    default: return launch_dma<T, 96, 96, 2, 2, 3>(batch, M, N, K, A, B, C, s, f);
+    case 6: return launch_dma<T, 128, 128, 2, 2, 2>(batch, M, N, K, A, B, C, s, f, part, part_bytes);
+    case 7: return launch_dma<T, 128, 96, 2, 2, 2>(batch, M, N, K, A, B, C, s, f, part, part_bytes);
+    case 8: return launch_dma<T, 128, 64, 2, 2, 3>(batch, M, N, K, A, B, C, s, f, part, part_bytes);
+    default: return launch_dma<T, 96, 96, 2, 2, 3>(batch, M, N, K, A, B, C, s, f, part, part_bytes);
   }
-}
-
-// Estimated time of a tiling: padded tile work, rounded up to whole waves of
-// tiles over the 256 compute units, divided by the tile's measured efficiency.
-double tile_cost(int64_t batch, int64_t M, int64_t N, const FpTile& t) {
-  const int64_t tiles = batch * ((M + t.bm - 1) / t.bm) * ((N + t.bn - 1) / t.bn);
-  const int64_t waves = (tiles + 255) / 256;
-  return static_cast<double>(waves) * t.bm * t.bn / t.eff;
-}
-
-// aligned: A and B start on 16-byte boundaries (required by the DMA tiles).
-int pick_fp_tile(int64_t batch, int64_t M, int64_t N, int64_t K, int elem, bool aligned) {
-  auto usable = [&](const FpTile& t) {
-    if (!t.dma) return true;
-    return aligned && K % (128 / elem) == 0 && N % (16 / elem) == 0 && (t.bn * elem / 16) % 16 == 0;
-  };
-  const char* forced = std::getenv("SYMT_GEMM_TILE");
-  if (forced)
-    for (int i = 0; i < kNumFpTiles; ++i)
-      if (std::strcmp(forced, kFpTiles[i].name) == 0 && usable(kFpTiles[i])) return i;
-  int best = -1;
-  double best_cost = 0;
-  for (int i = 0; i < kNumFpTiles; ++i) {
-    if (!usable(kFpTiles[i])) continue;
-    const double c = tile_cost(batch, M, N, kFpTiles[i]);
-    if (best < 0 || c < best_cost) { best = i; best_cost = c; }
-  }
-  return best;
 }
 
 }  // namespace
 
 int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t n, const void* A,
                        const void* B, void* C, hipStream_t stream, std::string* err,
-                       const FusedTables* fused) {
+                       const FusedTables* fused, void* part, size_t part_bytes) {
   if (batch == 0 || m == 0 || n == 0) return SYMT_OK;
   if (m > INT32_MAX || n > INT32_MAX || k > INT32_MAX) {
     if (err) *err = "sector product dimension above 2^31-1";
@@ -675,9 +823,10 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
     const int vec = (K % vw == 0 && N % vw == 0) ? vw : 1;
     const bool aligned = (reinterpret_cast<uintptr_t>(A) & 15) == 0 &&
                          (reinterpret_cast<uintptr_t>(B) & 15) == 0 && (!fused || fused->vec > 1);
-    const int tile = pick_fp_tile(batch, M, N, K, f64 ? 8 : 4, aligned);
-    e = f64 ? launch_fp_tile<double>(tile, vec, batch, M, N, K, A, B, C, stream, fused)
-            : launch_fp_tile<float>(tile, vec, batch, M, N, K, A, B, C, stream, fused);
+    const GemmChoice gc = choose_fp_gemm(batch, M, N, K, f64 ? 8 : 4, aligned);
+    if (!gc.sk || (reinterpret_cast<uintptr_t>(part) & 15) != 0) part = nullptr;
+    e = f64 ? launch_fp_tile<double>(gc.tile, vec, batch, M, N, K, A, B, C, stream, fused, part, part_bytes)
+            : launch_fp_tile<float>(gc.tile, vec, batch, M, N, K, A, B, C, stream, fused, part, part_bytes);
   }
   if (e != hipSuccess) {
     if (err) *err = std::string("sector product launch: ") + hipGetErrorString(e);

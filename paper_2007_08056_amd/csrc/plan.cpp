@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 namespace symt {
@@ -290,7 +291,85 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
                       round_up(8 * G * p->N, 256);
     p->workspace = round_up(p->bytes_v_al, 256) + p->bytes_tables;
   }
+  // Room for stream-K pieces when the model would pick it on 16-byte aligned operands.
+  if (compute != SYMT_COMPUTE_BF16X3 && p->M > 0 && p->N > 0 && p->Kd > 0) {
+    const GemmChoice gc = choose_fp_gemm(p->g.size, p->M, p->N, p->Kd,
+                                         compute == SYMT_COMPUTE_F64 ? 8 : 4, true);
+    p->bytes_partial = gc.partial_bytes;
+    p->workspace += round_up(p->bytes_partial, 256);
+  }
   return SYMT_OK;
+}
+
+namespace {
+struct FpTile {
+  const char* name;
+  int bm, bn;
+  bool dma;
+  double eff;     // measured f64 MFMA efficiency on a large, evenly tiled product
+};
+// Order = dispatch order of the f64 / f32 launcher.
+constexpr FpTile kFpTiles[] = {
+    {"128x128", 128, 128, false, 0.80},  {"128x96", 128, 96, false, 0.76},
+    {"128x64", 128, 64, false, 0.77},    {"128x48", 128, 48, false, 0.72},
+    {"96x96", 96, 96, false, 0.72},      {"64x96", 64, 96, false, 0.71},
+    {"d128x128s2", 128, 128, true, 0.84}, {"d128x96s2", 128, 96, true, 0.79},
+    {"d128x64s3", 128, 64, true, 0.77},  {"d96x96s3", 96, 96, true, 0.74},
+};
+constexpr int kNumFpTiles = sizeof(kFpTiles) / sizeof(kFpTiles[0]);
+}  // namespace
+
+// Time model: a tile costs 2*bm*bn*K flops at its measured efficiency of one
+// CU's share of the MFMA peak.  Data-parallel launches pay whole waves of 256
+// tiles; stream-K pays the exact fraction plus writing and re-reading the
+// pieces of cut tiles (at most two per persistent workgroup) and one more launch.
+namespace {
+GemmChoice choose_among(int64_t batch, int64_t M, int64_t N, int64_t K, int elem, bool aligned,
+                        const char* forced, int sk_mode) {
+  auto usable = [&](const FpTile& t) {
+    if (!t.dma) return true;
+    return aligned && K % (128 / elem) == 0 && N % (16 / elem) == 0 && (t.bn * elem / 16) % 16 == 0;
+  };
+  const double per_cu = (elem == 8 ? 78.6e12 : 157.3e12) / 256.0;
+  GemmChoice best;
+  double best_t = 0;
+  for (int i = 0; i < kNumFpTiles; ++i) {
+    const FpTile& t = kFpTiles[i];
+    if (!usable(t)) continue;
+    if (forced && std::strcmp(forced, t.name) != 0) continue;
+    const int64_t tiles = batch * ((M + t.bm - 1) / t.bm) * ((N + t.bn - 1) / t.bn);
+    const double t_tile = 2.0 * t.bm * t.bn * static_cast<double>(K) / (t.eff * per_cu);
+    for (int sk = 0; sk < 2; ++sk) {
+      if (sk && (!t.dma || sk_mode == 0)) continue;
+      if (!sk && t.dma && sk_mode == 1) continue;
+      double time;
+      size_t partial = 0;
+      if (!sk) {
+        time = static_cast<double>((tiles + 255) / 256) * t_tile;
+      } else {
+        partial = 2 * static_cast<size_t>(kSkSlots) * t.bm * t.bn * elem;
+        time = static_cast<double>(tiles) / 256.0 * t_tile + 2.0 * static_cast<double>(partial) / 5e12 + 4e-6;
+      }
+      if (best.tile < 0 || time < best_t) {
+        best.tile = i; best.bm = t.bm; best.bn = t.bn; best.dma = t.dma; best.sk = sk;
+        best.partial_bytes = partial;
+        best_t = time;
+      }
+    }
+  }
+  return best;
+}
+}  // namespace
+
+// SYMT_GEMM_TILE=<name> restricts the choice to one tile (ignored where it does
+// not apply); SYMT_GEMM_SK=0 / 1 forbids / forces stream-K on the DMA tiles.
+GemmChoice choose_fp_gemm(int64_t batch, int64_t M, int64_t N, int64_t K, int elem, bool aligned) {
+  const char* forced = std::getenv("SYMT_GEMM_TILE");
+  const char* sk_env = std::getenv("SYMT_GEMM_SK");
+  const int sk_mode = sk_env ? std::atoi(sk_env) : -1;
+  GemmChoice g = choose_among(batch, M, N, K, elem, aligned, forced, sk_mode);
+  if (g.tile < 0) g = choose_among(batch, M, N, K, elem, aligned, nullptr, sk_mode);
+  return g;
 }
 
 namespace {

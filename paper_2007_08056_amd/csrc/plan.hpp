@@ -130,6 +130,7 @@ struct Plan {
   bool fused = false;               // A read from U's standard form, C written to W's
   size_t bytes_u_al = 0, bytes_v_al = 0, bytes_w_al = 0, workspace = 0;
   size_t bytes_tables = 0;          // fused: the four offset tables
+  size_t bytes_partial = 0;         // stream-K pieces of the product (0: data-parallel tiles)
   double flops = 0.0;
 };
 
@@ -142,6 +143,21 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
 constexpr int32_t kForceSteps = 0x100;
 // K-depth of every f64/f32 product tile (the fused path needs contiguous runs of it).
 constexpr int kFpBK = 16;
+
+// Launch choice of the f64 / f32 sector product, from a host-side cost model.
+struct GemmChoice {
+  int tile = -1;              // row of the tile table (dispatch order of the launcher)
+  int bm = 0, bn = 0;
+  bool dma = false;           // global-to-LDS tile
+  bool sk = false;            // stream-K: persistent workgroups split the K-iterations of all
+                              // tiles evenly; tiles cut between two of them are summed after
+  size_t partial_bytes = 0;   // stream-K workspace for the pieces of cut tiles
+};
+// Persistent workgroups of a stream-K product: 256 CUs x 2 resident workgroups.
+constexpr int kSkSlots = 512;
+// Fewest K-iterations a stream-K workgroup takes on (bounds the pieces per tile).
+constexpr int kSkMinIters = 4;
+GemmChoice choose_fp_gemm(int64_t batch, int64_t M, int64_t N, int64_t K, int elem, bool aligned);
 
 // Transform descriptor for operand 0 (U), 1 (V) or 2 (W) in the given direction.
 // `in_type` / `out_type` are the element types of the source and destination.

@@ -16,7 +16,8 @@ int launch_xform(const XformParams& p, bool in_f64, int out, const void* src, vo
                  hipStream_t stream, std::string* err);
 int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t n, const void* A,
                        const void* B, void* C, hipStream_t stream, std::string* err,
-                       const FusedTables* fused = nullptr);
+                       const FusedTables* fused = nullptr, void* part = nullptr,
+                       size_t part_bytes = 0);
 int launch_offsets(const OffsetParams& p, int64_t* out, hipStream_t stream, std::string* err);
 }  // namespace symt
 
@@ -115,10 +116,10 @@ int do_unalign(symt_ctx* ctx, const Plan& p, const void* wal, hipStream_t s) {
 
 int do_gemm(symt_ctx* ctx, int compute, int64_t batch, int64_t m, int64_t k, int64_t n,
             const void* a, const void* b, void* c, hipStream_t s,
-            const symt::FusedTables* fused = nullptr) {
+            const symt::FusedTables* fused = nullptr, void* part = nullptr, size_t part_bytes = 0) {
   std::string err;
   const int rc = timed(ctx, 2, s, [&] {
-    return symt::launch_sector_gemm(compute, batch, m, k, n, a, b, c, s, &err, fused);
+    return symt::launch_sector_gemm(compute, batch, m, k, n, a, b, c, s, &err, fused, part, part_bytes);
   });
   return rc ? ctx_fail(ctx, rc, err) : SYMT_OK;
 }
@@ -144,7 +145,9 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s) {
   if (rc_) return ctx_fail(ctx, rc_, err);
   if ((rc_ = do_align(ctx, p, 1, val, s))) return rc_;
   symt::FusedTables f{ra, ca, rc, cc, aligned16(p.U.data) ? 2 : 1};
-  return do_gemm(ctx, p.compute, p.g.size, p.M, p.Kd, p.N, p.U.data, val, p.W.data, s, &f);
+  char* part = reinterpret_cast<char*>(cc) + round_up(8 * G * p.N, 256);
+  return do_gemm(ctx, p.compute, p.g.size, p.M, p.Kd, p.N, p.U.data, val, p.W.data, s, &f,
+                 p.bytes_partial ? part : nullptr, p.bytes_partial);
 }
 
 int plan_for(symt_ctx* ctx, const char* einsum, const symt_group* group, const symt_tensor* u,
@@ -270,9 +273,12 @@ int symtensor_contract(symt_ctx* ctx, const char* einsum, const symt_group* grou
   void* ual = base;
   void* val = base + symt::round_up(p.bytes_u_al, 256);
   void* wal = base + symt::round_up(p.bytes_u_al, 256) + symt::round_up(p.bytes_v_al, 256);
+  char* part = static_cast<char*>(wal) + symt::round_up(p.bytes_w_al, 256);
   if ((rc = do_align(ctx, p, 0, ual, s))) return rc;
   if ((rc = do_align(ctx, p, 1, val, s))) return rc;
-  if ((rc = do_gemm(ctx, p.compute, p.g.size, p.M, p.Kd, p.N, ual, val, wal, s))) return rc;
+  if ((rc = do_gemm(ctx, p.compute, p.g.size, p.M, p.Kd, p.N, ual, val, wal, s, nullptr,
+                    p.bytes_partial ? part : nullptr, p.bytes_partial)))
+    return rc;
   if ((rc = do_unalign(ctx, p, wal, s))) return rc;
   return SYMT_OK;
 }
@@ -314,8 +320,21 @@ int symtensor_unalign(symt_ctx* ctx, const char* einsum, const symt_group* group
   return do_unalign(ctx, p, aligned_w, static_cast<hipStream_t>(stream));
 }
 
+int symtensor_sector_gemm_workspace_size(int32_t compute, int64_t batch, int64_t m, int64_t k,
+                                         int64_t n, size_t* bytes) {
+  if (!bytes) return ctx_fail(nullptr, SYMT_EINVAL, "bytes is NULL");
+  *bytes = 0;
+  if (compute < SYMT_COMPUTE_F64 || compute > SYMT_COMPUTE_BF16X3)
+    return ctx_fail(nullptr, SYMT_EDTYPE, "unknown compute mode");
+  if (batch < 0 || m < 0 || k < 0 || n < 0) return ctx_fail(nullptr, SYMT_EINVAL, "negative size");
+  if (compute != SYMT_COMPUTE_BF16X3 && batch > 0 && m > 0 && k > 0 && n > 0)
+    *bytes = symt::choose_fp_gemm(batch, m, n, k, compute == SYMT_COMPUTE_F64 ? 8 : 4, true).partial_bytes;
+  return SYMT_OK;
+}
+
 int symtensor_sector_gemm(symt_ctx* ctx, int32_t compute, int64_t batch, int64_t m, int64_t k,
-                          int64_t n, const void* a, const void* b, void* c, void* stream) {
+                          int64_t n, const void* a, const void* b, void* c, void* workspace,
+                          size_t workspace_bytes, void* stream) {
   if (!ctx) return ctx_fail(nullptr, SYMT_EINVAL, "context is NULL");
   if (compute < SYMT_COMPUTE_F64 || compute > SYMT_COMPUTE_BF16X3)
     return ctx_fail(ctx, SYMT_EDTYPE, "unknown compute mode");
@@ -332,9 +351,16 @@ int symtensor_sector_gemm(symt_ctx* ctx, int32_t compute, int64_t batch, int64_t
     return ctx_fail(ctx, SYMT_EUNSUPPORTED, "split-bf16 product needs k % 8 == 0 and 16-byte aligned planes");
   if (compute != SYMT_COMPUTE_BF16X3 && (!aligned16(a) || !aligned16(b) || !aligned16(c)))
     return ctx_fail(ctx, SYMT_EUNSUPPORTED, "sector product buffers must be 16-byte aligned");
+  if (!workspace) workspace_bytes = 0;
+  if (workspace_bytes && !aligned16(workspace))
+    return ctx_fail(ctx, SYMT_EUNSUPPORTED, "workspace must be 16-byte aligned");
+  if (overlaps(c, nc, workspace, workspace_bytes) || overlaps(a, na, workspace, workspace_bytes) ||
+      overlaps(b, nb, workspace, workspace_bytes))
+    return ctx_fail(ctx, SYMT_EALIAS, "workspace overlaps a, b or c");
   int rc = set_device(ctx);
   if (rc) return rc;
-  return do_gemm(ctx, compute, batch, m, k, n, a, b, c, static_cast<hipStream_t>(stream));
+  return do_gemm(ctx, compute, batch, m, k, n, a, b, c, static_cast<hipStream_t>(stream), nullptr,
+                 workspace_bytes ? workspace : nullptr, workspace_bytes);
 }
 
 int symtensor_set_timing(symt_ctx* ctx, int32_t enable) {

@@ -228,8 +228,21 @@ def unalign(subscripts: str, u: SymTensor, v: SymTensor, w: SymTensor, aligned_w
     return w
 
 
-def sector_gemm(a: torch.Tensor, b: torch.Tensor, compute: str = "f64", c: torch.Tensor | None = None):
-    """c[q] = a[q] b[q] on the aligned layouts (see include/symtensor.h)."""
+def sector_gemm_workspace_size(compute: str, batch: int, m: int, k: int, n: int) -> int:
+    """Bytes with which sector_gemm may run stream-K on this shape (0: never)."""
+    out = ctypes.c_size_t()
+    L.check(L.LIB.symtensor_sector_gemm_workspace_size(L.COMPUTE[compute], batch, m, k, n,
+                                                       ctypes.byref(out)))
+    return out.value
+
+
+def sector_gemm(a: torch.Tensor, b: torch.Tensor, compute: str = "f64", c: torch.Tensor | None = None,
+                workspace: torch.Tensor | None | bool = True):
+    """c[q] = a[q] b[q] on the aligned layouts (see include/symtensor.h).
+
+    ``workspace``: a uint8 device tensor, True (allocate what the launch model
+    asks for) or None (one workgroup per tile).
+    """
     dev = a.device
     if compute == "bf16x3":
         _, batch, m, k = a.shape
@@ -241,10 +254,16 @@ def sector_gemm(a: torch.Tensor, b: torch.Tensor, compute: str = "f64", c: torch
         cdt = a.dtype
     if c is None:
         c = torch.empty((batch, m, n), dtype=cdt, device=dev)
+    if workspace is True:
+        need = sector_gemm_workspace_size(compute, batch, m, k, n)
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev) if need else None
+    ws_ptr = ctypes.c_void_p(workspace.data_ptr()) if workspace is not None else None
+    ws_bytes = workspace.numel() if workspace is not None else 0
     ctx = L.context(dev.index or 0)
     L.check(L.LIB.symtensor_sector_gemm(ctx, L.COMPUTE[compute], batch, m, k, n,
                                         ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
-                                        ctypes.c_void_p(c.data_ptr()), ctypes.c_void_p(_stream(dev))), ctx)
+                                        ctypes.c_void_p(c.data_ptr()), ws_ptr, ws_bytes,
+                                        ctypes.c_void_p(_stream(dev))), ctx)
     return c
 
 

@@ -8,7 +8,7 @@ import torch
 
 _PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsynthgen.so")
 if not os.path.exists(_PATH):
-    raise ImportError(f"{_PATH} is missing; build it with `python -m paper_2007_08056_amd.build`")
+    raise ImportError(f"{_PATH} is missing; build it with `python paper_2007_08056_amd/build.py`")
 _LIB = ctypes.CDLL(_PATH)
 _LIB.synth_fill.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint32,
                             ctypes.c_uint32, ctypes.c_int, ctypes.c_double, ctypes.c_int,

@@ -168,7 +168,7 @@ def test_null_arguments():
     # context-taking calls reject a NULL context before touching the device
     assert L.LIB.symtensor_contract(None, b"abkl,klij->abij", ctypes.byref(g), good.ref, good.ref, good.ref,
                                     0, None, 0, None) == L.SYMT_EINVAL
-    assert L.LIB.symtensor_sector_gemm(None, 0, 1, 1, 1, 1, None, None, None, None) == L.SYMT_EINVAL
+    assert L.LIB.symtensor_sector_gemm(None, 0, 1, 1, 1, 1, None, None, None, None, 0, None) == L.SYMT_EINVAL
     assert L.LIB.symtensor_destroy(None) == 0
 
 
@@ -192,3 +192,38 @@ def test_status_strings():
     for code in range(-8, 1):
         assert L.status_string(code) not in ("", "unknown status")
     assert L.status_string(-99) == "unknown status"
+
+
+def _gemm_ws(compute, batch, m, k, n):
+    out = ctypes.c_size_t()
+    rc = L.LIB.symtensor_sector_gemm_workspace_size(compute, batch, m, k, n, ctypes.byref(out))
+    return rc, out.value
+
+
+def test_stream_k_choice_and_workspace(monkeypatch):
+    """Stream-K is chosen where whole waves of tiles would idle the device."""
+    monkeypatch.delenv("SYMT_GEMM_SK", raising=False)
+    monkeypatch.delenv("SYMT_GEMM_TILE", raising=False)
+    # CCD ladder over Z_8 (24 virtual, 6 occupied per sector): 864 tiles of 128 x 96
+    # on 256 CUs leave a last wave 3/8 full.
+    rc, ladder = _gemm_ws(L.COMPUTE["f64"], 8, 4608, 4608, 288)
+    assert rc == 0 and ladder > 0 and ladder % (2 * 512 * 8) == 0
+    # 16384 tiles: whole waves, nothing to recover.
+    assert _gemm_ws(L.COMPUTE["f64"], 16, 16384, 16384, 1024) == (0, 0)
+    # split-bf16 and empty products never need it
+    assert _gemm_ws(L.COMPUTE["bf16x3"], 8, 4608, 4608, 288) == (0, 0)
+    assert _gemm_ws(L.COMPUTE["f64"], 8, 0, 4608, 288) == (0, 0)
+    assert _gemm_ws(7, 1, 1, 1, 1)[0] == L.SYMT_EDTYPE
+    assert _gemm_ws(L.COMPUTE["f64"], 1, -1, 1, 1)[0] == L.SYMT_EINVAL
+    # forbidding it drops the workspace; the contraction's workspace carries the same pieces
+    u = _desc("++--", 0, (24, 24, 24, 24))
+    v = _desc("++--", 0, (24, 24, 6, 6))
+    g = L.make_group(8)
+    info = L.plan("abcd,cdij->abij", g, u, v, None, L.COMPUTE["f64"])
+    assert (info.m, info.k, info.n) == (4608, 4608, 288) and info.fused
+    r = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    base = r(info.bytes_v_al) + r(8 * 8 * 4608) * 2 + r(8 * 8 * 4608) + r(8 * 8 * 288)
+    assert info.workspace_bytes == base + r(ladder)
+    monkeypatch.setenv("SYMT_GEMM_SK", "0")
+    assert _gemm_ws(L.COMPUTE["f64"], 8, 4608, 4608, 288) == (0, 0)
+    assert L.plan("abcd,cdij->abij", g, u, v, None, L.COMPUTE["f64"]).workspace_bytes == base

@@ -402,14 +402,19 @@ def test_fused_product_equals_steps_and_oracle(P, case, compute):
     assert torch.equal(w_o.data, w_s.data)
 
 
-@pytest.mark.parametrize("tile", ["d128x128s2", "d128x96s2", "d128x64s3", "d96x96s3", "128x48", "64x96"])
+@pytest.mark.parametrize("tile,sk", [("d128x128s2", "0"), ("d128x96s2", "0"), ("d128x64s3", "0"),
+                                     ("d96x96s3", "0"), ("128x48", "0"), ("64x96", "0"),
+                                     ("d128x128s2", "1"), ("d128x96s2", "1"), ("d128x64s3", "1"),
+                                     ("d96x96s3", "1")])
 @pytest.mark.parametrize("compute", ["f64", "f32"])
-def test_sector_gemm_every_tile_on_ragged_shapes(P, tile, compute, monkeypatch):
-    """Each tile shape, forced, on shapes that leave partial tiles in M and N."""
+def test_sector_gemm_every_tile_on_ragged_shapes(P, tile, sk, compute, monkeypatch):
+    """Each tile shape, forced, on shapes that leave partial tiles in M and N;
+    sk = "1" forces stream-K, whose tiles are cut into 1 to 8 pieces here."""
     monkeypatch.setenv("SYMT_GEMM_TILE", tile)
-    for shape in ((2, 130, 64, 68), (3, 257, 96, 196), (1, 16, 32, 4)):
+    monkeypatch.setenv("SYMT_GEMM_SK", sk)
+    for shape in ((2, 130, 64, 68), (3, 257, 96, 196), (1, 16, 32, 4), (2, 200, 512, 100)):
         b, m, k, n = shape
-        say(f"sector_gemm tile={tile} {compute} {shape}")
+        say(f"sector_gemm tile={tile} sk={sk} {compute} {shape}")
         rng = np.random.default_rng(m + n + k)
         dt = torch.float64 if compute == "f64" else torch.float32
         a = torch.from_numpy(rng.standard_normal((b, m, k))).to(DEV, dt)
@@ -420,3 +425,5 @@ def test_sector_gemm_every_tile_on_ragged_shapes(P, tile, compute, monkeypatch):
         absb = np.matmul(np.abs(A64), np.abs(B64))
         fac = 2 * H.gamma(k, H.U64) if compute == "f64" else 1.05 * H.gamma(k, H.U32)
         assert np.all(np.abs(C - ref) <= fac * absb), (tile, compute, shape)
+        # the same launch again gives the same bits (pieces are summed in K order)
+        assert np.array_equal(H.to_np(P.sector_gemm(a, bb, compute)), C)
