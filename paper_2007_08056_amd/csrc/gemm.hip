@@ -385,22 +385,27 @@ __device__ __forceinline__ void store_piece(T* __restrict__ piece, const Acc (&a
       for (int r = 0; r < 4; ++r) pw[((i * TN + j) * 4 + r) * 64] = acc[i][j][r];
 }
 
-// Stream-K partition: persistent workgroup w owns K-iterations [bound(w), bound(w+1))
-// of the concatenation of all tiles (tile-major, nk iterations each).
-__device__ __forceinline__ int64_t sk_bound(int64_t w, int64_t total, int P) {
-  return w * total / P;
+// Stream-K partition.  Tiles come in groups of `ts` (1, or the tiles_n tiles of
+// one (q, M-panel), which read the same A rows).  A team of ts workgroups, one
+// per tile of a group, owns the K-iterations [bound(t), bound(t+1)) of the
+// concatenation of all groups (group-major, nk iterations each): its members
+// walk the same groups and K-steps side by side, so each A panel is fetched
+// into L2 once per team rather than once per tile.
+__device__ __forceinline__ int64_t sk_bound(int64_t t, int64_t total, int nteam) {
+  return t * total / nteam;
 }
 
 // Sector product on global-to-LDS tiles.  SK = false: one workgroup per tile
-// (XCD-aware order).  SK = true: gridDim.x persistent workgroups take equal
-// shares of all K-iterations; a tile one of them covers whole is written as
-// usual, the pieces of a cut tile go to `part` for k_sk_fixup.
+// (XCD-aware order).  SK = true: gridDim.x = 8 * teams_x * ts persistent
+// workgroups (teams_x teams of ts on each of the 8 XCDs, which receive
+// workgroups round-robin); a tile a team covers whole is written as usual,
+// the pieces of a cut tile go to `part` for k_sk_fixup.
 template <typename T, int BM, int BN, int WM, int WN, int S, bool FA, bool FC, bool SK>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm_dma(
     const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C, int M, int N, int K,
     int tiles_m, int tiles_n, int64_t ntiles, const int64_t* __restrict__ ra,
     const int64_t* __restrict__ ca, const int64_t* __restrict__ rc, const int64_t* __restrict__ cc,
-    T* __restrict__ part) {
+    T* __restrict__ part, int ts) {
   using D = DmaTile<T, BM, BN, WM, WN, S>;
   constexpr int TM = D::TM, TN = D::TN;
   __shared__ __attribute__((aligned(1024))) char smem[S * D::STAGE];
@@ -420,19 +425,22 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_dma(
                                                   smem, acc);
     store_tile<T, BM, BN, WM, WN, TM, TN, FC>(C, M, N, q, tm * BM, tn * BN, rc, cc, acc);
   } else {
-    const int P = static_cast<int>(gridDim.x);
     const int b = static_cast<int>(blockIdx.x);
-    // Neighbouring shares run on one XCD (workgroups are dealt round-robin to
-    // the 8 XCDs), so tiles sharing A rows meet in the same L2.
-    const int w = (P % 8 == 0) ? (b % 8) * (P / 8) + b / 8 : b;
-    const int64_t total = ntiles * nk;
-    int64_t it = sk_bound(w, total, P);
-    const int64_t end = sk_bound(w + 1, total, P);
+    const int teams_x = static_cast<int>(gridDim.x) / (8 * ts);
+    const int l = b / 8;                                   // slot on this XCD
+    const int team = (b % 8) * teams_x + l / ts;
+    const int member = l % ts;
+    const int nteam = 8 * teams_x;
+    const int64_t total = ntiles / ts * nk;
+    int64_t it = sk_bound(team, total, nteam);
+    const int64_t end = sk_bound(team + 1, total, nteam);
     const int64_t first = it / nk;
+    T* my_part = part + 2 * static_cast<int64_t>(team * ts + member) * (BM * BN);
     while (it < end) {
-      const int64_t tile = it / nk;
-      const int kt0 = static_cast<int>(it - tile * nk);
+      const int64_t grp = it / nk;
+      const int kt0 = static_cast<int>(it - grp * nk);
       const int kt1 = static_cast<int>(min(static_cast<int64_t>(nk), kt0 + (end - it)));
+      const int64_t tile = grp * ts + member;
       const int tn = static_cast<int>(tile % tiles_n);
       const int64_t t2 = tile / tiles_n;
       const int tm = static_cast<int>(t2 % tiles_m);
@@ -447,7 +455,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_dma(
       if (kt0 == 0 && kt1 == nk)
         store_tile<T, BM, BN, WM, WN, TM, TN, FC>(C, M, N, q, tm * BM, tn * BN, rc, cc, acc);
       else
-        store_piece<TM, TN>(part + (2 * static_cast<int64_t>(w) + (tile == first ? 0 : 1)) * (BM * BN), acc);
+        store_piece<TM, TN>(my_part + (grp == first ? 0 : BM * BN), acc);
       it += kt1 - kt0;
     }
   }
@@ -455,30 +463,32 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_dma(
 
 // Sums the pieces of every tile that stream-K cut, in increasing K order (so
 // the result does not depend on scheduling), and writes the tile.  One
-// workgroup per tile; tiles covered whole by one workgroup return at once.
+// workgroup per tile; tiles covered whole by one team return at once.
 template <typename T, int BM, int BN, int WM, int WN, bool FC>
 __global__ __launch_bounds__(64 * WM * WN) void k_sk_fixup(
     const T* __restrict__ part, T* __restrict__ C, int M, int N, int nk, int tiles_m, int tiles_n,
-    int64_t ntiles, int P, const int64_t* __restrict__ rc, const int64_t* __restrict__ cc) {
+    int64_t ntiles, int ts, int nteam, const int64_t* __restrict__ rc, const int64_t* __restrict__ cc) {
   constexpr int TM = BM / WM / 16, TN = BN / WN / 16;
   using Acc = typename Mfma<T>::Acc;
   const int64_t tile = blockIdx.x;
-  const int64_t total = ntiles * nk;
-  const int64_t x0 = tile * nk, x1 = x0 + nk;
-  // last workgroup whose share starts at or before x0 (its share is not empty)
-  int64_t w = ((x0 + 1) * P - 1) / total;
-  if (sk_bound(w + 1, total, P) >= x1) return;
+  const int64_t grp = tile / ts;
+  const int member = static_cast<int>(tile - grp * ts);
+  const int64_t total = ntiles / ts * nk;
+  const int64_t x0 = grp * nk, x1 = x0 + nk;
+  // last team whose share starts at or before x0 (its share is not empty)
+  int64_t t = ((x0 + 1) * nteam - 1) / total;
+  if (sk_bound(t + 1, total, nteam) >= x1) return;
   Acc acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = Acc{};
   const int lane = threadIdx.x & 63;
-  for (; w < P; ++w) {
-    const int64_t b0 = sk_bound(w, total, P), b1 = sk_bound(w + 1, total, P);
+  for (; t < nteam; ++t) {
+    const int64_t b0 = sk_bound(t, total, nteam), b1 = sk_bound(t + 1, total, nteam);
     if (b0 >= x1) break;
     if (b1 == b0) continue;
-    const T* pw = part + (2 * w + (b0 / nk == tile ? 0 : 1)) * (BM * BN) +
+    const T* pw = part + (2 * (t * ts + member) + (b0 / nk == grp ? 0 : 1)) * (BM * BN) +
                   (threadIdx.x >> 6) * (TM * TN * 4 * 64) + lane;
 #pragma unroll
     for (int i = 0; i < TM; ++i)
@@ -718,7 +728,7 @@ hipError_t launch_dma(int64_t batch, int M, int N, int K, const void* A, const v
   const int64_t* rc = f ? f->rc : nullptr;
   const int64_t* cc = f ? f->cc : nullptr;
   const int nk = K / DmaTile<T, BM, BN, WM, WN, S>::BK;
-  int P = 0;
+  int P = 0, ts = 1;
   if (part) {
     // resident workgroups per CU of this instantiation (fused or not), cached
     static std::atomic<int> occupancy[2];
@@ -730,36 +740,42 @@ hipError_t launch_dma(int64_t batch, int M, int N, int K, const void* A, const v
         occ = 1;
       occupancy[f ? 1 : 0].store(occ, std::memory_order_relaxed);
     }
-    const int64_t slots = static_cast<int64_t>(device_cus()) * occ;
-    const int64_t by_work = ntiles * nk / kSkMinIters;
-    P = static_cast<int>(std::min<int64_t>({static_cast<int64_t>(kSkSlots), slots, by_work}));
-    if (P < 1 || 2 * static_cast<size_t>(P) * BM * BN * sizeof(T) > part_bytes) P = 0;
+    const int64_t slots = std::min<int64_t>(kSkSlots, static_cast<int64_t>(device_cus()) * occ);
+    // Teams of tiles_n siblings when 8 XCDs hold at least one team each.
+    const int64_t per_xcd = slots / 8;
+    ts = (tiles_n <= per_xcd) ? tiles_n : 1;
+    int64_t teams_x = per_xcd / ts;
+    const int64_t by_work = (ntiles / ts) * nk / kSkMinIters;        // teams with >= kSkMinIters each
+    teams_x = std::min<int64_t>(teams_x, by_work / 8);
+    P = static_cast<int>(8 * teams_x * ts);
+    if (P < 8 || 2 * static_cast<size_t>(P) * BM * BN * sizeof(T) > part_bytes) P = 0;
   }
   T* pt = static_cast<T*>(part);
   if (P > 0) {
+    const int nteam = P / ts;
     if (f)
       hipLaunchKernelGGL((k_gemm_dma<T, BM, BN, WM, WN, S, true, true, true>), dim3(P), block, 0, s, a,
-                         b, c, M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt);
+                         b, c, M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, ts);
     else
       hipLaunchKernelGGL((k_gemm_dma<T, BM, BN, WM, WN, S, false, false, true>), dim3(P), block, 0, s,
-                         a, b, c, M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt);
+                         a, b, c, M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, ts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (f)
       hipLaunchKernelGGL((k_sk_fixup<T, BM, BN, WM, WN, true>), dim3(static_cast<unsigned>(ntiles)),
-                         block, 0, s, pt, c, M, N, nk, tiles_m, tiles_n, ntiles, P, rc, cc);
+                         block, 0, s, pt, c, M, N, nk, tiles_m, tiles_n, ntiles, ts, nteam, rc, cc);
     else
       hipLaunchKernelGGL((k_sk_fixup<T, BM, BN, WM, WN, false>), dim3(static_cast<unsigned>(ntiles)),
-                         block, 0, s, pt, c, M, N, nk, tiles_m, tiles_n, ntiles, P, rc, cc);
+                         block, 0, s, pt, c, M, N, nk, tiles_m, tiles_n, ntiles, ts, nteam, rc, cc);
     return hipGetLastError();
   }
   const dim3 grid(static_cast<unsigned>(ntiles));
   if (f)
     hipLaunchKernelGGL((k_gemm_dma<T, BM, BN, WM, WN, S, true, true, false>), grid, block, 0, s, a, b,
-                       c, M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt);
+                       c, M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, 1);
   else
     hipLaunchKernelGGL((k_gemm_dma<T, BM, BN, WM, WN, S, false, false, false>), grid, block, 0, s, a,
-                       b, c, M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt);
+                       b, c, M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, 1);
   return hipGetLastError();
   }
 }
