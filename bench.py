@@ -35,6 +35,12 @@ HBM_PEAK_GBS = 8000.0
 WORKLOAD = "ccd_ladder_z8"
 
 
+# Sources that decide the sector product's machine code and launch choice;
+# stored counter readings apply only while their digest is unchanged.
+PRODUCT_SOURCES = ("paper_2007_08056_amd/csrc/gemm.hip", "paper_2007_08056_amd/csrc/plan.hpp",
+                   "paper_2007_08056_amd/csrc/plan.cpp", "paper_2007_08056_amd/build.py")
+
+
 def source_digest(*rel):
     h = hashlib.sha256()
     for r in rel:
@@ -220,7 +226,7 @@ def main():
 
     gemm_ms = ms[2] / max(1, launches[2])
     achieved = info.flops / (gemm_ms * 1e-3) / 1e12
-    digest = source_digest("paper_2007_08056_amd/csrc/gemm.hip")
+    digest = source_digest(*PRODUCT_SOURCES)
     traffic = gemm_traffic("sector_gemm_f64_ccd_ladder_z8", digest)
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["f64"], "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK["f64"], 4), "traffic": traffic}

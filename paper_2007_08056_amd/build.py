@@ -18,9 +18,13 @@ ROOT = os.path.dirname(HERE)
 ARCH = os.environ.get("SYMT_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-# Packed FP32 ops are disabled for all device code.
+# Packed FP32 ops are disabled for all device code.  MFMA accumulators live in
+# VGPRs (gfx950 MFMAs read and write C/D there): otherwise loop-carried
+# accumulators are copied through AGPRs around every K-step, and reading an
+# MFMA result back drains the matrix pipe each time.
 COMMON = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17",
-          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-mllvm", "-amdgpu-mfma-vgpr-form"]
 
 LIB_SOURCES = ["plan.cpp", "symtensor.cpp", "xform.hip", "gemm.hip"]
 

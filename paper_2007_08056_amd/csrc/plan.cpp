@@ -309,12 +309,13 @@ struct FpTile {
   double eff;     // measured f64 MFMA efficiency on a large, evenly tiled product
 };
 // Order = dispatch order of the f64 / f32 launcher.
+// Efficiencies: f64, 16 x 6144 x 2048 x 1152, a whole number of 256-tile waves for every tile.
 constexpr FpTile kFpTiles[] = {
-    {"128x128", 128, 128, false, 0.80},  {"128x96", 128, 96, false, 0.76},
-    {"128x64", 128, 64, false, 0.77},    {"128x48", 128, 48, false, 0.72},
-    {"96x96", 96, 96, false, 0.72},      {"64x96", 64, 96, false, 0.71},
-    {"d128x128s2", 128, 128, true, 0.84}, {"d128x96s2", 128, 96, true, 0.79},
-    {"d128x64s3", 128, 64, true, 0.77},  {"d96x96s3", 96, 96, true, 0.74},
+    {"128x128", 128, 128, false, 0.78},  {"128x96", 128, 96, false, 0.75},
+    {"128x64", 128, 64, false, 0.72},    {"128x48", 128, 48, false, 0.73},
+    {"96x96", 96, 96, false, 0.73},      {"64x96", 64, 96, false, 0.73},
+    {"d128x128s2", 128, 128, true, 0.86}, {"d128x96s2", 128, 96, true, 0.84},
+    {"d128x64s3", 128, 64, true, 0.81},  {"d96x96s3", 96, 96, true, 0.84},
 };
 constexpr int kNumFpTiles = sizeof(kFpTiles) / sizeof(kFpTiles[0]);
 }  // namespace
@@ -322,7 +323,8 @@ constexpr int kNumFpTiles = sizeof(kFpTiles) / sizeof(kFpTiles[0]);
 // Time model: a tile costs 2*bm*bn*K flops at its measured efficiency of one
 // CU's share of the MFMA peak.  Data-parallel launches pay whole waves of 256
 // tiles; stream-K pays the exact fraction plus writing and re-reading the
-// pieces of cut tiles (at most two per persistent workgroup) and one more launch.
+// pieces of cut tiles (at most two per persistent workgroup), their pipeline
+// fills (~1.5 us each), and one more launch (~5 us).
 namespace {
 GemmChoice choose_among(int64_t batch, int64_t M, int64_t N, int64_t K, int elem, bool aligned,
                         const char* forced, int sk_mode) {
@@ -348,7 +350,8 @@ GemmChoice choose_among(int64_t batch, int64_t M, int64_t N, int64_t K, int elem
         time = static_cast<double>((tiles + 255) / 256) * t_tile;
       } else {
         partial = 2 * static_cast<size_t>(kSkSlots) * t.bm * t.bn * elem;
-        time = static_cast<double>(tiles) / 256.0 * t_tile + 2.0 * static_cast<double>(partial) / 5e12 + 4e-6;
+        time = static_cast<double>(tiles) / 256.0 * t_tile + 2.0 * static_cast<double>(partial) / 5e12 +
+               2 * 1.5e-6 + 5e-6;
       }
       if (best.tile < 0 || time < best_t) {
         best.tile = i; best.bm = t.bm; best.bn = t.bn; best.dma = t.dma; best.sk = sk;
