@@ -63,25 +63,44 @@ def gemm_traffic(kernel_key, digest):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(wl, budget_s=12.0):
-    """Loop-over-blocks oracle on a sample of V's stored blocks, timed on the host cores."""
+def cpu_baseline(wl, budget_s=12.0, threads=None):
+    """Loop-over-blocks oracle on a sample of V's stored blocks, timed on the host cores
+    (all of them, or `threads` BLAS threads)."""
+    import contextlib
+
     import numpy as np
     import oracle as O
     import synth
     from synth import philox
+    limit = contextlib.nullcontext()
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        from threadpoolctl import threadpool_info, threadpool_limits
+        if threads:
+            limit = threadpool_limits(limits=threads)
+        cores = threads or max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:  # noqa: BLE001
-        cores = os.cpu_count() or 1
+        cores = threads or os.cpu_count() or 1
+    with limit:
+        return _oracle_sample(wl, budget_s, cores, np, O, synth, philox)
+
+
+_ORACLE_INPUTS: dict = {}
+
+
+def _oracle_sample(wl, budget_s, cores, np, O, synth, philox):
     st = wl.steps[0]
     g = O.Group(wl.group)
     ou, ov = wl.operands[st.u], wl.operands[st.v]
     su = O.Sym.make(ou.signs, ou.charge, ou.dims, g)
     sv = O.Sym.make(ov.signs, ov.charge, ov.dims, g)
     G = g.size
-    Rv = synth.host_input(wl, st.v)                       # T: 10.6 M elements
-    Ru = np.zeros(wl.reduced_shape(st.u))
+    # V blocks are generated once per process and shared by the timed samples
+    cache = _ORACLE_INPUTS.setdefault(wl.name, {})
+    if "Rv" not in cache:
+        cache["Rv"] = synth.host_input(wl, st.v)          # T: 10.6 M elements
+        cache["Ru"] = np.zeros(wl.reduced_shape(st.u))
+        cache["made"] = set()
+    Rv, Ru, made = cache["Rv"], cache["Ru"], cache["made"]
     blk = int(np.prod(ou.dims))
     all_blocks = [(a, b, c) for a in range(G) for b in range(G) for c in range(G)]
     done_blocks, flops_per_block = 0, 2 * blk * int(np.prod(ov.dims[2:])) * G
@@ -90,6 +109,9 @@ def cpu_baseline(wl, budget_s=12.0):
     while i < len(all_blocks) and elapsed < budget_s:
         batch = all_blocks[i:i + 8]
         for b in batch:                                   # generate the sampled V blocks
+            if b in made:
+                continue
+            made.add(b)
             lin = np.ravel_multi_index(b, (G, G, G)) * blk
             Ru[b] = philox.values_at(np.arange(lin, lin + blk), wl.seed, ou.tensor_id, ou.dist,
                                      ou.scale).reshape(ou.dims)
@@ -102,6 +124,35 @@ def cpu_baseline(wl, budget_s=12.0):
     return {"value": round(gflops, 3), "unit": "GFLOP/s", "cores": int(cores), "kind": "oracle",
             "sample": f"loop-over-blocks oracle (numpy FP64) over {done_blocks} of {len(all_blocks)} "
                       f"stored blocks of V_abcd against all of T_cdij, {elapsed:.1f} s"}
+
+
+def cold_and_copy(P, st, u, v, w, ws, reps=5):
+    """Median step time with the 256 MB Infinity Cache flushed before every
+    repetition (a 1 GiB write), and the device-to-device copy rate of 1 GiB
+    (read + write bytes per second), the practical ceiling of a transform."""
+    import torch
+    flush = torch.empty(2 ** 27, dtype=torch.float64, device="cuda:0")
+    times = []
+    for _ in range(reps):
+        flush.fill_(1.0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        P.contract_into(st.einsum, u, v, w, "f64", ws)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    src = torch.ones(2 ** 27, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del flush, src, dst
+    return sorted(times)[len(times) // 2], copy_gbs
 
 
 def chain_flops(wl, compute):
@@ -122,6 +173,9 @@ def time_workload(P, SG, wl, compute, steps, warmup, grad=False):
 
     With grad, the backward of every step is two contractions of the forward's
     size (dU and dV), so the step does three times the forward's flops.
+    Warm-up runs at least `warmup` steps and at least 50 ms (clocks ramp up
+    after host-side idle); the figure is the median of three timed batches of
+    at least `steps` steps and 10 ms each.
     """
     import torch
     dt = torch.float64 if compute == "f64" else torch.float32
@@ -140,16 +194,23 @@ def time_workload(P, SG, wl, compute, steps, warmup, grad=False):
             cur[st.w] = P.einsum(st.einsum, cur[st.u], cur[st.v], compute)
         if grad:
             (cur[wl.output].data * cur["R"].data).sum().backward()
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
+
+    def run(n):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            step()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+    n, spent = 0, 0.0
+    while n < warmup or spent < 0.05:
+        spent += run(1)
+        n += 1
+    per = spent / n
+    batch = max(steps, int(0.01 / max(per, 1e-6)) + 1)
+    ms = sorted(run(batch) * 1e3 / batch for _ in range(3))[1]
     return {"ms_per_step": round(ms, 4), "tflops": round(flops / (ms * 1e-3) / 1e12, 2),
-            "flops_per_step": flops}
+            "flops_per_step": flops, "steps_per_batch": batch}
 
 
 def main():
@@ -245,6 +306,10 @@ def main():
         "bytes_u": info.elems_u * 8, "bytes_v": info.elems_v * 8, "bytes_w": info.elems_w * 8,
         "gemm_source_digest": digest,
     }
+    cold_ms, copy_gbs = cold_and_copy(P, st, u, v, w, ws)
+    extra["cold_ms_per_step"] = round(cold_ms, 4)
+    extra["cold_gflops"] = round(info.flops / (cold_ms * 1e-3) / 1e9, 2)
+    extra["d2d_copy_GBs"] = round(copy_gbs, 1)
     xf = extra["steps_kernel_ms_per_launch"]
     for key, nbytes in (("align_u", 2 * info.elems_u * 8), ("align_v", 2 * info.elems_v * 8),
                         ("unalign_w", 2 * info.elems_w * 8)):
@@ -272,6 +337,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(wl)
+        extra["cpu_baseline_1thread"] = cpu_baseline(wl, budget_s=6.0, threads=1)
 
     line = {
         "metric": "effective GFLOP/s of symmetric contraction (fwd) vs FP64 plain",
