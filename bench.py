@@ -11,7 +11,7 @@ dominant kernel (the sector product; its duration from HIP events the library
 records around each launch on the stream it launches on), and the CPU oracle's
 rate on a bounded sample of the same workload.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--extra PATH] [--all]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--extra PATH] [--all] [--suite]
 
 Where the layout allows (here it does), one step runs the fused product: A is
 read straight from V_abcd's standard form and C written straight into W_abij's,
@@ -222,6 +222,8 @@ def main():
     ap.add_argument("--extra", default="", help="write per-kernel details to this JSON file")
     ap.add_argument("--all", action="store_true",
                     help="also time every workload in every precision (written to --extra)")
+    ap.add_argument("--suite", action="store_true",
+                    help="also time the paper's Table 2 suite at full size (written to --extra)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run one plain elementwise kernel that reads and writes 256 MiB "
                          "(the reference for scaling HBM byte counters)")
@@ -333,6 +335,23 @@ def main():
                 print(f"{key}: {r['ms_per_step']:.3f} ms, {r['tflops']:.1f} TFLOP/s", file=sys.stderr, flush=True)
                 torch.cuda.empty_cache()
         extra["workloads"] = table
+
+    if args.suite:
+        import synth as S
+        table = {}
+        for label in S.configs.SUITE_LABELS:
+            wlx = S.configs.paper_suite_case(label)
+            for c in ("f64", "f32", "bf16x3"):
+                try:
+                    r = time_workload(P, SG, wlx, c, 3, 2)
+                except P._lib.SymtError as e:      # e.g. split-bf16 with K not a multiple of 8
+                    table[f"{label}/{c}"] = {"unsupported": str(e)}
+                    continue
+                table[f"{label}/{c}"] = r
+                print(f"suite {label}/{c}: {r['ms_per_step']:.3f} ms, {r['tflops']:.1f} TFLOP/s",
+                      file=sys.stderr, flush=True)
+                torch.cuda.empty_cache()
+        extra["suite"] = table
 
     cpu = None
     if not args.no_cpu:

@@ -32,6 +32,24 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
+// Tile order of one-workgroup-per-tile launches: within each Q, groups of
+// kGroupM M-panels, column by column, so the workgroups in flight on an XCD
+// (a contiguous run of tiles, see xcd_remap) share A panels and B panels in L2.
+constexpr int kGroupM = 8;
+__device__ __forceinline__ void tile_coords(int64_t tile, int tiles_m, int tiles_n, int64_t& q, int& tm,
+                                            int& tn) {
+  const int64_t per_q = static_cast<int64_t>(tiles_m) * tiles_n;
+  q = tile / per_q;
+  const int64_t t = tile - q * per_q;
+  const int64_t group_tiles = static_cast<int64_t>(kGroupM) * tiles_n;
+  const int64_t g = t / group_tiles;
+  const int first_m = static_cast<int>(g * kGroupM);
+  const int gm = min(tiles_m - first_m, kGroupM);
+  const int r = static_cast<int>(t - g * group_tiles);
+  tm = first_m + r % gm;
+  tn = r / gm;
+}
+
 __device__ __forceinline__ int64_t xcd_remap(int64_t wg, int64_t n) {
   const int64_t per = n / 8;
   if (wg >= per * 8) return wg;
@@ -101,10 +119,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
   __shared__ T Bs[2][BK][BN + PADB];
 
   const int64_t tile = xcd_remap(blockIdx.x, ntiles);
-  const int tn = static_cast<int>(tile % tiles_n);
-  const int64_t t2 = tile / tiles_n;
-  const int tm = static_cast<int>(t2 % tiles_m);
-  const int64_t q = t2 / tiles_m;
+  int64_t q;
+  int tm, tn;
+  tile_coords(tile, tiles_m, tiles_n, q, tm, tn);
   const T* Aq = A + (FA ? 0 : q * static_cast<int64_t>(M) * K);
   const T* Bq = B + q * static_cast<int64_t>(K) * N;
   T* Cq = C + (FC ? 0 : q * static_cast<int64_t>(M) * N);
@@ -413,10 +430,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_dma(
   const int nk = K / D::BK;
   if constexpr (!SK) {
     const int64_t tile = xcd_remap(blockIdx.x, ntiles);
-    const int tn = static_cast<int>(tile % tiles_n);
-    const int64_t t2 = tile / tiles_n;
-    const int tm = static_cast<int>(t2 % tiles_m);
-    const int64_t q = t2 / tiles_m;
+    int64_t q;
+    int tm, tn;
+    tile_coords(tile, tiles_m, tiles_n, q, tm, tn);
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -526,10 +542,9 @@ __global__ __launch_bounds__(64 * WM * WN, (WM * WN == 4 && BK == 32) ? 2 : 1) v
   __shared__ uint16_t Bsh[2][BN][LDK], Bsl[2][BN][LDK];
 
   const int64_t tile = xcd_remap(blockIdx.x, ntiles);
-  const int tn = static_cast<int>(tile % tiles_n);
-  const int64_t t2 = tile / tiles_n;
-  const int tm = static_cast<int>(t2 % tiles_m);
-  const int64_t q = t2 / tiles_m;
+  int64_t q;
+  int tm, tn;
+  tile_coords(tile, tiles_m, tiles_n, q, tm, tn);
   const int64_t offA = q * static_cast<int64_t>(M) * K;
   const int64_t offB = q * static_cast<int64_t>(N) * K;
   double* Cq = C + q * static_cast<int64_t>(M) * N;

@@ -599,12 +599,17 @@ XformParams make_xform(const Plan& p, int operand, bool to_aligned, int in_bytes
     while (lanes < 64 && lanes < vecs) { lanes *= 2; ++lg; }
     x.lanes_per_row = lanes;
     x.lanes_log2 = lg;
-    int64_t rpt = std::max<int64_t>(1, 32768 / std::max<int64_t>(1, x.run_len * in_bytes));
+    // Long runs are cut into chunks of 8192 elements (a multiple of every
+    // vector width) so that a block with few rows still spreads over many
+    // workgroups (a whole matrix block can be a single run).
+    x.run_chunk = x.run_len > 16384 ? 8192 : std::max<int64_t>(x.run_len, 1);
+    x.run_tiles = (x.run_len + x.run_chunk - 1) / x.run_chunk;
+    int64_t rpt = std::max<int64_t>(1, 32768 / std::max<int64_t>(1, x.run_chunk * in_bytes));
     rpt = std::max<int64_t>(rpt, 256 / lanes);
     rpt = std::min<int64_t>(rpt, 256);
     rpt = std::min<int64_t>(rpt, x.rows);
     x.rows_per_tile = std::max<int64_t>(rpt, 1);
-    x.tiles_per_block = (x.rows + x.rows_per_tile - 1) / x.rows_per_tile;
+    x.tiles_per_block = (x.rows + x.rows_per_tile - 1) / x.rows_per_tile * x.run_tiles;
   } else {
     x.vec = 1;
     x.tiles_run = static_cast<int32_t>((x.run_len + 63) / 64);

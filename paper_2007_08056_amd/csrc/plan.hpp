@@ -71,6 +71,7 @@ struct XformParams {
   int64_t bds[kMaxDims];
   int64_t rows;                     // product of bsize
   int64_t rows_per_tile;            // copy: rows per workgroup
+  int64_t run_chunk, run_tiles;     // copy: run elements per workgroup, chunks per run
   int64_t tiles_per_block;          // workgroups per block
   int32_t lanes_per_row;            // copy: power of two <= 64
   int32_t lanes_log2;
@@ -92,6 +93,16 @@ struct OffsetParams {
   int64_t dim[kMaxOrder];           // inner dims of the group's modes (group order)
   int64_t stride[kMaxOrder];        // their standard-form strides
   int64_t weight[kMaxOrder];        // standard-form offset of one unit of each mode's sector
+};
+
+// Up to six offset tables filled by one launch (entries of table t:
+// out[t][q * count + i] for q < |G|).
+constexpr int kMaxOffsetTables = 6;
+struct OffsetBatch {
+  int32_t n = 0;
+  OffsetParams t[kMaxOffsetTables];
+  int64_t* out[kMaxOffsetTables];
+  int64_t end[kMaxOffsetTables];    // running sum of |G| * count
 };
 
 // Device pointers of the four offset tables of the fused product: rows and

@@ -18,7 +18,7 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
                        const void* B, void* C, hipStream_t stream, std::string* err,
                        const FusedTables* fused = nullptr, void* part = nullptr,
                        size_t part_bytes = 0);
-int launch_offsets(const OffsetParams& p, int64_t* out, hipStream_t stream, std::string* err);
+int launch_offsets(const OffsetBatch& batch, hipStream_t stream, std::string* err);
 }  // namespace symt
 
 using symt::Plan;
@@ -136,11 +136,18 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s) {
   int64_t* cc = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(rc) + round_up(8 * G * p.M, 256));
   std::string err;
   int rc_ = timed(ctx, 0, s, [&] {
-    int r = symt::launch_offsets(symt::make_offsets(p, 0, true), ra, s, &err);
-    if (!r) r = symt::launch_offsets(symt::make_offsets(p, 0, false), ca, s, &err);
-    if (!r) r = symt::launch_offsets(symt::make_offsets(p, 2, true), rc, s, &err);
-    if (!r) r = symt::launch_offsets(symt::make_offsets(p, 2, false), cc, s, &err);
-    return r;
+    symt::OffsetBatch b;
+    const int ops[4] = {0, 0, 2, 2};
+    int64_t* outs[4] = {ra, ca, rc, cc};
+    int64_t run = 0;
+    for (int t = 0; t < 4; ++t) {
+      b.t[t] = symt::make_offsets(p, ops[t], t % 2 == 0);
+      b.out[t] = outs[t];
+      run += b.t[t].count * G;
+      b.end[t] = run;
+    }
+    b.n = 4;
+    return symt::launch_offsets(b, s, &err);
   });
   if (rc_) return ctx_fail(ctx, rc_, err);
   if ((rc_ = do_align(ctx, p, 1, val, s))) return rc_;

@@ -81,11 +81,14 @@ __global__ __launch_bounds__(256) void k_xform_copy(const Tin* __restrict__ src,
   const int64_t wg = blockIdx.x;
   const int64_t blk = wg / p.tiles_per_block;
   const int64_t tile = wg - blk * p.tiles_per_block;
+  const int64_t row_tile = tile / p.run_tiles;
+  const int64_t c_begin = (tile - row_tile * p.run_tiles) * p.run_chunk;
+  const int64_t c_end = c_begin + p.run_chunk < p.run_len ? c_begin + p.run_chunk : p.run_len;
   int64_t sb, ab;
   block_bases(p, blk, sb, ab);
   const int64_t src_base = p.to_aligned ? sb : ab;
   const int64_t dst_base = p.to_aligned ? ab : sb;
-  const int64_t r0 = tile * p.rows_per_tile;
+  const int64_t r0 = row_tile * p.rows_per_tile;
   const int64_t left = p.rows - r0;
   const int nr = static_cast<int>(left < p.rows_per_tile ? left : p.rows_per_tile);
   for (int r = threadIdx.x; r < nr; r += blockDim.x) {
@@ -107,7 +110,7 @@ __global__ __launch_bounds__(256) void k_xform_copy(const Tin* __restrict__ src,
   const int64_t step = static_cast<int64_t>(p.lanes_per_row) * V;
   for (int r = sub; r < nr; r += rpp) {
     const int64_t s0 = soff[r], d0 = doff[r];
-    for (int64_t c = static_cast<int64_t>(lane) * V; c < p.run_len; c += step) {
+    for (int64_t c = c_begin + static_cast<int64_t>(lane) * V; c < c_end; c += step) {
       double x[V];
       if constexpr (V == 1) {
         x[0] = static_cast<double>(src[s0 + c * p.run_ss]);
@@ -207,24 +210,28 @@ hipError_t launch_typed(const XformParams& p, const void* src, void* dst, hipStr
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_offsets(int64_t* __restrict__ out, const OffsetParams p,
-                                                 int64_t total) {
+__global__ __launch_bounds__(256) void k_offsets(const OffsetBatch b) {
+  const int64_t total = b.n > 0 ? b.end[b.n - 1] : 0;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += stride) {
-    const int q = static_cast<int>(i / p.count);
-    out[i] = group_offset(p, q, i - q * p.count);
+    int t = 0;
+    while (i >= b.end[t]) ++t;
+    const int64_t j = i - (t > 0 ? b.end[t - 1] : 0);
+    const OffsetParams& p = b.t[t];
+    const int q = static_cast<int>(j / p.count);
+    b.out[t][j] = group_offset(p, q, j - q * p.count);
   }
 }
 
 }  // namespace
 
-// Offset table of one sector group for every auxiliary sector: out[q * count + i].
-int launch_offsets(const OffsetParams& p, int64_t* out, hipStream_t stream, std::string* err) {
-  const int64_t total = p.count * p.g.size;
+// Every table of the batch in one launch.
+int launch_offsets(const OffsetBatch& batch, hipStream_t stream, std::string* err) {
+  const int64_t total = batch.n > 0 ? batch.end[batch.n - 1] : 0;
   if (total == 0) return SYMT_OK;
   int64_t blocks = (total + 255) / 256;
   if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_offsets, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, out, p, total);
+  hipLaunchKernelGGL(k_offsets, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, batch);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     if (err) *err = std::string("offset table launch: ") + hipGetErrorString(e);

@@ -9,7 +9,8 @@ example, Sec. 3).  Values come from ``synth.philox`` keyed by
 (seed, tensor id).
 
 Workloads (shapes taken from the paper's coupled-cluster and tensor-network
-contractions, Sec. 4 and Table 2):
+contractions, Sec. 4 and Table 2); ``paper_suite_case`` gives the twelve
+Table 2 cases of the Table 1 contractions (MM, CC1-3, MPS, PEPS):
 
 * ``plain_z4``      w_abij = sum_kl u_abkl v_klij, Z_4, every block dim 4.
 * ``ccd_ladder_z8`` w_abij = sum_cd V_abcd T_cdij, Z_8, virtual 24, occupied 6.
@@ -137,6 +138,48 @@ def mps_env_z2z3() -> Workload:
 
 def mps_env_grad() -> Workload:
     return _mps_env("mps_env_grad", 128, 4, True)
+
+
+# ---------------------------------------------------------------------------
+# The paper's benchmark suite (Table 1 contractions at Table 2 dimensions).
+# Block dimension per mode letter as in Table 2; signs are not given there and
+# are read as: every contracted pair carries opposite signs, and each operand's
+# signs sum to zero over its modes where the order allows (CC tensors ++--,
+# matrices +-, MPS tensors ++-); charges 0; values uniform in [-1, 1).
+# ---------------------------------------------------------------------------
+_SUITE = {
+    # label: (G, einsum, u signs, v signs, derived w signs, block dim per letter)
+    "cc1a": (8, "ijkl,mnkl->ijmn", "++--", "--++", "++--", dict(i=32, j=32, k=32, l=32, m=16, n=16)),
+    "cc2a": (8, "opij,opkm->ijmk", "++--", "--++", "--++", dict(i=32, j=32, k=32, m=16, o=16, p=16)),
+    "cc3a": (8, "opmn,opij->ijmn", "++--", "--++", "++--", dict(i=32, j=32, m=16, n=16, o=16, p=16)),
+    "cc1b": (16, "ijkl,mnkl->ijmn", "++--", "--++", "++--", dict(i=16, j=16, k=16, l=16, m=8, n=8)),
+    "cc2b": (16, "opij,opkm->ijmk", "++--", "--++", "--++", dict(i=16, j=16, k=16, m=8, o=8, p=8)),
+    "cc3b": (16, "opmn,opij->ijmn", "++--", "--++", "++--", dict(i=16, j=16, m=8, n=8, o=8, p=8)),
+    "mma": (2, "ij,jk->ik", "+-", "+-", "+-", dict(i=10000, j=10000, k=10000)),
+    "mmb": (100, "ij,jk->ik", "+-", "+-", "+-", dict(i=2000, j=2000, k=2000)),
+    "mpsa": (2, "ijk,klm->ijlm", "++-", "++-", "+++-", dict(i=3000, j=10, k=3000, l=1, m=3000)),
+    "mpsb": (5, "ijk,klm->ijlm", "++-", "++-", "+++-", dict(i=700, j=10, k=700, l=1, m=700)),
+    "pepsa": (2, "ijkl,klmn->ijmn", "++--", "++--", "++--", dict(i=400, j=400, k=20, l=20, m=20, n=20)),
+    "pepsb": (10, "ijkl,klmn->ijmn", "++--", "++--", "++--", dict(i=64, j=64, k=8, l=8, m=8, n=8)),
+}
+
+
+def paper_suite_case(label: str, dims: dict | None = None) -> Workload:
+    """One Table 2 case (``dims`` overrides block dimensions, for small test copies)."""
+    G, sub, su, sv, sw, d = _SUITE[label]
+    d = dict(d, **(dims or {}))
+    tu, rest = sub.split(",")
+    tv, tw = rest.split("->")
+    cid = 32 + sorted(_SUITE).index(label)
+    ops = {
+        "U": Operand("U", tu, su, 0, tuple(d[m] for m in tu), DIST_UNIFORM, 1.0, cid * 16 + 0),
+        "V": Operand("V", tv, sv, 0, tuple(d[m] for m in tv), DIST_UNIFORM, 1.0, cid * 16 + 1),
+        "W": Operand("W", tw, sw, 0, tuple(d[m] for m in tw)),
+    }
+    return Workload("suite_" + label, (G,), ops, (Contraction(sub, "U", "V", "W"),), ("U", "V"), "W")
+
+
+SUITE_LABELS = tuple(_SUITE)
 
 
 ALL = {

@@ -215,6 +215,18 @@ def test_align_unalign_ragged_inner_dims(P, case):
         done += 1
 
 
+@pytest.mark.parametrize("orders,sub,cu,du,cv,dv", [
+    # a whole matrix block is one run of 90000 elements: cut into ragged chunks
+    ((2,), "ij,jk->ik", (1, -1), (300, 300), (1, -1), (300, 300)),
+    ((3,), "ij,jk->ik", (1, -1), (200, 150), (1, -1), (150, 170)),
+    ((2,), "ijk,klm->ijlm", (1, 1, -1), (100, 3, 100), (1, 1, -1), (100, 1, 100)),
+])
+def test_align_unalign_long_runs(P, orders, sub, cu, du, cv, dv):
+    g = O.Group(orders)
+    say(f"long-run align {sub} G={orders} {du} {dv}")
+    _check_align_unalign(P, sub, O.Sym(cu, 0, du, g), O.Sym(cv, 0, dv, g), np.random.default_rng(9))
+
+
 @pytest.mark.parametrize("sub,cu,du,cv,dv", [
     # environment steps of an MPS with physical dim 2 and MPO bond 4 (bond 33)
     ("bcsA,bsSB->cASB", (-1, -1, 1, -1), (4, 33, 2, 33), (1, -1, -1, -1), (4, 2, 2, 4)),

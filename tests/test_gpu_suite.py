@@ -1,0 +1,120 @@
+"""The paper's benchmark suite (Table 1 contractions at Table 2 dimensions) on the GPU.
+
+Small copies (every block dimension shrunk, the group kept) are compared with
+the loop-over-blocks oracle in three precisions; the full Table 2 sizes are
+contracted in f64 and checked on sampled outputs against the sampled
+brute-force oracle.  These cases exercise operands whose contracted modes lead
+(CC2, CC3), a single contracted mode (MPS), |G| up to 100 (MM_b), and very
+tall products (PEPS_a: M = 320000).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from tests import gpu_helpers as H
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+SMALL = {
+    "cc": dict(i=4, j=3, k=5, l=2, m=3, n=2, o=2, p=3),
+    "mm": dict(i=7, j=5, k=6),
+    "mps": dict(i=5, j=3, k=6, l=1, m=4),
+    "peps": dict(i=5, j=4, k=3, l=2, m=3, n=2),
+}
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2007_08056_amd
+    return paper_2007_08056_amd
+
+
+@pytest.fixture(scope="module")
+def SG():
+    import synth.gpu
+    return synth.gpu
+
+
+def _small(label):
+    fam = "".join(ch for ch in label if ch.isalpha())[:-1]
+    return synth.configs.paper_suite_case(label, SMALL[fam])
+
+
+def _sym(wl, name):
+    op = wl.operands[name]
+    return O.Sym.make(op.signs, op.charge, op.dims, O.Group(wl.group))
+
+
+def _tensor(P, SG, wl, name, dtype=torch.float64):
+    op = wl.operands[name]
+    return P.SymTensor(SG.device_input(wl, name, dtype=dtype, device=DEV), op.signs, op.charge, wl.group)
+
+
+@pytest.mark.parametrize("label", synth.configs.SUITE_LABELS)
+def test_suite_small_vs_oracle(P, SG, label):
+    wl = _small(label)
+    st = wl.steps[0]
+    su, sv = _sym(wl, "U"), _sym(wl, "V")
+    Ru, Rv = synth.host_input(wl, "U"), synth.host_input(wl, "V")
+    ref, sw = O.contract_blocks(st.einsum, Ru, su, Rv, sv)
+    absref, _ = O.contract_blocks(st.einsum, np.abs(Ru), su, np.abs(Rv), sv)
+    assert sw.sign_string() == wl.operands["W"].signs or \
+        sw.sign_string() == "".join("+" if c == "-" else "-" for c in wl.operands["W"].signs)
+    k = H.contracted_extent(st.einsum, su)
+    for compute in ("f64", "f32", "bf16x3"):
+        dt = torch.float64 if compute == "f64" else torch.float32
+        u, v = _tensor(P, SG, wl, "U", dt), _tensor(P, SG, wl, "V", dt)
+        info = P.plan(st.einsum, u, v, compute)
+        if compute == "bf16x3" and info.k % 8:
+            continue
+        say(f"suite {label} small {compute}: batch {info.group_size} m {info.m} k {info.k} n {info.n}")
+        w = P.output_like(st.einsum, u, v, dtype=torch.float64)
+        P.contract_into(st.einsum, u, v, w, compute)
+        got = H.to_np(w.data)
+        if compute == "f64":
+            assert H.rel_err(got, ref) <= 1e-12
+            assert np.all(np.abs(got - ref) <= H.bound_factor("f64", k) * absref + 1e-300)
+            assert np.array_equal(O.expand(got, sw) == 0, O.expand(ref, sw) == 0)
+        else:
+            # against the binary64 inputs: adds the input rounding
+            assert np.all(np.abs(got - ref) <= (H.bound_factor(compute, k) + 2.1 * H.U32) * absref + 1e-300)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("label", synth.configs.SUITE_LABELS)
+def test_suite_full_size_sampled(P, SG, label):
+    wl = synth.configs.paper_suite_case(label)
+    st = wl.steps[0]
+    su, sv = _sym(wl, "U"), _sym(wl, "V")
+    say(f"suite {label} full: generating inputs")
+    u, v = _tensor(P, SG, wl, "U"), _tensor(P, SG, wl, "V")
+    w = P.output_like(st.einsum, u, v)
+    info = P.plan(st.einsum, u, v, "f64", w)
+    say(f"suite {label} full: batch {info.group_size} m {info.m} k {info.k} n {info.n}, "
+        f"{info.flops / 1e12:.3f} TFLOP, fused {info.fused}")
+    P.contract_into(st.einsum, u, v, w, "f64")
+    torch.cuda.synchronize()
+    del u, v
+    torch.cuda.empty_cache()
+    sw = O.output_symmetry(st.einsum, su, sv)
+    red, full = H.random_w_positions(sw, 32, np.random.default_rng(7))
+    got = np.array([w.data[r].item() for r in red])
+    del w
+    torch.cuda.empty_cache()
+    say(f"suite {label} full: oracle on {len(red)} sampled outputs")
+    ref = O.sample_contract(st.einsum, su, sv, H.value_fn(wl, "U"), H.value_fn(wl, "V"), full)
+    absref = O.sample_contract(st.einsum, su, sv, H.value_fn(wl, "U", True), H.value_fn(wl, "V", True), full)
+    k = H.contracted_extent(st.einsum, su)
+    err = H.rel_err(got, ref)
+    say(f"  normwise relative error on samples {err:.3e}")
+    assert err <= 1e-12
+    assert np.all(np.abs(got - ref) <= H.bound_factor("f64", k) * absref)
