@@ -288,7 +288,8 @@ __device__ __forceinline__ void dma_tile_accumulate(
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  // wave-uniform: LDS destinations of the DMA loads (M0) stay scalar arithmetic
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm0 = (wave / WN) * (BM / WM);
   const int wn0 = (wave % WN) * (BN / WN);
 
@@ -312,9 +313,16 @@ __device__ __forceinline__ void dma_tile_accumulate(
     const int gn = min(n0 + gch * VE, N - VE);
     b_src[i] = static_cast<int64_t>(k) * N + gn;
   }
+  // Fused A: column offset of each K-step, fetched one issue ahead so its
+  // latency hides behind the previous step's products.
+  int64_t acol_next = FA && kt0 < kt1 ? ca[q * K + static_cast<int64_t>(kt0) * BK] : 0;
   auto issue = [&](int kt, int stage) {
     const int k0 = kt * BK;
-    const int64_t acol = FA ? ca[q * K + k0] : k0;
+    int64_t acol = k0;
+    if constexpr (FA) {
+      acol = acol_next;
+      if (kt + 1 < kt1) acol_next = ca[q * K + static_cast<int64_t>(kt + 1) * BK];
+    }
     char* base = smem + stage * STAGE;
 #pragma unroll
     for (int i = 0; i < A_LOADS; ++i)

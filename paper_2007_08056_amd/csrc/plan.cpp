@@ -306,17 +306,21 @@ struct FpTile {
   const char* name;
   int bm, bn;
   bool dma;
-  double eff;     // measured f64 MFMA efficiency on a large, evenly tiled product
+  double eff64, eff32;   // measured MFMA efficiency on a large, evenly tiled product
 };
-// Order = dispatch order of the f64 / f32 launcher.
-// Efficiencies: f64, 16 x 6144 x 2048 x 1152, a whole number of 256-tile waves for every tile.
+// Efficiencies: 16 x 6144 x 2048 x 1152, a whole number of 256-tile waves for
+// every tile; f64 and f32.
 constexpr FpTile kFpTiles[] = {
-    {"128x128", 128, 128, false, 0.78},  {"128x96", 128, 96, false, 0.75},
-    {"128x64", 128, 64, false, 0.72},    {"128x48", 128, 48, false, 0.73},
-    {"96x96", 96, 96, false, 0.73},      {"64x96", 64, 96, false, 0.73},
-    {"d128x128s2", 128, 128, true, 0.86}, {"d128x96s2", 128, 96, true, 0.84},
-    {"d128x64s3", 128, 64, true, 0.81},  {"d96x96s3", 96, 96, true, 0.84},
+    {"128x128", 128, 128, false, 0.78, 0.78},  {"128x96", 128, 96, false, 0.75, 0.79},
+    {"128x64", 128, 64, false, 0.72, 0.78},    {"128x48", 128, 48, false, 0.74, 0.75},
+    {"96x96", 96, 96, false, 0.72, 0.77},      {"64x96", 64, 96, false, 0.73, 0.76},
+    {"d128x128s2", 128, 128, true, 0.87, 0.85}, {"d128x96s2", 128, 96, true, 0.86, 0.84},
+    {"d128x64s3", 128, 64, true, 0.84, 0.78},  {"d96x96s3", 96, 96, true, 0.86, 0.84},
 };
+// Stream-K keeps this share of a tile's steady-state efficiency (B panels are
+// fetched at staggered K positions, pieces and their fixup); measured on the
+// CCD ladder over Z_8.
+constexpr double kSkEff64 = 0.965, kSkEff32 = 0.80;
 constexpr int kNumFpTiles = sizeof(kFpTiles) / sizeof(kFpTiles[0]);
 }  // namespace
 
@@ -340,7 +344,8 @@ GemmChoice choose_among(int64_t batch, int64_t M, int64_t N, int64_t K, int elem
     if (!usable(t)) continue;
     if (forced && std::strcmp(forced, t.name) != 0) continue;
     const int64_t tiles = batch * ((M + t.bm - 1) / t.bm) * ((N + t.bn - 1) / t.bn);
-    const double t_tile = 2.0 * t.bm * t.bn * static_cast<double>(K) / (t.eff * per_cu);
+    const double eff = elem == 8 ? t.eff64 : t.eff32;
+    const double t_tile = 2.0 * t.bm * t.bn * static_cast<double>(K) / (eff * per_cu);
     for (int sk = 0; sk < 2; ++sk) {
       if (sk && (!t.dma || sk_mode == 0)) continue;
       if (!sk && t.dma && sk_mode == 1) continue;
@@ -350,7 +355,8 @@ GemmChoice choose_among(int64_t batch, int64_t M, int64_t N, int64_t K, int elem
         time = static_cast<double>((tiles + 255) / 256) * t_tile;
       } else {
         partial = 2 * static_cast<size_t>(kSkSlots) * t.bm * t.bn * elem;
-        time = static_cast<double>(tiles) / 256.0 * t_tile + 2.0 * static_cast<double>(partial) / 5e12 +
+        time = static_cast<double>(tiles) / 256.0 * t_tile / (elem == 8 ? kSkEff64 : kSkEff32) +
+               2.0 * static_cast<double>(partial) / 5e12 +
                2 * 1.5e-6 + 5e-6;
       }
       if (best.tile < 0 || time < best_t) {
