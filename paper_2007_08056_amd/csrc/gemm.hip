@@ -703,6 +703,150 @@ hipError_t launch_fp(int vec, int64_t batch, int M, int N, int K, const void* A,
   return hipGetLastError();
 }
 
+// Split-bf16 product on global-to-LDS tiles.  A planes (batch, M, K) and B
+// planes (batch, N, K) both have K contiguous; a K-step is 32 bf16 = one
+// 64-byte row of 4 chunks per operand row and plane, rows XOR-swizzled by
+// chunk ((row >> 1) & 3) so that the 16-byte operand reads of 8 consecutive
+// rows (one 128-byte bank window) fall on distinct banks; S stages in flight keep the loads S-1 K-steps ahead of the
+// products, which a bf16 K-step (48 MFMAs per wave) is too short to hide
+// otherwise.  K must be a multiple of 32; rows past M or N are clamped (their
+// results are never stored).
+template <int BM, int BN, int WM, int WN, int S>
+__global__ __launch_bounds__(64 * WM * WN, 1) void k_gemm_bf16x3_dma(
+    const uint16_t* __restrict__ Ahi, const uint16_t* __restrict__ Alo,
+    const uint16_t* __restrict__ Bhi, const uint16_t* __restrict__ Blo, double* __restrict__ C,
+    int M, int N, int K, int tiles_m, int tiles_n, int64_t ntiles) {
+  constexpr int NW = WM * WN;
+  constexpr int NT = 64 * NW;
+  constexpr int BK = 32;
+  constexpr int TM = BM / WM / 16;
+  constexpr int TN = BN / WN / 16;
+  constexpr int A_LOADS = BM * 8 / NT;            // 16-byte chunks of both A planes per thread
+  constexpr int B_LOADS = BN * 8 / NT;
+  constexpr int PA = BM * 64, PB = BN * 64;       // bytes per plane per stage
+  constexpr int STAGE = 2 * PA + 2 * PB;
+  static_assert(TM * WM * 16 == BM && TN * WN * 16 == BN, "tile shape");
+  static_assert(A_LOADS * NT == BM * 8 && B_LOADS * NT == BN * 8, "loads must divide evenly");
+  __shared__ __attribute__((aligned(1024))) char smem[S * STAGE];
+
+  const int64_t tile = xcd_remap(blockIdx.x, ntiles);
+  int64_t q;
+  int tm, tn;
+  tile_coords(tile, tiles_m, tiles_n, q, tm, tn);
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm0 = (wave / WN) * (BM / WM);
+  const int wn0 = (wave % WN) * (BN / WN);
+  const int64_t offA = q * static_cast<int64_t>(M) * K;
+  const int64_t offB = q * static_cast<int64_t>(N) * K;
+
+  // Load slot s = tid + i * NT covers [plane][row][chunk]; the chunk stored at
+  // LDS position c of row r comes from global chunk c ^ ((r >> 1) & 3).
+  const uint16_t* a_src[A_LOADS];
+#pragma unroll
+  for (int i = 0; i < A_LOADS; ++i) {
+    const int slot = tid + i * NT;
+    const int plane = slot / (BM * 4);
+    const int rem = slot - plane * (BM * 4);
+    const int r = rem >> 2, c = rem & 3;
+    const int gr = min(m0 + r, M - 1);
+    a_src[i] = (plane ? Alo : Ahi) + offA + static_cast<int64_t>(gr) * K + (c ^ ((r >> 1) & 3)) * 8;
+  }
+  const uint16_t* b_src[B_LOADS];
+#pragma unroll
+  for (int i = 0; i < B_LOADS; ++i) {
+    const int slot = tid + i * NT;
+    const int plane = slot / (BN * 4);
+    const int rem = slot - plane * (BN * 4);
+    const int r = rem >> 2, c = rem & 3;
+    const int gr = min(n0 + r, N - 1);
+    b_src[i] = (plane ? Blo : Bhi) + offB + static_cast<int64_t>(gr) * K + (c ^ ((r >> 1) & 3)) * 8;
+  }
+  auto issue = [&](int kt, int stage) {
+    const int k0 = kt * BK;
+    char* base = smem + stage * STAGE;
+#pragma unroll
+    for (int i = 0; i < A_LOADS; ++i) lds_dma16(a_src[i] + k0, base + (i * NT + wave * 64) * 16);
+#pragma unroll
+    for (int i = 0; i < B_LOADS; ++i) lds_dma16(b_src[i] + k0, base + 2 * PA + (i * NT + wave * 64) * 16);
+  };
+
+  f4 acc_hh[TM][TN], acc_x[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc_hh[i][j] = acc_x[i][j] = f4{};
+
+  const int nk = K / BK;
+  const int kc = lane >> 4;                       // operand chunk: k = 8 * kc .. 8 * kc + 7
+#pragma unroll
+  for (int s = 0; s < S - 1; ++s)
+    if (s < nk) issue(s, s);
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + S - 2 < nk) wait_vmcnt<(S - 2) * (A_LOADS + B_LOADS)>();
+    else wait_vmcnt<0>();
+    // a plain barrier: the wait above covers this wave's loads of step kt
+    asm volatile("s_barrier" ::: "memory");
+    if (kt + S - 1 < nk) issue(kt + S - 1, (kt + S - 1) % S);
+    const char* base = smem + (kt % S) * STAGE;
+    bf8 ah[TM], al[TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int r = wm0 + i * 16 + (lane & 15);
+      const int off = r * 64 + ((kc ^ ((r >> 1) & 3)) << 4);
+      ah[i] = *reinterpret_cast<const bf8*>(base + off);
+      al[i] = *reinterpret_cast<const bf8*>(base + PA + off);
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int r = wn0 + j * 16 + (lane & 15);
+      const int off = 2 * PA + r * 64 + ((kc ^ ((r >> 1) & 3)) << 4);
+      const bf8 bh = *reinterpret_cast<const bf8*>(base + off);
+      const bf8 bl = *reinterpret_cast<const bf8*>(base + PB + off);
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        acc_hh[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc_hh[i][j], 0, 0, 0);
+        acc_x[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc_x[i][j], 0, 0, 0);
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+        acc_x[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc_x[i][j], 0, 0, 0);
+    }
+  }
+
+  double* Cq = C + q * static_cast<int64_t>(M) * N;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int col = n0 + wn0 + j * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm0 + i * 16 + 4 * (lane >> 4) + r;
+        if (row < M && col < N)
+          Cq[static_cast<int64_t>(row) * N + col] =
+              static_cast<double>(acc_hh[i][j][r]) + static_cast<double>(acc_x[i][j][r]);
+      }
+    }
+}
+
+template <int BM, int BN, int WM, int WN, int S>
+hipError_t launch_bf16x3_dma(int64_t batch, int M, int N, int K, const void* A, const void* B, void* C,
+                             hipStream_t s) {
+  const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
+  const int64_t ntiles = batch * tiles_m * tiles_n;
+  const uint16_t* a = static_cast<const uint16_t*>(A);
+  const uint16_t* b = static_cast<const uint16_t*>(B);
+  const int64_t pa = batch * static_cast<int64_t>(M) * K;
+  const int64_t pb = batch * static_cast<int64_t>(N) * K;
+  hipLaunchKernelGGL((k_gemm_bf16x3_dma<BM, BN, WM, WN, S>), dim3(static_cast<unsigned>(ntiles)),
+                     dim3(64 * WM * WN), 0, s, a, a + pa, b, b + pb, static_cast<double*>(C), M, N, K,
+                     tiles_m, tiles_n, ntiles);
+  return hipGetLastError();
+}
+
 template <int BM, int BN, int BK, int WM, int WN>
 hipError_t launch_bf16x3(int64_t batch, int M, int N, int K, const void* A, const void* B, void* C,
                          hipStream_t s) {
@@ -844,12 +988,17 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
     }
     const char* forced = std::getenv("SYMT_GEMM_TILE");
     const std::string f = forced ? forced : "";
-    if (f == "b128x128k64") e = launch_bf16x3<128, 128, 64, 2, 2>(batch, M, N, K, A, B, C, stream);
+    const bool dma_ok = K % 32 == 0;
+    if (f == "bd256x128s3" && dma_ok) e = launch_bf16x3_dma<256, 128, 4, 2, 3>(batch, M, N, K, A, B, C, stream);
+    else if (f == "bd128x256s3" && dma_ok) e = launch_bf16x3_dma<128, 256, 2, 4, 3>(batch, M, N, K, A, B, C, stream);
+    else if (f == "b128x128k64") e = launch_bf16x3<128, 128, 64, 2, 2>(batch, M, N, K, A, B, C, stream);
     else if (f == "b128x128k32") e = launch_bf16x3<128, 128, 32, 2, 2>(batch, M, N, K, A, B, C, stream);
     else if (f == "b256x128k32") e = launch_bf16x3<256, 128, 32, 4, 2>(batch, M, N, K, A, B, C, stream);
     else if (f == "b128x256k32") e = launch_bf16x3<128, 256, 32, 2, 4>(batch, M, N, K, A, B, C, stream);
     else if (f == "b128x64k32") e = launch_bf16x3<128, 64, 32, 4, 1>(batch, M, N, K, A, B, C, stream);
     else if (f == "b64x64k32") e = launch_bf16x3<64, 64, 32, 2, 2>(batch, M, N, K, A, B, C, stream);
+    else if (dma_ok && f.empty() && M >= 256 && N >= 512)
+      e = launch_bf16x3_dma<128, 256, 2, 4, 3>(batch, M, N, K, A, B, C, stream);
     else if (N <= 64)
       e = launch_bf16x3<128, 64, 32, 4, 1>(batch, M, N, K, A, B, C, stream);
     else if (N >= 1024 && M >= 1024)

@@ -88,10 +88,18 @@ def test_sector_gemm_fp(P, shape, compute):
     assert np.all(np.abs(C - ref) <= fac * absb + 1e-300), compute
 
 
-@pytest.mark.parametrize("shape", [(1, 16, 32, 16), (3, 64, 64, 64), (2, 130, 56, 70), (4, 200, 96, 288),
-                                   (2, 257, 40, 47), (6, 300, 48, 48), (1, 128, 256, 128)])
-def test_sector_gemm_bf16x3(P, shape):
-    say(f"sector_gemm bf16x3 {shape}")
+@pytest.mark.parametrize("tile,shape", [
+    (None, (1, 16, 32, 16)), (None, (3, 64, 64, 64)), (None, (2, 130, 56, 70)), (None, (4, 200, 96, 288)),
+    (None, (2, 257, 40, 47)), (None, (6, 300, 48, 48)), (None, (1, 128, 256, 128)),
+    # global-to-LDS split-bf16 tiles (K a multiple of 32), ragged in M and N, and the default pick
+    ("bd256x128s3", (2, 300, 96, 200)), ("bd256x128s3", (1, 512, 64, 256)),
+    ("bd128x256s3", (2, 200, 128, 300)), ("bd128x256s3", (3, 130, 32, 70)),
+    (None, (2, 600, 256, 384)),
+])
+def test_sector_gemm_bf16x3(P, tile, shape, monkeypatch):
+    if tile:
+        monkeypatch.setenv("SYMT_GEMM_TILE", tile)
+    say(f"sector_gemm bf16x3 tile={tile} {shape}")
     b, m, k, n = shape
     rng = np.random.default_rng(m * 7 + n)
     A = rng.standard_normal((b, m, k)).astype(np.float32)
