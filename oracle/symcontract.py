@@ -17,6 +17,12 @@ Groups are Z_{g_1} x ... x Z_{g_k} (Sec. 3 mentions products of cyclic
 groups).  An element is flattened mixed-radix, first factor most significant,
 and added component-wise.
 
+Charge tables (optional, per mode): sector label L of mode m carries the
+charge chi_m(L), a permutation of the group elements (identity when absent),
+and the rule reads sum_m c_m chi_m(I_m) == Z.  Stored axes of every reduced
+form, standard or aligned, are indexed by label; Q and the deltas of Alg. 2
+are in charges.
+
 Forms of the reference result (all must agree):
 
 1. ``contract_dense``   expand both operands to full tensors with their zero
@@ -87,19 +93,39 @@ class Group:
 
 @dataclass(frozen=True)
 class Sym:
-    """Symmetry of one operand: coefficients (+1/-1), total charge, block dims, group."""
+    """Symmetry of one operand: coefficients (+1/-1), total charge, block dims, group,
+    and optional per-mode charge tables (None: every label is its own charge)."""
     signs: tuple
     charge: int
     dims: tuple
     group: Group
+    charges: tuple | None = None
 
     @staticmethod
-    def make(signs, charge, dims, group):
+    def make(signs, charge, dims, group, charges=None):
         if isinstance(signs, str):
             signs = tuple(+1 if ch == "+" else -1 for ch in signs)
         if not isinstance(group, Group):
             group = Group(group)
-        return Sym(tuple(int(s) for s in signs), int(charge) % group.size, tuple(int(d) for d in dims), group)
+        if charges is not None:
+            charges = tuple(tuple(int(x) for x in row) for row in charges)
+            if len(charges) != len(signs) or any(sorted(r) != list(range(group.size)) for r in charges):
+                raise ValueError("charge tables must be one permutation of the group per mode")
+            if all(r == tuple(range(group.size)) for r in charges):
+                charges = None
+        return Sym(tuple(int(s) for s in signs), int(charge) % group.size, tuple(int(d) for d in dims), group,
+                   charges)
+
+    def chi(self, m, label):
+        """Charge of sector label `label` of mode m."""
+        return label if self.charges is None else self.charges[m][label]
+
+    def label(self, m, charge):
+        """Sector label of mode m that carries `charge`."""
+        return charge if self.charges is None else self.charges[m].index(charge)
+
+    def table(self, m):
+        return tuple(range(self.group.size)) if self.charges is None else self.charges[m]
 
     @property
     def order(self):
@@ -116,8 +142,8 @@ class Sym:
 
 
 def allowed(sym: Sym, sectors) -> bool:
-    """Conservation rule of Eq. symtsr: sum_m c_m I_m == Z."""
-    return sym.group.total(sym.signs, sectors) == sym.charge
+    """Conservation rule of Eq. symtsr: sum_m c_m chi_m(I_m) == Z."""
+    return sym.group.total(sym.signs, [sym.chi(m, s) for m, s in enumerate(sectors)]) == sym.charge
 
 
 def implicit_sector(sym: Sym, known, position=None):
@@ -130,9 +156,10 @@ def implicit_sector(sym: Sym, known, position=None):
     """
     g = sym.group
     p = sym.order - 1 if position is None else position
-    others = [c for m, c in enumerate(sym.signs) if m != p]
-    rest = g.sub(sym.charge, g.total(others, known))
-    return g.times(sym.signs[p], rest)
+    modes = [m for m in range(sym.order) if m != p]
+    others = [sym.signs[m] for m in modes]
+    rest = g.sub(sym.charge, g.total(others, [sym.chi(m, s) for m, s in zip(modes, known)]))
+    return sym.label(p, g.times(sym.signs[p], rest))
 
 
 def full_sectors(sym: Sym, stored):
@@ -231,21 +258,25 @@ def output_symmetry(sub, su: Sym, sv: Sym) -> Sym:
     tu, tv, tw, I, K, J = parse_einsum(sub)
     sigma = contracted_sign_ratio(sub, su, sv)
     g = su.group
-    signs, dims = [], []
+    signs, dims, tables = [], [], []
     for m in tw:
         if m in I:
             signs.append(su.signs[tu.index(m)])
             dims.append(su.dims[tu.index(m)])
+            tables.append(su.table(tu.index(m)))
         else:
             signs.append(-sigma * sv.signs[tv.index(m)])
             dims.append(sv.dims[tv.index(m)])
+            tables.append(sv.table(tv.index(m)))
     charge = g.sub(su.charge, g.times(sigma, sv.charge))
-    return Sym(tuple(signs), charge, tuple(dims), g)
+    return Sym.make(tuple(signs), charge, tuple(dims), g, tables)
 
 
 def same_symmetry(a: Sym, b: Sym) -> bool:
     """(c, Z) and (-c, -Z) state the same rule and give the same reduced layout."""
     if a.dims != b.dims or a.group.orders != b.group.orders:
+        return False
+    if any(a.table(m) != b.table(m) for m in range(a.order)):
         return False
     if a.signs == b.signs and a.charge == b.charge:
         return True
@@ -261,6 +292,8 @@ def check_operands(sub, su: Sym, sv: Sym):
     for k in K:
         if su.dims[tu.index(k)] != sv.dims[tv.index(k)]:
             raise ValueError(f"contracted mode {k} has different block sizes")
+        if su.table(tu.index(k)) != sv.table(tv.index(k)):
+            raise ValueError(f"contracted mode {k} has different charge tables")
     return tu, tv, tw, I, K, J
 
 
@@ -335,11 +368,12 @@ def _vector_allowed(sym: Sym, secs):
     g = sym.group
     shape = np.broadcast(*secs).shape
     ok = np.ones(shape, dtype=bool)
+    chg = [np.asarray(sym.table(m), dtype=np.int64)[np.asarray(s)] for m, s in enumerate(secs)]
     stride = 1
     for o in reversed(g.orders):
         tot = np.zeros(shape, dtype=np.int64)
-        for c, s in zip(sym.signs, secs):
-            tot += c * ((np.asarray(s) // stride) % o)
+        for c, s in zip(sym.signs, chg):
+            tot += c * ((s // stride) % o)
         ok &= (tot - (sym.charge // stride) % o) % o == 0
         stride *= o
     return ok
@@ -417,13 +451,19 @@ def contract_bruteforce(sub, Ru, su: Sym, Rv, sv: Sym):
 # ----------------------------------------------------------------------------
 # Form 5: Alg. 2 with dense generalized Kronecker deltas
 # ----------------------------------------------------------------------------
-def kron_delta(group: Group, coefs, q_coef, remainder):
-    """Dense 0/1 tensor over (sectors..., Q): 1 iff sum coefs*S + q_coef*Q == remainder."""
+def kron_delta(group: Group, coefs, q_coef, remainder, tables=None):
+    """Dense 0/1 tensor over (sector labels..., Q): 1 iff sum coefs*chi(S) + q_coef*Q == remainder.
+
+    ``tables`` gives each sector axis's charge table (identity when absent);
+    the Q axis is a charge.
+    """
     G = group.size
     p = len(coefs)
+    tables = tables or [tuple(range(G))] * p
     D = np.zeros((G,) * (p + 1), dtype=np.float64)
     for secs in itertools.product(range(G), repeat=p + 1):
-        if group.total(list(coefs) + [q_coef], secs) == remainder:
+        chg = [tables[a][x] for a, x in enumerate(secs[:-1])] + [secs[-1]]
+        if group.total(list(coefs) + [q_coef], chg) == remainder:
             D[secs] = 1.0
     return D
 
@@ -432,7 +472,11 @@ def _full_sector_form(R, sym: Sym):
     """Order-2N array [S_0..S_{N-1}, i_0..i_{N-1}]: the reduced form times its delta (Eq. redform)."""
     G = sym.group.size
     N = sym.order
-    Dt = kron_delta(sym.group, sym.signs[:-1], sym.signs[-1], sym.charge)
+    # the last sector axis is a label too: delta over (labels 0..N-2, charge of N-1),
+    # then the charge axis re-indexed by label
+    Dt = kron_delta(sym.group, sym.signs[:-1], sym.signs[-1], sym.charge,
+                    [sym.table(m) for m in range(N - 1)])
+    Dt = Dt[..., list(sym.table(N - 1))]
     letters = _letters(2 * N)
     S, inner = letters[:N], letters[N:]
     return np.einsum(f"{''.join(S[:-1])}{''.join(inner)},{''.join(S)}->{''.join(S)}{''.join(inner)}",
@@ -457,9 +501,9 @@ def alignment_deltas(sub, su: Sym, sv: Sym):
     tu, tv, tw, I, K, J = check_operands(sub, su, sv)
     sigma = contracted_sign_ratio(sub, su, sv)
     g = su.group
-    d1 = kron_delta(g, [su.signs[tu.index(m)] for m in I], +1, su.charge)
-    d2 = kron_delta(g, [su.signs[tu.index(m)] for m in K], -1, 0)
-    d3 = kron_delta(g, [sv.signs[tv.index(m)] for m in J], sigma, sv.charge)
+    d1 = kron_delta(g, [su.signs[tu.index(m)] for m in I], +1, su.charge, [su.table(tu.index(m)) for m in I])
+    d2 = kron_delta(g, [su.signs[tu.index(m)] for m in K], -1, 0, [su.table(tu.index(m)) for m in K])
+    d3 = kron_delta(g, [sv.signs[tv.index(m)] for m in J], sigma, sv.charge, [sv.table(tv.index(m)) for m in J])
     return d1, d2, d3
 
 

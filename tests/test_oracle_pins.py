@@ -440,3 +440,116 @@ def test_planted_transposed_block_product_is_caught(monkeypatch):
         return out
     monkeypatch.setattr(S.np, "einsum", wrong)
     assert not _pins_pass()
+
+
+# ---------------------------------------------------------------------------
+# Charge tables: sector label L of mode m carries charge chi_m(L).  A tensor
+# with tables is the identity-table tensor with each mode's sector blocks
+# permuted, so every form must commute with relabelling.
+# ---------------------------------------------------------------------------
+def _random_tables(rng, order, G):
+    return tuple(tuple(int(x) for x in rng.permutation(G)) for _ in range(order))
+
+
+def _relabel_reduced(R, sym):
+    """Identity-table reduced form of the same tensor: stored axes indexed by charge."""
+    inv = [np.argsort(np.asarray(sym.table(m))) for m in range(sym.order - 1)]
+    return np.asarray(R)[np.ix_(*inv)] if inv else np.asarray(R)
+
+
+def _relabel_full(T, sym):
+    """Full tensor with each mode's sector blocks moved from label to charge position."""
+    out = np.asarray(T)
+    for m in range(sym.order):
+        n = sym.dims[m]
+        perm = np.empty(sym.group.size * n, dtype=np.int64)
+        for L in range(sym.group.size):
+            c = sym.table(m)[L]
+            perm[c * n:(c + 1) * n] = np.arange(L * n, (L + 1) * n)
+        out = np.take(out, perm, axis=m)
+    return out
+
+
+def _plain(sym):
+    return O.Sym(sym.signs, sym.charge, sym.dims, sym.group)
+
+
+@pytest.mark.parametrize("orders", [(3,), (4,), (2, 3), (5,)])
+def test_charge_tables_expand_is_a_relabelling(orders):
+    rng = np.random.default_rng(sum(orders) * 13)
+    g = O.Group(orders)
+    for order in (1, 2, 3, 4):
+        sym = O.Sym.make(tuple(rng.choice([-1, 1], order)), int(rng.integers(g.size)),
+                         tuple(int(d) for d in rng.integers(1, 3, order)), g,
+                         _random_tables(rng, order, g.size))
+        R = rng.standard_normal(sym.reduced_shape())
+        full = O.expand(R, sym)
+        ref = O.expand(_relabel_reduced(R, sym), _plain(sym))
+        assert np.array_equal(_relabel_full(full, sym), ref)
+        back, zero_ok = O.reduce_full(full, sym)
+        assert zero_ok and np.array_equal(back, R)
+
+
+@pytest.mark.parametrize("orders,s,t,v", [((3,), 1, 1, 1), ((4,), 2, 1, 1), ((2, 3), 1, 2, 1), ((3,), 2, 2, 2)])
+def test_charge_tables_contraction_commutes_with_relabelling(orders, s, t, v):
+    rng = np.random.default_rng(s * 100 + t * 10 + v + len(orders))
+    g = O.Group(orders)
+    for sigma in (-1, 1):
+        sub, _, su0, _, sv0 = _random_case(rng, orders, s, t, v, sigma=sigma)
+        tu, rest = sub.split(",")
+        tv, tw = rest.split("->")
+        # shared tables on the contracted modes, independent ones elsewhere
+        tab = {m: tuple(int(x) for x in rng.permutation(g.size)) for m in set(tu) | set(tv)}
+        su = O.Sym.make(su0.signs, su0.charge, su0.dims, g, [tab[m] for m in tu])
+        sv = O.Sym.make(sv0.signs, sv0.charge, sv0.dims, g, [tab[m] for m in tv])
+        Ru, Rv = rng.standard_normal(su.reduced_shape()), rng.standard_normal(sv.reduced_shape())
+        sw = O.output_symmetry(sub, su, sv)
+        assert all(sw.table(p) == tab[m] for p, m in enumerate(tw))
+        blocks, _ = O.contract_blocks(sub, Ru, su, Rv, sv)
+        dense, _, zero_ok = O.contract_dense(sub, Ru, su, Rv, sv)
+        aligned = O.contract_irrep_aligned(sub, Ru, su, Rv, sv)[0]
+        assert zero_ok
+        assert np.allclose(blocks, dense, rtol=1e-12, atol=1e-12)
+        assert np.allclose(aligned, dense, rtol=1e-12, atol=1e-12)
+        # relabelled operands through the identity-table path give the relabelled output
+        ref, swp = O.contract_blocks(sub, _relabel_reduced(Ru, su), _plain(su), _relabel_reduced(Rv, sv), _plain(sv))
+        assert np.allclose(_relabel_reduced(blocks, sw), ref, rtol=1e-12, atol=1e-12)
+
+
+def test_charge_tables_bruteforce_tiny():
+    rng = np.random.default_rng(77)
+    g = O.Group((3,))
+    tab = {m: tuple(int(x) for x in rng.permutation(3)) for m in "abk"}
+    su = O.Sym.make((1, -1), 1, (2, 1), g, [tab["a"], tab["k"]])
+    sv = O.Sym.make((1, 1), 2, (1, 2), g, [tab["k"], tab["b"]])
+    Ru, Rv = rng.standard_normal(su.reduced_shape()), rng.standard_normal(sv.reduced_shape())
+    brute, sw, zero_ok = O.contract_bruteforce("ak,kb->ab", Ru, su, Rv, sv)
+    blocks, _ = O.contract_blocks("ak,kb->ab", Ru, su, Rv, sv)
+    assert zero_ok and np.allclose(brute, blocks, rtol=1e-13, atol=1e-13)
+
+
+def test_charge_tables_mismatch_on_contracted_mode_is_rejected():
+    g = O.Group((3,))
+    su = O.Sym.make((1, -1), 0, (2, 2), g, [(0, 1, 2), (1, 2, 0)])
+    sv = O.Sym.make((1, -1), 0, (2, 2), g, [(0, 1, 2), (0, 1, 2)])
+    with pytest.raises(ValueError):
+        O.contract_blocks("ak,kb->ab", np.zeros(su.reduced_shape()), su, np.zeros(sv.reduced_shape()), sv)
+
+
+def test_planted_mistake_tables_ignored_in_implicit_sector(monkeypatch):
+    """Solving the implicit sector as if labels were charges must break the relabelling pin."""
+    rng = np.random.default_rng(5)
+    g = O.Group((4,))
+    sym = O.Sym.make((1, -1, 1), 1, (1, 2, 1), g, _random_tables(rng, 3, 4))
+    R = rng.standard_normal(sym.reduced_shape())
+    good = O.expand(R, sym)
+
+    def wrong(sym_, known, position=None):
+        gg = sym_.group
+        p = sym_.order - 1 if position is None else position
+        others = [c for m, c in enumerate(sym_.signs) if m != p]
+        return gg.times(sym_.signs[p], gg.sub(sym_.charge, gg.total(others, known)))
+    monkeypatch.setattr(O.symcontract, "implicit_sector", wrong)
+    bad = O.expand(R, sym)
+    assert not np.array_equal(bad, good)
+    assert not np.array_equal(_relabel_full(bad, sym), O.expand(_relabel_reduced(R, sym), _plain(sym)))
