@@ -126,7 +126,19 @@ typedef struct {
 /* One operand.  `signs` holds nmodes characters '+' / '-' (c_m, einsum-term
  * order); `charge` is Z in [0,|G|); `dims` holds the nmodes block sizes n_m
  * (each >= 0); `data` is a device pointer to the standard reduced form in
- * `dtype`, or NULL when the tensor has no elements or is only being planned. */
+ * `dtype`, or NULL when the tensor has no elements or is only being planned.
+ *
+ * `mode_charges` (host pointer, may be NULL) relabels sectors: row m (|G|
+ * int32) gives the charge carried by each sector label of mode m, a
+ * permutation of 0..|G|-1, and the rule of Eq. symtsr reads
+ * sum_m c_m chi_m(I_m) == Z.  NULL means every label is its own charge.
+ * Reduced forms stay indexed by label.  A contracted mode must carry the same
+ * row in u and v, and w's rows must be the derived ones (u's on I modes, v's
+ * on J modes; NULL stands for identity rows) -- else SYMT_ESYM; a row that is
+ * not a permutation is SYMT_EINVAL.  Supported by symtensor_plan and
+ * symtensor_contract; symtensor_align and symtensor_unalign return
+ * SYMT_EUNSUPPORTED for non-identity tables (their device copies live in the
+ * contraction's workspace). */
 typedef struct {
   int32_t nmodes;
   const char* signs;
@@ -134,6 +146,7 @@ typedef struct {
   const int64_t* dims;
   int32_t dtype;           /* symt_dtype */
   void* data;
+  const int32_t* mode_charges;
 } symt_tensor;
 
 /* Result of planning one contraction (host-only, no device needed). */
@@ -180,7 +193,8 @@ int symtensor_workspace_size(const char* einsum, const symt_group* group, const 
  * info.workspace_bytes bytes holding U_al, V_al and W_al (256-byte aligned
  * sub-buffers, in that order), or for the fused product V_al and the offset
  * tables; then, where the product runs stream-K (see symtensor_sector_gemm),
- * the pieces of the tiles it cuts.
+ * the pieces of the tiles it cuts; then, with non-identity charge tables,
+ * their device copies.
  * w->data must not overlap u->data, v->data or the workspace (SYMT_EALIAS).
  * Storage dtypes: SYMT_COMPUTE_F64 takes any mix of F64/F32 operands
  * (converted exactly to binary64); SYMT_COMPUTE_F32 and BF16X3 take any mix,

@@ -45,7 +45,8 @@ class SymtGroup(ctypes.Structure):
 
 class SymtTensor(ctypes.Structure):
     _fields_ = [("nmodes", c_int32), ("signs", c_char_p), ("charge", c_int32),
-                ("dims", POINTER(c_int64)), ("dtype", c_int32), ("data", c_void_p)]
+                ("dims", POINTER(c_int64)), ("dtype", c_int32), ("data", c_void_p),
+                ("mode_charges", POINTER(c_int32))]
 
 
 class SymtPlanInfo(ctypes.Structure):
@@ -125,11 +126,15 @@ def make_group(orders) -> SymtGroup:
 class TensorDesc:
     """Keeps a SymtTensor and the buffers it points to alive together."""
 
-    def __init__(self, signs: str, charge: int, dims, dtype: int, data_ptr: int | None):
+    def __init__(self, signs: str, charge: int, dims, dtype: int, data_ptr: int | None, mode_charges=None):
         self._signs = signs.encode()
         self._dims = (c_int64 * max(1, len(dims)))(*[int(d) for d in dims])
+        self._charges = None
+        if mode_charges is not None:
+            flat = [int(x) for row in mode_charges for x in row]
+            self._charges = (c_int32 * len(flat))(*flat)
         self.c = SymtTensor(len(signs), self._signs, int(charge), self._dims, int(dtype),
-                            c_void_p(data_ptr) if data_ptr else None)
+                            c_void_p(data_ptr) if data_ptr else None, self._charges)
 
     @property
     def ref(self):

@@ -76,6 +76,34 @@ int read_group(const symt_group* grp, GroupDesc* g, std::string* err) {
   return SYMT_OK;
 }
 
+// Charge tables of an operand: n rows of |G| labels -> charges, each a
+// permutation; an all-identity table is stored as empty.
+int read_charges(const symt_tensor* t, const GroupDesc& g, std::vector<int32_t>* out, const char* name,
+                 std::string* err) {
+  out->clear();
+  if (!t->mode_charges) return SYMT_OK;
+  const int G = g.size;
+  bool identity = true;
+  std::vector<char> seen(static_cast<size_t>(G));
+  for (int m = 0; m < t->nmodes; ++m) {
+    std::fill(seen.begin(), seen.end(), 0);
+    for (int l = 0; l < G; ++l) {
+      const int32_t c = t->mode_charges[static_cast<size_t>(m) * G + l];
+      if (c < 0 || c >= G || seen[c])
+        return fail(err, SYMT_EINVAL, "operand %s: charge table of mode %s is not a permutation of the group",
+                    name, std::to_string(m).c_str());
+      seen[c] = 1;
+      identity = identity && c == l;
+    }
+  }
+  if (!identity) out->assign(t->mode_charges, t->mode_charges + static_cast<size_t>(t->nmodes) * G);
+  return SYMT_OK;
+}
+
+int32_t table_at(const std::vector<int32_t>& tab, int G, int mode, int label) {
+  return tab.empty() ? label : tab[static_cast<size_t>(mode) * G + label];
+}
+
 int read_operand(const symt_tensor* t, const GroupDesc& g, OperandDesc* o, const char* name,
                  std::string* err) {
   if (!t) return fail(err, SYMT_EINVAL, "operand %s is NULL", name);
@@ -180,6 +208,8 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   // ---- operands
   if ((rc = read_operand(u, p->g, &p->U, "u", err))) return rc;
   if ((rc = read_operand(v, p->g, &p->V, "v", err))) return rc;
+  if ((rc = read_charges(u, p->g, &p->chg[0], "u", err))) return rc;
+  if ((rc = read_charges(v, p->g, &p->chg[1], "v", err))) return rc;
   if (p->U.n != static_cast<int>(tu.size()) || p->V.n != static_cast<int>(tv.size()))
     return fail(err, SYMT_EINVAL, "operand order differs from its einsum term");
   for (int i = 0; i < p->s; ++i) p->posI_u[i] = static_cast<int32_t>(tu.find(I[i]));
@@ -201,6 +231,10 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
     if (sigma == 0) sigma = r;
     else if (r != sigma)
       return fail(err, SYMT_ESYM, "contracted modes carry mixed sign ratios c^V/c^U");
+    for (int l = 0; l < p->g.size; ++l)
+      if (table_at(p->chg[0], p->g.size, p->posK_u[i], l) != table_at(p->chg[1], p->g.size, p->posK_v[i], l))
+        return fail(err, SYMT_ESYM, "contracted mode '%s' carries different charge tables in u and v",
+                    std::string(1, K[i]).c_str());
   }
   p->sigma = sigma;
 
@@ -211,6 +245,24 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
     p->w_sign[m] = (pu != std::string::npos) ? p->U.sign[pu] : -sigma * p->V.sign[tv.find(c)];
   }
   p->w_charge = gsub(p->g, p->U.charge, gtimes(p->g, sigma, p->V.charge));
+  // derived charge tables: u's rows on I modes, v's on J modes
+  std::vector<int32_t> w_chg;
+  if (!p->chg[0].empty() || !p->chg[1].empty()) {
+    const int G = p->g.size;
+    w_chg.resize(tw.size() * static_cast<size_t>(G));
+    bool identity = true;
+    for (size_t m = 0; m < tw.size(); ++m) {
+      const char c = tw[m];
+      const size_t pu = tu.find(c);
+      for (int l = 0; l < G; ++l) {
+        const int32_t x = pu != std::string::npos ? table_at(p->chg[0], G, static_cast<int>(pu), l)
+                                                   : table_at(p->chg[1], G, static_cast<int>(tv.find(c)), l);
+        w_chg[m * G + l] = x;
+        identity = identity && x == l;
+      }
+    }
+    if (identity) w_chg.clear();
+  }
 
   // ---- output descriptor
   p->has_w = (w != nullptr);
@@ -231,6 +283,10 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
     }
     if (!same && !flipped)
       return fail(err, SYMT_ESYM, "output signs/charge differ from the rule implied by u and v");
+    std::vector<int32_t> given;
+    if ((rc = read_charges(w, p->g, &given, "w", err))) return rc;
+    if (given != w_chg)
+      return fail(err, SYMT_ESYM, "output charge tables differ from u's (I modes) and v's (J modes)");
   } else {
     p->W = OperandDesc{};
     p->W.n = static_cast<int32_t>(tw.size());
@@ -247,6 +303,8 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
     p->W.dtype = SYMT_F64;
     p->W.elems = e;
   }
+  p->chg[2] = w_chg;
+  p->charges = !p->chg[0].empty() || !p->chg[1].empty() || !p->chg[2].empty();
 
   // ---- aligned shapes M = G^(s-1) n_I, Kd = G^(v-1) n_K, N = G^(t-1) n_J
   p->nI = p->nK = p->nJ = 1;
@@ -291,6 +349,9 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
                       round_up(8 * G * p->N, 256);
     p->workspace = round_up(p->bytes_v_al, 256) + p->bytes_tables;
   }
+  if (p->charges) {
+    p->bytes_charges = 4 * 2 * static_cast<size_t>(p->g.size) * (p->U.n + p->V.n + p->W.n);
+  }
   // Room for stream-K pieces when the model would pick it on 16-byte aligned operands.
   if (compute != SYMT_COMPUTE_BF16X3 && p->M > 0 && p->N > 0 && p->Kd > 0) {
     const GemmChoice gc = choose_fp_gemm(p->g.size, p->M, p->N, p->Kd,
@@ -298,7 +359,27 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
     p->bytes_partial = gc.partial_bytes;
     p->workspace += round_up(p->bytes_partial, 256);
   }
+  p->workspace += round_up(p->bytes_charges, 256);
   return SYMT_OK;
+}
+
+std::vector<int32_t> charge_tables_device(const Plan& p, int64_t offset[3]) {
+  const int G = p.g.size;
+  const int n[3] = {p.U.n, p.V.n, p.W.n};
+  std::vector<int32_t> out;
+  for (int op = 0; op < 3; ++op) {
+    offset[op] = static_cast<int64_t>(out.size());
+    for (int m = 0; m < n[op]; ++m) {
+      const size_t base = out.size();
+      out.resize(base + 2 * static_cast<size_t>(G));
+      for (int l = 0; l < G; ++l) {
+        const int32_t c = table_at(p.chg[op], G, m, l);
+        out[base + l] = c;
+        out[base + G + c] = l;
+      }
+    }
+  }
+  return out;
 }
 
 namespace {
@@ -412,6 +493,7 @@ void sector_groups(const Plan& p, int operand, SectorGroup* R, SectorGroup* C) {
 
 OffsetParams make_offsets(const Plan& p, int operand, bool rows) {
   OffsetParams o;
+  o.chg = nullptr;                  // set at launch when the operand has charge tables
   std::memset(&o, 0, sizeof o);
   o.g = p.g;
   SectorGroup R, C;
@@ -448,6 +530,7 @@ OffsetParams make_offsets(const Plan& p, int operand, bool rows) {
 XformParams make_xform(const Plan& p, int operand, bool to_aligned, int in_bytes, int out_bytes,
                        bool out_is_split) {
   XformParams x;
+  x.chg = nullptr;                  // set at launch when the operand has charge tables
   std::memset(&x, 0, sizeof x);
   x.g = p.g;
   const OperandDesc& X = operand == 0 ? p.U : operand == 1 ? p.V : p.W;

@@ -5,6 +5,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "symtensor.h"
 
@@ -77,6 +78,7 @@ struct XformParams {
   int32_t lanes_log2;
   int32_t vec;                      // elements per thread access along the run (1, 2, 4)
   int32_t tiles_run, tiles_t;       // transpose: tiles along run and tdim
+  const int32_t* chg;               // device charge tables of the operand, or nullptr (identity)
 };
 
 // Offsets of one sector group of an aligned operand inside its standard
@@ -93,6 +95,7 @@ struct OffsetParams {
   int64_t dim[kMaxOrder];           // inner dims of the group's modes (group order)
   int64_t stride[kMaxOrder];        // their standard-form strides
   int64_t weight[kMaxOrder];        // standard-form offset of one unit of each mode's sector
+  const int32_t* chg;               // device charge tables of the operand, or nullptr (identity)
 };
 
 // Up to six offset tables filled by one launch (entries of table t:
@@ -142,6 +145,11 @@ struct Plan {
   size_t bytes_u_al = 0, bytes_v_al = 0, bytes_w_al = 0, workspace = 0;
   size_t bytes_tables = 0;          // fused: the four offset tables
   size_t bytes_partial = 0;         // stream-K pieces of the product (0: data-parallel tiles)
+  // Charge tables (label -> charge) of U, V, W, n x |G| each; empty = identity.
+  // On the device each operand's block is [mode][label -> charge | charge -> label][|G|].
+  std::vector<int32_t> chg[3];
+  bool charges = false;             // some table is not the identity
+  size_t bytes_charges = 0;         // device copy of all three (0 when charges is false)
   double flops = 0.0;
 };
 
@@ -182,5 +190,9 @@ OffsetParams make_offsets(const Plan& p, int operand, bool rows);
 AlignedLayout aligned_layout(int32_t compute, int operand);
 
 size_t round_up(size_t x, size_t a);
+
+// Device layout of the charge tables of all three operands (forward and
+// inverse per mode); `offset[op]` is each operand's first int32.
+std::vector<int32_t> charge_tables_device(const Plan& p, int64_t offset[3]);
 
 }  // namespace symt

@@ -19,6 +19,7 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
                        const FusedTables* fused = nullptr, void* part = nullptr,
                        size_t part_bytes = 0);
 int launch_offsets(const OffsetBatch& batch, hipStream_t stream, std::string* err);
+int launch_put_i32(int32_t* dst, const int32_t* src, int64_t n, hipStream_t stream, std::string* err);
 }  // namespace symt
 
 using symt::Plan;
@@ -86,13 +87,16 @@ int aligned_elem_bytes(int compute) {
   return compute == SYMT_COMPUTE_F64 ? 8 : compute == SYMT_COMPUTE_F32 ? 4 : 2;
 }
 
-// Align operand 0 (U) or 1 (V) from its standard form into `dst`.
-int do_align(symt_ctx* ctx, const Plan& p, int operand, void* dst, hipStream_t s) {
+// Align operand 0 (U) or 1 (V) from its standard form into `dst`; `chg`: the
+// operand's device charge tables (nullptr: identity).
+int do_align(symt_ctx* ctx, const Plan& p, int operand, void* dst, hipStream_t s,
+             const int32_t* chg = nullptr) {
   const symt::OperandDesc& X = operand == 0 ? p.U : p.V;
   if (X.elems == 0) return SYMT_OK;
   const int kind = out_kind_aligned(p.compute);
   symt::XformParams x = symt::make_xform(p, operand, true, static_cast<int>(elem_bytes(X.dtype)),
                                          aligned_elem_bytes(p.compute), kind == 2);
+  x.chg = chg;
   if (!aligned16(X.data) || !aligned16(dst)) x.vec = 1;
   std::string err;
   const int rc = timed(ctx, operand, s, [&] {
@@ -101,11 +105,12 @@ int do_align(symt_ctx* ctx, const Plan& p, int operand, void* dst, hipStream_t s
   return rc ? ctx_fail(ctx, rc, err) : SYMT_OK;
 }
 
-int do_unalign(symt_ctx* ctx, const Plan& p, const void* wal, hipStream_t s) {
+int do_unalign(symt_ctx* ctx, const Plan& p, const void* wal, hipStream_t s, const int32_t* chg = nullptr) {
   if (p.W.elems == 0) return SYMT_OK;
   const bool in_f64 = p.compute != SYMT_COMPUTE_F32;
   symt::XformParams x = symt::make_xform(p, 2, false, in_f64 ? 8 : 4,
                                          static_cast<int>(elem_bytes(p.W.dtype)), false);
+  x.chg = chg;
   if (!aligned16(wal) || !aligned16(p.W.data)) x.vec = 1;
   std::string err;
   const int rc = timed(ctx, 3, s, [&] {
@@ -126,7 +131,7 @@ int do_gemm(symt_ctx* ctx, int compute, int64_t batch, int64_t m, int64_t k, int
 
 // Fused path: offset tables of U's rows and columns and of W's rows and
 // columns, V aligned, then one product that reads U and writes W in place.
-int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s) {
+int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int32_t* const chg[3]) {
   using symt::round_up;
   const size_t G = static_cast<size_t>(p.g.size);
   void* val = base;
@@ -142,6 +147,7 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s) {
     int64_t run = 0;
     for (int t = 0; t < 4; ++t) {
       b.t[t] = symt::make_offsets(p, ops[t], t % 2 == 0);
+      b.t[t].chg = chg[ops[t]];
       b.out[t] = outs[t];
       run += b.t[t].count * G;
       b.end[t] = run;
@@ -150,7 +156,7 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s) {
     return symt::launch_offsets(b, s, &err);
   });
   if (rc_) return ctx_fail(ctx, rc_, err);
-  if ((rc_ = do_align(ctx, p, 1, val, s))) return rc_;
+  if ((rc_ = do_align(ctx, p, 1, val, s, chg[1]))) return rc_;
   symt::FusedTables f{ra, ca, rc, cc, aligned16(p.U.data) ? 2 : 1};
   char* part = reinterpret_cast<char*>(cc) + round_up(8 * G * p.N, 256);
   return do_gemm(ctx, p.compute, p.g.size, p.M, p.Kd, p.N, p.U.data, val, p.W.data, s, &f,
@@ -276,17 +282,29 @@ int symtensor_contract(symt_ctx* ctx, const char* einsum, const symt_group* grou
   if ((rc = set_device(ctx))) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(workspace);
-  if (p.fused) return do_fused(ctx, p, base, s);
+  // charge tables: forward and inverse per mode, uploaded into the workspace's last region
+  const int32_t* chg[3] = {nullptr, nullptr, nullptr};
+  if (p.charges) {
+    int32_t* dev = reinterpret_cast<int32_t*>(base + p.workspace - symt::round_up(p.bytes_charges, 256));
+    int64_t off[3];
+    const std::vector<int32_t> host = symt::charge_tables_device(p, off);
+    std::string err;
+    if ((rc = symt::launch_put_i32(dev, host.data(), static_cast<int64_t>(host.size()), s, &err)))
+      return ctx_fail(ctx, rc, err);
+    for (int op = 0; op < 3; ++op)
+      if (!p.chg[op].empty()) chg[op] = dev + off[op];
+  }
+  if (p.fused) return do_fused(ctx, p, base, s, chg);
   void* ual = base;
   void* val = base + symt::round_up(p.bytes_u_al, 256);
   void* wal = base + symt::round_up(p.bytes_u_al, 256) + symt::round_up(p.bytes_v_al, 256);
   char* part = static_cast<char*>(wal) + symt::round_up(p.bytes_w_al, 256);
-  if ((rc = do_align(ctx, p, 0, ual, s))) return rc;
-  if ((rc = do_align(ctx, p, 1, val, s))) return rc;
+  if ((rc = do_align(ctx, p, 0, ual, s, chg[0]))) return rc;
+  if ((rc = do_align(ctx, p, 1, val, s, chg[1]))) return rc;
   if ((rc = do_gemm(ctx, p.compute, p.g.size, p.M, p.Kd, p.N, ual, val, wal, s, nullptr,
                     p.bytes_partial ? part : nullptr, p.bytes_partial)))
     return rc;
-  if ((rc = do_unalign(ctx, p, wal, s))) return rc;
+  if ((rc = do_unalign(ctx, p, wal, s, chg[2]))) return rc;
   return SYMT_OK;
 }
 
@@ -299,6 +317,9 @@ int symtensor_align(symt_ctx* ctx, const char* einsum, const symt_group* group,
   Plan p;
   int rc = plan_for(ctx, einsum, group, u, v, w, compute, &p);
   if (rc) return rc;
+  if (p.charges)
+    return ctx_fail(ctx, SYMT_EUNSUPPORTED,
+                    "non-identity charge tables are supported by symtensor_contract only");
   const symt::OperandDesc& X = operand == 0 ? p.U : p.V;
   if ((rc = check_data(ctx, X, operand == 0 ? "u" : "v"))) return rc;
   const size_t need = operand == 0 ? p.bytes_u_al : p.bytes_v_al;
@@ -318,6 +339,9 @@ int symtensor_unalign(symt_ctx* ctx, const char* einsum, const symt_group* group
   Plan p;
   int rc = plan_for(ctx, einsum, group, u, v, w, compute, &p);
   if (rc) return rc;
+  if (p.charges)
+    return ctx_fail(ctx, SYMT_EUNSUPPORTED,
+                    "non-identity charge tables are supported by symtensor_contract only");
   if ((rc = check_data(ctx, p.W, "w"))) return rc;
   if (p.W.elems > 0 && !aligned_w) return ctx_fail(ctx, SYMT_EINVAL, "aligned_w is NULL");
   if (overlaps(p.W.data, static_cast<size_t>(p.W.elems) * elem_bytes(p.W.dtype), aligned_w,

@@ -223,7 +223,32 @@ __global__ __launch_bounds__(256) void k_offsets(const OffsetBatch b) {
   }
 }
 
+// A few KB of host data (charge tables) written into device memory from kernel
+// arguments: stream-ordered, with no host buffer that must outlive the call.
+struct I32Chunk {
+  int32_t v[512];
+};
+
+__global__ __launch_bounds__(256) void k_put_i32(int32_t* __restrict__ dst, int n, const I32Chunk c) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = c.v[i];
+}
+
 }  // namespace
+
+int launch_put_i32(int32_t* dst, const int32_t* src, int64_t n, hipStream_t stream, std::string* err) {
+  for (int64_t o = 0; o < n; o += 512) {
+    I32Chunk c;
+    const int k = static_cast<int>(n - o < 512 ? n - o : 512);
+    for (int i = 0; i < k; ++i) c.v[i] = src[o + i];
+    hipLaunchKernelGGL(k_put_i32, dim3(1), dim3(256), 0, stream, dst + o, k, c);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+      if (err) *err = std::string("charge table upload: ") + hipGetErrorString(e);
+      return SYMT_EHIP;
+    }
+  }
+  return SYMT_OK;
+}
 
 // Every table of the batch in one launch.
 int launch_offsets(const OffsetBatch& batch, hipStream_t stream, std::string* err) {

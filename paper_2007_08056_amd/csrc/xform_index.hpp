@@ -47,19 +47,25 @@ __host__ __device__ inline int dg_times(const GroupDesc& g, int c, int a) {
   return c >= 0 ? a : dg_neg(g, a);
 }
 
-// Sectors of one group's modes: the stored ones are the digits of `digits`
-// (base |G|, first most significant); the last one solves the group's delta.
+// Sector labels of one group's modes: the stored ones are the digits of
+// `digits` (base |G|, first most significant); the last one solves the
+// group's delta.  The deltas hold on charges: with charge tables `chg`
+// ([mode][label -> charge | charge -> label][|G|], nullptr for identity) the
+// stored labels are mapped to charges and the solved charge back to a label.
 __host__ __device__ inline void fill_sectors(const GroupDesc& g, const SectorGroup& sg,
-                                             int64_t digits, int q, int* S) {
+                                             int64_t digits, int q, int* S, const int32_t* chg) {
   int acc = 0;
   for (int i = sg.count - 2; i >= 0; --i) {
     const int d = static_cast<int>(digits % g.size);
     digits /= g.size;
     S[sg.pos[i]] = d;
-    acc = dg_add(g, acc, dg_times(g, sg.coef[i], d));
+    const int c = chg ? chg[(2 * sg.pos[i]) * g.size + d] : d;
+    acc = dg_add(g, acc, dg_times(g, sg.coef[i], c));
   }
   const int rhs = dg_add(g, dg_times(g, sg.alpha, q), sg.beta);
-  S[sg.pos[sg.count - 1]] = dg_times(g, sg.coef[sg.count - 1], dg_add(g, rhs, dg_neg(g, acc)));
+  const int last = sg.pos[sg.count - 1];
+  const int c = dg_times(g, sg.coef[sg.count - 1], dg_add(g, rhs, dg_neg(g, acc)));
+  S[last] = chg ? chg[(2 * last + 1) * g.size + c] : c;
 }
 
 // Aligned block index -> (standard-form element offset, aligned element offset).
@@ -70,8 +76,8 @@ __host__ __device__ inline void block_bases(const XformParams& p, int64_t blk, i
   const int64_t rs = t % p.gpow_row;
   const int q = static_cast<int>(t / p.gpow_row);
   int S[kMaxOrder];
-  fill_sectors(p.g, p.row, rs, q, S);
-  fill_sectors(p.g, p.col, cs, q, S);
+  fill_sectors(p.g, p.row, rs, q, S, p.chg);
+  fill_sectors(p.g, p.col, cs, q, S, p.chg);
   int64_t sb = 0;
   for (int m = 0; m < p.order - 1; ++m) sb = sb * p.g.size + S[m];
   std_base = sb * p.blk_elems;
@@ -85,7 +91,7 @@ __host__ __device__ inline int64_t group_offset(const OffsetParams& p, int q, in
   int64_t digits = i / p.n_inner;
   int64_t inner = i - digits * p.n_inner;
   int S[kMaxOrder];
-  fill_sectors(p.g, p.grp, digits, q, S);
+  fill_sectors(p.g, p.grp, digits, q, S, p.chg);
   int64_t off = 0;
   for (int j = p.grp.count - 1; j >= 0; --j) {
     const int64_t d = inner % p.dim[j];

@@ -36,13 +36,29 @@ def group_size(group) -> int:
     return g
 
 
+def _norm_charges(tables, n, G):
+    """Charge tables as a tuple of n rows of G ints, or None for all-identity."""
+    if tables is None:
+        return None
+    rows = tuple(tuple(int(x) for x in row) for row in tables)
+    if len(rows) != n or any(len(r) != G for r in rows):
+        raise ValueError(f"charge tables must be {n} rows of {G} entries")
+    return None if all(r == tuple(range(G)) for r in rows) else rows
+
+
 @dataclass
 class SymTensor:
-    """A tensor with cyclic (or product-of-cyclic) group symmetry, stored reduced."""
+    """A tensor with cyclic (or product-of-cyclic) group symmetry, stored reduced.
+
+    ``mode_charges`` optionally gives, per mode, the charge carried by each
+    sector label (a permutation of the group elements); None: every label is
+    its own charge (include/symtensor.h, symt_tensor).
+    """
     data: torch.Tensor
     signs: str
     charge: int
     group: tuple
+    mode_charges: tuple | None = None
 
     def __post_init__(self):
         self.group = _group_tuple(self.group)
@@ -53,6 +69,7 @@ class SymTensor:
         if self.data.dtype not in _DTYPE_CODE:
             raise TypeError("reduced form must be float64 or float32")
         self.charge = int(self.charge) % G
+        self.mode_charges = _norm_charges(self.mode_charges, n, G)
 
     @property
     def dims(self):
@@ -66,7 +83,11 @@ class SymTensor:
     def desc(self, data=None) -> L.TensorDesc:
         d = self.data if data is None else data
         return L.TensorDesc(self.signs, self.charge, self.dims, _DTYPE_CODE[d.dtype],
-                            d.data_ptr() if d.numel() else None)
+                            d.data_ptr() if d.numel() else None, self.mode_charges)
+
+    def table(self, m):
+        G = group_size(self.group)
+        return tuple(range(G)) if self.mode_charges is None else self.mode_charges[m]
 
 
 def _check_dense(t: torch.Tensor):
@@ -94,8 +115,17 @@ def plan(subscripts: str, u: SymTensor, v: SymTensor, compute: str = "f64", w: S
                   _code(compute, steps))
 
 
+def derived_charges(subscripts: str, u: SymTensor, v: SymTensor):
+    """Charge tables of the output: u's rows on its kept modes, v's on its kept modes."""
+    if u.mode_charges is None and v.mode_charges is None:
+        return None
+    tu, rest = subscripts.split(",")
+    tv, tw = rest.split("->")
+    return tuple(u.table(tu.index(m)) if m in tu else v.table(tv.index(m)) for m in tw)
+
+
 def output_like(subscripts: str, u: SymTensor, v: SymTensor, dtype=None) -> SymTensor:
-    """A zero-filled output with the derived sign string and charge."""
+    """A zero-filled output with the derived sign string, charge and charge tables."""
     info = plan(subscripts, u, v)
     tu, rest = subscripts.split(",")
     tv, tw = rest.split("->")
@@ -106,7 +136,7 @@ def output_like(subscripts: str, u: SymTensor, v: SymTensor, dtype=None) -> SymT
     shape = [G] * (len(tw) - 1) + dims
     dtype = dtype or u.data.dtype
     data = torch.zeros(shape, dtype=dtype, device=u.data.device)
-    return SymTensor(data, info.w_signs.decode(), info.w_charge, u.group)
+    return SymTensor(data, info.w_signs.decode(), info.w_charge, u.group, derived_charges(subscripts, u, v))
 
 
 def contract_into(subscripts: str, u: SymTensor, v: SymTensor, w: SymTensor, compute: str = "f64",
@@ -143,7 +173,7 @@ class _Contract(torch.autograd.Function):
     def forward(ctx, subscripts, meta_u, meta_v, meta_w, compute, ud, vd):
         u = SymTensor(ud, *meta_u)
         v = SymTensor(vd, *meta_v)
-        w = SymTensor(torch.empty(meta_w[3], dtype=ud.dtype, device=ud.device), *meta_w[:3])
+        w = SymTensor(torch.empty(meta_w[4], dtype=ud.dtype, device=ud.device), *meta_w[:4])
         contract_into(subscripts, u, v, w, compute)
         ctx.save_for_backward(ud, vd)
         ctx.meta = (subscripts, meta_u, meta_v, meta_w, compute)
@@ -154,7 +184,7 @@ class _Contract(torch.autograd.Function):
         subscripts, meta_u, meta_v, meta_w, compute = ctx.meta
         ud, vd = ctx.saved_tensors
         tu, tv, tw = _swap(subscripts)
-        dW = SymTensor(gw.contiguous().to(ud.dtype), *meta_w[:3])
+        dW = SymTensor(gw.contiguous().to(ud.dtype), *meta_w[:4])
         gu = gv = None
         if ctx.needs_input_grad[5]:
             # dU[I,K] = sum_J dW[I,J] V[K,J]; the derived rule of (dW, V) is U's.
@@ -180,11 +210,12 @@ def einsum(subscripts: str, u: SymTensor, v: SymTensor, compute: str = "f64") ->
     dims = [u.dims[tu.index(m)] if m in tu else v.dims[tv.index(m)] for m in tw]
     G = group_size(u.group)
     shape = tuple([G] * (len(tw) - 1) + dims)
-    meta_u = (u.signs, u.charge, u.group)
-    meta_v = (v.signs, v.charge, v.group)
-    meta_w = (info.w_signs.decode(), info.w_charge, u.group, shape)
+    meta_u = (u.signs, u.charge, u.group, u.mode_charges)
+    meta_v = (v.signs, v.charge, v.group, v.mode_charges)
+    wc = derived_charges(subscripts, u, v)
+    meta_w = (info.w_signs.decode(), info.w_charge, u.group, wc, shape)
     wd = _Contract.apply(subscripts, meta_u, meta_v, meta_w, compute, u.data, v.data)
-    return SymTensor(wd, meta_w[0], meta_w[1], u.group)
+    return SymTensor(wd, meta_w[0], meta_w[1], u.group, wc)
 
 
 # ---------------------------------------------------------------------------

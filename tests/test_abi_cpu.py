@@ -227,3 +227,36 @@ def test_stream_k_choice_and_workspace(monkeypatch):
     monkeypatch.setenv("SYMT_GEMM_SK", "0")
     assert _gemm_ws(L.COMPUTE["f64"], 8, 4608, 4608, 288) == (0, 0)
     assert L.plan("abcd,cdij->abij", g, u, v, None, L.COMPUTE["f64"]).workspace_bytes == base
+
+
+# ---------------------------------------------------------------------------
+# charge tables (symt_tensor.mode_charges)
+# ---------------------------------------------------------------------------
+def _cdesc(signs, charge, dims, tables):
+    return L.TensorDesc(signs, charge, dims, L.SYMT_F64, None, tables)
+
+
+def test_charge_tables_validation():
+    G = 3
+    ident = [0, 1, 2]
+    a, k, b = [1, 2, 0], [2, 0, 1], [0, 2, 1]
+    u = _cdesc("+-", 0, (2, 3), [a, k])
+    v = _cdesc("+-", 0, (3, 4), [k, b])
+    rc, info = _plan("ak,kb->ab", G, u, v)
+    assert rc == 0
+    base_rc, base = _plan("ak,kb->ab", G, _desc("+-", 0, (2, 3)), _desc("+-", 0, (3, 4)))
+    # the device copy of the tables (forward and inverse per mode of u, v, w) adds workspace
+    assert info.workspace_bytes >= base.workspace_bytes + 4 * 2 * G * 6
+    # all-identity tables are the same as none
+    rc, same = _plan("ak,kb->ab", G, _cdesc("+-", 0, (2, 3), [ident, ident]), _cdesc("+-", 0, (3, 4), [ident, ident]))
+    assert rc == 0 and same.workspace_bytes == base.workspace_bytes
+    # not a permutation
+    assert _plan("ak,kb->ab", G, _cdesc("+-", 0, (2, 3), [[0, 0, 1], k]), v)[0] == L.SYMT_EINVAL
+    assert _plan("ak,kb->ab", G, _cdesc("+-", 0, (2, 3), [[0, 1, 3], k]), v)[0] == L.SYMT_EINVAL
+    # contracted mode with different tables in u and v
+    assert _plan("ak,kb->ab", G, u, _cdesc("+-", 0, (3, 4), [ident, b]))[0] == L.SYMT_ESYM
+    # w must carry the derived tables (u's on a, v's on b); NULL stands for identity
+    sig = info.w_signs.decode()
+    assert _plan("ak,kb->ab", G, u, v, _cdesc(sig, info.w_charge, (2, 4), [a, b]))[0] == 0
+    assert _plan("ak,kb->ab", G, u, v, _desc(sig, info.w_charge, (2, 4)))[0] == L.SYMT_ESYM
+    assert _plan("ak,kb->ab", G, u, v, _cdesc(sig, info.w_charge, (2, 4), [b, a]))[0] == L.SYMT_ESYM

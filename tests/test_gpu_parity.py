@@ -40,7 +40,7 @@ def SG():
 
 def _sym_tensor(P, R: np.ndarray, sym: O.Sym, dtype=torch.float64):
     return P.SymTensor(torch.from_numpy(np.ascontiguousarray(R)).to(DEV, dtype), sym.sign_string(),
-                       sym.charge, sym.group.orders)
+                       sym.charge, sym.group.orders, sym.charges)
 
 
 # ---------------------------------------------------------------------------
@@ -447,3 +447,83 @@ def test_sector_gemm_every_tile_on_ragged_shapes(P, tile, sk, compute, monkeypat
         assert np.all(np.abs(C - ref) <= fac * absb), (tile, compute, shape)
         # the same launch again gives the same bits (pieces are summed in K order)
         assert np.array_equal(H.to_np(P.sector_gemm(a, bb, compute)), C)
+
+
+
+# ---------------------------------------------------------------------------
+# charge tables: every sector label of a mode carries a permuted charge
+# ---------------------------------------------------------------------------
+def _with_tables(rng, sub, su, sv):
+    tu, rest = sub.split(",")
+    tv, _ = rest.split("->")
+    G = su.group.size
+    tab = {m: tuple(int(x) for x in rng.permutation(G)) for m in set(tu) | set(tv)}
+    return (O.Sym.make(su.signs, su.charge, su.dims, su.group, [tab[m] for m in tu]),
+            O.Sym.make(sv.signs, sv.charge, sv.dims, sv.group, [tab[m] for m in tv]))
+
+
+@pytest.mark.parametrize("case", [((4,), 2, 2, 2), ((3,), 1, 1, 1), ((2, 3), 2, 1, 2), ((5,), 1, 2, 1),
+                                  ((8,), 2, 2, 2)])
+def test_contract_with_charge_tables_vs_oracle(P, case):
+    orders, ns, nt, nv = case
+    rng = np.random.default_rng(abs(hash(("charges",) + case)) % 2 ** 31)
+    for rep in range(2):
+        sub, su0, sv0 = H.random_case(rng, orders, ns, nt, nv, nmax=5)
+        su, sv = _with_tables(rng, sub, su0, sv0)
+        say(f"charge tables {sub} G={orders} rep={rep}")
+        Ru, Rv = rng.standard_normal(su.reduced_shape()), rng.standard_normal(sv.reduced_shape())
+        ref, sw = O.contract_blocks(sub, Ru, su, Rv, sv)
+        absref, _ = O.contract_blocks(sub, np.abs(Ru), su, np.abs(Rv), sv)
+        k = H.contracted_extent(sub, su)
+        u, v = _sym_tensor(P, Ru, su), _sym_tensor(P, Rv, sv)
+        for compute in ("f64", "f32", "bf16x3"):
+            info = P.plan(sub, u, v, compute)
+            if compute == "bf16x3" and info.k % 8:
+                continue
+            w = P.output_like(sub, u, v)
+            assert w.mode_charges == sw.charges
+            P.contract_into(sub, u, v, w, compute)
+            got = H.to_np(w.data)
+            assert np.all(np.abs(got - ref) <= H.bound_factor(compute, k) * absref + 1e-300), compute
+            if compute == "f64":
+                assert H.rel_err(got, ref) <= 1e-12
+                ws = P.output_like(sub, u, v)
+                P.contract_into(sub, u, v, ws, compute, steps=True)
+                assert torch.equal(ws.data, w.data)          # fused (where it applies) == three steps
+
+
+def test_charge_tables_fused_path_and_gradient(P):
+    """A fused-layout contraction (trailing contracted modes) with tables, and its backward."""
+    rng = np.random.default_rng(31)
+    g = O.Group((4,))
+    su0 = O.Sym.make("++--", 1, (3, 2, 4, 4), g)
+    sv0 = O.Sym.make("++--", 2, (4, 4, 2, 3), g)
+    sub = "abkl,klij->abij"
+    su, sv = _with_tables(rng, sub, su0, sv0)
+    Ru, Rv = rng.standard_normal(su.reduced_shape()), rng.standard_normal(sv.reduced_shape())
+    u, v = _sym_tensor(P, Ru, su), _sym_tensor(P, Rv, sv)
+    assert P.plan(sub, u, v, "f64").fused
+    ud = u.data.clone().requires_grad_(True)
+    vd = v.data.clone().requires_grad_(True)
+    w = P.einsum(sub, P.SymTensor(ud, u.signs, u.charge, u.group, u.mode_charges),
+                 P.SymTensor(vd, v.signs, v.charge, v.group, v.mode_charges))
+    ref, sw = O.contract_blocks(sub, Ru, su, Rv, sv)
+    assert H.rel_err(H.to_np(w.data), ref) <= 1e-12
+    Rg = rng.standard_normal(sw.reduced_shape())
+    (w.data * torch.from_numpy(Rg).to(DEV)).sum().backward()
+    # dU = dW . V over J; dV = U . dW over I, with the same tables
+    gu_ref, _ = O.contract_blocks("abij,klij->abkl", Rg, sw, Rv, sv)
+    gv_ref, _ = O.contract_blocks("abkl,abij->klij", Ru, su, Rg, sw)
+    assert H.rel_err(H.to_np(ud.grad), gu_ref) <= 1e-12
+    assert H.rel_err(H.to_np(vd.grad), gv_ref) <= 1e-12
+
+
+def test_charge_tables_rejected_by_standalone_align(P):
+    rng = np.random.default_rng(3)
+    g = O.Group((3,))
+    su, sv = _with_tables(rng, "ak,kb->ab", O.Sym.make("+-", 0, (2, 3), g), O.Sym.make("+-", 0, (3, 2), g))
+    u = _sym_tensor(P, rng.standard_normal(su.reduced_shape()), su)
+    v = _sym_tensor(P, rng.standard_normal(sv.reduced_shape()), sv)
+    with pytest.raises(P._lib.SymtError) as e:
+        P.align("ak,kb->ab", u, v, 0)
+    assert e.value.code == P._lib.SYMT_EUNSUPPORTED
