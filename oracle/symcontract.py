@@ -242,6 +242,10 @@ def contracted_sign_ratio(sub, su: Sym, sv: Sym) -> int:
     auxiliary sector Q then describes both operands.
     """
     tu, tv, tw, I, K, J = parse_einsum(sub)
+    if not K:
+        # v = 0 (outer product): Q is pinned to 0 and no ratio is defined; -1
+        # makes W's coefficients U's followed by V's, Z^W = Z^U + Z^V
+        return -1
     ratios = {su.signs[tu.index(k)] * sv.signs[tv.index(k)] for k in K}
     if len(ratios) != 1:
         raise ValueError("contracted modes carry mixed sign ratios")
@@ -287,6 +291,8 @@ def check_operands(sub, su: Sym, sv: Sym):
     tu, tv, tw, I, K, J = parse_einsum(sub)
     if len(tu) != su.order or len(tv) != sv.order:
         raise ValueError("term length does not match operand order")
+    if not tw:
+        raise ValueError("the output needs at least one mode")
     if su.group.orders != sv.group.orders:
         raise ValueError("operands use different groups")
     for k in K:
@@ -346,15 +352,20 @@ def contract_blocks(sub, Ru, su: Sym, Rv, sv: Sym, u_blocks=None):
         ustored = tuple(ustored)
         usec = full_sectors(su, ustored)
         sec = {m: usec[p] for p, m in enumerate(tu)}
-        for jfree in itertools.product(range(G), repeat=len(J) - 1):
+        for jfree in itertools.product(range(G), repeat=max(len(J) - 1, 0)):
             for m, e in zip(J[:-1], jfree):
                 sec[m] = e
-            # last J sector from V's conservation rule, solved at its position in V
-            known = [sec[m] for m in tv if m != J[-1]]
-            sec[J[-1]] = implicit_sector(sv, known, position=tv.index(J[-1]))
+            if J:
+                # last J sector from V's conservation rule, solved at its position in V
+                known = [sec[m] for m in tv if m != J[-1]]
+                sec[J[-1]] = implicit_sector(sv, known, position=tv.index(J[-1]))
             vsec = tuple(sec[m] for m in tv)
             wsec = tuple(sec[m] for m in tw)
-            assert allowed(sv, vsec) and allowed(sw, wsec)
+            if not allowed(sv, vsec):
+                # only with t = 0: V's rule then constrains U's contracted sectors
+                assert not J
+                continue
+            assert allowed(sw, wsec)
             blk = np.einsum(inner_sub, Ru[ustored], Rv[vsec[:-1]], optimize=True)
             Rw[wsec[:-1]] += blk
     return Rw, sw
@@ -525,8 +536,9 @@ def _align_operand(Rfs, t, sym: Sym, row_modes, col_modes, d_row, d_col):
     out = (q + "".join(S[m] for m in row_modes[:-1]) + "".join(inner[m] for m in row_modes)
            + "".join(S[m] for m in col_modes[:-1]) + "".join(inner[m] for m in col_modes))
     A = np.einsum(f"{src},{drow},{dcol}->{out}", Rfs, d_row, d_col, optimize=True)
-    nrow = G ** (len(row_modes) - 1) * int(np.prod([sym.dims[t.index(m)] for m in row_modes]))
-    ncol = G ** (len(col_modes) - 1) * int(np.prod([sym.dims[t.index(m)] for m in col_modes]))
+    # an empty group (s, t or v = 0) has one row or column; its delta pins Q
+    nrow = G ** max(len(row_modes) - 1, 0) * int(np.prod([sym.dims[t.index(m)] for m in row_modes]))
+    ncol = G ** max(len(col_modes) - 1, 0) * int(np.prod([sym.dims[t.index(m)] for m in col_modes]))
     return A.reshape(G, nrow, ncol)
 
 
@@ -550,8 +562,8 @@ def unalign_w(sub, Wal, su: Sym, sv: Sym):
     G = su.group.size
     NW = len(tw)
     dims = {m: sw.dims[p] for p, m in enumerate(tw)}
-    A = np.asarray(Wal).reshape((G,) + (G,) * (len(I) - 1) + tuple(dims[m] for m in I)
-                                + (G,) * (len(J) - 1) + tuple(dims[m] for m in J))
+    A = np.asarray(Wal).reshape((G,) + (G,) * max(len(I) - 1, 0) + tuple(dims[m] for m in I)
+                                + (G,) * max(len(J) - 1, 0) + tuple(dims[m] for m in J))
     L = _letters(2 * NW + 1)
     S = {m: L[p] for p, m in enumerate(tw)}
     inner = {m: L[NW + p] for p, m in enumerate(tw)}
@@ -582,7 +594,8 @@ def aligned_shape(sub, su: Sym, sv: Sym):
     nI = math.prod(su.dims[tu.index(m)] for m in I)
     nK = math.prod(su.dims[tu.index(m)] for m in K)
     nJ = math.prod(sv.dims[tv.index(m)] for m in J)
-    return G, G ** (len(I) - 1) * nI, G ** (len(K) - 1) * nK, G ** (len(J) - 1) * nJ
+    return (G, G ** max(len(I) - 1, 0) * nI, G ** max(len(K) - 1, 0) * nK,
+            G ** max(len(J) - 1, 0) * nJ)
 
 
 # ----------------------------------------------------------------------------

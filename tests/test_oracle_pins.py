@@ -553,3 +553,59 @@ def test_planted_mistake_tables_ignored_in_implicit_sector(monkeypatch):
     bad = O.expand(R, sym)
     assert not np.array_equal(bad, good)
     assert not np.array_equal(_relabel_full(bad, sym), O.expand(_relabel_reduced(R, sym), _plain(sym)))
+
+
+# ---------------------------------------------------------------------------
+# s, t or v = 0: one delta pins Q to a single value (the case noted after Alg. 2)
+# ---------------------------------------------------------------------------
+DEGENERATE = ["a,b->ab", "ab,c->abc", "ab,cd->acbd",        # v = 0: outer products
+              "k,kb->b", "kl,klij->ij", "lk,klb->b",         # s = 0
+              "ak,k->a", "abk,k->ab", "akl,lk->a"]           # t = 0
+
+
+@pytest.mark.parametrize("sub", DEGENERATE)
+@pytest.mark.parametrize("orders", [(3,), (2, 2)])
+def test_degenerate_contractions_all_forms_agree(sub, orders):
+    rng = np.random.default_rng(abs(hash((sub, orders))) % 2 ** 31)
+    g = O.Group(orders)
+    tu, rest = sub.split(",")
+    tv, tw = rest.split("->")
+    for with_tables in (False, True):
+        dims = {m: int(rng.integers(1, 3)) for m in set(tu + tv)}
+        cu = {m: int(rng.choice([-1, 1])) for m in tu}
+        sigma = int(rng.choice([-1, 1]))
+        cv = {m: (sigma * cu[m] if m in tu else int(rng.choice([-1, 1]))) for m in tv}
+        tab = {m: tuple(int(x) for x in rng.permutation(g.size)) for m in set(tu + tv)} if with_tables else None
+        su = O.Sym.make([cu[m] for m in tu], int(rng.integers(g.size)), [dims[m] for m in tu], g,
+                        [tab[m] for m in tu] if tab else None)
+        sv = O.Sym.make([cv[m] for m in tv], int(rng.integers(g.size)), [dims[m] for m in tv], g,
+                        [tab[m] for m in tv] if tab else None)
+        Ru, Rv = rng.standard_normal(su.reduced_shape()), rng.standard_normal(sv.reduced_shape())
+        brute, sw, zero_ok = O.contract_bruteforce(sub, Ru, su, Rv, sv)
+        assert zero_ok
+        blocks, sw2 = O.contract_blocks(sub, Ru, su, Rv, sv)
+        dense, _, _ = O.contract_dense(sub, Ru, su, Rv, sv)
+        aligned = O.contract_irrep_aligned(sub, Ru, su, Rv, sv)[0]
+        assert sw2 == sw
+        for got in (blocks, dense, aligned):
+            assert np.allclose(got, brute, rtol=1e-13, atol=1e-13)
+        # allowed-block products: closed form vs a count of nonzero terms
+        G = g.size
+        nz = 0
+        for us in itertools.product(range(G), repeat=su.order):
+            if not O.allowed(su, us):
+                continue
+            sec = dict(zip(tu, us))
+            for vs in itertools.product(range(G), repeat=sv.order):
+                if all(sec.get(m, x) == x for m, x in zip(tv, vs)) and O.allowed(sv, vs):
+                    nz += 1
+        n = int(np.prod([dims[m] for m in set(tu + tv)]))
+        assert O.flop_count(sub, su, sv) == 2 * n * nz
+
+
+def test_degenerate_output_of_order_zero_is_rejected():
+    g = O.Group((3,))
+    su = O.Sym.make("+-", 0, (2, 2), g)
+    sv = O.Sym.make("-+", 0, (2, 2), g)
+    with pytest.raises(ValueError):
+        O.contract_blocks("kl,kl->", np.zeros(su.reduced_shape()), su, np.zeros(sv.reduced_shape()), sv)
