@@ -8,9 +8,9 @@
  * group symmetry"):
  *   (a) each operand's standard reduced form is remapped into an aligned
  *       reduced form indexed by an auxiliary sector Q (Sec. 2.1 "aligned"
- *       maps; Alg. 2, step li:rf);
+ *       maps; Alg. 2, aligned-operand step);
  *   (b) one dense product per Q value contracts the aligned forms (Sec. 2.1,
- *       einsum "AQL,LQJ->AQJ"; Alg. 2, step li:contra);
+ *       einsum "AQL,LQJ->AQJ"; Alg. 2, product step);
  *   (c) the aligned output is remapped to the standard reduced form of W
  *       (Alg. 2, final step).
  *
@@ -54,6 +54,16 @@
  *   nearest even; the product is hi*hi + hi*lo + lo*hi with binary32
  *   accumulation (two accumulators) and a binary64 sum of the two at the end.
  *
+ * EMPTY MODE GROUPS (s, t or v = 0; Sec. 2.1's deltas with an empty sum).  One
+ * delta then fixes Q on its own: v = 0 (an outer product) gives Q = 0 and
+ * sigma is reported as -1; s = 0 gives Q = Z^U; t = 0 gives Q = sigma Z^V.
+ * The forms that carry that delta are zero outside that slice: U_al when s or
+ * v is 0, V_al when t or v is 0, and W_al always.  symtensor_align writes the
+ * whole form, zeros included; symtensor_contract only needs and multiplies the
+ * one slice (its workspace holds one slice of each form).  With v = 0 the
+ * derived rule of W also admits blocks that break u's own rule; they are
+ * written as zeros.
+ *
  * FUSED PRODUCT.  The standard-form offset of aligned element (Q, r, c) of any
  * operand splits as R(Q, r) + C(Q, c) (the block index and the in-block offset
  * are linear in the sectors and indices, and each implicit sector belongs to one
@@ -94,8 +104,8 @@ extern "C" {
 enum {
   SYMT_OK = 0,
   SYMT_EINVAL = -1,        /* null pointer, negative or mismatched sizes, bad group */
-  SYMT_EEINSUM = -2,       /* malformed subscripts, repeated letter in a term, a letter in
-                              all three terms or in only one, s, t or v = 0 */
+  SYMT_EEINSUM = -2,       /* malformed subscripts, an empty term (s = t = 0), repeated letter
+                              in a term, a letter in all three terms or in only one */
   SYMT_ESYM = -3,          /* mixed sign ratio over contracted modes, W's rule differs from the
                               derived one, bad sign string or charge */
   SYMT_EDTYPE = -4,        /* unsupported storage dtype / compute mode pair */
@@ -156,8 +166,9 @@ typedef struct {
   int32_t group_size;              /* |G| = batch of the aligned product */
   int64_t m, k, n;                 /* aligned product shape per Q */
   int64_t elems_u, elems_v, elems_w;
-  double flops;                    /* 2 |G| m k n: multiply-adds of allowed blocks only */
-  size_t bytes_u_al, bytes_v_al, bytes_w_al;  /* aligned buffer sizes for this compute mode */
+  double flops;                    /* 2 |G| m k n (2 m k n with Q pinned): allowed blocks only */
+  size_t bytes_u_al, bytes_v_al, bytes_w_al;  /* whole aligned forms (all |G| slices) in this
+                                                 compute mode's layout */
   size_t workspace_bytes;          /* what symtensor_contract needs */
   char w_signs[SYMT_MAX_ORDER + 1];/* derived output sign string (tw order), NUL-terminated */
   int32_t w_charge;                /* derived output charge */
@@ -175,7 +186,7 @@ int symtensor_create(symt_ctx** out, int device);
 int symtensor_destroy(symt_ctx* ctx);
 
 /* Validate a contraction and report its shapes, flops, derived output rule and
- * workspace size (Alg. 2 steps li:coeff to li:delta).  Host-only: operand
+ * workspace size (Alg. 2, coefficient and delta steps).  Host-only: operand
  * `data` pointers are not read.  `w` may be NULL, in which case only the
  * derived rule is reported.  `compute` is a symt_compute. */
 int symtensor_plan(const char* einsum, const symt_group* group, const symt_tensor* u,

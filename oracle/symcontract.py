@@ -10,8 +10,8 @@ index is x_m = I_m * n_m + i_m (sector I_m, in-block position i_m).  With
 coefficients c_m = +1 or -1 and total charge Z, an element can be nonzero only
 if sum_m c_m I_m == Z in the group.  The standard reduced form stores the
 sectors of modes 0..N-2 and every in-block index; the sector of the last mode
-is implied by the conservation rule (paper Sec. 2.1 footnote, Alg. 2 step
-"li:rf" assumption, API example of Sec. 3).
+is implied by the conservation rule (paper Sec. 2.1 footnote, the assumption
+Alg. 2 makes when it forms the aligned operands, API example of Sec. 3).
 
 Groups are Z_{g_1} x ... x Z_{g_k} (Sec. 3 mentions products of cyclic
 groups).  An element is flattened mixed-radix, first factor most significant,
@@ -304,7 +304,7 @@ def check_operands(sub, su: Sym, sv: Sym):
 
 
 def flop_count(sub, su: Sym, sv: Sym) -> int:
-    """Multiply-adds x 2 over allowed block products only: 2 n^(s+t+v) G^(s+t+v-2) (Alg. 2 li:contra)."""
+    """Multiply-adds x 2 over allowed block products only: 2 n^(s+t+v) G^(s+t+v-2) (Alg. 2, product step)."""
     tu, tv, tw, I, K, J = check_operands(sub, su, sv)
     n = 1
     for m in I + K:
@@ -502,7 +502,7 @@ def _letters(n, skip=""):
 
 
 def alignment_deltas(sub, su: Sym, sv: Sym):
-    """delta(1) on (I, Q), delta(2) on (K, Q), delta(3) on (J, Q) (Alg. 2 li:coeff, li:delta).
+    """delta(1) on (I, Q), delta(2) on (K, Q), delta(3) on (J, Q) (Alg. 2, coefficient and delta steps).
 
     Q is the sum of the contracted sectors weighted by U's coefficients
     (delta(2): sum c^U_K K - Q == 0).  delta(1): sum c^U_I I + Q == Z^U.
@@ -519,7 +519,7 @@ def alignment_deltas(sub, su: Sym, sv: Sym):
 
 
 def _align_operand(Rfs, t, sym: Sym, row_modes, col_modes, d_row, d_col):
-    """Sum a full-sector operand against the row- and column-group deltas (Alg. 2 li:rf).
+    """Sum a full-sector operand against the row- and column-group deltas (Alg. 2, aligned-operand step).
 
     Output layout: [Q][row sectors but the last][row inner dims][col sectors
     but the last][col inner dims], reshaped to (|G|, M, Kc).
@@ -582,7 +582,7 @@ def contract_irrep_aligned(sub, Ru, su: Sym, Rv, sv: Sym):
     """Alg. 2 end to end; returns (R_W, sym_W, U_al, V_al, W_al)."""
     Ual = align_u(sub, Ru, su, sv)
     Val = align_v(sub, Rv, su, sv)
-    Wal = np.matmul(Ual, Val)           # Alg. 2 li:contra, one product per Q
+    Wal = np.matmul(Ual, Val)           # Alg. 2's product step, one product per Q
     Rw, sw = unalign_w(sub, Wal, su, sv)
     return Rw, sw, Ual, Val, Wal
 

@@ -1,4 +1,4 @@
-// Sector-batched dense product of the aligned forms (Alg. 2, step li:contra;
+// Sector-batched dense product of the aligned forms (Alg. 2's product step;
 // the einsum "AQL,LQJ->AQJ" of Sec. 2.1): for every auxiliary sector Q,
 // C[Q] (M x N) = A[Q] (M x K) * B[Q] (K x N), all slices the same shape.
 //
@@ -832,15 +832,14 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void k_gemm_bf16x3_dma(
     }
 }
 
+// pa / pb: elements from each hi plane to its lo plane.
 template <int BM, int BN, int WM, int WN, int S>
 hipError_t launch_bf16x3_dma(int64_t batch, int M, int N, int K, const void* A, const void* B, void* C,
-                             hipStream_t s) {
+                             hipStream_t s, int64_t pa, int64_t pb) {
   const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
   const int64_t ntiles = batch * tiles_m * tiles_n;
   const uint16_t* a = static_cast<const uint16_t*>(A);
   const uint16_t* b = static_cast<const uint16_t*>(B);
-  const int64_t pa = batch * static_cast<int64_t>(M) * K;
-  const int64_t pb = batch * static_cast<int64_t>(N) * K;
   hipLaunchKernelGGL((k_gemm_bf16x3_dma<BM, BN, WM, WN, S>), dim3(static_cast<unsigned>(ntiles)),
                      dim3(64 * WM * WN), 0, s, a, a + pa, b, b + pb, static_cast<double*>(C), M, N, K,
                      tiles_m, tiles_n, ntiles);
@@ -849,14 +848,12 @@ hipError_t launch_bf16x3_dma(int64_t batch, int M, int N, int K, const void* A, 
 
 template <int BM, int BN, int BK, int WM, int WN>
 hipError_t launch_bf16x3(int64_t batch, int M, int N, int K, const void* A, const void* B, void* C,
-                         hipStream_t s) {
+                         hipStream_t s, int64_t pa, int64_t pb) {
   const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
   const int64_t ntiles = batch * tiles_m * tiles_n;
   const dim3 grid(static_cast<unsigned>(ntiles)), block(64 * WM * WN);
   const uint16_t* a = static_cast<const uint16_t*>(A);
   const uint16_t* b = static_cast<const uint16_t*>(B);
-  const int64_t pa = batch * static_cast<int64_t>(M) * K;
-  const int64_t pb = batch * static_cast<int64_t>(N) * K;
   hipLaunchKernelGGL((k_gemm_bf16x3<BM, BN, BK, WM, WN>), grid, block, 0, s, a, a + pa, b, b + pb,
                      static_cast<double*>(C), M, N, K, tiles_m, tiles_n, ntiles);
   return hipGetLastError();
@@ -971,9 +968,12 @@ hipError_t launch_fp_tile(int idx, int vec, int64_t batch, int M, int N, int K, 
 
 }  // namespace
 
+// plane_a / plane_b (split-bf16 only): elements from a hi plane to its lo
+// plane, 0 for the packed layout (batch * m * k, batch * n * k).
 int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t n, const void* A,
                        const void* B, void* C, hipStream_t stream, std::string* err,
-                       const FusedTables* fused, void* part, size_t part_bytes) {
+                       const FusedTables* fused, void* part, size_t part_bytes, int64_t plane_a,
+                       int64_t plane_b) {
   if (batch == 0 || m == 0 || n == 0) return SYMT_OK;
   if (m > INT32_MAX || n > INT32_MAX || k > INT32_MAX) {
     if (err) *err = "sector product dimension above 2^31-1";
@@ -989,22 +989,24 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
     const char* forced = std::getenv("SYMT_GEMM_TILE");
     const std::string f = forced ? forced : "";
     const bool dma_ok = K % 32 == 0;
-    if (f == "bd256x128s3" && dma_ok) e = launch_bf16x3_dma<256, 128, 4, 2, 3>(batch, M, N, K, A, B, C, stream);
-    else if (f == "bd128x256s3" && dma_ok) e = launch_bf16x3_dma<128, 256, 2, 4, 3>(batch, M, N, K, A, B, C, stream);
-    else if (f == "b128x128k64") e = launch_bf16x3<128, 128, 64, 2, 2>(batch, M, N, K, A, B, C, stream);
-    else if (f == "b128x128k32") e = launch_bf16x3<128, 128, 32, 2, 2>(batch, M, N, K, A, B, C, stream);
-    else if (f == "b256x128k32") e = launch_bf16x3<256, 128, 32, 4, 2>(batch, M, N, K, A, B, C, stream);
-    else if (f == "b128x256k32") e = launch_bf16x3<128, 256, 32, 2, 4>(batch, M, N, K, A, B, C, stream);
-    else if (f == "b128x64k32") e = launch_bf16x3<128, 64, 32, 4, 1>(batch, M, N, K, A, B, C, stream);
-    else if (f == "b64x64k32") e = launch_bf16x3<64, 64, 32, 2, 2>(batch, M, N, K, A, B, C, stream);
+    const int64_t pa = plane_a > 0 ? plane_a : batch * static_cast<int64_t>(M) * K;
+    const int64_t pb = plane_b > 0 ? plane_b : batch * static_cast<int64_t>(N) * K;
+    if (f == "bd256x128s3" && dma_ok) e = launch_bf16x3_dma<256, 128, 4, 2, 3>(batch, M, N, K, A, B, C, stream, pa, pb);
+    else if (f == "bd128x256s3" && dma_ok) e = launch_bf16x3_dma<128, 256, 2, 4, 3>(batch, M, N, K, A, B, C, stream, pa, pb);
+    else if (f == "b128x128k64") e = launch_bf16x3<128, 128, 64, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb);
+    else if (f == "b128x128k32") e = launch_bf16x3<128, 128, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb);
+    else if (f == "b256x128k32") e = launch_bf16x3<256, 128, 32, 4, 2>(batch, M, N, K, A, B, C, stream, pa, pb);
+    else if (f == "b128x256k32") e = launch_bf16x3<128, 256, 32, 2, 4>(batch, M, N, K, A, B, C, stream, pa, pb);
+    else if (f == "b128x64k32") e = launch_bf16x3<128, 64, 32, 4, 1>(batch, M, N, K, A, B, C, stream, pa, pb);
+    else if (f == "b64x64k32") e = launch_bf16x3<64, 64, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb);
     else if (dma_ok && f.empty() && M >= 256 && N >= 512)
-      e = launch_bf16x3_dma<128, 256, 2, 4, 3>(batch, M, N, K, A, B, C, stream);
+      e = launch_bf16x3_dma<128, 256, 2, 4, 3>(batch, M, N, K, A, B, C, stream, pa, pb);
     else if (N <= 64)
-      e = launch_bf16x3<128, 64, 32, 4, 1>(batch, M, N, K, A, B, C, stream);
+      e = launch_bf16x3<128, 64, 32, 4, 1>(batch, M, N, K, A, B, C, stream, pa, pb);
     else if (N >= 1024 && M >= 1024)
-      e = launch_bf16x3<128, 256, 32, 2, 4>(batch, M, N, K, A, B, C, stream);
+      e = launch_bf16x3<128, 256, 32, 2, 4>(batch, M, N, K, A, B, C, stream, pa, pb);
     else
-      e = launch_bf16x3<128, 128, 32, 2, 2>(batch, M, N, K, A, B, C, stream);
+      e = launch_bf16x3<128, 128, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb);
   } else {
     const bool f64 = compute == SYMT_COMPUTE_F64;
     const int vw = f64 ? 2 : 4;

@@ -1,6 +1,6 @@
 // Host planner: einsum parsing, mode classification, the derived output rule,
-// aligned shapes and the transform descriptors (Alg. 2, steps li:coeff,
-// li:delta and the index maps of li:rf and the final step).
+// aligned shapes and the transform descriptors (Alg. 2: its coefficient
+// and delta steps, and the index maps of its aligned-operand and final steps).
 #include "plan.hpp"
 
 #include <algorithm>
@@ -202,8 +202,6 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   p->s = static_cast<int32_t>(I.size());
   p->v = static_cast<int32_t>(K.size());
   p->t = static_cast<int32_t>(J.size());
-  if (p->s == 0 || p->t == 0 || p->v == 0)
-    return fail(err, SYMT_EEINSUM, "s, t and v must all be >= 1 (no outer products or vectors)");
 
   // ---- operands
   if ((rc = read_operand(u, p->g, &p->U, "u", err))) return rc;
@@ -236,7 +234,10 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
         return fail(err, SYMT_ESYM, "contracted mode '%s' carries different charge tables in u and v",
                     std::string(1, K[i]).c_str());
   }
-  p->sigma = sigma;
+  // v = 0 (outer product): no ratio is defined; -1 makes W's coefficients u's
+  // followed by v's and Z^W = Z^U + Z^V
+  p->sigma = p->v == 0 ? -1 : sigma;
+  sigma = p->sigma;
 
   // ---- derived output rule: c^W = (c^U_I, -sigma c^V_J), Z^W = Z^U - sigma Z^V
   for (size_t m = 0; m < tw.size(); ++m) {
@@ -245,6 +246,10 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
     p->w_sign[m] = (pu != std::string::npos) ? p->U.sign[pu] : -sigma * p->V.sign[tv.find(c)];
   }
   p->w_charge = gsub(p->g, p->U.charge, gtimes(p->g, sigma, p->V.charge));
+  // With an empty mode group one generalized delta fixes Q: delta(2) with no K
+  // modes gives Q = 0, delta(1) with no I modes Q = Z^U, delta(3) with no J
+  // modes sigma Q = Z^V.  Only that slice of the aligned forms is nonzero.
+  p->q_pin = p->v == 0 ? 0 : p->s == 0 ? p->U.charge : p->t == 0 ? gtimes(p->g, sigma, p->V.charge) : -1;
   // derived charge tables: u's rows on I modes, v's on J modes
   std::vector<int32_t> w_chg;
   if (!p->chg[0].empty() || !p->chg[1].empty()) {
@@ -319,19 +324,25 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
     return fail(err, SYMT_EINVAL, "aligned shape overflows");
   if (p->M > INT32_MAX || p->N > INT32_MAX || p->Kd > INT32_MAX)
     return fail(err, SYMT_EUNSUPPORTED, "aligned matrix dimension above 2^31-1");
-  p->flops = 2.0 * p->g.size * static_cast<double>(p->M) * static_cast<double>(p->Kd) *
+  p->flops = 2.0 * (p->q_pin >= 0 ? 1 : p->g.size) * static_cast<double>(p->M) * static_cast<double>(p->Kd) *
              static_cast<double>(p->N);
 
-  // ---- buffer sizes for the compute mode
-  const size_t eu = static_cast<size_t>(p->U.elems), ev = static_cast<size_t>(p->V.elems),
-               ew = static_cast<size_t>(p->W.elems);
-  switch (compute) {
-    case SYMT_COMPUTE_F64: p->bytes_u_al = 8 * eu; p->bytes_v_al = 8 * ev; p->bytes_w_al = 8 * ew; break;
-    case SYMT_COMPUTE_F32: p->bytes_u_al = 4 * eu; p->bytes_v_al = 4 * ev; p->bytes_w_al = 4 * ew; break;
-    default: p->bytes_u_al = 4 * eu; p->bytes_v_al = 4 * ev; p->bytes_w_al = 8 * ew; break;
-  }
-  p->workspace = round_up(p->bytes_u_al, 256) + round_up(p->bytes_v_al, 256) +
-                 round_up(p->bytes_w_al, 256);
+  // ---- buffer sizes for the compute mode.  The aligned forms hold |G| M K,
+  // |G| K N and |G| M N elements; with Q pinned the contraction keeps only the
+  // one nonzero slice of each in its workspace.
+  int64_t au = 0, av = 0, aw = 0;
+  if (!mul_ok(p->M, p->Kd, &au) || !mul_ok(au, p->g.size, &au) || !mul_ok(p->Kd, p->N, &av) ||
+      !mul_ok(av, p->g.size, &av) || !mul_ok(p->M, p->N, &aw) || !mul_ok(aw, p->g.size, &aw))
+    return fail(err, SYMT_EINVAL, "aligned form size overflows");
+  const size_t ea = compute == SYMT_COMPUTE_F64 ? 8 : 4, ec = compute == SYMT_COMPUTE_F32 ? 4 : 8;
+  p->bytes_u_al = ea * static_cast<size_t>(au);
+  p->bytes_v_al = ea * static_cast<size_t>(av);
+  p->bytes_w_al = ec * static_cast<size_t>(aw);
+  const size_t slices = p->q_pin >= 0 ? static_cast<size_t>(p->g.size) : 1;
+  p->ws_u_al = p->bytes_u_al / slices;
+  p->ws_v_al = p->bytes_v_al / slices;
+  p->ws_w_al = p->bytes_w_al / slices;
+  p->workspace = round_up(p->ws_u_al, 256) + round_up(p->ws_v_al, 256) + round_up(p->ws_w_al, 256);
 
   // ---- fused product: A read from U's standard form along contiguous K runs
   // (U's last v modes are its contracted modes and their block holds whole
@@ -340,21 +351,21 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   bool trailing_k = true;
   for (int i = 0; i < p->v; ++i) trailing_k = trailing_k && p->posK_u[i] == p->U.n - p->v + i;
   const int vw = compute == SYMT_COMPUTE_F64 ? 2 : 4;
-  p->fused = !force_steps && compute != SYMT_COMPUTE_BF16X3 && p->U.dtype == want &&
+  p->fused = !force_steps && p->q_pin < 0 && compute != SYMT_COMPUTE_BF16X3 && p->U.dtype == want &&
              (!w || p->W.dtype == want) && trailing_k && p->nK % kFpBK == 0 && p->N % vw == 0 &&
              p->M > 0 && p->N > 0 && p->Kd > 0 && p->U.elems > 0;
   if (p->fused) {
     const size_t G = static_cast<size_t>(p->g.size);
     p->bytes_tables = round_up(8 * G * p->M, 256) * 2 + round_up(8 * G * p->Kd, 256) +
                       round_up(8 * G * p->N, 256);
-    p->workspace = round_up(p->bytes_v_al, 256) + p->bytes_tables;
+    p->workspace = round_up(p->ws_v_al, 256) + p->bytes_tables;
   }
   if (p->charges) {
     p->bytes_charges = 4 * 2 * static_cast<size_t>(p->g.size) * (p->U.n + p->V.n + p->W.n);
   }
   // Room for stream-K pieces when the model would pick it on 16-byte aligned operands.
   if (compute != SYMT_COMPUTE_BF16X3 && p->M > 0 && p->N > 0 && p->Kd > 0) {
-    const GemmChoice gc = choose_fp_gemm(p->g.size, p->M, p->N, p->Kd,
+    const GemmChoice gc = choose_fp_gemm(p->q_pin >= 0 ? 1 : p->g.size, p->M, p->N, p->Kd,
                                          compute == SYMT_COMPUTE_F64 ? 8 : 4, true);
     p->bytes_partial = gc.partial_bytes;
     p->workspace += round_up(p->bytes_partial, 256);
@@ -493,8 +504,7 @@ void sector_groups(const Plan& p, int operand, SectorGroup* R, SectorGroup* C) {
 
 OffsetParams make_offsets(const Plan& p, int operand, bool rows) {
   OffsetParams o;
-  o.chg = nullptr;                  // set at launch when the operand has charge tables
-  std::memset(&o, 0, sizeof o);
+  std::memset(&o, 0, sizeof o);     // chg (charge tables) stays nullptr until launch
   o.g = p.g;
   SectorGroup R, C;
   sector_groups(p, operand, &R, &C);
@@ -528,10 +538,9 @@ OffsetParams make_offsets(const Plan& p, int operand, bool rows) {
 }
 
 XformParams make_xform(const Plan& p, int operand, bool to_aligned, int in_bytes, int out_bytes,
-                       bool out_is_split) {
+                       bool out_is_split, bool slice_only) {
   XformParams x;
-  x.chg = nullptr;                  // set at launch when the operand has charge tables
-  std::memset(&x, 0, sizeof x);
+  std::memset(&x, 0, sizeof x);     // chg (charge tables) stays nullptr until launch
   x.g = p.g;
   const OperandDesc& X = operand == 0 ? p.U : operand == 1 ? p.V : p.W;
   x.order = X.n;
@@ -545,7 +554,10 @@ XformParams make_xform(const Plan& p, int operand, bool to_aligned, int in_bytes
   for (int i = 1; i < R.count; ++i) x.gpow_row *= G;
   x.gpow_col = 1;
   for (int i = 1; i < C.count; ++i) x.gpow_col *= G;
-  x.nblocks = x.gpow_row * x.gpow_col * G;
+  // Q is fixed where one of the form's own deltas has an empty sum; the
+  // contraction's workspace copy keeps slice q_pin of every form.
+  x.q_pin = slice_only || pinned_form(p, operand) ? p.q_pin : -1;
+  x.nblocks = x.gpow_row * x.gpow_col * (x.q_pin >= 0 ? 1 : G);
   x.blk_elems = 1;
   for (int m = 0; m < X.n; ++m) x.blk_elems *= X.dims[m];
   int64_t nR = 1, nC = 1;
@@ -553,8 +565,10 @@ XformParams make_xform(const Plan& p, int operand, bool to_aligned, int in_bytes
   for (int i = 0; i < C.count; ++i) nC *= X.dims[C.pos[i]];
   const int64_t rows_tot = x.gpow_row * nR, cols_tot = x.gpow_col * nC;
   const AlignedLayout lay = aligned_layout(p.compute, operand);
-  x.q_stride = rows_tot * cols_tot;
-  x.plane = static_cast<int64_t>(G) * rows_tot * cols_tot;
+  // one slice only (Q pinned, workspace copy): every block lands at Q offset 0
+  const bool one_slice = slice_only && x.q_pin >= 0;
+  x.q_stride = one_slice ? 0 : rows_tot * cols_tot;
+  x.plane = (one_slice ? 1 : static_cast<int64_t>(G)) * rows_tot * cols_tot;
   const int64_t row_unit = lay == kRowMajor ? cols_tot : 1;   // aligned stride of one row
   const int64_t col_unit = lay == kRowMajor ? 1 : rows_tot;   // aligned stride of one column
   x.rs_stride = nR * row_unit;

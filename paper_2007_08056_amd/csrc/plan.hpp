@@ -49,7 +49,8 @@ struct XformParams {
   int32_t order;                    // modes of the operand
   SectorGroup row, col;
   int64_t gpow_row, gpow_col;       // |G|^(count-1) of each group
-  int64_t nblocks;                  // |G|^(order-1) blocks (bijection std <-> aligned)
+  int64_t nblocks;                  // aligned blocks moved: |G|^(order-1), or one Q slice's
+  int32_t q_pin;                    // -1, or the only Q with nonzero aligned blocks
   int64_t blk_elems;                // elements per block (product of inner dims)
   int64_t q_stride, rs_stride, cs_stride;  // aligned block base = Q*q + Rs*rs + Cs*cs
   int64_t plane;                    // elements between the hi and lo bf16 planes
@@ -132,6 +133,7 @@ struct Plan {
   GroupDesc g;
   std::string tu, tv, tw;
   int32_t s = 0, t = 0, v = 0, sigma = 0;
+  int32_t q_pin = -1;               // s, t or v = 0: the one auxiliary sector with nonzero blocks
   int32_t posI_u[kMaxOrder], posK_u[kMaxOrder], posK_v[kMaxOrder], posJ_v[kMaxOrder];
   int32_t posI_w[kMaxOrder], posJ_w[kMaxOrder];
   int64_t nI = 1, nK = 1, nJ = 1;
@@ -143,6 +145,7 @@ struct Plan {
   int32_t compute = 0;
   bool fused = false;               // A read from U's standard form, C written to W's
   size_t bytes_u_al = 0, bytes_v_al = 0, bytes_w_al = 0, workspace = 0;
+  size_t ws_u_al = 0, ws_v_al = 0, ws_w_al = 0;   // their regions in the contraction's workspace
   size_t bytes_tables = 0;          // fused: the four offset tables
   size_t bytes_partial = 0;         // stream-K pieces of the product (0: data-parallel tiles)
   // Charge tables (label -> charge) of U, V, W, n x |G| each; empty = identity.
@@ -178,10 +181,20 @@ constexpr int kSkSlots = 512;
 constexpr int kSkMinIters = 4;
 GemmChoice choose_fp_gemm(int64_t batch, int64_t M, int64_t N, int64_t K, int elem, bool aligned);
 
+// True when the aligned form of operand 0 (U), 1 (V) or 2 (W) is zero outside
+// slice q_pin: U_al carries deltas (1) and (2), V_al (2) and (3), W_al is their
+// product.
+inline bool pinned_form(const Plan& p, int operand) {
+  if (p.q_pin < 0) return false;
+  return operand == 0 ? (p.s == 0 || p.v == 0) : operand == 1 ? (p.t == 0 || p.v == 0) : true;
+}
+
 // Transform descriptor for operand 0 (U), 1 (V) or 2 (W) in the given direction.
-// `in_type` / `out_type` are the element types of the source and destination.
+// `in_elem_bytes` / `out_elem_bytes` are the element sizes of the source and
+// destination.  `slice_only`: with Q pinned, the aligned side is the one nonzero
+// slice (the contraction's workspace) rather than the full |G|-slice form.
 XformParams make_xform(const Plan& p, int operand, bool to_aligned, int in_elem_bytes,
-                       int out_elem_bytes, bool out_is_split);
+                       int out_elem_bytes, bool out_is_split, bool slice_only);
 
 // Row (rows = true) or column offset table of operand 0 (U), 1 (V) or 2 (W).
 OffsetParams make_offsets(const Plan& p, int operand, bool rows);

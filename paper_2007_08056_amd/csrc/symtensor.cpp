@@ -17,9 +17,10 @@ int launch_xform(const XformParams& p, bool in_f64, int out, const void* src, vo
 int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t n, const void* A,
                        const void* B, void* C, hipStream_t stream, std::string* err,
                        const FusedTables* fused = nullptr, void* part = nullptr,
-                       size_t part_bytes = 0);
+                       size_t part_bytes = 0, int64_t plane_a = 0, int64_t plane_b = 0);
 int launch_offsets(const OffsetBatch& batch, hipStream_t stream, std::string* err);
 int launch_put_i32(int32_t* dst, const int32_t* src, int64_t n, hipStream_t stream, std::string* err);
+int launch_zero(void* ptr, size_t bytes, hipStream_t stream, std::string* err);
 }  // namespace symt
 
 using symt::Plan;
@@ -89,13 +90,14 @@ int aligned_elem_bytes(int compute) {
 
 // Align operand 0 (U) or 1 (V) from its standard form into `dst`; `chg`: the
 // operand's device charge tables (nullptr: identity).
-int do_align(symt_ctx* ctx, const Plan& p, int operand, void* dst, hipStream_t s,
+// `slice_only`: dst is the contraction's workspace copy (one slice when Q is pinned).
+int do_align(symt_ctx* ctx, const Plan& p, int operand, void* dst, hipStream_t s, bool slice_only,
              const int32_t* chg = nullptr) {
   const symt::OperandDesc& X = operand == 0 ? p.U : p.V;
   if (X.elems == 0) return SYMT_OK;
   const int kind = out_kind_aligned(p.compute);
   symt::XformParams x = symt::make_xform(p, operand, true, static_cast<int>(elem_bytes(X.dtype)),
-                                         aligned_elem_bytes(p.compute), kind == 2);
+                                         aligned_elem_bytes(p.compute), kind == 2, slice_only);
   x.chg = chg;
   if (!aligned16(X.data) || !aligned16(dst)) x.vec = 1;
   std::string err;
@@ -105,15 +107,21 @@ int do_align(symt_ctx* ctx, const Plan& p, int operand, void* dst, hipStream_t s
   return rc ? ctx_fail(ctx, rc, err) : SYMT_OK;
 }
 
-int do_unalign(symt_ctx* ctx, const Plan& p, const void* wal, hipStream_t s, const int32_t* chg = nullptr) {
+int do_unalign(symt_ctx* ctx, const Plan& p, const void* wal, hipStream_t s, bool slice_only,
+               const int32_t* chg = nullptr) {
   if (p.W.elems == 0) return SYMT_OK;
   const bool in_f64 = p.compute != SYMT_COMPUTE_F32;
   symt::XformParams x = symt::make_xform(p, 2, false, in_f64 ? 8 : 4,
-                                         static_cast<int>(elem_bytes(p.W.dtype)), false);
+                                         static_cast<int>(elem_bytes(p.W.dtype)), false, slice_only);
   x.chg = chg;
   if (!aligned16(wal) || !aligned16(p.W.data)) x.vec = 1;
   std::string err;
   const int rc = timed(ctx, 3, s, [&] {
+    // v = 0: W's rule admits blocks that break u's own rule; they hold zeros
+    if (p.v == 0) {
+      const int r = symt::launch_zero(p.W.data, static_cast<size_t>(p.W.elems) * elem_bytes(p.W.dtype), s, &err);
+      if (r) return r;
+    }
     return symt::launch_xform(x, in_f64, p.W.dtype == SYMT_F64 ? 0 : 1, wal, p.W.data, s, &err);
   });
   return rc ? ctx_fail(ctx, rc, err) : SYMT_OK;
@@ -121,10 +129,12 @@ int do_unalign(symt_ctx* ctx, const Plan& p, const void* wal, hipStream_t s, con
 
 int do_gemm(symt_ctx* ctx, int compute, int64_t batch, int64_t m, int64_t k, int64_t n,
             const void* a, const void* b, void* c, hipStream_t s,
-            const symt::FusedTables* fused = nullptr, void* part = nullptr, size_t part_bytes = 0) {
+            const symt::FusedTables* fused = nullptr, void* part = nullptr, size_t part_bytes = 0,
+            int64_t plane_a = 0, int64_t plane_b = 0) {
   std::string err;
   const int rc = timed(ctx, 2, s, [&] {
-    return symt::launch_sector_gemm(compute, batch, m, k, n, a, b, c, s, &err, fused, part, part_bytes);
+    return symt::launch_sector_gemm(compute, batch, m, k, n, a, b, c, s, &err, fused, part, part_bytes,
+                                    plane_a, plane_b);
   });
   return rc ? ctx_fail(ctx, rc, err) : SYMT_OK;
 }
@@ -135,7 +145,7 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
   using symt::round_up;
   const size_t G = static_cast<size_t>(p.g.size);
   void* val = base;
-  int64_t* ra = reinterpret_cast<int64_t*>(base + round_up(p.bytes_v_al, 256));
+  int64_t* ra = reinterpret_cast<int64_t*>(base + round_up(p.ws_v_al, 256));
   int64_t* ca = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(ra) + round_up(8 * G * p.M, 256));
   int64_t* rc = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(ca) + round_up(8 * G * p.Kd, 256));
   int64_t* cc = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(rc) + round_up(8 * G * p.M, 256));
@@ -156,7 +166,7 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
     return symt::launch_offsets(b, s, &err);
   });
   if (rc_) return ctx_fail(ctx, rc_, err);
-  if ((rc_ = do_align(ctx, p, 1, val, s, chg[1]))) return rc_;
+  if ((rc_ = do_align(ctx, p, 1, val, s, true, chg[1]))) return rc_;
   symt::FusedTables f{ra, ca, rc, cc, aligned16(p.U.data) ? 2 : 1};
   char* part = reinterpret_cast<char*>(cc) + round_up(8 * G * p.N, 256);
   return do_gemm(ctx, p.compute, p.g.size, p.M, p.Kd, p.N, p.U.data, val, p.W.data, s, &f,
@@ -296,15 +306,21 @@ int symtensor_contract(symt_ctx* ctx, const char* einsum, const symt_group* grou
   }
   if (p.fused) return do_fused(ctx, p, base, s, chg);
   void* ual = base;
-  void* val = base + symt::round_up(p.bytes_u_al, 256);
-  void* wal = base + symt::round_up(p.bytes_u_al, 256) + symt::round_up(p.bytes_v_al, 256);
-  char* part = static_cast<char*>(wal) + symt::round_up(p.bytes_w_al, 256);
-  if ((rc = do_align(ctx, p, 0, ual, s, chg[0]))) return rc;
-  if ((rc = do_align(ctx, p, 1, val, s, chg[1]))) return rc;
-  if ((rc = do_gemm(ctx, p.compute, p.g.size, p.M, p.Kd, p.N, ual, val, wal, s, nullptr,
-                    p.bytes_partial ? part : nullptr, p.bytes_partial)))
+  void* val = base + symt::round_up(p.ws_u_al, 256);
+  void* wal = base + symt::round_up(p.ws_u_al, 256) + symt::round_up(p.ws_v_al, 256);
+  char* part = static_cast<char*>(wal) + symt::round_up(p.ws_w_al, 256);
+  if ((rc = do_align(ctx, p, 0, ual, s, true, chg[0]))) return rc;
+  if ((rc = do_align(ctx, p, 1, val, s, true, chg[1]))) return rc;
+  if (p.q_pin >= 0) {
+    // the workspace holds slice q_pin alone: one product of it
+    if ((rc = do_gemm(ctx, p.compute, 1, p.M, p.Kd, p.N, ual, val, wal, s, nullptr,
+                      p.bytes_partial ? part : nullptr, p.bytes_partial, p.M * p.Kd, p.Kd * p.N)))
+      return rc;
+  } else if ((rc = do_gemm(ctx, p.compute, p.g.size, p.M, p.Kd, p.N, ual, val, wal, s, nullptr,
+                           p.bytes_partial ? part : nullptr, p.bytes_partial))) {
     return rc;
-  if ((rc = do_unalign(ctx, p, wal, s, chg[2]))) return rc;
+  }
+  if ((rc = do_unalign(ctx, p, wal, s, true, chg[2]))) return rc;
   return SYMT_OK;
 }
 
@@ -328,7 +344,13 @@ int symtensor_align(symt_ctx* ctx, const char* einsum, const symt_group* group,
   if (overlaps(aligned, need, X.data, static_cast<size_t>(X.elems) * elem_bytes(X.dtype)))
     return ctx_fail(ctx, SYMT_EALIAS, "aligned buffer overlaps the operand");
   if ((rc = set_device(ctx))) return rc;
-  return do_align(ctx, p, operand, aligned, static_cast<hipStream_t>(stream));
+  if (symt::pinned_form(p, operand) && need > 0) {
+    // Q pinned: the other slices of the aligned form are zero (Alg. 2's deltas)
+    std::string err;
+    if ((rc = symt::launch_zero(aligned, need, static_cast<hipStream_t>(stream), &err)))
+      return ctx_fail(ctx, rc, err);
+  }
+  return do_align(ctx, p, operand, aligned, static_cast<hipStream_t>(stream), false);
 }
 
 int symtensor_unalign(symt_ctx* ctx, const char* einsum, const symt_group* group,
@@ -348,7 +370,7 @@ int symtensor_unalign(symt_ctx* ctx, const char* einsum, const symt_group* group
                p.bytes_w_al))
     return ctx_fail(ctx, SYMT_EALIAS, "output overlaps the aligned buffer");
   if ((rc = set_device(ctx))) return rc;
-  return do_unalign(ctx, p, aligned_w, static_cast<hipStream_t>(stream));
+  return do_unalign(ctx, p, aligned_w, static_cast<hipStream_t>(stream), false);
 }
 
 int symtensor_sector_gemm_workspace_size(int32_t compute, int64_t batch, int64_t m, int64_t k,

@@ -1,5 +1,5 @@
-// Reduced-form transforms of the irrep-alignment method (Alg. 2, step li:rf
-// for the inputs and the final step for the output).
+// Reduced-form transforms of the irrep-alignment method (Alg. 2: the step that
+// forms the aligned operands, and its final step for the output).
 //
 // The aligned form of an operand and its standard reduced form hold the same
 // blocks in a different arrangement: each aligned block (Q, stored row
@@ -246,6 +246,28 @@ int launch_put_i32(int32_t* dst, const int32_t* src, int64_t n, hipStream_t stre
       if (err) *err = std::string("charge table upload: ") + hipGetErrorString(e);
       return SYMT_EHIP;
     }
+  }
+  return SYMT_OK;
+}
+
+__global__ __launch_bounds__(256) void k_zero_u32(uint32_t* __restrict__ p, int64_t n) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0u;
+}
+
+// Clears `bytes` (a multiple of 4) at a 4-byte aligned device address; a kernel
+// rather than a memset node, so that captured streams replay it reliably.
+int launch_zero(void* ptr, size_t bytes, hipStream_t stream, std::string* err) {
+  const int64_t n = static_cast<int64_t>(bytes / 4);
+  if (n == 0) return SYMT_OK;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream,
+                     static_cast<uint32_t*>(ptr), n);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    if (err) *err = std::string("clear launch: ") + hipGetErrorString(e);
+    return SYMT_EHIP;
   }
   return SYMT_OK;
 }

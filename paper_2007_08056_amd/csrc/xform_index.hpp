@@ -54,6 +54,7 @@ __host__ __device__ inline int dg_times(const GroupDesc& g, int c, int a) {
 // stored labels are mapped to charges and the solved charge back to a label.
 __host__ __device__ inline void fill_sectors(const GroupDesc& g, const SectorGroup& sg,
                                              int64_t digits, int q, int* S, const int32_t* chg) {
+  if (sg.count == 0) return;        // an empty group only pins Q
   int acc = 0;
   for (int i = sg.count - 2; i >= 0; --i) {
     const int d = static_cast<int>(digits % g.size);
@@ -74,7 +75,7 @@ __host__ __device__ inline void block_bases(const XformParams& p, int64_t blk, i
   const int64_t cs = blk % p.gpow_col;
   const int64_t t = blk / p.gpow_col;
   const int64_t rs = t % p.gpow_row;
-  const int q = static_cast<int>(t / p.gpow_row);
+  const int q = p.q_pin >= 0 ? p.q_pin : static_cast<int>(t / p.gpow_row);
   int S[kMaxOrder];
   fill_sectors(p.g, p.row, rs, q, S, p.chg);
   fill_sectors(p.g, p.col, cs, q, S, p.chg);

@@ -221,11 +221,13 @@ def einsum(subscripts: str, u: SymTensor, v: SymTensor, compute: str = "f64") ->
 # ---------------------------------------------------------------------------
 # The three steps on their own (tests, profiling)
 # ---------------------------------------------------------------------------
-def align(subscripts: str, u: SymTensor, v: SymTensor, operand: int, compute: str = "f64") -> torch.Tensor:
+def align(subscripts: str, u: SymTensor, v: SymTensor, operand: int, compute: str = "f64",
+          out: torch.Tensor | None = None) -> torch.Tensor:
     """Aligned form of u (operand 0) or v (operand 1) in the compute mode's layout.
 
     f64 / f32: a (|G|, M, K) or (|G|, K, N) tensor.  bf16x3: an int16 tensor of
     raw bf16 bits, (2, |G|, M, K) for u and (2, |G|, N, K) for v (hi plane first).
+    `out`, if given, is a contiguous tensor of that shape and dtype, overwritten.
     """
     dev = u.data.device
     g = L.make_group(u.group)
@@ -233,11 +235,15 @@ def align(subscripts: str, u: SymTensor, v: SymTensor, operand: int, compute: st
     info = L.plan(subscripts, g, du, dv, None, L.COMPUTE[compute])
     G, M, K, N = info.group_size, info.m, info.k, info.n
     if compute == "f64":
-        out = torch.empty((G, M, K) if operand == 0 else (G, K, N), dtype=torch.float64, device=dev)
+        shape, dtype = ((G, M, K) if operand == 0 else (G, K, N)), torch.float64
     elif compute == "f32":
-        out = torch.empty((G, M, K) if operand == 0 else (G, K, N), dtype=torch.float32, device=dev)
+        shape, dtype = ((G, M, K) if operand == 0 else (G, K, N)), torch.float32
     else:
-        out = torch.empty((2, G, M, K) if operand == 0 else (2, G, N, K), dtype=torch.int16, device=dev)
+        shape, dtype = ((2, G, M, K) if operand == 0 else (2, G, N, K)), torch.int16
+    if out is None:
+        out = torch.empty(shape, dtype=dtype, device=dev)
+    elif tuple(out.shape) != shape or out.dtype != dtype or not out.is_contiguous() or out.device != dev:
+        raise ValueError(f"align: out must be a contiguous {dtype} tensor of shape {shape} on {dev}")
     ctx = L.context(dev.index or 0)
     nbytes = out.numel() * out.element_size()
     L.check(L.LIB.symtensor_align(ctx, subscripts.encode(), ctypes.byref(g), du.ref, dv.ref, None,

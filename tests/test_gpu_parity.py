@@ -527,3 +527,69 @@ def test_charge_tables_rejected_by_standalone_align(P):
     with pytest.raises(P._lib.SymtError) as e:
         P.align("ak,kb->ab", u, v, 0)
     assert e.value.code == P._lib.SYMT_EUNSUPPORTED
+
+
+# ---------------------------------------------------------------------------
+# s, t or v = 0: Q pinned to one value, the product on a single slice
+# ---------------------------------------------------------------------------
+DEGENERATE = ["a,b->ab", "ab,c->abc", "ab,cd->acbd",        # v = 0: outer products
+              "k,kb->b", "kl,klij->ij", "lk,klb->b",         # s = 0
+              "ak,k->a", "abk,k->ab", "akl,lk->a"]           # t = 0
+
+
+def _degenerate_case(rng, sub, orders, nmax=5):
+    g = O.Group(orders)
+    tu, rest = sub.split(",")
+    tv, tw = rest.split("->")
+    dims = {m: int(rng.integers(1, nmax + 1)) for m in set(tu + tv)}
+    cu = {m: int(rng.choice([-1, 1])) for m in tu}
+    sigma = int(rng.choice([-1, 1]))
+    cv = {m: (sigma * cu[m] if m in tu else int(rng.choice([-1, 1]))) for m in tv}
+    su = O.Sym.make([cu[m] for m in tu], int(rng.integers(g.size)), [dims[m] for m in tu], g)
+    sv = O.Sym.make([cv[m] for m in tv], int(rng.integers(g.size)), [dims[m] for m in tv], g)
+    return su, sv
+
+
+@pytest.mark.parametrize("sub", DEGENERATE)
+@pytest.mark.parametrize("orders", [(4,), (2, 3)])
+def test_degenerate_contractions_vs_oracle(P, sub, orders):
+    rng = np.random.default_rng(abs(hash(("degenerate", sub, orders))) % 2 ** 31)
+    for with_tables in (False, True):
+        su, sv = _degenerate_case(rng, sub, orders)
+        if with_tables:
+            su, sv = _with_tables(rng, sub, su, sv)
+        say(f"degenerate {sub} G={orders} tables={with_tables}")
+        Ru, Rv = rng.standard_normal(su.reduced_shape()), rng.standard_normal(sv.reduced_shape())
+        ref, sw = O.contract_blocks(sub, Ru, su, Rv, sv)
+        absref, _ = O.contract_blocks(sub, np.abs(Ru), su, np.abs(Rv), sv)
+        k = H.contracted_extent(sub, su) if "," in sub and set(sub.split(",")[0]) & set(sub.split(",")[1].split("->")[0]) else 1
+        u, v = _sym_tensor(P, Ru, su), _sym_tensor(P, Rv, sv)
+        assert P.plan(sub, u, v).flops == O.flop_count(sub, su, sv)
+        for compute in ("f64", "f32", "bf16x3"):
+            info = P.plan(sub, u, v, compute)
+            if compute == "bf16x3" and info.k % 8:
+                continue
+            w = P.output_like(sub, u, v)
+            w.data.fill_(7.0)                      # every element must be overwritten
+            assert w.signs == sw.sign_string() and w.charge == sw.charge
+            P.contract_into(sub, u, v, w, compute)
+            got = H.to_np(w.data)
+            assert np.all(np.abs(got - ref) <= H.bound_factor(compute, k) * absref + 1e-300), compute
+            if compute == "f64":
+                assert H.rel_err(got, ref) <= 1e-12 or np.max(np.abs(ref)) == 0
+                assert np.array_equal(O.expand(got, sw) == 0, O.expand(ref, sw) == 0)
+        if not with_tables:
+            # steps (a) and (c) alone, bit-exact against Alg. 2 with dense deltas (zero Q slices included)
+            Ual, Val = O.align_u(sub, Ru, su, sv), O.align_v(sub, Rv, su, sv)
+            for op, ref_al in ((0, Ual), (1, Val)):
+                # into a NaN-filled buffer: the slices that must be zero are written too
+                for compute, dt in (("f64", torch.float64), ("f32", torch.float32)):
+                    buf = torch.full(ref_al.shape, float("nan"), dtype=dt, device=DEV)
+                    got_al = H.to_np(P.align(sub, u, v, op, compute, out=buf))
+                    assert np.array_equal(got_al, ref_al.astype(got_al.dtype)), (op, compute)
+            Wal = np.matmul(Ual, Val)
+            ref_w, _ = O.unalign_w(sub, Wal, su, sv)
+            w = P.output_like(sub, u, v)
+            w.data.fill_(3.0)
+            P.unalign(sub, u, v, w, torch.from_numpy(Wal).to(DEV), "f64")
+            assert np.array_equal(H.to_np(w.data), ref_w)

@@ -296,7 +296,7 @@ def test_product_group_equals_z6_after_crt_relabelling():
 
 
 # ---------------------------------------------------------------------------
-# Costs (paper Sec. 2.1, Alg. 2 li:contra, Table 1)
+# Costs (paper Sec. 2.1, Alg. 2's product step, Table 1)
 # ---------------------------------------------------------------------------
 def test_flop_counts_closed_forms():
     for G, n in ((4, 4), (8, 3), (3, 5)):
