@@ -593,3 +593,32 @@ def test_degenerate_contractions_vs_oracle(P, sub, orders):
             w.data.fill_(3.0)
             P.unalign(sub, u, v, w, torch.from_numpy(Wal).to(DEV), "f64")
             assert np.array_equal(H.to_np(w.data), ref_w)
+
+
+# ---------------------------------------------------------------------------
+# U(1) emulated by Z_G with per-mode charge tables (Sec. 3): the library's
+# result, expanded, is the dense U(1) einsum at the labels that carry U(1)
+# charges and zero elsewhere.  The reference is np.einsum on dense U(1)
+# tensors built with integer charges, independent of the oracle's contraction.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("sub", ["ij,jk->ik", "ijk,klm->ijlm", "abcd,cdij->abij", "ak,k->a", "a,b->ab"])
+def test_u1_emulation_vs_dense_u1_einsum(P, sub):
+    from tests import u1_cases as U1
+    rng = np.random.default_rng(abs(hash(("u1-gpu", sub))) % 2 ** 31)
+    for g_extra in (0, 3):
+        c = U1.random_case(rng, sub, g_extra, nmax=4)
+        say(f"u1 {sub} G={c['G']}")
+        u, v = _sym_tensor(P, c["Ru"], c["su"]), _sym_tensor(P, c["Rv"], c["sv"])
+        sw = O.output_symmetry(sub, c["su"], c["sv"])
+        absref = np.einsum(sub, np.abs(c["Tu"]), np.abs(c["Tv"]))
+        k = P.plan(sub, u, v).k + int(np.prod([d for m, d in zip(sub.split(",")[0], c["Tu"].shape)
+                                                 if m in sub.split(",")[1].split("->")[0]]))
+        for compute in ("f64", "f32", "bf16x3"):
+            if compute == "bf16x3" and P.plan(sub, u, v, compute).k % 8:
+                continue
+            w = P.output_like(sub, u, v)
+            w.data.fill_(7.0)
+            P.contract_into(sub, u, v, w, compute)
+            phys, rest = U1.physical_part(O.expand(H.to_np(w.data), sw), c["Pw"], c["nw"])
+            assert rest == 0.0, compute
+            assert np.all(np.abs(phys - c["ref"]) <= H.bound_factor(compute, k) * absref + 1e-300), compute

@@ -609,3 +609,34 @@ def test_degenerate_output_of_order_zero_is_rejected():
     sv = O.Sym.make("-+", 0, (2, 2), g)
     with pytest.raises(ValueError):
         O.contract_blocks("kl,kl->", np.zeros(su.reduced_shape()), su, np.zeros(sv.reduced_shape()), sv)
+
+
+# ---------------------------------------------------------------------------
+# U(1) emulated by a cyclic group (Sec. 3): dense U(1) tensors with integer
+# charge conservation, embedded in Z_G by per-mode charge tables, contract to
+# the embedding of the dense U(1) einsum; wrapped-around blocks stay zero.
+# ---------------------------------------------------------------------------
+U1_SUBS = ["ij,jk->ik", "ijk,klm->ijlm", "abcd,cdij->abij", "ak,k->a", "a,b->ab", "bk,ka->ab"]
+
+
+@pytest.mark.parametrize("sub", U1_SUBS)
+@pytest.mark.parametrize("g_extra", [0, 3])
+def test_u1_emulation_matches_dense_u1_einsum(sub, g_extra):
+    from tests import u1_cases as U1
+    rng = np.random.default_rng(abs(hash(("u1", sub, g_extra))) % 2 ** 31)
+    for _ in range(3):
+        c = U1.random_case(rng, sub, g_extra)
+        for form in (O.contract_blocks, O.contract_irrep_aligned, O.contract_dense):
+            Rw, sw = form(sub, c["Ru"], c["su"], c["Rv"], c["sv"])[:2]
+            phys, rest = U1.physical_part(O.expand(Rw, sw), c["Pw"], c["nw"])
+            assert rest == 0.0, form.__name__
+            np.testing.assert_allclose(phys, c["ref"], rtol=0, atol=1e-12 * max(1.0, np.abs(c["ref"]).max()))
+
+
+def test_u1_emulation_needs_one_label_per_charge():
+    # with G below a mode's number of charges two charges share a label: not representable
+    from tests import u1_cases as U1
+    rng = np.random.default_rng(7)
+    T = U1.dense_u1(rng, [1, -1], 0, [0, 0], [3, 3], [1, 1])
+    with pytest.raises(Exception):
+        U1.embed(T, [1, -1], 0, [0, 0], [3, 3], [1, 1], 2)
