@@ -2,7 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY.  Nothing in the library imports this module; only
 the test suite, the smoke check and the benchmark's CPU-baseline leg may call
-it.  It shares no code with the GPU path.  Arithmetic is binary64 throughout.
+it.  It shares no code with the GPU path.  Arithmetic is binary64 throughout,
+complex binary64 when an operand is complex (tensors over R or C, Sec. 2.2).
 
 Notation (paper Sec. 2.2, Eq. symtsr and Eq. redform).  A tensor of order N has
 modes m = 0..N-1; mode m has |G| sectors and block dimension n_m, so its full
@@ -48,6 +49,11 @@ import numpy as np
 # ----------------------------------------------------------------------------
 # Groups
 # ----------------------------------------------------------------------------
+def _ftype(*arrays):
+    """binary64, or complex binary64 when any input is complex (tensors over R or C, Sec. 2.2)."""
+    return np.result_type(*[np.asarray(a).dtype for a in arrays], np.float64)
+
+
 class Group:
     """Z_{orders[0]} x Z_{orders[1]} x ...; elements are ints in [0, size)."""
 
@@ -171,11 +177,12 @@ def full_sectors(sym: Sym, stored):
 # ----------------------------------------------------------------------------
 def expand(R, sym: Sym) -> np.ndarray:
     """Full tensor with every zero block materialised (Eq. symtsr)."""
-    R = np.asarray(R, dtype=np.float64)
+    R = np.asarray(R)
+    R = R.astype(_ftype(R), copy=False)
     if R.shape != sym.reduced_shape():
         raise ValueError(f"reduced form has shape {R.shape}, expected {sym.reduced_shape()}")
     G = sym.group.size
-    full = np.zeros(sym.full_shape(), dtype=np.float64)
+    full = np.zeros(sym.full_shape(), dtype=R.dtype)
     for stored in itertools.product(range(G), repeat=sym.order - 1):
         secs = full_sectors(sym, stored)
         sl = tuple(slice(s * n, (s + 1) * n) for s, n in zip(secs, sym.dims))
@@ -204,7 +211,7 @@ def lookup(R, sym: Sym, full_index):
     inner = tuple(x % n for x, n in zip(full_index, sym.dims))
     if not allowed(sym, secs):
         return 0.0
-    return float(R[secs[:-1] + inner])
+    return R[secs[:-1] + inner].item()
 
 
 # ----------------------------------------------------------------------------
@@ -343,9 +350,10 @@ def contract_blocks(sub, Ru, su: Sym, Rv, sv: Sym, u_blocks=None):
     sw = output_symmetry(sub, su, sv)
     g = su.group
     G = g.size
-    Ru = np.asarray(Ru, dtype=np.float64)
-    Rv = np.asarray(Rv, dtype=np.float64)
-    Rw = np.zeros(sw.reduced_shape(), dtype=np.float64)
+    dt = _ftype(Ru, Rv)
+    Ru = np.asarray(Ru, dtype=dt)
+    Rv = np.asarray(Rv, dtype=dt)
+    Rw = np.zeros(sw.reduced_shape(), dtype=dt)
     inner_sub = sub.replace(" ", "")
     outer = itertools.product(range(G), repeat=su.order - 1) if u_blocks is None else u_blocks
     for ustored in outer:
@@ -390,7 +398,7 @@ def _vector_allowed(sym: Sym, secs):
     return ok
 
 
-def sample_contract(sub, su: Sym, sv: Sym, u_values, v_values, w_full_positions):
+def sample_contract(sub, su: Sym, sv: Sym, u_values, v_values, w_full_positions, dtype=np.float64):
     """W at the given full positions, each summed over every contracted full index.
 
     ``u_values(stored_sectors, inner)`` / ``v_values`` return operand values at
@@ -398,13 +406,13 @@ def sample_contract(sub, su: Sym, sv: Sym, u_values, v_values, w_full_positions)
     the N in-block indices).  Each term's factors are looked up through the
     conservation rule, so disallowed entries contribute exactly zero; nothing
     else about the symmetry is used.  ``w_full_positions`` is an int array of
-    shape (S, order_W).
+    shape (S, order_W); ``dtype`` is float64 or complex128.
     """
     tu, tv, tw, I, K, J = check_operands(sub, su, sv)
     kdims = [su.group.size * su.dims[tu.index(k)] for k in K]
     grids = np.meshgrid(*[np.arange(d, dtype=np.int64) for d in kdims], indexing="ij")
     kfull = {k: gr.ravel() for k, gr in zip(K, grids)}
-    out = np.zeros(len(w_full_positions), dtype=np.float64)
+    out = np.zeros(len(w_full_positions), dtype=dtype)
     for s, pos in enumerate(np.asarray(w_full_positions, dtype=np.int64)):
         wfull = {m: int(x) for m, x in zip(tw, pos)}
 
@@ -413,7 +421,7 @@ def sample_contract(sub, su: Sym, sv: Sym, u_values, v_values, w_full_positions)
             secs = [x // n for x, n in zip(full, sym.dims)]
             inner = [x % n for x, n in zip(full, sym.dims)]
             ok = _vector_allowed(sym, secs)
-            vals = np.zeros(ok.shape, dtype=np.float64)
+            vals = np.zeros(ok.shape, dtype=dtype)
             idx = np.nonzero(ok)[0]
             if idx.size:
                 vals[idx] = fn([x[idx] for x in secs[:-1]], [x[idx] for x in inner])
@@ -421,7 +429,7 @@ def sample_contract(sub, su: Sym, sv: Sym, u_values, v_values, w_full_positions)
 
         uv = gather(tu, su, u_values)
         vv = gather(tv, sv, v_values)
-        out[s] = float(np.dot(uv, vv))
+        out[s] = np.dot(uv, vv)
     return out
 
 
@@ -445,7 +453,7 @@ def contract_bruteforce(sub, Ru, su: Sym, Rv, sv: Sym):
     for t, sym in ((tu, su), (tv, sv)):
         for p, m in enumerate(t):
             size[m] = sym.group.size * sym.dims[p]
-    Wf = np.zeros(tuple(size[m] for m in tw), dtype=np.float64)
+    Wf = np.zeros(tuple(size[m] for m in tw), dtype=_ftype(Ru, Rv))
     for wi in itertools.product(*[range(size[m]) for m in tw]):
         idx = dict(zip(tw, wi))
         acc = 0.0
@@ -491,7 +499,7 @@ def _full_sector_form(R, sym: Sym):
     letters = _letters(2 * N)
     S, inner = letters[:N], letters[N:]
     return np.einsum(f"{''.join(S[:-1])}{''.join(inner)},{''.join(S)}->{''.join(S)}{''.join(inner)}",
-                     np.asarray(R, dtype=np.float64), Dt)
+                     np.asarray(R, dtype=_ftype(R)), Dt)
 
 
 def _letters(n, skip=""):

@@ -640,3 +640,44 @@ def test_u1_emulation_needs_one_label_per_charge():
     T = U1.dense_u1(rng, [1, -1], 0, [0, 0], [3, 3], [1, 1])
     with pytest.raises(Exception):
         U1.embed(T, [1, -1], 0, [0, 0], [3, 3], [1, 1], 2)
+
+
+# ---------------------------------------------------------------------------
+# Complex tensors (Sec. 2.2 defines tensors over R or C).  Pins: the complex
+# contraction is the bilinear combination of four real ones (checked against
+# the real forms pinned above), np.einsum on the expanded complex operands
+# agrees, and Alg. 2 with dense deltas agrees.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("orders,s,t,v", [((3,), 1, 1, 1), ((4,), 2, 1, 2), ((2, 3), 1, 2, 1), ((5,), 2, 2, 1),
+                                          ((4,), 1, 1, 0), ((3,), 0, 2, 1)])
+def test_complex_contraction_is_four_real_ones(orders, s, t, v):
+    rng = np.random.default_rng(abs(hash(("complex", orders, s, t, v))) % 2 ** 31)
+    for _ in range(2):
+        sub, _, su, _, sv = _random_case(rng, orders, s, t, v, nmax=3)
+        Ur, Ui = rng.standard_normal(su.reduced_shape()), rng.standard_normal(su.reduced_shape())
+        Vr, Vi = rng.standard_normal(sv.reduced_shape()), rng.standard_normal(sv.reduced_shape())
+        real = lambda a, b: O.contract_blocks(sub, a, su, b, sv)[0]  # noqa: E731
+        ref = (real(Ur, Vr) - real(Ui, Vi)) + 1j * (real(Ur, Vi) + real(Ui, Vr))
+        U, V = Ur + 1j * Ui, Vr + 1j * Vi
+        scale = max(1.0, np.abs(ref).max())
+        for form in (O.contract_blocks, O.contract_dense, O.contract_irrep_aligned):
+            Rw, sw = form(sub, U, su, V, sv)[:2]
+            assert np.iscomplexobj(Rw)
+            np.testing.assert_allclose(Rw, ref, rtol=0, atol=1e-12 * scale)
+        Wd = np.einsum(sub, O.expand(U, su), O.expand(V, sv))
+        np.testing.assert_allclose(O.expand(ref, O.output_symmetry(sub, su, sv)), Wd, rtol=0, atol=1e-12 * scale)
+
+
+def test_complex_bruteforce_and_samples_tiny():
+    rng = np.random.default_rng(31)
+    sub, _, su, _, sv = _random_case(rng, (3,), 1, 1, 1, nmax=2)
+    U = rng.standard_normal(su.reduced_shape()) + 1j * rng.standard_normal(su.reduced_shape())
+    V = rng.standard_normal(sv.reduced_shape()) + 1j * rng.standard_normal(sv.reduced_shape())
+    Rb, sw, ok = O.contract_bruteforce(sub, U, su, V, sv)
+    assert ok
+    np.testing.assert_allclose(Rb, O.contract_blocks(sub, U, su, V, sv)[0], rtol=0, atol=1e-12)
+    full = O.expand(Rb, sw)
+    pos = np.array(list(itertools.product(*[range(d) for d in full.shape]))[:20])
+    got = O.sample_contract(sub, su, sv, O.reduced_value_fn(U, su), O.reduced_value_fn(V, sv), pos,
+                            dtype=np.complex128)
+    np.testing.assert_allclose(got, full[tuple(pos.T)], rtol=0, atol=1e-12)
