@@ -155,21 +155,26 @@ def cold_and_copy(P, st, u, v, w, ws, reps=5):
     return sorted(times)[len(times) // 2], copy_gbs
 
 
-def chain_flops(wl, compute):
-    """Algorithmic flops of a workload's contraction chain (host-only planning)."""
+def chain_flops(wl, compute, cplx=False):
+    """Algorithmic flops of a workload's contraction chain (host-only planning); complex
+    operands count 8 real flops per complex multiply-add."""
     from paper_2007_08056_amd import _lib as L
+    dt = L.SYMT_C128 if cplx else L.SYMT_F64
     total = 0.0
     for st in wl.steps:
         ou, ov = wl.operands[st.u], wl.operands[st.v]
         info = L.plan(st.einsum, L.make_group(wl.group),
-                      L.TensorDesc(ou.signs, ou.charge, ou.dims, L.SYMT_F64, None),
-                      L.TensorDesc(ov.signs, ov.charge, ov.dims, L.SYMT_F64, None), None, L.COMPUTE[compute])
+                      L.TensorDesc(ou.signs, ou.charge, ou.dims, dt, None),
+                      L.TensorDesc(ov.signs, ov.charge, ov.dims, dt, None), None, L.COMPUTE[compute])
         total += info.flops
     return total
 
 
-def time_workload(P, SG, wl, compute, steps, warmup, grad=False):
+def time_workload(P, SG, wl, compute, steps, warmup, grad=False, cplx=False):
     """ms per step and effective TFLOP/s of a workload's contraction chain (optionally fwd+bwd).
+
+    cplx: complex operands (storage complex128 for f64, complex64 for f32), the
+    imaginary parts from a second seeded fill of the same distribution.
 
     With grad, the backward of every step is two contractions of the forward's
     size (dU and dV), so the step does three times the forward's flops.
@@ -183,10 +188,13 @@ def time_workload(P, SG, wl, compute, steps, warmup, grad=False):
     for name in wl.inputs:
         op = wl.operands[name]
         d = SG.device_input(wl, name, dtype=dt, device="cuda:0")
+        if cplx:
+            im = SG.fill_(torch.empty_like(d), wl.seed, op.tensor_id + 1000, op.dist, op.scale)
+            d = torch.complex(d, im)
         if grad and name != "R":
             d.requires_grad_(True)
         t[name] = P.SymTensor(d, op.signs, op.charge, wl.group)
-    flops = chain_flops(wl, compute) * (3.0 if grad else 1.0)
+    flops = chain_flops(wl, compute, cplx) * (3.0 if grad else 1.0)
 
     def step():
         cur = dict(t)
@@ -321,16 +329,19 @@ def main():
     if args.all:
         import synth as S
         table = {}
-        for name, computes, grad in (("plain_z4", ("f64",), False), ("ccd_ladder_z8", ("f32", "bf16x3"), False),
-                                     ("mps_env_z2z3", ("f64", "f32", "bf16x3"), False),
-                                     ("ccd_ladder_z16", ("f64", "f32", "bf16x3"), False),
-                                     ("mps_env_grad", ("f64", "f32"), False),
-                                     ("mps_env_grad", ("f64", "f32"), True)):
+        for name, computes, grad, cplx in (("plain_z4", ("f64",), False, False),
+                                           ("ccd_ladder_z8", ("f32", "bf16x3"), False, False),
+                                           ("mps_env_z2z3", ("f64", "f32", "bf16x3"), False, False),
+                                           ("ccd_ladder_z16", ("f64", "f32", "bf16x3"), False, False),
+                                           ("mps_env_grad", ("f64", "f32"), False, False),
+                                           ("mps_env_grad", ("f64", "f32"), True, False),
+                                           ("ccd_ladder_z8", ("f64", "f32"), False, True),
+                                           ("mps_env_z2z3", ("f64", "f32"), False, True)):
             wlx = S.configs.get(name)
             for c in computes:
                 n_steps = 3 if name == "ccd_ladder_z16" else 10
-                r = time_workload(P, SG, wlx, c, n_steps, 2, grad)
-                key = f"{name}/{c}" + ("/fwd+bwd" if grad else "")
+                r = time_workload(P, SG, wlx, c, n_steps, 2, grad, cplx)
+                key = f"{name}/{c}" + ("/complex" if cplx else "") + ("/fwd+bwd" if grad else "")
                 table[key] = r
                 print(f"{key}: {r['ms_per_step']:.3f} ms, {r['tflops']:.1f} TFLOP/s", file=sys.stderr, flush=True)
                 torch.cuda.empty_cache()

@@ -54,6 +54,18 @@
  *   nearest even; the product is hi*hi + hi*lo + lo*hi with binary32
  *   accumulation (two accumulators) and a binary64 sum of the two at the end.
  *
+ * COMPLEX OPERANDS (Sec. 2.2 allows tensors over C).  u, v and w are all
+ * complex (SYMT_C128 / SYMT_C64) or all real, else SYMT_EDTYPE; compute F64
+ * or F32 (BF16X3: SYMT_EDTYPE).  The product runs on the real representation
+ * of C: with Kd and N the complex extents,
+ *   U_al  real (|G|, M, 2 Kd): the (re, im) pair of column k at 2k, 2k + 1;
+ *   V_al  real (|G|, 2 Kd, 2 N): row 2k holds (re, im) of V's row k, row
+ *         2k + 1 holds (-im, re), pairs at columns 2n, 2n + 1;
+ *   W_al  real (|G|, M, 2 N): (re, im) of W's column n at 2n, 2n + 1;
+ * so the real product U_al V_al is the complex one.  symt_plan_info reports
+ * this real product (k = 2 Kd, n = 2 N, flops = 8 |G| M Kd N).  No fused
+ * product for complex operands.
+ *
  * EMPTY MODE GROUPS (s, t or v = 0; Sec. 2.1's deltas with an empty sum).  One
  * delta then fixes Q on its own: v = 0 (an outer product) gives Q = 0 and
  * sigma is reported as -1; s = 0 gives Q = Z^U; t = 0 gives Q = sigma Z^V.
@@ -115,7 +127,8 @@ enum {
   SYMT_EHIP = -8           /* HIP runtime error (launch, device query) */
 };
 
-typedef enum { SYMT_F64 = 0, SYMT_F32 = 1 } symt_dtype;
+/* Complex dtypes hold (re, im) pairs, interleaved; see COMPLEX OPERANDS. */
+typedef enum { SYMT_F64 = 0, SYMT_F32 = 1, SYMT_C128 = 2, SYMT_C64 = 3 } symt_dtype;
 typedef enum {
   SYMT_COMPUTE_F64 = 0,    /* binary64 MFMA products */
   SYMT_COMPUTE_F32 = 1,    /* binary32 MFMA products, binary32 accumulation */
@@ -164,7 +177,7 @@ typedef struct {
   int32_t s, t, v;                 /* modes of I, J, K */
   int32_t sigma;                   /* c^V_k / c^U_k */
   int32_t group_size;              /* |G| = batch of the aligned product */
-  int64_t m, k, n;                 /* aligned product shape per Q */
+  int64_t m, k, n;                 /* aligned product shape per Q (the real product for complex) */
   int64_t elems_u, elems_v, elems_w;
   double flops;                    /* 2 |G| m k n (2 m k n with Q pinned): allowed blocks only */
   size_t bytes_u_al, bytes_v_al, bytes_w_al;  /* whole aligned forms (all |G| slices) in this
@@ -209,7 +222,8 @@ int symtensor_workspace_size(const char* einsum, const symt_group* group, const 
  * w->data must not overlap u->data, v->data or the workspace (SYMT_EALIAS).
  * Storage dtypes: SYMT_COMPUTE_F64 takes any mix of F64/F32 operands
  * (converted exactly to binary64); SYMT_COMPUTE_F32 and BF16X3 take any mix,
- * F64 inputs being rounded to binary32 first. */
+ * F64 inputs being rounded to binary32 first.  Complex operands likewise mix
+ * C128 and C64 under F64 and F32 (see COMPLEX OPERANDS). */
 int symtensor_contract(symt_ctx* ctx, const char* einsum, const symt_group* group,
                        const symt_tensor* u, const symt_tensor* v, const symt_tensor* w,
                        int32_t compute, void* workspace, size_t workspace_bytes, void* stream);

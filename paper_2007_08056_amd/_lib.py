@@ -28,6 +28,8 @@ SYMT_EHIP = -8
 
 SYMT_F64 = 0
 SYMT_F32 = 1
+SYMT_C128 = 2
+SYMT_C64 = 3
 COMPUTE = {"f64": 0, "f32": 1, "bf16x3": 2}
 SYMT_FLAG_STEPS = 0x100
 

@@ -123,8 +123,8 @@ int read_operand(const symt_tensor* t, const GroupDesc& g, OperandDesc* o, const
   if (t->charge < 0 || t->charge >= g.size)
     return fail(err, SYMT_ESYM, "operand %s: charge outside [0,|G|)", name);
   o->charge = t->charge;
-  if (t->dtype != SYMT_F64 && t->dtype != SYMT_F32)
-    return fail(err, SYMT_EDTYPE, "operand %s: dtype must be SYMT_F64 or SYMT_F32", name);
+  if (t->dtype < SYMT_F64 || t->dtype > SYMT_C64)
+    return fail(err, SYMT_EDTYPE, "operand %s: dtype must be SYMT_F64, F32, C128 or C64", name);
   o->dtype = t->dtype;
   o->data = t->data;
   int64_t e = 1;
@@ -206,6 +206,11 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   // ---- operands
   if ((rc = read_operand(u, p->g, &p->U, "u", err))) return rc;
   if ((rc = read_operand(v, p->g, &p->V, "v", err))) return rc;
+  p->cplx = is_complex(p->U.dtype);
+  if (is_complex(p->V.dtype) != p->cplx)
+    return fail(err, SYMT_EDTYPE, "u and v must both be complex or both be real");
+  if (p->cplx && compute == SYMT_COMPUTE_BF16X3)
+    return fail(err, SYMT_EDTYPE, "complex operands take compute F64 or F32");
   if ((rc = read_charges(u, p->g, &p->chg[0], "u", err))) return rc;
   if ((rc = read_charges(v, p->g, &p->chg[1], "v", err))) return rc;
   if (p->U.n != static_cast<int>(tu.size()) || p->V.n != static_cast<int>(tv.size()))
@@ -273,6 +278,8 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   p->has_w = (w != nullptr);
   if (w) {
     if ((rc = read_operand(w, p->g, &p->W, "w", err))) return rc;
+    if (is_complex(p->W.dtype) != p->cplx)
+      return fail(err, SYMT_EDTYPE, "w must be complex exactly when u and v are");
     if (p->W.n != static_cast<int>(tw.size()))
       return fail(err, SYMT_EINVAL, "output order differs from its einsum term");
     for (size_t m = 0; m < tw.size(); ++m) {
@@ -305,7 +312,7 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
       if (!mul_ok(e, p->W.dims[m], &e)) return fail(err, SYMT_EINVAL, "output size overflows");
     }
     p->W.charge = p->w_charge;
-    p->W.dtype = SYMT_F64;
+    p->W.dtype = p->cplx ? SYMT_C128 : SYMT_F64;
     p->W.elems = e;
   }
   p->chg[2] = w_chg;
@@ -322,17 +329,20 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   for (int i = 1; i < p->v; ++i) mul_ok(gv, p->g.size, &gv);
   if (!mul_ok(gs, p->nI, &p->M) || !mul_ok(gv, p->nK, &p->Kd) || !mul_ok(gt, p->nJ, &p->N))
     return fail(err, SYMT_EINVAL, "aligned shape overflows");
-  if (p->M > INT32_MAX || p->N > INT32_MAX || p->Kd > INT32_MAX)
+  // complex: the real representation doubles the contracted and output columns
+  p->gk = p->cplx ? 2 * p->Kd : p->Kd;
+  p->gn = p->cplx ? 2 * p->N : p->N;
+  if (p->M > INT32_MAX || p->gn > INT32_MAX || p->gk > INT32_MAX)
     return fail(err, SYMT_EUNSUPPORTED, "aligned matrix dimension above 2^31-1");
-  p->flops = 2.0 * (p->q_pin >= 0 ? 1 : p->g.size) * static_cast<double>(p->M) * static_cast<double>(p->Kd) *
-             static_cast<double>(p->N);
+  p->flops = 2.0 * (p->q_pin >= 0 ? 1 : p->g.size) * static_cast<double>(p->M) * static_cast<double>(p->gk) *
+             static_cast<double>(p->gn);
 
   // ---- buffer sizes for the compute mode.  The aligned forms hold |G| M K,
-  // |G| K N and |G| M N elements; with Q pinned the contraction keeps only the
-  // one nonzero slice of each in its workspace.
+  // |G| K N and |G| M N reals (K and N of the real product); with Q pinned the
+  // contraction keeps only the one nonzero slice of each in its workspace.
   int64_t au = 0, av = 0, aw = 0;
-  if (!mul_ok(p->M, p->Kd, &au) || !mul_ok(au, p->g.size, &au) || !mul_ok(p->Kd, p->N, &av) ||
-      !mul_ok(av, p->g.size, &av) || !mul_ok(p->M, p->N, &aw) || !mul_ok(aw, p->g.size, &aw))
+  if (!mul_ok(p->M, p->gk, &au) || !mul_ok(au, p->g.size, &au) || !mul_ok(p->gk, p->gn, &av) ||
+      !mul_ok(av, p->g.size, &av) || !mul_ok(p->M, p->gn, &aw) || !mul_ok(aw, p->g.size, &aw))
     return fail(err, SYMT_EINVAL, "aligned form size overflows");
   const size_t ea = compute == SYMT_COMPUTE_F64 ? 8 : 4, ec = compute == SYMT_COMPUTE_F32 ? 4 : 8;
   p->bytes_u_al = ea * static_cast<size_t>(au);
@@ -351,7 +361,7 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   bool trailing_k = true;
   for (int i = 0; i < p->v; ++i) trailing_k = trailing_k && p->posK_u[i] == p->U.n - p->v + i;
   const int vw = compute == SYMT_COMPUTE_F64 ? 2 : 4;
-  p->fused = !force_steps && p->q_pin < 0 && compute != SYMT_COMPUTE_BF16X3 && p->U.dtype == want &&
+  p->fused = !force_steps && !p->cplx && p->q_pin < 0 && compute != SYMT_COMPUTE_BF16X3 && p->U.dtype == want &&
              (!w || p->W.dtype == want) && trailing_k && p->nK % kFpBK == 0 && p->N % vw == 0 &&
              p->M > 0 && p->N > 0 && p->Kd > 0 && p->U.elems > 0;
   if (p->fused) {
@@ -364,8 +374,8 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
     p->bytes_charges = 4 * 2 * static_cast<size_t>(p->g.size) * (p->U.n + p->V.n + p->W.n);
   }
   // Room for stream-K pieces when the model would pick it on 16-byte aligned operands.
-  if (compute != SYMT_COMPUTE_BF16X3 && p->M > 0 && p->N > 0 && p->Kd > 0) {
-    const GemmChoice gc = choose_fp_gemm(p->q_pin >= 0 ? 1 : p->g.size, p->M, p->N, p->Kd,
+  if (compute != SYMT_COMPUTE_BF16X3 && p->M > 0 && p->gn > 0 && p->gk > 0) {
+    const GemmChoice gc = choose_fp_gemm(p->q_pin >= 0 ? 1 : p->g.size, p->M, p->gn, p->gk,
                                          compute == SYMT_COMPUTE_F64 ? 8 : 4, true);
     p->bytes_partial = gc.partial_bytes;
     p->workspace += round_up(p->bytes_partial, 256);
@@ -558,43 +568,50 @@ XformParams make_xform(const Plan& p, int operand, bool to_aligned, int in_bytes
   // contraction's workspace copy keeps slice q_pin of every form.
   x.q_pin = slice_only || pinned_form(p, operand) ? p.q_pin : -1;
   x.nblocks = x.gpow_row * x.gpow_col * (x.q_pin >= 0 ? 1 : G);
-  x.blk_elems = 1;
+  // Complex operands move as reals: each element is a (re, im) pair, one more
+  // in-block dim (std stride 1) that sits innermost among the aligned columns;
+  // V's complex rows go to every other real row (the odd ones are filled from
+  // them: the real representation of C).
+  const int cm = p.cplx ? 2 : 1;
+  const int row_mult = p.cplx && operand == 1 ? 2 : 1;
+  x.blk_elems = cm;
   for (int m = 0; m < X.n; ++m) x.blk_elems *= X.dims[m];
   int64_t nR = 1, nC = 1;
   for (int i = 0; i < R.count; ++i) nR *= X.dims[R.pos[i]];
   for (int i = 0; i < C.count; ++i) nC *= X.dims[C.pos[i]];
-  const int64_t rows_tot = x.gpow_row * nR, cols_tot = x.gpow_col * nC;
+  const int64_t rows_tot = x.gpow_row * nR * row_mult, cols_tot = x.gpow_col * nC * cm;
   const AlignedLayout lay = aligned_layout(p.compute, operand);
   // one slice only (Q pinned, workspace copy): every block lands at Q offset 0
   const bool one_slice = slice_only && x.q_pin >= 0;
   x.q_stride = one_slice ? 0 : rows_tot * cols_tot;
   x.plane = (one_slice ? 1 : static_cast<int64_t>(G)) * rows_tot * cols_tot;
-  const int64_t row_unit = lay == kRowMajor ? cols_tot : 1;   // aligned stride of one row
-  const int64_t col_unit = lay == kRowMajor ? 1 : rows_tot;   // aligned stride of one column
-  x.rs_stride = nR * row_unit;
-  x.cs_stride = nC * col_unit;
+  const int64_t row_unit = lay == kRowMajor ? cols_tot : 1;   // aligned stride of one real row
+  const int64_t col_unit = lay == kRowMajor ? 1 : rows_tot;   // aligned stride of one real column
+  x.rs_stride = nR * row_mult * row_unit;
+  x.cs_stride = nC * cm * col_unit;
   x.to_aligned = to_aligned ? 1 : 0;
 
-  // Inner dims in aligned order with both strides.
+  // Inner dims in aligned order with both strides (in reals).
   int64_t std_stride[kMaxOrder];
   {
-    int64_t acc = 1;
+    int64_t acc = cm;
     for (int m = X.n - 1; m >= 0; --m) { std_stride[m] = acc; acc *= X.dims[m]; }
   }
   int nd = 0;
   int64_t size[kMaxDims], s_std[kMaxDims], s_al[kMaxDims];
   {
-    int64_t acc = 1;
+    int64_t acc = row_mult;
     int64_t tmp_al[kMaxOrder];
     for (int i = R.count - 1; i >= 0; --i) { tmp_al[i] = acc * row_unit; acc *= X.dims[R.pos[i]]; }
     for (int i = 0; i < R.count; ++i) {
       size[nd] = X.dims[R.pos[i]]; s_std[nd] = std_stride[R.pos[i]]; s_al[nd] = tmp_al[i]; ++nd;
     }
-    acc = 1;
+    acc = cm;
     for (int i = C.count - 1; i >= 0; --i) { tmp_al[i] = acc * col_unit; acc *= X.dims[C.pos[i]]; }
     for (int i = 0; i < C.count; ++i) {
       size[nd] = X.dims[C.pos[i]]; s_std[nd] = std_stride[C.pos[i]]; s_al[nd] = tmp_al[i]; ++nd;
     }
+    if (p.cplx) { size[nd] = 2; s_std[nd] = 1; s_al[nd] = col_unit; ++nd; }
   }
   // Drop unit dims, then merge neighbours that nest the same way in both layouts.
   int md = 0;

@@ -138,6 +138,8 @@ struct Plan {
   int32_t posI_w[kMaxOrder], posJ_w[kMaxOrder];
   int64_t nI = 1, nK = 1, nJ = 1;
   int64_t M = 0, Kd = 0, N = 0;
+  bool cplx = false;                // complex operands: the product runs on C's real representation
+  int64_t gk = 0, gn = 0;           // the real product's K and N (2 Kd, 2 N when complex)
   OperandDesc U, V, W;
   bool has_w = false;
   int32_t w_sign[kMaxOrder];        // derived
@@ -198,6 +200,10 @@ XformParams make_xform(const Plan& p, int operand, bool to_aligned, int in_elem_
 
 // Row (rows = true) or column offset table of operand 0 (U), 1 (V) or 2 (W).
 OffsetParams make_offsets(const Plan& p, int operand, bool rows);
+
+// Complex storage dtype, and bytes of one real component of an element.
+inline bool is_complex(int32_t dtype) { return dtype == SYMT_C128 || dtype == SYMT_C64; }
+inline int real_bytes(int32_t dtype) { return dtype == SYMT_F64 || dtype == SYMT_C128 ? 8 : 4; }
 
 // Aligned layout used for an operand under a compute mode.
 AlignedLayout aligned_layout(int32_t compute, int operand);

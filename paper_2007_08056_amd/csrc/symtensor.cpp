@@ -21,6 +21,8 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
 int launch_offsets(const OffsetBatch& batch, hipStream_t stream, std::string* err);
 int launch_put_i32(int32_t* dst, const int32_t* src, int64_t n, hipStream_t stream, std::string* err);
 int launch_zero(void* ptr, size_t bytes, hipStream_t stream, std::string* err);
+int launch_cplx_rows(void* v, bool f64, int64_t slices, int64_t rows, int64_t pairs, hipStream_t stream,
+                     std::string* err);
 }  // namespace symt
 
 using symt::Plan;
@@ -43,7 +45,7 @@ int ctx_fail(symt_ctx* ctx, int code, const std::string& msg) {
   return code;
 }
 
-size_t elem_bytes(int dtype) { return dtype == SYMT_F64 ? 8 : 4; }
+size_t elem_bytes(int dtype) { return dtype == SYMT_C128 ? 16 : dtype == SYMT_F64 || dtype == SYMT_C64 ? 8 : 4; }
 
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
   if (!a || !b || na == 0 || nb == 0) return false;
@@ -96,13 +98,19 @@ int do_align(symt_ctx* ctx, const Plan& p, int operand, void* dst, hipStream_t s
   const symt::OperandDesc& X = operand == 0 ? p.U : p.V;
   if (X.elems == 0) return SYMT_OK;
   const int kind = out_kind_aligned(p.compute);
-  symt::XformParams x = symt::make_xform(p, operand, true, static_cast<int>(elem_bytes(X.dtype)),
+  symt::XformParams x = symt::make_xform(p, operand, true, symt::real_bytes(X.dtype),
                                          aligned_elem_bytes(p.compute), kind == 2, slice_only);
   x.chg = chg;
   if (!aligned16(X.data) || !aligned16(dst)) x.vec = 1;
   std::string err;
   const int rc = timed(ctx, operand, s, [&] {
-    return symt::launch_xform(x, X.dtype == SYMT_F64, kind, X.data, dst, s, &err);
+    int r = symt::launch_xform(x, symt::real_bytes(X.dtype) == 8, kind, X.data, dst, s, &err);
+    if (r == SYMT_OK && p.cplx && operand == 1) {
+      // complex V: the odd real rows of the real representation of C
+      const int64_t slices = slice_only && p.q_pin >= 0 ? 1 : p.g.size;
+      r = symt::launch_cplx_rows(dst, p.compute == SYMT_COMPUTE_F64, slices, p.Kd, p.N, s, &err);
+    }
+    return r;
   });
   return rc ? ctx_fail(ctx, rc, err) : SYMT_OK;
 }
@@ -111,8 +119,8 @@ int do_unalign(symt_ctx* ctx, const Plan& p, const void* wal, hipStream_t s, boo
                const int32_t* chg = nullptr) {
   if (p.W.elems == 0) return SYMT_OK;
   const bool in_f64 = p.compute != SYMT_COMPUTE_F32;
-  symt::XformParams x = symt::make_xform(p, 2, false, in_f64 ? 8 : 4,
-                                         static_cast<int>(elem_bytes(p.W.dtype)), false, slice_only);
+  symt::XformParams x = symt::make_xform(p, 2, false, in_f64 ? 8 : 4, symt::real_bytes(p.W.dtype), false,
+                                         slice_only);
   x.chg = chg;
   if (!aligned16(wal) || !aligned16(p.W.data)) x.vec = 1;
   std::string err;
@@ -122,7 +130,7 @@ int do_unalign(symt_ctx* ctx, const Plan& p, const void* wal, hipStream_t s, boo
       const int r = symt::launch_zero(p.W.data, static_cast<size_t>(p.W.elems) * elem_bytes(p.W.dtype), s, &err);
       if (r) return r;
     }
-    return symt::launch_xform(x, in_f64, p.W.dtype == SYMT_F64 ? 0 : 1, wal, p.W.data, s, &err);
+    return symt::launch_xform(x, in_f64, symt::real_bytes(p.W.dtype) == 8 ? 0 : 1, wal, p.W.data, s, &err);
   });
   return rc ? ctx_fail(ctx, rc, err) : SYMT_OK;
 }
@@ -237,8 +245,8 @@ int symtensor_plan(const char* einsum, const symt_group* group, const symt_tenso
   info->sigma = p.sigma;
   info->group_size = p.g.size;
   info->m = p.M;
-  info->k = p.Kd;
-  info->n = p.N;
+  info->k = p.gk;
+  info->n = p.gn;
   info->elems_u = p.U.elems;
   info->elems_v = p.V.elems;
   info->elems_w = p.W.elems;
@@ -284,7 +292,7 @@ int symtensor_contract(symt_ctx* ctx, const char* einsum, const symt_group* grou
       overlaps(p.W.data, wb, p.V.data, static_cast<size_t>(p.V.elems) * elem_bytes(p.V.dtype)) ||
       overlaps(p.W.data, wb, workspace, p.workspace))
     return ctx_fail(ctx, SYMT_EALIAS, "output overlaps an input or the workspace");
-  if (p.compute == SYMT_COMPUTE_BF16X3 && p.Kd % 8 != 0)
+  if (p.compute == SYMT_COMPUTE_BF16X3 && p.gk % 8 != 0)
     return ctx_fail(ctx, SYMT_EUNSUPPORTED,
                     "split-bf16 product needs the aligned contracted extent to be a multiple of 8");
   if (p.workspace > 0 && !aligned16(workspace))
@@ -313,10 +321,10 @@ int symtensor_contract(symt_ctx* ctx, const char* einsum, const symt_group* grou
   if ((rc = do_align(ctx, p, 1, val, s, true, chg[1]))) return rc;
   if (p.q_pin >= 0) {
     // the workspace holds slice q_pin alone: one product of it
-    if ((rc = do_gemm(ctx, p.compute, 1, p.M, p.Kd, p.N, ual, val, wal, s, nullptr,
-                      p.bytes_partial ? part : nullptr, p.bytes_partial, p.M * p.Kd, p.Kd * p.N)))
+    if ((rc = do_gemm(ctx, p.compute, 1, p.M, p.gk, p.gn, ual, val, wal, s, nullptr,
+                      p.bytes_partial ? part : nullptr, p.bytes_partial, p.M * p.gk, p.gk * p.gn)))
       return rc;
-  } else if ((rc = do_gemm(ctx, p.compute, p.g.size, p.M, p.Kd, p.N, ual, val, wal, s, nullptr,
+  } else if ((rc = do_gemm(ctx, p.compute, p.g.size, p.M, p.gk, p.gn, ual, val, wal, s, nullptr,
                            p.bytes_partial ? part : nullptr, p.bytes_partial))) {
     return rc;
   }

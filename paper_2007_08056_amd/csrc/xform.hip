@@ -223,6 +223,24 @@ __global__ __launch_bounds__(256) void k_offsets(const OffsetBatch b) {
   }
 }
 
+// Odd rows of a complex V_al in the real representation of C: in every slice,
+// real row 2k + 1 holds (-im, re) of the (re, im) pairs in row 2k.  One thread
+// per pair; `rows` complex rows and `pairs` complex columns per slice.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cplx_rows(T* __restrict__ v, int64_t slices, int64_t rows,
+                                                   int64_t pairs) {
+  const int64_t total = slices * rows * pairs;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int64_t c = i % pairs;
+    const int64_t r = i / pairs;                  // slice * rows + row
+    T* even = v + (2 * r) * (2 * pairs) + 2 * c;
+    const T re = even[0], im = even[1];
+    even[2 * pairs] = -im;
+    even[2 * pairs + 1] = re;
+  }
+}
+
 // A few KB of host data (charge tables) written into device memory from kernel
 // arguments: stream-ordered, with no host buffer that must outlive the call.
 struct I32Chunk {
@@ -246,6 +264,26 @@ int launch_put_i32(int32_t* dst, const int32_t* src, int64_t n, hipStream_t stre
       if (err) *err = std::string("charge table upload: ") + hipGetErrorString(e);
       return SYMT_EHIP;
     }
+  }
+  return SYMT_OK;
+}
+
+int launch_cplx_rows(void* v, bool f64, int64_t slices, int64_t rows, int64_t pairs, hipStream_t stream,
+                     std::string* err) {
+  const int64_t total = slices * rows * pairs;
+  if (total == 0) return SYMT_OK;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  if (f64)
+    hipLaunchKernelGGL(k_cplx_rows<double>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream,
+                       static_cast<double*>(v), slices, rows, pairs);
+  else
+    hipLaunchKernelGGL(k_cplx_rows<float>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream,
+                       static_cast<float*>(v), slices, rows, pairs);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    if (err) *err = std::string("complex rows launch: ") + hipGetErrorString(e);
+    return SYMT_EHIP;
   }
   return SYMT_OK;
 }

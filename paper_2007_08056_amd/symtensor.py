@@ -22,7 +22,8 @@ import torch
 
 from . import _lib as L
 
-_DTYPE_CODE = {torch.float64: L.SYMT_F64, torch.float32: L.SYMT_F32}
+_DTYPE_CODE = {torch.float64: L.SYMT_F64, torch.float32: L.SYMT_F32,
+               torch.complex128: L.SYMT_C128, torch.complex64: L.SYMT_C64}
 
 
 def _group_tuple(group):
@@ -67,7 +68,7 @@ class SymTensor:
         if self.data.dim() != 2 * n - 1 or any(int(s) != G for s in self.data.shape[: n - 1]):
             raise ValueError(f"reduced form must have shape [{G}]*{n - 1} + dims, got {tuple(self.data.shape)}")
         if self.data.dtype not in _DTYPE_CODE:
-            raise TypeError("reduced form must be float64 or float32")
+            raise TypeError("reduced form must be float64, float32, complex128 or complex64")
         self.charge = int(self.charge) % G
         self.mode_charges = _norm_charges(self.mode_charges, n, G)
 
@@ -185,16 +186,19 @@ class _Contract(torch.autograd.Function):
         ud, vd = ctx.saved_tensors
         tu, tv, tw = _swap(subscripts)
         dW = SymTensor(gw.contiguous().to(ud.dtype), *meta_w[:4])
+        # complex operands: gradients with respect to the conjugate (Wirtinger),
+        # so the other factor enters conjugated
+        conj = (lambda t: t.conj().resolve_conj()) if ud.is_complex() else (lambda t: t)
         gu = gv = None
         if ctx.needs_input_grad[5]:
             # dU[I,K] = sum_J dW[I,J] V[K,J]; the derived rule of (dW, V) is U's.
             out = SymTensor(torch.empty_like(ud), *meta_u)
-            contract_into(f"{tw},{tv}->{tu}", dW, SymTensor(vd, *meta_v), out, compute)
+            contract_into(f"{tw},{tv}->{tu}", dW, SymTensor(conj(vd), *meta_v), out, compute)
             gu = out.data
         if ctx.needs_input_grad[6]:
             # dV[K,J] = sum_I U[I,K] dW[I,J]; the derived rule of (U, dW) is V's up to a global sign.
             out = SymTensor(torch.empty_like(vd), *meta_v)
-            contract_into(f"{tu},{tw}->{tv}", SymTensor(ud, *meta_u), dW, out, compute)
+            contract_into(f"{tu},{tw}->{tv}", SymTensor(conj(ud), *meta_u), dW, out, compute)
             gv = out.data
         return None, None, None, None, None, gu, gv
 
@@ -227,6 +231,8 @@ def align(subscripts: str, u: SymTensor, v: SymTensor, operand: int, compute: st
 
     f64 / f32: a (|G|, M, K) or (|G|, K, N) tensor.  bf16x3: an int16 tensor of
     raw bf16 bits, (2, |G|, M, K) for u and (2, |G|, N, K) for v (hi plane first).
+    Complex operands: the real representation of C (include/symtensor.h,
+    COMPLEX OPERANDS), a real tensor with K and N doubled.
     `out`, if given, is a contiguous tensor of that shape and dtype, overwritten.
     """
     dev = u.data.device

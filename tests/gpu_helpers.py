@@ -81,8 +81,9 @@ def bf16_bits_to_f64(bits: np.ndarray) -> np.ndarray:
 
 
 def rel_err(got, ref) -> float:
-    got = np.asarray(got, dtype=np.float64)
-    ref = np.asarray(ref, dtype=np.float64)
+    dt = np.result_type(np.asarray(got).dtype, np.asarray(ref).dtype, np.float64)   # complex stays complex
+    got = np.asarray(got, dtype=dt)
+    ref = np.asarray(ref, dtype=dt)
     den = np.max(np.abs(ref)) if ref.size else 0.0
     return float(np.max(np.abs(got - ref)) / den) if den > 0 else float(np.max(np.abs(got - ref), initial=0.0))
 

@@ -260,3 +260,28 @@ def test_charge_tables_validation():
     assert _plan("ak,kb->ab", G, u, v, _cdesc(sig, info.w_charge, (2, 4), [a, b]))[0] == 0
     assert _plan("ak,kb->ab", G, u, v, _desc(sig, info.w_charge, (2, 4)))[0] == L.SYMT_ESYM
     assert _plan("ak,kb->ab", G, u, v, _cdesc(sig, info.w_charge, (2, 4), [b, a]))[0] == L.SYMT_ESYM
+
+
+def test_complex_planning():
+    G = 4
+    u = _desc("+-", 1, (3, 5), L.SYMT_C128)
+    v = _desc("+-", 2, (5, 6), L.SYMT_C64)
+    rc, info = _plan("ak,kb->ab", G, u, v)
+    assert rc == 0
+    # the real representation of C: K and N doubled, 8 real flops per complex multiply-add
+    assert (info.m, info.k, info.n) == (3, 10, 12)
+    assert info.flops == 8 * G * 3 * 5 * 6
+    assert info.bytes_u_al == 8 * G * 3 * 10 and info.bytes_v_al == 8 * G * 10 * 12
+    assert info.bytes_w_al == 8 * G * 3 * 12
+    assert info.fused == 0
+    rc32, info32 = _plan("ak,kb->ab", G, u, v, compute=1)
+    assert rc32 == 0 and info32.bytes_v_al == 4 * G * 10 * 12
+    # all complex or all real; no split-bf16 product for complex operands
+    assert _plan("ak,kb->ab", G, u, _desc("+-", 2, (5, 6)))[0] == L.SYMT_EDTYPE
+    assert _plan("ak,kb->ab", G, u, v, compute=2)[0] == L.SYMT_EDTYPE
+    sig = info.w_signs.decode()
+    assert _plan("ak,kb->ab", G, u, v, _desc(sig, info.w_charge, (3, 6), L.SYMT_C128))[0] == 0
+    assert _plan("ak,kb->ab", G, u, v, _desc(sig, info.w_charge, (3, 6)))[0] == L.SYMT_EDTYPE
+    assert _plan("ak,kb->ab", G, _desc("+-", 1, (3, 5)), _desc("+-", 2, (5, 6)),
+                 _desc(sig, info.w_charge, (3, 6), L.SYMT_C64))[0] == L.SYMT_EDTYPE
+    assert _plan("ak,kb->ab", G, _desc("+-", 1, (3, 5), 7), v)[0] == L.SYMT_EDTYPE

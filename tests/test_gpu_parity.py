@@ -622,3 +622,89 @@ def test_u1_emulation_vs_dense_u1_einsum(P, sub):
             phys, rest = U1.physical_part(O.expand(H.to_np(w.data), sw), c["Pw"], c["nw"])
             assert rest == 0.0, compute
             assert np.all(np.abs(phys - c["ref"]) <= H.bound_factor(compute, k) * absref + 1e-300), compute
+
+
+# ---------------------------------------------------------------------------
+# Complex operands (Sec. 2.2 allows tensors over C): the product runs on the
+# real representation of C.  Results against the complex oracle; the aligned
+# forms bit-exact against Alg. 2 with dense deltas (U_al and W_al are the
+# complex forms viewed as interleaved reals; V_al's even real rows hold V, its
+# odd rows i V); gradients against dense complex autograd on the CPU.
+# ---------------------------------------------------------------------------
+COMPLEX_CASES = [((4,), 1, 1, 1), ((3,), 2, 1, 2), ((2, 3), 1, 2, 1), ((5,), 2, 2, 1),
+                 ((4,), 1, 1, 0), ((3,), 0, 2, 1), ((3,), 2, 0, 1)]
+
+
+def _cplx(rng, shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+@pytest.mark.parametrize("orders,s,t,v", COMPLEX_CASES)
+def test_complex_contractions_vs_oracle(P, orders, s, t, v):
+    rng = np.random.default_rng(abs(hash(("cplx-gpu", orders, s, t, v))) % 2 ** 31)
+    for with_tables in (False, True):
+        sub, su, sv = H.random_case(rng, orders, s, t, v, nmax=5)
+        if with_tables:
+            su, sv = _with_tables(rng, sub, su, sv)
+        say(f"complex {sub} G={orders} tables={with_tables}")
+        Ru, Rv = _cplx(rng, su.reduced_shape()), _cplx(rng, sv.reduced_shape())
+        ref, sw = O.contract_blocks(sub, Ru, su, Rv, sv)
+        absref, _ = O.contract_blocks(sub, np.abs(Ru), su, np.abs(Rv), sv)
+        u, v_ = _sym_tensor(P, Ru, su, torch.complex128), _sym_tensor(P, Rv, sv, torch.complex128)
+        info = P.plan(sub, u, v_)
+        assert info.flops == 4 * O.flop_count(sub, su, sv)      # 8 real flops per complex multiply-add
+        k = info.k                                              # real terms per output component
+        for compute in ("f64", "f32"):
+            w = P.output_like(sub, u, v_)
+            assert w.data.dtype == torch.complex128
+            w.data.fill_(7.0 + 7.0j)
+            P.contract_into(sub, u, v_, w, compute)
+            got = H.to_np(w.data)
+            # each component is a real sum of 2 K terms bounded by |u||v| (Cauchy-Schwarz)
+            for part in (np.real, np.imag):
+                assert np.all(np.abs(part(got) - part(ref)) <= H.bound_factor(compute, k) * absref + 1e-300), compute
+            if compute == "f64":
+                assert H.rel_err(got, ref) <= 1e-12 or np.max(np.abs(ref)) == 0
+        with pytest.raises(Exception):
+            P.contract_into(sub, u, v_, P.output_like(sub, u, v_), "bf16x3")
+        if not with_tables:
+            Ual, Val = O.align_u(sub, Ru, su, sv), O.align_v(sub, Rv, su, sv)
+            bu = torch.full((Ual.shape[0], Ual.shape[1], 2 * Ual.shape[2]), float("nan"), dtype=torch.float64, device=DEV)
+            gu = H.to_np(P.align(sub, u, v_, 0, "f64", out=bu))
+            assert np.array_equal(gu.view(np.complex128), Ual)
+            bv = torch.full((Val.shape[0], 2 * Val.shape[1], 2 * Val.shape[2]), float("nan"), dtype=torch.float64,
+                            device=DEV)
+            gv = H.to_np(P.align(sub, u, v_, 1, "f64", out=bv))
+            assert np.array_equal(np.ascontiguousarray(gv[:, 0::2, :]).view(np.complex128), Val)
+            assert np.array_equal(np.ascontiguousarray(gv[:, 1::2, :]).view(np.complex128), 1j * Val)
+            Wal = np.matmul(Ual, Val)
+            ref_w, _ = O.unalign_w(sub, Wal, su, sv)
+            w = P.output_like(sub, u, v_)
+            w.data.fill_(3.0)
+            P.unalign(sub, u, v_, w, torch.from_numpy(np.ascontiguousarray(Wal).view(np.float64)).to(DEV), "f64")
+            assert np.array_equal(H.to_np(w.data), ref_w)
+
+
+@pytest.mark.parametrize("orders,s,t,v", [((3,), 1, 1, 1), ((2, 2), 2, 1, 1), ((4,), 1, 1, 0)])
+def test_complex_gradients_vs_dense_autograd(P, orders, s, t, v):
+    rng = np.random.default_rng(abs(hash(("cplx-grad", orders, s, t, v))) % 2 ** 31)
+    sub, su, sv = H.random_case(rng, orders, s, t, v, nmax=4)
+    say(f"complex gradient {sub} G={orders}")
+    Ru, Rv = _cplx(rng, su.reduced_shape()), _cplx(rng, sv.reduced_shape())
+    sw = O.output_symmetry(sub, su, sv)
+    Rr = _cplx(rng, sw.reduced_shape())
+    ud = torch.from_numpy(Ru).to(DEV).requires_grad_(True)
+    vd = torch.from_numpy(Rv).to(DEV).requires_grad_(True)
+    w = P.einsum(sub, P.SymTensor(ud, su.sign_string(), su.charge, su.group.orders),
+                 P.SymTensor(vd, sv.sign_string(), sv.charge, sv.group.orders))
+    loss = (w.data * torch.from_numpy(Rr).to(DEV)).sum().real
+    loss.backward()
+    du = torch.from_numpy(O.expand(Ru, su)).requires_grad_(True)
+    dv = torch.from_numpy(O.expand(Rv, sv)).requires_grad_(True)
+    dloss = (torch.einsum(sub, du, dv) * torch.from_numpy(O.expand(Rr, sw))).sum().real
+    dloss.backward()
+    assert abs(loss.item() - dloss.item()) <= 1e-12 * max(1.0, abs(dloss.item()))
+    for got, dense, sym in ((ud.grad, du.grad, su), (vd.grad, dv.grad, sv)):
+        ref, zero_ok = O.reduce_full(dense.numpy(), sym)
+        assert zero_ok
+        assert H.rel_err(H.to_np(got), ref) <= 1e-12
