@@ -99,28 +99,56 @@ class Group:
 
 @dataclass(frozen=True)
 class Sym:
-    """Symmetry of one operand: coefficients (+1/-1), total charge, block dims, group,
-    and optional per-mode charge tables (None: every label is its own charge)."""
+    """Symmetry of one operand: signs (+1/-1), total charge, block dims, group,
+    optional per-mode charge tables (None: every label is its own charge) and
+    optional per-mode sector counts H_m (None: |G| each).
+
+    A mode with H_m < |G| sectors carries the coefficient sign * |G| / H_m
+    (Sec. 2.2, Eq. symtsr: c_i = +-G/H_i); its sectors are 0..H_m-1.
+    Sector counts other than |G| need a cyclic group and no charge tables.
+    """
     signs: tuple
     charge: int
     dims: tuple
     group: Group
     charges: tuple | None = None
+    sectors: tuple | None = None
 
     @staticmethod
-    def make(signs, charge, dims, group, charges=None):
+    def make(signs, charge, dims, group, charges=None, sectors=None):
         if isinstance(signs, str):
             signs = tuple(+1 if ch == "+" else -1 for ch in signs)
         if not isinstance(group, Group):
             group = Group(group)
+        G = group.size
         if charges is not None:
             charges = tuple(tuple(int(x) for x in row) for row in charges)
-            if len(charges) != len(signs) or any(sorted(r) != list(range(group.size)) for r in charges):
+            if len(charges) != len(signs) or any(sorted(r) != list(range(G)) for r in charges):
                 raise ValueError("charge tables must be one permutation of the group per mode")
-            if all(r == tuple(range(group.size)) for r in charges):
+            if all(r == tuple(range(G)) for r in charges):
                 charges = None
-        return Sym(tuple(int(s) for s in signs), int(charge) % group.size, tuple(int(d) for d in dims), group,
-                   charges)
+        if sectors is not None:
+            sectors = tuple(int(h) for h in sectors)
+            if len(sectors) != len(signs) or any(h < 1 or G % h for h in sectors):
+                raise ValueError("sector counts must divide |G|, one per mode")
+            if all(h == G for h in sectors):
+                sectors = None
+            elif len(group.orders) != 1 or charges is not None:
+                raise ValueError("sector counts below |G| need a cyclic group and no charge tables")
+        return Sym(tuple(int(s) for s in signs), int(charge) % G, tuple(int(d) for d in dims), group,
+                   charges, sectors)
+
+    def H(self, m):
+        """Number of sectors of mode m."""
+        return self.group.size if self.sectors is None else self.sectors[m]
+
+    def coef(self, m):
+        """Integer coefficient c_m of Eq. symtsr: sign * |G| / H_m."""
+        return self.signs[m] * (self.group.size // self.H(m))
+
+    @property
+    def coefs(self):
+        return tuple(self.coef(m) for m in range(self.order))
 
     def chi(self, m, label):
         """Charge of sector label `label` of mode m."""
@@ -138,10 +166,10 @@ class Sym:
         return len(self.signs)
 
     def reduced_shape(self):
-        return (self.group.size,) * (self.order - 1) + self.dims
+        return tuple(self.H(m) for m in range(self.order - 1)) + self.dims
 
     def full_shape(self):
-        return tuple(self.group.size * n for n in self.dims)
+        return tuple(self.H(m) * n for m, n in enumerate(self.dims))
 
     def sign_string(self):
         return "".join("+" if c > 0 else "-" for c in self.signs)
@@ -149,7 +177,7 @@ class Sym:
 
 def allowed(sym: Sym, sectors) -> bool:
     """Conservation rule of Eq. symtsr: sum_m c_m chi_m(I_m) == Z."""
-    return sym.group.total(sym.signs, [sym.chi(m, s) for m, s in enumerate(sectors)]) == sym.charge
+    return sym.group.total(sym.coefs, [sym.chi(m, s) for m, s in enumerate(sectors)]) == sym.charge
 
 
 def implicit_sector(sym: Sym, known, position=None):
@@ -158,18 +186,32 @@ def implicit_sector(sym: Sym, known, position=None):
     ``known`` lists the sectors of every mode except ``position`` (default: the
     last mode, the implicit one of the standard reduced form).  Solves
     c_p I_p == Z - sum_{m != p} c_m I_m; with c_p = +1 or -1 the inverse of c_p
-    is c_p itself.
+    is c_p itself.  With c_p = s |G| / H_p (a subgroup mode) the equation has
+    the one solution I_p = s (rest / (|G| / H_p)) mod H_p when |G| / H_p
+    divides rest, and none otherwise: then None (no such block).
     """
     g = sym.group
     p = sym.order - 1 if position is None else position
     modes = [m for m in range(sym.order) if m != p]
-    others = [sym.signs[m] for m in modes]
+    others = [sym.coef(m) for m in modes]
     rest = g.sub(sym.charge, g.total(others, [sym.chi(m, s) for m, s in zip(modes, known)]))
-    return sym.label(p, g.times(sym.signs[p], rest))
+    d = g.size // sym.H(p)
+    if d == 1:
+        return sym.label(p, g.times(sym.signs[p], rest))
+    if rest % d:
+        return None
+    return (sym.signs[p] * (rest // d)) % sym.H(p)
 
 
 def full_sectors(sym: Sym, stored):
-    return tuple(stored) + (implicit_sector(sym, stored),)
+    """All sectors of a block from its stored ones, or None if the rule has no solution."""
+    last = implicit_sector(sym, stored)
+    return None if last is None else tuple(stored) + (last,)
+
+
+def stored_tuples(sym: Sym):
+    """Every stored-sector tuple of the standard reduced form (modes 0..N-2)."""
+    return itertools.product(*[range(sym.H(m)) for m in range(sym.order - 1)])
 
 
 # ----------------------------------------------------------------------------
@@ -181,10 +223,11 @@ def expand(R, sym: Sym) -> np.ndarray:
     R = R.astype(_ftype(R), copy=False)
     if R.shape != sym.reduced_shape():
         raise ValueError(f"reduced form has shape {R.shape}, expected {sym.reduced_shape()}")
-    G = sym.group.size
     full = np.zeros(sym.full_shape(), dtype=R.dtype)
-    for stored in itertools.product(range(G), repeat=sym.order - 1):
+    for stored in stored_tuples(sym):
         secs = full_sectors(sym, stored)
+        if secs is None:
+            continue
         sl = tuple(slice(s * n, (s + 1) * n) for s, n in zip(secs, sym.dims))
         full[sl] = R[stored]
     return full
@@ -193,10 +236,9 @@ def expand(R, sym: Sym) -> np.ndarray:
 def reduce_full(T, sym: Sym):
     """Standard reduced form of a full tensor, and whether every disallowed block is exactly 0."""
     T = np.asarray(T)
-    G = sym.group.size
     R = np.zeros(sym.reduced_shape(), dtype=T.dtype)
     zero_ok = True
-    for secs in itertools.product(range(G), repeat=sym.order):
+    for secs in itertools.product(*[range(sym.H(m)) for m in range(sym.order)]):
         sl = tuple(slice(s * n, (s + 1) * n) for s, n in zip(secs, sym.dims))
         if allowed(sym, secs):
             R[secs[:-1]] = T[sl]
@@ -269,23 +311,25 @@ def output_symmetry(sub, su: Sym, sv: Sym) -> Sym:
     tu, tv, tw, I, K, J = parse_einsum(sub)
     sigma = contracted_sign_ratio(sub, su, sv)
     g = su.group
-    signs, dims, tables = [], [], []
+    signs, dims, tables, hs = [], [], [], []
     for m in tw:
         if m in I:
             signs.append(su.signs[tu.index(m)])
             dims.append(su.dims[tu.index(m)])
             tables.append(su.table(tu.index(m)))
+            hs.append(su.H(tu.index(m)))
         else:
             signs.append(-sigma * sv.signs[tv.index(m)])
             dims.append(sv.dims[tv.index(m)])
             tables.append(sv.table(tv.index(m)))
+            hs.append(sv.H(tv.index(m)))
     charge = g.sub(su.charge, g.times(sigma, sv.charge))
-    return Sym.make(tuple(signs), charge, tuple(dims), g, tables)
+    return Sym.make(tuple(signs), charge, tuple(dims), g, tables, hs)
 
 
 def same_symmetry(a: Sym, b: Sym) -> bool:
     """(c, Z) and (-c, -Z) state the same rule and give the same reduced layout."""
-    if a.dims != b.dims or a.group.orders != b.group.orders:
+    if a.dims != b.dims or a.group.orders != b.group.orders or a.sectors != b.sectors:
         return False
     if any(a.table(m) != b.table(m) for m in range(a.order)):
         return False
@@ -307,6 +351,8 @@ def check_operands(sub, su: Sym, sv: Sym):
             raise ValueError(f"contracted mode {k} has different block sizes")
         if su.table(tu.index(k)) != sv.table(tv.index(k)):
             raise ValueError(f"contracted mode {k} has different charge tables")
+        if su.H(tu.index(k)) != sv.H(tv.index(k)):
+            raise ValueError(f"contracted mode {k} has different sector counts")
     return tu, tv, tw, I, K, J
 
 
@@ -319,7 +365,17 @@ def flop_count(sub, su: Sym, sv: Sym) -> int:
     for m in J:
         n *= sv.dims[tv.index(m)]
     s, v, t = len(I), len(K), len(J)
-    return 2 * n * su.group.size ** (s + t + v - 2)
+    if su.sectors is None and sv.sectors is None:
+        return 2 * n * su.group.size ** (s + t + v - 2)
+    # subgroup modes: count the pairs of allowed U and V blocks that meet
+    hs = {m: su.H(tu.index(m)) for m in I + K}
+    hs.update({m: sv.H(tv.index(m)) for m in J})
+    pairs = 0
+    for secs in itertools.product(*[range(hs[m]) for m in I + K + J]):
+        sec = dict(zip(I + K + J, secs))
+        if allowed(su, [sec[m] for m in tu]) and allowed(sv, [sec[m] for m in tv]):
+            pairs += 1
+    return 2 * n * pairs
 
 
 # ----------------------------------------------------------------------------
@@ -355,18 +411,22 @@ def contract_blocks(sub, Ru, su: Sym, Rv, sv: Sym, u_blocks=None):
     Rv = np.asarray(Rv, dtype=dt)
     Rw = np.zeros(sw.reduced_shape(), dtype=dt)
     inner_sub = sub.replace(" ", "")
-    outer = itertools.product(range(G), repeat=su.order - 1) if u_blocks is None else u_blocks
+    outer = stored_tuples(su) if u_blocks is None else u_blocks
     for ustored in outer:
         ustored = tuple(ustored)
         usec = full_sectors(su, ustored)
+        if usec is None:
+            continue
         sec = {m: usec[p] for p, m in enumerate(tu)}
-        for jfree in itertools.product(range(G), repeat=max(len(J) - 1, 0)):
+        for jfree in itertools.product(*[range(sv.H(tv.index(m))) for m in J[:-1]]):
             for m, e in zip(J[:-1], jfree):
                 sec[m] = e
             if J:
                 # last J sector from V's conservation rule, solved at its position in V
                 known = [sec[m] for m in tv if m != J[-1]]
                 sec[J[-1]] = implicit_sector(sv, known, position=tv.index(J[-1]))
+                if sec[J[-1]] is None:
+                    continue
             vsec = tuple(sec[m] for m in tv)
             wsec = tuple(sec[m] for m in tw)
             if not allowed(sv, vsec):
@@ -391,7 +451,7 @@ def _vector_allowed(sym: Sym, secs):
     stride = 1
     for o in reversed(g.orders):
         tot = np.zeros(shape, dtype=np.int64)
-        for c, s in zip(sym.signs, chg):
+        for c, s in zip(sym.coefs, chg):
             tot += c * ((s // stride) % o)
         ok &= (tot - (sym.charge // stride) % o) % o == 0
         stride *= o
@@ -409,7 +469,7 @@ def sample_contract(sub, su: Sym, sv: Sym, u_values, v_values, w_full_positions,
     shape (S, order_W); ``dtype`` is float64 or complex128.
     """
     tu, tv, tw, I, K, J = check_operands(sub, su, sv)
-    kdims = [su.group.size * su.dims[tu.index(k)] for k in K]
+    kdims = [su.H(tu.index(k)) * su.dims[tu.index(k)] for k in K]
     grids = np.meshgrid(*[np.arange(d, dtype=np.int64) for d in kdims], indexing="ij")
     kfull = {k: gr.ravel() for k, gr in zip(K, grids)}
     out = np.zeros(len(w_full_positions), dtype=dtype)
@@ -452,7 +512,7 @@ def contract_bruteforce(sub, Ru, su: Sym, Rv, sv: Sym):
     size = {}
     for t, sym in ((tu, su), (tv, sv)):
         for p, m in enumerate(t):
-            size[m] = sym.group.size * sym.dims[p]
+            size[m] = sym.H(p) * sym.dims[p]
     Wf = np.zeros(tuple(size[m] for m in tw), dtype=_ftype(Ru, Rv))
     for wi in itertools.product(*[range(size[m]) for m in tw]):
         idx = dict(zip(tw, wi))
@@ -470,17 +530,19 @@ def contract_bruteforce(sub, Ru, su: Sym, Rv, sv: Sym):
 # ----------------------------------------------------------------------------
 # Form 5: Alg. 2 with dense generalized Kronecker deltas
 # ----------------------------------------------------------------------------
-def kron_delta(group: Group, coefs, q_coef, remainder, tables=None):
+def kron_delta(group: Group, coefs, q_coef, remainder, tables=None, radices=None):
     """Dense 0/1 tensor over (sector labels..., Q): 1 iff sum coefs*chi(S) + q_coef*Q == remainder.
 
     ``tables`` gives each sector axis's charge table (identity when absent);
-    the Q axis is a charge.
+    ``radices`` each sector axis's number of sectors (|G| when absent); the Q
+    axis is a charge, |G| values.
     """
     G = group.size
     p = len(coefs)
     tables = tables or [tuple(range(G))] * p
-    D = np.zeros((G,) * (p + 1), dtype=np.float64)
-    for secs in itertools.product(range(G), repeat=p + 1):
+    radices = list(radices) if radices is not None else [G] * p
+    D = np.zeros(tuple(radices) + (G,), dtype=np.float64)
+    for secs in itertools.product(*[range(r) for r in radices], range(G)):
         chg = [tables[a][x] for a, x in enumerate(secs[:-1])] + [secs[-1]]
         if group.total(list(coefs) + [q_coef], chg) == remainder:
             D[secs] = 1.0
@@ -489,13 +551,12 @@ def kron_delta(group: Group, coefs, q_coef, remainder, tables=None):
 
 def _full_sector_form(R, sym: Sym):
     """Order-2N array [S_0..S_{N-1}, i_0..i_{N-1}]: the reduced form times its delta (Eq. redform)."""
-    G = sym.group.size
     N = sym.order
-    # the last sector axis is a label too: delta over (labels 0..N-2, charge of N-1),
-    # then the charge axis re-indexed by label
-    Dt = kron_delta(sym.group, sym.signs[:-1], sym.signs[-1], sym.charge,
-                    [sym.table(m) for m in range(N - 1)])
-    Dt = Dt[..., list(sym.table(N - 1))]
+    # the operand's own delta over all N sector labels: 1 where the rule holds
+    Dt = np.zeros(tuple(sym.H(m) for m in range(N)), dtype=np.float64)
+    for secs in itertools.product(*[range(sym.H(m)) for m in range(N)]):
+        if allowed(sym, secs):
+            Dt[secs] = 1.0
     letters = _letters(2 * N)
     S, inner = letters[:N], letters[N:]
     return np.einsum(f"{''.join(S[:-1])}{''.join(inner)},{''.join(S)}->{''.join(S)}{''.join(inner)}",
@@ -520,9 +581,12 @@ def alignment_deltas(sub, su: Sym, sv: Sym):
     tu, tv, tw, I, K, J = check_operands(sub, su, sv)
     sigma = contracted_sign_ratio(sub, su, sv)
     g = su.group
-    d1 = kron_delta(g, [su.signs[tu.index(m)] for m in I], +1, su.charge, [su.table(tu.index(m)) for m in I])
-    d2 = kron_delta(g, [su.signs[tu.index(m)] for m in K], -1, 0, [su.table(tu.index(m)) for m in K])
-    d3 = kron_delta(g, [sv.signs[tv.index(m)] for m in J], sigma, sv.charge, [sv.table(tv.index(m)) for m in J])
+    d1 = kron_delta(g, [su.coef(tu.index(m)) for m in I], +1, su.charge, [su.table(tu.index(m)) for m in I],
+                    [su.H(tu.index(m)) for m in I])
+    d2 = kron_delta(g, [su.coef(tu.index(m)) for m in K], -1, 0, [su.table(tu.index(m)) for m in K],
+                    [su.H(tu.index(m)) for m in K])
+    d3 = kron_delta(g, [sv.coef(tv.index(m)) for m in J], sigma, sv.charge, [sv.table(tv.index(m)) for m in J],
+                    [sv.H(tv.index(m)) for m in J])
     return d1, d2, d3
 
 
@@ -545,8 +609,8 @@ def _align_operand(Rfs, t, sym: Sym, row_modes, col_modes, d_row, d_col):
            + "".join(S[m] for m in col_modes[:-1]) + "".join(inner[m] for m in col_modes))
     A = np.einsum(f"{src},{drow},{dcol}->{out}", Rfs, d_row, d_col, optimize=True)
     # an empty group (s, t or v = 0) has one row or column; its delta pins Q
-    nrow = G ** max(len(row_modes) - 1, 0) * int(np.prod([sym.dims[t.index(m)] for m in row_modes]))
-    ncol = G ** max(len(col_modes) - 1, 0) * int(np.prod([sym.dims[t.index(m)] for m in col_modes]))
+    nrow = int(np.prod([sym.H(t.index(m)) for m in row_modes[:-1]] + [sym.dims[t.index(m)] for m in row_modes]))
+    ncol = int(np.prod([sym.H(t.index(m)) for m in col_modes[:-1]] + [sym.dims[t.index(m)] for m in col_modes]))
     return A.reshape(G, nrow, ncol)
 
 
@@ -570,8 +634,9 @@ def unalign_w(sub, Wal, su: Sym, sv: Sym):
     G = su.group.size
     NW = len(tw)
     dims = {m: sw.dims[p] for p, m in enumerate(tw)}
-    A = np.asarray(Wal).reshape((G,) + (G,) * max(len(I) - 1, 0) + tuple(dims[m] for m in I)
-                                + (G,) * max(len(J) - 1, 0) + tuple(dims[m] for m in J))
+    hs = {m: sw.H(p) for p, m in enumerate(tw)}
+    A = np.asarray(Wal).reshape((G,) + tuple(hs[m] for m in I[:-1]) + tuple(dims[m] for m in I)
+                                + tuple(hs[m] for m in J[:-1]) + tuple(dims[m] for m in J))
     L = _letters(2 * NW + 1)
     S = {m: L[p] for p, m in enumerate(tw)}
     inner = {m: L[NW + p] for p, m in enumerate(tw)}
@@ -602,8 +667,10 @@ def aligned_shape(sub, su: Sym, sv: Sym):
     nI = math.prod(su.dims[tu.index(m)] for m in I)
     nK = math.prod(su.dims[tu.index(m)] for m in K)
     nJ = math.prod(sv.dims[tv.index(m)] for m in J)
-    return (G, G ** max(len(I) - 1, 0) * nI, G ** max(len(K) - 1, 0) * nK,
-            G ** max(len(J) - 1, 0) * nJ)
+    hI = math.prod(su.H(tu.index(m)) for m in I[:-1])
+    hK = math.prod(su.H(tu.index(m)) for m in K[:-1])
+    hJ = math.prod(sv.H(tv.index(m)) for m in J[:-1])
+    return (G, hI * nI, hK * nK, hJ * nJ)
 
 
 # ----------------------------------------------------------------------------

@@ -681,3 +681,90 @@ def test_complex_bruteforce_and_samples_tiny():
     got = O.sample_contract(sub, su, sv, O.reduced_value_fn(U, su), O.reduced_value_fn(V, sv), pos,
                             dtype=np.complex128)
     np.testing.assert_allclose(got, full[tuple(pos.T)], rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Subgroup modes (Sec. 2.2, Eq. symtsr with c_i = +-G/H_i): mode i has H_i | G
+# sectors.  Pins: with one H for every mode the tensor is a Z_H tensor with
+# charge Z / (G/H) (the pinned Z_H oracle); mixed H_i against brute force over
+# full indices (Eq. ctr summed term by term) and np.einsum on the expanded
+# operands; the zero pattern of the output; flops against a count of terms.
+# ---------------------------------------------------------------------------
+def _divisors(G):
+    return [h for h in range(1, G + 1) if G % h == 0]
+
+
+def _subgroup_case(rng, G, s, t, v, nmax=2, uniform_h=None):
+    g = O.Group(G)
+    letters = iter("abcdefghijklmnop")
+    I = [next(letters) for _ in range(s)]
+    K = [next(letters) for _ in range(v)]
+    J = [next(letters) for _ in range(t)]
+    tu = list(I + K); rng.shuffle(tu)
+    tv = list(K + J); rng.shuffle(tv)
+    tw = list(I + J); rng.shuffle(tw)
+    hs = {m: (uniform_h or int(rng.choice(_divisors(G)))) for m in I + K + J}
+    dims = {m: int(rng.integers(1, nmax + 1)) for m in I + K + J}
+    cu = {m: int(rng.choice([-1, 1])) for m in tu}
+    sigma = int(rng.choice([-1, 1]))
+    cv = {m: (sigma * cu[m] if m in K else int(rng.choice([-1, 1]))) for m in tv}
+
+    def reach(term, c):
+        # a total charge that some sector combination reaches
+        return sum(c[m] * (G // hs[m]) * int(rng.integers(hs[m])) for m in term) % G
+    su = O.Sym.make([cu[m] for m in tu], reach(tu, cu), [dims[m] for m in tu], g, sectors=[hs[m] for m in tu])
+    sv = O.Sym.make([cv[m] for m in tv], reach(tv, cv), [dims[m] for m in tv], g, sectors=[hs[m] for m in tv])
+    return f"{''.join(tu)},{''.join(tv)}->{''.join(tw)}", su, sv
+
+
+@pytest.mark.parametrize("G,H", [(4, 2), (6, 3), (6, 2), (8, 4), (12, 6)])
+@pytest.mark.parametrize("stv", [(1, 1, 1), (2, 1, 1), (1, 2, 2)])
+def test_uniform_subgroup_is_the_smaller_cyclic_group(G, H, stv):
+    rng = np.random.default_rng(abs(hash(("subgroup-uniform", G, H, stv))) % 2 ** 31)
+    sub, su, sv = _subgroup_case(rng, G, *stv, uniform_h=H)
+    d = G // H
+    assert su.charge % d == 0 and sv.charge % d == 0
+    small = lambda sym: O.Sym.make(sym.signs, sym.charge // d, sym.dims, O.Group(H))  # noqa: E731
+    Ru, Rv = rng.standard_normal(su.reduced_shape()), rng.standard_normal(sv.reduced_shape())
+    assert su.reduced_shape() == small(su).reduced_shape()
+    Rw, sw = O.contract_blocks(sub, Ru, su, Rv, sv)
+    Rh, swh = O.contract_blocks(sub, Ru, small(su), Rv, small(sv))
+    np.testing.assert_allclose(Rw, Rh, rtol=0, atol=1e-12)
+    assert sw.charge == swh.charge * d and sw.signs == swh.signs
+    Ra = O.contract_irrep_aligned(sub, Ru, su, Rv, sv)[0]
+    np.testing.assert_allclose(Ra, Rh, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("G", [4, 6, 8])
+@pytest.mark.parametrize("stv", [(1, 1, 1), (2, 1, 1), (1, 1, 2), (1, 2, 1), (1, 1, 0), (0, 2, 1)])
+def test_mixed_subgroups_all_forms_agree_with_brute_force(G, stv):
+    rng = np.random.default_rng(abs(hash(("subgroup-mixed", G, stv))) % 2 ** 31)
+    for _ in range(3):
+        sub, su, sv = _subgroup_case(rng, G, *stv)
+        Ru, Rv = rng.standard_normal(su.reduced_shape()), rng.standard_normal(sv.reduced_shape())
+        Rb, sw, zero_ok = O.contract_bruteforce(sub, Ru, su, Rv, sv)
+        assert zero_ok
+        Wd = np.einsum(sub, O.expand(Ru, su), O.expand(Rv, sv))
+        np.testing.assert_allclose(O.expand(Rb, sw), Wd, rtol=0, atol=1e-12)
+        for form in (O.contract_dense, O.contract_blocks, O.contract_irrep_aligned):
+            R, swf = form(sub, Ru, su, Rv, sv)[:2]
+            assert O.same_symmetry(swf, sw)
+            np.testing.assert_allclose(O.expand(R, sw), O.expand(Rb, sw), rtol=0, atol=1e-12)
+        # flops: 2 x the number of nonzero scalar terms of Eq. ctr
+        U, V = O.expand(np.ones(su.reduced_shape()), su), O.expand(np.ones(sv.reduced_shape()), sv)
+        assert O.flop_count(sub, su, sv) == 2 * int(round(np.einsum(sub, U, V).sum()))
+
+
+def test_subgroup_dead_blocks_and_rules():
+    # Z_4 with a Z_2 mode (c = 2): a + 2b == 1 has solutions only for odd a
+    su = O.Sym.make("++", 1, (1, 1), O.Group(4), sectors=(4, 2))
+    assert O.implicit_sector(su, (0,)) is None and O.implicit_sector(su, (2,)) is None
+    assert O.implicit_sector(su, (1,)) == 0 and O.implicit_sector(su, (3,)) == 1
+    R = np.arange(4.0).reshape(4, 1, 1) + 1
+    full = O.expand(R, su)
+    assert full.shape == (4, 2) and full[0].sum() == 0 and full[2].sum() == 0
+    assert full[1, 0] == 2 and full[3, 1] == 4
+    with pytest.raises(ValueError):
+        O.Sym.make("++", 0, (1, 1), O.Group(4), sectors=(4, 3))
+    with pytest.raises(ValueError):
+        O.Sym.make("++", 0, (1, 1), O.Group((2, 2)), sectors=(4, 2))
