@@ -164,8 +164,9 @@ def chain_flops(wl, compute, cplx=False):
     for st in wl.steps:
         ou, ov = wl.operands[st.u], wl.operands[st.v]
         info = L.plan(st.einsum, L.make_group(wl.group),
-                      L.TensorDesc(ou.signs, ou.charge, ou.dims, dt, None),
-                      L.TensorDesc(ov.signs, ov.charge, ov.dims, dt, None), None, L.COMPUTE[compute])
+                      L.TensorDesc(ou.signs, ou.charge, ou.dims, dt, None, None, ou.sectors),
+                      L.TensorDesc(ov.signs, ov.charge, ov.dims, dt, None, None, ov.sectors), None,
+                      L.COMPUTE[compute])
         total += info.flops
     return total
 
@@ -193,7 +194,7 @@ def time_workload(P, SG, wl, compute, steps, warmup, grad=False, cplx=False):
             d = torch.complex(d, im)
         if grad and name != "R":
             d.requires_grad_(True)
-        t[name] = P.SymTensor(d, op.signs, op.charge, wl.group)
+        t[name] = P.SymTensor(d, op.signs, op.charge, wl.group, None, op.sectors)
     flops = chain_flops(wl, compute, cplx) * (3.0 if grad else 1.0)
 
     def step():
@@ -336,6 +337,7 @@ def main():
                                            ("mps_env_grad", ("f64", "f32"), False, False),
                                            ("mps_env_grad", ("f64", "f32"), True, False),
                                            ("ccd_ladder_z8", ("f64", "f32"), False, True),
+                                           ("ccd_ladder_z8_sub", ("f64", "f32", "bf16x3"), False, False),
                                            ("mps_env_z2z3", ("f64", "f32"), False, True)):
             wlx = S.configs.get(name)
             for c in computes:

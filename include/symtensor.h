@@ -41,7 +41,9 @@
  *   U_al[Q][I stored sectors][I inner][K stored sectors][K inner]  -> (|G|, M, Kd)
  *   V_al[Q][K stored sectors][K inner][J stored sectors][J inner]  -> (|G|, Kd, N)
  *   W_al[Q][I stored sectors][I inner][J stored sectors][J inner]  -> (|G|, M, N)
- * with M = |G|^(s-1) prod n_I, Kd = |G|^(v-1) prod n_K, N = |G|^(t-1) prod n_J.
+ * with M = |G|^(s-1) prod n_I, Kd = |G|^(v-1) prod n_K, N = |G|^(t-1) prod n_J
+ * (with subgroup modes each |G| factor is the stored mode's sector count H_m;
+ * aligned blocks whose implicit sector has no solution are zero).
  * Implicit sectors: last I from sum c^U_I I + Q == Z^U; last K from
  * sum c^U_K K == Q; last J from sum c^V_J J + sigma Q == Z^V.
  * Per compute mode the aligned buffers hold:
@@ -161,7 +163,18 @@ typedef struct {
  * not a permutation is SYMT_EINVAL.  Supported by symtensor_plan and
  * symtensor_contract; symtensor_align and symtensor_unalign return
  * SYMT_EUNSUPPORTED for non-identity tables (their device copies live in the
- * contraction's workspace). */
+ * contraction's workspace).
+ *
+ * `sectors` (host pointer, may be NULL) gives each mode's number of sectors
+ * H_m, a divisor of |G| (Sec. 2.2, Eq. symtsr): mode m then carries the
+ * coefficient c_m = sign_m |G| / H_m and sectors 0..H_m-1, and the standard
+ * reduced form is [H_0]..[H_{N-2}] + dims.  NULL means |G| for every mode.
+ * Stored sector tuples whose last sector has no solution hold no block (their
+ * entries are ignored on input and written as zero on output).  A contracted
+ * mode needs the same count in u and v, w's counts must be the derived ones
+ * (u's on I modes, v's on J modes) -- else SYMT_ESYM; a count that does not
+ * divide |G| is SYMT_EINVAL.  Counts below |G| need a cyclic group and no
+ * charge tables (SYMT_EUNSUPPORTED), and disable the fused product. */
 typedef struct {
   int32_t nmodes;
   const char* signs;
@@ -170,6 +183,7 @@ typedef struct {
   int32_t dtype;           /* symt_dtype */
   void* data;
   const int32_t* mode_charges;
+  const int32_t* sectors;
 } symt_tensor;
 
 /* Result of planning one contraction (host-only, no device needed). */

@@ -48,7 +48,7 @@ class SymtGroup(ctypes.Structure):
 class SymtTensor(ctypes.Structure):
     _fields_ = [("nmodes", c_int32), ("signs", c_char_p), ("charge", c_int32),
                 ("dims", POINTER(c_int64)), ("dtype", c_int32), ("data", c_void_p),
-                ("mode_charges", POINTER(c_int32))]
+                ("mode_charges", POINTER(c_int32)), ("sectors", POINTER(c_int32))]
 
 
 class SymtPlanInfo(ctypes.Structure):
@@ -128,15 +128,19 @@ def make_group(orders) -> SymtGroup:
 class TensorDesc:
     """Keeps a SymtTensor and the buffers it points to alive together."""
 
-    def __init__(self, signs: str, charge: int, dims, dtype: int, data_ptr: int | None, mode_charges=None):
+    def __init__(self, signs: str, charge: int, dims, dtype: int, data_ptr: int | None, mode_charges=None,
+                 sectors=None):
         self._signs = signs.encode()
         self._dims = (c_int64 * max(1, len(dims)))(*[int(d) for d in dims])
         self._charges = None
         if mode_charges is not None:
             flat = [int(x) for row in mode_charges for x in row]
             self._charges = (c_int32 * len(flat))(*flat)
+        self._sectors = None
+        if sectors is not None:
+            self._sectors = (c_int32 * len(sectors))(*[int(h) for h in sectors])
         self.c = SymtTensor(len(signs), self._signs, int(charge), self._dims, int(dtype),
-                            c_void_p(data_ptr) if data_ptr else None, self._charges)
+                            c_void_p(data_ptr) if data_ptr else None, self._charges, self._sectors)
 
     @property
     def ref(self):

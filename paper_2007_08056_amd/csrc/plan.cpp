@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <numeric>
 
 namespace symt {
 
@@ -127,9 +128,16 @@ int read_operand(const symt_tensor* t, const GroupDesc& g, OperandDesc* o, const
     return fail(err, SYMT_EDTYPE, "operand %s: dtype must be SYMT_F64, F32, C128 or C64", name);
   o->dtype = t->dtype;
   o->data = t->data;
+  for (int m = 0; m < o->n; ++m) {
+    const int32_t h = t->sectors ? t->sectors[m] : g.size;
+    if (h < 1 || h > g.size || g.size % h != 0)
+      return fail(err, SYMT_EINVAL, "operand %s: sector count of mode %s does not divide |G|", name,
+                  std::to_string(m).c_str());
+    o->hs[m] = h;
+  }
   int64_t e = 1;
   for (int m = 0; m < o->n - 1; ++m)
-    if (!mul_ok(e, g.size, &e)) return fail(err, SYMT_EINVAL, "operand %s: size overflows", name);
+    if (!mul_ok(e, o->hs[m], &e)) return fail(err, SYMT_EINVAL, "operand %s: size overflows", name);
   for (int m = 0; m < o->n; ++m) {
     if (t->dims[m] < 0) return fail(err, SYMT_EINVAL, "operand %s: negative block dimension", name);
     o->dims[m] = t->dims[m];
@@ -238,7 +246,15 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
       if (table_at(p->chg[0], p->g.size, p->posK_u[i], l) != table_at(p->chg[1], p->g.size, p->posK_v[i], l))
         return fail(err, SYMT_ESYM, "contracted mode '%s' carries different charge tables in u and v",
                     std::string(1, K[i]).c_str());
+    if (p->U.hs[p->posK_u[i]] != p->V.hs[p->posK_v[i]])
+      return fail(err, SYMT_ESYM, "contracted mode '%s' has different sector counts in u and v",
+                  std::string(1, K[i]).c_str());
   }
+  // subgroup modes (fewer than |G| sectors): cyclic groups, no charge tables
+  for (int m = 0; m < p->U.n; ++m) p->subgroups = p->subgroups || p->U.hs[m] != p->g.size;
+  for (int m = 0; m < p->V.n; ++m) p->subgroups = p->subgroups || p->V.hs[m] != p->g.size;
+  if (p->subgroups && (p->g.nf != 1 || !p->chg[0].empty() || !p->chg[1].empty()))
+    return fail(err, SYMT_EUNSUPPORTED, "subgroup modes need a cyclic group and no charge tables");
   // v = 0 (outer product): no ratio is defined; -1 makes W's coefficients u's
   // followed by v's and Z^W = Z^U + Z^V
   p->sigma = p->v == 0 ? -1 : sigma;
@@ -255,6 +271,35 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   // modes gives Q = 0, delta(1) with no I modes Q = Z^U, delta(3) with no J
   // modes sigma Q = Z^V.  Only that slice of the aligned forms is nonzero.
   p->q_pin = p->v == 0 ? 0 : p->s == 0 ? p->U.charge : p->t == 0 ? gtimes(p->g, sigma, p->V.charge) : -1;
+  {
+    // The sum of a delta's terms ranges over the subgroup generated by its
+    // coefficients' magnitudes (multiples of their gcd d with |G|), or is 0 for
+    // an empty sum (d = |G|).  A Q for which one of the three deltas cannot
+    // hold has an all-zero slice in the aligned forms and is skipped.
+    const int G = p->g.size;
+    auto gcd_of = [&](const OperandDesc& X, const int32_t* pos, int count) {
+      if (count == 0) return G;
+      int d = G;
+      for (int i = 0; i < count; ++i) d = std::gcd(d, G / X.hs[pos[i]]);
+      return d;
+    };
+    const int dI = gcd_of(p->U, p->posI_u, p->s), dK = gcd_of(p->U, p->posK_u, p->v),
+              dJ = gcd_of(p->V, p->posJ_v, p->t);
+    auto reach = [&](int x, int d) { return d == 1 || (d == G ? x == 0 : x % d == 0); };
+    std::vector<int> live;
+    for (int q = 0; q < G; ++q)
+      if (reach(gsub(p->g, p->U.charge, q), dI) && reach(q, dK) &&
+          reach(gsub(p->g, p->V.charge, gtimes(p->g, sigma, q)), dJ))
+        live.push_back(q);
+    p->nq = static_cast<int64_t>(live.size());
+    p->q0 = live.empty() ? 0 : live[0];
+    p->q_step = live.size() > 1 ? live[1] - live[0] : 1;
+    for (size_t i = 0; i < live.size(); ++i)
+      if (live[i] != p->q0 + static_cast<int>(i) * p->q_step) {   // not a progression: move every slice
+        p->q0 = 0, p->q_step = 1, p->nq = G;
+        break;
+      }
+  }
   // derived charge tables: u's rows on I modes, v's on J modes
   std::vector<int32_t> w_chg;
   if (!p->chg[0].empty() || !p->chg[1].empty()) {
@@ -287,6 +332,9 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
       const size_t pu = tu.find(c);
       const int64_t d = (pu != std::string::npos) ? p->U.dims[pu] : p->V.dims[tv.find(c)];
       if (p->W.dims[m] != d) return fail(err, SYMT_EINVAL, "output block sizes differ from inputs'");
+      const int32_t h = (pu != std::string::npos) ? p->U.hs[pu] : p->V.hs[tv.find(c)];
+      if (p->W.hs[m] != h)
+        return fail(err, SYMT_ESYM, "output sector counts differ from u's (I modes) and v's (J modes)");
     }
     bool same = p->W.charge == p->w_charge, flipped = p->W.charge == gneg(p->g, p->w_charge);
     for (size_t m = 0; m < tw.size(); ++m) {
@@ -302,8 +350,12 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   } else {
     p->W = OperandDesc{};
     p->W.n = static_cast<int32_t>(tw.size());
+    for (size_t m = 0; m < tw.size(); ++m) {
+      const size_t pu = tu.find(tw[m]);
+      p->W.hs[m] = (pu != std::string::npos) ? p->U.hs[pu] : p->V.hs[tv.find(tw[m])];
+    }
     int64_t e = 1;
-    for (int m = 0; m < p->W.n - 1; ++m) mul_ok(e, p->g.size, &e);
+    for (int m = 0; m < p->W.n - 1; ++m) mul_ok(e, p->W.hs[m], &e);
     for (size_t m = 0; m < tw.size(); ++m) {
       const char c = tw[m];
       const size_t pu = tu.find(c);
@@ -318,15 +370,16 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   p->chg[2] = w_chg;
   p->charges = !p->chg[0].empty() || !p->chg[1].empty() || !p->chg[2].empty();
 
-  // ---- aligned shapes M = G^(s-1) n_I, Kd = G^(v-1) n_K, N = G^(t-1) n_J
+  // ---- aligned shapes M = G^(s-1) n_I, Kd = G^(v-1) n_K, N = G^(t-1) n_J (each
+  // G factor is a stored mode's sector count: the group's modes but its last)
   p->nI = p->nK = p->nJ = 1;
   for (int i = 0; i < p->s; ++i) mul_ok(p->nI, p->U.dims[p->posI_u[i]], &p->nI);
   for (int i = 0; i < p->v; ++i) mul_ok(p->nK, p->U.dims[p->posK_u[i]], &p->nK);
   for (int i = 0; i < p->t; ++i) mul_ok(p->nJ, p->V.dims[p->posJ_v[i]], &p->nJ);
   int64_t gs = 1, gt = 1, gv = 1;
-  for (int i = 1; i < p->s; ++i) mul_ok(gs, p->g.size, &gs);
-  for (int i = 1; i < p->t; ++i) mul_ok(gt, p->g.size, &gt);
-  for (int i = 1; i < p->v; ++i) mul_ok(gv, p->g.size, &gv);
+  for (int i = 0; i + 1 < p->s; ++i) mul_ok(gs, p->U.hs[p->posI_u[i]], &gs);
+  for (int i = 0; i + 1 < p->t; ++i) mul_ok(gt, p->V.hs[p->posJ_v[i]], &gt);
+  for (int i = 0; i + 1 < p->v; ++i) mul_ok(gv, p->U.hs[p->posK_u[i]], &gv);
   if (!mul_ok(gs, p->nI, &p->M) || !mul_ok(gv, p->nK, &p->Kd) || !mul_ok(gt, p->nJ, &p->N))
     return fail(err, SYMT_EINVAL, "aligned shape overflows");
   // complex: the real representation doubles the contracted and output columns
@@ -334,7 +387,7 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   p->gn = p->cplx ? 2 * p->N : p->N;
   if (p->M > INT32_MAX || p->gn > INT32_MAX || p->gk > INT32_MAX)
     return fail(err, SYMT_EUNSUPPORTED, "aligned matrix dimension above 2^31-1");
-  p->flops = 2.0 * (p->q_pin >= 0 ? 1 : p->g.size) * static_cast<double>(p->M) * static_cast<double>(p->gk) *
+  p->flops = 2.0 * static_cast<double>(p->nq) * static_cast<double>(p->M) * static_cast<double>(p->gk) *
              static_cast<double>(p->gn);
 
   // ---- buffer sizes for the compute mode.  The aligned forms hold |G| M K,
@@ -348,10 +401,10 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   p->bytes_u_al = ea * static_cast<size_t>(au);
   p->bytes_v_al = ea * static_cast<size_t>(av);
   p->bytes_w_al = ec * static_cast<size_t>(aw);
-  const size_t slices = p->q_pin >= 0 ? static_cast<size_t>(p->g.size) : 1;
-  p->ws_u_al = p->bytes_u_al / slices;
-  p->ws_v_al = p->bytes_v_al / slices;
-  p->ws_w_al = p->bytes_w_al / slices;
+  const size_t G = static_cast<size_t>(p->g.size), nq = static_cast<size_t>(p->nq);
+  p->ws_u_al = p->bytes_u_al / G * nq;
+  p->ws_v_al = p->bytes_v_al / G * nq;
+  p->ws_w_al = p->bytes_w_al / G * nq;
   p->workspace = round_up(p->ws_u_al, 256) + round_up(p->ws_v_al, 256) + round_up(p->ws_w_al, 256);
 
   // ---- fused product: A read from U's standard form along contiguous K runs
@@ -361,7 +414,8 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   bool trailing_k = true;
   for (int i = 0; i < p->v; ++i) trailing_k = trailing_k && p->posK_u[i] == p->U.n - p->v + i;
   const int vw = compute == SYMT_COMPUTE_F64 ? 2 : 4;
-  p->fused = !force_steps && !p->cplx && p->q_pin < 0 && compute != SYMT_COMPUTE_BF16X3 && p->U.dtype == want &&
+  p->fused = !force_steps && !p->cplx && !p->subgroups && p->nq == p->g.size && compute != SYMT_COMPUTE_BF16X3 &&
+             p->U.dtype == want &&
              (!w || p->W.dtype == want) && trailing_k && p->nK % kFpBK == 0 && p->N % vw == 0 &&
              p->M > 0 && p->N > 0 && p->Kd > 0 && p->U.elems > 0;
   if (p->fused) {
@@ -374,8 +428,8 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
     p->bytes_charges = 4 * 2 * static_cast<size_t>(p->g.size) * (p->U.n + p->V.n + p->W.n);
   }
   // Room for stream-K pieces when the model would pick it on 16-byte aligned operands.
-  if (compute != SYMT_COMPUTE_BF16X3 && p->M > 0 && p->gn > 0 && p->gk > 0) {
-    const GemmChoice gc = choose_fp_gemm(p->q_pin >= 0 ? 1 : p->g.size, p->M, p->gn, p->gk,
+  if (compute != SYMT_COMPUTE_BF16X3 && p->nq > 0 && p->M > 0 && p->gn > 0 && p->gk > 0) {
+    const GemmChoice gc = choose_fp_gemm(p->nq, p->M, p->gn, p->gk,
                                          compute == SYMT_COMPUTE_F64 ? 8 : 4, true);
     p->bytes_partial = gc.partial_bytes;
     p->workspace += round_up(p->bytes_partial, 256);
@@ -509,6 +563,13 @@ void sector_groups(const Plan& p, int operand, SectorGroup* R, SectorGroup* C) {
     for (int i = 0; i < p.t; ++i) { C->pos[i] = p.posJ_w[i]; C->coef[i] = p.V.sign[p.posJ_v[i]]; }
     C->alpha = -p.sigma; C->beta = p.V.charge;
   }
+  // sector counts of the members (subgroup modes: H < |G|, coefficient magnitude |G|/H)
+  const OperandDesc& X = operand == 0 ? p.U : operand == 1 ? p.V : p.W;
+  for (SectorGroup* sg : {R, C})
+    for (int i = 0; i < sg->count; ++i) {
+      sg->rad[i] = X.hs[sg->pos[i]];
+      sg->mag[i] = p.g.size / sg->rad[i];
+    }
 }
 }  // namespace
 
@@ -531,10 +592,10 @@ OffsetParams make_offsets(const Plan& p, int operand, bool rows) {
   for (int m = X.n - 1; m >= 0; --m) {
     if (m == X.n - 1) { wsec[m] = 0; continue; }
     wsec[m] = w;
-    w *= p.g.size;
+    w *= X.hs[m];
   }
   o.gpow = 1;
-  for (int i = 1; i < o.grp.count; ++i) o.gpow *= p.g.size;
+  for (int i = 0; i + 1 < o.grp.count; ++i) o.gpow *= o.grp.rad[i];
   o.n_inner = 1;
   for (int i = 0; i < o.grp.count; ++i) {
     const int m = o.grp.pos[i];
@@ -561,13 +622,23 @@ XformParams make_xform(const Plan& p, int operand, bool to_aligned, int in_bytes
   const int G = p.g.size;
   sector_groups(p, operand, &R, &C);
   x.gpow_row = 1;
-  for (int i = 1; i < R.count; ++i) x.gpow_row *= G;
+  for (int i = 0; i + 1 < R.count; ++i) x.gpow_row *= R.rad[i];
   x.gpow_col = 1;
-  for (int i = 1; i < C.count; ++i) x.gpow_col *= G;
-  // Q is fixed where one of the form's own deltas has an empty sum; the
-  // contraction's workspace copy keeps slice q_pin of every form.
-  x.q_pin = slice_only || pinned_form(p, operand) ? p.q_pin : -1;
-  x.nblocks = x.gpow_row * x.gpow_col * (x.q_pin >= 0 ? 1 : G);
+  for (int i = 0; i + 1 < C.count; ++i) x.gpow_col *= C.rad[i];
+  for (int m = 0; m < X.n; ++m) x.hs[m] = X.hs[m];
+  // The contraction's workspace copy holds the live slices (q0 + q_step j) in
+  // order; a whole form (standalone transforms) holds all |G|, of which only
+  // q_pin is moved where one of the form's own deltas has an empty sum.
+  int64_t nslices = G;
+  x.q0 = 0; x.q_step = 1; x.q_full = 1;
+  if (slice_only) {
+    x.q0 = p.q0; x.q_step = p.q_step; x.q_full = 0;
+    nslices = p.nq;
+  } else if (pinned_form(p, operand)) {
+    x.q0 = p.q_pin;
+    nslices = 1;
+  }
+  x.nblocks = x.gpow_row * x.gpow_col * nslices;
   // Complex operands move as reals: each element is a (re, im) pair, one more
   // in-block dim (std stride 1) that sits innermost among the aligned columns;
   // V's complex rows go to every other real row (the odd ones are filled from
@@ -581,10 +652,8 @@ XformParams make_xform(const Plan& p, int operand, bool to_aligned, int in_bytes
   for (int i = 0; i < C.count; ++i) nC *= X.dims[C.pos[i]];
   const int64_t rows_tot = x.gpow_row * nR * row_mult, cols_tot = x.gpow_col * nC * cm;
   const AlignedLayout lay = aligned_layout(p.compute, operand);
-  // one slice only (Q pinned, workspace copy): every block lands at Q offset 0
-  const bool one_slice = slice_only && x.q_pin >= 0;
-  x.q_stride = one_slice ? 0 : rows_tot * cols_tot;
-  x.plane = (one_slice ? 1 : static_cast<int64_t>(G)) * rows_tot * cols_tot;
+  x.q_stride = rows_tot * cols_tot;
+  x.plane = (x.q_full ? static_cast<int64_t>(G) : nslices) * rows_tot * cols_tot;
   const int64_t row_unit = lay == kRowMajor ? cols_tot : 1;   // aligned stride of one real row
   const int64_t col_unit = lay == kRowMajor ? 1 : rows_tot;   // aligned stride of one real column
   x.rs_stride = nR * row_mult * row_unit;

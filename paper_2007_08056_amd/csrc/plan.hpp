@@ -29,7 +29,9 @@ struct GroupDesc {
 struct SectorGroup {
   int32_t count;
   int32_t pos[kMaxOrder];
-  int32_t coef[kMaxOrder];
+  int32_t coef[kMaxOrder];          // sign of each member's coefficient
+  int32_t rad[kMaxOrder];           // sectors of each member (|G|, or H for a subgroup mode)
+  int32_t mag[kMaxOrder];           // |G| / rad: the coefficient's magnitude
   int32_t alpha;
   int32_t beta;
 };
@@ -48,9 +50,12 @@ struct XformParams {
   GroupDesc g;
   int32_t order;                    // modes of the operand
   SectorGroup row, col;
-  int64_t gpow_row, gpow_col;       // |G|^(count-1) of each group
-  int64_t nblocks;                  // aligned blocks moved: |G|^(order-1), or one Q slice's
-  int32_t q_pin;                    // -1, or the only Q with nonzero aligned blocks
+  int64_t gpow_row, gpow_col;       // stored-sector tuples of each group (product of radices)
+  int32_t hs[kMaxOrder];            // sectors of each mode of the operand (standard block index radices)
+  int64_t nblocks;                  // aligned blocks moved: slices x stored-sector tuples
+  int32_t q0, q_step;               // auxiliary sectors moved: Q = q0 + q_step * slice
+  int32_t q_full;                   // 1: the aligned buffer holds all |G| slices (offset by Q);
+                                    // 0: only the moved slices, in order (offset by slice)
   int64_t blk_elems;                // elements per block (product of inner dims)
   int64_t q_stride, rs_stride, cs_stride;  // aligned block base = Q*q + Rs*rs + Cs*cs
   int64_t plane;                    // elements between the hi and lo bf16 planes
@@ -109,6 +114,10 @@ struct OffsetBatch {
   int64_t end[kMaxOffsetTables];    // running sum of |G| * count
 };
 
+// Both descriptors travel as kernel arguments (at most 4 KB).
+static_assert(sizeof(OffsetBatch) <= 4000, "offset batch exceeds the kernel argument space");
+static_assert(sizeof(XformParams) <= 4000, "transform descriptor exceeds the kernel argument space");
+
 // Device pointers of the four offset tables of the fused product: rows and
 // columns of U (A operand) and of W (output), each |G| x (rows or columns).
 struct FusedTables {
@@ -124,6 +133,7 @@ struct OperandDesc {
   int32_t sign[kMaxOrder];          // +1 / -1
   int32_t charge;
   int64_t dims[kMaxOrder];
+  int32_t hs[kMaxOrder];            // sectors per mode: |G|, or H | |G| for a subgroup mode
   int32_t dtype;
   void* data;
   int64_t elems;                    // elements of the standard reduced form
@@ -134,11 +144,16 @@ struct Plan {
   std::string tu, tv, tw;
   int32_t s = 0, t = 0, v = 0, sigma = 0;
   int32_t q_pin = -1;               // s, t or v = 0: the one auxiliary sector with nonzero blocks
+  // auxiliary sectors for which all three deltas can hold (a coset q0 + q_step Z of Z_G,
+  // nq of them): the slices the contraction aligns, multiplies and writes back
+  int32_t q0 = 0, q_step = 1;
+  int64_t nq = 0;
   int32_t posI_u[kMaxOrder], posK_u[kMaxOrder], posK_v[kMaxOrder], posJ_v[kMaxOrder];
   int32_t posI_w[kMaxOrder], posJ_w[kMaxOrder];
   int64_t nI = 1, nK = 1, nJ = 1;
   int64_t M = 0, Kd = 0, N = 0;
   bool cplx = false;                // complex operands: the product runs on C's real representation
+  bool subgroups = false;           // some mode has fewer than |G| sectors
   int64_t gk = 0, gn = 0;           // the real product's K and N (2 Kd, 2 N when complex)
   OperandDesc U, V, W;
   bool has_w = false;

@@ -107,7 +107,7 @@ int do_align(symt_ctx* ctx, const Plan& p, int operand, void* dst, hipStream_t s
     int r = symt::launch_xform(x, symt::real_bytes(X.dtype) == 8, kind, X.data, dst, s, &err);
     if (r == SYMT_OK && p.cplx && operand == 1) {
       // complex V: the odd real rows of the real representation of C
-      const int64_t slices = slice_only && p.q_pin >= 0 ? 1 : p.g.size;
+      const int64_t slices = slice_only ? p.nq : p.g.size;
       r = symt::launch_cplx_rows(dst, p.compute == SYMT_COMPUTE_F64, slices, p.Kd, p.N, s, &err);
     }
     return r;
@@ -125,8 +125,9 @@ int do_unalign(symt_ctx* ctx, const Plan& p, const void* wal, hipStream_t s, boo
   if (!aligned16(wal) || !aligned16(p.W.data)) x.vec = 1;
   std::string err;
   const int rc = timed(ctx, 3, s, [&] {
-    // v = 0: W's rule admits blocks that break u's own rule; they hold zeros
-    if (p.v == 0) {
+    // Skipped slices (s, t or v = 0, subgroup modes) leave blocks of W that no
+    // product reaches, and subgroup modes stored tuples without a block: zeros.
+    if (p.nq < p.g.size || p.subgroups) {
       const int r = symt::launch_zero(p.W.data, static_cast<size_t>(p.W.elems) * elem_bytes(p.W.dtype), s, &err);
       if (r) return r;
     }
@@ -319,15 +320,11 @@ int symtensor_contract(symt_ctx* ctx, const char* einsum, const symt_group* grou
   char* part = static_cast<char*>(wal) + symt::round_up(p.ws_w_al, 256);
   if ((rc = do_align(ctx, p, 0, ual, s, true, chg[0]))) return rc;
   if ((rc = do_align(ctx, p, 1, val, s, true, chg[1]))) return rc;
-  if (p.q_pin >= 0) {
-    // the workspace holds slice q_pin alone: one product of it
-    if ((rc = do_gemm(ctx, p.compute, 1, p.M, p.gk, p.gn, ual, val, wal, s, nullptr,
-                      p.bytes_partial ? part : nullptr, p.bytes_partial, p.M * p.gk, p.gk * p.gn)))
-      return rc;
-  } else if ((rc = do_gemm(ctx, p.compute, p.g.size, p.M, p.gk, p.gn, ual, val, wal, s, nullptr,
-                           p.bytes_partial ? part : nullptr, p.bytes_partial))) {
+  // the workspace holds the nq live slices in order: one batched product of them
+  // (none live: no block of W is reached, and the unalign step clears W)
+  if (p.nq > 0 && (rc = do_gemm(ctx, p.compute, p.nq, p.M, p.gk, p.gn, ual, val, wal, s, nullptr,
+                                p.bytes_partial ? part : nullptr, p.bytes_partial)))
     return rc;
-  }
   if ((rc = do_unalign(ctx, p, wal, s, true, chg[2]))) return rc;
   return SYMT_OK;
 }

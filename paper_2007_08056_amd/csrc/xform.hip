@@ -85,7 +85,10 @@ __global__ __launch_bounds__(256) void k_xform_copy(const Tin* __restrict__ src,
   const int64_t c_begin = (tile - row_tile * p.run_tiles) * p.run_chunk;
   const int64_t c_end = c_begin + p.run_chunk < p.run_len ? c_begin + p.run_chunk : p.run_len;
   int64_t sb, ab;
-  block_bases(p, blk, sb, ab);
+  // a block that does not exist (subgroup modes): its aligned block is zero,
+  // and there is nothing to write into the (cleared) standard form
+  const bool live = block_bases(p, blk, sb, ab);
+  if (!live && !p.to_aligned) return;
   const int64_t src_base = p.to_aligned ? sb : ab;
   const int64_t dst_base = p.to_aligned ? ab : sb;
   const int64_t r0 = row_tile * p.rows_per_tile;
@@ -113,12 +116,17 @@ __global__ __launch_bounds__(256) void k_xform_copy(const Tin* __restrict__ src,
     for (int64_t c = c_begin + static_cast<int64_t>(lane) * V; c < c_end; c += step) {
       double x[V];
       if constexpr (V == 1) {
-        x[0] = static_cast<double>(src[s0 + c * p.run_ss]);
+        x[0] = live ? static_cast<double>(src[s0 + c * p.run_ss]) : 0.0;
         store_vec<OUT, 1>(dst, d0 + c * p.run_ds, p.plane, x);
       } else {
-        const VecT<Tin, V> in = *reinterpret_cast<const VecT<Tin, V>*>(src + s0 + c);
+        if (live) {
+          const VecT<Tin, V> in = *reinterpret_cast<const VecT<Tin, V>*>(src + s0 + c);
 #pragma unroll
-        for (int i = 0; i < V; ++i) x[i] = static_cast<double>(in.v[i]);
+          for (int i = 0; i < V; ++i) x[i] = static_cast<double>(in.v[i]);
+        } else {
+#pragma unroll
+          for (int i = 0; i < V; ++i) x[i] = 0.0;
+        }
         store_vec<OUT, V>(dst, d0 + c, p.plane, x);
       }
     }
@@ -153,7 +161,8 @@ __global__ __launch_bounds__(256) void k_xform_transpose(const Tin* __restrict__
   const int64_t ta = rem % p.tiles_run;
   int64_t row = rem / p.tiles_run;
   int64_t sb, ab;
-  block_bases(p, blk, sb, ab);
+  const bool live = block_bases(p, blk, sb, ab);
+  if (!live && !p.to_aligned) return;             // as in k_xform_copy
   int64_t so = p.to_aligned ? sb : ab;
   int64_t dof = p.to_aligned ? ab : sb;
   for (int i = p.nbatch - 1; i >= 0; --i) {
@@ -178,7 +187,7 @@ __global__ __launch_bounds__(256) void k_xform_transpose(const Tin* __restrict__
   const int y = t >> 6;
   if (x < na) {
     const int64_t sx = so + a_src[x];
-    for (int j = y; j < nb; j += 4) tile[j][x] = static_cast<double>(src[sx + b_src[j]]);
+    for (int j = y; j < nb; j += 4) tile[j][x] = live ? static_cast<double>(src[sx + b_src[j]]) : 0.0;
   }
   __syncthreads();
   if (x < nb) {

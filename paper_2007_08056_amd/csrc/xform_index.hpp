@@ -48,41 +48,58 @@ __host__ __device__ inline int dg_times(const GroupDesc& g, int c, int a) {
 }
 
 // Sector labels of one group's modes: the stored ones are the digits of
-// `digits` (base |G|, first most significant); the last one solves the
-// group's delta.  The deltas hold on charges: with charge tables `chg`
-// ([mode][label -> charge | charge -> label][|G|], nullptr for identity) the
-// stored labels are mapped to charges and the solved charge back to a label.
-__host__ __device__ inline void fill_sectors(const GroupDesc& g, const SectorGroup& sg,
+// `digits` (mixed radix over the members' sector counts, first most
+// significant); the last one solves the group's delta.  The deltas hold on
+// charges: with charge tables `chg` ([mode][label -> charge | charge -> label]
+// [|G|], nullptr for identity) the stored labels are mapped to charges and the
+// solved charge back to a label.  A subgroup member (H < |G| sectors,
+// coefficient +-|G|/H; cyclic groups only) adds mag * label; as the last
+// member its equation s mag x == r has a solution only when mag divides r.
+// Returns false when the block does not exist.
+__host__ __device__ inline bool fill_sectors(const GroupDesc& g, const SectorGroup& sg,
                                              int64_t digits, int q, int* S, const int32_t* chg) {
-  if (sg.count == 0) return;        // an empty group only pins Q
+  if (sg.count == 0) return true;   // an empty group only pins Q
   int acc = 0;
   for (int i = sg.count - 2; i >= 0; --i) {
-    const int d = static_cast<int>(digits % g.size);
-    digits /= g.size;
+    const int d = static_cast<int>(digits % sg.rad[i]);
+    digits /= sg.rad[i];
     S[sg.pos[i]] = d;
-    const int c = chg ? chg[(2 * sg.pos[i]) * g.size + d] : d;
+    int c = chg ? chg[(2 * sg.pos[i]) * g.size + d] : d;
+    if (sg.mag[i] != 1) c = (sg.mag[i] * c) % g.size;
     acc = dg_add(g, acc, dg_times(g, sg.coef[i], c));
   }
   const int rhs = dg_add(g, dg_times(g, sg.alpha, q), sg.beta);
-  const int last = sg.pos[sg.count - 1];
-  const int c = dg_times(g, sg.coef[sg.count - 1], dg_add(g, rhs, dg_neg(g, acc)));
+  const int n = sg.count - 1;
+  const int last = sg.pos[n];
+  const int r = dg_add(g, rhs, dg_neg(g, acc));
+  if (sg.mag[n] != 1) {
+    if (r % sg.mag[n] != 0) return false;
+    const int x = r / sg.mag[n];
+    S[last] = sg.coef[n] >= 0 || x == 0 ? x : sg.rad[n] - x;
+    return true;
+  }
+  const int c = dg_times(g, sg.coef[n], r);
   S[last] = chg ? chg[(2 * last + 1) * g.size + c] : c;
+  return true;
 }
 
-// Aligned block index -> (standard-form element offset, aligned element offset).
-__host__ __device__ inline void block_bases(const XformParams& p, int64_t blk, int64_t& std_base,
+// Aligned block index -> (standard-form element offset, aligned element
+// offset); false when the block does not exist (its aligned block is zero).
+__host__ __device__ inline bool block_bases(const XformParams& p, int64_t blk, int64_t& std_base,
                                             int64_t& al_base) {
   const int64_t cs = blk % p.gpow_col;
   const int64_t t = blk / p.gpow_col;
   const int64_t rs = t % p.gpow_row;
-  const int q = p.q_pin >= 0 ? p.q_pin : static_cast<int>(t / p.gpow_row);
+  const int64_t slice = t / p.gpow_row;
+  const int q = p.q0 + p.q_step * static_cast<int>(slice);
+  al_base = (p.q_full ? q : slice) * p.q_stride + rs * p.rs_stride + cs * p.cs_stride;
   int S[kMaxOrder];
-  fill_sectors(p.g, p.row, rs, q, S, p.chg);
-  fill_sectors(p.g, p.col, cs, q, S, p.chg);
+  std_base = 0;
+  if (!fill_sectors(p.g, p.row, rs, q, S, p.chg) || !fill_sectors(p.g, p.col, cs, q, S, p.chg)) return false;
   int64_t sb = 0;
-  for (int m = 0; m < p.order - 1; ++m) sb = sb * p.g.size + S[m];
+  for (int m = 0; m < p.order - 1; ++m) sb = sb * p.hs[m] + S[m];
   std_base = sb * p.blk_elems;
-  al_base = q * p.q_stride + rs * p.rs_stride + cs * p.cs_stride;
+  return true;
 }
 
 // Entry i of an offset table for auxiliary sector q: the group's stored sectors
@@ -92,7 +109,7 @@ __host__ __device__ inline int64_t group_offset(const OffsetParams& p, int q, in
   int64_t digits = i / p.n_inner;
   int64_t inner = i - digits * p.n_inner;
   int S[kMaxOrder];
-  fill_sectors(p.g, p.grp, digits, q, S, p.chg);
+  (void)fill_sectors(p.g, p.grp, digits, q, S, p.chg);   // offset tables: no subgroup modes
   int64_t off = 0;
   for (int j = p.grp.count - 1; j >= 0; --j) {
     const int64_t d = inner % p.dim[j];

@@ -53,20 +53,30 @@ class SymTensor:
 
     ``mode_charges`` optionally gives, per mode, the charge carried by each
     sector label (a permutation of the group elements); None: every label is
-    its own charge (include/symtensor.h, symt_tensor).
+    its own charge (include/symtensor.h, symt_tensor).  ``sectors``
+    optionally gives each mode's number of sectors H_m, a divisor of |G|
+    (coefficient sign |G|/H_m); None: |G| each.
     """
     data: torch.Tensor
     signs: str
     charge: int
     group: tuple
     mode_charges: tuple | None = None
+    sectors: tuple | None = None
 
     def __post_init__(self):
         self.group = _group_tuple(self.group)
         n = len(self.signs)
         G = group_size(self.group)
-        if self.data.dim() != 2 * n - 1 or any(int(s) != G for s in self.data.shape[: n - 1]):
-            raise ValueError(f"reduced form must have shape [{G}]*{n - 1} + dims, got {tuple(self.data.shape)}")
+        if self.sectors is not None:
+            self.sectors = tuple(int(h) for h in self.sectors)
+            if len(self.sectors) != n:
+                raise ValueError(f"sectors must hold {n} counts")
+            if all(h == G for h in self.sectors):
+                self.sectors = None
+        hs = self.sectors or (G,) * n
+        if self.data.dim() != 2 * n - 1 or tuple(int(s) for s in self.data.shape[: n - 1]) != hs[: n - 1]:
+            raise ValueError(f"reduced form must have shape {list(hs[: n - 1])} + dims, got {tuple(self.data.shape)}")
         if self.data.dtype not in _DTYPE_CODE:
             raise TypeError("reduced form must be float64, float32, complex128 or complex64")
         self.charge = int(self.charge) % G
@@ -84,7 +94,7 @@ class SymTensor:
     def desc(self, data=None) -> L.TensorDesc:
         d = self.data if data is None else data
         return L.TensorDesc(self.signs, self.charge, self.dims, _DTYPE_CODE[d.dtype],
-                            d.data_ptr() if d.numel() else None, self.mode_charges)
+                            d.data_ptr() if d.numel() else None, self.mode_charges, self.sectors)
 
     def table(self, m):
         G = group_size(self.group)
@@ -125,8 +135,19 @@ def derived_charges(subscripts: str, u: SymTensor, v: SymTensor):
     return tuple(u.table(tu.index(m)) if m in tu else v.table(tv.index(m)) for m in tw)
 
 
+def derived_sectors(subscripts: str, u: SymTensor, v: SymTensor):
+    """Sector counts of the output: u's on its kept modes, v's on its kept modes."""
+    if u.sectors is None and v.sectors is None:
+        return None
+    G = group_size(u.group)
+    tu, rest = subscripts.split(",")
+    tv, tw = rest.split("->")
+    hu, hv = u.sectors or (G,) * len(tu), v.sectors or (G,) * len(tv)
+    return tuple(hu[tu.index(m)] if m in tu else hv[tv.index(m)] for m in tw)
+
+
 def output_like(subscripts: str, u: SymTensor, v: SymTensor, dtype=None) -> SymTensor:
-    """A zero-filled output with the derived sign string, charge and charge tables."""
+    """A zero-filled output with the derived sign string, charge, charge tables and sector counts."""
     info = plan(subscripts, u, v)
     tu, rest = subscripts.split(",")
     tv, tw = rest.split("->")
@@ -134,10 +155,12 @@ def output_like(subscripts: str, u: SymTensor, v: SymTensor, dtype=None) -> SymT
     for m in tw:
         dims.append(u.dims[tu.index(m)] if m in tu else v.dims[tv.index(m)])
     G = group_size(u.group)
-    shape = [G] * (len(tw) - 1) + dims
+    hs = derived_sectors(subscripts, u, v) or (G,) * len(tw)
+    shape = list(hs[: len(tw) - 1]) + dims
     dtype = dtype or u.data.dtype
     data = torch.zeros(shape, dtype=dtype, device=u.data.device)
-    return SymTensor(data, info.w_signs.decode(), info.w_charge, u.group, derived_charges(subscripts, u, v))
+    return SymTensor(data, info.w_signs.decode(), info.w_charge, u.group, derived_charges(subscripts, u, v),
+                     derived_sectors(subscripts, u, v))
 
 
 def contract_into(subscripts: str, u: SymTensor, v: SymTensor, w: SymTensor, compute: str = "f64",
@@ -174,7 +197,7 @@ class _Contract(torch.autograd.Function):
     def forward(ctx, subscripts, meta_u, meta_v, meta_w, compute, ud, vd):
         u = SymTensor(ud, *meta_u)
         v = SymTensor(vd, *meta_v)
-        w = SymTensor(torch.empty(meta_w[4], dtype=ud.dtype, device=ud.device), *meta_w[:4])
+        w = SymTensor(torch.empty(meta_w[5], dtype=ud.dtype, device=ud.device), *meta_w[:5])
         contract_into(subscripts, u, v, w, compute)
         ctx.save_for_backward(ud, vd)
         ctx.meta = (subscripts, meta_u, meta_v, meta_w, compute)
@@ -185,7 +208,7 @@ class _Contract(torch.autograd.Function):
         subscripts, meta_u, meta_v, meta_w, compute = ctx.meta
         ud, vd = ctx.saved_tensors
         tu, tv, tw = _swap(subscripts)
-        dW = SymTensor(gw.contiguous().to(ud.dtype), *meta_w[:4])
+        dW = SymTensor(gw.contiguous().to(ud.dtype), *meta_w[:5])
         # complex operands: gradients with respect to the conjugate (Wirtinger),
         # so the other factor enters conjugated
         conj = (lambda t: t.conj().resolve_conj()) if ud.is_complex() else (lambda t: t)
@@ -213,13 +236,14 @@ def einsum(subscripts: str, u: SymTensor, v: SymTensor, compute: str = "f64") ->
     tu, tv, tw = _swap(subscripts)
     dims = [u.dims[tu.index(m)] if m in tu else v.dims[tv.index(m)] for m in tw]
     G = group_size(u.group)
-    shape = tuple([G] * (len(tw) - 1) + dims)
-    meta_u = (u.signs, u.charge, u.group, u.mode_charges)
-    meta_v = (v.signs, v.charge, v.group, v.mode_charges)
+    ws = derived_sectors(subscripts, u, v)
+    shape = tuple(list((ws or (G,) * len(tw))[: len(tw) - 1]) + dims)
+    meta_u = (u.signs, u.charge, u.group, u.mode_charges, u.sectors)
+    meta_v = (v.signs, v.charge, v.group, v.mode_charges, v.sectors)
     wc = derived_charges(subscripts, u, v)
-    meta_w = (info.w_signs.decode(), info.w_charge, u.group, wc, shape)
+    meta_w = (info.w_signs.decode(), info.w_charge, u.group, wc, ws, shape)
     wd = _Contract.apply(subscripts, meta_u, meta_v, meta_w, compute, u.data, v.data)
-    return SymTensor(wd, meta_w[0], meta_w[1], u.group, wc)
+    return SymTensor(wd, meta_w[0], meta_w[1], u.group, wc, ws)
 
 
 # ---------------------------------------------------------------------------

@@ -39,6 +39,7 @@ class Operand:
     dist: int = DIST_UNIFORM
     scale: float = 1.0
     tensor_id: int = 0
+    sectors: tuple | None = None   # sectors per mode (a divisor of |G|); None: |G| each
 
     @property
     def order(self) -> int:
@@ -73,14 +74,18 @@ class Workload:
 
     def reduced_shape(self, name: str) -> tuple:
         op = self.operands[name]
-        return (self.group_size,) * (op.order - 1) + tuple(op.dims)
+        hs = op.sectors or (self.group_size,) * op.order
+        return tuple(hs[: op.order - 1]) + tuple(op.dims)
 
 
-def _ladder(name, G, nv, no, cid):
+def _ladder(name, G, nv, no, cid, h_ab=None):
+    # h_ab: sectors of the external virtual modes a, b (a subgroup of Z_G), or all |G|
+    sv = (h_ab, h_ab, G, G) if h_ab else None
+    sw = (h_ab, h_ab, G, G) if h_ab else None
     ops = {
-        "V": Operand("V", "abcd", "++--", 0, (nv, nv, nv, nv), DIST_NORMAL, 1.0, cid * 16 + 0),
+        "V": Operand("V", "abcd", "++--", 0, (nv, nv, nv, nv), DIST_NORMAL, 1.0, cid * 16 + 0, sv),
         "T": Operand("T", "cdij", "++--", 0, (nv, nv, no, no), DIST_NORMAL, 1e-2, cid * 16 + 1),
-        "W": Operand("W", "abij", "++--", 0, (nv, nv, no, no)),
+        "W": Operand("W", "abij", "++--", 0, (nv, nv, no, no), sectors=sw),
     }
     return Workload(name, (G,), ops, (Contraction("abcd,cdij->abij", "V", "T", "W"),),
                     ("V", "T"), "W")
@@ -99,6 +104,11 @@ def plain_z4() -> Workload:
 
 def ccd_ladder_z8() -> Workload:
     return _ladder("ccd_ladder_z8", 8, 24, 6, 1)
+
+
+def ccd_ladder_z8_sub() -> Workload:
+    """The Z_8 ladder with a and b in the Z_4 subgroup (4 sectors, coefficient 2)."""
+    return _ladder("ccd_ladder_z8_sub", 8, 24, 6, 5, h_ab=4)
 
 
 def ccd_ladder_z16() -> Workload:
@@ -188,6 +198,7 @@ ALL = {
     "mps_env_z2z3": mps_env_z2z3,
     "ccd_ladder_z16": ccd_ladder_z16,
     "mps_env_grad": mps_env_grad,
+    "ccd_ladder_z8_sub": ccd_ladder_z8_sub,
 }
 
 
@@ -204,6 +215,7 @@ def scaled(wl: Workload, dims_map: dict) -> Workload:
     ops = {}
     for k, op in wl.operands.items():
         dims = tuple(dims_map.get(m, d) for m, d in zip(op.modes, op.dims))
-        ops[k] = Operand(op.name, op.modes, op.signs, op.charge, dims, op.dist, op.scale, op.tensor_id)
+        ops[k] = Operand(op.name, op.modes, op.signs, op.charge, dims, op.dist, op.scale, op.tensor_id,
+                         op.sectors)
     return Workload(wl.name + "_scaled", wl.group, ops, wl.steps, wl.inputs, wl.output, wl.seed,
                     dict(wl.extra))

@@ -116,3 +116,34 @@ def random_case(rng, orders, s, t, v, nmax=3, nmin=1, sigma=None, dim_choices=No
     su = O.Sym(tuple(cu[m] for m in tu), int(rng.integers(g.size)), tuple(dims[m] for m in tu), g)
     sv = O.Sym(tuple(cv[m] for m in tv), int(rng.integers(g.size)), tuple(dims[m] for m in tv), g)
     return f"{''.join(tu)},{''.join(tv)}->{''.join(tw)}", su, sv
+
+
+def subgroup_case(rng, G, s, t, v, nmax=3):
+    """A random contraction over Z_G whose modes have random sector counts H | G
+    (coefficient sign G/H, Sec. 2.2), contracted modes sharing theirs, with total
+    charges that some sector combination reaches."""
+    g = O.Group(G)
+    letters = iter("abcdefghijklmnop")
+    I = [next(letters) for _ in range(s)]
+    K = [next(letters) for _ in range(v)]
+    J = [next(letters) for _ in range(t)]
+    tu = list(I + K); rng.shuffle(tu)
+    tv = list(K + J); rng.shuffle(tv)
+    tw = list(I + J); rng.shuffle(tw)
+    divs = [h for h in range(1, G + 1) if G % h == 0]
+    hs = {m: int(rng.choice(divs)) for m in I + K + J}
+    dims = {m: int(rng.integers(1, nmax + 1)) for m in I + K + J}
+    cu = {m: int(rng.choice([-1, 1])) for m in tu}
+    sigma = int(rng.choice([-1, 1]))
+    cv = {m: (sigma * cu[m] if m in K else int(rng.choice([-1, 1]))) for m in tv}
+
+    def reach(term, c):
+        return sum(c[m] * (G // hs[m]) * int(rng.integers(hs[m])) for m in term) % G
+    su = O.Sym.make([cu[m] for m in tu], reach(tu, cu), [dims[m] for m in tu], g, sectors=[hs[m] for m in tu])
+    sv = O.Sym.make([cv[m] for m in tv], reach(tv, cv), [dims[m] for m in tv], g, sectors=[hs[m] for m in tv])
+    return f"{''.join(tu)},{''.join(tv)}->{''.join(tw)}", su, sv
+
+
+def dead_stored_tuples(sym):
+    """Stored-sector tuples of the standard reduced form that hold no block."""
+    return [st for st in O.stored_tuples(sym) if O.full_sectors(sym, st) is None]

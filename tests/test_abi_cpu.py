@@ -39,10 +39,11 @@ def test_plan_matches_oracle_on_workloads(name):
     g = O.Group(wl.group)
     for st in wl.steps:
         ou, ov, ow = (wl.operands[x] for x in (st.u, st.v, st.w))
-        su = O.Sym.make(ou.signs, ou.charge, ou.dims, g)
-        sv = O.Sym.make(ov.signs, ov.charge, ov.dims, g)
-        rc, info = _plan(st.einsum, wl.group, _desc(ou.signs, ou.charge, ou.dims),
-                         _desc(ov.signs, ov.charge, ov.dims), _desc(ow.signs, ow.charge, ow.dims))
+        su = O.Sym.make(ou.signs, ou.charge, ou.dims, g, sectors=ou.sectors)
+        sv = O.Sym.make(ov.signs, ov.charge, ov.dims, g, sectors=ov.sectors)
+        rc, info = _plan(st.einsum, wl.group, _sdesc(ou.signs, ou.charge, ou.dims, ou.sectors),
+                         _sdesc(ov.signs, ov.charge, ov.dims, ov.sectors),
+                         _sdesc(ow.signs, ow.charge, ow.dims, ow.sectors))
         assert rc == 0, L.last_error()
         G, M, K, N = O.aligned_shape(st.einsum, su, sv)
         assert (info.group_size, info.m, info.k, info.n) == (G, M, K, N)
@@ -55,7 +56,7 @@ def test_plan_matches_oracle_on_workloads(name):
         k_modes = [m for m in tu if m in tv]
         trailing = tu.endswith("".join(k_modes))
         nK = int(np.prod([ou.dims[tu.index(m)] for m in k_modes]))
-        assert info.fused == int(trailing and nK % 16 == 0)
+        assert info.fused == int(trailing and nK % 16 == 0 and su.sectors is None and sv.sectors is None)
         G = info.group_size
         if info.fused:
             # V aligned plus four offset tables of U and W
@@ -285,3 +286,58 @@ def test_complex_planning():
     assert _plan("ak,kb->ab", G, _desc("+-", 1, (3, 5)), _desc("+-", 2, (5, 6)),
                  _desc(sig, info.w_charge, (3, 6), L.SYMT_C64))[0] == L.SYMT_EDTYPE
     assert _plan("ak,kb->ab", G, _desc("+-", 1, (3, 5), 7), v)[0] == L.SYMT_EDTYPE
+
+
+def _sdesc(signs, charge, dims, sectors, dtype=L.SYMT_F64):
+    return L.TensorDesc(signs, charge, dims, dtype, None, None, sectors)
+
+
+def test_subgroup_sector_counts_planning():
+    G = 6
+    # a: 3 sectors (c = 2), k: 2 sectors (c = 3), b: 6 sectors
+    u = _sdesc("+-", 2, (2, 3), (3, 2))
+    v = _sdesc("+-", 3, (3, 4), (2, 6))
+    rc, info = _plan("ak,kb->ab", G, u, v)
+    assert rc == 0
+    # stored-sector radices: I and K have one mode each, so M = n_a, K = n_k, N = n_b
+    assert (info.m, info.k, info.n) == (2, 3, 4) and info.fused == 0
+    assert info.elems_u == 3 * 2 * 3 and info.elems_v == 2 * 3 * 4
+    rc, info2 = _plan("abk,kc->abc", G, _sdesc("++-", 0, (2, 2, 3), (3, 2, 2)), _sdesc("+-", 0, (3, 4), (2, 6)))
+    assert rc == 0 and info2.m == 3 * 2 * 2          # a (3 sectors) stored, b implicit
+    # counts must divide |G|
+    assert _plan("ak,kb->ab", G, _sdesc("+-", 2, (2, 3), (4, 2)), v)[0] == L.SYMT_EINVAL
+    # a contracted mode carries one count
+    assert _plan("ak,kb->ab", G, u, _sdesc("+-", 3, (3, 4), (3, 6)))[0] == L.SYMT_ESYM
+    # w carries the derived counts (NULL stands for |G| everywhere)
+    sig = info.w_signs.decode()
+    assert _plan("ak,kb->ab", G, u, v, _sdesc(sig, info.w_charge, (2, 4), (3, 6)))[0] == 0
+    assert _plan("ak,kb->ab", G, u, v, _desc(sig, info.w_charge, (2, 4)))[0] == L.SYMT_ESYM
+    # a cyclic group and no charge tables
+    assert _plan("ak,kb->ab", (2, 3), _sdesc("+-", 2, (2, 3), (3, 2)), _sdesc("+-", 3, (3, 4), (2, 6)))[0] \
+        == L.SYMT_EUNSUPPORTED
+    tab = [[1, 0, 2, 3, 4, 5], [0, 1, 2, 3, 4, 5]]          # a relabelled, k identity
+    withtab = L.TensorDesc("+-", 2, (2, 3), L.SYMT_F64, None, tab, (3, 2))
+    assert _plan("ak,kb->ab", G, withtab, v)[0] == L.SYMT_EUNSUPPORTED
+    # all counts |G| is the plain case
+    rc, plain = _plan("ak,kb->ab", G, _sdesc("+-", 2, (2, 16), (6, 6)), _sdesc("+-", 3, (16, 4), (6, 6)))
+    assert rc == 0 and plain.fused == 1
+    rc, sub = _plan("ak,kb->ab", G, _sdesc("+-", 2, (2, 16), (3, 6)), _sdesc("+-", 3, (16, 4), (6, 6)))
+    assert rc == 0 and sub.fused == 0
+
+
+@pytest.mark.parametrize("G,s,t,v", [(4, 1, 1, 1), (6, 2, 1, 1), (8, 1, 2, 1), (12, 1, 1, 2), (6, 2, 2, 1),
+                                     (6, 1, 1, 0), (4, 0, 2, 1), (6, 2, 0, 1), (5, 1, 1, 1)])
+def test_live_slices_match_the_oracles_nonzero_slices(G, s, t, v):
+    """The planner multiplies only the Q slices where all three deltas can hold:
+    exactly those where the oracle's U_al and V_al (random data) are both nonzero."""
+    from tests import gpu_helpers as H
+    rng = np.random.default_rng(abs(hash(("live", G, s, t, v))) % 2 ** 31)
+    for _ in range(4):
+        sub, su, sv = H.subgroup_case(rng, G, s, t, v, nmax=2)
+        Ru, Rv = rng.standard_normal(su.reduced_shape()), rng.standard_normal(sv.reduced_shape())
+        Ual, Val = O.align_u(sub, Ru, su, sv), O.align_v(sub, Rv, su, sv)
+        live = sum(1 for q in range(G) if np.any(Ual[q] != 0) and np.any(Val[q] != 0))
+        rc, info = _plan(sub, G, _sdesc(su.sign_string(), su.charge, su.dims, su.sectors),
+                         _sdesc(sv.sign_string(), sv.charge, sv.dims, sv.sectors))
+        assert rc == 0
+        assert info.flops == 2 * live * info.m * info.k * info.n

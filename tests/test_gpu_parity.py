@@ -40,7 +40,7 @@ def SG():
 
 def _sym_tensor(P, R: np.ndarray, sym: O.Sym, dtype=torch.float64):
     return P.SymTensor(torch.from_numpy(np.ascontiguousarray(R)).to(DEV, dtype), sym.sign_string(),
-                       sym.charge, sym.group.orders, sym.charges)
+                       sym.charge, sym.group.orders, sym.charges, sym.sectors)
 
 
 # ---------------------------------------------------------------------------
@@ -708,3 +708,84 @@ def test_complex_gradients_vs_dense_autograd(P, orders, s, t, v):
         ref, zero_ok = O.reduce_full(dense.numpy(), sym)
         assert zero_ok
         assert H.rel_err(H.to_np(got), ref) <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Subgroup modes (Sec. 2.2, Eq. symtsr with c_i = +-G/H_i): against the oracle
+# in three precisions; stored tuples of W without a block come out zero; the
+# standalone transforms bit-exact against Alg. 2 with dense deltas (aligned
+# blocks without a standard block are zero); complex operands; gradients.
+# ---------------------------------------------------------------------------
+SUBGROUP_CASES = [(4, 1, 1, 1), (6, 2, 1, 1), (8, 1, 2, 1), (12, 1, 1, 2), (6, 2, 2, 1),
+                  (6, 1, 1, 0), (4, 0, 2, 1), (6, 2, 0, 1)]
+
+
+@pytest.mark.parametrize("G,s,t,v", SUBGROUP_CASES)
+def test_subgroup_contractions_vs_oracle(P, G, s, t, v):
+    rng = np.random.default_rng(abs(hash(("subgroup-gpu", G, s, t, v))) % 2 ** 31)
+    for trial in range(3):
+        sub, su, sv = H.subgroup_case(rng, G, s, t, v, nmax=5)
+        say(f"subgroup {sub} G={G} sectors {su.sectors} {sv.sectors}")
+        Ru, Rv = rng.standard_normal(su.reduced_shape()), rng.standard_normal(sv.reduced_shape())
+        ref, sw = O.contract_blocks(sub, Ru, su, Rv, sv)
+        absref, _ = O.contract_blocks(sub, np.abs(Ru), su, np.abs(Rv), sv)
+        u, v_ = _sym_tensor(P, Ru, su), _sym_tensor(P, Rv, sv)
+        Gs, M, K, N = O.aligned_shape(sub, su, sv)
+        info = P.plan(sub, u, v_)
+        assert (info.m, info.k, info.n) == (M, K, N) and info.fused == 0
+        dead = H.dead_stored_tuples(sw)
+        for compute in ("f64", "f32", "bf16x3"):
+            if compute == "bf16x3" and K % 8:
+                continue
+            w = P.output_like(sub, u, v_)
+            assert w.sectors == sw.sectors
+            w.data.fill_(7.0)
+            P.contract_into(sub, u, v_, w, compute)
+            got = H.to_np(w.data)
+            assert np.all(np.abs(got - ref) <= H.bound_factor(compute, K) * absref + 1e-300), compute
+            assert all(np.all(got[st] == 0) for st in dead), compute
+            if compute == "f64":
+                assert H.rel_err(got, ref) <= 1e-12 or np.max(np.abs(ref)) == 0
+        if trial == 0:
+            Ual, Val = O.align_u(sub, Ru, su, sv), O.align_v(sub, Rv, su, sv)
+            for op, ref_al in ((0, Ual), (1, Val)):
+                buf = torch.full(ref_al.shape, float("nan"), dtype=torch.float64, device=DEV)
+                assert np.array_equal(H.to_np(P.align(sub, u, v_, op, "f64", out=buf)), ref_al), op
+            Wal = np.matmul(Ual, Val)
+            ref_w, _ = O.unalign_w(sub, Wal, su, sv)
+            w = P.output_like(sub, u, v_)
+            w.data.fill_(3.0)
+            P.unalign(sub, u, v_, w, torch.from_numpy(Wal).to(DEV), "f64")
+            assert np.array_equal(H.to_np(w.data), ref_w)
+        if trial == 1:
+            Cu = Ru + 1j * rng.standard_normal(su.reduced_shape())
+            Cv = Rv + 1j * rng.standard_normal(sv.reduced_shape())
+            cref, _ = O.contract_blocks(sub, Cu, su, Cv, sv)
+            w = P.output_like(sub, _sym_tensor(P, Cu, su, torch.complex128), _sym_tensor(P, Cv, sv, torch.complex128))
+            P.contract_into(sub, _sym_tensor(P, Cu, su, torch.complex128), _sym_tensor(P, Cv, sv, torch.complex128), w)
+            assert H.rel_err(H.to_np(w.data), cref) <= 1e-12 or np.max(np.abs(cref)) == 0
+
+
+@pytest.mark.parametrize("G,s,t,v", [(6, 1, 1, 1), (4, 2, 1, 1)])
+def test_subgroup_gradients_vs_dense_autograd(P, G, s, t, v):
+    rng = np.random.default_rng(abs(hash(("subgroup-grad", G, s, t, v))) % 2 ** 31)
+    sub, su, sv = H.subgroup_case(rng, G, s, t, v, nmax=4)
+    say(f"subgroup gradient {sub} G={G}")
+    Ru, Rv = rng.standard_normal(su.reduced_shape()), rng.standard_normal(sv.reduced_shape())
+    sw = O.output_symmetry(sub, su, sv)
+    Rr = rng.standard_normal(sw.reduced_shape())
+    ud = torch.from_numpy(Ru).to(DEV).requires_grad_(True)
+    vd = torch.from_numpy(Rv).to(DEV).requires_grad_(True)
+    w = P.einsum(sub, P.SymTensor(ud, su.sign_string(), su.charge, G, None, su.sectors),
+                 P.SymTensor(vd, sv.sign_string(), sv.charge, G, None, sv.sectors))
+    (w.data * torch.from_numpy(Rr).to(DEV)).sum().backward()
+    du = torch.from_numpy(O.expand(Ru, su)).requires_grad_(True)
+    dv = torch.from_numpy(O.expand(Rv, sv)).requires_grad_(True)
+    (torch.einsum(sub, du, dv) * torch.from_numpy(O.expand(Rr, sw))).sum().backward()
+    for got, dense, sym in ((ud.grad, du.grad, su), (vd.grad, dv.grad, sv)):
+        ref, zero_ok = O.reduce_full(dense.numpy(), sym)
+        assert zero_ok
+        g = H.to_np(got)
+        for st in H.dead_stored_tuples(sym):
+            g[st] = 0.0          # entries without a block carry no gradient meaning
+        assert H.rel_err(g, ref) <= 1e-12

@@ -342,9 +342,9 @@ def test_workload_output_signs_are_the_derived_ones(name):
     g = O.Group(wl.group)
     for st in wl.steps:
         ou, ov, ow = (wl.operands[x] for x in (st.u, st.v, st.w))
-        su = O.Sym.make(ou.signs, ou.charge, ou.dims, g)
-        sv = O.Sym.make(ov.signs, ov.charge, ov.dims, g)
-        sw = O.Sym.make(ow.signs, ow.charge, ow.dims, g)
+        su = O.Sym.make(ou.signs, ou.charge, ou.dims, g, sectors=ou.sectors)
+        sv = O.Sym.make(ov.signs, ov.charge, ov.dims, g, sectors=ov.sectors)
+        sw = O.Sym.make(ow.signs, ow.charge, ow.dims, g, sectors=ow.sectors)
         assert O.same_symmetry(O.output_symmetry(st.einsum, su, sv), sw)
 
 
