@@ -410,18 +410,24 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   // ---- fused product: A read from U's standard form along contiguous K runs
   // (U's last v modes are its contracted modes and their block holds whole
   // K-depths), C written straight into W's standard form.
-  const int want = compute == SYMT_COMPUTE_F64 ? SYMT_F64 : SYMT_F32;
+  // Complex operands read and write their interleaved pairs as reals (a K run
+  // of nK pairs is 2 nK reals).  Every product tile reads one K-step from one
+  // run: 16 reals on the register tiles, one 128-byte row (16 f64 or 32 f32)
+  // on the global-to-LDS tiles.
+  const int want = p->cplx ? (compute == SYMT_COMPUTE_F64 ? SYMT_C128 : SYMT_C64)
+                           : (compute == SYMT_COMPUTE_F64 ? SYMT_F64 : SYMT_F32);
   bool trailing_k = true;
   for (int i = 0; i < p->v; ++i) trailing_k = trailing_k && p->posK_u[i] == p->U.n - p->v + i;
   const int vw = compute == SYMT_COMPUTE_F64 ? 2 : 4;
-  p->fused = !force_steps && !p->cplx && !p->subgroups && p->nq == p->g.size && compute != SYMT_COMPUTE_BF16X3 &&
-             p->U.dtype == want &&
-             (!w || p->W.dtype == want) && trailing_k && p->nK % kFpBK == 0 && p->N % vw == 0 &&
-             p->M > 0 && p->N > 0 && p->Kd > 0 && p->U.elems > 0;
+  const int64_t run = (p->cplx ? 2 : 1) * p->nK;
+  const int64_t step = 128 / (compute == SYMT_COMPUTE_F64 ? 8 : 4);
+  p->fused = !force_steps && !p->subgroups && p->nq == p->g.size && compute != SYMT_COMPUTE_BF16X3 &&
+             p->U.dtype == want && (!w || p->W.dtype == want) && trailing_k && run % kFpBK == 0 &&
+             run % step == 0 && p->gn % vw == 0 && p->M > 0 && p->N > 0 && p->Kd > 0 && p->U.elems > 0;
   if (p->fused) {
     const size_t G = static_cast<size_t>(p->g.size);
-    p->bytes_tables = round_up(8 * G * p->M, 256) * 2 + round_up(8 * G * p->Kd, 256) +
-                      round_up(8 * G * p->N, 256);
+    p->bytes_tables = round_up(8 * G * p->M, 256) * 2 + round_up(8 * G * p->gk, 256) +
+                      round_up(8 * G * p->gn, 256);
     p->workspace = round_up(p->ws_v_al, 256) + p->bytes_tables;
   }
   if (p->charges) {
@@ -604,7 +610,10 @@ OffsetParams make_offsets(const Plan& p, int operand, bool rows) {
     o.weight[i] = wsec[m];
     o.n_inner *= X.dims[m];
   }
-  o.count = o.gpow * o.n_inner;
+  // complex operands: offsets in reals; a column table lists (re, im) of each column
+  o.scale = p.cplx ? 2 : 1;
+  o.pairs = p.cplx && !rows ? 1 : 0;
+  o.count = o.gpow * o.n_inner * (o.pairs ? 2 : 1);
   return o;
 }
 

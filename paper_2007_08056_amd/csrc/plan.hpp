@@ -97,7 +97,9 @@ struct OffsetParams {
   SectorGroup grp;                  // the group's modes, coefficients and delta
   int64_t gpow;                     // |G|^(count-1): stored sector combinations
   int64_t n_inner;                  // product of the group's inner dims
-  int64_t count;                    // entries per Q = gpow * n_inner
+  int64_t count;                    // entries per Q = gpow * n_inner (x 2 with pairs)
+  int32_t scale;                    // reals per element: 2 for complex operands, else 1
+  int32_t pairs;                    // 1: column table of a complex operand, entry 2c + comp
   int64_t dim[kMaxOrder];           // inner dims of the group's modes (group order)
   int64_t stride[kMaxOrder];        // their standard-form strides
   int64_t weight[kMaxOrder];        // standard-form offset of one unit of each mode's sector

@@ -156,7 +156,7 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
   void* val = base;
   int64_t* ra = reinterpret_cast<int64_t*>(base + round_up(p.ws_v_al, 256));
   int64_t* ca = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(ra) + round_up(8 * G * p.M, 256));
-  int64_t* rc = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(ca) + round_up(8 * G * p.Kd, 256));
+  int64_t* rc = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(ca) + round_up(8 * G * p.gk, 256));
   int64_t* cc = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(rc) + round_up(8 * G * p.M, 256));
   std::string err;
   int rc_ = timed(ctx, 0, s, [&] {
@@ -177,8 +177,8 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
   if (rc_) return ctx_fail(ctx, rc_, err);
   if ((rc_ = do_align(ctx, p, 1, val, s, true, chg[1]))) return rc_;
   symt::FusedTables f{ra, ca, rc, cc, aligned16(p.U.data) ? 2 : 1};
-  char* part = reinterpret_cast<char*>(cc) + round_up(8 * G * p.N, 256);
-  return do_gemm(ctx, p.compute, p.g.size, p.M, p.Kd, p.N, p.U.data, val, p.W.data, s, &f,
+  char* part = reinterpret_cast<char*>(cc) + round_up(8 * G * p.gn, 256);
+  return do_gemm(ctx, p.compute, p.g.size, p.M, p.gk, p.gn, p.U.data, val, p.W.data, s, &f,
                  p.bytes_partial ? part : nullptr, p.bytes_partial);
 }
 

@@ -228,7 +228,7 @@ __global__ __launch_bounds__(256) void k_offsets(const OffsetBatch b) {
     const int64_t j = i - (t > 0 ? b.end[t - 1] : 0);
     const OffsetParams& p = b.t[t];
     const int q = static_cast<int>(j / p.count);
-    b.out[t][j] = group_offset(p, q, j - q * p.count);
+    b.out[t][j] = table_entry(p, q, j - q * p.count);
   }
 }
 

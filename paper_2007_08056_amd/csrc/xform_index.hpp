@@ -119,4 +119,16 @@ __host__ __device__ inline int64_t group_offset(const OffsetParams& p, int q, in
   return off;
 }
 
+// Entry i of an offset table for auxiliary sector q, in reals: complex
+// operands double every offset, and their column tables hold (re, im) of each
+// column at 2c, 2c + 1.
+__host__ __device__ inline int64_t table_entry(const OffsetParams& p, int q, int64_t i) {
+  int comp = 0;
+  if (p.pairs) {
+    comp = static_cast<int>(i & 1);
+    i >>= 1;
+  }
+  return p.scale * group_offset(p, q, i) + comp;
+}
+
 }  // namespace symt

@@ -341,3 +341,24 @@ def test_live_slices_match_the_oracles_nonzero_slices(G, s, t, v):
                          _sdesc(sv.sign_string(), sv.charge, sv.dims, sv.sectors))
         assert rc == 0
         assert info.flops == 2 * live * info.m * info.k * info.n
+
+
+def test_fused_needs_whole_k_steps_per_run():
+    """The global-to-LDS tiles read a 128-byte K-step (16 f64, 32 f32) from one run of
+    contracted indices: f32 needs runs of 32, complex operands count reals."""
+    G = 4
+    u16, v16 = _desc("+-+-", 0, (3, 5, 4, 4)), _desc("+-+-", 0, (4, 4, 4, 4))
+    assert _plan("abkl,klij->abij", G, u16, v16, compute=0)[1].fused == 1
+    f16, fv16 = _desc("+-+-", 0, (3, 5, 4, 4), L.SYMT_F32), _desc("+-+-", 0, (4, 4, 4, 4), L.SYMT_F32)
+    assert _plan("abkl,klij->abij", G, f16, fv16, compute=1)[1].fused == 0
+    f32, fv32 = _desc("+-+-", 0, (3, 5, 4, 8), L.SYMT_F32), _desc("+-+-", 0, (4, 8, 4, 4), L.SYMT_F32)
+    assert _plan("abkl,klij->abij", G, f32, fv32, compute=1)[1].fused == 1
+    c16 = _desc("+-+-", 0, (3, 5, 4, 4), L.SYMT_C64)
+    cv16 = _desc("+-+-", 0, (4, 4, 4, 4), L.SYMT_C64)
+    assert _plan("abkl,klij->abij", G, c16, cv16, compute=1)[1].fused == 1      # 2 x 16 reals
+    c8 = _desc("+-+-", 0, (3, 5, 2, 4), L.SYMT_C128)
+    cv8 = _desc("+-+-", 0, (2, 4, 4, 4), L.SYMT_C128)
+    assert _plan("abkl,klij->abij", G, c8, cv8, compute=0)[1].fused == 1       # 2 x 8 reals
+    c8s = _desc("+-+-", 0, (3, 5, 2, 4), L.SYMT_C64)
+    cv8s = _desc("+-+-", 0, (2, 4, 4, 4), L.SYMT_C64)
+    assert _plan("abkl,klij->abij", G, c8s, cv8s, compute=1)[1].fused == 0

@@ -383,7 +383,18 @@ FUSED_CASES = [
     ("ak,kb->ba", (2, 3), "--", "-+", (17, 32), (32, 8)),
     ("xykcd,kcdz->zxy", (2,), "+-+--", "-++-", (3, 3, 2, 2, 4), (2, 2, 4, 8)),
     ("abcd,cdij->abij", (8,), "++--", "++--", (5, 6, 4, 4), (4, 4, 3, 2)),
+    ("abkl,klij->abij", (4,), "++--", "++--", (3, 5, 4, 8), (4, 8, 2, 3)),
+    ("akl,klb->ab", (3,), "+-+", "-++", (7, 2, 16), (2, 16, 12)),
 ]
+
+
+def _fusable(compute, sub, du):
+    # every product tile reads one K-step from one contiguous run of K: 16 reals,
+    # and 32 f32 on the global-to-LDS tiles
+    tu, rest = sub.split(",")
+    tv = rest.split("->")[0]
+    nK = int(np.prod([d for m, d in zip(tu, du) if m in tv]))
+    return nK % (16 if compute == "f64" else 32) == 0
 
 
 @pytest.mark.parametrize("case", FUSED_CASES)
@@ -400,7 +411,7 @@ def test_fused_product_equals_steps_and_oracle(P, case, compute):
     dt = torch.float64 if compute == "f64" else torch.float32
     u = _sym_tensor(P, Ru, su, dt)
     v = _sym_tensor(P, Rv, sv, dt)
-    assert P.plan(sub, u, v, compute).fused == 1
+    assert P.plan(sub, u, v, compute).fused == int(_fusable(compute, sub, du))
     assert P.plan(sub, u, v, compute, steps=True).fused == 0
     w_f = P.output_like(sub, u, v, dtype=dt)
     w_s = P.output_like(sub, u, v, dtype=dt)
@@ -789,3 +800,34 @@ def test_subgroup_gradients_vs_dense_autograd(P, G, s, t, v):
         for st in H.dead_stored_tuples(sym):
             g[st] = 0.0          # entries without a block carry no gradient meaning
         assert H.rel_err(g, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("case", [FUSED_CASES[0], FUSED_CASES[2], FUSED_CASES[5], FUSED_CASES[6]])
+@pytest.mark.parametrize("compute", ["f64", "f32"])
+def test_complex_fused_product_equals_steps_and_oracle(P, case, compute):
+    """Complex operands on the fused product: A read as interleaved reals from U's
+    standard form (K runs of 2 nK reals), C scattered into W's pairs."""
+    sub, orders, cu, cv, du, dv = case
+    rng = np.random.default_rng(len(sub) * 37 + sum(du))
+    g = O.Group(orders)
+    su = O.Sym.make(cu, int(rng.integers(g.size)), du, g)
+    sv = O.Sym.make(cv, int(rng.integers(g.size)), dv, g)
+    say(f"complex fused {sub} G={orders} {compute}")
+    Ru, Rv = _cplx(rng, su.reduced_shape()), _cplx(rng, sv.reduced_shape())
+    dt = torch.complex128 if compute == "f64" else torch.complex64
+    u, v = _sym_tensor(P, Ru, su, dt), _sym_tensor(P, Rv, sv, dt)
+    tu, rest = sub.split(",")
+    nK = int(np.prod([d for m, d in zip(tu, du) if m in rest.split("->")[0]]))
+    assert P.plan(sub, u, v, compute).fused == int((2 * nK) % (16 if compute == "f64" else 32) == 0)
+    w_f = P.output_like(sub, u, v, dtype=dt)
+    w_s = P.output_like(sub, u, v, dtype=dt)
+    P.contract_into(sub, u, v, w_f, compute)
+    P.contract_into(sub, u, v, w_s, compute, steps=True)
+    assert torch.equal(w_f.data, w_s.data)
+    ref, sw = O.contract_blocks(sub, H.to_np(u.data).astype(np.complex128), su,
+                                H.to_np(v.data).astype(np.complex128), sv)
+    absref, _ = O.contract_blocks(sub, np.abs(Ru), su, np.abs(Rv), sv)
+    k = 2 * H.contracted_extent(sub, su)
+    got = H.to_np(w_f.data).astype(np.complex128)
+    for part in (np.real, np.imag):
+        assert np.all(np.abs(part(got) - part(ref)) <= H.bound_factor(compute, k) * absref + 1e-300)
