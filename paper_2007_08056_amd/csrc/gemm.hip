@@ -425,8 +425,13 @@ __device__ __forceinline__ int64_t sk_bound(int64_t t, int64_t total, int nteam)
 // workgroups (teams_x teams of ts on each of the 8 XCDs, which receive
 // workgroups round-robin); a tile a team covers whole is written as usual,
 // the pieces of a cut tile go to `part` for k_sk_fixup.
+// Two-stage 96 x 96 tiles fit three workgroups per CU in LDS; ask the register
+// allocator for the matching three waves per SIMD.
+template <int BM, int BN, int S>
+constexpr int kDmaWavesPerSimd = (S == 2 && BM * BN <= 96 * 96) ? 3 : 1;
+
 template <typename T, int BM, int BN, int WM, int WN, int S, bool FA, bool FC, bool SK>
-__global__ __launch_bounds__(64 * WM * WN) void k_gemm_dma(
+__global__ __launch_bounds__(64 * WM * WN, (kDmaWavesPerSimd<BM, BN, S>)) void k_gemm_dma(
     const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C, int M, int N, int K,
     int tiles_m, int tiles_n, int64_t ntiles, const int64_t* __restrict__ ra,
     const int64_t* __restrict__ ca, const int64_t* __restrict__ rc, const int64_t* __restrict__ cc,
@@ -904,7 +909,9 @@ hipError_t launch_dma(int64_t batch, int M, int N, int K, const void* A, const v
         occ = 1;
       occupancy[f ? 1 : 0].store(occ, std::memory_order_relaxed);
     }
-    const int64_t slots = std::min<int64_t>(kSkSlots, static_cast<int64_t>(device_cus()) * occ);
+    // no more persistent workgroups than resident ones, nor than the pieces buffer holds
+    const int64_t fit = static_cast<int64_t>(part_bytes / (2 * static_cast<size_t>(BM) * BN * sizeof(T)));
+    const int64_t slots = std::min<int64_t>({kSkSlots, static_cast<int64_t>(device_cus()) * occ, fit});
     // Teams of tiles_n siblings when 8 XCDs hold at least one team each.
     const int64_t per_xcd = slots / 8;
     ts = (tiles_n <= per_xcd) ? tiles_n : 1;
@@ -962,7 +969,8 @@ hipError_t launch_fp_tile(int idx, int vec, int64_t batch, int M, int N, int K, 
     case 6: return launch_dma<T, 128, 128, 2, 2, 2>(batch, M, N, K, A, B, C, s, f, part, part_bytes);
     case 7: return launch_dma<T, 128, 96, 2, 2, 2>(batch, M, N, K, A, B, C, s, f, part, part_bytes);
     case 8: return launch_dma<T, 128, 64, 2, 2, 3>(batch, M, N, K, A, B, C, s, f, part, part_bytes);
-    default: return launch_dma<T, 96, 96, 2, 2, 3>(batch, M, N, K, A, B, C, s, f, part, part_bytes);
+    case 9: return launch_dma<T, 96, 96, 2, 2, 3>(batch, M, N, K, A, B, C, s, f, part, part_bytes);
+    default: return launch_dma<T, 96, 96, 2, 2, 2>(batch, M, N, K, A, B, C, s, f, part, part_bytes);
   }
 }
 

@@ -469,15 +469,18 @@ struct FpTile {
   int bm, bn;
   bool dma;
   double eff64, eff32;   // measured MFMA efficiency on a large, evenly tiled product
+  int wgs;               // resident workgroups per CU (global-to-LDS tiles)
 };
 // Efficiencies: 16 x 6144 x 2048 x 1152, a whole number of 256-tile waves for
 // every tile; f64 and f32.
 constexpr FpTile kFpTiles[] = {
-    {"128x128", 128, 128, false, 0.78, 0.78},  {"128x96", 128, 96, false, 0.75, 0.79},
-    {"128x64", 128, 64, false, 0.72, 0.78},    {"128x48", 128, 48, false, 0.74, 0.75},
-    {"96x96", 96, 96, false, 0.72, 0.77},      {"64x96", 64, 96, false, 0.73, 0.76},
-    {"d128x128s2", 128, 128, true, 0.87, 0.85}, {"d128x96s2", 128, 96, true, 0.86, 0.84},
-    {"d128x64s3", 128, 64, true, 0.84, 0.78},  {"d96x96s3", 96, 96, true, 0.86, 0.84},
+    {"128x128", 128, 128, false, 0.78, 0.78, 0},  {"128x96", 128, 96, false, 0.75, 0.79, 0},
+    {"128x64", 128, 64, false, 0.72, 0.78, 0},    {"128x48", 128, 48, false, 0.74, 0.75, 0},
+    {"96x96", 96, 96, false, 0.72, 0.77, 0},      {"64x96", 64, 96, false, 0.73, 0.76, 0},
+    {"d128x128s2", 128, 128, true, 0.87, 0.85, 2}, {"d128x96s2", 128, 96, true, 0.86, 0.84, 2},
+    {"d128x64s3", 128, 64, true, 0.84, 0.78, 2},  {"d96x96s3", 96, 96, true, 0.86, 0.84, 2},
+    // two stages: 48 KB of LDS, three workgroups (three waves per SIMD) per CU
+    {"d96x96s2", 96, 96, true, 0.875, 0.84, 3},
 };
 // Stream-K keeps this share of a tile's steady-state efficiency (B panels are
 // fetched at staggered K positions, pieces and their fixup); measured on the
@@ -516,7 +519,7 @@ GemmChoice choose_among(int64_t batch, int64_t M, int64_t N, int64_t K, int elem
       if (!sk) {
         time = static_cast<double>((tiles + 255) / 256) * t_tile;
       } else {
-        partial = 2 * static_cast<size_t>(kSkSlots) * t.bm * t.bn * elem;
+        partial = 2 * static_cast<size_t>(std::min(kSkSlots, 256 * t.wgs)) * t.bm * t.bn * elem;
         time = static_cast<double>(tiles) / 256.0 * t_tile / (elem == 8 ? kSkEff64 : kSkEff32) +
                2.0 * static_cast<double>(partial) / 5e12 +
                2 * 1.5e-6 + 5e-6;

@@ -194,8 +194,11 @@ struct GemmChoice {
                               // tiles evenly; tiles cut between two of them are summed after
   size_t partial_bytes = 0;   // stream-K workspace for the pieces of cut tiles
 };
-// Persistent workgroups of a stream-K product: 256 CUs x 2 resident workgroups.
-constexpr int kSkSlots = 512;
+// Most persistent workgroups of a stream-K product: 256 CUs x up to 3 resident
+// workgroups (the two-stage 96 x 96 tile).  The planner sizes the pieces
+// buffer (two pieces per workgroup) from each tile's resident workgroups; a
+// launch runs no more workgroups than that buffer holds.
+constexpr int kSkSlots = 768;
 // Fewest K-iterations a stream-K workgroup takes on (bounds the pieces per tile).
 constexpr int kSkMinIters = 4;
 GemmChoice choose_fp_gemm(int64_t batch, int64_t M, int64_t N, int64_t K, int elem, bool aligned);

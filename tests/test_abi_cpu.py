@@ -205,10 +205,11 @@ def test_stream_k_choice_and_workspace(monkeypatch):
     """Stream-K is chosen where whole waves of tiles would idle the device."""
     monkeypatch.delenv("SYMT_GEMM_SK", raising=False)
     monkeypatch.delenv("SYMT_GEMM_TILE", raising=False)
-    # CCD ladder over Z_8 (24 virtual, 6 occupied per sector): 864 tiles of 128 x 96
-    # on 256 CUs leave a last wave 3/8 full.
+    # CCD ladder over Z_8 (24 virtual, 6 occupied per sector): 1152 tiles of 96 x 96
+    # on 768 resident workgroups leave a last wave half full; two f64 pieces per
+    # persistent workgroup
     rc, ladder = _gemm_ws(L.COMPUTE["f64"], 8, 4608, 4608, 288)
-    assert rc == 0 and ladder > 0 and ladder % (2 * 512 * 8) == 0
+    assert rc == 0 and ladder == 2 * 768 * 96 * 96 * 8
     # 16384 tiles: whole waves, nothing to recover.
     assert _gemm_ws(L.COMPUTE["f64"], 16, 16384, 16384, 1024) == (0, 0)
     # split-bf16 and empty products never need it

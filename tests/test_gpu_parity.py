@@ -436,7 +436,7 @@ def test_fused_product_equals_steps_and_oracle(P, case, compute):
 @pytest.mark.parametrize("tile,sk", [("d128x128s2", "0"), ("d128x96s2", "0"), ("d128x64s3", "0"),
                                      ("d96x96s3", "0"), ("128x48", "0"), ("64x96", "0"),
                                      ("d128x128s2", "1"), ("d128x96s2", "1"), ("d128x64s3", "1"),
-                                     ("d96x96s3", "1")])
+                                     ("d96x96s3", "1"), ("d96x96s2", "0"), ("d96x96s2", "1")])
 @pytest.mark.parametrize("compute", ["f64", "f32"])
 def test_sector_gemm_every_tile_on_ragged_shapes(P, tile, sk, compute, monkeypatch):
     """Each tile shape, forced, on shapes that leave partial tiles in M and N;
