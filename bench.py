@@ -222,6 +222,28 @@ def time_workload(P, SG, wl, compute, steps, warmup, grad=False, cplx=False):
             "flops_per_step": flops, "steps_per_batch": batch}
 
 
+def dense_ms(wl, reps=3):
+    """The symmetry-oblivious baseline of the paper's G sweeps: one dense f64 einsum of
+    full tensors of the same shapes (every block materialised; values are random, the
+    time does not depend on them), through torch's vendor BLAS."""
+    import torch
+    st = wl.steps[0]
+    G = wl.group_size
+    full = lambda name: torch.randn([G * d for d in wl.operands[name].dims], dtype=torch.float64,  # noqa: E731
+                                    device="cuda:0")
+    u, v = full(st.u), full(st.v)
+    torch.einsum(st.einsum, u, v)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        torch.einsum(st.einsum, u, v)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    del u, v
+    torch.cuda.empty_cache()
+    return round(ms, 4)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,6 +255,8 @@ def main():
                     help="also time every workload in every precision (written to --extra)")
     ap.add_argument("--suite", action="store_true",
                     help="also time the paper's Table 2 suite at full size (written to --extra)")
+    ap.add_argument("--sweeps", action="store_true",
+                    help="also time the paper's (s, t, v) sweep and its G sweeps (written to --extra)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run one plain elementwise kernel that reads and writes 256 MiB "
                          "(the reference for scaling HBM byte counters)")
@@ -348,6 +372,29 @@ def main():
                 print(f"{key}: {r['ms_per_step']:.3f} ms, {r['tflops']:.1f} TFLOP/s", file=sys.stderr, flush=True)
                 torch.cuda.empty_cache()
         extra["workloads"] = table
+
+    if args.sweeps:
+        import synth as S
+        stv = {}
+        for case in S.configs.STV_CASES:
+            wlx = S.configs.stv_case(*case)
+            r = time_workload(P, SG, wlx, "f64", 3, 2)
+            r["einsum"], r["block_dim"] = wlx.steps[0].einsum, wlx.operands["U"].dims[0]
+            stv["".join(map(str, case))] = r
+            print(f"stv {case}: {r['ms_per_step']:.3f} ms, {r['tflops']:.1f} TFLOP/s", file=sys.stderr, flush=True)
+            torch.cuda.empty_cache()
+        extra["stv_sweep"] = stv
+        gs = {}
+        for fam, Gs in S.configs.G_SWEEP.items():
+            for G in Gs:
+                wlx = S.configs.g_sweep_case(fam, G)
+                r = time_workload(P, SG, wlx, "f64", 5, 2)
+                r["dense_ms"] = dense_ms(wlx)
+                gs[f"{fam}/G={G}"] = r
+                print(f"G sweep {fam} G={G}: {r['ms_per_step']:.3f} ms ({r['tflops']:.1f} TFLOP/s); "
+                      f"dense {r['dense_ms']:.3f} ms", file=sys.stderr, flush=True)
+                torch.cuda.empty_cache()
+        extra["g_sweep"] = gs
 
     if args.suite:
         import synth as S

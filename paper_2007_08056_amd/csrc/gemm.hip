@@ -90,7 +90,10 @@ struct alignas(sizeof(T) * V) VecT {
 // element (q, m, k) at ra[q*M + m] + ca[q*K + k], and C is written straight
 // into W's standard reduced form at rc[q*M + m] + cc[q*N + n] (separable offset
 // tables).  FA needs every BK-aligned run of K to be contiguous in U.
-template <typename T, int BM, int BN, int BK, int WM, int WN, int V, bool FA, bool FC>
+// SPLIT: gridDim.x = ntiles * splits; workgroup (tile, s) multiplies the s-th of
+// `splits` equal runs of K-steps and stores its partial tile in accumulator
+// order at part + (tile * splits + s) * BM * BN; k_split_sum adds them.
+template <typename T, int BM, int BN, int BK, int WM, int WN, int V, bool FA, bool FC, bool SPLIT = false>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
                                                        const T* __restrict__ B,
                                                        T* __restrict__ C, int M, int N, int K,
@@ -98,7 +101,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
                                                        const int64_t* __restrict__ ra,
                                                        const int64_t* __restrict__ ca,
                                                        const int64_t* __restrict__ rc,
-                                                       const int64_t* __restrict__ cc) {
+                                                       const int64_t* __restrict__ cc,
+                                                       T* __restrict__ part = nullptr, int splits = 1) {
   constexpr int NT = 64 * WM * WN;
   constexpr int PAD = 16 / sizeof(T);
   // B rows: a fragment read touches 16 consecutive n at 4 consecutive k; pad each
@@ -118,7 +122,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
   __shared__ T As[2][BM][BK + PAD];
   __shared__ T Bs[2][BK][BN + PADB];
 
-  const int64_t tile = xcd_remap(blockIdx.x, ntiles);
+  const int64_t tile = SPLIT ? static_cast<int64_t>(blockIdx.x) / splits : xcd_remap(blockIdx.x, ntiles);
+  const int split = SPLIT ? static_cast<int>(blockIdx.x - tile * splits) : 0;
   int64_t q;
   int tm, tn;
   tile_coords(tile, tiles_m, tiles_n, q, tm, tn);
@@ -187,13 +192,19 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = Acc{};
 
-  const int nk = (K + BK - 1) / BK;
-  load_tiles(0);
-  store_tiles(0);
+  const int nk_all = (K + BK - 1) / BK;
+  // this workgroup's K-steps [kt0, kt1): all of them, or its split's share
+  const int per = SPLIT ? (nk_all + splits - 1) / splits : nk_all;
+  const int kt0 = SPLIT ? min(nk_all, split * per) : 0;
+  const int kt1 = SPLIT ? min(nk_all, kt0 + per) : nk_all;
+  if (kt0 < kt1) {
+    load_tiles(kt0 * BK);
+    store_tiles(0);
+  }
   __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) load_tiles((kt + 1) * BK);
+  for (int kt = kt0; kt < kt1; ++kt) {
+    const int buf = (kt - kt0) & 1;
+    if (kt + 1 < kt1) load_tiles((kt + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       T a[TM], b[TN];
@@ -206,10 +217,73 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<T>::run(a[i], b[j], acc[i][j]);
     }
-    if (kt + 1 < nk) store_tiles(buf ^ 1);
+    if (kt + 1 < kt1) store_tiles(buf ^ 1);
     __syncthreads();
   }
 
+  if constexpr (SPLIT) {
+    // partial tile in accumulator order: element ((wave*TM + i)*TN + j)*4 + r of lane l
+    // at 64 * that + l, so these stores and k_split_sum's loads coalesce
+    T* pw = part + (tile * splits + split) * static_cast<int64_t>(BM * BN) + wave * (TM * TN * 4 * 64) + lane;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pw[((i * TN + j) * 4 + r) * 64] = acc[i][j][r];
+    return;
+  }
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int col = n0 + wn0 + j * 16 + (lane & 15);
+    const int64_t ccol = (FC && col < N) ? cc[q * N + col] : col;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm0 + i * 16 + Mfma<T>::row(lane, r);
+        if (row < M && col < N) {
+          const int64_t crow = FC ? rc[q * M + row] : static_cast<int64_t>(row) * N;
+          Cq[crow + ccol] = acc[i][j][r];
+        }
+      }
+  }
+}
+
+// Sums the `splits` partial tiles of each tile in split order (so the result does
+// not depend on scheduling) and writes the tile, as k_gemm's epilogue would.  One
+// workgroup per tile, threads laid out as in k_gemm.
+template <typename T, int BM, int BN, int WM, int WN, bool FC>
+__global__ __launch_bounds__(64 * WM * WN) void k_split_sum(const T* __restrict__ part, T* __restrict__ C,
+                                                            int M, int N, int tiles_m, int tiles_n, int splits,
+                                                            const int64_t* __restrict__ rc,
+                                                            const int64_t* __restrict__ cc) {
+  constexpr int TM = BM / WM / 16, TN = BN / WN / 16;
+  using Acc = typename Mfma<T>::Acc;
+  const int64_t tile = blockIdx.x;
+  int64_t q;
+  int tm, tn;
+  tile_coords(tile, tiles_m, tiles_n, q, tm, tn);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wm0 = (wave / WN) * (BM / WM);
+  const int wn0 = (wave % WN) * (BN / WN);
+  Acc acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = Acc{};
+  for (int sp = 0; sp < splits; ++sp) {
+    const T* pw = part + (tile * splits + sp) * static_cast<int64_t>(BM * BN) + wave * (TM * TN * 4 * 64) + lane;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[i][j][r] += pw[((i * TN + j) * 4 + r) * 64];
+  }
+  T* Cq = C + (FC ? 0 : q * static_cast<int64_t>(M) * N);
+  const int m0 = tm * BM, n0 = tn * BN;
 #pragma unroll
   for (int j = 0; j < TN; ++j) {
     const int col = n0 + wn0 + j * 16 + (lane & 15);
@@ -684,26 +758,59 @@ __global__ __launch_bounds__(64 * WM * WN, (WM * WN == 4 && BK == 32) ? 2 : 1) v
 
 template <typename T, int BM, int BN, int BK, int WM, int WN>
 hipError_t launch_fp(int vec, int64_t batch, int M, int N, int K, const void* A, const void* B,
-                     void* C, hipStream_t s, const FusedTables* f) {
+                     void* C, hipStream_t s, const FusedTables* f, int splits, void* part, size_t part_bytes) {
   const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
   const int64_t ntiles = batch * tiles_m * tiles_n;
-  const dim3 grid(static_cast<unsigned>(ntiles)), block(64 * WM * WN);
+  const dim3 block(64 * WM * WN);
   const T* a = static_cast<const T*>(A);
   const T* b = static_cast<const T*>(B);
   T* c = static_cast<T*>(C);
   constexpr int VV = 16 / sizeof(T);
-  if (f && f->vec > 1) {
+  const int64_t* ra = f ? f->ra : nullptr;
+  const int64_t* ca = f ? f->ca : nullptr;
+  const int64_t* rc = f ? f->rc : nullptr;
+  const int64_t* cc = f ? f->cc : nullptr;
+  const bool fv = f ? f->vec > 1 : vec > 1;
+  // split-K only where the workspace holds every partial tile
+  if (splits > 1 && (!part || static_cast<size_t>(ntiles) * splits * BM * BN * sizeof(T) > part_bytes)) splits = 1;
+  if (splits > 1) {
+    T* pt = static_cast<T*>(part);
+    const dim3 grid(static_cast<unsigned>(ntiles * splits));
+    if (f && fv)
+      hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, VV, true, true, true>), grid, block, 0, s, a, b, c, M, N,
+                         K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, splits);
+    else if (f)
+      hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, 1, true, true, true>), grid, block, 0, s, a, b, c, M, N,
+                         K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, splits);
+    else if (fv)
+      hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, VV, false, false, true>), grid, block, 0, s, a, b, c, M,
+                         N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, splits);
+    else
+      hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, 1, false, false, true>), grid, block, 0, s, a, b, c, M,
+                         N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, splits);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (f)
+      hipLaunchKernelGGL((k_split_sum<T, BM, BN, WM, WN, true>), dim3(static_cast<unsigned>(ntiles)), block, 0, s,
+                         pt, c, M, N, tiles_m, tiles_n, splits, rc, cc);
+    else
+      hipLaunchKernelGGL((k_split_sum<T, BM, BN, WM, WN, false>), dim3(static_cast<unsigned>(ntiles)), block, 0,
+                         s, pt, c, M, N, tiles_m, tiles_n, splits, rc, cc);
+    return hipGetLastError();
+  }
+  const dim3 grid(static_cast<unsigned>(ntiles));
+  if (f && fv) {
     hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, VV, true, true>), grid, block, 0, s, a, b, c,
-                       M, N, K, tiles_m, tiles_n, ntiles, f->ra, f->ca, f->rc, f->cc);
+                       M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, nullptr, 1);
   } else if (f) {
     hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, 1, true, true>), grid, block, 0, s, a, b, c,
-                       M, N, K, tiles_m, tiles_n, ntiles, f->ra, f->ca, f->rc, f->cc);
-  } else if (vec > 1) {
+                       M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, nullptr, 1);
+  } else if (fv) {
     hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, VV, false, false>), grid, block, 0, s, a, b,
-                       c, M, N, K, tiles_m, tiles_n, ntiles, nullptr, nullptr, nullptr, nullptr);
+                       c, M, N, K, tiles_m, tiles_n, ntiles, nullptr, nullptr, nullptr, nullptr, nullptr, 1);
   } else {
     hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, 1, false, false>), grid, block, 0, s, a, b, c,
-                       M, N, K, tiles_m, tiles_n, ntiles, nullptr, nullptr, nullptr, nullptr);
+                       M, N, K, tiles_m, tiles_n, ntiles, nullptr, nullptr, nullptr, nullptr, nullptr, 1);
   }
   return hipGetLastError();
 }
@@ -958,14 +1065,14 @@ hipError_t launch_dma(int64_t batch, int M, int N, int K, const void* A, const v
 template <typename T>
 hipError_t launch_fp_tile(int idx, int vec, int64_t batch, int M, int N, int K, const void* A,
                           const void* B, void* C, hipStream_t s, const FusedTables* f, void* part,
-                          size_t part_bytes) {
+                          size_t part_bytes, int splits) {
   switch (idx) {
-    case 0: return launch_fp<T, 128, 128, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s, f);
-    case 1: return launch_fp<T, 128, 96, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s, f);
-    case 2: return launch_fp<T, 128, 64, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s, f);
-    case 3: return launch_fp<T, 128, 48, 16, 4, 1>(vec, batch, M, N, K, A, B, C, s, f);
-    case 4: return launch_fp<T, 96, 96, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s, f);
-    case 5: return launch_fp<T, 64, 96, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s, f);
+    case 0: return launch_fp<T, 128, 128, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s, f, splits, part, part_bytes);
+    case 1: return launch_fp<T, 128, 96, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s, f, splits, part, part_bytes);
+    case 2: return launch_fp<T, 128, 64, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s, f, splits, part, part_bytes);
+    case 3: return launch_fp<T, 128, 48, 16, 4, 1>(vec, batch, M, N, K, A, B, C, s, f, splits, part, part_bytes);
+    case 4: return launch_fp<T, 96, 96, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s, f, splits, part, part_bytes);
+    case 5: return launch_fp<T, 64, 96, 16, 2, 2>(vec, batch, M, N, K, A, B, C, s, f, splits, part, part_bytes);
     case 6: return launch_dma<T, 128, 128, 2, 2, 2>(batch, M, N, K, A, B, C, s, f, part, part_bytes);
     case 7: return launch_dma<T, 128, 96, 2, 2, 2>(batch, M, N, K, A, B, C, s, f, part, part_bytes);
     case 8: return launch_dma<T, 128, 64, 2, 2, 3>(batch, M, N, K, A, B, C, s, f, part, part_bytes);
@@ -1022,9 +1129,11 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
     const bool aligned = (reinterpret_cast<uintptr_t>(A) & 15) == 0 &&
                          (reinterpret_cast<uintptr_t>(B) & 15) == 0 && (!fused || fused->vec > 1);
     const GemmChoice gc = choose_fp_gemm(batch, M, N, K, f64 ? 8 : 4, aligned);
-    if (!gc.sk || (reinterpret_cast<uintptr_t>(part) & 15) != 0) part = nullptr;
-    e = f64 ? launch_fp_tile<double>(gc.tile, vec, batch, M, N, K, A, B, C, stream, fused, part, part_bytes)
-            : launch_fp_tile<float>(gc.tile, vec, batch, M, N, K, A, B, C, stream, fused, part, part_bytes);
+    if ((!gc.sk && gc.splits <= 1) || (reinterpret_cast<uintptr_t>(part) & 15) != 0) part = nullptr;
+    e = f64 ? launch_fp_tile<double>(gc.tile, vec, batch, M, N, K, A, B, C, stream, fused, part, part_bytes,
+                                     gc.splits)
+            : launch_fp_tile<float>(gc.tile, vec, batch, M, N, K, A, B, C, stream, fused, part, part_bytes,
+                                    gc.splits);
   }
   if (e != hipSuccess) {
     if (err) *err = std::string("sector product launch: ") + hipGetErrorString(e);

@@ -526,8 +526,28 @@ GemmChoice choose_among(int64_t batch, int64_t M, int64_t N, int64_t K, int elem
       }
       if (best.tile < 0 || time < best_t) {
         best.tile = i; best.bm = t.bm; best.bn = t.bn; best.dma = t.dma; best.sk = sk;
+        best.splits = 1;
         best.partial_bytes = partial;
         best_t = time;
+      }
+    }
+    // Register tiles with few tiles and a long K: split each tile's K-steps into
+    // runs for more workgroups (about two per CU), summed in order afterwards.
+    // Each run pays a pipeline fill of about two K-steps.
+    if (!t.dma && sk_mode != 0) {
+      const int64_t nk = (K + 15) / 16;
+      const int64_t sp = std::min<int64_t>({(512 + tiles - 1) / std::max<int64_t>(tiles, 1), nk / 8, 128});
+      if (sp > 1) {
+        const size_t partial = static_cast<size_t>(tiles * sp) * t.bm * t.bn * elem;
+        const double time = static_cast<double>((tiles * sp + 255) / 256) * t_tile / static_cast<double>(sp) *
+                                (1.0 + 2.0 * static_cast<double>(sp) / static_cast<double>(nk)) +
+                            2.0 * static_cast<double>(partial) / 5e12 + 5e-6;
+        if (time < best_t) {
+          best.tile = i; best.bm = t.bm; best.bn = t.bn; best.dma = false; best.sk = false;
+          best.splits = static_cast<int>(sp);
+          best.partial_bytes = partial;
+          best_t = time;
+        }
       }
     }
   }
@@ -536,7 +556,8 @@ GemmChoice choose_among(int64_t batch, int64_t M, int64_t N, int64_t K, int elem
 }  // namespace
 
 // SYMT_GEMM_TILE=<name> restricts the choice to one tile (ignored where it does
-// not apply); SYMT_GEMM_SK=0 / 1 forbids / forces stream-K on the DMA tiles.
+// not apply); SYMT_GEMM_SK=0 forbids stream-K and split K, 1 forces stream-K on
+// the DMA tiles.
 GemmChoice choose_fp_gemm(int64_t batch, int64_t M, int64_t N, int64_t K, int elem, bool aligned) {
   const char* forced = std::getenv("SYMT_GEMM_TILE");
   const char* sk_env = std::getenv("SYMT_GEMM_SK");

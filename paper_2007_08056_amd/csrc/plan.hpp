@@ -192,7 +192,8 @@ struct GemmChoice {
   bool dma = false;           // global-to-LDS tile
   bool sk = false;            // stream-K: persistent workgroups split the K-iterations of all
                               // tiles evenly; tiles cut between two of them are summed after
-  size_t partial_bytes = 0;   // stream-K workspace for the pieces of cut tiles
+  int splits = 1;             // register tiles: each tile's K-steps in this many runs, summed after
+  size_t partial_bytes = 0;   // workspace for stream-K pieces or split partial tiles
 };
 // Most persistent workgroups of a stream-K product: 256 CUs x up to 3 resident
 // workgroups (the two-stage 96 x 96 tile).  The planner sizes the pieces

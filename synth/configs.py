@@ -192,6 +192,67 @@ def paper_suite_case(label: str, dims: dict | None = None) -> Workload:
 SUITE_LABELS = tuple(_SUITE)
 
 
+# ---------------------------------------------------------------------------
+# The paper's generic-contraction sweep (Sec. 4): (s, t, v) free and contracted
+# mode counts at G = 4, every mode's block dimension N chosen so that the
+# contraction costs 80 GFLOP (2 N^(s+t+v) G^(s+t+v-2), N rounded to the nearest
+# integer).  Which (s, t, v) the paper plotted is not recoverable; these are
+# every pattern with s, t, v in 1..3 and s + t + v <= 6, plus the three
+# one-sided order-5 patterns.  Signs: U's free modes +, its contracted modes -;
+# V's contracted modes + (opposite to U's), its free modes -; charges 0.
+# ---------------------------------------------------------------------------
+STV_CASES = ((1, 1, 1), (2, 1, 1), (1, 2, 1), (1, 1, 2), (2, 2, 1), (2, 1, 2), (1, 2, 2),
+             (2, 2, 2), (3, 1, 1), (1, 3, 1), (1, 1, 3))
+
+
+def stv_case(s: int, t: int, v: int, G: int = 4, total_flops: float = 80e9, n: int | None = None) -> Workload:
+    """W[I,J] = sum_K U[I,K] V[K,J] with s, t, v modes of block dimension N (``n`` overrides)."""
+    order = s + t + v
+    if n is None:
+        n = max(1, round((total_flops / 2.0 / G ** (order - 2)) ** (1.0 / order)))
+    letters = "abcdefghijklmnop"
+    I, K, J = letters[:s], letters[s:s + v], letters[s + v:s + v + t]
+    tu, tv, tw = I + K, K + J, I + J
+    ops = {
+        "U": Operand("U", tu, "+" * s + "-" * v, 0, (n,) * len(tu), DIST_UNIFORM, 1.0, 600 + 16 * (9 * s + 3 * t + v)),
+        "V": Operand("V", tv, "+" * v + "-" * t, 0, (n,) * len(tv), DIST_UNIFORM, 1.0,
+                     601 + 16 * (9 * s + 3 * t + v)),
+        # derived: c^W = (c^U_I, -sigma c^V_J) with sigma = -1
+        "W": Operand("W", tw, "+" * s + "-" * t, 0, (n,) * len(tw)),
+    }
+    return Workload(f"stv_{s}{t}{v}", (G,), ops, (Contraction(f"{tu},{tv}->{tw}", "U", "V", "W"),), ("U", "V"), "W")
+
+
+# ---------------------------------------------------------------------------
+# The paper's sensitivity-to-G sweeps (Sec. 4): MM with N = 500 over G = 4..12,
+# CC1 over G = 4..12 and PEPS over G = 2..10.  The CC1 dimensions are printed
+# for eight mode letters of a six-mode contraction; read as U's four modes
+# i, j, k, l at 8 and V's free modes m, n at 16.  PEPS: the boundary-MPS
+# bonds i, j at 16, the PEPS bonds k, l, m, n at 4.  Signs as in the suite.
+# ---------------------------------------------------------------------------
+G_SWEEP = {"mm": tuple(range(4, 13)), "cc1": tuple(range(4, 13)), "peps": tuple(range(2, 11))}
+_G_SWEEP_SHAPES = {
+    "mm": ("ij,jk->ik", "+-", "+-", "+-", dict(i=500, j=500, k=500)),
+    "cc1": ("ijkl,mnkl->ijmn", "++--", "--++", "++--", dict(i=8, j=8, k=8, l=8, m=16, n=16)),
+    "peps": ("ijkl,klmn->ijmn", "++--", "++--", "++--", dict(i=16, j=16, k=4, l=4, m=4, n=4)),
+}
+
+
+def g_sweep_case(family: str, G: int, dims: dict | None = None) -> Workload:
+    """One point of a G sweep (``dims`` overrides block dimensions, for small test copies)."""
+    sub, su, sv, sw, d = _G_SWEEP_SHAPES[family]
+    d = dict(d, **(dims or {}))
+    tu, rest = sub.split(",")
+    tv, tw = rest.split("->")
+    cid = 700 + 16 * (3 * list(_G_SWEEP_SHAPES).index(family)) + G
+    ops = {
+        "U": Operand("U", tu, su, 0, tuple(d[m] for m in tu), DIST_UNIFORM, 1.0, cid * 16 + 0),
+        "V": Operand("V", tv, sv, 0, tuple(d[m] for m in tv), DIST_UNIFORM, 1.0, cid * 16 + 1),
+        "W": Operand("W", tw, sw, 0, tuple(d[m] for m in tw)),
+    }
+    return Workload(f"gsweep_{family}_{G}", (G,), ops, (Contraction(sub, "U", "V", "W"),), ("U", "V"), "W")
+
+
 ALL = {
     "plain_z4": plain_z4,
     "ccd_ladder_z8": ccd_ladder_z8,

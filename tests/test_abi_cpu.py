@@ -363,3 +363,17 @@ def test_fused_needs_whole_k_steps_per_run():
     c8s = _desc("+-+-", 0, (3, 5, 2, 4), L.SYMT_C64)
     cv8s = _desc("+-+-", 0, (2, 4, 4, 4), L.SYMT_C64)
     assert _plan("abkl,klij->abij", G, c8s, cv8s, compute=1)[1].fused == 0
+
+
+def test_split_k_for_few_tiles_and_long_k(monkeypatch):
+    """Register tiles split a long K into runs when a launch has too few tiles to fill the CUs."""
+    monkeypatch.delenv("SYMT_GEMM_SK", raising=False)
+    monkeypatch.delenv("SYMT_GEMM_TILE", raising=False)
+    # the (s, t, v) = (1, 1, 3) sweep case: 4 x (57 x 2963088 x 57); N odd rules out the DMA tiles
+    rc, ws = _gemm_ws(L.COMPUTE["f64"], 4, 57, 2963088, 57)
+    assert rc == 0 and ws > 0
+    monkeypatch.setenv("SYMT_GEMM_SK", "0")
+    assert _gemm_ws(L.COMPUTE["f64"], 4, 57, 2963088, 57) == (0, 0)
+    monkeypatch.delenv("SYMT_GEMM_SK")
+    # short K: nothing to split
+    assert _gemm_ws(L.COMPUTE["f64"], 4, 57, 64, 57) == (0, 0)

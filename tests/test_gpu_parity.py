@@ -831,3 +831,54 @@ def test_complex_fused_product_equals_steps_and_oracle(P, case, compute):
     got = H.to_np(w_f.data).astype(np.complex128)
     for part in (np.real, np.imag):
         assert np.all(np.abs(part(got) - part(ref)) <= H.bound_factor(compute, k) * absref + 1e-300)
+
+
+# ---------------------------------------------------------------------------
+# Split K on the register tiles: few tiles and a long K (odd N rules out the
+# global-to-LDS tiles), partial tiles summed in order by k_split_sum.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("compute", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(2, 40, 60000, 33), (3, 7, 20000, 5), (1, 130, 9000, 17)])
+def test_sector_gemm_split_k(P, compute, shape):
+    b, m, k, n = shape
+    assert P.sector_gemm_workspace_size(compute, b, m, k, n) > 0
+    say(f"split-K sector product {shape} {compute}")
+    g = torch.Generator().manual_seed(b * m + k + n)
+    dt = torch.float64 if compute == "f64" else torch.float32
+    a = torch.rand(b, m, k, generator=g, dtype=torch.float64) * 2 - 1
+    bb = torch.rand(b, k, n, generator=g, dtype=torch.float64) * 2 - 1
+    ref = torch.bmm(a.to(dt).double(), bb.to(dt).double())
+    absref = torch.bmm(a.to(dt).double().abs(), bb.to(dt).double().abs())
+    c = P.sector_gemm(a.to(DEV, dt), bb.to(DEV, dt), compute)
+    c2 = P.sector_gemm(a.to(DEV, dt), bb.to(DEV, dt), compute)
+    assert torch.equal(c, c2)                      # the sum of the splits does not depend on scheduling
+    err = (c.double().cpu() - ref).abs()
+    assert torch.all(err <= H.bound_factor(compute, k) * absref + 1e-300)
+
+
+def test_fused_split_k_contraction(P):
+    """Fused product on register tiles (U misaligned by one element) with split K."""
+    rng = np.random.default_rng(5)
+    g = O.Group(3)
+    su = O.Sym.make("+-", 1, (5, 4096), g)
+    sv = O.Sym.make("++", 2, (4096, 8), g)
+    sub = "ak,kb->ab"
+    Ru, Rv = rng.standard_normal(su.reduced_shape()), rng.standard_normal(sv.reduced_shape())
+    u = _sym_tensor(P, Ru, su)
+    v = _sym_tensor(P, Rv, sv)
+    buf = torch.zeros(u.data.numel() + 1, dtype=torch.float64, device=DEV)
+    buf[1:] = u.data.reshape(-1)
+    u_off = P.SymTensor(buf[1:].view(u.data.shape), u.signs, u.charge, u.group)
+    assert P.plan(sub, u_off, v).fused == 1
+    say("fused split-K contraction")
+    w_f = P.output_like(sub, u, v)
+    w_s = P.output_like(sub, u, v)
+    P.contract_into(sub, u_off, v, w_f)
+    P.contract_into(sub, u, v, w_s, steps=True)
+    ref, sw = O.contract_blocks(sub, Ru, su, Rv, sv)
+    absref, _ = O.contract_blocks(sub, np.abs(Ru), su, np.abs(Rv), sv)
+    k = H.contracted_extent(sub, su)
+    for w in (w_f, w_s):
+        got = H.to_np(w.data)
+        assert H.rel_err(got, ref) <= 1e-12
+        assert np.all(np.abs(got - ref) <= H.bound_factor("f64", k) * absref + 1e-300)

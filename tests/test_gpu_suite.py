@@ -118,3 +118,81 @@ def test_suite_full_size_sampled(P, SG, label):
     say(f"  normwise relative error on samples {err:.3e}")
     assert err <= 1e-12
     assert np.all(np.abs(got - ref) <= H.bound_factor("f64", k) * absref)
+
+
+# ---------------------------------------------------------------------------
+# The paper's generic (s, t, v) sweep at G = 4 and its G sweeps (MM, CC1, PEPS):
+# small copies against the oracle in three precisions, and a few full-size
+# cases on sampled outputs.
+# ---------------------------------------------------------------------------
+def _check_small(P, SG, wl, label):
+    st = wl.steps[0]
+    su, sv = _sym(wl, "U"), _sym(wl, "V")
+    Ru, Rv = synth.host_input(wl, "U"), synth.host_input(wl, "V")
+    ref, sw = O.contract_blocks(st.einsum, Ru, su, Rv, sv)
+    absref, _ = O.contract_blocks(st.einsum, np.abs(Ru), su, np.abs(Rv), sv)
+    assert sw.sign_string() == wl.operands["W"].signs
+    k = H.contracted_extent(st.einsum, su)
+    for compute in ("f64", "f32", "bf16x3"):
+        dt = torch.float64 if compute == "f64" else torch.float32
+        u, v = _tensor(P, SG, wl, "U", dt), _tensor(P, SG, wl, "V", dt)
+        info = P.plan(st.einsum, u, v, compute)
+        if compute == "bf16x3" and info.k % 8:
+            continue
+        say(f"{label} small {compute}: batch {info.group_size} m {info.m} k {info.k} n {info.n}")
+        w = P.output_like(st.einsum, u, v, dtype=torch.float64)
+        P.contract_into(st.einsum, u, v, w, compute)
+        got = H.to_np(w.data)
+        if compute == "f64":
+            assert H.rel_err(got, ref) <= 1e-12
+            assert np.array_equal(O.expand(got, sw) == 0, O.expand(ref, sw) == 0)
+        bound = H.bound_factor(compute, k) + (0 if compute == "f64" else 2.1 * H.U32)
+        assert np.all(np.abs(got - ref) <= bound * absref + 1e-300)
+
+
+@pytest.mark.parametrize("stv", synth.configs.STV_CASES)
+def test_stv_sweep_small_vs_oracle(P, SG, stv):
+    _check_small(P, SG, synth.configs.stv_case(*stv, n=3), f"stv {stv}")
+
+
+@pytest.mark.parametrize("family", list(synth.configs.G_SWEEP))
+def test_g_sweep_small_vs_oracle(P, SG, family):
+    small = {"mm": dict(i=9, j=7, k=8), "cc1": dict(i=2, j=3, k=2, l=3, m=4, n=2),
+             "peps": dict(i=4, j=3, k=2, l=2, m=3, n=2)}[family]
+    for G in (synth.configs.G_SWEEP[family][0], synth.configs.G_SWEEP[family][-1]):
+        _check_small(P, SG, synth.configs.g_sweep_case(family, G, small), f"G sweep {family} G={G}")
+
+
+def _check_full_sampled(P, SG, wl, label):
+    st = wl.steps[0]
+    su, sv = _sym(wl, "U"), _sym(wl, "V")
+    u, v = _tensor(P, SG, wl, "U"), _tensor(P, SG, wl, "V")
+    w = P.output_like(st.einsum, u, v)
+    info = P.plan(st.einsum, u, v, "f64", w)
+    say(f"{label} full: batch {info.group_size} m {info.m} k {info.k} n {info.n}, {info.flops / 1e9:.1f} GFLOP")
+    P.contract_into(st.einsum, u, v, w, "f64")
+    torch.cuda.synchronize()
+    del u, v
+    torch.cuda.empty_cache()
+    sw = O.output_symmetry(st.einsum, su, sv)
+    red, full = H.random_w_positions(sw, 24, np.random.default_rng(11))
+    got = np.array([w.data[r].item() for r in red])
+    del w
+    torch.cuda.empty_cache()
+    ref = O.sample_contract(st.einsum, su, sv, H.value_fn(wl, "U"), H.value_fn(wl, "V"), full)
+    absref = O.sample_contract(st.einsum, su, sv, H.value_fn(wl, "U", True), H.value_fn(wl, "V", True), full)
+    assert H.rel_err(got, ref) <= 1e-12
+    assert np.all(np.abs(got - ref) <= H.bound_factor("f64", H.contracted_extent(st.einsum, su)) * absref)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("stv", [(1, 1, 1), (2, 2, 2), (3, 1, 1), (2, 1, 2)])
+def test_stv_sweep_full_size_sampled(P, SG, stv):
+    _check_full_sampled(P, SG, synth.configs.stv_case(*stv), f"stv {stv}")
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("family", list(synth.configs.G_SWEEP))
+def test_g_sweep_full_size_sampled(P, SG, family):
+    G = synth.configs.G_SWEEP[family][-1]
+    _check_full_sampled(P, SG, synth.configs.g_sweep_case(family, G), f"G sweep {family} G={G}")
