@@ -770,7 +770,8 @@ hipError_t launch_fp(int vec, int64_t batch, int M, int N, int K, const void* A,
   const int64_t* ca = f ? f->ca : nullptr;
   const int64_t* rc = f ? f->rc : nullptr;
   const int64_t* cc = f ? f->cc : nullptr;
-  const bool fv = f ? f->vec > 1 : vec > 1;
+  // one vector width for A and B loads: K and N (and for the fused loads, U's runs) must allow it
+  const bool fv = vec > 1 && (!f || f->vec > 1);
   // split-K only where the workspace holds every partial tile
   if (splits > 1 && (!part || static_cast<size_t>(ntiles) * splits * BM * BN * sizeof(T) > part_bytes)) splits = 1;
   if (splits > 1) {

@@ -418,12 +418,14 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
                            : (compute == SYMT_COMPUTE_F64 ? SYMT_F64 : SYMT_F32);
   bool trailing_k = true;
   for (int i = 0; i < p->v; ++i) trailing_k = trailing_k && p->posK_u[i] == p->U.n - p->v + i;
-  const int vw = compute == SYMT_COMPUTE_F64 ? 2 : 4;
+  // A single run (one contracted mode, or every contracted sector fixed) holds
+  // any K-step; the product masks the steps past its end.
   const int64_t run = (p->cplx ? 2 : 1) * p->nK;
   const int64_t step = 128 / (compute == SYMT_COMPUTE_F64 ? 8 : 4);
+  const bool whole_steps = (run % kFpBK == 0 && run % step == 0) || run == p->gk;
   p->fused = !force_steps && !p->subgroups && p->nq == p->g.size && compute != SYMT_COMPUTE_BF16X3 &&
-             p->U.dtype == want && (!w || p->W.dtype == want) && trailing_k && run % kFpBK == 0 &&
-             run % step == 0 && p->gn % vw == 0 && p->M > 0 && p->N > 0 && p->Kd > 0 && p->U.elems > 0;
+             p->U.dtype == want && (!w || p->W.dtype == want) && trailing_k && whole_steps &&
+             p->M > 0 && p->N > 0 && p->Kd > 0 && p->U.elems > 0;
   if (p->fused) {
     const size_t G = static_cast<size_t>(p->g.size);
     p->bytes_tables = round_up(8 * G * p->M, 256) * 2 + round_up(8 * G * p->gk, 256) +

@@ -176,7 +176,9 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
   });
   if (rc_) return ctx_fail(ctx, rc_, err);
   if ((rc_ = do_align(ctx, p, 1, val, s, true, chg[1]))) return rc_;
-  symt::FusedTables f{ra, ca, rc, cc, aligned16(p.U.data) ? 2 : 1};
+  // 16-byte loads of A need every row's K run to start 16-byte aligned
+  const int64_t run = (p.cplx ? 2 : 1) * p.nK, vw = p.compute == SYMT_COMPUTE_F64 ? 2 : 4;
+  symt::FusedTables f{ra, ca, rc, cc, aligned16(p.U.data) && run % vw == 0 ? 2 : 1};
   char* part = reinterpret_cast<char*>(cc) + round_up(8 * G * p.gn, 256);
   return do_gemm(ctx, p.compute, p.g.size, p.M, p.gk, p.gn, p.U.data, val, p.W.data, s, &f,
                  p.bytes_partial ? part : nullptr, p.bytes_partial);

@@ -56,7 +56,8 @@ def test_plan_matches_oracle_on_workloads(name):
         k_modes = [m for m in tu if m in tv]
         trailing = tu.endswith("".join(k_modes))
         nK = int(np.prod([ou.dims[tu.index(m)] for m in k_modes]))
-        assert info.fused == int(trailing and nK % 16 == 0 and su.sectors is None and sv.sectors is None)
+        assert info.fused == int(trailing and (nK % 16 == 0 or len(k_modes) == 1) and su.sectors is None
+                                 and sv.sectors is None)
         G = info.group_size
         if info.fused:
             # V aligned plus four offset tables of U and W
@@ -275,7 +276,7 @@ def test_complex_planning():
     assert info.flops == 8 * G * 3 * 5 * 6
     assert info.bytes_u_al == 8 * G * 3 * 10 and info.bytes_v_al == 8 * G * 10 * 12
     assert info.bytes_w_al == 8 * G * 3 * 12
-    assert info.fused == 0
+    assert info.fused == 1          # one contracted mode: a single run of 2 x 5 reals
     rc32, info32 = _plan("ak,kb->ab", G, u, v, compute=1)
     assert rc32 == 0 and info32.bytes_v_al == 4 * G * 10 * 12
     # all complex or all real; no split-bf16 product for complex operands
@@ -363,6 +364,10 @@ def test_fused_needs_whole_k_steps_per_run():
     c8s = _desc("+-+-", 0, (3, 5, 2, 4), L.SYMT_C64)
     cv8s = _desc("+-+-", 0, (2, 4, 4, 4), L.SYMT_C64)
     assert _plan("abkl,klij->abij", G, c8s, cv8s, compute=1)[1].fused == 0
+    # one contracted mode: its run is the whole K range, of any length
+    assert _plan("ak,kb->ab", G, _desc("+-", 0, (3, 57)), _desc("+-", 0, (57, 5)), compute=0)[1].fused == 1
+    assert _plan("ak,kb->ab", G, _desc("+-", 0, (3, 57), L.SYMT_F32), _desc("+-", 0, (57, 5), L.SYMT_F32),
+                 compute=1)[1].fused == 1
 
 
 def test_split_k_for_few_tiles_and_long_k(monkeypatch):
