@@ -65,8 +65,8 @@
  *         2k + 1 holds (-im, re), pairs at columns 2n, 2n + 1;
  *   W_al  real (|G|, M, 2 N): (re, im) of W's column n at 2n, 2n + 1;
  * so the real product U_al V_al is the complex one.  symt_plan_info reports
- * this real product (k = 2 Kd, n = 2 N, flops = 8 |G| M Kd N).  No fused
- * product for complex operands.
+ * this real product (k = 2 Kd, n = 2 N, flops = 8 |G| M Kd N).  The fused
+ * product (below) reads u's and writes w's (re, im) pairs as reals.
  *
  * EMPTY MODE GROUPS (s, t or v = 0; Sec. 2.1's deltas with an empty sum).  One
  * delta then fixes Q on its own: v = 0 (an outer product) gives Q = 0 and
@@ -81,14 +81,24 @@
  * FUSED PRODUCT.  The standard-form offset of aligned element (Q, r, c) of any
  * operand splits as R(Q, r) + C(Q, c) (the block index and the in-block offset
  * are linear in the sectors and indices, and each implicit sector belongs to one
- * sector group).  When compute is F64 or F32, u is stored in the compute type,
- * w (if given) too, u's last v modes are exactly its contracted modes and their
- * block size is a multiple of 16, symtensor_contract builds the four offset
- * tables of U and W in the workspace and runs one product that reads A straight
- * from u's standard form and writes C straight into w's, so U_al and W_al are
- * never materialised; only V is aligned.  The workspace then holds V_al and the
- * tables (info.fused = 1) and is much smaller.  Results are identical in value
- * to the three-step path up to the product's summation order, which is the same.
+ * sector group).  symtensor_contract uses this when compute is F64 or F32, u is
+ * stored in the compute type (complex: its complex counterpart), w too, no mode
+ * is a subgroup mode, every Q slice is live, u's last v modes are exactly its
+ * contracted modes, and a K run (the contracted block in reals) either holds
+ * whole K-steps of the product (16 reals, and 16 f64 / 32 f32 on the
+ * global-to-LDS tiles) or is all of K.  It then builds the offset tables of U
+ * and W in the workspace and runs one product that reads A straight from u's
+ * standard form and writes C straight into w's, so U_al and W_al are never
+ * materialised (info.fused = 1).  V is aligned as usual, unless v is real and
+ * in the compute type, its contracted modes are affine in u's K order (each
+ * one's stride is the next one's stride times its block size), a K run holds
+ * whole K-steps, its last modes are output modes whose contiguous run is a
+ * multiple of 16 bytes, the product runs on global-to-LDS tiles, and u and v
+ * are 16-byte aligned: then two more tables let the product read B from v's
+ * standard form as well (info.fused_v = 1) and no aligned form is written at
+ * all.  The workspace holds V_al (used when v is not read in place) and the
+ * tables.  Results are identical in value to the three-step path: the product
+ * sums in the same order.
  *
  * Execution and ownership.  Every device buffer (operand data, workspace,
  * aligned buffers) is allocated and owned by the caller.  A context holds only
@@ -200,6 +210,8 @@ typedef struct {
   char w_signs[SYMT_MAX_ORDER + 1];/* derived output sign string (tw order), NUL-terminated */
   int32_t w_charge;                /* derived output charge */
   int32_t fused;                   /* 1 if symtensor_contract will run the fused product */
+  int32_t fused_v;                 /* 1 if that product also reads v in place (no V_al), given
+                                      16-byte aligned u and v data */
 } symt_plan_info;
 
 typedef struct symt_ctx symt_ctx;

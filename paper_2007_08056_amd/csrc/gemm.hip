@@ -348,17 +348,21 @@ struct DmaTile {
 // Accumulates K-steps [kt0, kt1) of the tile at (q, m0, n0) into acc (which the
 // caller zeroes).  Every wave leaves with its own loads drained; LDS may still
 // be read by other waves, so a caller that reuses smem barriers first.
-template <typename T, int BM, int BN, int WM, int WN, int S, bool FA>
+// FB: B is V's standard form, row k0 + k of a K-step at rb[q*K + k0] + k * ldb
+// and 16-byte column chunk n at cb[q*N + n] (every K-step inside one affine run
+// of rows, every chunk inside one contiguous run of columns).
+template <typename T, int BM, int BN, int WM, int WN, int S, bool FA, bool FB>
 __device__ __forceinline__ void dma_tile_accumulate(
     const T* __restrict__ A, const T* __restrict__ B, int M, int N, int K, int64_t q, int m0, int n0,
-    int kt0, int kt1, const int64_t* __restrict__ ra, const int64_t* __restrict__ ca, char* smem,
+    int kt0, int kt1, const int64_t* __restrict__ ra, const int64_t* __restrict__ ca,
+    const int64_t* __restrict__ rb, const int64_t* __restrict__ cb, int64_t ldb, char* smem,
     typename DmaTile<T, BM, BN, WM, WN, S>::Acc (&acc)[DmaTile<T, BM, BN, WM, WN, S>::TM]
                                                       [DmaTile<T, BM, BN, WM, WN, S>::TN]) {
   using D = DmaTile<T, BM, BN, WM, WN, S>;
   constexpr int NT = D::NT, VE = D::VE, BK = D::BK, TM = D::TM, TN = D::TN, BCH = D::BCH;
   constexpr int A_LOADS = D::A_LOADS, B_LOADS = D::B_LOADS, STAGE = D::STAGE;
   const T* Aq = A + (FA ? 0 : q * static_cast<int64_t>(M) * K);
-  const T* Bq = B + q * static_cast<int64_t>(K) * N;
+  const T* Bq = B + (FB ? 0 : q * static_cast<int64_t>(K) * N);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -385,11 +389,12 @@ __device__ __forceinline__ void dma_tile_accumulate(
     const int k = slot / BCH, c = slot % BCH;
     const int gch = c ^ ((k & 1) << 3);
     const int gn = min(n0 + gch * VE, N - VE);
-    b_src[i] = static_cast<int64_t>(k) * N + gn;
+    b_src[i] = FB ? static_cast<int64_t>(k) * ldb + cb[q * N + gn] : static_cast<int64_t>(k) * N + gn;
   }
-  // Fused A: column offset of each K-step, fetched one issue ahead so its
-  // latency hides behind the previous step's products.
+  // Fused A (B): column (row) offset of each K-step, fetched one issue ahead so
+  // its latency hides behind the previous step's products.
   int64_t acol_next = FA && kt0 < kt1 ? ca[q * K + static_cast<int64_t>(kt0) * BK] : 0;
+  int64_t brow_next = FB && kt0 < kt1 ? rb[q * K + static_cast<int64_t>(kt0) * BK] : 0;
   auto issue = [&](int kt, int stage) {
     const int k0 = kt * BK;
     int64_t acol = k0;
@@ -397,13 +402,18 @@ __device__ __forceinline__ void dma_tile_accumulate(
       acol = acol_next;
       if (kt + 1 < kt1) acol_next = ca[q * K + static_cast<int64_t>(kt + 1) * BK];
     }
+    int64_t brow = static_cast<int64_t>(k0) * N;
+    if constexpr (FB) {
+      brow = brow_next;
+      if (kt + 1 < kt1) brow_next = rb[q * K + static_cast<int64_t>(kt + 1) * BK];
+    }
     char* base = smem + stage * STAGE;
 #pragma unroll
     for (int i = 0; i < A_LOADS; ++i)
       lds_dma16(Aq + a_src[i] + acol + a_chunk[i] * VE, base + (i * NT + wave * 64) * 16);
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i)
-      lds_dma16(Bq + b_src[i] + static_cast<int64_t>(k0) * N, base + BM * 128 + (i * NT + wave * 64) * 16);
+      lds_dma16(Bq + b_src[i] + brow, base + BM * 128 + (i * NT + wave * 64) * 16);
   };
 
   const int nk = kt1 - kt0;
@@ -504,11 +514,12 @@ __device__ __forceinline__ int64_t sk_bound(int64_t t, int64_t total, int nteam)
 template <int BM, int BN, int S>
 constexpr int kDmaWavesPerSimd = (S == 2 && BM * BN <= 96 * 96) ? 3 : 1;
 
-template <typename T, int BM, int BN, int WM, int WN, int S, bool FA, bool FC, bool SK>
+template <typename T, int BM, int BN, int WM, int WN, int S, bool FA, bool FB, bool FC, bool SK>
 __global__ __launch_bounds__(64 * WM * WN, (kDmaWavesPerSimd<BM, BN, S>)) void k_gemm_dma(
     const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C, int M, int N, int K,
     int tiles_m, int tiles_n, int64_t ntiles, const int64_t* __restrict__ ra,
     const int64_t* __restrict__ ca, const int64_t* __restrict__ rc, const int64_t* __restrict__ cc,
+    const int64_t* __restrict__ rb, const int64_t* __restrict__ cb, int64_t ldb,
     T* __restrict__ part, int ts) {
   using D = DmaTile<T, BM, BN, WM, WN, S>;
   constexpr int TM = D::TM, TN = D::TN;
@@ -524,8 +535,8 @@ __global__ __launch_bounds__(64 * WM * WN, (kDmaWavesPerSimd<BM, BN, S>)) void k
     for (int i = 0; i < TM; ++i)
 #pragma unroll
       for (int j = 0; j < TN; ++j) acc[i][j] = typename D::Acc{};
-    dma_tile_accumulate<T, BM, BN, WM, WN, S, FA>(A, B, M, N, K, q, tm * BM, tn * BN, 0, nk, ra, ca,
-                                                  smem, acc);
+    dma_tile_accumulate<T, BM, BN, WM, WN, S, FA, FB>(A, B, M, N, K, q, tm * BM, tn * BN, 0, nk, ra, ca,
+                                                      rb, cb, ldb, smem, acc);
     store_tile<T, BM, BN, WM, WN, TM, TN, FC>(C, M, N, q, tm * BM, tn * BN, rc, cc, acc);
   } else {
     const int b = static_cast<int>(blockIdx.x);
@@ -553,8 +564,8 @@ __global__ __launch_bounds__(64 * WM * WN, (kDmaWavesPerSimd<BM, BN, S>)) void k
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = typename D::Acc{};
-      dma_tile_accumulate<T, BM, BN, WM, WN, S, FA>(A, B, M, N, K, q, tm * BM, tn * BN, kt0, kt1, ra,
-                                                    ca, smem, acc);
+      dma_tile_accumulate<T, BM, BN, WM, WN, S, FA, FB>(A, B, M, N, K, q, tm * BM, tn * BN, kt0, kt1, ra,
+                                                        ca, rb, cb, ldb, smem, acc);
       if (kt0 == 0 && kt1 == nk)
         store_tile<T, BM, BN, WM, WN, TM, TN, FC>(C, M, N, q, tm * BM, tn * BN, rc, cc, acc);
       else
@@ -985,6 +996,33 @@ int device_cus() {
   return n;
 }
 
+// Fused mode of a global-to-LDS product: 0 aligned operands, 1 A read from U and
+// C written to W in place, 2 B read from V in place as well.
+inline int dma_mode(const FusedTables* f) { return !f ? 0 : f->rb ? 2 : 1; }
+
+template <typename T, int BM, int BN, int WM, int WN, int S, bool SK>
+hipError_t launch_dma_kernel(int mode, dim3 grid, dim3 block, hipStream_t s, const T* a, const T* b, T* c,
+                             int M, int N, int K, int tiles_m, int tiles_n, int64_t ntiles,
+                             const FusedTables* f, T* pt, int ts) {
+  const int64_t* ra = f ? f->ra : nullptr;
+  const int64_t* ca = f ? f->ca : nullptr;
+  const int64_t* rc = f ? f->rc : nullptr;
+  const int64_t* cc = f ? f->cc : nullptr;
+  const int64_t* rb = f ? f->rb : nullptr;
+  const int64_t* cb = f ? f->cb : nullptr;
+  const int64_t ldb = f ? f->ldb : 0;
+  if (mode == 2)
+    hipLaunchKernelGGL((k_gemm_dma<T, BM, BN, WM, WN, S, true, true, true, SK>), grid, block, 0, s, a, b, c, M,
+                       N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, rb, cb, ldb, pt, ts);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_gemm_dma<T, BM, BN, WM, WN, S, true, false, true, SK>), grid, block, 0, s, a, b, c, M,
+                       N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, rb, cb, ldb, pt, ts);
+  else
+    hipLaunchKernelGGL((k_gemm_dma<T, BM, BN, WM, WN, S, false, false, false, SK>), grid, block, 0, s, a, b, c,
+                       M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, rb, cb, ldb, pt, ts);
+  return hipGetLastError();
+}
+
 // part / part_bytes: stream-K piece buffer (nullptr: one workgroup per tile).
 template <typename T, int BM, int BN, int WM, int WN, int S>
 hipError_t launch_dma(int64_t batch, int M, int N, int K, const void* A, const void* B, void* C,
@@ -1000,22 +1038,22 @@ hipError_t launch_dma(int64_t batch, int M, int N, int K, const void* A, const v
   const T* a = static_cast<const T*>(A);
   const T* b = static_cast<const T*>(B);
   T* c = static_cast<T*>(C);
-  const int64_t* ra = f ? f->ra : nullptr;
-  const int64_t* ca = f ? f->ca : nullptr;
   const int64_t* rc = f ? f->rc : nullptr;
   const int64_t* cc = f ? f->cc : nullptr;
+  const int mode = dma_mode(f);
   const int nk = K / DmaTile<T, BM, BN, WM, WN, S>::BK;
   int P = 0, ts = 1;
   if (part) {
-    // resident workgroups per CU of this instantiation (fused or not), cached
-    static std::atomic<int> occupancy[2];
-    int occ = occupancy[f ? 1 : 0].load(std::memory_order_relaxed);
+    // resident workgroups per CU of this instantiation (per fused mode), cached
+    static std::atomic<int> occupancy[3];
+    int occ = occupancy[mode].load(std::memory_order_relaxed);
     if (occ == 0) {
-      auto kern = f ? k_gemm_dma<T, BM, BN, WM, WN, S, true, true, true>
-                    : k_gemm_dma<T, BM, BN, WM, WN, S, false, false, true>;
+      auto kern = mode == 2   ? k_gemm_dma<T, BM, BN, WM, WN, S, true, true, true, true>
+                  : mode == 1 ? k_gemm_dma<T, BM, BN, WM, WN, S, true, false, true, true>
+                              : k_gemm_dma<T, BM, BN, WM, WN, S, false, false, false, true>;
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64 * WM * WN, 0) != hipSuccess || occ < 1)
         occ = 1;
-      occupancy[f ? 1 : 0].store(occ, std::memory_order_relaxed);
+      occupancy[mode].store(occ, std::memory_order_relaxed);
     }
     // no more persistent workgroups than resident ones, nor than the pieces buffer holds
     const int64_t fit = static_cast<int64_t>(part_bytes / (2 * static_cast<size_t>(BM) * BN * sizeof(T)));
@@ -1032,13 +1070,8 @@ hipError_t launch_dma(int64_t batch, int M, int N, int K, const void* A, const v
   T* pt = static_cast<T*>(part);
   if (P > 0) {
     const int nteam = P / ts;
-    if (f)
-      hipLaunchKernelGGL((k_gemm_dma<T, BM, BN, WM, WN, S, true, true, true>), dim3(P), block, 0, s, a,
-                         b, c, M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, ts);
-    else
-      hipLaunchKernelGGL((k_gemm_dma<T, BM, BN, WM, WN, S, false, false, true>), dim3(P), block, 0, s,
-                         a, b, c, M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, ts);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_dma_kernel<T, BM, BN, WM, WN, S, true>(mode, dim3(P), block, s, a, b, c, M, N, K,
+                                                                 tiles_m, tiles_n, ntiles, f, pt, ts);
     if (e != hipSuccess) return e;
     if (f)
       hipLaunchKernelGGL((k_sk_fixup<T, BM, BN, WM, WN, true>), dim3(static_cast<unsigned>(ntiles)),
@@ -1048,14 +1081,8 @@ hipError_t launch_dma(int64_t batch, int M, int N, int K, const void* A, const v
                          block, 0, s, pt, c, M, N, nk, tiles_m, tiles_n, ntiles, ts, nteam, rc, cc);
     return hipGetLastError();
   }
-  const dim3 grid(static_cast<unsigned>(ntiles));
-  if (f)
-    hipLaunchKernelGGL((k_gemm_dma<T, BM, BN, WM, WN, S, true, true, false>), grid, block, 0, s, a, b,
-                       c, M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, 1);
-  else
-    hipLaunchKernelGGL((k_gemm_dma<T, BM, BN, WM, WN, S, false, false, false>), grid, block, 0, s, a,
-                       b, c, M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, 1);
-  return hipGetLastError();
+  return launch_dma_kernel<T, BM, BN, WM, WN, S, false>(mode, dim3(static_cast<unsigned>(ntiles)), block, s, a,
+                                                        b, c, M, N, K, tiles_m, tiles_n, ntiles, f, pt, 1);
   }
 }
 
@@ -1130,6 +1157,10 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
     const bool aligned = (reinterpret_cast<uintptr_t>(A) & 15) == 0 &&
                          (reinterpret_cast<uintptr_t>(B) & 15) == 0 && (!fused || fused->vec > 1);
     const GemmChoice gc = choose_fp_gemm(batch, M, N, K, f64 ? 8 : 4, aligned);
+    if (fused && fused->rb && !gc.dma) {
+      if (err) *err = "B read in place needs a global-to-LDS tile and 16-byte aligned operands";
+      return SYMT_EUNSUPPORTED;
+    }
     if ((!gc.sk && gc.splits <= 1) || (reinterpret_cast<uintptr_t>(part) & 15) != 0) part = nullptr;
     e = f64 ? launch_fp_tile<double>(gc.tile, vec, batch, M, N, K, A, B, C, stream, fused, part, part_bytes,
                                      gc.splits)

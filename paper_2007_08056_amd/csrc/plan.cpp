@@ -158,6 +158,35 @@ AlignedLayout aligned_layout(int32_t compute, int operand) {
   return kRowMajor;
 }
 
+// The global-to-LDS tiles read row k0 + k of a K-step of V at rb(Q, k0) + k ldb
+// and 16-byte column chunks at cb(Q, n).  That needs, for a real V:
+//  * its contracted modes, in U's K order, affine: each one's stride is ldb
+//    times the block sizes of the later ones, ldb the stride of the last;
+//  * a K run (the contracted block, fixed sectors) of whole K-steps (16 f64 or
+//    32 f32 rows);
+//  * its last modes J modes whose contiguous run holds whole 16-byte chunks.
+bool v_in_place_layout(const Plan& p, int64_t* ldb) {
+  if (p.cplx || p.v < 1 || p.t < 1 || p.subgroups) return false;
+  if (p.compute != SYMT_COMPUTE_F64 && p.compute != SYMT_COMPUTE_F32) return false;
+  const int64_t elem = p.compute == SYMT_COMPUTE_F64 ? 8 : 4;
+  const OperandDesc& V = p.V;
+  int64_t st[kMaxOrder];
+  int64_t a = 1;
+  for (int m = V.n - 1; m >= 0; --m) { st[m] = a; a *= V.dims[m]; }
+  const int64_t stride = st[p.posK_v[p.v - 1]];
+  int64_t expect = stride;
+  for (int i = p.v - 1; i >= 0; --i) {
+    if (st[p.posK_v[i]] != expect) return false;
+    expect *= V.dims[p.posK_v[i]];
+  }
+  int64_t run_j = 1;
+  for (int i = p.t - 1; i >= 0 && st[p.posJ_v[i]] == run_j; --i) run_j *= V.dims[p.posJ_v[i]];
+  const int64_t ve = 16 / elem, step = 128 / elem;
+  if (p.nK % step != 0 || run_j % ve != 0 || p.gn % ve != 0) return false;
+  *ldb = stride;
+  return true;
+}
+
 int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
               const symt_tensor* v, const symt_tensor* w, int32_t compute, Plan* p,
               std::string* err) {
@@ -430,6 +459,18 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
     const size_t G = static_cast<size_t>(p->g.size);
     p->bytes_tables = round_up(8 * G * p->M, 256) * 2 + round_up(8 * G * p->gk, 256) +
                       round_up(8 * G * p->gn, 256);
+    p->workspace = round_up(p->ws_v_al, 256) + p->bytes_tables;
+  }
+  // ---- V read in place as well (see v_in_place_layout); V_al keeps its place in
+  // the workspace: a V that is not 16-byte aligned, or another tile choice at
+  // launch, aligns V as before.
+  int64_t ldb = 0;
+  if (p->fused && !p->cplx && p->V.dtype == want && v_in_place_layout(*p, &ldb) &&
+      choose_fp_gemm(p->g.size, p->M, p->gn, p->gk, static_cast<int>(ea), true).dma) {
+    const size_t G = static_cast<size_t>(p->g.size);
+    p->fused_b = true;
+    p->ldb = ldb;
+    p->bytes_tables += round_up(8 * G * p->gk, 256) + round_up(8 * G * p->gn, 256);
     p->workspace = round_up(p->ws_v_al, 256) + p->bytes_tables;
   }
   if (p->charges) {

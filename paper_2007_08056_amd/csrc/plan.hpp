@@ -120,14 +120,18 @@ struct OffsetBatch {
 static_assert(sizeof(OffsetBatch) <= 4000, "offset batch exceeds the kernel argument space");
 static_assert(sizeof(XformParams) <= 4000, "transform descriptor exceeds the kernel argument space");
 
-// Device pointers of the four offset tables of the fused product: rows and
-// columns of U (A operand) and of W (output), each |G| x (rows or columns).
+// Device pointers of the offset tables of the fused product: rows and columns
+// of U (A operand) and of W (output), each |G| x (rows or columns); with rb set,
+// also V's (B read in place: row k0 + k of a K-step at rb[k0] + k * ldb).
 struct FusedTables {
   const int64_t* ra;
   const int64_t* ca;
   const int64_t* rc;
   const int64_t* cc;
   int32_t vec;                      // 1: U is not 16-byte aligned, load A one element at a time
+  const int64_t* rb = nullptr;      // nullptr: B is the aligned V_al
+  const int64_t* cb = nullptr;
+  int64_t ldb = 0;
 };
 
 struct OperandDesc {
@@ -163,9 +167,14 @@ struct Plan {
   int32_t w_charge = 0;             // derived
   int32_t compute = 0;
   bool fused = false;               // A read from U's standard form, C written to W's
+  // B read from V's standard form too (no V_al): V's rows are affine inside every
+  // K-step (stride ldb), its columns come in runs of whole 16-byte chunks, and the
+  // product runs on global-to-LDS tiles (decided again at launch)
+  bool fused_b = false;
+  int64_t ldb = 0;
   size_t bytes_u_al = 0, bytes_v_al = 0, bytes_w_al = 0, workspace = 0;
   size_t ws_u_al = 0, ws_v_al = 0, ws_w_al = 0;   // their regions in the contraction's workspace
-  size_t bytes_tables = 0;          // fused: the four offset tables
+  size_t bytes_tables = 0;          // fused: the four offset tables (six with fused_b)
   size_t bytes_partial = 0;         // stream-K pieces of the product (0: data-parallel tiles)
   // Charge tables (label -> charge) of U, V, W, n x |G| each; empty = identity.
   // On the device each operand's block is [mode][label -> charge | charge -> label][|G|].
@@ -174,6 +183,10 @@ struct Plan {
   size_t bytes_charges = 0;         // device copy of all three (0 when charges is false)
   double flops = 0.0;
 };
+
+// Whether V's standard form can serve as the product's B operand directly
+// (affine rows inside every K-step, 16-byte column chunks); *ldb = row stride.
+bool v_in_place_layout(const Plan& p, int64_t* ldb);
 
 // Parse and validate; returns a SYMT_* status and fills `err` on failure.
 int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,

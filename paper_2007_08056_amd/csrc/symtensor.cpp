@@ -158,29 +158,43 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
   int64_t* ca = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(ra) + round_up(8 * G * p.M, 256));
   int64_t* rc = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(ca) + round_up(8 * G * p.gk, 256));
   int64_t* cc = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(rc) + round_up(8 * G * p.M, 256));
+  int64_t* rb = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(cc) + round_up(8 * G * p.gn, 256));
+  int64_t* cb = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(rb) + round_up(8 * G * p.gk, 256));
+  char* part = p.fused_b ? reinterpret_cast<char*>(cb) + round_up(8 * G * p.gn, 256)
+                         : reinterpret_cast<char*>(rb);
+  // 16-byte loads of A need every row's K run to start 16-byte aligned
+  const int64_t run = (p.cplx ? 2 : 1) * p.nK, vw = p.compute == SYMT_COMPUTE_F64 ? 2 : 4;
+  const int vec = aligned16(p.U.data) && run % vw == 0 ? 2 : 1;
+  // V in place: the launcher must pick a global-to-LDS tile for these operands
+  // (the same choice it makes below: A = U, B = V, both 16-byte aligned)
+  const int elem = p.compute == SYMT_COMPUTE_F64 ? 8 : 4;
+  const bool fb = p.fused_b && vec > 1 && aligned16(p.V.data) &&
+                  symt::choose_fp_gemm(p.g.size, p.M, p.gn, p.gk, elem, true).dma;
   std::string err;
   int rc_ = timed(ctx, 0, s, [&] {
     symt::OffsetBatch b;
-    const int ops[4] = {0, 0, 2, 2};
-    int64_t* outs[4] = {ra, ca, rc, cc};
-    int64_t run = 0;
-    for (int t = 0; t < 4; ++t) {
+    const int ops[6] = {0, 0, 2, 2, 1, 1};
+    int64_t* outs[6] = {ra, ca, rc, cc, rb, cb};
+    int64_t total = 0;
+    b.n = fb ? 6 : 4;
+    for (int t = 0; t < b.n; ++t) {
       b.t[t] = symt::make_offsets(p, ops[t], t % 2 == 0);
       b.t[t].chg = chg[ops[t]];
       b.out[t] = outs[t];
-      run += b.t[t].count * G;
-      b.end[t] = run;
+      total += b.t[t].count * G;
+      b.end[t] = total;
     }
-    b.n = 4;
     return symt::launch_offsets(b, s, &err);
   });
   if (rc_) return ctx_fail(ctx, rc_, err);
-  if ((rc_ = do_align(ctx, p, 1, val, s, true, chg[1]))) return rc_;
-  // 16-byte loads of A need every row's K run to start 16-byte aligned
-  const int64_t run = (p.cplx ? 2 : 1) * p.nK, vw = p.compute == SYMT_COMPUTE_F64 ? 2 : 4;
-  symt::FusedTables f{ra, ca, rc, cc, aligned16(p.U.data) && run % vw == 0 ? 2 : 1};
-  char* part = reinterpret_cast<char*>(cc) + round_up(8 * G * p.gn, 256);
-  return do_gemm(ctx, p.compute, p.g.size, p.M, p.gk, p.gn, p.U.data, val, p.W.data, s, &f,
+  if (!fb && (rc_ = do_align(ctx, p, 1, val, s, true, chg[1]))) return rc_;
+  symt::FusedTables f{ra, ca, rc, cc, vec};
+  if (fb) {
+    f.rb = rb;
+    f.cb = cb;
+    f.ldb = p.ldb;
+  }
+  return do_gemm(ctx, p.compute, p.g.size, p.M, p.gk, p.gn, p.U.data, fb ? p.V.data : val, p.W.data, s, &f,
                  p.bytes_partial ? part : nullptr, p.bytes_partial);
 }
 
@@ -262,6 +276,7 @@ int symtensor_plan(const char* einsum, const symt_group* group, const symt_tenso
   info->w_signs[p.tw.size()] = '\0';
   info->w_charge = p.w_charge;
   info->fused = p.fused ? 1 : 0;
+  info->fused_v = p.fused_b ? 1 : 0;
   return SYMT_OK;
 }
 

@@ -225,7 +225,10 @@ def test_stream_k_choice_and_workspace(monkeypatch):
     info = L.plan("abcd,cdij->abij", g, u, v, None, L.COMPUTE["f64"])
     assert (info.m, info.k, info.n) == (4608, 4608, 288) and info.fused
     r = lambda x: (x + 255) // 256 * 256  # noqa: E731
-    base = r(info.bytes_v_al) + r(8 * 8 * 4608) * 2 + r(8 * 8 * 4608) + r(8 * 8 * 288)
+    # V_al, then the row and column tables of U, W and (V read in place) V
+    assert info.fused_v == 1
+    base = r(info.bytes_v_al) + r(8 * 8 * 4608) * 2 + r(8 * 8 * 4608) + r(8 * 8 * 288) + \
+        r(8 * 8 * 4608) + r(8 * 8 * 288)
     assert info.workspace_bytes == base + r(ladder)
     monkeypatch.setenv("SYMT_GEMM_SK", "0")
     assert _gemm_ws(L.COMPUTE["f64"], 8, 4608, 4608, 288) == (0, 0)
@@ -368,6 +371,39 @@ def test_fused_needs_whole_k_steps_per_run():
     assert _plan("ak,kb->ab", G, _desc("+-", 0, (3, 57)), _desc("+-", 0, (57, 5)), compute=0)[1].fused == 1
     assert _plan("ak,kb->ab", G, _desc("+-", 0, (3, 57), L.SYMT_F32), _desc("+-", 0, (57, 5), L.SYMT_F32),
                  compute=1)[1].fused == 1
+
+
+def test_v_in_place_layout_rules(monkeypatch):
+    """The global-to-LDS tiles read B straight from V's standard form when V's
+    contracted modes are affine in U's K order, a K run holds whole K-steps, V's
+    trailing output modes form runs of whole 16-byte chunks, and the tile choice
+    is a global-to-LDS one; otherwise V is aligned as before."""
+    monkeypatch.delenv("SYMT_GEMM_TILE", raising=False)
+    monkeypatch.delenv("SYMT_GEMM_SK", raising=False)
+    u = _desc("++--", 0, (24, 24, 24, 24))
+    ladder = _plan("abcd,cdij->abij", 8, u, _desc("++--", 0, (24, 24, 6, 6)))[1]
+    assert ladder.fused == 1 and ladder.fused_v == 1
+    # contracted modes stored in the other order, or split by an output mode
+    assert _plan("abcd,dcij->abij", 8, u, _desc("++--", 0, (24, 24, 6, 6)))[1].fused_v == 0
+    assert _plan("abcd,cidj->abij", 8, u, _desc("+-+-", 0, (24, 6, 24, 6)))[1].fused_v == 0
+    # output run of 6 f64 = 48 bytes is whole chunks; 3 f64 (an odd run) is not
+    assert _plan("abcd,cdij->abij", 8, u, _desc("++--", 0, (24, 24, 3, 1)))[1].fused_v == 0
+    # K run of 24 f64 rows is not whole 16-row steps
+    u24 = _desc("++--", 0, (24, 24, 4, 6))
+    assert _plan("abcd,cdij->abij", 8, u24, _desc("++--", 0, (4, 6, 6, 6)))[1].fused_v == 0
+    # complex operands, small products (register tiles), a forced register tile
+    c = _desc("++--", 0, (24, 24, 24, 24), L.SYMT_C128)
+    assert _plan("abcd,cdij->abij", 8, c, _desc("++--", 0, (24, 24, 6, 6), L.SYMT_C128))[1].fused_v == 0
+    assert _plan("abcd,cdij->abij", 8, _desc("++--", 0, (4, 4, 4, 4)),
+                 _desc("++--", 0, (4, 4, 2, 2)))[1].fused_v == 0
+    monkeypatch.setenv("SYMT_GEMM_TILE", "128x48")
+    forced = _plan("abcd,cdij->abij", 8, u, _desc("++--", 0, (24, 24, 6, 6)))[1]
+    assert forced.fused == 1 and forced.fused_v == 0
+    assert forced.workspace_bytes < ladder.workspace_bytes
+    # a small product on a forced global-to-LDS tile reads V in place
+    monkeypatch.setenv("SYMT_GEMM_TILE", "d96x96s2")
+    small = _plan("abkl,klij->abij", 4, _desc("++--", 0, (3, 5, 4, 8)), _desc("++--", 0, (4, 8, 2, 6)))[1]
+    assert small.fused == 1 and small.fused_v == 1
 
 
 def test_split_k_for_few_tiles_and_long_k(monkeypatch):

@@ -434,6 +434,69 @@ def test_fused_product_equals_steps_and_oracle(P, case, compute):
     assert torch.equal(w_o.data, w_s.data)
 
 
+# V read in place: contracted modes first in V, in U's K order; K runs of 32
+# rows; V's trailing output run a multiple of 16 bytes (f64; the last case's run
+# of 6 is not for f32)
+VIP_CASES = [
+    ("abkl,klij->abij", (4,), "++--", "++--", (3, 5, 4, 8), (4, 8, 2, 6)),
+    ("ak,kb->ab", (5,), "+-", "++", (33, 32), (32, 20)),
+    ("abkl,klij->abji", (3,), "+-+-", "-+++", (2, 7, 4, 8), (4, 8, 2, 4)),
+    ("akl,klb->ab", (2, 3), "+-+", "-++", (7, 2, 16), (2, 16, 12)),
+    ("abcd,cdij->abij", (8,), "++--", "++--", (5, 6, 4, 8), (4, 8, 3, 2)),
+]
+
+
+@pytest.mark.parametrize("case", VIP_CASES)
+@pytest.mark.parametrize("compute", ["f64", "f32"])
+@pytest.mark.parametrize("tile,sk", [("d96x96s2", "0"), ("d96x96s2", "1"), ("d128x64s3", "0"),
+                                     ("d128x64s3", "1"), ("d128x128s2", "1")])
+def test_fused_product_reads_v_in_place(P, case, compute, tile, sk, monkeypatch):
+    """Global-to-LDS tiles reading B from V's standard form through its row and
+    column tables: bit-identical to the three-step path on the same tile, within
+    the product's bound of the oracle, with and without charge tables; a V that
+    is not 16-byte aligned is aligned first and gives the same bits."""
+    sub, orders, cu, cv, du, dv = case
+    monkeypatch.setenv("SYMT_GEMM_TILE", tile)
+    monkeypatch.setenv("SYMT_GEMM_SK", sk)
+    rng = np.random.default_rng(len(sub) * 17 + sum(dv))
+    g = O.Group(orders)
+    su0 = O.Sym.make(cu, int(rng.integers(g.size)), du, g)
+    sv0 = O.Sym.make(cv, int(rng.integers(g.size)), dv, g)
+    dt = torch.float64 if compute == "f64" else torch.float32
+    # f32 global-to-LDS tiles need B rows of whole 256-byte halves (not 96 wide)
+    applies = not (compute == "f32" and tile == "d96x96s2")
+    run_ok = compute == "f64" or dv[-1] * dv[-2] % 4 == 0
+    for tables in (False, True):
+        su, sv = _with_tables(rng, sub, su0, sv0) if tables else (su0, sv0)
+        say(f"v in place {sub} G={orders} {compute} tile={tile} sk={sk} tables={tables}")
+        Ru = rng.standard_normal(su.reduced_shape())
+        Rv = rng.standard_normal(sv.reduced_shape())
+        u = _sym_tensor(P, Ru, su, dt)
+        v = _sym_tensor(P, Rv, sv, dt)
+        info = P.plan(sub, u, v, compute)
+        assert info.fused == 1
+        assert info.fused_v == int(applies and run_ok)
+        w_f = P.output_like(sub, u, v, dtype=dt)
+        w_s = P.output_like(sub, u, v, dtype=dt)
+        P.contract_into(sub, u, v, w_f, compute)
+        P.contract_into(sub, u, v, w_s, compute, steps=True)
+        assert torch.equal(w_f.data, w_s.data)
+        ref, _ = O.contract_blocks(sub, H.to_np(u.data).astype(np.float64), su,
+                                   H.to_np(v.data).astype(np.float64), sv)
+        absref, _ = O.contract_blocks(sub, np.abs(H.to_np(u.data).astype(np.float64)), su,
+                                      np.abs(H.to_np(v.data).astype(np.float64)), sv)
+        k = H.contracted_extent(sub, su)
+        fac = 2 * H.gamma(k, H.U64) if compute == "f64" else 1.05 * H.gamma(k, H.U32) + H.gamma(k, H.U64)
+        assert np.all(np.abs(H.to_np(w_f.data) - ref) <= fac * absref + 1e-300)
+        # V starting one element into a buffer: not 16-byte aligned, so V_al is written
+        buf = torch.zeros(v.data.numel() + 1, dtype=dt, device=DEV)
+        buf[1:] = v.data.reshape(-1)
+        v_off = P.SymTensor(buf[1:].view(v.data.shape), v.signs, v.charge, v.group, v.mode_charges)
+        w_o = P.output_like(sub, u, v, dtype=dt)
+        P.contract_into(sub, u, v_off, w_o, compute)
+        assert torch.equal(w_o.data, w_s.data)
+
+
 @pytest.mark.parametrize("tile,sk", [("d128x128s2", "0"), ("d128x96s2", "0"), ("d128x64s3", "0"),
                                      ("d96x96s3", "0"), ("128x48", "0"), ("64x96", "0"),
                                      ("d128x128s2", "1"), ("d128x96s2", "1"), ("d128x64s3", "1"),
