@@ -1,7 +1,7 @@
 """Throughput of the irrep-alignment contraction on one MI355X.
 
 One step = the whole hot path on one batch of synthetic input already resident
-in HBM: align V_abcd, align T_cdij, one sector-batched FP64 product, unalign
+in HBM: align V_abcd and T_cdij, one sector-batched FP64 product, unalign
 W_abij -- the coupled-cluster particle-particle ladder w_abij = sum_cd
 V_abcd T_cdij with Z_8 symmetry, virtual block 24, occupied block 6.
 
@@ -14,9 +14,10 @@ rate on a bounded sample of the same workload.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--extra PATH] [--all] [--suite]
 
 Where the layout allows (here it does), one step runs the fused product: A is
-read straight from V_abcd's standard form and C written straight into W_abij's,
-so only T_cdij is aligned (include/symtensor.h, FUSED PRODUCT); the three
-separate steps are timed too and reported in the --extra file.
+read straight from V_abcd's standard form, B from T_cdij's and C written
+straight into W_abij's through offset tables, so no aligned form is written
+(include/symtensor.h, FUSED PRODUCT); the three separate steps are timed too
+and reported in the --extra file.
 """
 from __future__ import annotations
 
@@ -329,6 +330,7 @@ def main():
 
     extra = {
         "fused": bool(info.fused),
+        "fused_v": bool(info.fused_v),
         "kernel_ms_per_launch": {name: (ms[i] / launches[i] if launches[i] else None)
                                  for i, name in enumerate(("offset_tables" if info.fused else "align_u",
                                                            "align_v", "sector_gemm", "unalign_w"))},

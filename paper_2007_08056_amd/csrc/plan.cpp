@@ -465,7 +465,9 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   // the workspace: a V that is not 16-byte aligned, or another tile choice at
   // launch, aligns V as before.
   int64_t ldb = 0;
-  if (p->fused && !p->cplx && p->V.dtype == want && v_in_place_layout(*p, &ldb) &&
+  const char* vip_env = std::getenv("SYMT_FUSED_V");
+  const bool vip_off = vip_env && std::atoi(vip_env) == 0;
+  if (!vip_off && p->fused && !p->cplx && p->V.dtype == want && v_in_place_layout(*p, &ldb) &&
       choose_fp_gemm(p->g.size, p->M, p->gn, p->gk, static_cast<int>(ea), true).dma) {
     const size_t G = static_cast<size_t>(p->g.size);
     p->fused_b = true;
