@@ -89,7 +89,12 @@
  * global-to-LDS tiles) or is all of K.  It then builds the offset tables of U
  * and W in the workspace and runs one product that reads A straight from u's
  * standard form and writes C straight into w's, so U_al and W_al are never
- * materialised (info.fused = 1).  V is aligned as usual, unless v is real and
+ * materialised (info.fused = 1).  With compute BF16X3 the same holds when u is
+ * stored in binary64 or binary32, w in binary64, a K run holds whole 32-deep
+ * K-steps and the shape runs on register-staged tiles (not the global-to-LDS
+ * ones the product takes from 256 x 512 up): the product then splits u's
+ * elements into hi/lo in registers, giving the same bits as the hi/lo planes.
+ * V is aligned as usual, unless v is real and
  * in the compute type, its contracted modes are affine in u's K order (each
  * one's stride is the next one's stride times its block size), a K run holds
  * whole K-steps, its last modes are output modes whose contiguous run is a

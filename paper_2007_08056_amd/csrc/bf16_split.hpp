@@ -1,0 +1,28 @@
+// Split of a binary32 value into two bfloat16 parts, x = hi + lo + O(2^-16 x):
+// hi = bf16(x), lo = bf16(x - hi), both rounded to nearest even (the split-bf16
+// product form).  Shared by the transforms that write hi/lo planes and by the
+// product that splits U's elements in registers, so both give the same bits.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace symt {
+
+// bfloat16 by round-to-nearest-even on the binary32 bit pattern (finite inputs).
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float bf16_as_f32(uint16_t h) {
+  return __uint_as_float(static_cast<uint32_t>(h) << 16);
+}
+// x is taken in binary32 first (a binary64 input is rounded to nearest).
+__device__ __forceinline__ void bf16_split(double x, uint16_t& hi, uint16_t& lo) {
+  const float f = static_cast<float>(x);
+  hi = bf16_rne(f);
+  lo = bf16_rne(f - bf16_as_f32(hi));
+}
+
+}  // namespace symt

@@ -21,7 +21,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <type_traits>
 
+#include "bf16_split.hpp"
 #include "plan.hpp"
 
 namespace symt {
@@ -620,12 +622,20 @@ __global__ __launch_bounds__(64 * WM * WN) void k_sk_fixup(
 
 // ---------------------------------------------------------------------------
 // split-bf16: A planes [Q][M][K], B planes [Q][N][K] (K fastest), C f64.
+// TA = double or float (fused form): A is read from U's standard reduced form,
+// element (q, m, k) at ra[q*M + m] + ca[q*K + k] (every BK-step of K inside one
+// contiguous run), VA elements per load, and split into hi/lo in registers the
+// way the transforms split it; C goes to W's standard form at
+// rc[q*M + m] + cc[q*N + n].
 // ---------------------------------------------------------------------------
-template <int BM, int BN, int BK, int WM, int WN>
+template <int BM, int BN, int BK, int WM, int WN, typename TA = uint16_t, int VA = 8>
 __global__ __launch_bounds__(64 * WM * WN, (WM * WN == 4 && BK == 32) ? 2 : 1) void k_gemm_bf16x3(
     const uint16_t* __restrict__ Ahi, const uint16_t* __restrict__ Alo,
     const uint16_t* __restrict__ Bhi, const uint16_t* __restrict__ Blo, double* __restrict__ C,
-    int M, int N, int K, int tiles_m, int tiles_n, int64_t ntiles) {
+    int M, int N, int K, int tiles_m, int tiles_n, int64_t ntiles, const TA* __restrict__ U = nullptr,
+    const int64_t* __restrict__ ra = nullptr, const int64_t* __restrict__ ca = nullptr,
+    const int64_t* __restrict__ rc = nullptr, const int64_t* __restrict__ cc = nullptr) {
+  constexpr bool FUSED = !std::is_same<TA, uint16_t>::value;
   constexpr int NT = 64 * WM * WN;
   constexpr int V = 8;                // bf16 per 16-byte access
   constexpr int LDK = BK + 8;         // padded row (keeps 16-byte alignment)
@@ -633,6 +643,7 @@ __global__ __launch_bounds__(64 * WM * WN, (WM * WN == 4 && BK == 32) ? 2 : 1) v
   constexpr int TN = BN / WN / 16;
   static_assert(TM * WM * 16 == BM && TN * WN * 16 == BN, "tile shape");
   static_assert(BK % 32 == 0, "BK");
+  static_assert(!FUSED || (VA >= 1 && V % VA == 0 && VA * sizeof(TA) <= 16), "fused A loads");
   constexpr int LA = (BM * BK / V + NT - 1) / NT;
   constexpr int LB = (BN * BK / V + NT - 1) / NT;
 
@@ -645,7 +656,7 @@ __global__ __launch_bounds__(64 * WM * WN, (WM * WN == 4 && BK == 32) ? 2 : 1) v
   tile_coords(tile, tiles_m, tiles_n, q, tm, tn);
   const int64_t offA = q * static_cast<int64_t>(M) * K;
   const int64_t offB = q * static_cast<int64_t>(N) * K;
-  double* Cq = C + q * static_cast<int64_t>(M) * N;
+  double* Cq = C + (FUSED ? 0 : q * static_cast<int64_t>(M) * N);
   const int m0 = tm * BM, n0 = tn * BN;
 
   const int tid = threadIdx.x;
@@ -655,20 +666,44 @@ __global__ __launch_bounds__(64 * WM * WN, (WM * WN == 4 && BK == 32) ? 2 : 1) v
   const int wn0 = (wave % WN) * (BN / WN);
 
   using V8 = VecT<uint16_t, 8>;
+  using VAv = VecT<TA, (FUSED ? VA : 1)>;
+  constexpr int NA = FUSED ? V / VA : 1;     // source loads per 8 elements
   V8 rah[LA], ral[LA], rbh[LB], rbl[LB];
+  VAv xa[FUSED ? LA : 1][NA];
+  // fused A: the standard-form offset of each of this thread's tile rows
+  int64_t arow[LA];
+#pragma unroll
+  for (int i = 0; i < LA; ++i) {
+    const int gr = m0 + (tid + i * NT) * V / BK;
+    arow[i] = (FUSED && (tid + i * NT) * V < BM * BK && gr < M) ? ra[q * M + gr] : 0;
+  }
   auto load_tiles = [&](int k0) {
+    const int64_t acol = FUSED ? ca[q * K + k0] : 0;
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
       const int e = (tid + i * NT) * V;
       const int r = e / BK, c = e % BK;
       const int gr = m0 + r, gc = k0 + c;
-      if (e < BM * BK && gr < M && gc < K) {
-        const int64_t o = offA + static_cast<int64_t>(gr) * K + gc;
-        rah[i] = *reinterpret_cast<const V8*>(Ahi + o);
-        ral[i] = *reinterpret_cast<const V8*>(Alo + o);
-      } else {
+      if constexpr (FUSED) {
+        if (e < BM * BK && gr < M && gc < K) {
 #pragma unroll
-        for (int j = 0; j < V; ++j) rah[i].v[j] = ral[i].v[j] = 0;
+          for (int j = 0; j < NA; ++j)
+            xa[i][j] = *reinterpret_cast<const VAv*>(U + arow[i] + acol + c + j * VA);
+        } else {
+#pragma unroll
+          for (int j = 0; j < NA; ++j)
+#pragma unroll
+            for (int x = 0; x < VA; ++x) xa[i][j].v[x] = TA(0);
+        }
+      } else {
+        if (e < BM * BK && gr < M && gc < K) {
+          const int64_t o = offA + static_cast<int64_t>(gr) * K + gc;
+          rah[i] = *reinterpret_cast<const V8*>(Ahi + o);
+          ral[i] = *reinterpret_cast<const V8*>(Alo + o);
+        } else {
+#pragma unroll
+          for (int j = 0; j < V; ++j) rah[i].v[j] = ral[i].v[j] = 0;
+        }
       }
     }
 #pragma unroll
@@ -687,6 +722,15 @@ __global__ __launch_bounds__(64 * WM * WN, (WM * WN == 4 && BK == 32) ? 2 : 1) v
     }
   };
   auto store_tiles = [&](int buf) {
+    if constexpr (FUSED) {
+#pragma unroll
+      for (int i = 0; i < LA; ++i)
+#pragma unroll
+        for (int j = 0; j < NA; ++j)
+#pragma unroll
+          for (int x = 0; x < VA; ++x)
+            bf16_split(static_cast<double>(xa[i][j].v[x]), rah[i].v[j * VA + x], ral[i].v[j * VA + x]);
+    }
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
       const int e = (tid + i * NT) * V;
@@ -753,18 +797,20 @@ __global__ __launch_bounds__(64 * WM * WN, (WM * WN == 4 && BK == 32) ? 2 : 1) v
   }
 
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int j = 0; j < TN; ++j) {
+    const int col = n0 + wn0 + j * 16 + (lane & 15);
+    const int64_t ccol = (FUSED && col < N) ? cc[q * N + col] : col;
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int col = n0 + wn0 + j * 16 + (lane & 15);
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm0 + i * 16 + 4 * (lane >> 4) + r;
-        if (row < M && col < N)
-          Cq[static_cast<int64_t>(row) * N + col] =
-              static_cast<double>(acc_hh[i][j][r]) + static_cast<double>(acc_x[i][j][r]);
+        if (row < M && col < N) {
+          const int64_t crow = FUSED ? rc[q * M + row] : static_cast<int64_t>(row) * N;
+          Cq[crow + ccol] = static_cast<double>(acc_hh[i][j][r]) + static_cast<double>(acc_x[i][j][r]);
+        }
       }
-    }
+  }
 }
 
 template <typename T, int BM, int BN, int BK, int WM, int WN>
@@ -983,6 +1029,36 @@ hipError_t launch_bf16x3(int64_t batch, int M, int N, int K, const void* A, cons
   return hipGetLastError();
 }
 
+// Fused split-bf16 product: A from U's standard form (binary64 or binary32,
+// 16-byte loads where U is 16-byte aligned), C into W's standard form.
+template <int BM, int BN, int BK, int WM, int WN>
+hipError_t launch_bf16x3_fused(int64_t batch, int M, int N, int K, const void* U, const void* B, void* C,
+                               hipStream_t s, int64_t pb, const FusedTables* f) {
+  const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
+  const int64_t ntiles = batch * tiles_m * tiles_n;
+  const dim3 grid(static_cast<unsigned>(ntiles)), block(64 * WM * WN);
+  const uint16_t* b = static_cast<const uint16_t*>(B);
+  double* c = static_cast<double*>(C);
+  if (f->a_bytes == 8) {
+    const double* u = static_cast<const double*>(U);
+    if (f->vec > 1)
+      hipLaunchKernelGGL((k_gemm_bf16x3<BM, BN, BK, WM, WN, double, 2>), grid, block, 0, s, nullptr, nullptr, b,
+                         b + pb, c, M, N, K, tiles_m, tiles_n, ntiles, u, f->ra, f->ca, f->rc, f->cc);
+    else
+      hipLaunchKernelGGL((k_gemm_bf16x3<BM, BN, BK, WM, WN, double, 1>), grid, block, 0, s, nullptr, nullptr, b,
+                         b + pb, c, M, N, K, tiles_m, tiles_n, ntiles, u, f->ra, f->ca, f->rc, f->cc);
+  } else {
+    const float* u = static_cast<const float*>(U);
+    if (f->vec > 1)
+      hipLaunchKernelGGL((k_gemm_bf16x3<BM, BN, BK, WM, WN, float, 4>), grid, block, 0, s, nullptr, nullptr, b,
+                         b + pb, c, M, N, K, tiles_m, tiles_n, ntiles, u, f->ra, f->ca, f->rc, f->cc);
+    else
+      hipLaunchKernelGGL((k_gemm_bf16x3<BM, BN, BK, WM, WN, float, 1>), grid, block, 0, s, nullptr, nullptr, b,
+                         b + pb, c, M, N, K, tiles_m, tiles_n, ntiles, u, f->ra, f->ca, f->rc, f->cc);
+  }
+  return hipGetLastError();
+}
+
 // Compute units of the current device (cached per device).
 int device_cus() {
   static std::atomic<int> cus[64];
@@ -1134,13 +1210,25 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
     const bool dma_ok = K % 32 == 0;
     const int64_t pa = plane_a > 0 ? plane_a : batch * static_cast<int64_t>(M) * K;
     const int64_t pb = plane_b > 0 ? plane_b : batch * static_cast<int64_t>(N) * K;
-    if (f == "bd256x128s3" && dma_ok) e = launch_bf16x3_dma<256, 128, 4, 2, 3>(batch, M, N, K, A, B, C, stream, pa, pb);
+    if (fused) {
+      // register tiles only (the planner fuses where the launcher would pick one)
+      if (!bf16x3_register_tile(M, N, K) || K % 32 != 0) {
+        if (err) *err = "fused split-bf16 product needs a register tile and whole 32-deep K-steps";
+        return SYMT_EUNSUPPORTED;
+      }
+      const int t = bf16x3_fused_tile(M, N);
+      e = t == 0   ? launch_bf16x3_fused<128, 64, 32, 4, 1>(batch, M, N, K, A, B, C, stream, pb, fused)
+          : t == 2 ? launch_bf16x3_fused<128, 256, 32, 2, 4>(batch, M, N, K, A, B, C, stream, pb, fused)
+          : t == 3 ? launch_bf16x3_fused<128, 96, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pb, fused)
+                   : launch_bf16x3_fused<128, 128, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pb, fused);
+    } else if (f == "bd256x128s3" && dma_ok) e = launch_bf16x3_dma<256, 128, 4, 2, 3>(batch, M, N, K, A, B, C, stream, pa, pb);
     else if (f == "bd128x256s3" && dma_ok) e = launch_bf16x3_dma<128, 256, 2, 4, 3>(batch, M, N, K, A, B, C, stream, pa, pb);
     else if (f == "b128x128k64") e = launch_bf16x3<128, 128, 64, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb);
     else if (f == "b128x128k32") e = launch_bf16x3<128, 128, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb);
     else if (f == "b256x128k32") e = launch_bf16x3<256, 128, 32, 4, 2>(batch, M, N, K, A, B, C, stream, pa, pb);
     else if (f == "b128x256k32") e = launch_bf16x3<128, 256, 32, 2, 4>(batch, M, N, K, A, B, C, stream, pa, pb);
     else if (f == "b128x64k32") e = launch_bf16x3<128, 64, 32, 4, 1>(batch, M, N, K, A, B, C, stream, pa, pb);
+    else if (f == "b128x96k32") e = launch_bf16x3<128, 96, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb);
     else if (f == "b64x64k32") e = launch_bf16x3<64, 64, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb);
     else if (dma_ok && f.empty() && M >= 256 && N >= 512)
       e = launch_bf16x3_dma<128, 256, 2, 4, 3>(batch, M, N, K, A, B, C, stream, pa, pb);
@@ -1148,6 +1236,8 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
       e = launch_bf16x3<128, 64, 32, 4, 1>(batch, M, N, K, A, B, C, stream, pa, pb);
     else if (N >= 1024 && M >= 1024)
       e = launch_bf16x3<128, 256, 32, 2, 4>(batch, M, N, K, A, B, C, stream, pa, pb);
+    else if ((N + 95) / 96 * 96 - N < (N + 127) / 128 * 128 - N)   // fewer padded columns
+      e = launch_bf16x3<128, 96, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb);
     else
       e = launch_bf16x3<128, 128, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb);
   } else {

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <string>
 #include <cstring>
 #include <numeric>
 
@@ -452,8 +453,14 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   const int64_t run = (p->cplx ? 2 : 1) * p->nK;
   const int64_t step = 128 / (compute == SYMT_COMPUTE_F64 ? 8 : 4);
   const bool whole_steps = (run % kFpBK == 0 && run % step == 0) || run == p->gk;
-  p->fused = !force_steps && !p->subgroups && p->nq == p->g.size && compute != SYMT_COMPUTE_BF16X3 &&
-             p->U.dtype == want && (!w || p->W.dtype == want) && trailing_k && whole_steps &&
+  const bool fp_ok = compute != SYMT_COMPUTE_BF16X3 && p->U.dtype == want && (!w || p->W.dtype == want) &&
+                     whole_steps;
+  // split-bf16: the register-staged tiles read U (binary64 or binary32) along
+  // 32-deep K-steps and split it into hi/lo in registers; W takes binary64
+  const bool bf_ok = compute == SYMT_COMPUTE_BF16X3 && !p->cplx &&
+                     (p->U.dtype == SYMT_F64 || p->U.dtype == SYMT_F32) && (!w || p->W.dtype == SYMT_F64) &&
+                     run % 32 == 0 && bf16x3_register_tile(p->M, p->gn, p->gk);
+  p->fused = !force_steps && !p->subgroups && p->nq == p->g.size && (fp_ok || bf_ok) && trailing_k &&
              p->M > 0 && p->N > 0 && p->Kd > 0 && p->U.elems > 0;
   if (p->fused) {
     const size_t G = static_cast<size_t>(p->g.size);
@@ -610,6 +617,32 @@ GemmChoice choose_fp_gemm(int64_t batch, int64_t M, int64_t N, int64_t K, int el
   GemmChoice g = choose_among(batch, M, N, K, elem, aligned, forced, sk_mode);
   if (g.tile < 0) g = choose_among(batch, M, N, K, elem, aligned, nullptr, sk_mode);
   return g;
+}
+
+// The split-bf16 launcher's choice: SYMT_GEMM_TILE may name one of its tiles;
+// by default global-to-LDS tiles where K holds whole 32-deep steps and the
+// product is at least 256 x 512.
+bool bf16x3_register_tile(int64_t M, int64_t N, int64_t K) {
+  const char* forced = std::getenv("SYMT_GEMM_TILE");
+  const std::string f = forced ? forced : "";
+  const bool dma_ok = K % 32 == 0;
+  if ((f == "bd256x128s3" || f == "bd128x256s3") && dma_ok) return false;
+  if (f == "b128x128k64" || f == "b128x128k32" || f == "b256x128k32" || f == "b128x256k32" ||
+      f == "b128x64k32" || f == "b128x96k32" || f == "b64x64k32")
+    return true;
+  return !(dma_ok && M >= 256 && N >= 512);
+}
+
+int bf16x3_fused_tile(int64_t M, int64_t N) {
+  const char* forced = std::getenv("SYMT_GEMM_TILE");
+  const std::string f = forced ? forced : "";
+  if (f == "b128x64k32") return 0;
+  if (f == "b128x256k32") return 2;
+  if (f == "b128x128k32") return 1;
+  if (f == "b128x96k32") return 3;
+  if (N <= 64) return 0;
+  if (N >= 1024 && M >= 1024) return 2;
+  return 1;
 }
 
 namespace {

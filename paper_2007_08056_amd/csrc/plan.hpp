@@ -132,6 +132,7 @@ struct FusedTables {
   const int64_t* rb = nullptr;      // nullptr: B is the aligned V_al
   const int64_t* cb = nullptr;
   int64_t ldb = 0;
+  int32_t a_bytes = 8;              // split-bf16 product: U's element size (8 binary64, 4 binary32)
 };
 
 struct OperandDesc {
@@ -216,6 +217,11 @@ constexpr int kSkSlots = 768;
 // Fewest K-iterations a stream-K workgroup takes on (bounds the pieces per tile).
 constexpr int kSkMinIters = 4;
 GemmChoice choose_fp_gemm(int64_t batch, int64_t M, int64_t N, int64_t K, int elem, bool aligned);
+// Split-bf16 product: whether the launcher runs register-staged tiles on this
+// shape (else global-to-LDS ones), and which of the fused product's three
+// register tiles it takes (0: 128 x 64, 1: 128 x 128, 2: 128 x 256, 3: 128 x 96).
+bool bf16x3_register_tile(int64_t M, int64_t N, int64_t K);
+int bf16x3_fused_tile(int64_t M, int64_t N);
 
 // True when the aligned form of operand 0 (U), 1 (V) or 2 (W) is zero outside
 // slice q_pin: U_al carries deltas (1) and (2), V_al (2) and (3), W_al is their

@@ -164,7 +164,7 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
                          : reinterpret_cast<char*>(rb);
   // 16-byte loads of A need every row's K run to start 16-byte aligned
   const int64_t run = (p.cplx ? 2 : 1) * p.nK, vw = p.compute == SYMT_COMPUTE_F64 ? 2 : 4;
-  const int vec = aligned16(p.U.data) && run % vw == 0 ? 2 : 1;
+  const int vec = aligned16(p.U.data) && (p.compute == SYMT_COMPUTE_BF16X3 || run % vw == 0) ? 2 : 1;
   // V in place: the launcher must pick a global-to-LDS tile for these operands
   // (the same choice it makes below: A = U, B = V, both 16-byte aligned)
   const int elem = p.compute == SYMT_COMPUTE_F64 ? 8 : 4;
@@ -189,6 +189,7 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
   if (rc_) return ctx_fail(ctx, rc_, err);
   if (!fb && (rc_ = do_align(ctx, p, 1, val, s, true, chg[1]))) return rc_;
   symt::FusedTables f{ra, ca, rc, cc, vec};
+  f.a_bytes = static_cast<int32_t>(elem_bytes(p.U.dtype));
   if (fb) {
     f.rb = rb;
     f.cb = cb;

@@ -23,6 +23,7 @@
 #include <cstdint>
 #include <string>
 
+#include "bf16_split.hpp"
 #include "plan.hpp"
 #include "xform_index.hpp"
 
@@ -34,16 +35,6 @@ template <typename T, int V>
 struct alignas(sizeof(T) * V) VecT {
   T v[V];
 };
-
-// bfloat16 by round-to-nearest-even on the binary32 bit pattern (finite inputs).
-__device__ __forceinline__ uint16_t bf16_rne(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return static_cast<uint16_t>(u >> 16);
-}
-__device__ __forceinline__ float bf16_as_f32(uint16_t h) {
-  return __uint_as_float(static_cast<uint32_t>(h) << 16);
-}
 
 // OUT: 0 -> f64, 1 -> f32, 2 -> bf16 hi plane at off, lo plane at off + plane.
 template <int OUT, int V>
@@ -61,12 +52,7 @@ __device__ __forceinline__ void store_vec(void* dst, int64_t off, int64_t plane,
   } else {
     VecT<uint16_t, V> h, l;
 #pragma unroll
-    for (int i = 0; i < V; ++i) {
-      const float f = static_cast<float>(x[i]);
-      const uint16_t hb = bf16_rne(f);
-      h.v[i] = hb;
-      l.v[i] = bf16_rne(f - bf16_as_f32(hb));
-    }
+    for (int i = 0; i < V; ++i) bf16_split(x[i], h.v[i], l.v[i]);
     uint16_t* d = static_cast<uint16_t*>(dst);
     *reinterpret_cast<VecT<uint16_t, V>*>(d + off) = h;
     *reinterpret_cast<VecT<uint16_t, V>*>(d + off + plane) = l;

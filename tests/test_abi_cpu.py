@@ -9,6 +9,7 @@ import pytest
 import oracle as O
 import synth
 from paper_2007_08056_amd import _lib as L
+from tests.seeding import seed
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -336,7 +337,7 @@ def test_live_slices_match_the_oracles_nonzero_slices(G, s, t, v):
     """The planner multiplies only the Q slices where all three deltas can hold:
     exactly those where the oracle's U_al and V_al (random data) are both nonzero."""
     from tests import gpu_helpers as H
-    rng = np.random.default_rng(abs(hash(("live", G, s, t, v))) % 2 ** 31)
+    rng = np.random.default_rng(seed(("live", G, s, t, v)))
     for _ in range(4):
         sub, su, sv = H.subgroup_case(rng, G, s, t, v, nmax=2)
         Ru, Rv = rng.standard_normal(su.reduced_shape()), rng.standard_normal(sv.reduced_shape())
@@ -404,6 +405,32 @@ def test_v_in_place_layout_rules(monkeypatch):
     monkeypatch.setenv("SYMT_GEMM_TILE", "d96x96s2")
     small = _plan("abkl,klij->abij", 4, _desc("++--", 0, (3, 5, 4, 8)), _desc("++--", 0, (4, 8, 2, 6)))[1]
     assert small.fused == 1 and small.fused_v == 1
+
+
+def test_split_bf16_fused_plans(monkeypatch):
+    """The split-bf16 product reads U in place (binary64 or binary32, split into
+    hi/lo in registers) when U's trailing contracted block holds whole 32-deep
+    K-steps, W is binary64 and the launcher runs register tiles on the shape."""
+    monkeypatch.delenv("SYMT_GEMM_TILE", raising=False)
+    bf = L.COMPUTE["bf16x3"]
+    v = _desc("++--", 0, (24, 24, 6, 6))
+    ladder = _plan("abcd,cdij->abij", 8, _desc("++--", 0, (24, 24, 24, 24)), v, compute=bf)[1]
+    assert ladder.fused == 1 and ladder.fused_v == 0
+    r = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    assert ladder.workspace_bytes == r(ladder.bytes_v_al) + r(8 * 8 * 4608) * 2 + r(8 * 8 * 4608) + \
+        r(8 * 8 * 288)
+    u32, v32 = _desc("++--", 0, (24, 24, 24, 24), L.SYMT_F32), _desc("++--", 0, (24, 24, 6, 6), L.SYMT_F32)
+    assert _plan("abcd,cdij->abij", 8, u32, v32, compute=bf)[1].fused == 1
+    # a binary32 output, a contracted block of 16, a global-to-LDS shape (Z_16 ladder)
+    w32 = _desc("++--", 0, (24, 24, 6, 6), L.SYMT_F32)
+    assert _plan("abcd,cdij->abij", 8, _desc("++--", 0, (24, 24, 24, 24)), v, w32, compute=bf)[1].fused == 0
+    assert _plan("abcd,cdij->abij", 8, _desc("++--", 0, (24, 24, 4, 4)),
+                 _desc("++--", 0, (4, 4, 6, 6)), compute=bf)[1].fused == 0
+    assert _plan("abcd,cdij->abij", 16, _desc("++--", 0, (32, 32, 32, 32)),
+                 _desc("++--", 0, (32, 32, 8, 8)), compute=bf)[1].fused == 0
+    monkeypatch.setenv("SYMT_GEMM_TILE", "b128x128k32")
+    assert _plan("abcd,cdij->abij", 16, _desc("++--", 0, (32, 32, 32, 32)),
+                 _desc("++--", 0, (32, 32, 8, 8)), compute=bf)[1].fused == 1
 
 
 def test_split_k_for_few_tiles_and_long_k(monkeypatch):

@@ -13,6 +13,7 @@ import oracle as O
 import synth
 from synth import philox
 from tests import gpu_helpers as H
+from tests.seeding import seed
 
 pytestmark = pytest.mark.gpu
 
@@ -95,6 +96,8 @@ def test_sector_gemm_fp(P, shape, compute):
     ("bd256x128s3", (2, 300, 96, 200)), ("bd256x128s3", (1, 512, 64, 256)),
     ("bd128x256s3", (2, 200, 128, 300)), ("bd128x256s3", (3, 130, 32, 70)),
     (None, (2, 600, 256, 384)),
+    # the 96-wide register tile, ragged in M and N
+    ("b128x96k32", (2, 130, 64, 200)), ("b128x96k32", (3, 257, 40, 96)),
 ])
 def test_sector_gemm_bf16x3(P, tile, shape, monkeypatch):
     if tile:
@@ -138,7 +141,7 @@ def _bf16_planes_of(x64):
 @pytest.mark.parametrize("case", ALIGN_CASES)
 def test_align_and_unalign_bit_exact(P, case):
     orders, ns, nt, nv = case
-    rng = np.random.default_rng(abs(hash(case)) % 2 ** 32)
+    rng = np.random.default_rng(seed(case))
     for rep in range(3):
         sub, su, sv = H.random_case(rng, orders, ns, nt, nv, nmax=4)
         say(f"align {sub} G={orders} rep={rep} dims_u={su.dims} dims_v={sv.dims}")
@@ -207,7 +210,7 @@ def _check_align_unalign(P, sub, su, sv, rng):
 @pytest.mark.parametrize("case", RAGGED_CASES)
 def test_align_unalign_ragged_inner_dims(P, case):
     orders, ns, nt, nv = case
-    rng = np.random.default_rng(abs(hash(("ragged",) + case)) % 2 ** 32)
+    rng = np.random.default_rng(seed(("ragged",) + case))
     G = int(np.prod(orders))
     done = 0
     while done < 3:
@@ -254,7 +257,7 @@ def test_align_unalign_mps_environment_shapes(P, sub, cu, du, cv, dv):
 @pytest.mark.parametrize("case", ALIGN_CASES)
 def test_contract_random_vs_oracle(P, case):
     orders, ns, nt, nv = case
-    rng = np.random.default_rng(abs(hash(case)) % 2 ** 31 + 1)
+    rng = np.random.default_rng(seed(case))
     for rep in range(2):
         sub, su, sv = H.random_case(rng, orders, ns, nt, nv, nmax=5)
         say(f"contract {sub} G={orders} rep={rep}")
@@ -434,6 +437,61 @@ def test_fused_product_equals_steps_and_oracle(P, case, compute):
     assert torch.equal(w_o.data, w_s.data)
 
 
+# split-bf16 fused product: U's trailing contracted block a multiple of 32
+BF_FUSED_CASES = [
+    ("abkl,klij->abij", (4,), "++--", "++--", (3, 5, 4, 8), (4, 8, 2, 6)),
+    ("ak,kb->ab", (5,), "+-", "++", (33, 64), (64, 20)),
+    ("abkl,klij->abji", (3,), "+-+-", "-+++", (2, 7, 8, 4), (8, 4, 2, 1)),
+    ("akl,klb->ab", (2, 3), "+-+", "-++", (7, 2, 16), (2, 16, 12)),
+    ("xykcd,kcdz->zxy", (2,), "+-+--", "-++-", (3, 3, 2, 2, 8), (2, 2, 8, 5)),
+    ("abkl,klij->abij", (4,), "++--", "++--", (3, 5, 4, 4), (4, 4, 2, 3)),   # run 16: not fused
+]
+
+
+@pytest.mark.parametrize("case", BF_FUSED_CASES)
+@pytest.mark.parametrize("udt", ["f64", "f32"])
+@pytest.mark.parametrize("tile", ["", "b128x64k32", "b128x96k32", "b128x128k32", "b128x256k32"])
+def test_fused_split_bf16_product(P, case, udt, tile, monkeypatch):
+    """Split-bf16 product reading U in place (hi/lo split in registers) and writing W
+    in place: bit-identical to the three-step path (which writes hi/lo planes),
+    within the split-bf16 bound of the oracle; also for a U that is not 16-byte
+    aligned (one-element loads)."""
+    sub, orders, cu, cv, du, dv = case
+    if tile:
+        monkeypatch.setenv("SYMT_GEMM_TILE", tile)
+    else:
+        monkeypatch.delenv("SYMT_GEMM_TILE", raising=False)
+    rng = np.random.default_rng(len(sub) * 13 + sum(du))
+    g = O.Group(orders)
+    su = O.Sym.make(cu, int(rng.integers(g.size)), du, g)
+    sv = O.Sym.make(cv, int(rng.integers(g.size)), dv, g)
+    say(f"fused split-bf16 {sub} G={orders} u={udt} tile={tile or 'default'}")
+    dt = torch.float64 if udt == "f64" else torch.float32
+    Ru = rng.standard_normal(su.reduced_shape())
+    Rv = rng.standard_normal(sv.reduced_shape())
+    u = _sym_tensor(P, Ru, su, dt)
+    v = _sym_tensor(P, Rv, sv, dt)
+    tu = sub.split(",")[0]
+    nK = int(np.prod([d for m, d in zip(tu, du) if m in sub.split(",")[1].split("->")[0]]))
+    assert P.plan(sub, u, v, "bf16x3").fused == int(nK % 32 == 0)
+    w_f = P.output_like(sub, u, v, dtype=torch.float64)
+    w_s = P.output_like(sub, u, v, dtype=torch.float64)
+    P.contract_into(sub, u, v, w_f, "bf16x3")
+    P.contract_into(sub, u, v, w_s, "bf16x3", steps=True)
+    assert torch.equal(w_f.data, w_s.data)
+    U64, V64 = H.to_np(u.data).astype(np.float64), H.to_np(v.data).astype(np.float64)
+    ref, _ = O.contract_blocks(sub, U64, su, V64, sv)
+    absref, _ = O.contract_blocks(sub, np.abs(U64), su, np.abs(V64), sv)
+    k = H.contracted_extent(sub, su)
+    assert np.all(np.abs(H.to_np(w_f.data) - ref) <= H.bound_factor("bf16x3", k) * absref + 1e-300)
+    buf = torch.zeros(u.data.numel() + 1, dtype=dt, device=DEV)
+    buf[1:] = u.data.reshape(-1)
+    u_off = P.SymTensor(buf[1:].view(u.data.shape), u.signs, u.charge, u.group)
+    w_o = P.output_like(sub, u, v, dtype=torch.float64)
+    P.contract_into(sub, u_off, v, w_o, "bf16x3")
+    assert torch.equal(w_o.data, w_s.data)
+
+
 # V read in place: contracted modes first in V, in U's K order; K runs of 32
 # rows; V's trailing output run a multiple of 16 bytes (f64; the last case's run
 # of 6 is not for f32)
@@ -541,7 +599,7 @@ def _with_tables(rng, sub, su, sv):
                                   ((8,), 2, 2, 2)])
 def test_contract_with_charge_tables_vs_oracle(P, case):
     orders, ns, nt, nv = case
-    rng = np.random.default_rng(abs(hash(("charges",) + case)) % 2 ** 31)
+    rng = np.random.default_rng(seed(("charges",) + case))
     for rep in range(2):
         sub, su0, sv0 = H.random_case(rng, orders, ns, nt, nv, nmax=5)
         su, sv = _with_tables(rng, sub, su0, sv0)
@@ -628,7 +686,7 @@ def _degenerate_case(rng, sub, orders, nmax=5):
 @pytest.mark.parametrize("sub", DEGENERATE)
 @pytest.mark.parametrize("orders", [(4,), (2, 3)])
 def test_degenerate_contractions_vs_oracle(P, sub, orders):
-    rng = np.random.default_rng(abs(hash(("degenerate", sub, orders))) % 2 ** 31)
+    rng = np.random.default_rng(seed(("degenerate", sub, orders)))
     for with_tables in (False, True):
         su, sv = _degenerate_case(rng, sub, orders)
         if with_tables:
@@ -679,7 +737,7 @@ def test_degenerate_contractions_vs_oracle(P, sub, orders):
 @pytest.mark.parametrize("sub", ["ij,jk->ik", "ijk,klm->ijlm", "abcd,cdij->abij", "ak,k->a", "a,b->ab"])
 def test_u1_emulation_vs_dense_u1_einsum(P, sub):
     from tests import u1_cases as U1
-    rng = np.random.default_rng(abs(hash(("u1-gpu", sub))) % 2 ** 31)
+    rng = np.random.default_rng(seed(("u1-gpu", sub)))
     for g_extra in (0, 3):
         c = U1.random_case(rng, sub, g_extra, nmax=4)
         say(f"u1 {sub} G={c['G']}")
@@ -716,7 +774,7 @@ def _cplx(rng, shape):
 
 @pytest.mark.parametrize("orders,s,t,v", COMPLEX_CASES)
 def test_complex_contractions_vs_oracle(P, orders, s, t, v):
-    rng = np.random.default_rng(abs(hash(("cplx-gpu", orders, s, t, v))) % 2 ** 31)
+    rng = np.random.default_rng(seed(("cplx-gpu", orders, s, t, v)))
     for with_tables in (False, True):
         sub, su, sv = H.random_case(rng, orders, s, t, v, nmax=5)
         if with_tables:
@@ -762,7 +820,7 @@ def test_complex_contractions_vs_oracle(P, orders, s, t, v):
 
 @pytest.mark.parametrize("orders,s,t,v", [((3,), 1, 1, 1), ((2, 2), 2, 1, 1), ((4,), 1, 1, 0)])
 def test_complex_gradients_vs_dense_autograd(P, orders, s, t, v):
-    rng = np.random.default_rng(abs(hash(("cplx-grad", orders, s, t, v))) % 2 ** 31)
+    rng = np.random.default_rng(seed(("cplx-grad", orders, s, t, v)))
     sub, su, sv = H.random_case(rng, orders, s, t, v, nmax=4)
     say(f"complex gradient {sub} G={orders}")
     Ru, Rv = _cplx(rng, su.reduced_shape()), _cplx(rng, sv.reduced_shape())
@@ -797,7 +855,7 @@ SUBGROUP_CASES = [(4, 1, 1, 1), (6, 2, 1, 1), (8, 1, 2, 1), (12, 1, 1, 2), (6, 2
 
 @pytest.mark.parametrize("G,s,t,v", SUBGROUP_CASES)
 def test_subgroup_contractions_vs_oracle(P, G, s, t, v):
-    rng = np.random.default_rng(abs(hash(("subgroup-gpu", G, s, t, v))) % 2 ** 31)
+    rng = np.random.default_rng(seed(("subgroup-gpu", G, s, t, v)))
     for trial in range(3):
         sub, su, sv = H.subgroup_case(rng, G, s, t, v, nmax=5)
         say(f"subgroup {sub} G={G} sectors {su.sectors} {sv.sectors}")
@@ -807,7 +865,9 @@ def test_subgroup_contractions_vs_oracle(P, G, s, t, v):
         u, v_ = _sym_tensor(P, Ru, su), _sym_tensor(P, Rv, sv)
         Gs, M, K, N = O.aligned_shape(sub, su, sv)
         info = P.plan(sub, u, v_)
-        assert (info.m, info.k, info.n) == (M, K, N) and info.fused == 0
+        # a mode with fewer than |G| sectors takes the three-step path
+        has_sub = any(h < G for x in (su, sv) if x.sectors for h in x.sectors)
+        assert (info.m, info.k, info.n) == (M, K, N) and (info.fused == 0 or not has_sub)
         dead = H.dead_stored_tuples(sw)
         for compute in ("f64", "f32", "bf16x3"):
             if compute == "bf16x3" and K % 8:
@@ -843,7 +903,7 @@ def test_subgroup_contractions_vs_oracle(P, G, s, t, v):
 
 @pytest.mark.parametrize("G,s,t,v", [(6, 1, 1, 1), (4, 2, 1, 1)])
 def test_subgroup_gradients_vs_dense_autograd(P, G, s, t, v):
-    rng = np.random.default_rng(abs(hash(("subgroup-grad", G, s, t, v))) % 2 ** 31)
+    rng = np.random.default_rng(seed(("subgroup-grad", G, s, t, v)))
     sub, su, sv = H.subgroup_case(rng, G, s, t, v, nmax=4)
     say(f"subgroup gradient {sub} G={G}")
     Ru, Rv = rng.standard_normal(su.reduced_shape()), rng.standard_normal(sv.reduced_shape())
