@@ -98,8 +98,8 @@
  * in the compute type, its contracted modes are affine in u's K order (each
  * one's stride is the next one's stride times its block size), a K run holds
  * whole K-steps, its last modes are output modes whose contiguous run is a
- * multiple of 16 bytes, the product runs on global-to-LDS tiles, and u and v
- * are 16-byte aligned: then two more tables let the product read B from v's
+ * multiple of 16 bytes, and v is 16-byte aligned: then two more tables let
+ * the product read B from v's
  * standard form as well (info.fused_v = 1) and no aligned form is written at
  * all.  The workspace holds V_al (used when v is not read in place) and the
  * tables.  Results are identical in value to the three-step path: the product

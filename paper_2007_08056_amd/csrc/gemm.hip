@@ -92,6 +92,9 @@ struct alignas(sizeof(T) * V) VecT {
 // element (q, m, k) at ra[q*M + m] + ca[q*K + k], and C is written straight
 // into W's standard reduced form at rc[q*M + m] + cc[q*N + n] (separable offset
 // tables).  FA needs every BK-aligned run of K to be contiguous in U.
+// With FA and rb given, B is V's standard form: row k0 + r of a K-step at
+// rb[q*K + k0] + r * ldb, column n at cb[q*N + n] (every K-step inside one affine
+// run of rows, every V-wide load inside one contiguous run of columns).
 // SPLIT: gridDim.x = ntiles * splits; workgroup (tile, s) multiplies the s-th of
 // `splits` equal runs of K-steps and stores its partial tile in accumulator
 // order at part + (tile * splits + s) * BM * BN; k_split_sum adds them.
@@ -104,7 +107,10 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
                                                        const int64_t* __restrict__ ca,
                                                        const int64_t* __restrict__ rc,
                                                        const int64_t* __restrict__ cc,
-                                                       T* __restrict__ part = nullptr, int splits = 1) {
+                                                       T* __restrict__ part = nullptr, int splits = 1,
+                                                       const int64_t* __restrict__ rb = nullptr,
+                                                       const int64_t* __restrict__ cb = nullptr,
+                                                       int64_t ldb = 0) {
   constexpr int NT = 64 * WM * WN;
   constexpr int PAD = 16 / sizeof(T);
   // B rows: a fragment read touches 16 consecutive n at 4 consecutive k; pad each
@@ -129,8 +135,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
   int64_t q;
   int tm, tn;
   tile_coords(tile, tiles_m, tiles_n, q, tm, tn);
+  const bool fb = FA && rb != nullptr;   // uniform: B read in place
   const T* Aq = A + (FA ? 0 : q * static_cast<int64_t>(M) * K);
-  const T* Bq = B + q * static_cast<int64_t>(K) * N;
+  const T* Bq = B + (fb ? 0 : q * static_cast<int64_t>(K) * N);
   T* Cq = C + (FC ? 0 : q * static_cast<int64_t>(M) * N);
   const int m0 = tm * BM, n0 = tn * BN;
 
@@ -149,9 +156,21 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
     arow[i] = (FA && e < BM * BK && gr < M) ? ra[q * M + gr] : static_cast<int64_t>(gr) * K;
   }
 
-  VecT<T, V> ra_[LA], rb[LB];
+  // B: offset of each of this thread's tile positions, fixed across K-steps
+  // (row r of the step, column gc), plus one row offset per K-step
+  int64_t bpos[LB];
+#pragma unroll
+  for (int i = 0; i < LB; ++i) {
+    const int e = (tid + i * NT) * V;
+    const int r = e / BN, gc = n0 + e % BN;
+    bpos[i] = fb ? static_cast<int64_t>(r) * ldb + (e < BK * BN && gc < N ? cb[q * N + gc] : 0)
+                 : static_cast<int64_t>(r) * N + gc;
+  }
+
+  VecT<T, V> ra_[LA], rb_[LB];
   auto load_tiles = [&](int k0) {
     const int64_t acol = FA ? ca[q * K + k0] : k0;
+    const int64_t brow = fb ? rb[q * K + k0] : static_cast<int64_t>(k0) * N;
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
       const int e = (tid + i * NT) * V;              // element index inside the BM x BK tile
@@ -169,10 +188,10 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
       const int r = e / BN, c = e % BN;
       const int gr = k0 + r, gc = n0 + c;
       if (e < BK * BN && gr < K && gc < N)
-        rb[i] = *reinterpret_cast<const VecT<T, V>*>(Bq + static_cast<int64_t>(gr) * N + gc);
+        rb_[i] = *reinterpret_cast<const VecT<T, V>*>(Bq + brow + bpos[i]);
       else
 #pragma unroll
-        for (int j = 0; j < V; ++j) rb[i].v[j] = T(0);
+        for (int j = 0; j < V; ++j) rb_[i].v[j] = T(0);
     }
   };
   auto store_tiles = [&](int buf) {
@@ -184,7 +203,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
 #pragma unroll
     for (int i = 0; i < LB; ++i) {
       const int e = (tid + i * NT) * V;
-      if (e < BK * BN) *reinterpret_cast<VecT<T, V>*>(&Bs[buf][e / BN][e % BN]) = rb[i];
+      if (e < BK * BN) *reinterpret_cast<VecT<T, V>*>(&Bs[buf][e / BN][e % BN]) = rb_[i];
     }
   };
 
@@ -836,10 +855,10 @@ hipError_t launch_fp(int vec, int64_t batch, int M, int N, int K, const void* A,
     const dim3 grid(static_cast<unsigned>(ntiles * splits));
     if (f && fv)
       hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, VV, true, true, true>), grid, block, 0, s, a, b, c, M, N,
-                         K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, splits);
+                         K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, splits, f->rb, f->cb, f->ldb);
     else if (f)
       hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, 1, true, true, true>), grid, block, 0, s, a, b, c, M, N,
-                         K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, splits);
+                         K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, splits, f->rb, f->cb, f->ldb);
     else if (fv)
       hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, VV, false, false, true>), grid, block, 0, s, a, b, c, M,
                          N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, splits);
@@ -859,10 +878,10 @@ hipError_t launch_fp(int vec, int64_t batch, int M, int N, int K, const void* A,
   const dim3 grid(static_cast<unsigned>(ntiles));
   if (f && fv) {
     hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, VV, true, true>), grid, block, 0, s, a, b, c,
-                       M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, nullptr, 1);
+                       M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, nullptr, 1, f->rb, f->cb, f->ldb);
   } else if (f) {
     hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, 1, true, true>), grid, block, 0, s, a, b, c,
-                       M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, nullptr, 1);
+                       M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, nullptr, 1, f->rb, f->cb, f->ldb);
   } else if (fv) {
     hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, VV, false, false>), grid, block, 0, s, a, b,
                        c, M, N, K, tiles_m, tiles_n, ntiles, nullptr, nullptr, nullptr, nullptr, nullptr, 1);
@@ -1247,10 +1266,6 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
     const bool aligned = (reinterpret_cast<uintptr_t>(A) & 15) == 0 &&
                          (reinterpret_cast<uintptr_t>(B) & 15) == 0 && (!fused || fused->vec > 1);
     const GemmChoice gc = choose_fp_gemm(batch, M, N, K, f64 ? 8 : 4, aligned);
-    if (fused && fused->rb && !gc.dma) {
-      if (err) *err = "B read in place needs a global-to-LDS tile and 16-byte aligned operands";
-      return SYMT_EUNSUPPORTED;
-    }
     if ((!gc.sk && gc.splits <= 1) || (reinterpret_cast<uintptr_t>(part) & 15) != 0) part = nullptr;
     e = f64 ? launch_fp_tile<double>(gc.tile, vec, batch, M, N, K, A, B, C, stream, fused, part, part_bytes,
                                      gc.splits)

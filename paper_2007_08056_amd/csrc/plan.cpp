@@ -159,8 +159,8 @@ AlignedLayout aligned_layout(int32_t compute, int operand) {
   return kRowMajor;
 }
 
-// The global-to-LDS tiles read row k0 + k of a K-step of V at rb(Q, k0) + k ldb
-// and 16-byte column chunks at cb(Q, n).  That needs, for a real V:
+// The product tiles read row k0 + k of a K-step of V at rb(Q, k0) + k ldb and
+// 16-byte column chunks at cb(Q, n).  That needs, for a real V:
 //  * its contracted modes, in U's K order, affine: each one's stride is ldb
 //    times the block sizes of the later ones, ldb the stride of the last;
 //  * a K run (the contracted block, fixed sectors) of whole K-steps (16 f64 or
@@ -469,13 +469,11 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
     p->workspace = round_up(p->ws_v_al, 256) + p->bytes_tables;
   }
   // ---- V read in place as well (see v_in_place_layout); V_al keeps its place in
-  // the workspace: a V that is not 16-byte aligned, or another tile choice at
-  // launch, aligns V as before.
+  // the workspace: a V that is not 16-byte aligned is aligned as before.
   int64_t ldb = 0;
   const char* vip_env = std::getenv("SYMT_FUSED_V");
   const bool vip_off = vip_env && std::atoi(vip_env) == 0;
-  if (!vip_off && p->fused && !p->cplx && p->V.dtype == want && v_in_place_layout(*p, &ldb) &&
-      choose_fp_gemm(p->g.size, p->M, p->gn, p->gk, static_cast<int>(ea), true).dma) {
+  if (!vip_off && p->fused && !p->cplx && p->V.dtype == want && v_in_place_layout(*p, &ldb)) {
     const size_t G = static_cast<size_t>(p->g.size);
     p->fused_b = true;
     p->ldb = ldb;

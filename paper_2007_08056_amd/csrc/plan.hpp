@@ -169,8 +169,8 @@ struct Plan {
   int32_t compute = 0;
   bool fused = false;               // A read from U's standard form, C written to W's
   // B read from V's standard form too (no V_al): V's rows are affine inside every
-  // K-step (stride ldb), its columns come in runs of whole 16-byte chunks, and the
-  // product runs on global-to-LDS tiles (decided again at launch)
+  // K-step (stride ldb) and its columns come in runs of whole 16-byte chunks
+  // (used when V is 16-byte aligned)
   bool fused_b = false;
   int64_t ldb = 0;
   size_t bytes_u_al = 0, bytes_v_al = 0, bytes_w_al = 0, workspace = 0;

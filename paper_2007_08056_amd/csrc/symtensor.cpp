@@ -165,11 +165,9 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
   // 16-byte loads of A need every row's K run to start 16-byte aligned
   const int64_t run = (p.cplx ? 2 : 1) * p.nK, vw = p.compute == SYMT_COMPUTE_F64 ? 2 : 4;
   const int vec = aligned16(p.U.data) && (p.compute == SYMT_COMPUTE_BF16X3 || run % vw == 0) ? 2 : 1;
-  // V in place: the launcher must pick a global-to-LDS tile for these operands
-  // (the same choice it makes below: A = U, B = V, both 16-byte aligned)
-  const int elem = p.compute == SYMT_COMPUTE_F64 ? 8 : 4;
-  const bool fb = p.fused_b && vec > 1 && aligned16(p.V.data) &&
-                  symt::choose_fp_gemm(p.g.size, p.M, p.gn, p.gk, elem, true).dma;
+  // V in place: its column chunks take 16-byte loads (global-to-LDS tiles, and
+  // register tiles whose loads are vectors), so V must be 16-byte aligned
+  const bool fb = p.fused_b && aligned16(p.V.data);
   std::string err;
   int rc_ = timed(ctx, 0, s, [&] {
     symt::OffsetBatch b;

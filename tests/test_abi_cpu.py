@@ -375,10 +375,10 @@ def test_fused_needs_whole_k_steps_per_run():
 
 
 def test_v_in_place_layout_rules(monkeypatch):
-    """The global-to-LDS tiles read B straight from V's standard form when V's
-    contracted modes are affine in U's K order, a K run holds whole K-steps, V's
-    trailing output modes form runs of whole 16-byte chunks, and the tile choice
-    is a global-to-LDS one; otherwise V is aligned as before."""
+    """The product reads B straight from V's standard form when V's contracted
+    modes are affine in U's K order, a K run holds whole K-steps and V's
+    trailing output modes form runs of whole 16-byte chunks; otherwise V is
+    aligned as before."""
     monkeypatch.delenv("SYMT_GEMM_TILE", raising=False)
     monkeypatch.delenv("SYMT_GEMM_SK", raising=False)
     u = _desc("++--", 0, (24, 24, 24, 24))
@@ -392,19 +392,24 @@ def test_v_in_place_layout_rules(monkeypatch):
     # K run of 24 f64 rows is not whole 16-row steps
     u24 = _desc("++--", 0, (24, 24, 4, 6))
     assert _plan("abcd,cdij->abij", 8, u24, _desc("++--", 0, (4, 6, 6, 6)))[1].fused_v == 0
-    # complex operands, small products (register tiles), a forced register tile
+    # complex operands; a K run of 4 x 4 = 16 rows is one whole step
     c = _desc("++--", 0, (24, 24, 24, 24), L.SYMT_C128)
     assert _plan("abcd,cdij->abij", 8, c, _desc("++--", 0, (24, 24, 6, 6), L.SYMT_C128))[1].fused_v == 0
     assert _plan("abcd,cdij->abij", 8, _desc("++--", 0, (4, 4, 4, 4)),
-                 _desc("++--", 0, (4, 4, 2, 2)))[1].fused_v == 0
+                 _desc("++--", 0, (4, 4, 2, 2)))[1].fused_v == 1
+    # register tiles read V in place too: a forced one, a small product, binary32
     monkeypatch.setenv("SYMT_GEMM_TILE", "128x48")
     forced = _plan("abcd,cdij->abij", 8, u, _desc("++--", 0, (24, 24, 6, 6)))[1]
-    assert forced.fused == 1 and forced.fused_v == 0
-    assert forced.workspace_bytes < ladder.workspace_bytes
-    # a small product on a forced global-to-LDS tile reads V in place
-    monkeypatch.setenv("SYMT_GEMM_TILE", "d96x96s2")
+    assert forced.fused == 1 and forced.fused_v == 1
+    monkeypatch.delenv("SYMT_GEMM_TILE")
     small = _plan("abkl,klij->abij", 4, _desc("++--", 0, (3, 5, 4, 8)), _desc("++--", 0, (4, 8, 2, 6)))[1]
     assert small.fused == 1 and small.fused_v == 1
+    u32, v32 = _desc("++--", 0, (24, 24, 24, 24), L.SYMT_F32), _desc("++--", 0, (24, 24, 6, 6), L.SYMT_F32)
+    assert _plan("abcd,cdij->abij", 8, u32, v32, compute=1)[1].fused_v == 1
+    # switched off: V aligned, no V tables
+    monkeypatch.setenv("SYMT_FUSED_V", "0")
+    off = _plan("abcd,cdij->abij", 8, u, _desc("++--", 0, (24, 24, 6, 6)))[1]
+    assert off.fused == 1 and off.fused_v == 0 and off.workspace_bytes < ladder.workspace_bytes
 
 
 def test_split_bf16_fused_plans(monkeypatch):
