@@ -95,6 +95,9 @@ struct alignas(sizeof(T) * V) VecT {
 // With FA and rb given, B is V's standard form: row k0 + r of a K-step at
 // rb[q*K + k0] + r * ldb, column n at cb[q*N + n] (every K-step inside one affine
 // run of rows, every V-wide load inside one contiguous run of columns).
+// krun > 0: K is K / krun runs of krun indices, and each run is stepped on its
+// own (ceil(krun / BK) steps, the last one masked past the run's end), so a
+// K-step never straddles two runs whatever krun is; krun = 0 steps K plainly.
 // SPLIT: gridDim.x = ntiles * splits; workgroup (tile, s) multiplies the s-th of
 // `splits` equal runs of K-steps and stores its partial tile in accumulator
 // order at part + (tile * splits + s) * BM * BN; k_split_sum adds them.
@@ -110,7 +113,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
                                                        T* __restrict__ part = nullptr, int splits = 1,
                                                        const int64_t* __restrict__ rb = nullptr,
                                                        const int64_t* __restrict__ cb = nullptr,
-                                                       int64_t ldb = 0) {
+                                                       int64_t ldb = 0, int krun = 0) {
   constexpr int NT = 64 * WM * WN;
   constexpr int PAD = 16 / sizeof(T);
   // B rows: a fragment read touches 16 consecutive n at 4 consecutive k; pad each
@@ -168,15 +171,26 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
   }
 
   VecT<T, V> ra_[LA], rb_[LB];
-  auto load_tiles = [&](int k0) {
+  // K-step kt starts at k0 and holds kv valid indices (uniform)
+  const int spr = krun > 0 ? (krun + BK - 1) / BK : 0;
+  auto load_tiles = [&](int kt) {
+    int k0, kv;
+    if (krun > 0) {
+      const int run = kt / spr, st = kt - run * spr;
+      k0 = run * krun + st * BK;
+      kv = min(BK, krun - st * BK);
+    } else {
+      k0 = kt * BK;
+      kv = K - k0;
+    }
     const int64_t acol = FA ? ca[q * K + k0] : k0;
     const int64_t brow = fb ? rb[q * K + k0] : static_cast<int64_t>(k0) * N;
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
       const int e = (tid + i * NT) * V;              // element index inside the BM x BK tile
       const int r = e / BK, c = e % BK;
-      const int gr = m0 + r, gc = k0 + c;
-      if (e < BM * BK && gr < M && gc < K)
+      const int gr = m0 + r;
+      if (e < BM * BK && gr < M && c < kv)
         ra_[i] = *reinterpret_cast<const VecT<T, V>*>(Aq + arow[i] + acol + c);
       else
 #pragma unroll
@@ -186,8 +200,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
     for (int i = 0; i < LB; ++i) {
       const int e = (tid + i * NT) * V;              // element index inside the BK x BN tile
       const int r = e / BN, c = e % BN;
-      const int gr = k0 + r, gc = n0 + c;
-      if (e < BK * BN && gr < K && gc < N)
+      const int gc = n0 + c;
+      if (e < BK * BN && r < kv && gc < N)
         rb_[i] = *reinterpret_cast<const VecT<T, V>*>(Bq + brow + bpos[i]);
       else
 #pragma unroll
@@ -213,19 +227,19 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = Acc{};
 
-  const int nk_all = (K + BK - 1) / BK;
+  const int nk_all = krun > 0 ? K / krun * spr : (K + BK - 1) / BK;
   // this workgroup's K-steps [kt0, kt1): all of them, or its split's share
   const int per = SPLIT ? (nk_all + splits - 1) / splits : nk_all;
   const int kt0 = SPLIT ? min(nk_all, split * per) : 0;
   const int kt1 = SPLIT ? min(nk_all, kt0 + per) : nk_all;
   if (kt0 < kt1) {
-    load_tiles(kt0 * BK);
+    load_tiles(kt0);
     store_tiles(0);
   }
   __syncthreads();
   for (int kt = kt0; kt < kt1; ++kt) {
     const int buf = (kt - kt0) & 1;
-    if (kt + 1 < kt1) load_tiles((kt + 1) * BK);
+    if (kt + 1 < kt1) load_tiles(kt + 1);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       T a[TM], b[TN];
@@ -855,10 +869,10 @@ hipError_t launch_fp(int vec, int64_t batch, int M, int N, int K, const void* A,
     const dim3 grid(static_cast<unsigned>(ntiles * splits));
     if (f && fv)
       hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, VV, true, true, true>), grid, block, 0, s, a, b, c, M, N,
-                         K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, splits, f->rb, f->cb, f->ldb);
+                         K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, splits, f->rb, f->cb, f->ldb, f->krun);
     else if (f)
       hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, 1, true, true, true>), grid, block, 0, s, a, b, c, M, N,
-                         K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, splits, f->rb, f->cb, f->ldb);
+                         K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, splits, f->rb, f->cb, f->ldb, f->krun);
     else if (fv)
       hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, VV, false, false, true>), grid, block, 0, s, a, b, c, M,
                          N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, splits);
@@ -878,10 +892,10 @@ hipError_t launch_fp(int vec, int64_t batch, int M, int N, int K, const void* A,
   const dim3 grid(static_cast<unsigned>(ntiles));
   if (f && fv) {
     hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, VV, true, true>), grid, block, 0, s, a, b, c,
-                       M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, nullptr, 1, f->rb, f->cb, f->ldb);
+                       M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, nullptr, 1, f->rb, f->cb, f->ldb, f->krun);
   } else if (f) {
     hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, 1, true, true>), grid, block, 0, s, a, b, c,
-                       M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, nullptr, 1, f->rb, f->cb, f->ldb);
+                       M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, nullptr, 1, f->rb, f->cb, f->ldb, f->krun);
   } else if (fv) {
     hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, VV, false, false>), grid, block, 0, s, a, b,
                        c, M, N, K, tiles_m, tiles_n, ntiles, nullptr, nullptr, nullptr, nullptr, nullptr, 1);
@@ -1263,8 +1277,10 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
     const bool f64 = compute == SYMT_COMPUTE_F64;
     const int vw = f64 ? 2 : 4;
     const int vec = (K % vw == 0 && N % vw == 0) ? vw : 1;
+    // K stepped run by run (fused->krun) needs the register tiles
     const bool aligned = (reinterpret_cast<uintptr_t>(A) & 15) == 0 &&
-                         (reinterpret_cast<uintptr_t>(B) & 15) == 0 && (!fused || fused->vec > 1);
+                         (reinterpret_cast<uintptr_t>(B) & 15) == 0 &&
+                         (!fused || (fused->vec > 1 && fused->krun == 0));
     const GemmChoice gc = choose_fp_gemm(batch, M, N, K, f64 ? 8 : 4, aligned);
     if ((!gc.sk && gc.splits <= 1) || (reinterpret_cast<uintptr_t>(part) & 15) != 0) part = nullptr;
     e = f64 ? launch_fp_tile<double>(gc.tile, vec, batch, M, N, K, A, B, C, stream, fused, part, part_bytes,

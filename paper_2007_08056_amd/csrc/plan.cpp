@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <climits>
 #include <cstdlib>
 #include <string>
 #include <cstring>
@@ -160,14 +161,17 @@ AlignedLayout aligned_layout(int32_t compute, int operand) {
 }
 
 // The product tiles read row k0 + k of a K-step of V at rb(Q, k0) + k ldb and
-// 16-byte column chunks at cb(Q, n).  That needs, for a real V:
+// 16-byte column chunks at cb(Q, n) (single elements when K is stepped run by
+// run, which needs only the first condition).  That needs, for a real V:
 //  * its contracted modes, in U's K order, affine: each one's stride is ldb
 //    times the block sizes of the later ones, ldb the stride of the last;
 //  * a K run (the contracted block, fixed sectors) of whole K-steps (16 f64 or
 //    32 f32 rows);
 //  * its last modes J modes whose contiguous run holds whole 16-byte chunks.
-bool v_in_place_layout(const Plan& p, int64_t* ldb) {
+bool v_in_place_layout(const Plan& p, int64_t* ldb, bool* chunks) {
   if (p.cplx || p.v < 1 || p.t < 1 || p.subgroups) return false;
+  // (with K stepped run by run, every step lies in one run and loads are single
+  // elements: only the affine rows are needed)
   if (p.compute != SYMT_COMPUTE_F64 && p.compute != SYMT_COMPUTE_F32) return false;
   const int64_t elem = p.compute == SYMT_COMPUTE_F64 ? 8 : 4;
   const OperandDesc& V = p.V;
@@ -183,7 +187,9 @@ bool v_in_place_layout(const Plan& p, int64_t* ldb) {
   int64_t run_j = 1;
   for (int i = p.t - 1; i >= 0 && st[p.posJ_v[i]] == run_j; --i) run_j *= V.dims[p.posJ_v[i]];
   const int64_t ve = 16 / elem, step = 128 / elem;
-  if (p.nK % step != 0 || run_j % ve != 0 || p.gn % ve != 0) return false;
+  const bool whole_chunks = run_j % ve == 0 && p.gn % ve == 0;
+  if (chunks) *chunks = whole_chunks;
+  if (p.krun == 0 && (p.nK % step != 0 || !whole_chunks)) return false;
   *ldb = stride;
   return true;
 }
@@ -452,7 +458,8 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   // any K-step; the product masks the steps past its end.
   const int64_t run = (p->cplx ? 2 : 1) * p->nK;
   const int64_t step = 128 / (compute == SYMT_COMPUTE_F64 ? 8 : 4);
-  const bool whole_steps = (run % kFpBK == 0 && run % step == 0) || run == p->gk;
+  const bool whole_aligned = run % kFpBK == 0 && run % step == 0;
+  const bool whole_steps = whole_aligned || run == p->gk;
   const bool fp_ok = compute != SYMT_COMPUTE_BF16X3 && p->U.dtype == want && (!w || p->W.dtype == want) &&
                      whole_steps;
   // split-bf16: the register-staged tiles read U (binary64 or binary32) along
@@ -460,8 +467,17 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   const bool bf_ok = compute == SYMT_COMPUTE_BF16X3 && !p->cplx &&
                      (p->U.dtype == SYMT_F64 || p->U.dtype == SYMT_F32) && (!w || p->W.dtype == SYMT_F64) &&
                      run % 32 == 0 && bf16x3_register_tile(p->M, p->gn, p->gk);
-  p->fused = !force_steps && !p->subgroups && p->nq == p->g.size && (fp_ok || bf_ok) && trailing_k &&
+  // K runs that do not hold whole K-steps: where the product runs on register
+  // tiles anyway, they step each run on their own (masking its last step), so A
+  // is still read in place (and V, with one-element loads); global-to-LDS shapes
+  // keep the aligned forms.  A single such run is stepped the same way.
+  const bool stepped = !whole_aligned && compute != SYMT_COMPUTE_BF16X3 && !p->cplx && p->U.dtype == want &&
+                       (!w || p->W.dtype == want) && p->nK <= INT32_MAX && p->nK > 0 &&
+                       p->gk % p->nK == 0 &&
+                       !choose_fp_gemm(p->g.size, p->M, p->gn, p->gk, static_cast<int>(ea), true).dma;
+  p->fused = !force_steps && !p->subgroups && p->nq == p->g.size && (fp_ok || bf_ok || stepped) && trailing_k &&
              p->M > 0 && p->N > 0 && p->Kd > 0 && p->U.elems > 0;
+  p->krun = p->fused && stepped ? static_cast<int32_t>(p->nK) : 0;
   if (p->fused) {
     const size_t G = static_cast<size_t>(p->g.size);
     p->bytes_tables = round_up(8 * G * p->M, 256) * 2 + round_up(8 * G * p->gk, 256) +
@@ -473,9 +489,11 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   int64_t ldb = 0;
   const char* vip_env = std::getenv("SYMT_FUSED_V");
   const bool vip_off = vip_env && std::atoi(vip_env) == 0;
-  if (!vip_off && p->fused && !p->cplx && p->V.dtype == want && v_in_place_layout(*p, &ldb)) {
+  bool chunks = false;
+  if (!vip_off && p->fused && !p->cplx && p->V.dtype == want && v_in_place_layout(*p, &ldb, &chunks)) {
     const size_t G = static_cast<size_t>(p->g.size);
     p->fused_b = true;
+    p->fused_b_chunks = chunks;
     p->ldb = ldb;
     p->bytes_tables += round_up(8 * G * p->gk, 256) + round_up(8 * G * p->gn, 256);
     p->workspace = round_up(p->ws_v_al, 256) + p->bytes_tables;

@@ -133,6 +133,7 @@ struct FusedTables {
   const int64_t* cb = nullptr;
   int64_t ldb = 0;
   int32_t a_bytes = 8;              // split-bf16 product: U's element size (8 binary64, 4 binary32)
+  int32_t krun = 0;                 // > 0: K stepped run by run (register tiles)
 };
 
 struct OperandDesc {
@@ -172,7 +173,11 @@ struct Plan {
   // K-step (stride ldb) and its columns come in runs of whole 16-byte chunks
   // (used when V is 16-byte aligned)
   bool fused_b = false;
+  bool fused_b_chunks = false;      // V's columns in whole 16-byte chunks
   int64_t ldb = 0;
+  // fused with K runs that do not hold whole K-steps: the register tiles step each
+  // run on its own (krun = the run length; 0 = plain K-steps)
+  int32_t krun = 0;
   size_t bytes_u_al = 0, bytes_v_al = 0, bytes_w_al = 0, workspace = 0;
   size_t ws_u_al = 0, ws_v_al = 0, ws_w_al = 0;   // their regions in the contraction's workspace
   size_t bytes_tables = 0;          // fused: the four offset tables (six with fused_b)
@@ -186,8 +191,10 @@ struct Plan {
 };
 
 // Whether V's standard form can serve as the product's B operand directly
-// (affine rows inside every K-step, 16-byte column chunks); *ldb = row stride.
-bool v_in_place_layout(const Plan& p, int64_t* ldb);
+// (affine rows inside every K-step, 16-byte column chunks); *ldb = row stride,
+// *chunks = whether its columns come in whole 16-byte chunks (needed for vector
+// loads of B when K is stepped run by run).
+bool v_in_place_layout(const Plan& p, int64_t* ldb, bool* chunks = nullptr);
 
 // Parse and validate; returns a SYMT_* status and fills `err` on failure.
 int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,

@@ -164,10 +164,13 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
                          : reinterpret_cast<char*>(rb);
   // 16-byte loads of A need every row's K run to start 16-byte aligned
   const int64_t run = (p.cplx ? 2 : 1) * p.nK, vw = p.compute == SYMT_COMPUTE_F64 ? 2 : 4;
-  const int vec = aligned16(p.U.data) && (p.compute == SYMT_COMPUTE_BF16X3 || run % vw == 0) ? 2 : 1;
+  // (K stepped run by run: a run of whole vectors keeps every step's valid part whole)
+  int vec = aligned16(p.U.data) && (p.compute == SYMT_COMPUTE_BF16X3 || run % vw == 0) ? 2 : 1;
   // V in place: its column chunks take 16-byte loads (global-to-LDS tiles, and
   // register tiles whose loads are vectors), so V must be 16-byte aligned
-  const bool fb = p.fused_b && aligned16(p.V.data);
+  const bool fb = p.fused_b && (p.krun > 0 || aligned16(p.V.data));
+  // vector loads of B in place need 16-byte aligned, whole column chunks
+  if (fb && vec > 1 && !(aligned16(p.V.data) && p.fused_b_chunks)) vec = 1;
   std::string err;
   int rc_ = timed(ctx, 0, s, [&] {
     symt::OffsetBatch b;
@@ -188,6 +191,7 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
   if (!fb && (rc_ = do_align(ctx, p, 1, val, s, true, chg[1]))) return rc_;
   symt::FusedTables f{ra, ca, rc, cc, vec};
   f.a_bytes = static_cast<int32_t>(elem_bytes(p.U.dtype));
+  f.krun = p.krun;
   if (fb) {
     f.rb = rb;
     f.cb = cb;

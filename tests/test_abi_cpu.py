@@ -180,15 +180,27 @@ def test_workspace_sizes_per_compute_mode():
     v = _desc("++--", 0, (3, 3, 2, 2))
     sizes = {}
     for name, code in L.COMPUTE.items():
-        s = ctypes.c_size_t()
-        assert L.LIB.symtensor_workspace_size(b"abcd,cdij->abij", ctypes.byref(L.make_group(4)), u.ref,
-                                              v.ref, None, code, ctypes.byref(s)) == 0
-        sizes[name] = s.value
+        for steps in (False, True):
+            s = ctypes.c_size_t()
+            assert L.LIB.symtensor_workspace_size(b"abcd,cdij->abij", ctypes.byref(L.make_group(4)), u.ref,
+                                                  v.ref, None, code | (0x100 if steps else 0),
+                                                  ctypes.byref(s)) == 0
+            sizes[name, steps] = s.value
     eu, ev, ew = 4 ** 3 * 81, 4 ** 3 * 36, 4 ** 3 * 36
     r = lambda x: (x + 255) // 256 * 256  # noqa: E731
-    assert sizes["f64"] == r(8 * eu) + r(8 * ev) + r(8 * ew)
-    assert sizes["f32"] == r(4 * eu) + r(4 * ev) + r(4 * ew)
-    assert sizes["bf16x3"] == r(4 * eu) + r(4 * ev) + r(8 * ew)
+    # three steps: U_al | V_al | W_al
+    assert sizes["f64", True] == r(8 * eu) + r(8 * ev) + r(8 * ew)
+    assert sizes["f32", True] == r(4 * eu) + r(4 * ev) + r(4 * ew)
+    assert sizes["bf16x3", True] == r(4 * eu) + r(4 * ev) + r(8 * ew)
+    # fused (the contracted block of 9 is stepped on its own; U and V read in place):
+    # V_al, then row and column tables of U, W and V (M = K = 36, N = 16 per Q)
+    tables = lambda rows, cols: r(8 * 4 * rows) + r(8 * 4 * cols)  # noqa: E731
+    info = _plan("abcd,cdij->abij", 4, u, v, compute=L.COMPUTE["f64"])[1]
+    assert info.fused == 1 and info.fused_v == 1
+    assert sizes["f64", False] == r(8 * ev) + tables(36, 36) + tables(36, 16) + tables(36, 16)
+    # binary64 operands under f32 compute, and split-bf16 (whole 32-deep K-steps): three steps
+    assert sizes["f32", False] == sizes["f32", True]
+    assert sizes["bf16x3", False] == sizes["bf16x3", True]
 
 
 def test_status_strings():
@@ -349,14 +361,20 @@ def test_live_slices_match_the_oracles_nonzero_slices(G, s, t, v):
         assert info.flops == 2 * live * info.m * info.k * info.n
 
 
-def test_fused_needs_whole_k_steps_per_run():
+def test_fused_needs_whole_k_steps_per_run(monkeypatch):
     """The global-to-LDS tiles read a 128-byte K-step (16 f64, 32 f32) from one run of
-    contracted indices: f32 needs runs of 32, complex operands count reals."""
+    contracted indices: f32 needs runs of 32, complex operands count reals.  Other
+    runs are stepped one by one on register tiles (here forced to a global-to-LDS
+    tile, so the aligned forms are kept)."""
+    monkeypatch.setenv("SYMT_GEMM_TILE", "d128x128s2")
     G = 4
     u16, v16 = _desc("+-+-", 0, (3, 5, 4, 4)), _desc("+-+-", 0, (4, 4, 4, 4))
     assert _plan("abkl,klij->abij", G, u16, v16, compute=0)[1].fused == 1
     f16, fv16 = _desc("+-+-", 0, (3, 5, 4, 4), L.SYMT_F32), _desc("+-+-", 0, (4, 4, 4, 4), L.SYMT_F32)
     assert _plan("abkl,klij->abij", G, f16, fv16, compute=1)[1].fused == 0
+    # on the register tiles the run of 16 f32 is stepped on its own
+    monkeypatch.setenv("SYMT_GEMM_TILE", "128x128")
+    assert _plan("abkl,klij->abij", G, f16, fv16, compute=1)[1].fused == 1
     f32, fv32 = _desc("+-+-", 0, (3, 5, 4, 8), L.SYMT_F32), _desc("+-+-", 0, (4, 8, 4, 4), L.SYMT_F32)
     assert _plan("abkl,klij->abij", G, f32, fv32, compute=1)[1].fused == 1
     c16 = _desc("+-+-", 0, (3, 5, 4, 4), L.SYMT_C64)

@@ -415,26 +415,93 @@ def test_fused_product_equals_steps_and_oracle(P, case, compute):
     dt = torch.float64 if compute == "f64" else torch.float32
     u = _sym_tensor(P, Ru, su, dt)
     v = _sym_tensor(P, Rv, sv, dt)
-    assert P.plan(sub, u, v, compute).fused == int(_fusable(compute, sub, du))
+    whole = _fusable(compute, sub, du)
+    # runs that are not whole K-steps are stepped one by one on register tiles
+    # (fused as well, but summed in other groups than the three-step path)
+    assert P.plan(sub, u, v, compute).fused == 1 or not whole
     assert P.plan(sub, u, v, compute, steps=True).fused == 0
     w_f = P.output_like(sub, u, v, dtype=dt)
     w_s = P.output_like(sub, u, v, dtype=dt)
     P.contract_into(sub, u, v, w_f, compute)
     P.contract_into(sub, u, v, w_s, compute, steps=True)
-    assert torch.equal(w_f.data, w_s.data)
+    if whole:
+        assert torch.equal(w_f.data, w_s.data)
     ref, sw = O.contract_blocks(sub, H.to_np(u.data).astype(np.float64), su,
                                 H.to_np(v.data).astype(np.float64), sv)
     absref, _ = O.contract_blocks(sub, np.abs(Ru), su, np.abs(Rv), sv)
     k = H.contracted_extent(sub, su)
     fac = 2 * H.gamma(k, H.U64) if compute == "f64" else 1.05 * H.gamma(k, H.U32) + H.gamma(k, H.U64)
     assert np.all(np.abs(H.to_np(w_f.data) - ref) <= fac * absref + 1e-300)
+    assert np.all(np.abs(H.to_np(w_s.data) - ref) <= fac * absref + 1e-300)
     # U starting 8 bytes into a buffer: the fused product loads A one element at a time
     buf = torch.zeros(u.data.numel() + 1, dtype=dt, device=DEV)
     buf[1:] = u.data.reshape(-1)
     u_off = P.SymTensor(buf[1:].view(u.data.shape), u.signs, u.charge, u.group)
     w_o = P.output_like(sub, u, v, dtype=dt)
     P.contract_into(sub, u_off, v, w_o, compute)
-    assert torch.equal(w_o.data, w_s.data)
+    if whole:
+        assert torch.equal(w_o.data, w_s.data)
+    else:
+        assert np.all(np.abs(H.to_np(w_o.data) - ref) <= fac * absref + 1e-300)
+
+
+# Contracted blocks that are not whole K-steps (odd runs, as in the paper's
+# unbalanced (s, t, v) patterns): each run is stepped on its own on register tiles,
+# U and V read in place, W written in place.
+RUN_CASES = [
+    ("abcd,bcde->ae", (4,), "++--", "-++-", (5, 3, 5, 7), (3, 5, 7, 5)),
+    ("abcd,cde->abe", (3,), "+-+-", "-++", (4, 5, 3, 5), (3, 5, 6)),
+    ("abc,bcde->ade", (2, 2), "+++", "--+-", (6, 5, 3), (5, 3, 4, 5)),
+    ("abc,cde->abde", (5,), "++-", "+-+", (3, 4, 7), (7, 3, 5)),
+    ("ak,kb->ab", (2,), "+-", "++", (9, 3001), (3001, 7)),          # one long run, split K
+    ("abkl,klij->abij", (4,), "++--", "++--", (3, 5, 3, 3), (3, 3, 2, 3)),
+    # runs of 24: whole 16-byte vectors (binary64 V columns in pairs as well)
+    ("abcd,bcde->ae", (4,), "++--", "-++-", (5, 2, 3, 4), (2, 3, 4, 6)),
+]
+
+
+@pytest.mark.parametrize("case", RUN_CASES)
+@pytest.mark.parametrize("compute", ["f64", "f32"])
+@pytest.mark.parametrize("tile", ["", "128x48", "64x96", "128x128"])
+def test_fused_product_steps_each_run(P, case, compute, tile, monkeypatch):
+    """Run-by-run K-steps: U and V read in place and W written in place whatever the
+    run length, within the product's bound of the oracle (as is the three-step
+    path), with and without charge tables, and run-to-run identical."""
+    sub, orders, cu, cv, du, dv = case
+    if tile:
+        monkeypatch.setenv("SYMT_GEMM_TILE", tile)
+    else:
+        monkeypatch.delenv("SYMT_GEMM_TILE", raising=False)
+    monkeypatch.delenv("SYMT_GEMM_SK", raising=False)
+    rng = np.random.default_rng(seed("runs", sub, orders))
+    g = O.Group(orders)
+    su0 = O.Sym.make(cu, int(rng.integers(g.size)), du, g)
+    sv0 = O.Sym.make(cv, int(rng.integers(g.size)), dv, g)
+    dt = torch.float64 if compute == "f64" else torch.float32
+    for tables in (False, True):
+        su, sv = _with_tables(rng, sub, su0, sv0) if tables else (su0, sv0)
+        say(f"run-stepped {sub} G={orders} {compute} tile={tile or 'default'} tables={tables}")
+        Ru = rng.standard_normal(su.reduced_shape())
+        Rv = rng.standard_normal(sv.reduced_shape())
+        u = _sym_tensor(P, Ru, su, dt)
+        v = _sym_tensor(P, Rv, sv, dt)
+        info = P.plan(sub, u, v, compute)
+        assert info.fused == 1 and info.fused_v == 1
+        w_f = P.output_like(sub, u, v, dtype=dt)
+        w_s = P.output_like(sub, u, v, dtype=dt)
+        P.contract_into(sub, u, v, w_f, compute)
+        P.contract_into(sub, u, v, w_s, compute, steps=True)
+        U64, V64 = H.to_np(u.data).astype(np.float64), H.to_np(v.data).astype(np.float64)
+        ref, _ = O.contract_blocks(sub, U64, su, V64, sv)
+        absref, _ = O.contract_blocks(sub, np.abs(U64), su, np.abs(V64), sv)
+        k = H.contracted_extent(sub, su)
+        fac = 2 * H.gamma(k, H.U64) if compute == "f64" else 1.05 * H.gamma(k, H.U32) + H.gamma(k, H.U64)
+        for w in (w_f, w_s):
+            assert np.all(np.abs(H.to_np(w.data) - ref) <= fac * absref + 1e-300)
+        # the same launch twice gives the same bits
+        w_2 = P.output_like(sub, u, v, dtype=dt)
+        P.contract_into(sub, u, v, w_2, compute)
+        assert torch.equal(w_2.data, w_f.data)
 
 
 # split-bf16 fused product: U's trailing contracted block a multiple of 32
