@@ -83,27 +83,30 @@
  * are linear in the sectors and indices, and each implicit sector belongs to one
  * sector group).  symtensor_contract uses this when compute is F64 or F32, u is
  * stored in the compute type (complex: its complex counterpart), w too, no mode
- * is a subgroup mode, every Q slice is live, u's last v modes are exactly its
- * contracted modes, and a K run (the contracted block in reals) either holds
- * whole K-steps of the product (16 reals, and 16 f64 / 32 f32 on the
- * global-to-LDS tiles) or is all of K.  It then builds the offset tables of U
- * and W in the workspace and runs one product that reads A straight from u's
- * standard form and writes C straight into w's, so U_al and W_al are never
- * materialised (info.fused = 1).  With compute BF16X3 the same holds when u is
- * stored in binary64 or binary32, w in binary64, a K run holds whole 32-deep
- * K-steps and the shape runs on register-staged tiles (not the global-to-LDS
- * ones the product takes from 256 x 512 up): the product then splits u's
- * elements into hi/lo in registers, giving the same bits as the hi/lo planes.
- * V is aligned as usual, unless v is real and
- * in the compute type, its contracted modes are affine in u's K order (each
- * one's stride is the next one's stride times its block size), a K run holds
- * whole K-steps, its last modes are output modes whose contiguous run is a
- * multiple of 16 bytes, and v is 16-byte aligned: then two more tables let
- * the product read B from v's
- * standard form as well (info.fused_v = 1) and no aligned form is written at
- * all.  The workspace holds V_al (used when v is not read in place) and the
- * tables.  Results are identical in value to the three-step path: the product
- * sums in the same order.
+ * is a subgroup mode, every Q slice is live and u's last v modes are exactly its
+ * contracted modes.  It builds the offset tables of U and W in the workspace
+ * and runs one product that reads A straight from u's standard form and writes
+ * C straight into w's, so U_al and W_al are never materialised
+ * (info.fused = 1).  A K run (u's contracted block, in reals) that holds whole
+ * K-steps of the product (16 reals, and 16 f64 / 32 f32 on the global-to-LDS
+ * tiles), or is all of K, is stepped as usual; any other run length is stepped
+ * run by run (the last step of each run masked at its end) on register-staged
+ * tiles, real operands only, where the product would run on them anyway: the
+ * sums are then grouped differently from the three-step path's (within the
+ * same error bound).  With compute BF16X3 the fused product needs u in binary64
+ * or binary32, w in binary64, K runs of whole 32-deep K-steps and a shape on
+ * register-staged tiles (not the global-to-LDS ones the product takes from
+ * 256 x 512 up): it then splits u's elements into hi/lo in registers, giving
+ * the same bits as the hi/lo planes.  V is aligned as usual, unless v is real
+ * and in the compute type and its contracted modes are affine in u's K order
+ * (each one's stride is the next one's stride times its block size), with
+ * whole K-steps per K run and output modes last whose contiguous run is a
+ * multiple of 16 bytes (or K stepped run by run), and v is 16-byte aligned
+ * (or K stepped run by run): then two more tables let the product read B from
+ * v's standard form as well (info.fused_v = 1) and no aligned form is written
+ * at all.  The workspace holds V_al (used when v is not read in place) and the
+ * tables.  Where K-steps are the three-step path's, results are identical in
+ * value to it: the product sums in the same order.
  *
  * Execution and ownership.  Every device buffer (operand data, workspace,
  * aligned buffers) is allocated and owned by the caller.  A context holds only

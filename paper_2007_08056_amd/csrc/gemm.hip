@@ -91,7 +91,8 @@ struct alignas(sizeof(T) * V) VecT {
 // Fused forms (FA / FC): A is read straight from U's standard reduced form,
 // element (q, m, k) at ra[q*M + m] + ca[q*K + k], and C is written straight
 // into W's standard reduced form at rc[q*M + m] + cc[q*N + n] (separable offset
-// tables).  FA needs every BK-aligned run of K to be contiguous in U.
+// tables).  FA needs every K-step to be contiguous in U (BK-aligned steps of K,
+// or steps of each run with krun below).
 // With FA and rb given, B is V's standard form: row k0 + r of a K-step at
 // rb[q*K + k0] + r * ldb, column n at cb[q*N + n] (every K-step inside one affine
 // run of rows, every V-wide load inside one contiguous run of columns).
