@@ -104,7 +104,12 @@
  * multiple of 16 bytes (or K stepped run by run), and v is 16-byte aligned
  * (or K stepped run by run): then two more tables let the product read B from
  * v's standard form as well (info.fused_v = 1) and no aligned form is written
- * at all.  The workspace holds V_al (used when v is not read in place) and the
+ * at all.  Where u does not qualify (its contracted modes are not its last
+ * ones, or its runs suit neither stepping), compute is F64 or F32, the operands
+ * are real, w is in the compute type, no mode is a subgroup mode and every Q
+ * slice is live, u alone is aligned first and the same product reads U_al
+ * through affine tables (info.fused = 0, info.fused_w = 1).  The workspace holds
+ * U_al in that case, then V_al (used when v is not read in place) and the
  * tables.  Where K-steps are the three-step path's, results are identical in
  * value to it: the product sums in the same order.
  *
@@ -218,8 +223,10 @@ typedef struct {
   char w_signs[SYMT_MAX_ORDER + 1];/* derived output sign string (tw order), NUL-terminated */
   int32_t w_charge;                /* derived output charge */
   int32_t fused;                   /* 1 if symtensor_contract will run the fused product */
-  int32_t fused_v;                 /* 1 if that product also reads v in place (no V_al), given
-                                      16-byte aligned u and v data */
+  int32_t fused_v;                 /* 1 if the product also reads v in place (no V_al), given
+                                      16-byte aligned v data */
+  int32_t fused_w;                 /* 1 if the product writes w in place (fused = 1, or u
+                                      aligned first: see FUSED PRODUCT) */
 } symt_plan_info;
 
 typedef struct symt_ctx symt_ctx;

@@ -58,7 +58,7 @@ class SymtPlanInfo(ctypes.Structure):
                 ("flops", c_double), ("bytes_u_al", c_size_t), ("bytes_v_al", c_size_t),
                 ("bytes_w_al", c_size_t), ("workspace_bytes", c_size_t),
                 ("w_signs", c_char * (SYMT_MAX_ORDER + 1)), ("w_charge", c_int32), ("fused", c_int32),
-                ("fused_v", c_int32)]
+                ("fused_v", c_int32), ("fused_w", c_int32)]
 
 
 class SymtError(RuntimeError):

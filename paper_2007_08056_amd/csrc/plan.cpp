@@ -478,11 +478,17 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   p->fused = !force_steps && !p->subgroups && p->nq == p->g.size && (fp_ok || bf_ok || stepped) && trailing_k &&
              p->M > 0 && p->N > 0 && p->Kd > 0 && p->U.elems > 0;
   p->krun = p->fused && stepped ? static_cast<int32_t>(p->nK) : 0;
-  if (p->fused) {
+  // Otherwise, for real operands and W in the compute type, U alone is aligned
+  // and the same product reads U_al through affine tables, V in place where it
+  // can, and writes W in place.
+  p->fused_ua = !p->fused && !force_steps && !p->subgroups && p->nq == p->g.size &&
+                compute != SYMT_COMPUTE_BF16X3 && !p->cplx && (!w || p->W.dtype == want) &&
+                p->M > 0 && p->N > 0 && p->Kd > 0 && p->U.elems > 0;
+  if (p->fused || p->fused_ua) {
     const size_t G = static_cast<size_t>(p->g.size);
     p->bytes_tables = round_up(8 * G * p->M, 256) * 2 + round_up(8 * G * p->gk, 256) +
                       round_up(8 * G * p->gn, 256);
-    p->workspace = round_up(p->ws_v_al, 256) + p->bytes_tables;
+    p->workspace = (p->fused_ua ? round_up(p->ws_u_al, 256) : 0) + round_up(p->ws_v_al, 256) + p->bytes_tables;
   }
   // ---- V read in place as well (see v_in_place_layout); V_al keeps its place in
   // the workspace: a V that is not 16-byte aligned is aligned as before.
@@ -490,13 +496,14 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   const char* vip_env = std::getenv("SYMT_FUSED_V");
   const bool vip_off = vip_env && std::atoi(vip_env) == 0;
   bool chunks = false;
-  if (!vip_off && p->fused && !p->cplx && p->V.dtype == want && v_in_place_layout(*p, &ldb, &chunks)) {
+  if (!vip_off && (p->fused || p->fused_ua) && !p->cplx && p->V.dtype == want &&
+      v_in_place_layout(*p, &ldb, &chunks)) {
     const size_t G = static_cast<size_t>(p->g.size);
     p->fused_b = true;
     p->fused_b_chunks = chunks;
     p->ldb = ldb;
     p->bytes_tables += round_up(8 * G * p->gk, 256) + round_up(8 * G * p->gn, 256);
-    p->workspace = round_up(p->ws_v_al, 256) + p->bytes_tables;
+    p->workspace = (p->fused_ua ? round_up(p->ws_u_al, 256) : 0) + round_up(p->ws_v_al, 256) + p->bytes_tables;
   }
   if (p->charges) {
     p->bytes_charges = 4 * 2 * static_cast<size_t>(p->g.size) * (p->U.n + p->V.n + p->W.n);
@@ -732,6 +739,17 @@ OffsetParams make_offsets(const Plan& p, int operand, bool rows) {
   o.scale = p.cplx ? 2 : 1;
   o.pairs = p.cplx && !rows ? 1 : 0;
   o.count = o.gpow * o.n_inner * (o.pairs ? 2 : 1);
+  return o;
+}
+
+OffsetParams affine_offsets(const Plan& p, int64_t count, int64_t per_q, int64_t step) {
+  OffsetParams o;
+  std::memset(&o, 0, sizeof o);
+  o.g = p.g;
+  o.count = count;
+  o.affine = 1;
+  o.aff_q = per_q;
+  o.aff_i = step;
   return o;
 }
 

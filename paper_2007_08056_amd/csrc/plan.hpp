@@ -104,6 +104,9 @@ struct OffsetParams {
   int64_t stride[kMaxOrder];        // their standard-form strides
   int64_t weight[kMaxOrder];        // standard-form offset of one unit of each mode's sector
   const int32_t* chg;               // device charge tables of the operand, or nullptr (identity)
+  // affine = 1: entry (q, i) = q * aff_q + i * aff_i (the tables of an aligned form)
+  int32_t affine;
+  int64_t aff_q, aff_i;
 };
 
 // Up to six offset tables filled by one launch (entries of table t:
@@ -169,6 +172,9 @@ struct Plan {
   int32_t w_charge = 0;             // derived
   int32_t compute = 0;
   bool fused = false;               // A read from U's standard form, C written to W's
+  // fused product on U_al: U's contracted modes are not its last ones (or its runs
+  // do not suit the product's tiles), so U is aligned first; B and C as when fused
+  bool fused_ua = false;
   // B read from V's standard form too (no V_al): V's rows are affine inside every
   // K-step (stride ldb) and its columns come in runs of whole 16-byte chunks
   // (used when V is 16-byte aligned)
@@ -247,6 +253,9 @@ XformParams make_xform(const Plan& p, int operand, bool to_aligned, int in_elem_
 
 // Row (rows = true) or column offset table of operand 0 (U), 1 (V) or 2 (W).
 OffsetParams make_offsets(const Plan& p, int operand, bool rows);
+// Table of an aligned form held in order: entry (q, i) = q * per_q + i * step,
+// `count` entries per Q.
+OffsetParams affine_offsets(const Plan& p, int64_t count, int64_t per_q, int64_t step);
 
 // Complex storage dtype, and bytes of one real component of an element.
 inline bool is_complex(int32_t dtype) { return dtype == SYMT_C128 || dtype == SYMT_C64; }

@@ -153,6 +153,9 @@ int do_gemm(symt_ctx* ctx, int compute, int64_t batch, int64_t m, int64_t k, int
 int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int32_t* const chg[3]) {
   using symt::round_up;
   const size_t G = static_cast<size_t>(p.g.size);
+  // U aligned first (fused_ua): U_al, then the regions of the fused product
+  void* ual = base;
+  if (p.fused_ua) base += round_up(p.ws_u_al, 256);
   void* val = base;
   int64_t* ra = reinterpret_cast<int64_t*>(base + round_up(p.ws_v_al, 256));
   int64_t* ca = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(ra) + round_up(8 * G * p.M, 256));
@@ -163,9 +166,10 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
   char* part = p.fused_b ? reinterpret_cast<char*>(cb) + round_up(8 * G * p.gn, 256)
                          : reinterpret_cast<char*>(rb);
   // 16-byte loads of A need every row's K run to start 16-byte aligned
-  const int64_t run = (p.cplx ? 2 : 1) * p.nK, vw = p.compute == SYMT_COMPUTE_F64 ? 2 : 4;
-  // (K stepped run by run: a run of whole vectors keeps every step's valid part whole)
-  int vec = aligned16(p.U.data) && (p.compute == SYMT_COMPUTE_BF16X3 || run % vw == 0) ? 2 : 1;
+  // (K stepped run by run: a run of whole vectors keeps every step's valid part whole;
+  // U_al: one run of gk per row, 256-byte aligned)
+  const int64_t run = p.fused_ua ? p.gk : (p.cplx ? 2 : 1) * p.nK, vw = p.compute == SYMT_COMPUTE_F64 ? 2 : 4;
+  int vec = (p.fused_ua || aligned16(p.U.data)) && (p.compute == SYMT_COMPUTE_BF16X3 || run % vw == 0) ? 2 : 1;
   // V in place: its column chunks take 16-byte loads (global-to-LDS tiles, and
   // register tiles whose loads are vectors), so V must be 16-byte aligned
   const bool fb = p.fused_b && (p.krun > 0 || aligned16(p.V.data));
@@ -179,7 +183,10 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
     int64_t total = 0;
     b.n = fb ? 6 : 4;
     for (int t = 0; t < b.n; ++t) {
-      b.t[t] = symt::make_offsets(p, ops[t], t % 2 == 0);
+      if (p.fused_ua && ops[t] == 0)   // U_al: row m at (q M + m) gk, column k at k
+        b.t[t] = t == 0 ? symt::affine_offsets(p, p.M, p.M * p.gk, p.gk) : symt::affine_offsets(p, p.gk, 0, 1);
+      else
+        b.t[t] = symt::make_offsets(p, ops[t], t % 2 == 0);
       b.t[t].chg = chg[ops[t]];
       b.out[t] = outs[t];
       total += b.t[t].count * G;
@@ -188,16 +195,18 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
     return symt::launch_offsets(b, s, &err);
   });
   if (rc_) return ctx_fail(ctx, rc_, err);
+  if (p.fused_ua && (rc_ = do_align(ctx, p, 0, ual, s, true, chg[0]))) return rc_;
   if (!fb && (rc_ = do_align(ctx, p, 1, val, s, true, chg[1]))) return rc_;
   symt::FusedTables f{ra, ca, rc, cc, vec};
-  f.a_bytes = static_cast<int32_t>(elem_bytes(p.U.dtype));
+  f.a_bytes = static_cast<int32_t>(p.fused_ua ? (p.compute == SYMT_COMPUTE_F64 ? 8 : 4) : elem_bytes(p.U.dtype));
   f.krun = p.krun;
   if (fb) {
     f.rb = rb;
     f.cb = cb;
     f.ldb = p.ldb;
   }
-  return do_gemm(ctx, p.compute, p.g.size, p.M, p.gk, p.gn, p.U.data, fb ? p.V.data : val, p.W.data, s, &f,
+  return do_gemm(ctx, p.compute, p.g.size, p.M, p.gk, p.gn, p.fused_ua ? ual : p.U.data, fb ? p.V.data : val,
+                 p.W.data, s, &f,
                  p.bytes_partial ? part : nullptr, p.bytes_partial);
 }
 
@@ -280,6 +289,7 @@ int symtensor_plan(const char* einsum, const symt_group* group, const symt_tenso
   info->w_charge = p.w_charge;
   info->fused = p.fused ? 1 : 0;
   info->fused_v = p.fused_b ? 1 : 0;
+  info->fused_w = (p.fused || p.fused_ua) ? 1 : 0;
   return SYMT_OK;
 }
 
@@ -333,7 +343,7 @@ int symtensor_contract(symt_ctx* ctx, const char* einsum, const symt_group* grou
     for (int op = 0; op < 3; ++op)
       if (!p.chg[op].empty()) chg[op] = dev + off[op];
   }
-  if (p.fused) return do_fused(ctx, p, base, s, chg);
+  if (p.fused || p.fused_ua) return do_fused(ctx, p, base, s, chg);
   void* ual = base;
   void* val = base + symt::round_up(p.ws_u_al, 256);
   void* wal = base + symt::round_up(p.ws_u_al, 256) + symt::round_up(p.ws_v_al, 256);

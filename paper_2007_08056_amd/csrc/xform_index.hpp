@@ -123,6 +123,7 @@ __host__ __device__ inline int64_t group_offset(const OffsetParams& p, int q, in
 // operands double every offset, and their column tables hold (re, im) of each
 // column at 2c, 2c + 1.
 __host__ __device__ inline int64_t table_entry(const OffsetParams& p, int q, int64_t i) {
+  if (p.affine) return q * p.aff_q + i * p.aff_i;
   int comp = 0;
   if (p.pairs) {
     comp = static_cast<int>(i & 1);

@@ -198,8 +198,16 @@ def test_workspace_sizes_per_compute_mode():
     info = _plan("abcd,cdij->abij", 4, u, v, compute=L.COMPUTE["f64"])[1]
     assert info.fused == 1 and info.fused_v == 1
     assert sizes["f64", False] == r(8 * ev) + tables(36, 36) + tables(36, 16) + tables(36, 16)
-    # binary64 operands under f32 compute, and split-bf16 (whole 32-deep K-steps): three steps
-    assert sizes["f32", False] == sizes["f32", True]
+    # binary64 operands under f32 compute (w not given, so taken in binary32): U is
+    # aligned (converted) first, then U_al | V_al | tables of U_al, W
+    info = _plan("abcd,cdij->abij", 4, u, v, compute=L.COMPUTE["f32"])[1]
+    assert info.fused == 0 and info.fused_w == 1 and info.fused_v == 0
+    assert sizes["f32", False] == r(4 * eu) + r(4 * ev) + tables(36, 36) + tables(36, 16)
+    # with a binary64 w the product cannot write it: three steps
+    w64 = _desc("++--", 0, (3, 3, 2, 2))
+    info = _plan("abcd,cdij->abij", 4, u, v, w64, compute=L.COMPUTE["f32"])[1]
+    assert info.fused == 0 and info.fused_w == 0 and info.workspace_bytes == sizes["f32", True]
+    # split-bf16 needs whole 32-deep K-steps: three steps
     assert sizes["bf16x3", False] == sizes["bf16x3", True]
 
 

@@ -504,6 +504,62 @@ def test_fused_product_steps_each_run(P, case, compute, tile, monkeypatch):
         assert torch.equal(w_2.data, w_f.data)
 
 
+# U's contracted modes first (the paper's CC2 / CC3 layouts), or runs that do not
+# suit a global-to-LDS tile: U is aligned first, the product reads U_al through
+# affine tables, V in place where it can, and writes W in place.
+UA_CASES = [
+    ("klab,klij->abij", (4,), "--++", "++--", (4, 8, 3, 5), (4, 8, 2, 6)),
+    ("opij,opkm->ijmk", (8,), "--++", "++--", (4, 4, 3, 5), (4, 4, 2, 3)),
+    ("opmn,opij->ijmn", (2, 3), "+-+-", "-+-+", (4, 8, 3, 2), (4, 8, 5, 3)),
+    ("kab,kij->abij", (3,), "-++", "+--", (16, 7, 5), (16, 3, 4)),
+    ("abkl,klij->abij", (4,), "++--", "++--", (3, 5, 4, 6), (4, 6, 2, 4)),     # runs of 24
+]
+
+
+@pytest.mark.parametrize("case", UA_CASES)
+@pytest.mark.parametrize("compute", ["f64", "f32"])
+@pytest.mark.parametrize("tile,sk", [("", ""), ("d96x96s2", "0"), ("d96x96s2", "1"), ("d128x64s3", "1"),
+                                     ("128x48", "0"), ("64x96", "0")])
+def test_fused_product_on_aligned_u(P, case, compute, tile, sk, monkeypatch):
+    """U aligned first, then the fused product (V in place where its layout allows,
+    W in place): bit-identical to the three-step path on the same tile and within
+    the product's bound of the oracle, with and without charge tables."""
+    sub, orders, cu, cv, du, dv = case
+    for name, val in (("SYMT_GEMM_TILE", tile), ("SYMT_GEMM_SK", sk)):
+        if val:
+            monkeypatch.setenv(name, val)
+        else:
+            monkeypatch.delenv(name, raising=False)
+    rng = np.random.default_rng(seed("aligned-u", sub, orders))
+    g = O.Group(orders)
+    su0 = O.Sym.make(cu, int(rng.integers(g.size)), du, g)
+    sv0 = O.Sym.make(cv, int(rng.integers(g.size)), dv, g)
+    dt = torch.float64 if compute == "f64" else torch.float32
+    for tables in (False, True):
+        su, sv = _with_tables(rng, sub, su0, sv0) if tables else (su0, sv0)
+        say(f"aligned-u {sub} G={orders} {compute} tile={tile or 'default'} sk={sk} tables={tables}")
+        Ru = rng.standard_normal(su.reduced_shape())
+        Rv = rng.standard_normal(sv.reduced_shape())
+        u = _sym_tensor(P, Ru, su, dt)
+        v = _sym_tensor(P, Rv, sv, dt)
+        info = P.plan(sub, u, v, compute)
+        if info.fused:                 # runs of 24 on register tiles: stepped run by run instead
+            assert sub.startswith("abkl") and info.fused_w == 1
+            continue
+        assert info.fused_w == 1
+        w_f = P.output_like(sub, u, v, dtype=dt)
+        w_s = P.output_like(sub, u, v, dtype=dt)
+        P.contract_into(sub, u, v, w_f, compute)
+        P.contract_into(sub, u, v, w_s, compute, steps=True)
+        assert torch.equal(w_f.data, w_s.data)
+        U64, V64 = H.to_np(u.data).astype(np.float64), H.to_np(v.data).astype(np.float64)
+        ref, _ = O.contract_blocks(sub, U64, su, V64, sv)
+        absref, _ = O.contract_blocks(sub, np.abs(U64), su, np.abs(V64), sv)
+        k = H.contracted_extent(sub, su)
+        fac = 2 * H.gamma(k, H.U64) if compute == "f64" else 1.05 * H.gamma(k, H.U32) + H.gamma(k, H.U64)
+        assert np.all(np.abs(H.to_np(w_f.data) - ref) <= fac * absref + 1e-300)
+
+
 # split-bf16 fused product: U's trailing contracted block a multiple of 32
 BF_FUSED_CASES = [
     ("abkl,klij->abij", (4,), "++--", "++--", (3, 5, 4, 8), (4, 8, 2, 6)),
