@@ -186,7 +186,7 @@ struct Plan {
   int32_t krun = 0;
   size_t bytes_u_al = 0, bytes_v_al = 0, bytes_w_al = 0, workspace = 0;
   size_t ws_u_al = 0, ws_v_al = 0, ws_w_al = 0;   // their regions in the contraction's workspace
-  size_t bytes_tables = 0;          // fused: the four offset tables (six with fused_b)
+  size_t bytes_tables = 0;          // fused (or fused_ua): four offset tables, six with fused_b
   size_t bytes_partial = 0;         // stream-K pieces of the product (0: data-parallel tiles)
   // Charge tables (label -> charge) of U, V, W, n x |G| each; empty = identity.
   // On the device each operand's block is [mode][label -> charge | charge -> label][|G|].
