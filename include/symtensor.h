@@ -94,7 +94,8 @@
  * tiles, real operands only, where the product would run on them anyway: the
  * sums are then grouped differently from the three-step path's (within the
  * same error bound).  With compute BF16X3 the fused product needs u in binary64
- * or binary32, w in binary64, K runs of whole 32-deep K-steps and a shape on
+ * or binary32, w in binary64 or binary32 (the binary64 sums rounded on the
+ * store, as the W transform rounds them), K runs of whole 32-deep K-steps and a shape on
  * register-staged tiles (not the global-to-LDS ones the product takes from
  * 256 x 512 up): it then splits u's elements into hi/lo in registers, giving
  * the same bits as the hi/lo planes.  V is aligned as usual, unless v is real
@@ -108,7 +109,9 @@
  * ones, or its runs suit neither stepping), compute is F64 or F32, the operands
  * are real, w is in the compute type, no mode is a subgroup mode and every Q
  * slice is live, u alone is aligned first and the same product reads U_al
- * through affine tables (info.fused = 0, info.fused_w = 1).  The workspace holds
+ * through affine tables (info.fused = 0, info.fused_w = 1); with BF16X3, u and
+ * v go to their hi/lo planes and only w is written in place, where w (binary64
+ * or binary32) takes its product columns in contiguous runs of 16 or more.  The workspace holds
  * U_al in that case, then V_al (used when v is not read in place) and the
  * tables.  Where K-steps are the three-step path's, results are identical in
  * value to it: the product sums in the same order.

@@ -662,14 +662,19 @@ __global__ __launch_bounds__(64 * WM * WN) void k_sk_fixup(
 // way the transforms split it; C goes to W's standard form at
 // rc[q*M + m] + cc[q*N + n].
 // ---------------------------------------------------------------------------
-template <int BM, int BN, int BK, int WM, int WN, typename TA = uint16_t, int VA = 8>
+// FCW: A and B from planes, C to W's standard form through rc / cc.  TC: the
+// type C is stored in (binary64 sums rounded to binary32 for a binary32 W, as
+// the W transform would round them).
+template <int BM, int BN, int BK, int WM, int WN, typename TA = uint16_t, int VA = 8, bool FCW = false,
+          typename TC = double>
 __global__ __launch_bounds__(64 * WM * WN, (WM * WN == 4 && BK == 32) ? 2 : 1) void k_gemm_bf16x3(
     const uint16_t* __restrict__ Ahi, const uint16_t* __restrict__ Alo,
-    const uint16_t* __restrict__ Bhi, const uint16_t* __restrict__ Blo, double* __restrict__ C,
+    const uint16_t* __restrict__ Bhi, const uint16_t* __restrict__ Blo, TC* __restrict__ C,
     int M, int N, int K, int tiles_m, int tiles_n, int64_t ntiles, const TA* __restrict__ U = nullptr,
     const int64_t* __restrict__ ra = nullptr, const int64_t* __restrict__ ca = nullptr,
     const int64_t* __restrict__ rc = nullptr, const int64_t* __restrict__ cc = nullptr) {
   constexpr bool FUSED = !std::is_same<TA, uint16_t>::value;
+  constexpr bool FC = FUSED || FCW;
   constexpr int NT = 64 * WM * WN;
   constexpr int V = 8;                // bf16 per 16-byte access
   constexpr int LDK = BK + 8;         // padded row (keeps 16-byte alignment)
@@ -690,7 +695,8 @@ __global__ __launch_bounds__(64 * WM * WN, (WM * WN == 4 && BK == 32) ? 2 : 1) v
   tile_coords(tile, tiles_m, tiles_n, q, tm, tn);
   const int64_t offA = q * static_cast<int64_t>(M) * K;
   const int64_t offB = q * static_cast<int64_t>(N) * K;
-  double* Cq = C + (FUSED ? 0 : q * static_cast<int64_t>(M) * N);
+  static_assert(FC || std::is_same<TC, double>::value, "aligned W is binary64");
+  TC* Cq = C + (FC ? 0 : q * static_cast<int64_t>(M) * N);
   const int m0 = tm * BM, n0 = tn * BN;
 
   const int tid = threadIdx.x;
@@ -833,15 +839,16 @@ __global__ __launch_bounds__(64 * WM * WN, (WM * WN == 4 && BK == 32) ? 2 : 1) v
 #pragma unroll
   for (int j = 0; j < TN; ++j) {
     const int col = n0 + wn0 + j * 16 + (lane & 15);
-    const int64_t ccol = (FUSED && col < N) ? cc[q * N + col] : col;
+    const int64_t ccol = (FC && col < N) ? cc[q * N + col] : col;
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm0 + i * 16 + 4 * (lane >> 4) + r;
         if (row < M && col < N) {
-          const int64_t crow = FUSED ? rc[q * M + row] : static_cast<int64_t>(row) * N;
-          Cq[crow + ccol] = static_cast<double>(acc_hh[i][j][r]) + static_cast<double>(acc_x[i][j][r]);
+          const int64_t crow = FC ? rc[q * M + row] : static_cast<int64_t>(row) * N;
+          Cq[crow + ccol] =
+              static_cast<TC>(static_cast<double>(acc_hh[i][j][r]) + static_cast<double>(acc_x[i][j][r]));
         }
       }
   }
@@ -915,11 +922,13 @@ hipError_t launch_fp(int vec, int64_t batch, int M, int N, int K, const void* A,
 // products, which a bf16 K-step (48 MFMAs per wave) is too short to hide
 // otherwise.  K must be a multiple of 32; rows past M or N are clamped (their
 // results are never stored).
-template <int BM, int BN, int WM, int WN, int S>
+// FC: C goes to W's standard form at rc[q*M + m] + cc[q*N + n], stored as TC.
+template <int BM, int BN, int WM, int WN, int S, bool FC = false, typename TC = double>
 __global__ __launch_bounds__(64 * WM * WN, 1) void k_gemm_bf16x3_dma(
     const uint16_t* __restrict__ Ahi, const uint16_t* __restrict__ Alo,
-    const uint16_t* __restrict__ Bhi, const uint16_t* __restrict__ Blo, double* __restrict__ C,
-    int M, int N, int K, int tiles_m, int tiles_n, int64_t ntiles) {
+    const uint16_t* __restrict__ Bhi, const uint16_t* __restrict__ Blo, TC* __restrict__ C,
+    int M, int N, int K, int tiles_m, int tiles_n, int64_t ntiles,
+    const int64_t* __restrict__ rc = nullptr, const int64_t* __restrict__ cc = nullptr) {
   constexpr int NW = WM * WN;
   constexpr int NT = 64 * NW;
   constexpr int BK = 32;
@@ -1020,47 +1029,86 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void k_gemm_bf16x3_dma(
     }
   }
 
-  double* Cq = C + q * static_cast<int64_t>(M) * N;
+  static_assert(FC || std::is_same<TC, double>::value, "aligned W is binary64");
+  TC* Cq = C + (FC ? 0 : q * static_cast<int64_t>(M) * N);
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int j = 0; j < TN; ++j) {
+    const int col = n0 + wn0 + j * 16 + (lane & 15);
+    const int64_t ccol = (FC && col < N) ? cc[q * N + col] : col;
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int col = n0 + wn0 + j * 16 + (lane & 15);
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm0 + i * 16 + 4 * (lane >> 4) + r;
-        if (row < M && col < N)
-          Cq[static_cast<int64_t>(row) * N + col] =
-              static_cast<double>(acc_hh[i][j][r]) + static_cast<double>(acc_x[i][j][r]);
+        if (row < M && col < N) {
+          const int64_t crow = FC ? rc[q * M + row] : static_cast<int64_t>(row) * N;
+          Cq[crow + ccol] =
+              static_cast<TC>(static_cast<double>(acc_hh[i][j][r]) + static_cast<double>(acc_x[i][j][r]));
+        }
       }
-    }
+  }
 }
 
 // pa / pb: elements from each hi plane to its lo plane.
+// rc / cc: W's offset tables (C written in place), or nullptr (C row-major).
 template <int BM, int BN, int WM, int WN, int S>
 hipError_t launch_bf16x3_dma(int64_t batch, int M, int N, int K, const void* A, const void* B, void* C,
-                             hipStream_t s, int64_t pa, int64_t pb) {
+                             hipStream_t s, int64_t pa, int64_t pb, const int64_t* rc = nullptr,
+                             const int64_t* cc = nullptr, int c_bytes = 8) {
   const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
   const int64_t ntiles = batch * tiles_m * tiles_n;
   const uint16_t* a = static_cast<const uint16_t*>(A);
   const uint16_t* b = static_cast<const uint16_t*>(B);
-  hipLaunchKernelGGL((k_gemm_bf16x3_dma<BM, BN, WM, WN, S>), dim3(static_cast<unsigned>(ntiles)),
-                     dim3(64 * WM * WN), 0, s, a, a + pa, b, b + pb, static_cast<double*>(C), M, N, K,
-                     tiles_m, tiles_n, ntiles);
+  if (rc && c_bytes == 4)
+    hipLaunchKernelGGL((k_gemm_bf16x3_dma<BM, BN, WM, WN, S, true, float>), dim3(static_cast<unsigned>(ntiles)),
+                       dim3(64 * WM * WN), 0, s, a, a + pa, b, b + pb, static_cast<float*>(C), M, N, K,
+                       tiles_m, tiles_n, ntiles, rc, cc);
+  else if (rc)
+    hipLaunchKernelGGL((k_gemm_bf16x3_dma<BM, BN, WM, WN, S, true>), dim3(static_cast<unsigned>(ntiles)),
+                       dim3(64 * WM * WN), 0, s, a, a + pa, b, b + pb, static_cast<double*>(C), M, N, K,
+                       tiles_m, tiles_n, ntiles, rc, cc);
+  else
+    hipLaunchKernelGGL((k_gemm_bf16x3_dma<BM, BN, WM, WN, S>), dim3(static_cast<unsigned>(ntiles)),
+                       dim3(64 * WM * WN), 0, s, a, a + pa, b, b + pb, static_cast<double*>(C), M, N, K,
+                       tiles_m, tiles_n, ntiles);
   return hipGetLastError();
 }
 
 template <int BM, int BN, int BK, int WM, int WN>
 hipError_t launch_bf16x3(int64_t batch, int M, int N, int K, const void* A, const void* B, void* C,
-                         hipStream_t s, int64_t pa, int64_t pb) {
+                         hipStream_t s, int64_t pa, int64_t pb, const int64_t* rc = nullptr,
+                         const int64_t* cc = nullptr, int c_bytes = 8) {
   const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
   const int64_t ntiles = batch * tiles_m * tiles_n;
   const dim3 grid(static_cast<unsigned>(ntiles)), block(64 * WM * WN);
   const uint16_t* a = static_cast<const uint16_t*>(A);
   const uint16_t* b = static_cast<const uint16_t*>(B);
-  hipLaunchKernelGGL((k_gemm_bf16x3<BM, BN, BK, WM, WN>), grid, block, 0, s, a, a + pa, b, b + pb,
-                     static_cast<double*>(C), M, N, K, tiles_m, tiles_n, ntiles);
+  if (rc && c_bytes == 4)
+    hipLaunchKernelGGL((k_gemm_bf16x3<BM, BN, BK, WM, WN, uint16_t, 8, true, float>), grid, block, 0, s, a, a + pa,
+                       b, b + pb, static_cast<float*>(C), M, N, K, tiles_m, tiles_n, ntiles, nullptr, nullptr,
+                       nullptr, rc, cc);
+  else if (rc)
+    hipLaunchKernelGGL((k_gemm_bf16x3<BM, BN, BK, WM, WN, uint16_t, 8, true>), grid, block, 0, s, a, a + pa, b,
+                       b + pb, static_cast<double*>(C), M, N, K, tiles_m, tiles_n, ntiles, nullptr, nullptr,
+                       nullptr, rc, cc);
+  else
+    hipLaunchKernelGGL((k_gemm_bf16x3<BM, BN, BK, WM, WN>), grid, block, 0, s, a, a + pa, b, b + pb,
+                       static_cast<double*>(C), M, N, K, tiles_m, tiles_n, ntiles);
   return hipGetLastError();
+}
+
+template <int BM, int BN, int BK, int WM, int WN, typename TA, int VA>
+void launch_bf16x3_fused_tc(dim3 grid, dim3 block, hipStream_t s, const TA* u, const uint16_t* b, int64_t pb,
+                            void* C, int M, int N, int K, int tiles_m, int tiles_n, int64_t ntiles,
+                            const FusedTables* f) {
+  if (f->c_bytes == 4)
+    hipLaunchKernelGGL((k_gemm_bf16x3<BM, BN, BK, WM, WN, TA, VA, false, float>), grid, block, 0, s, nullptr,
+                       nullptr, b, b + pb, static_cast<float*>(C), M, N, K, tiles_m, tiles_n, ntiles, u, f->ra,
+                       f->ca, f->rc, f->cc);
+  else
+    hipLaunchKernelGGL((k_gemm_bf16x3<BM, BN, BK, WM, WN, TA, VA>), grid, block, 0, s, nullptr, nullptr, b,
+                       b + pb, static_cast<double*>(C), M, N, K, tiles_m, tiles_n, ntiles, u, f->ra, f->ca,
+                       f->rc, f->cc);
 }
 
 // Fused split-bf16 product: A from U's standard form (binary64 or binary32,
@@ -1072,23 +1120,22 @@ hipError_t launch_bf16x3_fused(int64_t batch, int M, int N, int K, const void* U
   const int64_t ntiles = batch * tiles_m * tiles_n;
   const dim3 grid(static_cast<unsigned>(ntiles)), block(64 * WM * WN);
   const uint16_t* b = static_cast<const uint16_t*>(B);
-  double* c = static_cast<double*>(C);
   if (f->a_bytes == 8) {
     const double* u = static_cast<const double*>(U);
     if (f->vec > 1)
-      hipLaunchKernelGGL((k_gemm_bf16x3<BM, BN, BK, WM, WN, double, 2>), grid, block, 0, s, nullptr, nullptr, b,
-                         b + pb, c, M, N, K, tiles_m, tiles_n, ntiles, u, f->ra, f->ca, f->rc, f->cc);
+      launch_bf16x3_fused_tc<BM, BN, BK, WM, WN, double, 2>(grid, block, s, u, b, pb, C, M, N, K, tiles_m, tiles_n,
+                                                            ntiles, f);
     else
-      hipLaunchKernelGGL((k_gemm_bf16x3<BM, BN, BK, WM, WN, double, 1>), grid, block, 0, s, nullptr, nullptr, b,
-                         b + pb, c, M, N, K, tiles_m, tiles_n, ntiles, u, f->ra, f->ca, f->rc, f->cc);
+      launch_bf16x3_fused_tc<BM, BN, BK, WM, WN, double, 1>(grid, block, s, u, b, pb, C, M, N, K, tiles_m, tiles_n,
+                                                            ntiles, f);
   } else {
     const float* u = static_cast<const float*>(U);
     if (f->vec > 1)
-      hipLaunchKernelGGL((k_gemm_bf16x3<BM, BN, BK, WM, WN, float, 4>), grid, block, 0, s, nullptr, nullptr, b,
-                         b + pb, c, M, N, K, tiles_m, tiles_n, ntiles, u, f->ra, f->ca, f->rc, f->cc);
+      launch_bf16x3_fused_tc<BM, BN, BK, WM, WN, float, 4>(grid, block, s, u, b, pb, C, M, N, K, tiles_m, tiles_n,
+                                                           ntiles, f);
     else
-      hipLaunchKernelGGL((k_gemm_bf16x3<BM, BN, BK, WM, WN, float, 1>), grid, block, 0, s, nullptr, nullptr, b,
-                         b + pb, c, M, N, K, tiles_m, tiles_n, ntiles, u, f->ra, f->ca, f->rc, f->cc);
+      launch_bf16x3_fused_tc<BM, BN, BK, WM, WN, float, 1>(grid, block, s, u, b, pb, C, M, N, K, tiles_m, tiles_n,
+                                                           ntiles, f);
   }
   return hipGetLastError();
 }
@@ -1244,7 +1291,10 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
     const bool dma_ok = K % 32 == 0;
     const int64_t pa = plane_a > 0 ? plane_a : batch * static_cast<int64_t>(M) * K;
     const int64_t pb = plane_b > 0 ? plane_b : batch * static_cast<int64_t>(N) * K;
-    if (fused) {
+    const int64_t* wrc = fused ? fused->rc : nullptr;   // C in place (planes for A and B)
+    const int64_t* wcc = fused ? fused->cc : nullptr;
+    const int wcb = fused ? fused->c_bytes : 8;           // W's element size
+    if (fused && fused->ra) {
       // register tiles only (the planner fuses where the launcher would pick one)
       if (!bf16x3_register_tile(M, N, K) || K % 32 != 0) {
         if (err) *err = "fused split-bf16 product needs a register tile and whole 32-deep K-steps";
@@ -1255,25 +1305,25 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
           : t == 2 ? launch_bf16x3_fused<128, 256, 32, 2, 4>(batch, M, N, K, A, B, C, stream, pb, fused)
           : t == 3 ? launch_bf16x3_fused<128, 96, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pb, fused)
                    : launch_bf16x3_fused<128, 128, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pb, fused);
-    } else if (f == "bd256x128s3" && dma_ok) e = launch_bf16x3_dma<256, 128, 4, 2, 3>(batch, M, N, K, A, B, C, stream, pa, pb);
-    else if (f == "bd128x256s3" && dma_ok) e = launch_bf16x3_dma<128, 256, 2, 4, 3>(batch, M, N, K, A, B, C, stream, pa, pb);
-    else if (f == "b128x128k64") e = launch_bf16x3<128, 128, 64, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb);
-    else if (f == "b128x128k32") e = launch_bf16x3<128, 128, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb);
-    else if (f == "b256x128k32") e = launch_bf16x3<256, 128, 32, 4, 2>(batch, M, N, K, A, B, C, stream, pa, pb);
-    else if (f == "b128x256k32") e = launch_bf16x3<128, 256, 32, 2, 4>(batch, M, N, K, A, B, C, stream, pa, pb);
-    else if (f == "b128x64k32") e = launch_bf16x3<128, 64, 32, 4, 1>(batch, M, N, K, A, B, C, stream, pa, pb);
-    else if (f == "b128x96k32") e = launch_bf16x3<128, 96, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb);
-    else if (f == "b64x64k32") e = launch_bf16x3<64, 64, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb);
+    } else if (f == "bd256x128s3" && dma_ok) e = launch_bf16x3_dma<256, 128, 4, 2, 3>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
+    else if (f == "bd128x256s3" && dma_ok) e = launch_bf16x3_dma<128, 256, 2, 4, 3>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
+    else if (f == "b128x128k64") e = launch_bf16x3<128, 128, 64, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
+    else if (f == "b128x128k32") e = launch_bf16x3<128, 128, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
+    else if (f == "b256x128k32") e = launch_bf16x3<256, 128, 32, 4, 2>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
+    else if (f == "b128x256k32") e = launch_bf16x3<128, 256, 32, 2, 4>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
+    else if (f == "b128x64k32") e = launch_bf16x3<128, 64, 32, 4, 1>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
+    else if (f == "b128x96k32") e = launch_bf16x3<128, 96, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
+    else if (f == "b64x64k32") e = launch_bf16x3<64, 64, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
     else if (dma_ok && f.empty() && M >= 256 && N >= 512)
-      e = launch_bf16x3_dma<128, 256, 2, 4, 3>(batch, M, N, K, A, B, C, stream, pa, pb);
+      e = launch_bf16x3_dma<128, 256, 2, 4, 3>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
     else if (N <= 64)
-      e = launch_bf16x3<128, 64, 32, 4, 1>(batch, M, N, K, A, B, C, stream, pa, pb);
+      e = launch_bf16x3<128, 64, 32, 4, 1>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
     else if (N >= 1024 && M >= 1024)
-      e = launch_bf16x3<128, 256, 32, 2, 4>(batch, M, N, K, A, B, C, stream, pa, pb);
+      e = launch_bf16x3<128, 256, 32, 2, 4>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
     else if ((N + 95) / 96 * 96 - N < (N + 127) / 128 * 128 - N)   // fewer padded columns
-      e = launch_bf16x3<128, 96, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb);
+      e = launch_bf16x3<128, 96, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
     else
-      e = launch_bf16x3<128, 128, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb);
+      e = launch_bf16x3<128, 128, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
   } else {
     const bool f64 = compute == SYMT_COMPUTE_F64;
     const int vw = f64 ? 2 : 4;

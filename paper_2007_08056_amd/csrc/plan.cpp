@@ -463,9 +463,11 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   const bool fp_ok = compute != SYMT_COMPUTE_BF16X3 && p->U.dtype == want && (!w || p->W.dtype == want) &&
                      whole_steps;
   // split-bf16: the register-staged tiles read U (binary64 or binary32) along
-  // 32-deep K-steps and split it into hi/lo in registers; W takes binary64
+  // 32-deep K-steps and split it into hi/lo in registers; W takes the binary64
+  // sums (rounded to binary32 for a binary32 W)
   const bool bf_ok = compute == SYMT_COMPUTE_BF16X3 && !p->cplx &&
-                     (p->U.dtype == SYMT_F64 || p->U.dtype == SYMT_F32) && (!w || p->W.dtype == SYMT_F64) &&
+                     (p->U.dtype == SYMT_F64 || p->U.dtype == SYMT_F32) &&
+                     (!w || p->W.dtype == SYMT_F64 || p->W.dtype == SYMT_F32) &&
                      run % 32 == 0 && bf16x3_register_tile(p->M, p->gn, p->gk);
   // K runs that do not hold whole K-steps: where the product runs on register
   // tiles anyway, they step each run on their own (masking its last step), so A
@@ -481,9 +483,23 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   // Otherwise, for real operands and W in the compute type, U alone is aligned
   // and the same product reads U_al through affine tables, V in place where it
   // can, and writes W in place.
-  p->fused_ua = !p->fused && !force_steps && !p->subgroups && p->nq == p->g.size &&
-                compute != SYMT_COMPUTE_BF16X3 && !p->cplx && (!w || p->W.dtype == want) &&
-                p->M > 0 && p->N > 0 && p->Kd > 0 && p->U.elems > 0;
+  // (split-bf16: U and V go to hi/lo planes as in three steps, and the product
+  // writes its binary64 sums straight into W)
+  const int w_want = compute == SYMT_COMPUTE_F32 ? SYMT_F32 : SYMT_F64;
+  // W's aligned columns: the contiguous run of its output modes from V (the
+  // split-bf16 epilogue only pays off where its column stores coalesce; with
+  // W's columns transposed, the W transform's LDS-tiled transpose is cheaper)
+  int64_t w_run = 1;
+  {
+    int64_t st[kMaxOrder];
+    int64_t a = 1;
+    for (int m = p->W.n - 1; m >= 0; --m) { st[m] = a; a *= p->W.dims[m]; }
+    for (int i = p->t - 1; i >= 0 && st[p->posJ_w[i]] == w_run; --i) w_run *= p->W.dims[p->posJ_w[i]];
+  }
+  p->fused_ua = !p->fused && !force_steps && !p->subgroups && p->nq == p->g.size && !p->cplx &&
+                (!w || p->W.dtype == w_want || (compute == SYMT_COMPUTE_BF16X3 && p->W.dtype == SYMT_F32)) &&
+                p->M > 0 && p->N > 0 && p->Kd > 0 && p->U.elems > 0 &&
+                (compute != SYMT_COMPUTE_BF16X3 || w_run >= 16);
   if (p->fused || p->fused_ua) {
     const size_t G = static_cast<size_t>(p->g.size);
     p->bytes_tables = round_up(8 * G * p->M, 256) * 2 + round_up(8 * G * p->gk, 256) +

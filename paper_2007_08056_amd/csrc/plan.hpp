@@ -137,6 +137,7 @@ struct FusedTables {
   int64_t ldb = 0;
   int32_t a_bytes = 8;              // split-bf16 product: U's element size (8 binary64, 4 binary32)
   int32_t krun = 0;                 // > 0: K stepped run by run (register tiles)
+  int32_t c_bytes = 8;              // split-bf16 products: W's element size (8 binary64, 4 binary32)
 };
 
 struct OperandDesc {

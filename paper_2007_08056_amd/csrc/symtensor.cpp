@@ -198,8 +198,11 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
   if (p.fused_ua && (rc_ = do_align(ctx, p, 0, ual, s, true, chg[0]))) return rc_;
   if (!fb && (rc_ = do_align(ctx, p, 1, val, s, true, chg[1]))) return rc_;
   symt::FusedTables f{ra, ca, rc, cc, vec};
+  // split-bf16 on aligned U: A and B come from the hi/lo planes, only W's tables apply
+  if (p.fused_ua && p.compute == SYMT_COMPUTE_BF16X3) f.ra = f.ca = nullptr;
   f.a_bytes = static_cast<int32_t>(p.fused_ua ? (p.compute == SYMT_COMPUTE_F64 ? 8 : 4) : elem_bytes(p.U.dtype));
   f.krun = p.krun;
+  f.c_bytes = static_cast<int32_t>(elem_bytes(p.W.dtype));
   if (fb) {
     f.rb = rb;
     f.cb = cb;

@@ -207,8 +207,16 @@ def test_workspace_sizes_per_compute_mode():
     w64 = _desc("++--", 0, (3, 3, 2, 2))
     info = _plan("abcd,cdij->abij", 4, u, v, w64, compute=L.COMPUTE["f32"])[1]
     assert info.fused == 0 and info.fused_w == 0 and info.workspace_bytes == sizes["f32", True]
-    # split-bf16 needs whole 32-deep K-steps: three steps
+    # split-bf16 (a contracted block of 9 is not whole 32-deep steps) writes W in place
+    # only where W's columns come in runs of >= 16 (here 2 x 2): three steps
+    info = _plan("abcd,cdij->abij", 4, u, v, compute=L.COMPUTE["bf16x3"])[1]
+    assert info.fused == 0 and info.fused_w == 0
     assert sizes["bf16x3", False] == sizes["bf16x3", True]
+    # ... with runs of 4 x 4: U and V to hi/lo planes, W in place (U planes | V planes | tables)
+    v4 = _desc("++--", 0, (3, 3, 4, 4))
+    info = _plan("abcd,cdij->abij", 4, u, v4, compute=L.COMPUTE["bf16x3"])[1]
+    assert info.fused == 0 and info.fused_w == 1
+    assert info.workspace_bytes == r(4 * eu) + r(4 * 4 ** 3 * 144) + tables(36, 36) + tables(36, 64)
 
 
 def test_status_strings():
@@ -452,13 +460,15 @@ def test_split_bf16_fused_plans(monkeypatch):
         r(8 * 8 * 288)
     u32, v32 = _desc("++--", 0, (24, 24, 24, 24), L.SYMT_F32), _desc("++--", 0, (24, 24, 6, 6), L.SYMT_F32)
     assert _plan("abcd,cdij->abij", 8, u32, v32, compute=bf)[1].fused == 1
-    # a binary32 output, a contracted block of 16, a global-to-LDS shape (Z_16 ladder)
+    # a binary32 output (the binary64 sums rounded on the store), a contracted block of
+    # 16, a global-to-LDS shape (Z_16 ladder)
     w32 = _desc("++--", 0, (24, 24, 6, 6), L.SYMT_F32)
-    assert _plan("abcd,cdij->abij", 8, _desc("++--", 0, (24, 24, 24, 24)), v, w32, compute=bf)[1].fused == 0
+    assert _plan("abcd,cdij->abij", 8, _desc("++--", 0, (24, 24, 24, 24)), v, w32, compute=bf)[1].fused == 1
     assert _plan("abcd,cdij->abij", 8, _desc("++--", 0, (24, 24, 4, 4)),
                  _desc("++--", 0, (4, 4, 6, 6)), compute=bf)[1].fused == 0
-    assert _plan("abcd,cdij->abij", 16, _desc("++--", 0, (32, 32, 32, 32)),
-                 _desc("++--", 0, (32, 32, 8, 8)), compute=bf)[1].fused == 0
+    z16 = _plan("abcd,cdij->abij", 16, _desc("++--", 0, (32, 32, 32, 32)), _desc("++--", 0, (32, 32, 8, 8)),
+                compute=bf)[1]
+    assert z16.fused == 0 and z16.fused_w == 1      # planes for U and V, W written in place
     monkeypatch.setenv("SYMT_GEMM_TILE", "b128x128k32")
     assert _plan("abcd,cdij->abij", 16, _desc("++--", 0, (32, 32, 32, 32)),
                  _desc("++--", 0, (32, 32, 8, 8)), compute=bf)[1].fused == 1

@@ -513,17 +513,36 @@ UA_CASES = [
     ("opmn,opij->ijmn", (2, 3), "+-+-", "-+-+", (4, 8, 3, 2), (4, 8, 5, 3)),
     ("kab,kij->abij", (3,), "-++", "+--", (16, 7, 5), (16, 3, 4)),
     ("abkl,klij->abij", (4,), "++--", "++--", (3, 5, 4, 6), (4, 6, 2, 4)),     # runs of 24
+    ("klab,klij->abij", (2,), "--++", "++--", (4, 8, 16, 16), (4, 8, 16, 16)),  # 512 x 64 x 512
 ]
 
 
+def _w_col_run(sub, du, dv):
+    """Contiguous run of W's aligned columns (V's output modes, in V's order) in W."""
+    tu, rest = sub.split(",")
+    tv, tw = rest.split("->")
+    dims = {m: d for m, d in list(zip(tu, du)) + list(zip(tv, dv))}
+    stride, acc = {}, 1
+    for m in reversed(tw):
+        stride[m] = acc
+        acc *= dims[m]
+    run = 1
+    for m in reversed([m for m in tv if m in tw]):
+        if stride[m] != run:
+            break
+        run *= dims[m]
+    return run
+
+
 @pytest.mark.parametrize("case", UA_CASES)
-@pytest.mark.parametrize("compute", ["f64", "f32"])
+@pytest.mark.parametrize("compute", ["f64", "f32", "bf16x3"])
 @pytest.mark.parametrize("tile,sk", [("", ""), ("d96x96s2", "0"), ("d96x96s2", "1"), ("d128x64s3", "1"),
                                      ("128x48", "0"), ("64x96", "0")])
 def test_fused_product_on_aligned_u(P, case, compute, tile, sk, monkeypatch):
     """U aligned first, then the fused product (V in place where its layout allows,
-    W in place): bit-identical to the three-step path on the same tile and within
-    the product's bound of the oracle, with and without charge tables."""
+    W in place; split-bf16: U and V on hi/lo planes, W in place, register and
+    global-to-LDS tiles): bit-identical to the three-step path on the same tile
+    and within the product's bound of the oracle, with and without charge tables."""
     sub, orders, cu, cv, du, dv = case
     for name, val in (("SYMT_GEMM_TILE", tile), ("SYMT_GEMM_SK", sk)):
         if val:
@@ -534,7 +553,7 @@ def test_fused_product_on_aligned_u(P, case, compute, tile, sk, monkeypatch):
     g = O.Group(orders)
     su0 = O.Sym.make(cu, int(rng.integers(g.size)), du, g)
     sv0 = O.Sym.make(cv, int(rng.integers(g.size)), dv, g)
-    dt = torch.float64 if compute == "f64" else torch.float32
+    dt = torch.float32 if compute == "f32" else torch.float64
     for tables in (False, True):
         su, sv = _with_tables(rng, sub, su0, sv0) if tables else (su0, sv0)
         say(f"aligned-u {sub} G={orders} {compute} tile={tile or 'default'} sk={sk} tables={tables}")
@@ -544,19 +563,25 @@ def test_fused_product_on_aligned_u(P, case, compute, tile, sk, monkeypatch):
         v = _sym_tensor(P, Rv, sv, dt)
         info = P.plan(sub, u, v, compute)
         if info.fused:                 # runs of 24 on register tiles: stepped run by run instead
-            assert sub.startswith("abkl") and info.fused_w == 1
+            assert sub.startswith("abkl") and info.fused_w == 1 and compute != "bf16x3"
             continue
-        assert info.fused_w == 1
+        # split-bf16 writes W in place only where W's columns come in runs of >= 16
+        assert info.fused_w == int(compute != "bf16x3" or _w_col_run(sub, du, dv) >= 16)
         w_f = P.output_like(sub, u, v, dtype=dt)
         w_s = P.output_like(sub, u, v, dtype=dt)
         P.contract_into(sub, u, v, w_f, compute)
         P.contract_into(sub, u, v, w_s, compute, steps=True)
         assert torch.equal(w_f.data, w_s.data)
+        if compute == "bf16x3":    # binary32 W: the same sums, rounded on the store
+            w32_f = P.output_like(sub, u, v, dtype=torch.float32)
+            assert P.plan(sub, u, v, compute, w=w32_f).fused_w == info.fused_w
+            P.contract_into(sub, u, v, w32_f, compute)
+            assert torch.equal(w32_f.data, w_s.data.to(torch.float32))
         U64, V64 = H.to_np(u.data).astype(np.float64), H.to_np(v.data).astype(np.float64)
         ref, _ = O.contract_blocks(sub, U64, su, V64, sv)
         absref, _ = O.contract_blocks(sub, np.abs(U64), su, np.abs(V64), sv)
         k = H.contracted_extent(sub, su)
-        fac = 2 * H.gamma(k, H.U64) if compute == "f64" else 1.05 * H.gamma(k, H.U32) + H.gamma(k, H.U64)
+        fac = H.bound_factor(compute, k)
         assert np.all(np.abs(H.to_np(w_f.data) - ref) <= fac * absref + 1e-300)
 
 
@@ -613,6 +638,14 @@ def test_fused_split_bf16_product(P, case, udt, tile, monkeypatch):
     w_o = P.output_like(sub, u, v, dtype=torch.float64)
     P.contract_into(sub, u_off, v, w_o, "bf16x3")
     assert torch.equal(w_o.data, w_s.data)
+    # a binary32 W takes the same sums rounded once, on the store
+    w32_f = P.output_like(sub, u, v, dtype=torch.float32)
+    w32_s = P.output_like(sub, u, v, dtype=torch.float32)
+    assert P.plan(sub, u, v, "bf16x3", w=w32_f).fused == int(nK % 32 == 0)
+    P.contract_into(sub, u, v, w32_f, "bf16x3")
+    P.contract_into(sub, u, v, w32_s, "bf16x3", steps=True)
+    assert torch.equal(w32_f.data, w32_s.data)
+    assert torch.equal(w32_f.data, w_s.data.to(torch.float32))
 
 
 # V read in place: contracted modes first in V, in U's K order; K runs of 32
