@@ -261,6 +261,9 @@ def main():
     ap.add_argument("--calibrate", action="store_true",
                     help="also run one plain elementwise kernel that reads and writes 256 MiB "
                          "(the reference for scaling HBM byte counters)")
+    ap.add_argument("--only", default="",
+                    help="WORKLOAD/COMPUTE (e.g. ccd_ladder_z8/bf16x3): time that one workload's chain "
+                         "(as --all does), print one line and exit; for profiling runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the contraction is benchmarked on a single MI355X "
@@ -274,6 +277,11 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.only:
+        name, compute = args.only.split("/")
+        r = time_workload(P, SG, synth.configs.get(name), compute, args.steps, args.warmup)
+        print(json.dumps({"workload": name, "compute": compute, **r}), flush=True)
+        return
     wl = synth.configs.get(WORKLOAD)
     st = wl.steps[0]
     ou, ov, ow = (wl.operands[x] for x in (st.u, st.v, st.w))
