@@ -225,7 +225,8 @@ typedef struct {
   size_t workspace_bytes;          /* what symtensor_contract needs */
   char w_signs[SYMT_MAX_ORDER + 1];/* derived output sign string (tw order), NUL-terminated */
   int32_t w_charge;                /* derived output charge */
-  int32_t fused;                   /* 1 if symtensor_contract will run the fused product */
+  int32_t fused;                   /* 1 if symtensor_contract's product reads u in place (and
+                                      writes w in place): see FUSED PRODUCT */
   int32_t fused_v;                 /* 1 if the product also reads v in place (no V_al), given
                                       16-byte aligned v data */
   int32_t fused_w;                 /* 1 if the product writes w in place (fused = 1, or u
