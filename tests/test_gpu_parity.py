@@ -585,6 +585,36 @@ def test_fused_product_on_aligned_u(P, case, compute, tile, sk, monkeypatch):
         assert np.all(np.abs(H.to_np(w_f.data) - ref) <= fac * absref + 1e-300)
 
 
+@pytest.mark.parametrize("sub,orders,cu,cv,du,dv", [UA_CASES[0], UA_CASES[2], FUSED_CASES[0]])
+@pytest.mark.parametrize("udt,vdt", [("f64", "f64"), ("f64", "f32"), ("f32", "f64")])
+def test_fused_products_with_mixed_storage(P, sub, orders, cu, cv, du, dv, udt, vdt):
+    """f32 compute on operands stored in binary64 (converted by their transforms, or
+    read as binary32 in place where stored so) with a binary32 W written in place:
+    identical to the three-step path and within the f32 bound of the oracle."""
+    rng = np.random.default_rng(seed("mixed", sub, udt, vdt))
+    g = O.Group(orders)
+    su = O.Sym.make(cu, int(rng.integers(g.size)), du, g)
+    sv = O.Sym.make(cv, int(rng.integers(g.size)), dv, g)
+    say(f"mixed storage {sub} u={udt} v={vdt}")
+    dtype = {"f64": torch.float64, "f32": torch.float32}
+    Ru = rng.standard_normal(su.reduced_shape())
+    Rv = rng.standard_normal(sv.reduced_shape())
+    u = _sym_tensor(P, Ru, su, dtype[udt])
+    v = _sym_tensor(P, Rv, sv, dtype[vdt])
+    w_f = P.output_like(sub, u, v, dtype=torch.float32)
+    w_s = P.output_like(sub, u, v, dtype=torch.float32)
+    info = P.plan(sub, u, v, "f32", w=w_f)
+    assert info.fused_w == 1
+    P.contract_into(sub, u, v, w_f, "f32")
+    P.contract_into(sub, u, v, w_s, "f32", steps=True)
+    assert torch.equal(w_f.data, w_s.data)
+    U64, V64 = H.to_np(u.data).astype(np.float64), H.to_np(v.data).astype(np.float64)
+    ref, _ = O.contract_blocks(sub, U64, su, V64, sv)
+    absref, _ = O.contract_blocks(sub, np.abs(U64), su, np.abs(V64), sv)
+    k = H.contracted_extent(sub, su)
+    assert np.all(np.abs(H.to_np(w_f.data) - ref) <= H.bound_factor("f32", k) * absref + 1e-300)
+
+
 # split-bf16 fused product: U's trailing contracted block a multiple of 32
 BF_FUSED_CASES = [
     ("abkl,klij->abij", (4,), "++--", "++--", (3, 5, 4, 8), (4, 8, 2, 6)),
