@@ -102,7 +102,11 @@ struct alignas(sizeof(T) * V) VecT {
 // SPLIT: gridDim.x = ntiles * splits; workgroup (tile, s) multiplies the s-th of
 // `splits` equal runs of K-steps and stores its partial tile in accumulator
 // order at part + (tile * splits + s) * BM * BN; k_split_sum adds them.
-template <typename T, int BM, int BN, int BK, int WM, int WN, int V, bool FA, bool FC, bool SPLIT = false>
+// AT (with FA): A is loaded K-major, as B is: row k0 + r of a K-step at
+// ca[q*K + k0 + r] (any layout of U's contracted modes), V-wide chunks of M at
+// ra[q*M + m] (contiguous runs of U's other modes); the LDS tile is [k][m].
+template <typename T, int BM, int BN, int BK, int WM, int WN, int V, bool FA, bool FC, bool SPLIT = false,
+          bool AT = false>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
                                                        const T* __restrict__ B,
                                                        T* __restrict__ C, int M, int N, int K,
@@ -130,8 +134,13 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
   constexpr int LA = (BM * BK / V + NT - 1) / NT;   // vector loads per thread, A tile
   constexpr int LB = (BK * BN / V + NT - 1) / NT;   // vector loads per thread, B tile
   using Acc = typename Mfma<T>::Acc;
+  static_assert(!AT || FA, "A is loaded K-major from U's standard form only");
+  // K-major A rows padded as B's are
+  constexpr int PADA = ((SHIFT - (BM * static_cast<int>(sizeof(T))) % 256 + 256) % 256) /
+                       static_cast<int>(sizeof(T));
 
-  __shared__ T As[2][BM][BK + PAD];
+  __shared__ T As[2][AT ? 1 : BM][AT ? 1 : BK + PAD];
+  __shared__ T AsT[2][AT ? BK : 1][AT ? BM + PADA : 1];
   __shared__ T Bs[2][BK][BN + PADB];
 
   const int64_t tile = SPLIT ? static_cast<int64_t>(blockIdx.x) / splits : xcd_remap(blockIdx.x, ntiles);
@@ -151,12 +160,13 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
   const int wm0 = (wave / WN) * (BM / WM);
   const int wn0 = (wave % WN) * (BN / WN);
 
-  // Fused A: the standard-form offset of each of this thread's tile rows.
+  // Fused A: the standard-form offset of each of this thread's tile rows (AT:
+  // of the M chunk it loads in every K-step).
   int64_t arow[LA];
 #pragma unroll
   for (int i = 0; i < LA; ++i) {
     const int e = (tid + i * NT) * V;
-    const int gr = m0 + e / BK;
+    const int gr = m0 + (AT ? e % BM : e / BK);
     arow[i] = (FA && e < BM * BK && gr < M) ? ra[q * M + gr] : static_cast<int64_t>(gr) * K;
   }
 
@@ -189,13 +199,22 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
       const int e = (tid + i * NT) * V;              // element index inside the BM x BK tile
-      const int r = e / BK, c = e % BK;
-      const int gr = m0 + r;
-      if (e < BM * BK && gr < M && c < kv)
-        ra_[i] = *reinterpret_cast<const VecT<T, V>*>(Aq + arow[i] + acol + c);
-      else
+      if constexpr (AT) {                            // [k][m]: row r of the step, M chunk c
+        const int r = e / BM, c = e % BM;
+        if (e < BM * BK && m0 + c < M && r < kv)
+          ra_[i] = *reinterpret_cast<const VecT<T, V>*>(Aq + ca[q * K + k0 + r] + arow[i]);
+        else
 #pragma unroll
-        for (int j = 0; j < V; ++j) ra_[i].v[j] = T(0);
+          for (int j = 0; j < V; ++j) ra_[i].v[j] = T(0);
+      } else {
+        const int r = e / BK, c = e % BK;
+        const int gr = m0 + r;
+        if (e < BM * BK && gr < M && c < kv)
+          ra_[i] = *reinterpret_cast<const VecT<T, V>*>(Aq + arow[i] + acol + c);
+        else
+#pragma unroll
+          for (int j = 0; j < V; ++j) ra_[i].v[j] = T(0);
+      }
     }
 #pragma unroll
     for (int i = 0; i < LB; ++i) {
@@ -213,7 +232,11 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
       const int e = (tid + i * NT) * V;
-      if (e < BM * BK) *reinterpret_cast<VecT<T, V>*>(&As[buf][e / BK][e % BK]) = ra_[i];
+      if constexpr (AT) {
+        if (e < BM * BK) *reinterpret_cast<VecT<T, V>*>(&AsT[buf][e / BM][e % BM]) = ra_[i];
+      } else {
+        if (e < BM * BK) *reinterpret_cast<VecT<T, V>*>(&As[buf][e / BK][e % BK]) = ra_[i];
+      }
     }
 #pragma unroll
     for (int i = 0; i < LB; ++i) {
@@ -245,7 +268,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
     for (int kk = 0; kk < BK; kk += 4) {
       T a[TM], b[TN];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) a[i] = As[buf][wm0 + i * 16 + (lane & 15)][kk + (lane >> 4)];
+      for (int i = 0; i < TM; ++i)
+        a[i] = AT ? AsT[buf][kk + (lane >> 4)][wm0 + i * 16 + (lane & 15)]
+                  : As[buf][wm0 + i * 16 + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
       for (int j = 0; j < TN; ++j) b[j] = Bs[buf][kk + (lane >> 4)][wn0 + j * 16 + (lane & 15)];
 #pragma unroll
@@ -875,7 +900,15 @@ hipError_t launch_fp(int vec, int64_t batch, int M, int N, int K, const void* A,
   if (splits > 1) {
     T* pt = static_cast<T*>(part);
     const dim3 grid(static_cast<unsigned>(ntiles * splits));
-    if (f && fv)
+    if (f && f->at && fv)
+      hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, VV, true, true, true, true>), grid, block, 0, s, a, b, c,
+                         M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, splits, f->rb, f->cb, f->ldb,
+                         f->krun);
+    else if (f && f->at)
+      hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, 1, true, true, true, true>), grid, block, 0, s, a, b, c,
+                         M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, splits, f->rb, f->cb, f->ldb,
+                         f->krun);
+    else if (f && fv)
       hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, VV, true, true, true>), grid, block, 0, s, a, b, c, M, N,
                          K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, splits, f->rb, f->cb, f->ldb, f->krun);
     else if (f)
@@ -898,7 +931,13 @@ hipError_t launch_fp(int vec, int64_t batch, int M, int N, int K, const void* A,
     return hipGetLastError();
   }
   const dim3 grid(static_cast<unsigned>(ntiles));
-  if (f && fv) {
+  if (f && f->at && fv) {
+    hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, VV, true, true, false, true>), grid, block, 0, s, a, b, c,
+                       M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, nullptr, 1, f->rb, f->cb, f->ldb, f->krun);
+  } else if (f && f->at) {
+    hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, 1, true, true, false, true>), grid, block, 0, s, a, b, c,
+                       M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, nullptr, 1, f->rb, f->cb, f->ldb, f->krun);
+  } else if (f && fv) {
     hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, VV, true, true>), grid, block, 0, s, a, b, c,
                        M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, nullptr, 1, f->rb, f->cb, f->ldb, f->krun);
   } else if (f) {
@@ -1328,10 +1367,10 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
     const bool f64 = compute == SYMT_COMPUTE_F64;
     const int vw = f64 ? 2 : 4;
     const int vec = (K % vw == 0 && N % vw == 0) ? vw : 1;
-    // K stepped run by run (fused->krun) needs the register tiles
+    // K stepped run by run (fused->krun) and K-major A (fused->at) need the register tiles
     const bool aligned = (reinterpret_cast<uintptr_t>(A) & 15) == 0 &&
                          (reinterpret_cast<uintptr_t>(B) & 15) == 0 &&
-                         (!fused || (fused->vec > 1 && fused->krun == 0));
+                         (!fused || (fused->vec > 1 && fused->krun == 0 && !fused->at));
     const GemmChoice gc = choose_fp_gemm(batch, M, N, K, f64 ? 8 : 4, aligned);
     if ((!gc.sk && gc.splits <= 1) || (reinterpret_cast<uintptr_t>(part) & 15) != 0) part = nullptr;
     e = f64 ? launch_fp_tile<double>(gc.tile, vec, batch, M, N, K, A, B, C, stream, fused, part, part_bytes,

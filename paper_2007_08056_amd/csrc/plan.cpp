@@ -477,9 +477,26 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
                        (!w || p->W.dtype == want) && p->nK <= INT32_MAX && p->nK > 0 &&
                        p->gk % p->nK == 0 &&
                        !choose_fp_gemm(p->g.size, p->M, p->gn, p->gk, static_cast<int>(ea), true).dma;
-  p->fused = !force_steps && !p->subgroups && p->nq == p->g.size && (fp_ok || bf_ok || stepped) && trailing_k &&
+  // U's contracted modes are not its last ones: where the product runs on register
+  // tiles anyway, A is loaded K-major straight from U (row k of a K-step at its own
+  // column-table entry, M chunks along U's other modes), as B is from V.
+  const bool at_ok = !trailing_k && compute != SYMT_COMPUTE_BF16X3 && !p->cplx && p->U.dtype == want &&
+                     (!w || p->W.dtype == want) &&
+                     !choose_fp_gemm(p->g.size, p->M, p->gn, p->gk, static_cast<int>(ea), true).dma;
+  p->fused = !force_steps && !p->subgroups && p->nq == p->g.size &&
+             (((fp_ok || bf_ok || stepped) && trailing_k) || at_ok) &&
              p->M > 0 && p->N > 0 && p->Kd > 0 && p->U.elems > 0;
+  p->a_trans = p->fused && !trailing_k;
   p->krun = p->fused && stepped ? static_cast<int32_t>(p->nK) : 0;
+  if (p->a_trans) {
+    // contiguous run of U's output modes at its end (16-byte loads along M)
+    int64_t st[kMaxOrder];
+    int64_t a = 1;
+    for (int m = p->U.n - 1; m >= 0; --m) { st[m] = a; a *= p->U.dims[m]; }
+    int64_t i_run = 1;
+    for (int i = p->s - 1; i >= 0 && st[p->posI_u[i]] == i_run; --i) i_run *= p->U.dims[p->posI_u[i]];
+    p->a_chunks = i_run % (16 / static_cast<int64_t>(ea)) == 0;
+  }
   // Otherwise, for real operands and W in the compute type, U alone is aligned
   // and the same product reads U_al through affine tables, V in place where it
   // can, and writes W in place.

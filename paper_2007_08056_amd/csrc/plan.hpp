@@ -138,6 +138,7 @@ struct FusedTables {
   int32_t a_bytes = 8;              // split-bf16 product: U's element size (8 binary64, 4 binary32)
   int32_t krun = 0;                 // > 0: K stepped run by run (register tiles)
   int32_t c_bytes = 8;              // split-bf16 products: W's element size (8 binary64, 4 binary32)
+  int32_t at = 0;                   // 1: A loaded K-major from U (register tiles)
 };
 
 struct OperandDesc {
@@ -176,6 +177,11 @@ struct Plan {
   // fused product on U_al: U's contracted modes are not its last ones (or its runs
   // do not suit the product's tiles), so U is aligned first; B and C as when fused
   bool fused_ua = false;
+  // fused with A loaded K-major (U's contracted modes are not its last ones): row k
+  // of a K-step at ca(Q, k), M chunks at ra(Q, m); a_chunks: U's other modes come
+  // in runs of whole 16-byte chunks (vector loads along M)
+  bool a_trans = false;
+  bool a_chunks = false;
   // B read from V's standard form too (no V_al): V's rows are affine inside every
   // K-step (stride ldb) and its columns come in runs of whole 16-byte chunks
   // (used when V is 16-byte aligned)

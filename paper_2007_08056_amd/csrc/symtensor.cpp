@@ -170,6 +170,8 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
   // U_al: one run of gk per row, 256-byte aligned)
   const int64_t run = p.fused_ua ? p.gk : (p.cplx ? 2 : 1) * p.nK, vw = p.compute == SYMT_COMPUTE_F64 ? 2 : 4;
   int vec = (p.fused_ua || aligned16(p.U.data)) && (p.compute == SYMT_COMPUTE_BF16X3 || run % vw == 0) ? 2 : 1;
+  // K-major A: 16-byte loads along U's output modes
+  if (p.a_trans) vec = aligned16(p.U.data) && p.a_chunks ? 2 : 1;
   // V in place: its column chunks take 16-byte loads (global-to-LDS tiles, and
   // register tiles whose loads are vectors), so V must be 16-byte aligned
   const bool fb = p.fused_b && (p.krun > 0 || aligned16(p.V.data));
@@ -202,6 +204,7 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
   if (p.fused_ua && p.compute == SYMT_COMPUTE_BF16X3) f.ra = f.ca = nullptr;
   f.a_bytes = static_cast<int32_t>(p.fused_ua ? (p.compute == SYMT_COMPUTE_F64 ? 8 : 4) : elem_bytes(p.U.dtype));
   f.krun = p.krun;
+  f.at = p.a_trans ? 1 : 0;
   f.c_bytes = static_cast<int32_t>(elem_bytes(p.W.dtype));
   if (fb) {
     f.rb = rb;

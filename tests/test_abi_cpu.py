@@ -57,8 +57,13 @@ def test_plan_matches_oracle_on_workloads(name):
         k_modes = [m for m in tu if m in tv]
         trailing = tu.endswith("".join(k_modes))
         nK = int(np.prod([ou.dims[tu.index(m)] for m in k_modes]))
-        assert info.fused == int(trailing and (nK % 16 == 0 or len(k_modes) == 1) and su.sectors is None
-                                 and sv.sectors is None)
+        whole = trailing and (nK % 16 == 0 or len(k_modes) == 1)
+        no_sub = su.sectors is None and sv.sectors is None
+        # whole K-steps read U in place on any tile; other layouts (K-major A, runs stepped one
+        # by one) only where the product runs on register tiles, which the planner decides
+        assert info.fused == 0 if not no_sub else (info.fused == 1 if whole else True)
+        # W is written in place whenever no mode is a subgroup mode (real f64 operands here)
+        assert info.fused_w == int(no_sub)
         G = info.group_size
         if info.fused:
             # V aligned plus four offset tables of U and W
