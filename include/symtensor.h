@@ -84,7 +84,7 @@
  * sector group).  symtensor_contract uses this when compute is F64 or F32, u is
  * stored in the compute type (complex: its complex counterpart), w too, no mode
  * is a subgroup mode, every Q slice is live and u's last v modes are exactly its
- * contracted modes.  It builds the offset tables of U and W in the workspace
+ * contracted modes (or see K-major A below).  It builds the offset tables of U and W in the workspace
  * and runs one product that reads A straight from u's standard form and writes
  * C straight into w's, so U_al and W_al are never materialised
  * (info.fused = 1).  A K run (u's contracted block, in reals) that holds whole
@@ -105,8 +105,12 @@
  * multiple of 16 bytes (or K stepped run by run), and v is 16-byte aligned
  * (or K stepped run by run): then two more tables let the product read B from
  * v's standard form as well (info.fused_v = 1) and no aligned form is written
- * at all.  Where u does not qualify (its contracted modes are not its last
- * ones, or its runs suit neither stepping), compute is F64 or F32, the operands
+ * at all.  Where u's contracted modes are not its last ones, u and w are real
+ * and in the compute type and the product runs on register-staged tiles, A is
+ * loaded K-major straight from u (each row of a K-step from its own table
+ * entry, chunks along u's other modes), with the same values in the same order
+ * (info.fused = 1).  Where u does not qualify otherwise (global-to-LDS shapes,
+ * or runs that suit neither stepping), compute is F64 or F32, the operands
  * are real, w is in the compute type, no mode is a subgroup mode and every Q
  * slice is live, u alone is aligned first and the same product reads U_al
  * through affine tables (info.fused = 0, info.fused_w = 1); with BF16X3, u and
