@@ -480,7 +480,7 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   // U's contracted modes are not its last ones: where the product runs on register
   // tiles anyway, A is loaded K-major straight from U (row k of a K-step at its own
   // column-table entry, M chunks along U's other modes), as B is from V.
-  const bool at_ok = !trailing_k && compute != SYMT_COMPUTE_BF16X3 && !p->cplx && p->U.dtype == want &&
+  const bool at_ok = !trailing_k && compute != SYMT_COMPUTE_BF16X3 && p->U.dtype == want &&
                      (!w || p->W.dtype == want) &&
                      !choose_fp_gemm(p->g.size, p->M, p->gn, p->gk, static_cast<int>(ea), true).dma;
   p->fused = !force_steps && !p->subgroups && p->nq == p->g.size &&
@@ -495,11 +495,12 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
     for (int m = p->U.n - 1; m >= 0; --m) { st[m] = a; a *= p->U.dims[m]; }
     int64_t i_run = 1;
     for (int i = p->s - 1; i >= 0 && st[p->posI_u[i]] == i_run; --i) i_run *= p->U.dims[p->posI_u[i]];
-    p->a_chunks = i_run % (16 / static_cast<int64_t>(ea)) == 0;
+    // (complex: pairs interleave, one-element loads)
+    p->a_chunks = !p->cplx && i_run % (16 / static_cast<int64_t>(ea)) == 0;
   }
-  // Otherwise, for real operands and W in the compute type, U alone is aligned
-  // and the same product reads U_al through affine tables, V in place where it
-  // can, and writes W in place.
+  // Otherwise, for W in the compute type (complex: its complex counterpart), U
+  // alone is aligned and the same product reads U_al through affine tables (in
+  // reals), V in place where it can, and writes W in place.
   // (split-bf16: U and V go to hi/lo planes as in three steps, and the product
   // writes its binary64 sums straight into W)
   const int w_want = compute == SYMT_COMPUTE_F32 ? SYMT_F32 : SYMT_F64;
@@ -513,8 +514,9 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
     for (int m = p->W.n - 1; m >= 0; --m) { st[m] = a; a *= p->W.dims[m]; }
     for (int i = p->t - 1; i >= 0 && st[p->posJ_w[i]] == w_run; --i) w_run *= p->W.dims[p->posJ_w[i]];
   }
-  p->fused_ua = !p->fused && !force_steps && !p->subgroups && p->nq == p->g.size && !p->cplx &&
-                (!w || p->W.dtype == w_want || (compute == SYMT_COMPUTE_BF16X3 && p->W.dtype == SYMT_F32)) &&
+  p->fused_ua = !p->fused && !force_steps && !p->subgroups && p->nq == p->g.size &&
+                (!w || p->W.dtype == (p->cplx ? want : w_want) ||
+                 (compute == SYMT_COMPUTE_BF16X3 && p->W.dtype == SYMT_F32)) &&
                 p->M > 0 && p->N > 0 && p->Kd > 0 && p->U.elems > 0 &&
                 (compute != SYMT_COMPUTE_BF16X3 || w_run >= 16);
   if (p->fused || p->fused_ua) {

@@ -1155,6 +1155,44 @@ def test_complex_fused_product_equals_steps_and_oracle(P, case, compute):
         assert np.all(np.abs(part(got) - part(ref)) <= H.bound_factor(compute, k) * absref + 1e-300)
 
 
+@pytest.mark.parametrize("case", UA_CASES[:4])
+@pytest.mark.parametrize("compute", ["f64", "f32"])
+@pytest.mark.parametrize("tile", ["", "128x48", "d96x96s2"])
+def test_complex_products_with_leading_contracted_modes(P, case, compute, tile, monkeypatch):
+    """Complex operands whose contracted modes lead in U: A loaded K-major as
+    interleaved reals on register tiles, or U aligned first on global-to-LDS
+    tiles; W's pairs written in place.  Bit-identical to the three-step path and
+    within the product's bound of the oracle."""
+    sub, orders, cu, cv, du, dv = case
+    if tile:
+        monkeypatch.setenv("SYMT_GEMM_TILE", tile)
+    else:
+        monkeypatch.delenv("SYMT_GEMM_TILE", raising=False)
+    monkeypatch.delenv("SYMT_GEMM_SK", raising=False)
+    rng = np.random.default_rng(seed("complex-leading", sub, orders))
+    g = O.Group(orders)
+    su = O.Sym.make(cu, int(rng.integers(g.size)), du, g)
+    sv = O.Sym.make(cv, int(rng.integers(g.size)), dv, g)
+    say(f"complex leading {sub} G={orders} {compute} tile={tile or 'default'}")
+    Ru, Rv = _cplx(rng, su.reduced_shape()), _cplx(rng, sv.reduced_shape())
+    dt = torch.complex128 if compute == "f64" else torch.complex64
+    u, v = _sym_tensor(P, Ru, su, dt), _sym_tensor(P, Rv, sv, dt)
+    info = P.plan(sub, u, v, compute)
+    assert info.fused_w == 1
+    w_f = P.output_like(sub, u, v, dtype=dt)
+    w_s = P.output_like(sub, u, v, dtype=dt)
+    P.contract_into(sub, u, v, w_f, compute)
+    P.contract_into(sub, u, v, w_s, compute, steps=True)
+    assert torch.equal(w_f.data, w_s.data)
+    ref, _ = O.contract_blocks(sub, H.to_np(u.data).astype(np.complex128), su,
+                               H.to_np(v.data).astype(np.complex128), sv)
+    absref, _ = O.contract_blocks(sub, np.abs(Ru), su, np.abs(Rv), sv)
+    k = 2 * H.contracted_extent(sub, su)
+    got = H.to_np(w_f.data).astype(np.complex128)
+    for part in (np.real, np.imag):
+        assert np.all(np.abs(part(got) - part(ref)) <= H.bound_factor(compute, k) * absref + 1e-300)
+
+
 # ---------------------------------------------------------------------------
 # Split K on the register tiles: few tiles and a long K (odd N rules out the
 # global-to-LDS tiles), partial tiles summed in order by k_split_sum.
