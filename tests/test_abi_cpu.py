@@ -479,6 +479,30 @@ def test_split_bf16_fused_plans(monkeypatch):
                  _desc("++--", 0, (32, 32, 8, 8)), compute=bf)[1].fused == 1
 
 
+def test_leading_contracted_modes_plans(monkeypatch):
+    """U's contracted modes first: on register tiles A is loaded K-major from U in
+    place (fused = 1, no U_al in the workspace); on a global-to-LDS tile U alone is
+    aligned (fused = 0, fused_w = 1, U_al first in the workspace); complex too."""
+    monkeypatch.delenv("SYMT_GEMM_TILE", raising=False)
+    monkeypatch.delenv("SYMT_GEMM_SK", raising=False)
+    u, v = _desc("--++", 0, (4, 8, 3, 5)), _desc("++--", 0, (4, 8, 2, 6))
+    r = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    km = _plan("klab,klij->abij", 4, u, v)[1]
+    assert km.fused == 1 and km.fused_w == 1 and km.fused_v == 1
+    assert km.workspace_bytes < km.bytes_u_al      # V_al and tables only
+    monkeypatch.setenv("SYMT_GEMM_TILE", "d96x96s2")
+    ua = _plan("klab,klij->abij", 4, u, v)[1]
+    assert ua.fused == 0 and ua.fused_w == 1
+    assert ua.workspace_bytes >= r(ua.bytes_u_al) + r(ua.bytes_v_al)
+    monkeypatch.delenv("SYMT_GEMM_TILE")
+    cu, cv = _desc("--++", 0, (4, 8, 3, 5), L.SYMT_C128), _desc("++--", 0, (4, 8, 2, 6), L.SYMT_C128)
+    c = _plan("klab,klij->abij", 4, cu, cv)[1]
+    assert c.fused == 1 and c.fused_w == 1 and c.fused_v == 0
+    # forced three steps
+    st = _plan("klab,klij->abij", 4, u, v, compute=0x100)[1]
+    assert st.fused == 0 and st.fused_w == 0
+
+
 def test_split_k_for_few_tiles_and_long_k(monkeypatch):
     """Register tiles split a long K into runs when a launch has too few tiles to fill the CUs."""
     monkeypatch.delenv("SYMT_GEMM_SK", raising=False)
