@@ -578,6 +578,13 @@ def test_fused_product_on_aligned_u(P, case, compute, tile, sk, monkeypatch):
         P.contract_into(sub, u, v, w_s, compute, steps=True)
         if not stepped:
             assert torch.equal(w_f.data, w_s.data)
+            # U one element into a buffer (not 16-byte aligned): one-element loads, same bits
+            buf = torch.zeros(u.data.numel() + 1, dtype=dt, device=DEV)
+            buf[1:] = u.data.reshape(-1)
+            u_off = P.SymTensor(buf[1:].view(u.data.shape), u.signs, u.charge, u.group, u.mode_charges)
+            w_o = P.output_like(sub, u, v, dtype=dt)
+            P.contract_into(sub, u_off, v, w_o, compute)
+            assert torch.equal(w_o.data, w_s.data)
         if compute == "bf16x3":    # binary32 W: the same sums, rounded on the store
             w32_f = P.output_like(sub, u, v, dtype=torch.float32)
             assert P.plan(sub, u, v, compute, w=w32_f).fused_w == info.fused_w
