@@ -131,6 +131,16 @@
  *
  * Return values: SYMT_OK (0) or one of the negative codes below; the detail of
  * the last failure on a context is in symtensor_last_error().
+ *
+ * Environment (read at planning and launch time; for tuning and tests only,
+ * never needed for correctness: every tile meets the same accuracy bound):
+ *   SYMT_GEMM_TILE=<name>  restricts the sector product to one tile where that
+ *                          tile applies (F64/F32: "128x96", "d96x96s2", ...;
+ *                          BF16X3: "b128x128k32", "bd128x256s3", ...); an
+ *                          unknown or inapplicable name is ignored.
+ *   SYMT_GEMM_SK=0 | 1     0 forbids stream-K and split K; 1 forces stream-K on
+ *                          the global-to-LDS tiles.
+ *   SYMT_FUSED_V=0         keeps V aligned in the fused product (info.fused_v = 0).
  */
 #ifndef SYMTENSOR_H
 #define SYMTENSOR_H
