@@ -15,7 +15,7 @@ subgroup modes against the smaller cyclic group and brute force.
 from .symcontract import (  # noqa: F401
     Group, Sym, allowed, implicit_sector, full_sectors, stored_tuples, expand, reduce_full, lookup,
     parse_einsum, contracted_sign_ratio, output_symmetry, same_symmetry, check_operands,
-    flop_count, contract_dense, contract_blocks, sample_contract, reduced_value_fn,
+    flop_count, contract_dense, contract_blocks, sample_contract, sample_contract_allowed, reduced_value_fn,
     contract_bruteforce, kron_delta, alignment_deltas, align_u, align_v, unalign_w,
     contract_irrep_aligned, aligned_shape, bf16_round, bf16_split,
 )

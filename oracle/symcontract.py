@@ -31,7 +31,9 @@ Forms of the reference result (all must agree):
 2. ``contract_blocks``  loop over allowed sector tuples, one block product each
    (Alg. 1, generalised to any number of free and contracted modes).
 3. ``sample_contract``  selected output elements, each summed over every
-   contracted full index with a conservation-aware element lookup.
+   contracted full index with a conservation-aware element lookup;
+   ``sample_contract_allowed`` the same sums over the allowed contracted
+   sectors only (fast enough for thousands of elements of a large contraction).
 4. ``contract_bruteforce`` pure-Python loops over full indices (tiny inputs).
 5. ``contract_irrep_aligned`` Alg. 2 itself, with the generalized Kronecker
    deltas built as dense 0/1 tensors and every step an einsum, as the paper's
@@ -490,6 +492,80 @@ def sample_contract(sub, su: Sym, sv: Sym, u_values, v_values, w_full_positions,
         uv = gather(tu, su, u_values)
         vv = gather(tv, sv, v_values)
         out[s] = np.dot(uv, vv)
+    return out
+
+
+def sample_contract_allowed(sub, su: Sym, sv: Sym, u_values, v_values, w_full_positions,
+                            dtype=np.float64, chunk: int = 1 << 20):
+    """W at the given full positions, summed over the allowed contracted sectors only.
+
+    The same sum as ``sample_contract`` (Eq. ctr at one output element) with its
+    zero terms left out: an output element fixes the sectors of I and J; every
+    contracted sector but the last is free, the last one follows from U's rule
+    (no solution: no term), and V's rule must then hold as well (Eq. symtsr for
+    both factors).  Each surviving sector tuple adds the dot product of the two
+    factors over the contracted in-block indices.  The cost per element is the
+    number of nonzero terms rather than every contracted full index, so
+    thousands of elements of a large contraction can be checked.
+    ``u_values`` / ``v_values`` are value functions as for ``sample_contract``.
+    """
+    tu, tv, tw, I, K, J = check_operands(sub, su, sv)
+    pos = np.asarray(w_full_positions, dtype=np.int64).reshape(-1, len(tw))
+    S = len(pos)
+    out = np.zeros(S, dtype=dtype)
+    if S == 0:
+        return out
+    sec, inn = {}, {}
+    for c, m in enumerate(tw):
+        n = su.dims[tu.index(m)] if m in tu else sv.dims[tv.index(m)]
+        sec[m] = pos[:, c] // n
+        inn[m] = pos[:, c] % n
+    kdims = [su.dims[tu.index(k)] for k in K]
+    nk = math.prod(kdims)
+    kin = dict(zip(K, np.unravel_index(np.arange(nk, dtype=np.int64), kdims))) if K else {}
+    # (sample, contracted sectors) of every nonzero term
+    terms_s, terms_k = [], []
+    free = [range(su.H(tu.index(k))) for k in K[:-1]]
+    for s in range(S):
+        for ks in itertools.product(*free):
+            ksec = dict(zip(K[:-1], ks))
+            if K:
+                p = tu.index(K[-1])
+                known = [int(sec[m][s]) if m in sec else ksec[m] for m in tu if m != K[-1]]
+                last = implicit_sector(su, known, position=p)
+                if last is None:
+                    continue
+                ksec[K[-1]] = last
+            usec = [int(sec[m][s]) if m in sec else ksec[m] for m in tu]
+            vsec = [int(sec[m][s]) if m in sec else ksec[m] for m in tv]
+            if not (allowed(su, usec) and allowed(sv, vsec)):
+                continue
+            terms_s.append(s)
+            terms_k.append(tuple(ksec[k] for k in K))
+    if not terms_s:
+        return out
+    terms_s = np.asarray(terms_s, dtype=np.int64)
+    terms_k = np.asarray(terms_k, dtype=np.int64).reshape(len(terms_s), len(K))
+    per = max(1, chunk // max(nk, 1))
+    for lo in range(0, len(terms_s), per):
+        ts = terms_s[lo:lo + per]
+        tk = terms_k[lo:lo + per]
+        T = len(ts)
+
+        def coords(term, sym, fn):
+            secs, inner = [], []
+            for m in term:
+                if m in sec:
+                    secs.append(np.repeat(sec[m][ts], nk))
+                    inner.append(np.repeat(inn[m][ts], nk))
+                else:
+                    secs.append(np.repeat(tk[:, K.index(m)], nk))
+                    inner.append(np.tile(kin[m], T))
+            return fn(secs[:-1], inner).reshape(T, nk)
+
+        uv = coords(tu, su, u_values)
+        vv = coords(tv, sv, v_values)
+        np.add.at(out, ts, np.sum(uv * vv, axis=1))
     return out
 
 

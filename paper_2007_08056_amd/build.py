@@ -3,6 +3,7 @@
 * ``paper_2007_08056_amd/libsymtensor.so`` -- the contraction library (C ABI
   of include/symtensor.h).
 * ``synth/libsynthgen.so`` -- the GPU twin of the seeded input generator.
+* ``synth/libphilox_host.so`` -- its host twin in C (test inputs and samples).
 
 Usage: ``python paper_2007_08056_amd/build.py`` (always recompiles).
 """
@@ -70,8 +71,18 @@ def build_synth(verbose=False) -> str:
     return out
 
 
+def build_synth_host(verbose=False) -> str:
+    src = os.path.join(ROOT, "synth", "csrc", "philox_host.c")
+    out = os.path.join(ROOT, "synth", "libphilox_host.so")
+    tmp = out + ".tmp"
+    _run([os.environ.get("CC", "gcc"), "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared", src,
+          "-o", tmp], verbose)
+    os.replace(tmp, out)
+    return out
+
+
 def build_all(verbose=False):
-    return build_symtensor(verbose), build_synth(verbose)
+    return build_symtensor(verbose), build_synth(verbose), build_synth_host(verbose)
 
 
 if __name__ == "__main__":

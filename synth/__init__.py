@@ -11,6 +11,10 @@ from . import configs  # noqa: F401
 
 
 def host_input(wl, name: str):
-    """The standard reduced form of input ``name`` of workload ``wl``, binary64, on the host."""
+    """The standard reduced form of input ``name`` of workload ``wl``, binary64, on the host
+    (through the C twin of the generator when it is built: the same bits, faster)."""
+    from . import host
     op = wl.operands[name]
+    if host.available():
+        return host.fill(wl.reduced_shape(name), wl.seed, op.tensor_id, op.dist, op.scale)
     return fill(wl.reduced_shape(name), wl.seed, op.tensor_id, op.dist, op.scale)

@@ -8,6 +8,7 @@ import torch
 
 import oracle as O
 import synth
+from synth import host as synth_host
 from synth import philox
 
 
@@ -20,9 +21,11 @@ def value_fn(wl, name, absolute=False):
     op = wl.operands[name]
     shape = wl.reduced_shape(name)
 
+    gen = synth_host.values_at if synth_host.available() else philox.values_at
+
     def fn(secs, inner):
         e = np.ravel_multi_index(tuple(secs) + tuple(inner), shape)
-        x = philox.values_at(e, wl.seed, op.tensor_id, op.dist, op.scale)
+        x = gen(e, wl.seed, op.tensor_id, op.dist, op.scale)
         return np.abs(x) if absolute else x
     return fn
 

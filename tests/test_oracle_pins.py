@@ -56,6 +56,20 @@ def test_normal_values_exact_moments():
     assert np.array_equal(y, x[:100] * np.float64(1e-2))
 
 
+def test_host_generator_is_bit_identical_to_numpy():
+    """The C twin (synth/csrc/philox_host.c) gives the NumPy generator's bits."""
+    from synth import host
+    if not host.available():
+        pytest.skip("synth/libphilox_host.so is not built")
+    e = np.concatenate([np.arange(0, 5000), RNG.integers(0, 2 ** 40, 5000)]).astype(np.int64)
+    for dist in (philox.DIST_UNIFORM, philox.DIST_NORMAL):
+        for scale in (1.0, 1e-2):
+            assert np.array_equal(host.values_at(e, 20070805, 17, dist, scale),
+                                  philox.values_at(e, 20070805, 17, dist, scale))
+    got = host.fill((7, 11), 3, 4, philox.DIST_NORMAL, 1.0, first=1000)
+    assert np.array_equal(got.ravel(), philox.values_at(np.arange(1000, 1077), 3, 4, philox.DIST_NORMAL))
+
+
 # ---------------------------------------------------------------------------
 # Group arithmetic
 # ---------------------------------------------------------------------------
@@ -239,6 +253,59 @@ def test_sampled_form_matches_dense():
     np.testing.assert_allclose(got, Wf[tuple(pos.T)], rtol=1e-12, atol=1e-13)
 
 
+def _all_full_positions(sw):
+    return np.array(list(itertools.product(*[range(d) for d in sw.full_shape()])), dtype=np.int64)
+
+
+@pytest.mark.parametrize("orders", [(2,), (3,), (2, 2)])
+@pytest.mark.parametrize("stv", [(1, 1, 1), (2, 1, 1), (1, 2, 1), (1, 1, 2), (2, 1, 2), (1, 2, 2)])
+def test_sampled_allowed_form_matches_brute_force_everywhere(orders, stv):
+    """The allowed-sector sampled form equals Eq. ctr summed term by term at every output element."""
+    rng = np.random.default_rng(seed(("allowed", orders, stv)))
+    for sigma in (-1, 1):
+        sub, Ru, su, Rv, sv = _random_case(rng, orders, *stv, sigma=sigma)
+        Rb, sw, zb = O.contract_bruteforce(sub, Ru, su, Rv, sv)
+        assert zb
+        full = O.expand(Rb, sw)
+        pos = _all_full_positions(sw)
+        got = O.sample_contract_allowed(sub, su, sv, O.reduced_value_fn(Ru, su), O.reduced_value_fn(Rv, sv),
+                                        pos, chunk=7)
+        np.testing.assert_allclose(got, full[tuple(pos.T)], rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("sub", ["a,b->ab", "ab,cd->acbd", "k,kb->b", "lk,klb->b", "ak,k->a", "akl,lk->a"])
+def test_sampled_allowed_form_degenerate_tables_subgroups_complex(sub):
+    rng = np.random.default_rng(seed(("allowed-deg", sub)))
+    g = O.Group((4,))
+    tu, rest = sub.split(",")
+    tv, tw = rest.split("->")
+    for variant in ("tables", "subgroups", "complex"):
+        dims = {m: int(rng.integers(1, 3)) for m in set(tu + tv)}
+        cu = {m: int(rng.choice([-1, 1])) for m in tu}
+        sigma = int(rng.choice([-1, 1]))
+        cv = {m: (sigma * cu[m] if m in tu else int(rng.choice([-1, 1]))) for m in tv}
+        tab = ({m: tuple(int(x) for x in rng.permutation(g.size)) for m in set(tu + tv)}
+               if variant == "tables" else None)
+        hs = {m: int(rng.choice([1, 2, 4])) for m in set(tu + tv)} if variant == "subgroups" else None
+        su = O.Sym.make([cu[m] for m in tu], int(rng.integers(g.size)), [dims[m] for m in tu], g,
+                        [tab[m] for m in tu] if tab else None, [hs[m] for m in tu] if hs else None)
+        sv = O.Sym.make([cv[m] for m in tv], int(rng.integers(g.size)), [dims[m] for m in tv], g,
+                        [tab[m] for m in tv] if tab else None, [hs[m] for m in tv] if hs else None)
+        Ru, Rv = rng.standard_normal(su.reduced_shape()), rng.standard_normal(sv.reduced_shape())
+        dt = np.float64
+        if variant == "complex":
+            Ru = Ru + 1j * rng.standard_normal(su.reduced_shape())
+            Rv = Rv + 1j * rng.standard_normal(sv.reduced_shape())
+            dt = np.complex128
+        Rb, sw, zb = O.contract_bruteforce(sub, Ru, su, Rv, sv)
+        assert zb
+        full = O.expand(Rb, sw)
+        pos = _all_full_positions(sw)
+        got = O.sample_contract_allowed(sub, su, sv, O.reduced_value_fn(Ru, su), O.reduced_value_fn(Rv, sv),
+                                        pos, dtype=dt)
+        np.testing.assert_allclose(got, full[tuple(pos.T)], rtol=1e-13, atol=1e-13)
+
+
 # ---------------------------------------------------------------------------
 # Special cases that reduce to textbook or library routines
 # ---------------------------------------------------------------------------
@@ -385,6 +452,12 @@ def _pins_pass(monkeypatch_ctx=None):
                 for R in (Rd, Rk, Ra):
                     if not np.allclose(R, Rb, rtol=1e-12, atol=1e-12):
                         return False
+                sw = O.output_symmetry(sub, su, sv)
+                pos = _all_full_positions(sw)
+                got = O.sample_contract_allowed(sub, su, sv, O.reduced_value_fn(Ru, su),
+                                                O.reduced_value_fn(Rv, sv), pos)
+                if not np.allclose(got, O.expand(Rb, sw)[tuple(pos.T)], rtol=1e-12, atol=1e-12):
+                    return False
     except (AssertionError, ValueError, IndexError):
         return False
     return True
