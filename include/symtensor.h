@@ -70,7 +70,12 @@
  *
  * EMPTY MODE GROUPS (s, t or v = 0; Sec. 2.1's deltas with an empty sum).  One
  * delta then fixes Q on its own: v = 0 (an outer product) gives Q = 0 and
- * sigma is reported as -1; s = 0 gives Q = Z^U; t = 0 gives Q = sigma Z^V.
+ * sigma is taken as -1 (W's rule then lists u's coefficients and v's, with
+ * Z^W = Z^U + Z^V), or as +1 when a given w carries the rule derived with +1
+ * and not the -1 one (an outer product's nonzero blocks obey u's and v's rules
+ * each on its own, so both rules describe them: the gradient dU = dW (x) V of
+ * a contraction whose only contracted modes are all of V's is such a case);
+ * s = 0 gives Q = Z^U; t = 0 gives Q = sigma Z^V.
  * The forms that carry that delta are zero outside that slice: U_al when s or
  * v is 0, V_al when t or v is 0, and W_al always.  symtensor_align writes the
  * whole form, zeros included; symtensor_contract only needs and multiplies the
@@ -122,7 +127,9 @@
  *
  * Execution and ownership.  Every device buffer (operand data, workspace,
  * aligned buffers) is allocated and owned by the caller.  A context holds only
- * host state; it allocates no device memory.  Functions taking a stream
+ * host state (the HIP device, timing events, the last error and a cache of the
+ * plans it has made, keyed by every planning input except data pointers and
+ * guarded by a mutex); it allocates no device memory.  Functions taking a stream
  * (a hipStream_t passed as void*, NULL = the null stream) enqueue their
  * kernels on it and return without synchronising.  All validation happens on
  * the host before the first launch: on any error no kernel is launched and no
@@ -278,7 +285,8 @@ int symtensor_workspace_size(const char* einsum, const symt_group* group, const 
  * tables; then, where the product runs stream-K (see symtensor_sector_gemm),
  * the pieces of the tiles it cuts; then, with non-identity charge tables,
  * their device copies.
- * w->data must not overlap u->data, v->data or the workspace (SYMT_EALIAS).
+ * w->data must not overlap u->data, v->data or the workspace, and u->data and
+ * v->data must not overlap the workspace (SYMT_EALIAS).
  * Storage dtypes: SYMT_COMPUTE_F64 takes any mix of F64/F32 operands
  * (converted exactly to binary64); SYMT_COMPUTE_F32 and BF16X3 take any mix,
  * F64 inputs being rounded to binary32 first.  Complex operands likewise mix

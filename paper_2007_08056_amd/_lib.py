@@ -143,6 +143,9 @@ class TensorDesc:
         self.c = SymtTensor(len(signs), self._signs, int(charge), self._dims, int(dtype),
                             c_void_p(data_ptr) if data_ptr else None, self._charges, self._sectors)
 
+    def set_data(self, data_ptr: int | None):
+        self.c.data = c_void_p(data_ptr) if data_ptr else None
+
     @property
     def ref(self):
         return ctypes.byref(self.c)

@@ -294,6 +294,26 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   // v = 0 (outer product): no ratio is defined; -1 makes W's coefficients u's
   // followed by v's and Z^W = Z^U + Z^V
   p->sigma = p->v == 0 ? -1 : sigma;
+  if (p->v == 0 && w && w->signs && w->nmodes == static_cast<int32_t>(tw.size()) &&
+      strnlen(w->signs, tw.size()) == tw.size()) {
+    // An outer product's nonzero blocks satisfy u's and v's rules each on its
+    // own, so the rule derived with sigma = +1 describes them as well (it is
+    // u's rule when v is an operand's gradient partner, as in dU = dW (x) V):
+    // take +1 when the given output carries that rule and not the -1 one.
+    auto matches = [&](int sg) {
+      const int zc = gsub(p->g, p->U.charge, gtimes(p->g, sg, p->V.charge));
+      bool same = w->charge == zc, flipped = w->charge == gneg(p->g, zc);
+      for (size_t m = 0; m < tw.size(); ++m) {
+        const size_t pu = tu.find(tw[m]);
+        const int c = (pu != std::string::npos) ? p->U.sign[pu] : -sg * p->V.sign[tv.find(tw[m])];
+        const int given = w->signs[m] == '+' ? 1 : w->signs[m] == '-' ? -1 : 0;
+        same = same && given == c;
+        flipped = flipped && given == -c;
+      }
+      return same || flipped;
+    };
+    if (!matches(-1) && matches(+1)) p->sigma = 1;
+  }
   sigma = p->sigma;
 
   // ---- derived output rule: c^W = (c^U_I, -sigma c^V_J), Z^W = Z^U - sigma Z^V

@@ -4,8 +4,11 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "plan.hpp"
@@ -33,6 +36,10 @@ struct symt_ctx {
   bool timing = false;
   std::vector<hipEvent_t> pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[4];
+  // Plans of contractions already validated on this context, keyed by every
+  // planning input except the data pointers (see plan_key).
+  std::mutex plan_mu;
+  std::unordered_map<std::string, Plan> plans;
 };
 
 namespace {
@@ -216,11 +223,86 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
                  p.bytes_partial ? part : nullptr, p.bytes_partial);
 }
 
+// Cache key of a planning request: the einsum, group, compute mode, every
+// descriptor field but `data`, and the tuning variables the planner reads.  An
+// empty key (malformed descriptors, which make_plan rejects) bypasses the cache.
+constexpr size_t kMaxCachedPlans = 1024;
+
+void key_add(std::string& k, const void* p, size_t n) { k.append(static_cast<const char*>(p), n); }
+
+bool key_tensor(std::string& k, const symt_tensor* t, int G) {
+  if (!t) {
+    k.push_back('N');
+    return true;
+  }
+  if (t->nmodes < 1 || t->nmodes > SYMT_MAX_ORDER || !t->signs || !t->dims) return false;
+  const size_t n = static_cast<size_t>(t->nmodes);
+  const size_t ns = strnlen(t->signs, n + 1);
+  k.push_back('T');
+  key_add(k, &t->nmodes, sizeof t->nmodes);
+  key_add(k, &ns, sizeof ns);
+  k.append(t->signs, ns);
+  key_add(k, &t->charge, sizeof t->charge);
+  key_add(k, &t->dtype, sizeof t->dtype);
+  key_add(k, t->dims, n * sizeof(int64_t));
+  k.push_back(t->mode_charges ? 'C' : 'c');
+  if (t->mode_charges) key_add(k, t->mode_charges, n * static_cast<size_t>(G) * sizeof(int32_t));
+  k.push_back(t->sectors ? 'S' : 's');
+  if (t->sectors) key_add(k, t->sectors, n * sizeof(int32_t));
+  return true;
+}
+
+std::string plan_key(const char* einsum, const symt_group* group, const symt_tensor* u, const symt_tensor* v,
+                     const symt_tensor* w, int32_t compute) {
+  if (!einsum || !group || !u || !v || group->nfactors < 1 || group->nfactors > SYMT_MAX_FACTORS) return {};
+  int64_t G = 1;
+  for (int f = 0; f < group->nfactors; ++f) {
+    if (group->order[f] < 1) return {};
+    G *= group->order[f];
+    if (G > (1 << 20)) return {};
+  }
+  std::string k(einsum);
+  k.push_back('\0');
+  key_add(k, &group->nfactors, sizeof group->nfactors);
+  key_add(k, group->order, static_cast<size_t>(group->nfactors) * sizeof(int32_t));
+  key_add(k, &compute, sizeof compute);
+  if (!key_tensor(k, u, static_cast<int>(G)) || !key_tensor(k, v, static_cast<int>(G)) ||
+      !key_tensor(k, w, static_cast<int>(G)))
+    return {};
+  for (const char* var : {"SYMT_FUSED_V", "SYMT_GEMM_TILE", "SYMT_GEMM_SK"}) {
+    const char* val = std::getenv(var);
+    k.push_back('|');
+    if (val) k.append(val);
+  }
+  return k;
+}
+
 int plan_for(symt_ctx* ctx, const char* einsum, const symt_group* group, const symt_tensor* u,
              const symt_tensor* v, const symt_tensor* w, int32_t compute, Plan* p) {
+  std::string key;
+  if (ctx) {
+    key = plan_key(einsum, group, u, v, w, compute);
+    if (!key.empty()) {
+      std::lock_guard<std::mutex> lock(ctx->plan_mu);
+      auto it = ctx->plans.find(key);
+      if (it != ctx->plans.end()) {
+        *p = it->second;
+        p->U.data = u->data;
+        p->V.data = v->data;
+        p->W.data = w ? w->data : nullptr;
+        return SYMT_OK;
+      }
+    }
+  }
   std::string err;
   const int rc = symt::make_plan(einsum, group, u, v, w, compute, p, &err);
-  return rc ? ctx_fail(ctx, rc, err) : SYMT_OK;
+  if (rc) return ctx_fail(ctx, rc, err);
+  if (!key.empty()) {
+    std::lock_guard<std::mutex> lock(ctx->plan_mu);
+    if (ctx->plans.size() >= kMaxCachedPlans) ctx->plans.clear();
+    ctx->plans.emplace(std::move(key), *p);
+  }
+  return SYMT_OK;
 }
 
 int check_data(symt_ctx* ctx, const symt::OperandDesc& X, const char* name) {
@@ -325,10 +407,14 @@ int symtensor_contract(symt_ctx* ctx, const char* einsum, const symt_group* grou
   if (workspace_bytes < p.workspace || (p.workspace > 0 && !workspace))
     return ctx_fail(ctx, SYMT_EWORKSPACE, "workspace smaller than symtensor_workspace_size()");
   const size_t wb = static_cast<size_t>(p.W.elems) * elem_bytes(p.W.dtype);
-  if (overlaps(p.W.data, wb, p.U.data, static_cast<size_t>(p.U.elems) * elem_bytes(p.U.dtype)) ||
-      overlaps(p.W.data, wb, p.V.data, static_cast<size_t>(p.V.elems) * elem_bytes(p.V.dtype)) ||
+  const size_t ub = static_cast<size_t>(p.U.elems) * elem_bytes(p.U.dtype),
+               vb = static_cast<size_t>(p.V.elems) * elem_bytes(p.V.dtype);
+  if (overlaps(p.W.data, wb, p.U.data, ub) || overlaps(p.W.data, wb, p.V.data, vb) ||
       overlaps(p.W.data, wb, workspace, p.workspace))
     return ctx_fail(ctx, SYMT_EALIAS, "output overlaps an input or the workspace");
+  // the workspace is written (aligned forms, tables, pieces) before u and v are read
+  if (overlaps(p.U.data, ub, workspace, p.workspace) || overlaps(p.V.data, vb, workspace, p.workspace))
+    return ctx_fail(ctx, SYMT_EALIAS, "an input overlaps the workspace");
   if (p.compute == SYMT_COMPUTE_BF16X3 && p.gk % 8 != 0)
     return ctx_fail(ctx, SYMT_EUNSUPPORTED,
                     "split-bf16 product needs the aligned contracted extent to be a multiple of 8");

@@ -96,6 +96,10 @@ class SymTensor:
         return L.TensorDesc(self.signs, self.charge, self.dims, _DTYPE_CODE[d.dtype],
                             d.data_ptr() if d.numel() else None, self.mode_charges, self.sectors)
 
+    def key(self):
+        """Every descriptor field but the data pointer (a planning cache key)."""
+        return (self.signs, self.charge, self.dims, self.data.dtype, self.mode_charges, self.sectors)
+
     def table(self, m):
         G = group_size(self.group)
         return tuple(range(G)) if self.mode_charges is None else self.mode_charges[m]
@@ -116,14 +120,34 @@ def _code(compute: str, steps: bool) -> int:
     return L.COMPUTE[compute] | (L.SYMT_FLAG_STEPS if steps else 0)
 
 
+# Planned contractions: key -> (group, descriptors of u, v, w, plan info).  The
+# descriptors are reused with their data pointers replaced on every call, so a
+# contraction is planned once per key here (and once per key in the library's
+# context, which caches its own plans).
+_PLANS: dict = {}
+_MAX_PLANS = 1024
+
+
+def _planned(subscripts, u, v, w, code):
+    key = (subscripts, u.group, u.key(), v.key(), w.key() if w is not None else None, code)
+    ent = _PLANS.get(key)
+    if ent is None:
+        if u.group != v.group:
+            raise ValueError("operands use different groups")
+        g = L.make_group(u.group)
+        du, dv = u.desc(), v.desc()
+        dw = w.desc() if w is not None else None
+        info = L.plan(subscripts, g, du, dv, dw, code)
+        if len(_PLANS) >= _MAX_PLANS:
+            _PLANS.clear()
+        ent = _PLANS[key] = (g, du, dv, dw, info)
+    return ent
+
+
 def plan(subscripts: str, u: SymTensor, v: SymTensor, compute: str = "f64", w: SymTensor | None = None,
          steps: bool = False):
     """Shapes, flops, workspace and derived output rule of a contraction (host only)."""
-    if u.group != v.group:
-        raise ValueError("operands use different groups")
-    g = L.make_group(u.group)
-    return L.plan(subscripts, g, u.desc(), v.desc(), w.desc() if w is not None else None,
-                  _code(compute, steps))
+    return _planned(subscripts, u, v, w, _code(compute, steps))[4]
 
 
 def derived_charges(subscripts: str, u: SymTensor, v: SymTensor):
@@ -173,10 +197,10 @@ def contract_into(subscripts: str, u: SymTensor, v: SymTensor, w: SymTensor, com
     for t in (u.data, v.data, w.data):
         _check_dense(t)
     dev = u.data.device
-    g = L.make_group(u.group)
-    du, dv, dw = u.desc(), v.desc(), w.desc()
     code = _code(compute, steps)
-    info = L.plan(subscripts, g, du, dv, dw, code)
+    g, du, dv, dw, info = _planned(subscripts, u, v, w, code)
+    for d, t in ((du, u.data), (dv, v.data), (dw, w.data)):
+        d.set_data(t.data_ptr() if t.numel() else None)
     if workspace is None or workspace.numel() < info.workspace_bytes:
         workspace = torch.empty(max(1, info.workspace_bytes), dtype=torch.uint8, device=dev)
     ctx = L.context(dev.index or 0)

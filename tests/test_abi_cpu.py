@@ -515,3 +515,28 @@ def test_split_k_for_few_tiles_and_long_k(monkeypatch):
     monkeypatch.delenv("SYMT_GEMM_SK")
     # short K: nothing to split
     assert _gemm_ws(L.COMPUTE["f64"], 4, 57, 64, 57) == (0, 0)
+
+
+def test_outer_product_takes_the_sign_ratio_that_matches_the_given_output():
+    """v = 0: the rule derived with sigma = +1 describes the outer product's blocks too.
+
+    'a,k->ak' is the gradient dU = dW (x) V of 'ak,k->a' (u +- with Z 2, v + with
+    Z 1 over Z_5: sigma = -1, W = + with Z 3); dU must carry u's own rule.
+    'k,b->kb' is dV = U (x) dW of 'k,kb->b' (u + with Z 2, v -+ with Z 1).
+    """
+    g = 5
+    rc, info = _plan("a,k->ak", g, _desc("+", 3, (3,)), _desc("+", 1, (4,)))
+    assert rc == 0 and info.sigma == -1 and info.w_signs.decode() == "++" and info.w_charge == 4
+    rc, info = _plan("a,k->ak", g, _desc("+", 3, (3,)), _desc("+", 1, (4,)), _desc("+-", 2, (3, 4)))
+    assert rc == 0, L.last_error()
+    assert info.sigma == 1 and info.w_signs.decode() == "+-" and info.w_charge == 2
+    # the -1 rule, when given, keeps -1
+    rc, info = _plan("a,k->ak", g, _desc("+", 3, (3,)), _desc("+", 1, (4,)), _desc("++", 4, (3, 4)))
+    assert rc == 0 and info.sigma == -1
+    # dV of 'k,kb->b': forward W = + with Z 3; dV carries v's rule (-+, 1) or its flip (+-, 4)
+    for wsig, wz in (("-+", 1), ("+-", 4)):
+        rc, info = _plan("k,b->kb", g, _desc("+", 2, (4,)), _desc("+", 3, (3,)), _desc(wsig, wz, (4, 3)))
+        assert rc == 0 and info.sigma == 1, L.last_error()
+    # a rule neither ratio derives is still rejected
+    rc, _ = _plan("a,k->ak", g, _desc("+", 3, (3,)), _desc("+", 1, (4,)), _desc("+-", 3, (3, 4)))
+    assert rc == L.SYMT_ESYM

@@ -368,12 +368,43 @@ def test_error_paths_on_device(P):
     with pytest.raises(L.SymtError) as e:
         P.contract_into("abkl,klij->abij", u, v_bad, w)
     assert e.value.code == L.SYMT_ESYM
+    say("errors: an input inside the workspace")
+    info = P.plan("abkl,klij->abij", u, v, w=w)
+    ws = torch.zeros(info.workspace_bytes + 4096, dtype=torch.uint8, device=DEV)
+    inside = ws[: u.data.numel() * 8].view(torch.float64).view(u.data.shape)
+    inside.copy_(u.data)
+    for uu, vv in ((P.SymTensor(inside, "++--", 0, (4,)), v), (u, P.SymTensor(inside, "++--", 0, (4,)))):
+        with pytest.raises(L.SymtError) as e:
+            P.contract_into("abkl,klij->abij", uu, vv, w, workspace=ws)
+        assert e.value.code == L.SYMT_EALIAS
     # nothing was written by the failed calls
     before = w.data.clone()
     with pytest.raises(L.SymtError):
         P.contract_into("abkl,klij->abij", u, v_bad, w)
     torch.cuda.synchronize()
     assert torch.equal(before, w.data)
+
+
+def test_plan_cache_reuses_plans_with_new_data(P, monkeypatch):
+    """Calls with the same descriptors and new data (a cached plan) and with a
+    tuning variable changed (a new plan) all match the oracle."""
+    rng = np.random.default_rng(14)
+    g = O.Group(4)
+    sub = "abkl,klij->abij"
+    su = O.Sym.make("++--", 1, (3, 5, 4, 4), g)
+    sv = O.Sym.make("++--", 2, (4, 4, 2, 3), g)
+    for tile in ("", "128x48", ""):
+        if tile:
+            monkeypatch.setenv("SYMT_GEMM_TILE", tile)
+        else:
+            monkeypatch.delenv("SYMT_GEMM_TILE", raising=False)
+        for _ in range(2):
+            Ru, Rv = rng.standard_normal(su.reduced_shape()), rng.standard_normal(sv.reduced_shape())
+            u, v = _sym_tensor(P, Ru, su), _sym_tensor(P, Rv, sv)
+            w = P.output_like(sub, u, v)
+            P.contract_into(sub, u, v, w)
+            ref, _ = O.contract_blocks(sub, Ru, su, Rv, sv)
+            assert H.rel_err(H.to_np(w.data), ref) <= 1e-12, tile
 
 
 # ---------------------------------------------------------------------------

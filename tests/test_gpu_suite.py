@@ -2,8 +2,8 @@
 
 Small copies (every block dimension shrunk, the group kept) are compared with
 the loop-over-blocks oracle in three precisions; the full Table 2 sizes are
-contracted in f64 and checked on sampled outputs against the sampled
-brute-force oracle.  These cases exercise operands whose contracted modes lead
+contracted in f64, f32 and split-bf16 and checked on sampled outputs against
+the oracle's allowed-sector sampled form.  These cases exercise operands whose contracted modes lead
 (CC2, CC3), a single contracted mode (MPS), |G| up to 100 (MM_b), and very
 tall products (PEPS_a: M = 320000).
 """
@@ -89,35 +89,53 @@ def test_suite_small_vs_oracle(P, SG, label):
             assert np.all(np.abs(got - ref) <= (H.bound_factor(compute, k) + 2.1 * H.U32) * absref + 1e-300)
 
 
+def _full_sampled_three_precisions(P, SG, wl, label, count, seed_):
+    """A full-size contraction in f64, f32 and split-bf16, on `count` sampled outputs against
+    the allowed-sector sampled oracle (binary64 inputs, binary32-rounded inputs, |inputs|)."""
+    st = wl.steps[0]
+    su, sv = _sym(wl, "U"), _sym(wl, "V")
+    sw = O.output_symmetry(st.einsum, su, sv)
+    red, full = H.random_w_positions(sw, count, np.random.default_rng(seed_))
+    fu, fv = H.value_fn(wl, "U"), H.value_fn(wl, "V")
+    say(f"{label} full: oracle on {len(red)} sampled outputs")
+    ref = O.sample_contract_allowed(st.einsum, su, sv, fu, fv, full)
+    ref32 = O.sample_contract_allowed(st.einsum, su, sv, H.f32_value_fn(fu), H.f32_value_fn(fv), full)
+    absref = O.sample_contract_allowed(st.einsum, su, sv, H.value_fn(wl, "U", True), H.value_fn(wl, "V", True),
+                                       full)
+    k = H.contracted_extent(st.einsum, su)
+    idx = torch.as_tensor(np.asarray(red, dtype=np.int64))
+    for compute in ("f64", "f32", "bf16x3"):
+        dt = torch.float64 if compute == "f64" else torch.float32
+        u, v = _tensor(P, SG, wl, "U", dt), _tensor(P, SG, wl, "V", dt)
+        info = P.plan(st.einsum, u, v, compute)
+        if compute == "bf16x3" and info.k % 8:
+            say(f"{label} full {compute}: skipped (contracted extent {info.k} is not a multiple of 8)")
+            continue
+        w = P.output_like(st.einsum, u, v, dtype=torch.float64)
+        say(f"{label} full {compute}: batch {info.group_size} m {info.m} k {info.k} n {info.n}, "
+            f"{info.flops / 1e9:.1f} GFLOP, fused {info.fused}")
+        P.contract_into(st.einsum, u, v, w, compute)
+        torch.cuda.synchronize()
+        del u, v
+        got = H.to_np(w.data[tuple(idx.to(w.data.device).T)])
+        del w
+        torch.cuda.empty_cache()
+        bf = H.bound_factor(compute, k)
+        if compute == "f64":
+            err = H.rel_err(got, ref)
+            say(f"  {compute}: normwise relative error on samples {err:.3e}")
+            assert err <= 1e-12
+            assert np.all(np.abs(got - ref) <= bf * absref)
+        else:
+            say(f"  {compute}: normwise relative error on samples {H.rel_err(got, ref):.3e} (FP64 oracle)")
+            assert np.all(np.abs(got - ref32) <= bf * (1.0 + 2.0 * H.U32) * absref)
+            assert np.all(np.abs(got - ref) <= (bf + 2.1 * H.U32) * absref)
+
+
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("label", synth.configs.SUITE_LABELS)
 def test_suite_full_size_sampled(P, SG, label):
-    wl = synth.configs.paper_suite_case(label)
-    st = wl.steps[0]
-    su, sv = _sym(wl, "U"), _sym(wl, "V")
-    say(f"suite {label} full: generating inputs")
-    u, v = _tensor(P, SG, wl, "U"), _tensor(P, SG, wl, "V")
-    w = P.output_like(st.einsum, u, v)
-    info = P.plan(st.einsum, u, v, "f64", w)
-    say(f"suite {label} full: batch {info.group_size} m {info.m} k {info.k} n {info.n}, "
-        f"{info.flops / 1e12:.3f} TFLOP, fused {info.fused}")
-    P.contract_into(st.einsum, u, v, w, "f64")
-    torch.cuda.synchronize()
-    del u, v
-    torch.cuda.empty_cache()
-    sw = O.output_symmetry(st.einsum, su, sv)
-    red, full = H.random_w_positions(sw, 32, np.random.default_rng(7))
-    got = np.array([w.data[r].item() for r in red])
-    del w
-    torch.cuda.empty_cache()
-    say(f"suite {label} full: oracle on {len(red)} sampled outputs")
-    ref = O.sample_contract(st.einsum, su, sv, H.value_fn(wl, "U"), H.value_fn(wl, "V"), full)
-    absref = O.sample_contract(st.einsum, su, sv, H.value_fn(wl, "U", True), H.value_fn(wl, "V", True), full)
-    k = H.contracted_extent(st.einsum, su)
-    err = H.rel_err(got, ref)
-    say(f"  normwise relative error on samples {err:.3e}")
-    assert err <= 1e-12
-    assert np.all(np.abs(got - ref) <= H.bound_factor("f64", k) * absref)
+    _full_sampled_three_precisions(P, SG, synth.configs.paper_suite_case(label), f"suite {label}", 32, 7)
 
 
 # ---------------------------------------------------------------------------
@@ -164,25 +182,7 @@ def test_g_sweep_small_vs_oracle(P, SG, family):
 
 
 def _check_full_sampled(P, SG, wl, label):
-    st = wl.steps[0]
-    su, sv = _sym(wl, "U"), _sym(wl, "V")
-    u, v = _tensor(P, SG, wl, "U"), _tensor(P, SG, wl, "V")
-    w = P.output_like(st.einsum, u, v)
-    info = P.plan(st.einsum, u, v, "f64", w)
-    say(f"{label} full: batch {info.group_size} m {info.m} k {info.k} n {info.n}, {info.flops / 1e9:.1f} GFLOP")
-    P.contract_into(st.einsum, u, v, w, "f64")
-    torch.cuda.synchronize()
-    del u, v
-    torch.cuda.empty_cache()
-    sw = O.output_symmetry(st.einsum, su, sv)
-    red, full = H.random_w_positions(sw, 24, np.random.default_rng(11))
-    got = np.array([w.data[r].item() for r in red])
-    del w
-    torch.cuda.empty_cache()
-    ref = O.sample_contract(st.einsum, su, sv, H.value_fn(wl, "U"), H.value_fn(wl, "V"), full)
-    absref = O.sample_contract(st.einsum, su, sv, H.value_fn(wl, "U", True), H.value_fn(wl, "V", True), full)
-    assert H.rel_err(got, ref) <= 1e-12
-    assert np.all(np.abs(got - ref) <= H.bound_factor("f64", H.contracted_extent(st.einsum, su)) * absref)
+    _full_sampled_three_precisions(P, SG, wl, label, 24, 11)
 
 
 @pytest.mark.timeout(600)
