@@ -25,6 +25,7 @@
 
 #include "bf16_split.hpp"
 #include "plan.hpp"
+#include "sk_index.hpp"
 
 namespace symt {
 
@@ -555,15 +556,7 @@ __device__ __forceinline__ void store_piece(T* __restrict__ piece, const Acc (&a
       for (int r = 0; r < 4; ++r) pw[((i * TN + j) * 4 + r) * 64] = acc[i][j][r];
 }
 
-// Stream-K partition.  Tiles come in groups of `ts` (1, or the tiles_n tiles of
-// one (q, M-panel), which read the same A rows).  A team of ts workgroups, one
-// per tile of a group, owns the K-iterations [bound(t), bound(t+1)) of the
-// concatenation of all groups (group-major, nk iterations each): its members
-// walk the same groups and K-steps side by side, so each A panel is fetched
-// into L2 once per team rather than once per tile.
-__device__ __forceinline__ int64_t sk_bound(int64_t t, int64_t total, int nteam) {
-  return t * total / nteam;
-}
+// Stream-K partition: sk_index.hpp.
 
 // Sector product on global-to-LDS tiles.  SK = false: one workgroup per tile
 // (XCD-aware order).  SK = true: gridDim.x = 8 * teams_x * ts persistent
@@ -600,17 +593,12 @@ __global__ __launch_bounds__(64 * WM * WN, (kDmaWavesPerSimd<BM, BN, S>)) void k
                                                       rb, cb, ldb, smem, acc);
     store_tile<T, BM, BN, WM, WN, TM, TN, FC>(C, M, N, q, tm * BM, tn * BN, rc, cc, acc);
   } else {
-    const int b = static_cast<int>(blockIdx.x);
-    const int teams_x = static_cast<int>(gridDim.x) / (8 * ts);
-    const int l = b / 8;                                   // slot on this XCD
-    const int team = (b % 8) * teams_x + l / ts;
-    const int member = l % ts;
-    const int nteam = 8 * teams_x;
+    const SkSlot sl = sk_slot(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x), ts);
+    const int team = sl.team, member = sl.member, nteam = sl.nteam;
     const int64_t total = ntiles / ts * nk;
     int64_t it = sk_bound(team, total, nteam);
     const int64_t end = sk_bound(team + 1, total, nteam);
     const int64_t first = it / nk;
-    T* my_part = part + 2 * static_cast<int64_t>(team * ts + member) * (BM * BN);
     while (it < end) {
       const int64_t grp = it / nk;
       const int kt0 = static_cast<int>(it - grp * nk);
@@ -630,7 +618,7 @@ __global__ __launch_bounds__(64 * WM * WN, (kDmaWavesPerSimd<BM, BN, S>)) void k
       if (kt0 == 0 && kt1 == nk)
         store_tile<T, BM, BN, WM, WN, TM, TN, FC>(C, M, N, q, tm * BM, tn * BN, rc, cc, acc);
       else
-        store_piece<TM, TN>(my_part + (grp == first ? 0 : BM * BN), acc);
+        store_piece<TM, TN>(part + sk_piece(team, member, ts, grp, first) * (BM * BN), acc);
       it += kt1 - kt0;
     }
   }
@@ -651,7 +639,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_sk_fixup(
   const int64_t total = ntiles / ts * nk;
   const int64_t x0 = grp * nk, x1 = x0 + nk;
   // last team whose share starts at or before x0 (its share is not empty)
-  int64_t t = ((x0 + 1) * nteam - 1) / total;
+  int64_t t = sk_first_team(x0, total, nteam);
   if (sk_bound(t + 1, total, nteam) >= x1) return;
   Acc acc[TM][TN];
 #pragma unroll
@@ -663,7 +651,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_sk_fixup(
     const int64_t b0 = sk_bound(t, total, nteam), b1 = sk_bound(t + 1, total, nteam);
     if (b0 >= x1) break;
     if (b1 == b0) continue;
-    const T* pw = part + (2 * (t * ts + member) + (b0 / nk == grp ? 0 : 1)) * (BM * BN) +
+    const T* pw = part + sk_piece(static_cast<int>(t), member, ts, grp, b0 / nk) * (BM * BN) +
                   (threadIdx.x >> 6) * (TM * TN * 4 * 64) + lane;
 #pragma unroll
     for (int i = 0; i < TM; ++i)
@@ -1252,16 +1240,12 @@ hipError_t launch_dma(int64_t batch, int M, int N, int K, const void* A, const v
       occupancy[mode].store(occ, std::memory_order_relaxed);
     }
     // no more persistent workgroups than resident ones, nor than the pieces buffer holds
-    const int64_t fit = static_cast<int64_t>(part_bytes / (2 * static_cast<size_t>(BM) * BN * sizeof(T)));
-    const int64_t slots = std::min<int64_t>({kSkSlots, static_cast<int64_t>(device_cus()) * occ, fit});
-    // Teams of tiles_n siblings when 8 XCDs hold at least one team each.
-    const int64_t per_xcd = slots / 8;
-    ts = (tiles_n <= per_xcd) ? tiles_n : 1;
-    int64_t teams_x = per_xcd / ts;
-    const int64_t by_work = (ntiles / ts) * nk / kSkMinIters;        // teams with >= kSkMinIters each
-    teams_x = std::min<int64_t>(teams_x, by_work / 8);
-    P = static_cast<int>(8 * teams_x * ts);
-    if (P < 8 || 2 * static_cast<size_t>(P) * BM * BN * sizeof(T) > part_bytes) P = 0;
+    const SkLaunch sl = sk_launch(ntiles, tiles_n, nk,
+                                  std::min<int64_t>(kSkSlots, static_cast<int64_t>(device_cus()) * occ),
+                                  static_cast<int64_t>(part_bytes / sizeof(T)), static_cast<int64_t>(BM) * BN,
+                                  kSkMinIters);
+    P = sl.P;
+    ts = sl.ts;
   }
   T* pt = static_cast<T*>(part);
   if (P > 0) {

@@ -1,0 +1,727 @@
+// Host replay of the library's index arithmetic: no GPU, built with g++ and
+// AddressSanitizer + UndefinedBehaviorSanitizer by tests/test_host_replay.py.
+//
+// It plans random contractions with the library's own planner (plan.cpp) and,
+// with the index functions the kernels share (xform_index.hpp, sk_index.hpp),
+// walks every loop of the launches the library would make, checking:
+//  * transforms (copy and tiled-transpose modes, every precision, whole forms
+//    and workspace slices): every read and write in bounds, vector accesses
+//    aligned and inside their run, every destination element written exactly
+//    once and every live source element read exactly once (a bijection);
+//  * offset tables of the fused product: U, V and W tables map (Q, row, col)
+//    one-to-one onto the stored elements, and the register tiles' load
+//    addresses (row offset + one column offset per K-step) equal the table
+//    offsets of every element they load, for every K-step layout the planner
+//    allows (plain steps, steps run by run, K-major A, V in place);
+//  * stream-K: every (tile, K-iteration) is multiplied exactly once, pieces
+//    land inside the buffer, each piece slot is written once, and the fixup
+//    sums exactly the pieces of its tile in increasing K order; split K covers
+//    each tile's K-steps once with partial tiles inside the buffer.
+// Exit status 0 when every check passes; the first failures are printed.
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "plan.hpp"
+#include "sk_index.hpp"
+#include "symtensor.h"
+#include "xform_index.hpp"
+
+using namespace symt;
+
+namespace {
+
+int g_failures = 0;
+int64_t g_checks = 0;
+std::string g_case;
+
+void fail(const char* what, long long a = 0, long long b = 0) {
+  if (++g_failures <= 20) std::fprintf(stderr, "FAIL [%s]: %s (%lld, %lld)\n", g_case.c_str(), what, a, b);
+}
+#define CHECK(cond, what, a, b) \
+  do {                          \
+    ++g_checks;                 \
+    if (!(cond)) fail(what, (long long)(a), (long long)(b)); \
+  } while (0)
+
+struct Rng {
+  uint64_t s;
+  uint64_t next() {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+  int below(int n) { return static_cast<int>(next() % static_cast<uint64_t>(n)); }
+  bool coin() { return next() & 1; }
+};
+
+// One operand descriptor with the storage it points to.
+struct Desc {
+  std::string signs;
+  int32_t charge = 0;
+  std::vector<int64_t> dims;
+  std::vector<int32_t> tables;   // empty: identity
+  std::vector<int32_t> sectors;  // empty: |G| each
+  int32_t dtype = SYMT_F64;
+  symt_tensor t{};
+  void bind() {
+    t.nmodes = static_cast<int32_t>(signs.size());
+    t.signs = signs.c_str();
+    t.charge = charge;
+    t.dims = dims.data();
+    t.dtype = dtype;
+    t.data = nullptr;
+    t.mode_charges = tables.empty() ? nullptr : tables.data();
+    t.sectors = sectors.empty() ? nullptr : sectors.data();
+  }
+};
+
+struct Case {
+  std::string einsum;
+  symt_group g{};
+  Desc u, v, w;
+  int32_t compute = 0;
+};
+
+int group_size(const symt_group& g) {
+  int n = 1;
+  for (int f = 0; f < g.nfactors; ++f) n *= g.order[f];
+  return n;
+}
+
+// ---------------------------------------------------------------------------
+// Transforms
+// ---------------------------------------------------------------------------
+// Walks every access of one transform launch (k_xform_copy / k_xform_transpose):
+// src_n / dst_n are the elements of the source and destination (per plane for
+// a split destination).  Counts land in `written` (2 dst_n with planes) and `read`.
+void replay_xform(const XformParams& x, int64_t src_n, int64_t dst_n, bool dst_split, std::vector<uint8_t>& written,
+                  std::vector<uint8_t>& read) {
+  const int64_t nwg = x.nblocks * x.tiles_per_block;
+  auto write = [&](int64_t d) {
+    CHECK(d >= 0 && d < dst_n, "destination out of bounds", d, dst_n);
+    if (d < 0 || d >= dst_n) return;
+    CHECK(written[d] == 0, "destination written twice", d, 0);
+    written[d]++;
+    if (dst_split) {
+      const int64_t e = d + x.plane;
+      CHECK(e >= dst_n && e < 2 * dst_n, "lo plane out of bounds", e, dst_n);
+      if (e >= 0 && e < 2 * dst_n) written[e]++;
+    }
+  };
+  auto readsrc = [&](int64_t s) {
+    CHECK(s >= 0 && s < src_n, "source out of bounds", s, src_n);
+    if (s >= 0 && s < src_n) {
+      CHECK(read[s] == 0, "source element read twice", s, 0);
+      read[s]++;
+    }
+  };
+  for (int64_t wg = 0; wg < nwg; ++wg) {
+    const int64_t blk = wg / x.tiles_per_block;
+    int64_t sb = 0, ab = 0;
+    const bool live = block_bases(x, blk, sb, ab);
+    if (!live && !x.to_aligned) continue;
+    const int64_t src_base = x.to_aligned ? sb : ab;
+    const int64_t dst_base = x.to_aligned ? ab : sb;
+    if (x.mode == 0) {
+      const int64_t tile = wg - blk * x.tiles_per_block;
+      const int64_t row_tile = tile / x.run_tiles;
+      const int64_t c_begin = (tile - row_tile * x.run_tiles) * x.run_chunk;
+      const int64_t c_end = std::min(c_begin + x.run_chunk, x.run_len);
+      const int64_t r0 = row_tile * x.rows_per_tile;
+      const int nr = static_cast<int>(std::min<int64_t>(x.rows - r0, x.rows_per_tile));
+      CHECK(nr <= 256, "rows per copy tile above the LDS row table", nr, 256);
+      const int V = x.vec;
+      CHECK(c_begin % V == 0, "vector chunk start", c_begin, V);
+      for (int r = 0; r < nr; ++r) {
+        int64_t rem = r0 + r, so = 0, dof = 0;
+        for (int i = x.nbatch - 1; i >= 0; --i) {
+          const int64_t qd = rem / x.bsize[i];
+          const int64_t d = rem - qd * x.bsize[i];
+          rem = qd;
+          so += d * x.bss[i];
+          dof += d * x.bds[i];
+        }
+        const int64_t s0 = src_base + so, d0 = dst_base + dof;
+        for (int64_t c = c_begin; c < c_end; c += V) {
+          if (V > 1) {
+            CHECK(c + V <= c_end, "vector past its run", c, c_end);
+            CHECK((s0 + c) % V == 0 && (d0 + c) % V == 0, "vector access misaligned", s0 + c, d0 + c);
+            CHECK(x.run_ss == 1 && x.run_ds == 1, "vector along a strided run", x.run_ss, x.run_ds);
+          }
+          for (int j = 0; j < V; ++j) {
+            if (live) readsrc(s0 + (c + j) * x.run_ss);
+            write(d0 + (c + j) * x.run_ds);
+          }
+        }
+      }
+    } else {
+      int64_t rem = wg - blk * x.tiles_per_block;
+      const int64_t tb = rem % x.tiles_t;
+      rem /= x.tiles_t;
+      const int64_t ta = rem % x.tiles_run;
+      int64_t row = rem / x.tiles_run;
+      int64_t so = src_base, dof = dst_base;
+      for (int i = x.nbatch - 1; i >= 0; --i) {
+        const int64_t qd = row / x.bsize[i];
+        const int64_t d = row - qd * x.bsize[i];
+        row = qd;
+        so += d * x.bss[i];
+        dof += d * x.bds[i];
+      }
+      const int64_t a0 = ta * 64, b0 = tb * 64;
+      const int na = static_cast<int>(std::min<int64_t>(x.run_len - a0, 64));
+      const int nb = static_cast<int>(std::min<int64_t>(x.t_len - b0, 64));
+      auto offs = [](int64_t i, int n, const int64_t* size, const int64_t* ss, const int64_t* ds, int64_t& s,
+                     int64_t& d) {
+        s = 0;
+        d = 0;
+        for (int k = 0; k < n; ++k) {
+          const int64_t q = i / size[k];
+          const int64_t c = i - q * size[k];
+          i = q;
+          s += c * ss[k];
+          d += c * ds[k];
+        }
+      };
+      for (int ia = 0; ia < na; ++ia) {
+        int64_t as, ad;
+        offs(a0 + ia, x.na, x.asize, x.ass, x.ads, as, ad);
+        for (int ib = 0; ib < nb; ++ib) {
+          int64_t bs, bd;
+          offs(b0 + ib, x.nb, x.tsize, x.tss, x.tds, bs, bd);
+          if (live) readsrc(so + as + bs);
+          write(dof + ad + bd);
+        }
+      }
+    }
+  }
+}
+
+// Aligned matrix of operand 0/1/2 in reals: rows and columns per Q slice.
+void aligned_dims(const Plan& p, int op, int64_t& rows, int64_t& cols) {
+  const int64_t rm = p.cplx && op == 1 ? 2 : 1;   // complex V: two real rows per complex row
+  if (op == 0) { rows = p.M; cols = p.gk; }
+  else if (op == 1) { rows = p.Kd * rm; cols = p.gn; }
+  else { rows = p.M; cols = p.gn; }
+}
+
+// k_cplx_rows over a complex V_al of `nsl` slices: row 2r + 1 from row 2r.
+// Outside [lo, hi) (slices a standalone transform cleared instead of moving)
+// it rewrites zeros: only its bounds are checked there.
+void replay_cplx_rows(const Plan& p, int64_t nsl, int64_t al_n, std::vector<uint8_t>& written, int64_t lo,
+                      int64_t hi) {
+  const int64_t pairs = p.N;
+  for (int64_t i = 0; i < nsl * p.Kd * pairs; ++i) {
+    const int64_t c = i % pairs, r = i / pairs;
+    const int64_t even = (2 * r) * (2 * pairs) + 2 * c;
+    CHECK(even >= 0 && even + 2 * pairs + 1 < al_n, "complex odd row out of bounds", even, al_n);
+    if (even < 0 || even + 2 * pairs + 1 >= al_n) continue;
+    if (even < lo || even >= hi) continue;
+    CHECK(written[even] == 1 && written[even + 1] == 1, "complex odd row from an unwritten even row", even, 0);
+    for (int64_t e : {even + 2 * pairs, even + 2 * pairs + 1}) {
+      CHECK(written[e] == 0, "complex odd row written twice", e, 0);
+      written[e]++;
+    }
+  }
+}
+
+void check_transforms(const Plan& p) {
+  const int G = p.g.size;
+  const int kind = p.compute == SYMT_COMPUTE_F64 ? 0 : p.compute == SYMT_COMPUTE_F32 ? 1 : 2;
+  const int al_bytes = kind == 0 ? 8 : kind == 1 ? 4 : 2;
+  for (int op = 0; op < 3; ++op) {
+    const OperandDesc& X = op == 0 ? p.U : op == 1 ? p.V : p.W;
+    if (X.elems == 0) continue;
+    const int64_t reals = X.elems * (p.cplx ? 2 : 1);
+    int64_t rows, cols;
+    aligned_dims(p, op, rows, cols);
+    const int64_t per_slice = rows * cols;
+    for (int slice_only = 0; slice_only < 2; ++slice_only) {
+      // standalone transforms take identity tables only (their aligned layouts are by label)
+      if (!slice_only && p.charges) continue;
+      const bool to_al = op != 2;
+      const bool split = to_al && kind == 2;
+      const int in_bytes = to_al ? real_bytes(X.dtype) : (p.compute == SYMT_COMPUTE_F32 ? 4 : 8);
+      const int out_bytes = to_al ? al_bytes : real_bytes(X.dtype);
+      const XformParams x0 = make_xform(p, op, to_al, in_bytes, out_bytes, split, slice_only != 0);
+      for (int scalar = 0; scalar < 2; ++scalar) {
+        XformParams x = x0;
+        if (scalar) {
+          if (x.vec == 1) continue;
+          x.vec = 1;     // operands that are not 16-byte aligned
+        }
+        const int64_t nsl = slice_only ? p.nq : G;
+        const int64_t al_n = nsl * per_slice;
+        if (to_al) {
+          std::vector<uint8_t> written(static_cast<size_t>(al_n) * (split ? 2 : 1), 0);
+          std::vector<uint8_t> read(static_cast<size_t>(reals), 0);
+          replay_xform(x, reals, al_n, split, written, read);
+          // every element of the moved slices written once (dead aligned blocks as
+          // zeros); with Q pinned the standalone transform moves one slice (the
+          // others are cleared by a separate launch)
+          int64_t lo = 0, hi = al_n;
+          if (!slice_only && pinned_form(p, op)) {
+            lo = static_cast<int64_t>(p.q_pin) * per_slice;
+            hi = lo + per_slice;
+          }
+          if (p.cplx && op == 1) replay_cplx_rows(p, nsl, al_n, written, lo, hi);
+          for (int64_t d = 0; d < al_n; ++d) {
+            const uint8_t want = d >= lo && d < hi ? 1 : 0;
+            CHECK(written[d] == want, "aligned element not written exactly once", d, written[d]);
+            if (split) CHECK(written[d + al_n] == want, "lo plane element not written exactly once", d, written[d + al_n]);
+          }
+        } else {
+          std::vector<uint8_t> written(static_cast<size_t>(reals), 0);
+          std::vector<uint8_t> read(static_cast<size_t>(al_n), 0);
+          replay_xform(x, al_n, reals, false, written, read);
+          // with every Q slice live and no subgroup mode, W is covered exactly
+          if (p.nq == G && !p.subgroups)
+            for (int64_t d = 0; d < reals; ++d) CHECK(written[d] == 1, "W element not written exactly once", d, written[d]);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Offset tables and the fused product's load addresses
+// ---------------------------------------------------------------------------
+std::vector<int64_t> table(const OffsetParams& o, int G) {
+  std::vector<int64_t> t(static_cast<size_t>(G * o.count));
+  for (int q = 0; q < G; ++q)
+    for (int64_t i = 0; i < o.count; ++i) t[q * o.count + i] = table_entry(o, q, i);
+  return t;
+}
+
+void check_bijection(const std::vector<int64_t>& R, const std::vector<int64_t>& C, int G, int64_t rows,
+                     int64_t cols, int64_t reals, const char* what) {
+  std::vector<uint8_t> hit(static_cast<size_t>(reals), 0);
+  for (int q = 0; q < G; ++q)
+    for (int64_t r = 0; r < rows; ++r)
+      for (int64_t c = 0; c < cols; ++c) {
+        const int64_t off = R[q * rows + r] + C[q * cols + c];
+        CHECK(off >= 0 && off < reals, what, off, reals);
+        if (off >= 0 && off < reals) hit[off]++;
+      }
+  for (int64_t e = 0; e < reals; ++e) CHECK(hit[e] == 1, what, e, hit[e]);
+}
+
+void check_fused(const Plan& p) {
+  if (!(p.fused || p.fused_ua)) return;
+  const int G = p.g.size;
+  const int cm = p.cplx ? 2 : 1;
+  std::vector<int64_t> ra, ca, rc, cc, rb, cb;
+  if (p.fused_ua) {
+    ra = table(affine_offsets(p, p.M, p.M * p.gk, p.gk), G);
+    ca = table(affine_offsets(p, p.gk, 0, 1), G);
+    check_bijection(ra, ca, G, p.M, p.gk, G * p.M * p.gk, "U_al affine tables");
+  } else {
+    ra = table(make_offsets(p, 0, true), G);
+    ca = table(make_offsets(p, 0, false), G);
+    check_bijection(ra, ca, G, p.M, p.gk, p.U.elems * cm, "U tables not a bijection onto U");
+  }
+  rc = table(make_offsets(p, 2, true), G);
+  cc = table(make_offsets(p, 2, false), G);
+  check_bijection(rc, cc, G, p.M, p.gn, p.W.elems * cm, "W tables not a bijection onto W");
+  if (p.fused_b) {
+    rb = table(make_offsets(p, 1, true), G);
+    cb = table(make_offsets(p, 1, false), G);
+    check_bijection(rb, cb, G, p.gk, p.gn, p.V.elems, "V tables not a bijection onto V");
+  }
+  if (p.compute == SYMT_COMPUTE_BF16X3) {
+    // register tiles split U in registers along 32-deep K-steps of one run
+    if (p.fused)
+      for (int q = 0; q < G; ++q)
+        for (int64_t k = 0; k < p.gk; ++k)
+          CHECK(ca[q * p.gk + k] == ca[q * p.gk + (k / 32) * 32] + k % 32, "split-bf16 A step not contiguous", k, q);
+    return;
+  }
+  // Register tiles (BK = 16): K-step kt starts at k0 with kv valid rows.
+  const int BK = kFpBK;
+  const int spr = p.krun > 0 ? (p.krun + BK - 1) / BK : 0;
+  const int64_t nk_all = p.krun > 0 ? p.gk / p.krun * spr : (p.gk + BK - 1) / BK;
+  const GemmChoice gc = choose_fp_gemm(G, p.M, p.gn, p.gk, p.compute == SYMT_COMPUTE_F64 ? 8 : 4, true);
+  for (int q = 0; q < G; ++q)
+    for (int64_t kt = 0; kt < nk_all; ++kt) {
+      int64_t k0, kv;
+      if (p.krun > 0) {
+        const int64_t run = kt / spr, st = kt - run * spr;
+        k0 = run * p.krun + st * BK;
+        kv = std::min<int64_t>(BK, p.krun - st * BK);
+      } else {
+        k0 = kt * BK;
+        kv = std::min<int64_t>(BK, p.gk - k0);
+      }
+      CHECK(k0 + kv <= p.gk, "K-step past K", k0 + kv, p.gk);
+      for (int64_t c = 0; c < kv; ++c) {
+        const int64_t k = k0 + c;
+        if (!p.a_trans)   // A row m of the step: ra(m) + ca(k0) + c
+          CHECK(ca[q * p.gk + k0] + c == ca[q * p.gk + k], "A K-step not contiguous in U", k, q);
+        if (p.fused_b)    // B row k of the step: rb(k0) + c * ldb
+          CHECK(rb[q * p.gk + k0] + c * p.ldb == rb[q * p.gk + k], "B K-step not affine in V", k, q);
+      }
+    }
+  if (gc.dma && !p.a_trans && p.krun == 0) {
+    // global-to-LDS tiles: one 128-byte A row per K-step
+    const int64_t bkd = 128 / (p.compute == SYMT_COMPUTE_F64 ? 8 : 4);
+    CHECK(p.gk % bkd == 0, "DMA tile with a partial K-step", p.gk, bkd);
+    for (int q = 0; q < G; ++q)
+      for (int64_t k = 0; k < p.gk; ++k) {
+        CHECK(ca[q * p.gk + k] == ca[q * p.gk + (k / bkd) * bkd] + k % bkd, "DMA A row not contiguous", k, q);
+        if (p.fused_b)
+          CHECK(rb[q * p.gk + k] == rb[q * p.gk + (k / bkd) * bkd] + (k % bkd) * p.ldb, "DMA B rows not affine", k, q);
+      }
+  }
+  // vector loads: 16-byte chunks contiguous and aligned (16-byte aligned operands)
+  const int vw = p.compute == SYMT_COMPUTE_F64 ? 2 : 4;
+  const int64_t run = p.fused_ua ? p.gk : cm * p.nK;
+  const bool avec = (p.compute == SYMT_COMPUTE_BF16X3 || run % vw == 0);
+  if (avec && !p.a_trans && p.krun == 0)
+    for (int q = 0; q < G; ++q)
+      for (int64_t m = 0; m < p.M; ++m)
+        for (int64_t k = 0; k < p.gk; k += vw)
+          CHECK((ra[q * p.M + m] + ca[q * p.gk + k]) % vw == 0, "vector A load misaligned", m, k);
+  if (p.a_trans && p.a_chunks)
+    for (int q = 0; q < G; ++q)
+      for (int64_t m = 0; m < p.M; m += vw) {
+        for (int j = 1; j < vw && m + j < p.M; ++j)
+          CHECK(ra[q * p.M + m + j] == ra[q * p.M + m] + j, "K-major A chunk not contiguous", m, j);
+        CHECK(ra[q * p.M + m] % vw == 0, "K-major A chunk misaligned", m, q);
+      }
+  if (p.fused_b && gc.dma && p.krun == 0)
+    CHECK(p.fused_b_chunks, "V in place on a DMA tile without whole column chunks", p.gn, p.ldb);
+  if (p.fused_b && p.fused_b_chunks)
+    for (int q = 0; q < G; ++q)
+      for (int64_t n = 0; n < p.gn; n += vw) {
+        for (int j = 1; j < vw && n + j < p.gn; ++j)
+          CHECK(cb[q * p.gn + n + j] == cb[q * p.gn + n] + j, "B column chunk not contiguous", n, j);
+        for (int64_t k = 0; k < p.gk; ++k)
+          CHECK((rb[q * p.gk + k] + cb[q * p.gn + n]) % vw == 0, "vector B load misaligned", k, n);
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Stream-K and split K
+// ---------------------------------------------------------------------------
+void check_stream_k(int64_t batch, int tiles_m, int tiles_n, int nk, int64_t resident, int64_t part_elems,
+                    int64_t tile_elems) {
+  const int64_t ntiles = batch * tiles_m * tiles_n;
+  const SkLaunch sl = sk_launch(ntiles, tiles_n, nk, resident, part_elems, tile_elems, kSkMinIters);
+  if (sl.P == 0) return;
+  const int P = sl.P, ts = sl.ts;
+  CHECK(P % (8 * ts) == 0, "persistent workgroups not whole teams on 8 XCDs", P, ts);
+  CHECK(P <= resident, "more persistent workgroups than resident slots", P, resident);
+  CHECK(2 * static_cast<int64_t>(P) * tile_elems <= part_elems, "pieces buffer too small", P, part_elems);
+  std::vector<uint8_t> cover(static_cast<size_t>(ntiles * nk), 0);
+  std::vector<uint8_t> whole(static_cast<size_t>(ntiles), 0);
+  std::map<int64_t, std::vector<std::pair<int, int64_t>>> pieces;   // tile -> (kt0, slot)
+  std::vector<uint8_t> slot_used(static_cast<size_t>(2 * P), 0);
+  for (int b = 0; b < P; ++b) {
+    const SkSlot s = sk_slot(b, P, ts);
+    CHECK(s.member >= 0 && s.member < ts && s.team >= 0 && s.team < s.nteam, "slot decode", s.team, s.member);
+    const int64_t total = ntiles / ts * nk;
+    int64_t it = sk_bound(s.team, total, s.nteam);
+    const int64_t end = sk_bound(s.team + 1, total, s.nteam);
+    const int64_t first = it / nk;
+    while (it < end) {
+      const int64_t grp = it / nk;
+      const int kt0 = static_cast<int>(it - grp * nk);
+      const int kt1 = static_cast<int>(std::min<int64_t>(nk, kt0 + (end - it)));
+      const int64_t tile = grp * ts + s.member;
+      CHECK(tile < ntiles, "tile past the launch", tile, ntiles);
+      for (int k = kt0; k < kt1; ++k) {
+        CHECK(cover[tile * nk + k] == 0, "K-iteration multiplied twice", tile, k);
+        cover[tile * nk + k]++;
+      }
+      if (kt0 == 0 && kt1 == nk) {
+        whole[tile]++;
+      } else {
+        const int64_t slot = sk_piece(s.team, s.member, ts, grp, first);
+        CHECK(slot >= 0 && slot < 2 * P, "piece slot out of range", slot, 2 * P);
+        CHECK((slot + 1) * tile_elems <= part_elems, "piece past the buffer", slot, part_elems);
+        if (slot >= 0 && slot < 2 * P) {
+          CHECK(slot_used[slot] == 0, "piece slot written twice", slot, tile);
+          slot_used[slot]++;
+        }
+        pieces[tile].push_back({kt0, slot});
+      }
+      it += kt1 - kt0;
+    }
+  }
+  for (int64_t i = 0; i < ntiles * nk; ++i) CHECK(cover[i] == 1, "K-iteration not multiplied", i / nk, i % nk);
+  // the fixup, tile by tile
+  const int nteam = P / ts;
+  const int64_t total = ntiles / ts * nk;
+  for (int64_t tile = 0; tile < ntiles; ++tile) {
+    const int64_t grp = tile / ts;
+    const int member = static_cast<int>(tile - grp * ts);
+    const int64_t x0 = grp * nk, x1 = x0 + nk;
+    int64_t t = sk_first_team(x0, total, nteam);
+    CHECK(sk_bound(t, total, nteam) <= x0 && (t + 1 >= nteam || sk_bound(t + 1, total, nteam) > x0),
+          "fixup's first team", t, x0);
+    if (sk_bound(t + 1, total, nteam) >= x1) {
+      CHECK(whole[tile] == 1 && pieces[tile].empty(), "uncut tile not stored whole once", tile, whole[tile]);
+      continue;
+    }
+    CHECK(whole[tile] == 0, "cut tile also stored whole", tile, 0);
+    std::vector<int64_t> got;
+    int64_t prev_b0 = -1;
+    for (; t < nteam; ++t) {
+      const int64_t b0 = sk_bound(t, total, nteam), b1 = sk_bound(t + 1, total, nteam);
+      if (b0 >= x1) break;
+      if (b1 == b0) continue;
+      CHECK(b0 > prev_b0, "fixup not in increasing K order", b0, prev_b0);
+      prev_b0 = b0;
+      got.push_back(sk_piece(static_cast<int>(t), member, ts, grp, b0 / nk));
+    }
+    std::vector<int64_t> want;
+    auto pc = pieces[tile];
+    std::sort(pc.begin(), pc.end());
+    for (auto& pr : pc) want.push_back(pr.second);
+    CHECK(got == want, "fixup does not read exactly its tile's pieces", tile, static_cast<int64_t>(got.size()));
+  }
+}
+
+void check_split_k(int64_t ntiles, int splits, int nk_all, int64_t part_elems, int64_t tile_elems) {
+  if (splits <= 1) return;
+  CHECK(ntiles * splits * tile_elems <= part_elems, "split partial tiles past the buffer", ntiles * splits, part_elems);
+  const int per = (nk_all + splits - 1) / splits;
+  std::vector<uint8_t> cover(static_cast<size_t>(nk_all), 0);
+  for (int sp = 0; sp < splits; ++sp) {
+    const int kt0 = std::min(nk_all, sp * per), kt1 = std::min(nk_all, kt0 + per);
+    for (int k = kt0; k < kt1; ++k) cover[k]++;
+  }
+  for (int k = 0; k < nk_all; ++k) CHECK(cover[k] == 1, "split K-step not covered once", k, cover[k]);
+}
+
+// ---------------------------------------------------------------------------
+// Random contractions
+// ---------------------------------------------------------------------------
+bool random_case(Rng& rng, Case& c, bool allow_tables, bool allow_sub, bool allow_cplx, int dmax) {
+  static const int orders[][3] = {{1, 2, 0}, {1, 3, 0}, {1, 4, 0}, {1, 5, 0}, {2, 2, 2}, {2, 2, 3}, {1, 8, 0},
+                                  {1, 6, 0}};
+  const auto& og = orders[rng.below(8)];
+  c.g = symt_group{};
+  c.g.nfactors = og[0];
+  c.g.order[0] = og[1];
+  if (og[0] == 2) c.g.order[1] = og[2];
+  const int G = group_size(c.g);
+  int s = rng.below(4), t = rng.below(4), v = rng.below(4);
+  if (s + t == 0) s = 1;
+  if (s + v > 6 || t + v > 6) return false;
+  const char* letters = "abcdefghijkl";
+  std::string I(letters, s), K(letters + s, v), J(letters + s + v, t);
+  std::string tu = I + K, tv = K + J, tw = I + J;
+  auto shuffle = [&](std::string& x) {
+    for (int i = static_cast<int>(x.size()) - 1; i > 0; --i) std::swap(x[i], x[rng.below(i + 1)]);
+  };
+  if (rng.below(3)) shuffle(tu);
+  if (rng.below(3)) shuffle(tv);
+  if (rng.below(3)) shuffle(tw);
+  c.einsum = tu + "," + tv + "->" + tw;
+  std::map<char, int64_t> dim;
+  std::map<char, int> cu, cv, hs;
+  std::map<char, std::vector<int32_t>> tab;
+  const bool sub = allow_sub && c.g.nfactors == 1 && rng.below(4) == 0;
+  const bool tables = allow_tables && !sub && rng.below(4) == 0;
+  for (char m : tu + J) {
+    const int r = rng.below(10);
+    dim[m] = r < 6 ? 1 + rng.below(dmax) : r < 8 ? 16 * (1 + rng.below(2)) : 1 + rng.below(40);
+    if (sub) {
+      std::vector<int> div;
+      for (int h = 1; h <= G; ++h)
+        if (G % h == 0) div.push_back(h);
+      hs[m] = div[rng.below(static_cast<int>(div.size()))];
+    } else {
+      hs[m] = G;
+    }
+    if (tables) {
+      std::vector<int32_t> perm(G);
+      std::iota(perm.begin(), perm.end(), 0);
+      for (int i = G - 1; i > 0; --i) std::swap(perm[i], perm[rng.below(i + 1)]);
+      tab[m] = perm;
+    }
+  }
+  for (char m : tu) cu[m] = rng.coin() ? 1 : -1;
+  const int sigma = rng.coin() ? 1 : -1;
+  for (char m : tv) cv[m] = K.find(m) != std::string::npos ? sigma * cu[m] : (rng.coin() ? 1 : -1);
+  auto fill = [&](Desc& d, const std::string& term, const std::map<char, int>& sg) {
+    d.signs.clear();
+    d.dims.clear();
+    d.tables.clear();
+    d.sectors.clear();
+    for (char m : term) {
+      d.signs.push_back(sg.at(m) > 0 ? '+' : '-');
+      d.dims.push_back(dim[m]);
+      if (tables) d.tables.insert(d.tables.end(), tab[m].begin(), tab[m].end());
+      if (sub) d.sectors.push_back(hs[m]);
+    }
+    d.charge = rng.below(G);
+  };
+  fill(c.u, tu, cu);
+  fill(c.v, tv, cv);
+  // W: derive through the planner (signs, charge); then its tables and sectors
+  const bool cplx = allow_cplx && !sub && rng.below(5) == 0;
+  c.u.dtype = cplx ? (rng.coin() ? SYMT_C128 : SYMT_C64) : (rng.coin() ? SYMT_F64 : SYMT_F32);
+  c.v.dtype = cplx ? (rng.coin() ? SYMT_C128 : SYMT_C64) : (rng.coin() ? SYMT_F64 : SYMT_F32);
+  c.u.bind();
+  c.v.bind();
+  const int cmp = cplx ? rng.below(2) : rng.below(3);
+  symt_plan_info info;
+  std::string err;
+  Plan pl;
+  if (make_plan(c.einsum.c_str(), &c.g, &c.u.t, &c.v.t, nullptr, cmp, &pl, &err) != SYMT_OK) return false;
+  c.w.signs = "";
+  for (size_t m = 0; m < tw.size(); ++m) c.w.signs.push_back(pl.w_sign[m] > 0 ? '+' : '-');
+  c.w.charge = pl.w_charge;
+  c.w.dims.clear();
+  c.w.tables.clear();
+  c.w.sectors.clear();
+  for (char m : tw) {
+    c.w.dims.push_back(dim[m]);
+    if (tables) c.w.tables.insert(c.w.tables.end(), tab[m].begin(), tab[m].end());
+    if (sub) c.w.sectors.push_back(hs[m]);
+  }
+  const int wt = rng.below(3);
+  c.w.dtype = cplx ? (cmp == 0 ? SYMT_C128 : SYMT_C64)
+                   : (wt == 0 ? SYMT_F64 : wt == 1 ? SYMT_F32 : (cmp == 1 ? SYMT_F32 : SYMT_F64));
+  c.w.bind();
+  c.compute = cmp;
+  (void)info;
+  return true;
+}
+
+int64_t elems_of(const Plan& p) { return p.U.elems + p.V.elems + p.W.elems; }
+
+void run_case(const Case& c, bool steps) {
+  Plan p;
+  std::string err;
+  const int rc = make_plan(c.einsum.c_str(), &c.g, &c.u.t, &c.v.t, &c.w.t, c.compute | (steps ? kForceSteps : 0),
+                           &p, &err);
+  if (rc != SYMT_OK) return;
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "%s G=%d compute=%d steps=%d fused=%d/%d/%d krun=%d at=%d", c.einsum.c_str(),
+                p.g.size, c.compute, steps ? 1 : 0, p.fused ? 1 : 0, p.fused_ua ? 1 : 0, p.fused_b ? 1 : 0,
+                p.krun, p.a_trans ? 1 : 0);
+  g_case = buf;
+  check_transforms(p);
+  check_fused(p);
+  // the product's split K on this shape
+  if (p.compute != SYMT_COMPUTE_BF16X3 && p.nq > 0 && p.M > 0 && p.gn > 0 && p.gk > 0) {
+    const int elem = p.compute == SYMT_COMPUTE_F64 ? 8 : 4;
+    const GemmChoice gc = choose_fp_gemm(p.nq, p.M, p.gn, p.gk, elem, true);
+    const int64_t tiles = p.nq * ((p.M + gc.bm - 1) / gc.bm) * ((p.gn + gc.bn - 1) / gc.bn);
+    const int spr = p.krun > 0 ? (p.krun + kFpBK - 1) / kFpBK : 0;
+    const int nk_all = static_cast<int>(p.krun > 0 ? p.gk / p.krun * spr : (p.gk + kFpBK - 1) / kFpBK);
+    check_split_k(tiles, gc.splits, nk_all, static_cast<int64_t>(p.bytes_partial / elem),
+                  static_cast<int64_t>(gc.bm) * gc.bn);
+  }
+}
+
+// The workloads' own shapes (small enough to walk element by element).
+void workload_cases() {
+  struct W {
+    const char* sub;
+    int G;
+    const char *su, *sv;
+    std::vector<int64_t> du, dv;
+  };
+  const std::vector<W> ws = {
+      {"abkl,klij->abij", 4, "++--", "++--", {4, 4, 4, 4}, {4, 4, 4, 4}},
+      {"abcd,cdij->abij", 8, "++--", "++--", {6, 6, 6, 6}, {6, 6, 3, 3}},
+      {"abc,asA->bcsA", 6, "---", "++-", {8, 4, 8}, {8, 2, 8}},
+      {"bcsA,bsSB->cASB", 6, "--+-", "+---", {4, 8, 2, 8}, {4, 2, 2, 4}},
+      {"cASB,cSC->ABC", 6, "----", "++-", {8, 8, 2, 4}, {8, 2, 8}},
+      {"opij,opkm->ijmk", 8, "++--", "--++", {3, 3, 4, 4}, {3, 3, 4, 2}},
+      {"ijk,klm->ijlm", 5, "++-", "++-", {7, 10, 7}, {7, 1, 7}},
+  };
+  for (const W& w : ws) {
+    Case c;
+    c.einsum = w.sub;
+    c.g.nfactors = w.G == 6 ? 2 : 1;
+    c.g.order[0] = w.G == 6 ? 2 : w.G;
+    if (w.G == 6) c.g.order[1] = 3;
+    c.u.signs = w.su;
+    c.v.signs = w.sv;
+    c.u.dims = w.du;
+    c.v.dims = w.dv;
+    c.u.bind();
+    c.v.bind();
+    Plan pl;
+    std::string err;
+    for (int cmp = 0; cmp < 3; ++cmp) {
+      if (make_plan(c.einsum.c_str(), &c.g, &c.u.t, &c.v.t, nullptr, cmp, &pl, &err) != SYMT_OK) {
+        g_case = w.sub;
+        fail("workload does not plan", cmp, 0);
+        continue;
+      }
+      c.w.signs.clear();
+      const std::string tw = c.einsum.substr(c.einsum.find("->") + 2);
+      for (size_t m = 0; m < tw.size(); ++m) c.w.signs.push_back(pl.w_sign[m] > 0 ? '+' : '-');
+      c.w.charge = pl.w_charge;
+      c.w.dims.assign(pl.W.dims, pl.W.dims + pl.W.n);
+      c.w.dtype = cmp == 1 ? SYMT_F32 : SYMT_F64;
+      c.w.bind();
+      c.compute = cmp;
+      for (int dt = 0; dt < 2; ++dt) {
+        c.u.dtype = c.v.dtype = dt ? SYMT_F32 : SYMT_F64;
+        c.u.bind();
+        c.v.bind();
+        run_case(c, false);
+        run_case(c, true);
+      }
+    }
+  }
+}
+
+}  // namespace
+
+int main(int argc, char** argv) {
+  const int n = argc > 1 ? std::atoi(argv[1]) : 400;
+  const uint64_t seed = argc > 2 ? std::strtoull(argv[2], nullptr, 10) : 20070805ull;
+  workload_cases();
+  Rng rng{seed};
+  int done = 0;
+  while (done < n) {
+    Case c;
+    if (!random_case(rng, c, true, true, true, 6)) continue;
+    Plan p;
+    std::string err;
+    if (make_plan(c.einsum.c_str(), &c.g, &c.u.t, &c.v.t, &c.w.t, c.compute, &p, &err) != SYMT_OK) continue;
+    if (elems_of(p) > 400000) continue;        // keep the element walks quick
+    run_case(c, false);
+    run_case(c, rng.below(3) == 0);
+    ++done;
+  }
+  // stream-K partitions over launch shapes, including the workloads' (Z_8 and
+  // Z_16 ladders on 96 x 96 tiles, the MPS chain's products)
+  g_case = "stream-K";
+  const int64_t resident[] = {256, 512, 768};
+  for (int64_t res : resident)
+    for (int64_t batch : {1, 2, 6, 8, 16})
+      for (int tm : {1, 2, 3, 5, 16, 48})
+        for (int tn : {1, 2, 3, 4, 11, 16})
+          for (int nk : {1, 3, 4, 7, 16, 36, 97, 288})
+            for (int64_t te : {96 * 96, 128 * 128}) {
+              check_stream_k(batch, tm, tn, nk, res, 2 * res * te, te);
+              check_stream_k(batch, tm, tn, nk, res, 2 * res * te - 1, te);   // a buffer one short
+            }
+  check_stream_k(8, 48, 3, 288, 768, 2 * 768 * 96 * 96, 96 * 96);          // Z_8 ladder (f64, K = 4608)
+  check_stream_k(16, 171, 11, 1024, 768, 2 * 768 * 96 * 96, 96 * 96);      // Z_16 ladder (f64, K = 16384)
+  g_case = "split-K";
+  for (int64_t tiles : {1, 2, 5, 64, 300})
+    for (int sp : {2, 3, 8, 64, 128})
+      for (int nk : {8, 16, 17, 100, 185193})
+        check_split_k(tiles, sp, nk, tiles * sp * 128 * 128, 128 * 128);
+  std::printf("host replay: %d random contractions + workload shapes, %lld checks, %d failures\n", done,
+              static_cast<long long>(g_checks), g_failures);
+  return g_failures == 0 ? 0 : 1;
+}

@@ -129,6 +129,16 @@ def _example_rows(golden_dir, kind):
     return out
 
 
+def test_example_maps_file_is_its_generators_output(golden_dir):
+    """tests/golden/make_sec21_example_maps.py (the paper's printed maps, evaluated) wrote the file."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("make_maps", os.path.join(golden_dir, "make_sec21_example_maps.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    with open(os.path.join(golden_dir, "sec21_example_maps_z3.txt")) as f:
+        assert f.read() == mod.HEADER + "\n".join(mod.lines()) + "\n"
+
+
 def test_standard_form_maps_of_the_example(golden_dir):
     g = O.Group(3)
     w = O.Sym.make("++--", 0, (1, 1, 1, 1), g)
