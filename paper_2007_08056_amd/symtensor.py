@@ -16,6 +16,7 @@ the method happens in Python.
 from __future__ import annotations
 
 import ctypes
+import os
 from dataclasses import dataclass
 
 import torch
@@ -128,8 +129,13 @@ _PLANS: dict = {}
 _MAX_PLANS = 1024
 
 
+# Tuning variables the library's planner reads (include/symtensor.h): part of every key.
+_TUNING_VARS = ("SYMT_FUSED_V", "SYMT_GEMM_TILE", "SYMT_GEMM_SK")
+
+
 def _planned(subscripts, u, v, w, code):
-    key = (subscripts, u.group, u.key(), v.key(), w.key() if w is not None else None, code)
+    key = (subscripts, u.group, u.key(), v.key(), w.key() if w is not None else None, code,
+           tuple(os.environ.get(k) for k in _TUNING_VARS))
     ent = _PLANS.get(key)
     if ent is None:
         if u.group != v.group:

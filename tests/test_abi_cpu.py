@@ -540,3 +540,22 @@ def test_outer_product_takes_the_sign_ratio_that_matches_the_given_output():
     # a rule neither ratio derives is still rejected
     rc, _ = _plan("a,k->ak", g, _desc("+", 3, (3,)), _desc("+", 1, (4,)), _desc("+-", 3, (3, 4)))
     assert rc == L.SYMT_ESYM
+
+
+def test_python_plan_cache_follows_the_tuning_variables(monkeypatch):
+    """The binding's plan cache keys on the tuning variables as the library's does: the
+    Z_8 ladder's workspace holds stream-K pieces by default and none with SYMT_GEMM_SK=0."""
+    import torch
+    import paper_2007_08056_amd as P
+    wl = synth.configs.get("ccd_ladder_z8")
+    st = wl.steps[0]
+    mk = lambda name: P.SymTensor(torch.empty(wl.reduced_shape(name), dtype=torch.float64),  # noqa: E731
+                                  wl.operands[name].signs, wl.operands[name].charge, wl.group)
+    u, v = mk(st.u), mk(st.v)
+    monkeypatch.delenv("SYMT_GEMM_SK", raising=False)
+    with_pieces = P.plan(st.einsum, u, v, "f64").workspace_bytes
+    monkeypatch.setenv("SYMT_GEMM_SK", "0")
+    without = P.plan(st.einsum, u, v, "f64").workspace_bytes
+    monkeypatch.delenv("SYMT_GEMM_SK")
+    assert with_pieces > without
+    assert P.plan(st.einsum, u, v, "f64").workspace_bytes == with_pieces
