@@ -1,23 +1,28 @@
 """Throughput of the irrep-alignment contraction on one MI355X.
 
 One step = the whole hot path on one batch of synthetic input already resident
-in HBM: align V_abcd and T_cdij, one sector-batched FP64 product, unalign
-W_abij -- the coupled-cluster particle-particle ladder w_abij = sum_cd
-V_abcd T_cdij with Z_8 symmetry, virtual block 24, occupied block 6.
+in HBM: the coupled-cluster particle-particle ladder w_abij = sum_cd V_abcd
+T_cdij with Z_16 symmetry, virtual block 32, occupied block 8, in FP64 (8.80
+TFLOP of allowed-block products per step).  Where the layout allows (here it
+does), the step is the fused product: offset tables, then one sector-batched
+product that reads V_abcd and T_cdij in their standard reduced forms and writes
+W_abij in place (include/symtensor.h, FUSED PRODUCT).
 
-Prints one JSON line: effective GFLOP/s (algorithmic flops of allowed blocks
-only, 2 |G| M K N, divided by the measured step time), the roofline of the
-dominant kernel (the sector product; its duration from HIP events the library
-records around each launch on the stream it launches on), and the CPU oracle's
-rate on a bounded sample of the same workload.
+Prints one JSON line: effective GFLOP/s of that forward step (algorithmic flops
+of allowed blocks only, 2 |G| M K N, divided by the measured step time), plus
+* roofline: the sector product's achieved TFLOP/s (HIP events that the library
+  records around its launches on the stream it launches on) against the f64
+  MFMA peak, and its HBM traffic from the committed counter summary;
+* error: the forward's normwise and componentwise error against the oracle on
+  sampled outputs, computed outside the timed region;
+* precisions: the same step in f32 and split-bf16 with their errors;
+* fwd_bwd: the differentiated tensor-network chain (MPS environment, bond 128,
+  L = <E', R>, forward plus the hand-written backward) in f64 and f32;
+* cpu_baseline: the CPU oracle (loop over blocks, NumPy FP64) on a bounded
+  sample of the same contraction, on all host cores and on one.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--extra PATH] [--all] [--suite]
-
-Where the layout allows (here it does), one step runs the fused product: A is
-read straight from V_abcd's standard form, B from T_cdij's and C written
-straight into W_abij's through offset tables, so no aligned form is written
-(include/symtensor.h, FUSED PRODUCT); the three separate steps are timed too
-and reported in the --extra file.
+                       [--sweeps] [--ladder-z8] [--calibrate] [--only WORKLOAD/COMPUTE]
 """
 from __future__ import annotations
 
@@ -33,7 +38,8 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0}     # dense MFMA TFLOP/s, MI355X
 HBM_PEAK_GBS = 8000.0
-WORKLOAD = "ccd_ladder_z8"
+WORKLOAD = "ccd_ladder_z16"
+METRIC = "effective GFLOP/s of symmetric contraction (fwd, fwd+bwd) vs FP64 plain at stated rel. error"
 
 
 # Sources that decide the sector product's machine code and launch choice;
@@ -64,96 +70,62 @@ def gemm_traffic(kernel_key, digest):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(wl, budget_s=12.0, threads=None):
-    """Loop-over-blocks oracle on a sample of V's stored blocks, timed on the host cores
-    (all of them, or `threads` BLAS threads)."""
+def _host_description():
+    model = ""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model
+
+
+def cpu_baseline(wl, blocks=64, threads=None, runs=3):
+    """The loop-over-blocks oracle (Alg. 1 generalised, NumPy FP64) on a bounded sample of the
+    workload: `blocks` stored blocks of U (spread evenly over its stored-sector tuples) against
+    all of V, one warm-up and `runs` timed repetitions (median), input generation excluded.
+    `threads`: BLAS threads (None: all the process may use)."""
     import contextlib
 
     import numpy as np
     import oracle as O
     import synth
-    from synth import philox
-    limit = contextlib.nullcontext()
-    try:
-        from threadpoolctl import threadpool_info, threadpool_limits
-        if threads:
-            limit = threadpool_limits(limits=threads)
-        cores = threads or max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:  # noqa: BLE001
-        cores = threads or os.cpu_count() or 1
+    from synth import host as synth_host
+    from threadpoolctl import threadpool_info, threadpool_limits
+    limit = threadpool_limits(limits=threads) if threads else contextlib.nullcontext()
     with limit:
-        return _oracle_sample(wl, budget_s, cores, np, O, synth, philox)
-
-
-_ORACLE_INPUTS: dict = {}
-
-
-def _oracle_sample(wl, budget_s, cores, np, O, synth, philox):
-    st = wl.steps[0]
-    g = O.Group(wl.group)
-    ou, ov = wl.operands[st.u], wl.operands[st.v]
-    su = O.Sym.make(ou.signs, ou.charge, ou.dims, g)
-    sv = O.Sym.make(ov.signs, ov.charge, ov.dims, g)
-    G = g.size
-    # V blocks are generated once per process and shared by the timed samples
-    cache = _ORACLE_INPUTS.setdefault(wl.name, {})
-    if "Rv" not in cache:
-        cache["Rv"] = synth.host_input(wl, st.v)          # T: 10.6 M elements
-        cache["Ru"] = np.zeros(wl.reduced_shape(st.u))
-        cache["made"] = set()
-    Rv, Ru, made = cache["Rv"], cache["Ru"], cache["made"]
-    blk = int(np.prod(ou.dims))
-    all_blocks = [(a, b, c) for a in range(G) for b in range(G) for c in range(G)]
-    done_blocks, flops_per_block = 0, 2 * blk * int(np.prod(ov.dims[2:])) * G
-    elapsed = 0.0
-    i = 0
-    while i < len(all_blocks) and elapsed < budget_s:
-        batch = all_blocks[i:i + 8]
-        for b in batch:                                   # generate the sampled V blocks
-            if b in made:
-                continue
-            made.add(b)
-            lin = np.ravel_multi_index(b, (G, G, G)) * blk
-            Ru[b] = philox.values_at(np.arange(lin, lin + blk), wl.seed, ou.tensor_id, ou.dist,
-                                     ou.scale).reshape(ou.dims)
-        t0 = time.perf_counter()
-        O.contract_blocks(st.einsum, Ru, su, Rv, sv, u_blocks=batch)
-        elapsed += time.perf_counter() - t0
-        done_blocks += len(batch)
-        i += len(batch)
-    gflops = done_blocks * flops_per_block / elapsed / 1e9
-    return {"value": round(gflops, 3), "unit": "GFLOP/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"loop-over-blocks oracle (numpy FP64) over {done_blocks} of {len(all_blocks)} "
-                      f"stored blocks of V_abcd against all of T_cdij, {elapsed:.1f} s"}
-
-
-def cold_and_copy(P, st, u, v, w, ws, reps=5):
-    """Median step time with the 256 MB Infinity Cache flushed before every
-    repetition (a 1 GiB write), and the device-to-device copy rate of 1 GiB
-    (read + write bytes per second), the practical ceiling of a transform."""
-    import torch
-    flush = torch.empty(2 ** 27, dtype=torch.float64, device="cuda:0")
-    times = []
-    for _ in range(reps):
-        flush.fill_(1.0)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        P.contract_into(st.einsum, u, v, w, "f64", ws)
-        e1.record()
-        torch.cuda.synchronize()
-        times.append(e0.elapsed_time(e1))
-    src = torch.ones(2 ** 27, dtype=torch.float64, device="cuda:0")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 2 * src.numel() * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del flush, src, dst
-    return sorted(times)[len(times) // 2], copy_gbs
+        info = threadpool_info()
+        blas = [f"{p.get('internal_api')} {p.get('version')}" for p in info if p.get("user_api") == "blas"]
+        used = max([p.get("num_threads", 1) for p in info if p.get("user_api") == "blas"] or [1])
+        st = wl.steps[0]
+        g = O.Group(wl.group)
+        ou, ov = wl.operands[st.u], wl.operands[st.v]
+        su = O.Sym.make(ou.signs, ou.charge, ou.dims, g)
+        sv = O.Sym.make(ov.signs, ov.charge, ov.dims, g)
+        shape = wl.reduced_shape(st.u)
+        stored = list(O.stored_tuples(su))
+        pick = [stored[i] for i in np.linspace(0, len(stored) - 1, blocks).astype(int)]
+        Rv = synth.host_input(wl, st.v)
+        Ru = np.zeros(shape)                     # untouched pages outside the sampled blocks
+        blk = int(np.prod(ou.dims))
+        for b in pick:
+            lin = int(np.ravel_multi_index(b, shape[:len(b)])) * blk
+            Ru[b] = synth_host.fill(ou.dims, wl.seed, ou.tensor_id, ou.dist, ou.scale, first=lin)
+        flops = O.flop_count(st.einsum, su, sv) / len(stored) * len(pick)
+        times = []
+        for rep in range(runs + 1):
+            t0 = time.perf_counter()
+            O.contract_blocks(st.einsum, Ru, su, Rv, sv, u_blocks=pick)
+            if rep:
+                times.append(time.perf_counter() - t0)
+        med = sorted(times)[len(times) // 2]
+    return {"value": round(flops / med / 1e9, 3), "unit": "GFLOP/s", "cores": int(used), "kind": "oracle",
+            "sample": f"loop-over-blocks oracle (NumPy FP64) over {len(pick)} of {len(stored)} stored blocks of "
+                      f"{st.u} against all of {st.v} ({flops / 1e9:.1f} GFLOP), median of {runs} after one "
+                      f"warm-up: {med:.2f} s",
+            "host": _host_description(), "blas": ", ".join(blas)}
 
 
 def chain_flops(wl, compute, cplx=False):
@@ -223,34 +195,148 @@ def time_workload(P, SG, wl, compute, steps, warmup, grad=False, cplx=False):
             "flops_per_step": flops, "steps_per_batch": batch}
 
 
-def dense_ms(wl, reps=3):
-    """The symmetry-oblivious baseline of the paper's G sweeps: one dense f64 einsum of
-    full tensors of the same shapes (every block materialised; values are random, the
-    time does not depend on them), through torch's vendor BLAS."""
+def timed_steps(step, steps, warmup):
+    """ms per step of `steps` calls after `warmup` (wall clock between two device synchronisations)."""
     import torch
-    st = wl.steps[0]
-    G = wl.group_size
-    full = lambda name: torch.randn([G * d for d in wl.operands[name].dims], dtype=torch.float64,  # noqa: E731
-                                    device="cuda:0")
-    u, v = full(st.u), full(st.v)
-    torch.einsum(st.einsum, u, v)
+    for _ in range(warmup):
+        step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(reps):
-        torch.einsum(st.einsum, u, v)
+    for _ in range(steps):
+        step()
     torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / reps
-    del u, v
-    torch.cuda.empty_cache()
-    return round(ms, 4)
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def random_reduced_positions(shape, count, seed):
+    """`count` random coordinates of a reduced form (plain indexing, no symmetry arithmetic)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.integers(0, d, count) for d in shape], axis=1).astype(np.int64)
+
+
+def chain_roofline_ms(wl, compute, grad):
+    """Roofline time of a contraction chain (forward, plus the backward's two contractions per
+    step with grad): each contraction costs max(flops / MFMA peak, bytes / HBM peak), its bytes
+    being one read of U and V and one write of W in the storage type (the fused path's minimum)."""
+    from paper_2007_08056_amd import _lib as L
+    elem = 8 if compute == "f64" else 4
+    g = L.make_group(wl.group)
+    total = 0.0
+
+    def cost(sub, a, b):
+        info = L.plan(sub, g, L.TensorDesc(a.signs, a.charge, a.dims, L.SYMT_F64, None),
+                      L.TensorDesc(b.signs, b.charge, b.dims, L.SYMT_F64, None), None, L.COMPUTE[compute])
+        byts = (info.elems_u + info.elems_v + info.elems_w) * elem
+        return max(info.flops / (PEAK[compute] * 1e12), byts / (HBM_PEAK_GBS * 1e9))
+    for st in wl.steps:
+        ou, ov, ow = wl.operands[st.u], wl.operands[st.v], wl.operands[st.w]
+        tu, rest = st.einsum.split(",")
+        tv, tw = rest.split("->")
+        total += cost(st.einsum, ou, ov)
+        if grad:
+            total += cost(f"{tw},{tv}->{tu}", ow, ov) + cost(f"{tu},{tw}->{tv}", ou, ow)
+    return total * 1e3
+
+
+def cpu_leg(wl, samples, losses):
+    """The CPU side of the benchmark: the oracle's own throughput (cpu_baseline, all host cores
+    and one), and the oracle's values at the GPU's sampled outputs (the stated errors)."""
+    import numpy as np
+    import oracle as O
+    import synth
+    from synth import host as synth_host
+    st = wl.steps[0]
+    g = O.Group(wl.group)
+    sym = {k: O.Sym.make(op.signs, op.charge, op.dims, g) for k, op in wl.operands.items()}
+    su, sv, sw = sym[st.u], sym[st.v], sym[st.w]
+    out = {}
+    red = samples["positions"]
+    full = []
+    for r in red:
+        secs = O.full_sectors(sw, tuple(int(x) for x in r[: sw.order - 1]))
+        full.append([S * n + int(i) for S, n, i in zip(secs, sw.dims, r[sw.order - 1:])])
+    full = np.asarray(full, dtype=np.int64)
+
+    def vf(name, absolute=False, round32=False):
+        op = wl.operands[name]
+        shape = wl.reduced_shape(name)
+
+        def fn(secs, inner):
+            x = synth_host.values_at(np.ravel_multi_index(tuple(secs) + tuple(inner), shape), wl.seed,
+                                     op.tensor_id, op.dist, op.scale)
+            if round32:
+                x = x.astype(np.float32).astype(np.float64)
+            return np.abs(x) if absolute else x
+        return fn
+    ref = O.sample_contract_allowed(st.einsum, su, sv, vf(st.u), vf(st.v), full)
+    absref = O.sample_contract_allowed(st.einsum, su, sv, vf(st.u, True), vf(st.v, True), full)
+    ref32 = O.sample_contract_allowed(st.einsum, su, sv, vf(st.u, round32=True), vf(st.v, round32=True), full)
+    den = float(np.max(np.abs(ref)))
+    for compute, got in samples["values"].items():
+        e = {"vs": "FP64 oracle, same sampled outputs", "samples": len(full),
+             "normwise": float(np.max(np.abs(got - ref)) / den),
+             "componentwise": float(np.max(np.abs(got - ref) / absref))}
+        if compute != "f64":
+            e["normwise_vs_binary32_inputs"] = float(np.max(np.abs(got - ref32)) / den)
+        out[compute] = e
+    # the differentiated chain: L of the library against the oracle's L
+    gwl = synth.configs.mps_env_grad()
+    gsym = {k: O.Sym.make(op.signs, op.charge, op.dims, O.Group(gwl.group)) for k, op in gwl.operands.items()}
+    cur = {k: synth.host_input(gwl, k) for k in gwl.inputs}
+    for gst in gwl.steps:
+        cur[gst.w], _ = O.contract_blocks(gst.einsum, cur[gst.u], gsym[gst.u], cur[gst.v], gsym[gst.v])
+    l_ref = float(np.sum(cur[gwl.output] * cur["R"]))
+    out["loss"] = {c: abs(v - l_ref) / abs(l_ref) for c, v in losses.items()}
+    out["cpu"] = cpu_baseline(wl)
+    out["cpu_1thread"] = cpu_baseline(wl, blocks=16, threads=1)
+    return out
+
+
+def ladder_z8_details(P, SG, extra):
+    """The Z_8 ladder (f64): fused step, its three separate steps, per-transform HBM rates."""
+    import torch
+    import synth
+    wl = synth.configs.get("ccd_ladder_z8")
+    st = wl.steps[0]
+    dev = torch.device("cuda:0")
+    ou, ov = (wl.operands[x] for x in (st.u, st.v))
+    u = P.SymTensor(SG.device_input(wl, st.u, device=dev), ou.signs, ou.charge, wl.group)
+    v = P.SymTensor(SG.device_input(wl, st.v, device=dev), ov.signs, ov.charge, wl.group)
+    w = P.output_like(st.einsum, u, v)
+    info = P.plan(st.einsum, u, v, "f64", w)
+    ws = torch.empty(info.workspace_bytes, dtype=torch.uint8, device=dev)
+    P.read_timing(0)
+    P.set_timing(0, True)
+    ms_step = timed_steps(lambda: P.contract_into(st.einsum, u, v, w, "f64", ws), 20, 30)
+    P.set_timing(0, False)
+    ms, launches = P.read_timing(0)
+    wsteps = P.output_like(st.einsum, u, v)
+    P.set_timing(0, True)
+    timed_steps(lambda: P.contract_into(st.einsum, u, v, wsteps, "f64", steps=True), 5, 2)
+    P.set_timing(0, False)
+    ms_s, launches_s = P.read_timing(0)
+    xf = {name: (ms_s[i] / launches_s[i] if launches_s[i] else None)
+          for i, name in enumerate(("align_u", "align_v", "sector_gemm", "unalign_w"))}
+    d = {"ms_per_step": round(ms_step, 4), "tflops": round(info.flops / (ms_step * 1e-3) / 1e12, 2),
+         "fused": bool(info.fused), "fused_v": bool(info.fused_v),
+         "kernel_ms_per_launch": {name: (ms[i] / launches[i] if launches[i] else None)
+                                  for i, name in enumerate(("offset_tables", "align_v", "sector_gemm", "unalign_w"))},
+         "steps_kernel_ms_per_launch": xf,
+         "steps_result_identical_to_fused": bool(torch.equal(wsteps.data, w.data))}
+    for key, nbytes in (("align_u", 2 * info.elems_u * 8), ("align_v", 2 * info.elems_v * 8),
+                        ("unalign_w", 2 * info.elems_w * 8)):
+        if xf[key]:
+            d[key + "_GBs"] = nbytes / (xf[key] * 1e-3) / 1e9
+    extra["ccd_ladder_z8"] = d
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU leg (oracle baseline and sampled errors)")
     ap.add_argument("--extra", default="", help="write per-kernel details to this JSON file")
     ap.add_argument("--all", action="store_true",
                     help="also time every workload in every precision (written to --extra)")
@@ -258,18 +344,23 @@ def main():
                     help="also time the paper's Table 2 suite at full size (written to --extra)")
     ap.add_argument("--sweeps", action="store_true",
                     help="also time the paper's (s, t, v) sweep and its G sweeps (written to --extra)")
+    ap.add_argument("--ladder-z8", action="store_true",
+                    help="also time the Z_8 ladder's fused and three-step paths (written to --extra)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run one plain elementwise kernel that reads and writes 256 MiB "
                          "(the reference for scaling HBM byte counters)")
     ap.add_argument("--only", default="",
                     help="WORKLOAD/COMPUTE (e.g. ccd_ladder_z8/bf16x3): time that one workload's chain "
                          "(as --all does), print one line and exit; for profiling runs")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time the headline step only (no precisions, fwd+bwd or CPU leg); for profiling runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the contraction is benchmarked on a single MI355X "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
     import paper_2007_08056_amd as P
     import synth
@@ -282,22 +373,31 @@ def main():
         r = time_workload(P, SG, synth.configs.get(name), compute, args.steps, args.warmup)
         print(json.dumps({"workload": name, "compute": compute, **r}), flush=True)
         return
-    wl = synth.configs.get(WORKLOAD)
-    st = wl.steps[0]
-    ou, ov, ow = (wl.operands[x] for x in (st.u, st.v, st.w))
-    u = P.SymTensor(SG.device_input(wl, st.u, device=dev), ou.signs, ou.charge, wl.group)
-    v = P.SymTensor(SG.device_input(wl, st.v, device=dev), ov.signs, ov.charge, wl.group)
-    w = P.output_like(st.einsum, u, v)
-    info = P.plan(st.einsum, u, v, "f64", w)
-    ws = torch.empty(info.workspace_bytes, dtype=torch.uint8, device=dev)
-    torch.cuda.synchronize()
-
     if args.calibrate:
         x = torch.ones(32 * 2 ** 20, dtype=torch.float64, device=dev)
         y = torch.empty_like(x)
         torch.neg(x, out=y)
         torch.cuda.synchronize()
         del x, y
+
+    wl = synth.configs.get(WORKLOAD)
+    st = wl.steps[0]
+    ou, ov = wl.operands[st.u], wl.operands[st.v]
+    positions = random_reduced_positions(wl.reduced_shape(st.w), 256, 5)
+    pos_t = torch.from_numpy(positions).to(dev)
+    values = {}
+    extra = {}
+
+    def make(dtype, wdtype=torch.float64):
+        u = P.SymTensor(SG.device_input(wl, st.u, dtype=dtype, device=dev), ou.signs, ou.charge, wl.group)
+        v = P.SymTensor(SG.device_input(wl, st.v, dtype=dtype, device=dev), ov.signs, ov.charge, wl.group)
+        w = P.output_like(st.einsum, u, v, dtype=wdtype)
+        return u, v, w
+
+    # ---- headline: Z_16 ladder, FP64, forward
+    u, v, w = make(torch.float64)
+    info = P.plan(st.einsum, u, v, "f64", w)
+    ws = torch.empty(max(1, info.workspace_bytes), dtype=torch.uint8, device=dev)
     for _ in range(args.warmup):
         P.contract_into(st.einsum, u, v, w, "f64", ws)
     torch.cuda.synchronize()
@@ -313,59 +413,73 @@ def main():
     ms, launches = P.read_timing(0)
     ms_step = (t1 - t0) * 1e3 / args.steps
     value = info.flops / (ms_step * 1e-3) / 1e9
-
-    # the three separate steps on the same inputs: per-transform HBM rates
-    wsteps = P.output_like(st.einsum, u, v)
-    for _ in range(2):
-        P.contract_into(st.einsum, u, v, wsteps, "f64", steps=True)
-    torch.cuda.synchronize()
-    P.read_timing(0)
-    P.set_timing(0, True)
-    for _ in range(5):
-        P.contract_into(st.einsum, u, v, wsteps, "f64", steps=True)
-    torch.cuda.synchronize()
-    P.set_timing(0, False)
-    ms_s, launches_s = P.read_timing(0)
-    same = bool(torch.equal(wsteps.data, w.data))
-    del wsteps
-
+    values["f64"] = w.data[tuple(pos_t.T)].cpu().numpy()
     gemm_ms = ms[2] / max(1, launches[2])
     achieved = info.flops / (gemm_ms * 1e-3) / 1e12
     digest = source_digest(*PRODUCT_SOURCES)
-    traffic = gemm_traffic("sector_gemm_f64_ccd_ladder_z8", digest)
+    traffic = gemm_traffic(f"sector_gemm_f64_{WORKLOAD}", digest)
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["f64"], "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK["f64"], 4), "traffic": traffic}
-
-    extra = {
-        "fused": bool(info.fused),
-        "fused_v": bool(info.fused_v),
+    extra["headline"] = {
+        "fused": bool(info.fused), "fused_v": bool(info.fused_v),
         "kernel_ms_per_launch": {name: (ms[i] / launches[i] if launches[i] else None)
-                                 for i, name in enumerate(("offset_tables" if info.fused else "align_u",
-                                                           "align_v", "sector_gemm", "unalign_w"))},
-        "steps_kernel_ms_per_launch": {name: (ms_s[i] / launches_s[i] if launches_s[i] else None)
-                                       for i, name in enumerate(("align_u", "align_v", "sector_gemm",
-                                                                 "unalign_w"))},
-        "steps_result_identical_to_fused": same,
-        "shape": {"batch": info.group_size, "m": info.m, "k": info.k, "n": info.n},
-        "flops": info.flops,
-        "bytes_u": info.elems_u * 8, "bytes_v": info.elems_v * 8, "bytes_w": info.elems_w * 8,
-        "gemm_source_digest": digest,
-    }
-    cold_ms, copy_gbs = cold_and_copy(P, st, u, v, w, ws)
-    extra["cold_ms_per_step"] = round(cold_ms, 4)
-    extra["cold_gflops"] = round(info.flops / (cold_ms * 1e-3) / 1e9, 2)
-    extra["d2d_copy_GBs"] = round(copy_gbs, 1)
-    xf = extra["steps_kernel_ms_per_launch"]
-    for key, nbytes in (("align_u", 2 * info.elems_u * 8), ("align_v", 2 * info.elems_v * 8),
-                        ("unalign_w", 2 * info.elems_w * 8)):
-        if xf[key]:
-            extra[key + "_GBs"] = nbytes / (xf[key] * 1e-3) / 1e9
+                                 for i, name in enumerate(("offset_tables", "align_v", "sector_gemm",
+                                                           "unalign_w"))},
+        "shape": {"batch": info.group_size, "m": info.m, "k": info.k, "n": info.n}, "flops": info.flops,
+        "gemm_source_digest": digest}
+    del u, v, w, ws
+    torch.cuda.empty_cache()
 
+    precisions, fwd_bwd, losses = {}, {}, {}
+    if not args.headline_only:
+        # ---- the same step in binary32 (binary32 W) and split-bf16 (binary32 operands, binary64 W)
+        for compute in ("f32", "bf16x3"):
+            u, v, w = make(torch.float32, torch.float32 if compute == "f32" else torch.float64)
+            ci = P.plan(st.einsum, u, v, compute, w)
+            wsc = torch.empty(max(1, ci.workspace_bytes), dtype=torch.uint8, device=dev)
+            P.read_timing(0)
+            P.set_timing(0, True)
+            m = timed_steps(lambda: P.contract_into(st.einsum, u, v, w, compute, wsc), 5, 2)
+            P.set_timing(0, False)
+            cms, cl = P.read_timing(0)
+            gm = cms[2] / max(1, cl[2])
+            values[compute] = w.data[tuple(pos_t.T)].double().cpu().numpy()
+            mfma_work = ci.flops * (3.0 if compute == "bf16x3" else 1.0)
+            precisions[compute] = {"ms_per_step": round(m, 4), "gflops": round(ci.flops / (m * 1e-3) / 1e9, 1),
+                                   "sector_gemm_ms": round(gm, 4),
+                                   "mfma_frac": round(mfma_work / (gm * 1e-3) / 1e12 / PEAK[compute], 4),
+                                   "fused": bool(ci.fused)}
+            del u, v, w, wsc
+            torch.cuda.empty_cache()
+        # ---- the differentiated MPS environment chain, forward + backward (bond 128)
+        gwl = synth.configs.get("mps_env_grad")
+        for compute in ("f64", "f32"):
+            r = time_workload(P, SG, gwl, compute, 20, 5, grad=True)
+            roof = chain_roofline_ms(gwl, compute, True)
+            fwd = time_workload(P, SG, gwl, compute, 20, 5)
+            fwd_bwd[compute] = {"ms_per_step": r["ms_per_step"], "gflops": round(r["tflops"] * 1e3, 1),
+                                "flops_per_step": r["flops_per_step"],
+                                "mfma_frac": round(r["tflops"] / PEAK[compute], 4),
+                                "roofline_ms": round(roof, 4), "roofline_frac": round(roof / r["ms_per_step"], 4),
+                                "fwd_ms_per_step": fwd["ms_per_step"], "fwd_gflops": round(fwd["tflops"] * 1e3, 1)}
+            dt = torch.float64 if compute == "f64" else torch.float32
+            t = {}
+            for name in gwl.inputs:
+                op = gwl.operands[name]
+                t[name] = P.SymTensor(SG.device_input(gwl, name, dtype=dt, device=dev), op.signs, op.charge,
+                                      gwl.group)
+            for gst in gwl.steps:
+                t[gst.w] = P.einsum(gst.einsum, t[gst.u], t[gst.v], compute)
+            losses[compute] = float((t[gwl.output].data.double() * t["R"].data.double()).sum().item())
+            del t
+            torch.cuda.empty_cache()
+
+    if args.ladder_z8:
+        ladder_z8_details(P, SG, extra)
     if args.all:
-        import synth as S
         table = {}
         for name, computes, grad, cplx in (("plain_z4", ("f64",), False, False),
-                                           ("ccd_ladder_z8", ("f32", "bf16x3"), False, False),
+                                           ("ccd_ladder_z8", ("f64", "f32", "bf16x3"), False, False),
                                            ("mps_env_z2z3", ("f64", "f32", "bf16x3"), False, False),
                                            ("ccd_ladder_z16", ("f64", "f32", "bf16x3"), False, False),
                                            ("mps_env_grad", ("f64", "f32"), False, False),
@@ -373,7 +487,7 @@ def main():
                                            ("ccd_ladder_z8", ("f64", "f32"), False, True),
                                            ("ccd_ladder_z8_sub", ("f64", "f32", "bf16x3"), False, False),
                                            ("mps_env_z2z3", ("f64", "f32"), False, True)):
-            wlx = S.configs.get(name)
+            wlx = synth.configs.get(name)
             for c in computes:
                 n_steps = 3 if name == "ccd_ladder_z16" else 10
                 r = time_workload(P, SG, wlx, c, n_steps, 2, grad, cplx)
@@ -382,12 +496,10 @@ def main():
                 print(f"{key}: {r['ms_per_step']:.3f} ms, {r['tflops']:.1f} TFLOP/s", file=sys.stderr, flush=True)
                 torch.cuda.empty_cache()
         extra["workloads"] = table
-
     if args.sweeps:
-        import synth as S
         stv = {}
-        for case in S.configs.STV_CASES:
-            wlx = S.configs.stv_case(*case)
+        for case in synth.configs.STV_CASES:
+            wlx = synth.configs.stv_case(*case)
             r = time_workload(P, SG, wlx, "f64", 3, 2)
             r["einsum"], r["block_dim"] = wlx.steps[0].einsum, wlx.operands["U"].dims[0]
             stv["".join(map(str, case))] = r
@@ -395,22 +507,18 @@ def main():
             torch.cuda.empty_cache()
         extra["stv_sweep"] = stv
         gs = {}
-        for fam, Gs in S.configs.G_SWEEP.items():
+        for fam, Gs in synth.configs.G_SWEEP.items():
             for G in Gs:
-                wlx = S.configs.g_sweep_case(fam, G)
-                r = time_workload(P, SG, wlx, "f64", 5, 2)
-                r["dense_ms"] = dense_ms(wlx)
+                r = time_workload(P, SG, synth.configs.g_sweep_case(fam, G), "f64", 5, 2)
                 gs[f"{fam}/G={G}"] = r
-                print(f"G sweep {fam} G={G}: {r['ms_per_step']:.3f} ms ({r['tflops']:.1f} TFLOP/s); "
-                      f"dense {r['dense_ms']:.3f} ms", file=sys.stderr, flush=True)
+                print(f"G sweep {fam} G={G}: {r['ms_per_step']:.3f} ms ({r['tflops']:.1f} TFLOP/s)",
+                      file=sys.stderr, flush=True)
                 torch.cuda.empty_cache()
         extra["g_sweep"] = gs
-
     if args.suite:
-        import synth as S
         table = {}
-        for label in S.configs.SUITE_LABELS:
-            wlx = S.configs.paper_suite_case(label)
+        for label in synth.configs.SUITE_LABELS:
+            wlx = synth.configs.paper_suite_case(label)
             for c in ("f64", "f32", "bf16x3"):
                 try:
                     r = time_workload(P, SG, wlx, c, 3, 2)
@@ -423,13 +531,21 @@ def main():
                 torch.cuda.empty_cache()
         extra["suite"] = table
 
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(wl)
-        extra["cpu_baseline_1thread"] = cpu_baseline(wl, budget_s=6.0, threads=1)
+    cpu, errors = None, None
+    if not args.no_cpu and not args.headline_only:
+        leg = cpu_leg(wl, {"positions": positions, "values": values}, losses)
+        cpu = leg.pop("cpu")
+        cpu["single_thread"] = leg.pop("cpu_1thread")
+        errors = leg
+    for compute in precisions:
+        if errors and compute in errors:
+            precisions[compute]["error"] = errors[compute]
+    for compute in fwd_bwd:
+        if errors and compute in errors.get("loss", {}):
+            fwd_bwd[compute]["loss_rel_err_vs_oracle"] = errors["loss"][compute]
 
     line = {
-        "metric": "effective GFLOP/s of symmetric contraction (fwd) vs FP64 plain",
+        "metric": METRIC,
         "value": round(value, 2),
         "unit": "GFLOP/s",
         "n_gpus": 1,
@@ -441,9 +557,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded Philox4x32-10, N(0,1) V, 1e-2 N(0,1) T)",
-        "config": {"workload": "ccd_ladder_z8: w_abij = sum_cd V_abcd T_cdij, Z_8, virtual block 24, "
-                               "occupied block 6, FP64; aligned product 8 x (4608 x 4608 x 288)",
-                   "group": "Z_8", "einsum": st.einsum, "flops_per_step": info.flops},
+        "config": {"workload": "ccd_ladder_z16: w_abij = sum_cd V_abcd T_cdij, Z_16, virtual block 32, "
+                               "occupied block 8, FP64, forward; aligned product 16 x (16384 x 16384 x 1024)",
+                   "group": "Z_16", "einsum": st.einsum, "flops_per_step": info.flops},
+        "error": errors["f64"] if errors else None,
+        "precisions": precisions,
+        "fwd_bwd": {"workload": "mps_env_grad: E'_ABC = E_abc A_asA W_bsSB A_cSC over Z_2 x Z_3, bond 128, "
+                                "L = <E', R>; forward and the hand-written backward (dL/dE, dL/dA, dL/dW)",
+                    **fwd_bwd} if fwd_bwd else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
