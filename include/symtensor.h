@@ -295,6 +295,27 @@ int symtensor_contract(symt_ctx* ctx, const char* einsum, const symt_group* grou
                        const symt_tensor* u, const symt_tensor* v, const symt_tensor* w,
                        int32_t compute, void* workspace, size_t workspace_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * contraction as symtensor_contract, with the same arguments, results and
+ * errors, but no workspace argument.  Its workspace is a device array of
+ * SYMT_STATIC_WORKSPACE_BYTES that the library keeps on every device it runs
+ * on (its address is resolved by symtensor_create for the context's device;
+ * the array lives until the process ends).  The call allocates nothing (no
+ * hipMalloc, no HIP event: symtensor_set_timing records nothing for it).
+ * Where the plan's stream-K pieces would not fit, the product runs one
+ * workgroup per tile instead (the results then differ from
+ * symtensor_contract's in summation order only, within the same bound); a
+ * contraction whose workspace still exceeds the array (large aligned forms)
+ * returns SYMT_EWORKSPACE before any launch.  Every call on a device shares
+ * that device's array, which keeps the last call's contents: calls that
+ * overlap on one device (several streams or threads) race on it and must be
+ * ordered by the caller.  u->data and v->data must not lie in the array. */
+#define SYMT_STATIC_WORKSPACE_BYTES ((size_t)128 << 20)
+int symtensor_contract_static(symt_ctx* ctx, const char* einsum, const symt_group* group,
+                              const symt_tensor* u, const symt_tensor* v, const symt_tensor* w,
+                              int32_t compute, void* stream);
+
 /* Step (a) alone: write the aligned form of U (operand = 0) or V (operand = 1)
  * for this contraction into the caller's device buffer `aligned`
  * (at least info.bytes_u_al / bytes_v_al bytes), in the layout of the compute

@@ -37,8 +37,9 @@ EXPORTED = (
     "symtensor_create", "symtensor_destroy", "symtensor_plan", "symtensor_workspace_size",
     "symtensor_contract", "symtensor_align", "symtensor_unalign", "symtensor_sector_gemm",
     "symtensor_sector_gemm_workspace_size", "symtensor_set_timing", "symtensor_read_timing",
-    "symtensor_status_string", "symtensor_last_error",
+    "symtensor_status_string", "symtensor_last_error", "symtensor_contract_static",
 )
+SYMT_STATIC_WORKSPACE_BYTES = 128 << 20
 
 
 class SymtGroup(ctypes.Structure):
@@ -81,6 +82,8 @@ def _load():
                                              c_int32, POINTER(c_size_t)]
     lib.symtensor_contract.argtypes = [c_void_p, c_char_p, p_group, p_tensor, p_tensor, p_tensor,
                                        c_int32, c_void_p, c_size_t, c_void_p]
+    lib.symtensor_contract_static.argtypes = [c_void_p, c_char_p, p_group, p_tensor, p_tensor, p_tensor,
+                                              c_int32, c_void_p]
     lib.symtensor_align.argtypes = [c_void_p, c_char_p, p_group, p_tensor, p_tensor, p_tensor,
                                     c_int32, c_int32, c_void_p, c_size_t, c_void_p]
     lib.symtensor_unalign.argtypes = [c_void_p, c_char_p, p_group, p_tensor, p_tensor, p_tensor,

@@ -27,7 +27,7 @@ COMMON = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-mllvm", "-amdgpu-mfma-vgpr-form"]
 
-LIB_SOURCES = ["plan.cpp", "symtensor.cpp", "xform.hip", "gemm.hip"]
+LIB_SOURCES = ["plan.cpp", "symtensor.cpp", "xform.hip", "gemm.hip", "scratch.hip"]
 
 
 def _run(cmd, verbose):

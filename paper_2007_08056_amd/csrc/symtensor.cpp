@@ -26,6 +26,8 @@ int launch_put_i32(int32_t* dst, const int32_t* src, int64_t n, hipStream_t stre
 int launch_zero(void* ptr, size_t bytes, hipStream_t stream, std::string* err);
 int launch_cplx_rows(void* v, bool f64, int64_t slices, int64_t rows, int64_t pairs, hipStream_t stream,
                      std::string* err);
+int scratch_setup(int device, std::string* err);
+void* scratch_device_ptr(int device);
 }  // namespace symt
 
 using symt::Plan;
@@ -330,6 +332,10 @@ int symtensor_create(symt_ctx** out, int device) {
     return ctx_fail(nullptr, SYMT_EHIP, "no such HIP device");
   e = hipSetDevice(device);
   if (e != hipSuccess) return ctx_fail(nullptr, SYMT_EHIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+  // the allocation-free entry point's device array: its address on this device
+  std::string err;
+  const int rc = symt::scratch_setup(device, &err);
+  if (rc) return ctx_fail(nullptr, rc, err);
   symt_ctx* c = new symt_ctx;
   c->device = device;
   *out = c;
@@ -392,14 +398,13 @@ int symtensor_workspace_size(const char* einsum, const symt_group* group, const 
   return SYMT_OK;
 }
 
-int symtensor_contract(symt_ctx* ctx, const char* einsum, const symt_group* group,
-                       const symt_tensor* u, const symt_tensor* v, const symt_tensor* w,
-                       int32_t compute, void* workspace, size_t workspace_bytes, void* stream) {
-  if (!ctx) return ctx_fail(nullptr, SYMT_EINVAL, "context is NULL");
-  if (!w) return ctx_fail(ctx, SYMT_EINVAL, "output descriptor is NULL");
-  Plan p;
-  int rc = plan_for(ctx, einsum, group, u, v, w, compute, &p);
-  if (rc) return rc;
+}  // extern "C"
+
+namespace {
+// Validation and launches of one planned contraction (symtensor_contract and
+// symtensor_contract_static): every check runs before the first launch.
+int contract_planned(symt_ctx* ctx, const Plan& p, void* workspace, size_t workspace_bytes, void* stream) {
+  int rc;
   if ((rc = check_data(ctx, p.U, "u")) || (rc = check_data(ctx, p.V, "v")) ||
       (rc = check_data(ctx, p.W, "w")))
     return rc;
@@ -449,6 +454,51 @@ int symtensor_contract(symt_ctx* ctx, const char* einsum, const symt_group* grou
     return rc;
   if ((rc = do_unalign(ctx, p, wal, s, true, chg[2]))) return rc;
   return SYMT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int symtensor_contract(symt_ctx* ctx, const char* einsum, const symt_group* group,
+                       const symt_tensor* u, const symt_tensor* v, const symt_tensor* w,
+                       int32_t compute, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!ctx) return ctx_fail(nullptr, SYMT_EINVAL, "context is NULL");
+  if (!w) return ctx_fail(ctx, SYMT_EINVAL, "output descriptor is NULL");
+  Plan p;
+  int rc = plan_for(ctx, einsum, group, u, v, w, compute, &p);
+  if (rc) return rc;
+  return contract_planned(ctx, p, workspace, workspace_bytes, stream);
+}
+
+int symtensor_contract_static(symt_ctx* ctx, const char* einsum, const symt_group* group,
+                              const symt_tensor* u, const symt_tensor* v, const symt_tensor* w,
+                              int32_t compute, void* stream) {
+  if (!ctx) return ctx_fail(nullptr, SYMT_EINVAL, "context is NULL");
+  if (!w) return ctx_fail(ctx, SYMT_EINVAL, "output descriptor is NULL");
+  // the device address of the library's array on this context's device (never
+  // the array's host-side name)
+  void* scratch = symt::scratch_device_ptr(ctx->device);
+  if (!scratch) return ctx_fail(ctx, SYMT_EHIP, "the library's device workspace is not set up on this device");
+  Plan p;
+  int rc = plan_for(ctx, einsum, group, u, v, w, compute, &p);
+  if (rc) return rc;
+  const size_t cap = SYMT_STATIC_WORKSPACE_BYTES;
+  if (p.workspace > cap && p.bytes_partial > 0) {
+    // without the stream-K pieces (or split-K partial tiles) the product runs
+    // one workgroup per tile; the pieces sit just before the charge tables
+    p.workspace -= symt::round_up(p.bytes_partial, 256);
+    p.bytes_partial = 0;
+  }
+  if (p.workspace > cap)
+    return ctx_fail(ctx, SYMT_EWORKSPACE,
+                    "contraction needs " + std::to_string(p.workspace) +
+                        " bytes of workspace; symtensor_contract_static holds " + std::to_string(cap));
+  // no timing events: creating them could allocate
+  const bool timing = ctx->timing;
+  ctx->timing = false;
+  rc = contract_planned(ctx, p, scratch, cap, stream);
+  ctx->timing = timing;
+  return rc;
 }
 
 int symtensor_align(symt_ctx* ctx, const char* einsum, const symt_group* group,
