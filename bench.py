@@ -45,7 +45,8 @@ METRIC = "effective GFLOP/s of symmetric contraction (fwd, fwd+bwd) vs FP64 plai
 # Sources that decide the sector product's machine code and launch choice;
 # stored counter readings apply only while their digest is unchanged.
 PRODUCT_SOURCES = ("paper_2007_08056_amd/csrc/gemm.hip", "paper_2007_08056_amd/csrc/plan.hpp",
-                   "paper_2007_08056_amd/csrc/plan.cpp", "paper_2007_08056_amd/build.py")
+                   "paper_2007_08056_amd/csrc/plan.cpp", "paper_2007_08056_amd/csrc/sk_index.hpp",
+                   "paper_2007_08056_amd/build.py")
 
 
 def source_digest(*rel):
