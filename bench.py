@@ -351,8 +351,9 @@ def main():
                     help="also run one plain elementwise kernel that reads and writes 256 MiB "
                          "(the reference for scaling HBM byte counters)")
     ap.add_argument("--only", default="",
-                    help="WORKLOAD/COMPUTE (e.g. ccd_ladder_z8/bf16x3): time that one workload's chain "
-                         "(as --all does), print one line and exit; for profiling runs")
+                    help="WORKLOAD/COMPUTE[/grad] (e.g. ccd_ladder_z8/bf16x3, mps_env_grad/f64/grad): time that "
+                         "one workload's chain (forward, or forward and backward), print one line and exit; "
+                         "for profiling runs")
     ap.add_argument("--headline-only", action="store_true",
                     help="time the headline step only (no precisions, fwd+bwd or CPU leg); for profiling runs")
     args = ap.parse_args()
@@ -369,17 +370,18 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    if args.only:
-        name, compute = args.only.split("/")
-        r = time_workload(P, SG, synth.configs.get(name), compute, args.steps, args.warmup)
-        print(json.dumps({"workload": name, "compute": compute, **r}), flush=True)
-        return
     if args.calibrate:
         x = torch.ones(32 * 2 ** 20, dtype=torch.float64, device=dev)
         y = torch.empty_like(x)
         torch.neg(x, out=y)
         torch.cuda.synchronize()
         del x, y
+    if args.only:
+        name, compute, *mode = args.only.split("/")
+        grad = mode == ["grad"]
+        r = time_workload(P, SG, synth.configs.get(name), compute, args.steps, args.warmup, grad=grad)
+        print(json.dumps({"workload": name, "compute": compute, "fwd+bwd": grad, **r}), flush=True)
+        return
 
     wl = synth.configs.get(WORKLOAD)
     st = wl.steps[0]

@@ -27,7 +27,10 @@ COMMON = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-mllvm", "-amdgpu-mfma-vgpr-form"]
 
-LIB_SOURCES = ["plan.cpp", "symtensor.cpp", "xform.hip", "gemm.hip", "scratch.hip"]
+LIB_SOURCES = ["plan.cpp", "symtensor.cpp", "xform.hip", "gemm.hip", "scratch.hip", "gemm_bf16x3.hip"]
+# The wide split-bf16 tiles keep their 256 accumulators in AGPRs: built without
+# the VGPR-form flag.
+NO_VGPR_FORM = {"gemm_bf16x3.hip"}
 
 
 def _run(cmd, verbose):
@@ -52,7 +55,8 @@ def build_symtensor(verbose=False) -> str:
         obj = os.path.join(bdir, src + ".o")
         objs.append(obj)
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmds.append([HIPCC] + COMMON + inc + lang + ["-c", os.path.join(csrc, src), "-o", obj])
+        flags = [f for f in COMMON if f not in ("-mllvm", "-amdgpu-mfma-vgpr-form")] if src in NO_VGPR_FORM else COMMON
+        cmds.append([HIPCC] + flags + inc + lang + ["-c", os.path.join(csrc, src), "-o", obj])
     with ThreadPoolExecutor(max_workers=min(4, len(cmds))) as ex:
         list(ex.map(lambda c: _run(c, verbose), cmds))
     out = os.path.join(HERE, "libsymtensor.so")

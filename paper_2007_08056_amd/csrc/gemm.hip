@@ -24,40 +24,13 @@
 #include <type_traits>
 
 #include "bf16_split.hpp"
+#include "gemm_common.hpp"
 #include "plan.hpp"
 #include "sk_index.hpp"
 
 namespace symt {
 
 namespace {
-
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-
-// Tile order of one-workgroup-per-tile launches: within each Q, groups of
-// kGroupM M-panels, column by column, so the workgroups in flight on an XCD
-// (a contiguous run of tiles, see xcd_remap) share A panels and B panels in L2.
-constexpr int kGroupM = 8;
-__device__ __forceinline__ void tile_coords(int64_t tile, int tiles_m, int tiles_n, int64_t& q, int& tm,
-                                            int& tn) {
-  const int64_t per_q = static_cast<int64_t>(tiles_m) * tiles_n;
-  q = tile / per_q;
-  const int64_t t = tile - q * per_q;
-  const int64_t group_tiles = static_cast<int64_t>(kGroupM) * tiles_n;
-  const int64_t g = t / group_tiles;
-  const int first_m = static_cast<int>(g * kGroupM);
-  const int gm = min(tiles_m - first_m, kGroupM);
-  const int r = static_cast<int>(t - g * group_tiles);
-  tm = first_m + r % gm;
-  tn = r / gm;
-}
-
-__device__ __forceinline__ int64_t xcd_remap(int64_t wg, int64_t n) {
-  const int64_t per = n / 8;
-  if (wg >= per * 8) return wg;
-  return (wg % 8) * per + wg / 8;
-}
 
 template <typename T>
 struct Mfma;
@@ -78,11 +51,6 @@ struct Mfma<float> {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
-};
-
-template <typename T, int V>
-struct alignas(sizeof(T) * V) VecT {
-  T v[V];
 };
 
 // ---------------------------------------------------------------------------
@@ -374,19 +342,6 @@ __global__ __launch_bounds__(64 * WM * WN) void k_split_sum(const T* __restrict_
 // the MFMA fragment reads free of bank conflicts.  Needs K % BK == 0; rows and
 // columns past M and N are clamped on load and never stored.
 // ---------------------------------------------------------------------------
-typedef __attribute__((address_space(1))) void* gptr_t;
-typedef __attribute__((address_space(3))) void* lptr_t;
-__device__ __forceinline__ void lds_dma16(const void* g, void* lds) {
-  __builtin_amdgcn_global_load_lds((gptr_t)(g), (lptr_t)(lds), 16, 0, 0);
-}
-
-// s_waitcnt with vmcnt <= n and the other counters untouched (gfx9 encoding).
-template <int N>
-__device__ __forceinline__ void wait_vmcnt() {
-  static_assert(N >= 0 && N < 64, "vmcnt");
-  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
-}
-
 // Geometry of a global-to-LDS tile: BM x BN outputs, K-steps of one 128-byte
 // A row, S LDS stages, WM x WN waves.
 template <typename T, int BM, int BN, int WM, int WN, int S>
@@ -1291,6 +1246,11 @@ hipError_t launch_fp_tile(int idx, int vec, int64_t batch, int M, int N, int K, 
 
 }  // namespace
 
+// Wide split-bf16 tiles with one binary32 accumulator (gemm_bf16x3.hip).
+hipError_t launch_bf16x3_wide(int variant, int64_t batch, int M, int N, int K, const void* A, const void* B,
+                              void* C, hipStream_t s, int64_t pa, int64_t pb, const int64_t* rc,
+                              const int64_t* cc, int c_bytes);
+
 // plane_a / plane_b (split-bf16 only): elements from a hi plane to its lo
 // plane, 0 for the packed layout (batch * m * k, batch * n * k).
 int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t n, const void* A,
@@ -1328,7 +1288,9 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
           : t == 2 ? launch_bf16x3_fused<128, 256, 32, 2, 4>(batch, M, N, K, A, B, C, stream, pb, fused)
           : t == 3 ? launch_bf16x3_fused<128, 96, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pb, fused)
                    : launch_bf16x3_fused<128, 128, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pb, fused);
-    } else if (f == "bd256x128s3" && dma_ok) e = launch_bf16x3_dma<256, 128, 4, 2, 3>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
+    } else if (f == "bw256x256s2" && dma_ok) e = launch_bf16x3_wide(0, batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
+    else if (f == "bw256x128s3" && dma_ok) e = launch_bf16x3_wide(1, batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
+    else if (f == "bd256x128s3" && dma_ok) e = launch_bf16x3_dma<256, 128, 4, 2, 3>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
     else if (f == "bd128x256s3" && dma_ok) e = launch_bf16x3_dma<128, 256, 2, 4, 3>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
     else if (f == "b128x128k64") e = launch_bf16x3<128, 128, 64, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
     else if (f == "b128x128k32") e = launch_bf16x3<128, 128, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
@@ -1337,6 +1299,8 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
     else if (f == "b128x64k32") e = launch_bf16x3<128, 64, 32, 4, 1>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
     else if (f == "b128x96k32") e = launch_bf16x3<128, 96, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
     else if (f == "b64x64k32") e = launch_bf16x3<64, 64, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
+    else if (dma_ok && f.empty() && bf16x3_wide_tile(batch, M, N) >= 0)
+      e = launch_bf16x3_wide(bf16x3_wide_tile(batch, M, N), batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
     else if (dma_ok && f.empty() && M >= 256 && N >= 512)
       e = launch_bf16x3_dma<128, 256, 2, 4, 3>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
     else if (N <= 64)

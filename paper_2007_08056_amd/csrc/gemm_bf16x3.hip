@@ -1,0 +1,192 @@
+// Split-bf16 sector product on wide global-to-LDS tiles (Alg. 2's product step
+// in the split-bfloat16 precision form): C[Q] = A[Q] B[Q] with A = Ahi + Alo and
+// B = Bhi + Blo given as bf16 planes (A [Q][M][K], B [Q][N][K], K fastest), C as
+// binary64 (aligned W, or W's standard form through its offset tables).
+//
+// Each workgroup owns a BM x BN output tile with WM x WN waves; a wave owns a
+// (BM/WM) x (BN/WN) block of 16 x 16 MFMA tiles (v_mfma_f32_16x16x32_bf16) and
+// keeps ONE binary32 accumulator per output element, into which it adds
+// Ahi*Bhi, Ahi*Blo and Alo*Bhi.  One accumulator (rather than one for hi*hi and
+// one for the cross terms) halves the accumulator registers, so each wave can
+// hold a 128 x 128 block: every 16-byte operand fragment read from LDS then
+// feeds 24 MFMAs instead of 12, which is what keeps the product off the LDS
+// bandwidth limit.  The accumulators live in AGPRs, so this file is compiled
+// without the VGPR-form flag of the other product kernels.
+//
+// K-steps are 32 deep (one MFMA); each stage of the LDS ring holds one K-step
+// of the four planes, loaded with global_load_lds (16 bytes per lane) into
+// rows of 64 bytes whose four chunks are XOR-swizzled by ((row >> 1) & 3), so
+// the fragment reads of 8 consecutive rows fall on distinct banks.  Rows past M
+// or N are clamped on load and never stored; K must be a multiple of 32.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "gemm_common.hpp"
+#include "plan.hpp"
+
+namespace symt {
+
+namespace {
+
+template <int BM, int BN, int WM, int WN, int S, bool FC, typename TC>
+__global__ __launch_bounds__(64 * WM * WN, 1) void k_bf16x3_wide(
+    const uint16_t* __restrict__ Ahi, const uint16_t* __restrict__ Alo, const uint16_t* __restrict__ Bhi,
+    const uint16_t* __restrict__ Blo, TC* __restrict__ C, int M, int N, int K, int tiles_m, int tiles_n,
+    int64_t ntiles, const int64_t* __restrict__ rc, const int64_t* __restrict__ cc) {
+  constexpr int NT = 64 * WM * WN;
+  constexpr int BK = 32;
+  constexpr int TM = BM / WM / 16;
+  constexpr int TN = BN / WN / 16;
+  constexpr int A_LOADS = BM * 8 / NT;            // 16-byte chunks of both A planes per thread
+  constexpr int B_LOADS = BN * 8 / NT;
+  constexpr int PA = BM * 64, PB = BN * 64;       // bytes per plane per stage
+  constexpr int STAGE = 2 * PA + 2 * PB;
+  static_assert(TM * WM * 16 == BM && TN * WN * 16 == BN, "tile shape");
+  static_assert(A_LOADS * NT == BM * 8 && B_LOADS * NT == BN * 8, "loads must divide evenly");
+  static_assert(S >= 2 && S * STAGE <= 160 * 1024, "LDS ring");
+  static_assert(FC || std::is_same<TC, double>::value, "aligned W is binary64");
+  __shared__ __attribute__((aligned(1024))) char smem[S * STAGE];
+
+  const int64_t tile = xcd_remap(blockIdx.x, ntiles);
+  int64_t q;
+  int tm, tn;
+  tile_coords(tile, tiles_m, tiles_n, q, tm, tn);
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm0 = (wave / WN) * (BM / WM);
+  const int wn0 = (wave % WN) * (BN / WN);
+  const int64_t offA = q * static_cast<int64_t>(M) * K;
+  const int64_t offB = q * static_cast<int64_t>(N) * K;
+
+  // Load slot s = tid + i * NT covers [plane][row][chunk]; LDS position c of row
+  // r holds global chunk c ^ ((r >> 1) & 3).
+  const uint16_t* a_src[A_LOADS];
+#pragma unroll
+  for (int i = 0; i < A_LOADS; ++i) {
+    const int slot = tid + i * NT;
+    const int plane = slot / (BM * 4);
+    const int rem = slot - plane * (BM * 4);
+    const int r = rem >> 2, c = rem & 3;
+    const int gr = min(m0 + r, M - 1);
+    a_src[i] = (plane ? Alo : Ahi) + offA + static_cast<int64_t>(gr) * K + (c ^ ((r >> 1) & 3)) * 8;
+  }
+  const uint16_t* b_src[B_LOADS];
+#pragma unroll
+  for (int i = 0; i < B_LOADS; ++i) {
+    const int slot = tid + i * NT;
+    const int plane = slot / (BN * 4);
+    const int rem = slot - plane * (BN * 4);
+    const int r = rem >> 2, c = rem & 3;
+    const int gr = min(n0 + r, N - 1);
+    b_src[i] = (plane ? Blo : Bhi) + offB + static_cast<int64_t>(gr) * K + (c ^ ((r >> 1) & 3)) * 8;
+  }
+  auto issue = [&](int kt, int stage) {
+    const int k0 = kt * BK;
+    char* base = smem + stage * STAGE;
+#pragma unroll
+    for (int i = 0; i < A_LOADS; ++i) lds_dma16(a_src[i] + k0, base + (i * NT + wave * 64) * 16);
+#pragma unroll
+    for (int i = 0; i < B_LOADS; ++i) lds_dma16(b_src[i] + k0, base + 2 * PA + (i * NT + wave * 64) * 16);
+  };
+
+  f4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f4{};
+
+  const int nk = K / BK;
+  const int kc = lane >> 4;                       // operand chunk: k = 8 * kc .. 8 * kc + 7
+#pragma unroll
+  for (int s = 0; s < S - 1; ++s)
+    if (s < nk) issue(s, s);
+  for (int kt = 0; kt < nk; ++kt) {
+    // step kt has landed once at most (S - 2) later steps' loads are outstanding
+    if (kt + S - 2 < nk) wait_vmcnt<(S - 2) * (A_LOADS + B_LOADS)>();
+    else wait_vmcnt<0>();
+    // a plain barrier: the wait above covers this wave's loads of step kt, and
+    // every wave has finished reading the stage that the next issue overwrites
+    asm volatile("s_barrier" ::: "memory");
+    if (kt + S - 1 < nk) issue(kt + S - 1, (kt + S - 1) % S);
+    const char* base = smem + (kt % S) * STAGE;
+    bf8 ah[TM], al[TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int r = wm0 + i * 16 + (lane & 15);
+      const int off = r * 64 + ((kc ^ ((r >> 1) & 3)) << 4);
+      ah[i] = *reinterpret_cast<const bf8*>(base + off);
+      al[i] = *reinterpret_cast<const bf8*>(base + PA + off);
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int r = wn0 + j * 16 + (lane & 15);
+      const int off = 2 * PA + r * 64 + ((kc ^ ((r >> 1) & 3)) << 4);
+      const bf8 bh = *reinterpret_cast<const bf8*>(base + off);
+      const bf8 bl = *reinterpret_cast<const bf8*>(base + PB + off);
+      // consecutive MFMAs update different accumulators (no dependent back-to-back pairs)
+#pragma unroll
+      for (int i = 0; i < TM; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < TM; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < TM; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+    }
+  }
+
+  // 16x16x32 bf16 accumulator layout: lane l, item r holds row 4 (l / 16) + r, column l % 16
+  TC* Cq = C + (FC ? 0 : q * static_cast<int64_t>(M) * N);
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int col = n0 + wn0 + j * 16 + (lane & 15);
+    const int64_t ccol = (FC && col < N) ? cc[q * N + col] : col;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm0 + i * 16 + 4 * (lane >> 4) + r;
+        if (row < M && col < N) {
+          const int64_t crow = FC ? rc[q * M + row] : static_cast<int64_t>(row) * N;
+          Cq[crow + ccol] = static_cast<TC>(acc[i][j][r]);
+        }
+      }
+  }
+}
+
+template <int BM, int BN, int WM, int WN, int S>
+hipError_t launch_wide(int64_t batch, int M, int N, int K, const void* A, const void* B, void* C, hipStream_t s,
+                       int64_t pa, int64_t pb, const int64_t* rc, const int64_t* cc, int c_bytes) {
+  const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
+  const int64_t ntiles = batch * tiles_m * tiles_n;
+  const dim3 grid(static_cast<unsigned>(ntiles)), block(64 * WM * WN);
+  const uint16_t* a = static_cast<const uint16_t*>(A);
+  const uint16_t* b = static_cast<const uint16_t*>(B);
+  if (rc && c_bytes == 4)
+    hipLaunchKernelGGL((k_bf16x3_wide<BM, BN, WM, WN, S, true, float>), grid, block, 0, s, a, a + pa, b, b + pb,
+                       static_cast<float*>(C), M, N, K, tiles_m, tiles_n, ntiles, rc, cc);
+  else if (rc)
+    hipLaunchKernelGGL((k_bf16x3_wide<BM, BN, WM, WN, S, true, double>), grid, block, 0, s, a, a + pa, b, b + pb,
+                       static_cast<double*>(C), M, N, K, tiles_m, tiles_n, ntiles, rc, cc);
+  else
+    hipLaunchKernelGGL((k_bf16x3_wide<BM, BN, WM, WN, S, false, double>), grid, block, 0, s, a, a + pa, b,
+                       b + pb, static_cast<double*>(C), M, N, K, tiles_m, tiles_n, ntiles, rc, cc);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// Wide split-bf16 tiles: 0 = 256 x 256 (4 waves of 128 x 128, two LDS stages),
+// 1 = 256 x 128 (4 waves of 128 x 64, three stages).  pa / pb: elements from
+// each hi plane to its lo plane; rc / cc: W's offset tables (nullptr: C is the
+// aligned W, binary64).  Needs K % 32 == 0 and 16-byte aligned planes.
+hipError_t launch_bf16x3_wide(int variant, int64_t batch, int M, int N, int K, const void* A, const void* B,
+                              void* C, hipStream_t s, int64_t pa, int64_t pb, const int64_t* rc,
+                              const int64_t* cc, int c_bytes) {
+  if (variant == 1) return launch_wide<256, 128, 2, 2, 3>(batch, M, N, K, A, B, C, s, pa, pb, rc, cc, c_bytes);
+  return launch_wide<256, 256, 2, 2, 2>(batch, M, N, K, A, B, C, s, pa, pb, rc, cc, c_bytes);
+}
+
+}  // namespace symt

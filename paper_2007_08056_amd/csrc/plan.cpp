@@ -704,11 +704,25 @@ bool bf16x3_register_tile(int64_t M, int64_t N, int64_t K) {
   const char* forced = std::getenv("SYMT_GEMM_TILE");
   const std::string f = forced ? forced : "";
   const bool dma_ok = K % 32 == 0;
-  if ((f == "bd256x128s3" || f == "bd128x256s3") && dma_ok) return false;
+  if ((f == "bd256x128s3" || f == "bd128x256s3" || f == "bw256x256s2" || f == "bw256x128s3") && dma_ok)
+    return false;
   if (f == "b128x128k64" || f == "b128x128k32" || f == "b256x128k32" || f == "b128x256k32" ||
       f == "b128x64k32" || f == "b128x96k32" || f == "b64x64k32")
     return true;
   return !(dma_ok && M >= 256 && N >= 512);
+}
+
+int bf16x3_wide_tile(int64_t batch, int64_t M, int64_t N) {
+  if (M < 256) return -1;
+  for (int v = 0; v < 2; ++v) {
+    const int64_t bn = v == 0 ? 256 : 128;
+    if (N < bn) continue;
+    const int64_t tn = (N + bn - 1) / bn;
+    if (8 * (tn * bn - N) > N) continue;                       // padded columns above 1/8
+    if (batch * ((M + 255) / 256) * tn < 256) continue;        // fewer tiles than CUs
+    return v;
+  }
+  return -1;
 }
 
 int bf16x3_fused_tile(int64_t M, int64_t N) {

@@ -242,6 +242,10 @@ GemmChoice choose_fp_gemm(int64_t batch, int64_t M, int64_t N, int64_t K, int el
 // register tiles it takes (0: 128 x 64, 1: 128 x 128, 2: 128 x 256, 3: 128 x 96).
 bool bf16x3_register_tile(int64_t M, int64_t N, int64_t K);
 int bf16x3_fused_tile(int64_t M, int64_t N);
+// Wide split-bf16 tile of the global-to-LDS product on bf16 planes (0: 256 x 256,
+// 1: 256 x 128, one binary32 accumulator), or -1 where N pads by more than an
+// eighth or the launch has fewer tiles than the device has CUs.
+int bf16x3_wide_tile(int64_t batch, int64_t M, int64_t N);
 
 // True when the aligned form of operand 0 (U), 1 (V) or 2 (W) is zero outside
 // slice q_pin: U_al carries deltas (1) and (2), V_al (2) and (3), W_al is their

@@ -66,13 +66,15 @@ def bound_factor(compute: str, k: int) -> float:
     f64: two summation orders (kernel and oracle), gamma_k(u64) each.
     f32: inputs rounded to binary32 (u32 each) plus binary32 accumulation.
     bf16x3: hi + lo keeps 16 bits of each binary32 input, the dropped lo*lo term
-    is below 2^-16 of the product, plus binary32 accumulation of two sums.
+    is below 2^-16 of the product, plus binary32 accumulation of the 3k products
+    (hi*hi, hi*lo, lo*hi: one accumulator on the wide tiles; their |terms| sum to
+    at most 1.01 |a||b|).
     """
     if compute == "f64":
         return 2.0 * gamma(k, U64)
     if compute == "f32":
         return 2.1 * U32 + 1.05 * gamma(k, U32) + gamma(k, U64)
-    return 3.1 * U_BF16_PAIR + 2.1 * U32 + 1.1 * gamma(k, U32) + gamma(k, U64)
+    return 3.1 * U_BF16_PAIR + 2.1 * U32 + 1.02 * gamma(3 * k, U32) + gamma(k, U64)
 
 
 def to_np(t: torch.Tensor) -> np.ndarray:
