@@ -148,6 +148,8 @@
  *   SYMT_GEMM_SK=0 | 1     0 forbids stream-K and split K; 1 forces stream-K on
  *                          the global-to-LDS tiles.
  *   SYMT_FUSED_V=0         keeps V aligned in the fused product (info.fused_v = 0).
+ *   SYMT_GEMM_GROUP_M=<n>  M-panels per group in the tile order of the wide
+ *                          split-bf16 tiles (default 8).
  */
 #ifndef SYMTENSOR_H
 #define SYMTENSOR_H

@@ -580,46 +580,98 @@ __global__ __launch_bounds__(64 * WM * WN, (kDmaWavesPerSimd<BM, BN, S>)) void k
 }
 
 // Sums the pieces of every tile that stream-K cut, in increasing K order (so
-// the result does not depend on scheduling), and writes the tile.  One
-// workgroup per tile; tiles covered whole by one team return at once.
+// the result does not depend on scheduling), and writes the tile.  Workgroup
+// (tile, chunk) handles the chunk-th of `chunks` equal ranges of the tile's
+// elements in accumulator order (a tile spread over many teams -- long K, few
+// tiles -- is summed by many workgroups); tiles covered whole by one team
+// return at once.  Each element's sum starts from zero and adds the pieces in
+// team order: the same arithmetic whatever `chunks` is.
 template <typename T, int BM, int BN, int WM, int WN, bool FC>
 __global__ __launch_bounds__(64 * WM * WN) void k_sk_fixup(
     const T* __restrict__ part, T* __restrict__ C, int M, int N, int nk, int tiles_m, int tiles_n,
     int64_t ntiles, int ts, int nteam, const int64_t* __restrict__ rc, const int64_t* __restrict__ cc) {
   constexpr int TM = BM / WM / 16, TN = BN / WN / 16;
-  using Acc = typename Mfma<T>::Acc;
+  constexpr int E = BM * BN;                      // elements of a tile (= of a piece)
+  constexpr int PER_WAVE = TM * TN * 4 * 64;
   const int64_t tile = blockIdx.x;
+  const int chunks = static_cast<int>(gridDim.y);
   const int64_t grp = tile / ts;
   const int member = static_cast<int>(tile - grp * ts);
   const int64_t total = ntiles / ts * nk;
   const int64_t x0 = grp * nk, x1 = x0 + nk;
   // last team whose share starts at or before x0 (its share is not empty)
-  int64_t t = sk_first_team(x0, total, nteam);
-  if (sk_bound(t + 1, total, nteam) >= x1) return;
-  Acc acc[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = Acc{};
-  const int lane = threadIdx.x & 63;
-  for (; t < nteam; ++t) {
-    const int64_t b0 = sk_bound(t, total, nteam), b1 = sk_bound(t + 1, total, nteam);
-    if (b0 >= x1) break;
-    if (b1 == b0) continue;
-    const T* pw = part + sk_piece(static_cast<int>(t), member, ts, grp, b0 / nk) * (BM * BN) +
-                  (threadIdx.x >> 6) * (TM * TN * 4 * 64) + lane;
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-      for (int j = 0; j < TN; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[i][j][r] += pw[((i * TN + j) * 4 + r) * 64];
+  const int64_t t_first = sk_first_team(x0, total, nteam);
+  if (sk_bound(t_first + 1, total, nteam) >= x1) return;
+  // teams t_first .. t_last hold the tile's pieces (the last one holds iteration
+  // x1 - 1); their piece offsets go to LDS once (-1: a team with an empty share)
+  constexpr int kList = 1024;
+  __shared__ int64_t list[kList];
+  const int64_t n_teams = sk_first_team(x1 - 1, total, nteam) - t_first + 1;
+  const bool listed = n_teams <= kList;
+  if (listed) {
+    for (int k = static_cast<int>(threadIdx.x); k < n_teams; k += static_cast<int>(blockDim.x)) {
+      const int64_t t = t_first + k;
+      const int64_t b0 = sk_bound(t, total, nteam), b1 = sk_bound(t + 1, total, nteam);
+      list[k] = b1 > b0 ? sk_piece(static_cast<int>(t), member, ts, grp, b0 / nk) * E : -1;
+    }
+    __syncthreads();
   }
   const int tn = static_cast<int>(tile % tiles_n);
   const int64_t t2 = tile / tiles_n;
   const int tm = static_cast<int>(t2 % tiles_m);
   const int64_t q = t2 / tiles_m;
-  store_tile<T, BM, BN, WM, WN, TM, TN, FC>(C, M, N, q, tm * BM, tn * BN, rc, cc, acc);
+  T* Cq = C + (FC ? 0 : q * static_cast<int64_t>(M) * N);
+  const int per = (E + chunks - 1) / chunks;
+  const int e0 = static_cast<int>(blockIdx.y) * per;
+  const int e1 = min(E, e0 + per);
+  // accumulator order: element ((w * TM + i) * TN + j) * 4 + r of lane l at 64 * that + l
+  auto store = [&](int e, T v) {
+    const int w = e / PER_WAVE;
+    const int rem = e - w * PER_WAVE;
+    const int lane = rem & 63;
+    const int ijr = rem >> 6;
+    const int r = ijr & 3;
+    const int ij = ijr >> 2;
+    const int i = ij / TN, j = ij - (ij / TN) * TN;
+    const int row = tm * BM + (w / WN) * (BM / WM) + i * 16 + Mfma<T>::row(lane, r);
+    const int col = tn * BN + (w % WN) * (BN / WN) + j * 16 + (lane & 15);
+    if (row < M && col < N) {
+      const int64_t crow = FC ? rc[q * M + row] : static_cast<int64_t>(row) * N;
+      const int64_t ccol = FC ? cc[q * N + col] : col;
+      Cq[crow + ccol] = v;
+    }
+  };
+  constexpr int NT = 64 * WM * WN;
+  constexpr int U = 4;                            // elements in flight per thread
+  for (int e = e0 + static_cast<int>(threadIdx.x); e < e1; e += U * NT) {
+    T acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] = T(0);
+    if (listed) {
+#pragma unroll 4
+      for (int k = 0; k < static_cast<int>(n_teams); ++k) {
+        const int64_t off = list[k];
+        if (off >= 0) {
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            if (e + u * NT < e1) acc[u] += part[off + e + u * NT];
+        }
+      }
+    } else {
+      for (int64_t t = t_first; t < nteam; ++t) {
+        const int64_t b0 = sk_bound(t, total, nteam), b1 = sk_bound(t + 1, total, nteam);
+        if (b0 >= x1) break;
+        if (b1 == b0) continue;
+        const int64_t off = sk_piece(static_cast<int>(t), member, ts, grp, b0 / nk) * E;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (e + u * NT < e1) acc[u] += part[off + e + u * NT];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (e + u * NT < e1) store(e + u * NT, acc[u]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1208,12 +1260,21 @@ hipError_t launch_dma(int64_t batch, int M, int N, int K, const void* A, const v
     hipError_t e = launch_dma_kernel<T, BM, BN, WM, WN, S, true>(mode, dim3(P), block, s, a, b, c, M, N, K,
                                                                  tiles_m, tiles_n, ntiles, f, pt, ts);
     if (e != hipSuccess) return e;
+    // a tile spans about nk / (iterations per team) + 1 teams' pieces: the sum of
+    // a tile goes to at least 4 workgroups (8192 elements each would leave one
+    // workgroup per compute unit waiting on memory), more when the tile has many
+    // pieces, down to one element per thread
+    const int64_t per_team = std::max<int64_t>(1, (ntiles / ts) * nk / nteam);
+    const int64_t spans = nk / per_team + 1;
+    const int64_t max_chunks = std::max<int64_t>(1, static_cast<int64_t>(BM) * BN / (64 * WM * WN));
+    const dim3 fgrid(static_cast<unsigned>(ntiles),
+                     static_cast<unsigned>(std::min<int64_t>(max_chunks, std::max<int64_t>(4, spans))));
     if (f)
-      hipLaunchKernelGGL((k_sk_fixup<T, BM, BN, WM, WN, true>), dim3(static_cast<unsigned>(ntiles)),
-                         block, 0, s, pt, c, M, N, nk, tiles_m, tiles_n, ntiles, ts, nteam, rc, cc);
+      hipLaunchKernelGGL((k_sk_fixup<T, BM, BN, WM, WN, true>), fgrid, block, 0, s, pt, c, M, N, nk, tiles_m,
+                         tiles_n, ntiles, ts, nteam, rc, cc);
     else
-      hipLaunchKernelGGL((k_sk_fixup<T, BM, BN, WM, WN, false>), dim3(static_cast<unsigned>(ntiles)),
-                         block, 0, s, pt, c, M, N, nk, tiles_m, tiles_n, ntiles, ts, nteam, rc, cc);
+      hipLaunchKernelGGL((k_sk_fixup<T, BM, BN, WM, WN, false>), fgrid, block, 0, s, pt, c, M, N, nk, tiles_m,
+                         tiles_n, ntiles, ts, nteam, rc, cc);
     return hipGetLastError();
   }
   return launch_dma_kernel<T, BM, BN, WM, WN, S, false>(mode, dim3(static_cast<unsigned>(ntiles)), block, s, a,

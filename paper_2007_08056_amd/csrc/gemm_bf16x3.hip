@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
 #include <type_traits>
 
 #include "gemm_common.hpp"
@@ -34,7 +35,7 @@ template <int BM, int BN, int WM, int WN, int S, bool FC, typename TC>
 __global__ __launch_bounds__(64 * WM * WN, 1) void k_bf16x3_wide(
     const uint16_t* __restrict__ Ahi, const uint16_t* __restrict__ Alo, const uint16_t* __restrict__ Bhi,
     const uint16_t* __restrict__ Blo, TC* __restrict__ C, int M, int N, int K, int tiles_m, int tiles_n,
-    int64_t ntiles, const int64_t* __restrict__ rc, const int64_t* __restrict__ cc) {
+    int64_t ntiles, const int64_t* __restrict__ rc, const int64_t* __restrict__ cc, int group_m) {
   constexpr int NT = 64 * WM * WN;
   constexpr int BK = 32;
   constexpr int TM = BM / WM / 16;
@@ -52,7 +53,7 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void k_bf16x3_wide(
   const int64_t tile = xcd_remap(blockIdx.x, ntiles);
   int64_t q;
   int tm, tn;
-  tile_coords(tile, tiles_m, tiles_n, q, tm, tn);
+  tile_coords(tile, tiles_m, tiles_n, q, tm, tn, group_m);
   const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -164,15 +165,22 @@ hipError_t launch_wide(int64_t batch, int M, int N, int K, const void* A, const 
   const dim3 grid(static_cast<unsigned>(ntiles)), block(64 * WM * WN);
   const uint16_t* a = static_cast<const uint16_t*>(A);
   const uint16_t* b = static_cast<const uint16_t*>(B);
+  // M-panels per group of the tile order (each XCD runs a contiguous range of
+  // tiles, so the workgroups in flight on one XCD are group_m M-panels by a few
+  // N-tiles); 8 measured best on the Z_16 ladder (4 to 64 tried).
+  // SYMT_GEMM_GROUP_M overrides it (tuning only).
+  const char* gm_env = std::getenv("SYMT_GEMM_GROUP_M");
+  int gm = gm_env ? std::atoi(gm_env) : 8;
+  if (gm < 1) gm = 1;
   if (rc && c_bytes == 4)
     hipLaunchKernelGGL((k_bf16x3_wide<BM, BN, WM, WN, S, true, float>), grid, block, 0, s, a, a + pa, b, b + pb,
-                       static_cast<float*>(C), M, N, K, tiles_m, tiles_n, ntiles, rc, cc);
+                       static_cast<float*>(C), M, N, K, tiles_m, tiles_n, ntiles, rc, cc, gm);
   else if (rc)
     hipLaunchKernelGGL((k_bf16x3_wide<BM, BN, WM, WN, S, true, double>), grid, block, 0, s, a, a + pa, b, b + pb,
-                       static_cast<double*>(C), M, N, K, tiles_m, tiles_n, ntiles, rc, cc);
+                       static_cast<double*>(C), M, N, K, tiles_m, tiles_n, ntiles, rc, cc, gm);
   else
     hipLaunchKernelGGL((k_bf16x3_wide<BM, BN, WM, WN, S, false, double>), grid, block, 0, s, a, a + pa, b,
-                       b + pb, static_cast<double*>(C), M, N, K, tiles_m, tiles_n, ntiles, rc, cc);
+                       b + pb, static_cast<double*>(C), M, N, K, tiles_m, tiles_n, ntiles, rc, cc, gm);
   return hipGetLastError();
 }
 

@@ -19,14 +19,14 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 // (a contiguous run of tiles, see xcd_remap) share A panels and B panels in L2.
 constexpr int kGroupM = 8;
 __device__ __forceinline__ void tile_coords(int64_t tile, int tiles_m, int tiles_n, int64_t& q, int& tm,
-                                            int& tn) {
+                                            int& tn, int group_m = kGroupM) {
   const int64_t per_q = static_cast<int64_t>(tiles_m) * tiles_n;
   q = tile / per_q;
   const int64_t t = tile - q * per_q;
-  const int64_t group_tiles = static_cast<int64_t>(kGroupM) * tiles_n;
+  const int64_t group_tiles = static_cast<int64_t>(group_m) * tiles_n;
   const int64_t g = t / group_tiles;
-  const int first_m = static_cast<int>(g * kGroupM);
-  const int gm = min(tiles_m - first_m, kGroupM);
+  const int first_m = static_cast<int>(g * group_m);
+  const int gm = min(tiles_m - first_m, group_m);
   const int r = static_cast<int>(t - g * group_tiles);
   tm = first_m + r % gm;
   tn = r / gm;

@@ -1007,10 +1007,15 @@ XformParams make_xform(const Plan& p, int operand, bool to_aligned, int in_bytes
     // workgroups (a whole matrix block can be a single run).
     x.run_chunk = x.run_len > 16384 ? 8192 : std::max<int64_t>(x.run_len, 1);
     x.run_tiles = (x.run_len + x.run_chunk - 1) / x.run_chunk;
-    int64_t rpt = std::max<int64_t>(1, 32768 / std::max<int64_t>(1, x.run_chunk * in_bytes));
+    // rows per workgroup: about 64 KB of source each (short runs take many rows,
+    // moved 256 at a time), so the per-workgroup block arithmetic stays small
+    int64_t rpt = std::max<int64_t>(1, 65536 / std::max<int64_t>(1, x.run_chunk * in_bytes));
     rpt = std::max<int64_t>(rpt, 256 / lanes);
-    rpt = std::min<int64_t>(rpt, 256);
+    rpt = std::min<int64_t>(rpt, 4096);
     rpt = std::min<int64_t>(rpt, x.rows);
+    // ... but keep at least 8192 workgroups (32 per compute unit) where the rows allow
+    const int64_t floor_rpt = std::max<int64_t>(1, 256 / lanes);
+    while (rpt > floor_rpt && rpt > 256 && x.nblocks * ((x.rows + rpt - 1) / rpt) * x.run_tiles < 8192) rpt /= 2;
     x.rows_per_tile = std::max<int64_t>(rpt, 1);
     x.tiles_per_block = (x.rows + x.rows_per_tile - 1) / x.rows_per_tile * x.run_tiles;
   } else {

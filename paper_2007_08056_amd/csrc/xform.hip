@@ -77,9 +77,16 @@ __global__ __launch_bounds__(256) void k_xform_copy(const Tin* __restrict__ src,
   if (!live && !p.to_aligned) return;
   const int64_t src_base = p.to_aligned ? sb : ab;
   const int64_t dst_base = p.to_aligned ? ab : sb;
-  const int64_t r0 = row_tile * p.rows_per_tile;
-  const int64_t left = p.rows - r0;
-  const int nr = static_cast<int>(left < p.rows_per_tile ? left : p.rows_per_tile);
+  // this workgroup's rows [r_begin, r_end), moved 256 at a time (their offsets in LDS)
+  const int64_t r_begin = row_tile * p.rows_per_tile;
+  const int64_t r_end = r_begin + p.rows_per_tile < p.rows ? r_begin + p.rows_per_tile : p.rows;
+  const int lane = threadIdx.x & (p.lanes_per_row - 1);
+  const int sub = threadIdx.x >> p.lanes_log2;
+  const int rpp = blockDim.x >> p.lanes_log2;
+  const int64_t step = static_cast<int64_t>(p.lanes_per_row) * V;
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += 256) {
+  const int nr = static_cast<int>(r_end - r0 < 256 ? r_end - r0 : 256);
+  if (r0 > r_begin) __syncthreads();             // the previous rows' offsets are no longer read
   for (int r = threadIdx.x; r < nr; r += blockDim.x) {
     int64_t rem = r0 + r, so = 0, dof = 0;
     for (int i = p.nbatch - 1; i >= 0; --i) {
@@ -93,10 +100,6 @@ __global__ __launch_bounds__(256) void k_xform_copy(const Tin* __restrict__ src,
     doff[r] = dst_base + dof;
   }
   __syncthreads();
-  const int lane = threadIdx.x & (p.lanes_per_row - 1);
-  const int sub = threadIdx.x >> p.lanes_log2;
-  const int rpp = blockDim.x >> p.lanes_log2;
-  const int64_t step = static_cast<int64_t>(p.lanes_per_row) * V;
   for (int r = sub; r < nr; r += rpp) {
     const int64_t s0 = soff[r], d0 = doff[r];
     for (int64_t c = c_begin + static_cast<int64_t>(lane) * V; c < c_end; c += step) {
@@ -116,6 +119,7 @@ __global__ __launch_bounds__(256) void k_xform_copy(const Tin* __restrict__ src,
         store_vec<OUT, V>(dst, d0 + c, p.plane, x);
       }
     }
+  }
   }
 }
 
@@ -205,16 +209,18 @@ hipError_t launch_typed(const XformParams& p, const void* src, void* dst, hipStr
   return hipGetLastError();
 }
 
+// (I: the index type, 32-bit when every table's entry count fits)
+template <typename I>
 __global__ __launch_bounds__(256) void k_offsets(const OffsetBatch b) {
-  const int64_t total = b.n > 0 ? b.end[b.n - 1] : 0;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += stride) {
+  const I total = static_cast<I>(b.n > 0 ? b.end[b.n - 1] : 0);
+  const I stride = static_cast<I>(gridDim.x) * blockDim.x;
+  for (I i = static_cast<I>(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += stride) {
     int t = 0;
     while (i >= b.end[t]) ++t;
-    const int64_t j = i - (t > 0 ? b.end[t - 1] : 0);
+    const I j = i - static_cast<I>(t > 0 ? b.end[t - 1] : 0);
     const OffsetParams& p = b.t[t];
-    const int q = static_cast<int>(j / p.count);
-    b.out[t][j] = table_entry(p, q, j - q * p.count);
+    const int q = static_cast<int>(j / static_cast<I>(p.count));
+    b.out[t][j] = table_entry(p, q, j - static_cast<I>(q) * static_cast<I>(p.count));
   }
 }
 
@@ -311,7 +317,10 @@ int launch_offsets(const OffsetBatch& batch, hipStream_t stream, std::string* er
   if (total == 0) return SYMT_OK;
   int64_t blocks = (total + 255) / 256;
   if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_offsets, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, batch);
+  if (total + static_cast<int64_t>(blocks) * 256 <= INT32_MAX)
+    hipLaunchKernelGGL(k_offsets<int32_t>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, batch);
+  else
+    hipLaunchKernelGGL(k_offsets<int64_t>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, batch);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     if (err) *err = std::string("offset table launch: ") + hipGetErrorString(e);

@@ -56,8 +56,9 @@ __host__ __device__ inline int dg_times(const GroupDesc& g, int c, int a) {
 // coefficient +-|G|/H; cyclic groups only) adds mag * label; as the last
 // member its equation s mag x == r has a solution only when mag divides r.
 // Returns false when the block does not exist.
+template <typename I>
 __host__ __device__ inline bool fill_sectors(const GroupDesc& g, const SectorGroup& sg,
-                                             int64_t digits, int q, int* S, const int32_t* chg) {
+                                             I digits, int q, int* S, const int32_t* chg) {
   if (sg.count == 0) return true;   // an empty group only pins Q
   int acc = 0;
   for (int i = sg.count - 2; i >= 0; --i) {
@@ -105,18 +106,27 @@ __host__ __device__ inline bool block_bases(const XformParams& p, int64_t blk, i
 // Entry i of an offset table for auxiliary sector q: the group's stored sectors
 // are the digits of i / n_inner, its in-block indices those of i % n_inner
 // (row-major in group order); the implicit sector solves the group's delta.
-__host__ __device__ inline int64_t group_offset(const OffsetParams& p, int q, int64_t i) {
-  int64_t digits = i / p.n_inner;
-  int64_t inner = i - digits * p.n_inner;
+// (32-bit division where the entry index fits: the tables of large groups have
+// millions of entries, and 64-bit division is many times slower on the device)
+template <typename I>
+__host__ __device__ inline int64_t group_offset_t(const OffsetParams& p, int q, I i) {
+  const I n_inner = static_cast<I>(p.n_inner);
+  const I digits = i / n_inner;
+  I inner = i - digits * n_inner;
   int S[kMaxOrder];
   (void)fill_sectors(p.g, p.grp, digits, q, S, p.chg);   // offset tables: no subgroup modes
   int64_t off = 0;
   for (int j = p.grp.count - 1; j >= 0; --j) {
-    const int64_t d = inner % p.dim[j];
-    inner /= p.dim[j];
-    off += d * p.stride[j] + static_cast<int64_t>(S[p.grp.pos[j]]) * p.weight[j];
+    const I dim = static_cast<I>(p.dim[j]);
+    const I d = inner % dim;
+    inner /= dim;
+    off += static_cast<int64_t>(d) * p.stride[j] + static_cast<int64_t>(S[p.grp.pos[j]]) * p.weight[j];
   }
   return off;
+}
+__host__ __device__ inline int64_t group_offset(const OffsetParams& p, int q, int64_t i) {
+  if (p.count <= INT32_MAX) return group_offset_t<int32_t>(p, q, static_cast<int32_t>(i));
+  return group_offset_t<int64_t>(p, q, i);
 }
 
 // Entry i of an offset table for auxiliary sector q, in reals: complex

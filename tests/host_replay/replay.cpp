@@ -137,7 +137,8 @@ void replay_xform(const XformParams& x, int64_t src_n, int64_t dst_n, bool dst_s
       const int64_t c_end = std::min(c_begin + x.run_chunk, x.run_len);
       const int64_t r0 = row_tile * x.rows_per_tile;
       const int nr = static_cast<int>(std::min<int64_t>(x.rows - r0, x.rows_per_tile));
-      CHECK(nr <= 256, "rows per copy tile above the LDS row table", nr, 256);
+      // (the kernel moves them 256 at a time through its LDS row table)
+      CHECK(nr >= 1, "copy tile without rows", nr, x.rows);
       const int V = x.vec;
       CHECK(c_begin % V == 0, "vector chunk start", c_begin, V);
       for (int r = 0; r < nr; ++r) {
@@ -482,6 +483,18 @@ void check_stream_k(int64_t batch, int tiles_m, int tiles_n, int nk, int64_t res
       prev_b0 = b0;
       got.push_back(sk_piece(static_cast<int>(t), member, ts, grp, b0 / nk));
     }
+    // the kernel lists teams t_first .. t_last (the holder of iteration x1 - 1)
+    // in LDS, skipping empty shares: the same pieces in the same order
+    const int64_t t_first = sk_first_team(x0, total, nteam), t_last = sk_first_team(x1 - 1, total, nteam);
+    CHECK(t_last >= t_first && t_last < nteam, "fixup's last team", t_last, nteam);
+    CHECK(sk_bound(t_last, total, nteam) < x1 && (t_last + 1 >= nteam || sk_bound(t_last + 1, total, nteam) >= x1),
+          "fixup's last team does not hold iteration x1 - 1", t_last, x1);
+    std::vector<int64_t> listed;
+    for (int64_t u = t_first; u <= t_last; ++u) {
+      const int64_t b0 = sk_bound(u, total, nteam), b1 = sk_bound(u + 1, total, nteam);
+      if (b1 > b0) listed.push_back(sk_piece(static_cast<int>(u), member, ts, grp, b0 / nk));
+    }
+    CHECK(listed == got, "fixup's team list differs from its pieces", tile, static_cast<int64_t>(listed.size()));
     std::vector<int64_t> want;
     auto pc = pieces[tile];
     std::sort(pc.begin(), pc.end());
