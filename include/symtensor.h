@@ -125,11 +125,19 @@
  * tables.  Where K-steps are the three-step path's, results are identical in
  * value to it: the product sums in the same order.
  *
- * Execution and ownership.  Every device buffer (operand data, workspace,
- * aligned buffers) is allocated and owned by the caller.  A context holds only
- * host state (the HIP device, timing events, the last error and a cache of the
- * plans it has made, keyed by every planning input except data pointers and
- * guarded by a mutex); it allocates no device memory.  Functions taking a stream
+ * Execution and ownership.  Every device buffer the caller names (operand
+ * data, workspace, aligned buffers) is allocated and owned by the caller.  A
+ * context holds the HIP device, timing events, the last error and a cache of
+ * the plans it has made (keyed by every planning input except data pointers,
+ * guarded by a mutex).  Its one device allocation: symtensor_contract keeps
+ * each cached plan's fused-product offset tables (they depend on the plan
+ * only) in device memory of its own, built on the stream of the plan's first
+ * call and awaited through an event by later calls on other streams; at most
+ * 1 GiB per context, freed when the cache is cleared (1024 plans) or the
+ * context destroyed (freeing waits for the device).  On a stream under graph
+ * capture, beyond that budget or when the allocation fails, the tables are
+ * built in the workspace on every call instead (the workspace size does not
+ * change).  symtensor_contract_static never allocates.  Functions taking a stream
  * (a hipStream_t passed as void*, NULL = the null stream) enqueue their
  * kernels on it and return without synchronising.  All validation happens on
  * the host before the first launch: on any error no kernel is launched and no
@@ -142,7 +150,10 @@
  * Environment (read at planning and launch time; for tuning and tests only,
  * never needed for correctness: every tile meets the same accuracy bound):
  *   SYMT_GEMM_TILE=<name>  restricts the sector product to one tile where that
- *                          tile applies (F64/F32: "128x96", "d96x96s2", ...;
+ *                          tile applies (F64/F32: "128x96", "d96x96s2", ...,
+ *                          "rows" = the row-streaming product taken by default
+ *                          where K and N are at most 64 and the slices hold at
+ *                          least 16384 rows in all;
  *                          BF16X3: "b128x128k32", "bd128x256s3", ...); an
  *                          unknown or inapplicable name is ignored.
  *   SYMT_GEMM_SK=0 | 1     0 forbids stream-K and split K; 1 forces stream-K on

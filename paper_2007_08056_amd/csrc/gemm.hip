@@ -1307,6 +1307,10 @@ hipError_t launch_fp_tile(int idx, int vec, int64_t batch, int M, int N, int K, 
 
 }  // namespace
 
+// Row-streaming product for K and N at most 64 (gemm_rows.hip).
+hipError_t launch_gemm_rows(bool f64, int64_t batch, int M, int N, int K, const void* A, const void* B, void* C,
+                            hipStream_t s, const FusedTables* f);
+
 // Wide split-bf16 tiles with one binary32 accumulator (gemm_bf16x3.hip).
 hipError_t launch_bf16x3_wide(int variant, int64_t batch, int M, int N, int K, const void* A, const void* B,
                               void* C, hipStream_t s, int64_t pa, int64_t pb, const int64_t* rc,
@@ -1382,7 +1386,8 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
                          (!fused || (fused->vec > 1 && fused->krun == 0 && !fused->at));
     const GemmChoice gc = choose_fp_gemm(batch, M, N, K, f64 ? 8 : 4, aligned);
     if ((!gc.sk && gc.splits <= 1) || (reinterpret_cast<uintptr_t>(part) & 15) != 0) part = nullptr;
-    e = f64 ? launch_fp_tile<double>(gc.tile, vec, batch, M, N, K, A, B, C, stream, fused, part, part_bytes,
+    e = gc.tile == kRowsTile ? launch_gemm_rows(f64, batch, M, N, K, A, B, C, stream, fused)
+        : f64 ? launch_fp_tile<double>(gc.tile, vec, batch, M, N, K, A, B, C, stream, fused, part, part_bytes,
                                      gc.splits)
             : launch_fp_tile<float>(gc.tile, vec, batch, M, N, K, A, B, C, stream, fused, part, part_bytes,
                                     gc.splits);

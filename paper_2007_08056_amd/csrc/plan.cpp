@@ -533,6 +533,10 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
     int64_t a = 1;
     for (int m = p->W.n - 1; m >= 0; --m) { st[m] = a; a *= p->W.dims[m]; }
     for (int i = p->t - 1; i >= 0 && st[p->posJ_w[i]] == w_run; --i) w_run *= p->W.dims[p->posJ_w[i]];
+    int64_t r_run = 1;
+    for (int i = p->s - 1; i >= 0 && st[p->posI_w[i]] == r_run; --i) r_run *= p->W.dims[p->posI_w[i]];
+    p->w_col_run = w_run;
+    p->w_row_run = r_run;
   }
   p->fused_ua = !p->fused && !force_steps && !p->subgroups && p->nq == p->g.size &&
                 (!w || p->W.dtype == (p->cplx ? want : w_want) ||
@@ -633,6 +637,17 @@ GemmChoice choose_among(int64_t batch, int64_t M, int64_t N, int64_t K, int elem
   };
   const double per_cu = (elem == 8 ? 78.6e12 : 157.3e12) / 256.0;
   GemmChoice best;
+  // K and N at most 64: 2 K N flops per 8 (K + N) bytes of A and C, bound by HBM
+  // on any tile; the row-streaming product reads A once and keeps B in LDS
+  // (named "rows"; it needs enough rows to spread over the device)
+  const bool rows_forced = forced && std::strcmp(forced, "rows") == 0;
+  if (K >= 1 && K <= 64 && N >= 1 && N <= 64 && batch >= 1 && batch <= 65535 && M >= 1 &&
+      (rows_forced || (!forced && batch * M >= 16384))) {
+    best.tile = kRowsTile;
+    best.bm = 32;
+    best.bn = static_cast<int>(N);
+    return best;
+  }
   double best_t = 0;
   for (int i = 0; i < kNumFpTiles; ++i) {
     const FpTile& t = kFpTiles[i];

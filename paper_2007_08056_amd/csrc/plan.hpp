@@ -139,6 +139,7 @@ struct FusedTables {
   int32_t krun = 0;                 // > 0: K stepped run by run (register tiles)
   int32_t c_bytes = 8;              // split-bf16 products: W's element size (8 binary64, 4 binary32)
   int32_t at = 0;                   // 1: A loaded K-major from U (register tiles)
+  int32_t c_trans = 0;              // 1: W's rows are its contiguous index (row-streaming product)
 };
 
 struct OperandDesc {
@@ -188,6 +189,9 @@ struct Plan {
   bool fused_b = false;
   bool fused_b_chunks = false;      // V's columns in whole 16-byte chunks
   int64_t ldb = 0;
+  // W's contiguous runs at its end: of its output modes from V (columns of the
+  // product) and of those from U (rows); one of them is 1
+  int64_t w_col_run = 1, w_row_run = 1;
   // fused with K runs that do not hold whole K-steps: the register tiles step each
   // run on its own (krun = the run length; 0 = plain K-steps)
   int32_t krun = 0;
@@ -234,6 +238,9 @@ struct GemmChoice {
 // buffer (two pieces per workgroup) from each tile's resident workgroups; a
 // launch runs no more workgroups than that buffer holds.
 constexpr int kSkSlots = 768;
+// GemmChoice::tile of the row-streaming product (K and N at most 64, many rows):
+// past the tile table.
+constexpr int kRowsTile = 64;
 // Fewest K-iterations a stream-K workgroup takes on (bounds the pieces per tile).
 constexpr int kSkMinIters = 4;
 GemmChoice choose_fp_gemm(int64_t batch, int64_t M, int64_t N, int64_t K, int elem, bool aligned);

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -32,6 +33,29 @@ void* scratch_device_ptr(int device);
 
 using symt::Plan;
 
+// Device copies of one plan's offset tables (the fused product's separable
+// row / column offsets).  They depend on the plan only, so the context builds
+// them once, on the stream of the first call that needs them, and later calls
+// wait for that build (an event) instead of rebuilding.
+struct TableCache {
+  std::mutex mu;
+  void* dev = nullptr;
+  size_t bytes = 0;
+  hipEvent_t ready = nullptr;
+  bool built = false;
+  bool done = false;       // the build has completed: no wait needed
+  bool refused = false;    // no device memory (or over the context's budget): use the workspace
+  ~TableCache() {
+    if (ready) (void)hipEventDestroy(ready);
+    if (dev) (void)hipFree(dev);
+  }
+};
+
+struct CachedPlan {
+  Plan plan;
+  std::shared_ptr<TableCache> tables;
+};
+
 struct symt_ctx {
   int device = 0;
   std::string last_error;
@@ -39,9 +63,10 @@ struct symt_ctx {
   std::vector<hipEvent_t> pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[4];
   // Plans of contractions already validated on this context, keyed by every
-  // planning input except the data pointers (see plan_key).
+  // planning input except the data pointers (see plan_key), with their tables.
   std::mutex plan_mu;
-  std::unordered_map<std::string, Plan> plans;
+  std::unordered_map<std::string, CachedPlan> plans;
+  size_t table_bytes = 0;  // device bytes held by cached tables (under plan_mu)
 };
 
 namespace {
@@ -159,7 +184,52 @@ int do_gemm(symt_ctx* ctx, int compute, int64_t batch, int64_t m, int64_t k, int
 
 // Fused path: offset tables of U's rows and columns and of W's rows and
 // columns, V aligned, then one product that reads U and writes W in place.
-int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int32_t* const chg[3]) {
+constexpr size_t kTableBudget = size_t(1) << 30;   // device bytes of cached tables per context
+
+// The cached tables of `tc` (built now on `s` when `build` comes back true), or
+// nullptr when the workspace must hold them: no cache slot, a captured stream
+// (no allocation or cross-stream wait there), or no device memory for them.
+// Called with tc->mu held.
+void* cached_tables(symt_ctx* ctx, TableCache* tc, size_t bytes, hipStream_t s, bool* build) {
+  *build = false;
+  if (!tc || bytes == 0) return nullptr;
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess || st != hipStreamCaptureStatusNone) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  if (!tc->dev && !tc->refused) {
+    bool room;
+    {
+      std::lock_guard<std::mutex> lock(ctx->plan_mu);
+      room = ctx->table_bytes + bytes <= kTableBudget;
+      if (room) ctx->table_bytes += bytes;
+    }
+    if (!room || hipMalloc(&tc->dev, bytes) != hipSuccess ||
+        hipEventCreateWithFlags(&tc->ready, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      if (tc->dev) (void)hipFree(tc->dev);
+      tc->dev = nullptr;
+      tc->refused = true;
+      return nullptr;
+    }
+    tc->bytes = bytes;
+  }
+  if (!tc->dev || tc->bytes != bytes) return nullptr;
+  if (!tc->built) {
+    *build = true;
+  } else if (!tc->done) {
+    if (hipEventQuery(tc->ready) == hipSuccess) tc->done = true;
+    else if (hipStreamWaitEvent(s, tc->ready, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+  }
+  return tc->dev;
+}
+
+int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int32_t* const chg[3],
+             TableCache* tc = nullptr) {
   using symt::round_up;
   const size_t G = static_cast<size_t>(p.g.size);
   // U aligned first (fused_ua): U_al, then the regions of the fused product
@@ -187,24 +257,50 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
   // vector loads of B in place need 16-byte aligned, whole column chunks
   if (fb && vec > 1 && !(aligned16(p.V.data) && p.fused_b_chunks)) vec = 1;
   std::string err;
-  int rc_ = timed(ctx, 0, s, [&] {
-    symt::OffsetBatch b;
-    const int ops[6] = {0, 0, 2, 2, 1, 1};
-    int64_t* outs[6] = {ra, ca, rc, cc, rb, cb};
-    int64_t total = 0;
-    b.n = fb ? 6 : 4;
-    for (int t = 0; t < b.n; ++t) {
-      if (p.fused_ua && ops[t] == 0)   // U_al: row m at (q M + m) gk, column k at k
-        b.t[t] = t == 0 ? symt::affine_offsets(p, p.M, p.M * p.gk, p.gk) : symt::affine_offsets(p, p.gk, 0, 1);
-      else
-        b.t[t] = symt::make_offsets(p, ops[t], t % 2 == 0);
-      b.t[t].chg = chg[ops[t]];
-      b.out[t] = outs[t];
-      total += b.t[t].count * G;
-      b.end[t] = total;
+  // the tables: cached on the context (all of the plan's tables, built once), or
+  // in the workspace (the ones this call reads, built every call)
+  const int n_plan = p.fused_b ? 6 : 4;
+  char* const t0 = reinterpret_cast<char*>(ra);
+  const size_t plan_bytes = static_cast<size_t>((p.fused_b ? reinterpret_cast<char*>(cb) +
+                                                                 round_up(8 * G * p.gn, 256)
+                                                           : reinterpret_cast<char*>(rb)) - t0);
+  bool build = true;
+  int n_build = fb ? 6 : 4;
+  std::unique_lock<std::mutex> tlock;
+  if (tc) tlock = std::unique_lock<std::mutex>(tc->mu);
+  if (char* cached = static_cast<char*>(cached_tables(ctx, tc, plan_bytes, s, &build))) {
+    auto move = [&](int64_t*& x) { x = reinterpret_cast<int64_t*>(cached + (reinterpret_cast<char*>(x) - t0)); };
+    move(ra); move(ca); move(rc); move(cc); move(rb); move(cb);
+    n_build = n_plan;
+  } else {
+    build = true;
+  }
+  int rc_ = SYMT_OK;
+  if (build) {
+    rc_ = timed(ctx, 0, s, [&] {
+      symt::OffsetBatch b;
+      const int ops[6] = {0, 0, 2, 2, 1, 1};
+      int64_t* outs[6] = {ra, ca, rc, cc, rb, cb};
+      int64_t total = 0;
+      b.n = n_build;
+      for (int t = 0; t < b.n; ++t) {
+        if (p.fused_ua && ops[t] == 0)   // U_al: row m at (q M + m) gk, column k at k
+          b.t[t] = t == 0 ? symt::affine_offsets(p, p.M, p.M * p.gk, p.gk) : symt::affine_offsets(p, p.gk, 0, 1);
+        else
+          b.t[t] = symt::make_offsets(p, ops[t], t % 2 == 0);
+        b.t[t].chg = chg[ops[t]];
+        b.out[t] = outs[t];
+        total += b.t[t].count * G;
+        b.end[t] = total;
+      }
+      return symt::launch_offsets(b, s, &err);
+    });
+    if (rc_ == SYMT_OK && tc && tc->dev && reinterpret_cast<char*>(ra) != t0 && !tc->built) {
+      if (hipEventRecord(tc->ready, s) == hipSuccess) tc->built = true;
+      else (void)hipGetLastError();
     }
-    return symt::launch_offsets(b, s, &err);
-  });
+  }
+  if (tlock.owns_lock()) tlock.unlock();
   if (rc_) return ctx_fail(ctx, rc_, err);
   if (p.fused_ua && (rc_ = do_align(ctx, p, 0, ual, s, true, chg[0]))) return rc_;
   if (!fb && (rc_ = do_align(ctx, p, 1, val, s, true, chg[1]))) return rc_;
@@ -215,6 +311,9 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
   f.krun = p.krun;
   f.at = p.a_trans ? 1 : 0;
   f.c_bytes = static_cast<int32_t>(elem_bytes(p.W.dtype));
+  // W written in place with its rows contiguous (and not its columns): the
+  // row-streaming product stores lanes along rows
+  f.c_trans = !p.cplx && p.w_row_run >= 16 && p.w_col_run < 8 ? 1 : 0;
   if (fb) {
     f.rb = rb;
     f.cb = cb;
@@ -279,8 +378,10 @@ std::string plan_key(const char* einsum, const symt_group* group, const symt_ten
   return k;
 }
 
+// `tables` (optional): the cached plan's device table slot.
 int plan_for(symt_ctx* ctx, const char* einsum, const symt_group* group, const symt_tensor* u,
-             const symt_tensor* v, const symt_tensor* w, int32_t compute, Plan* p) {
+             const symt_tensor* v, const symt_tensor* w, int32_t compute, Plan* p,
+             std::shared_ptr<TableCache>* tables = nullptr) {
   std::string key;
   if (ctx) {
     key = plan_key(einsum, group, u, v, w, compute);
@@ -288,10 +389,11 @@ int plan_for(symt_ctx* ctx, const char* einsum, const symt_group* group, const s
       std::lock_guard<std::mutex> lock(ctx->plan_mu);
       auto it = ctx->plans.find(key);
       if (it != ctx->plans.end()) {
-        *p = it->second;
+        *p = it->second.plan;
         p->U.data = u->data;
         p->V.data = v->data;
         p->W.data = w ? w->data : nullptr;
+        if (tables) *tables = it->second.tables;
         return SYMT_OK;
       }
     }
@@ -301,8 +403,15 @@ int plan_for(symt_ctx* ctx, const char* einsum, const symt_group* group, const s
   if (rc) return ctx_fail(ctx, rc, err);
   if (!key.empty()) {
     std::lock_guard<std::mutex> lock(ctx->plan_mu);
-    if (ctx->plans.size() >= kMaxCachedPlans) ctx->plans.clear();
-    ctx->plans.emplace(std::move(key), *p);
+    if (ctx->plans.size() >= kMaxCachedPlans) {
+      // (a call still holding a plan's tables keeps them alive until it returns;
+      // freeing device memory waits for the device)
+      ctx->plans.clear();
+      ctx->table_bytes = 0;
+    }
+    auto tc = std::make_shared<TableCache>();
+    ctx->plans.emplace(std::move(key), CachedPlan{*p, tc});
+    if (tables) *tables = tc;
   }
   return SYMT_OK;
 }
@@ -403,7 +512,8 @@ int symtensor_workspace_size(const char* einsum, const symt_group* group, const 
 namespace {
 // Validation and launches of one planned contraction (symtensor_contract and
 // symtensor_contract_static): every check runs before the first launch.
-int contract_planned(symt_ctx* ctx, const Plan& p, void* workspace, size_t workspace_bytes, void* stream) {
+int contract_planned(symt_ctx* ctx, const Plan& p, void* workspace, size_t workspace_bytes, void* stream,
+                     TableCache* tables = nullptr) {
   int rc;
   if ((rc = check_data(ctx, p.U, "u")) || (rc = check_data(ctx, p.V, "v")) ||
       (rc = check_data(ctx, p.W, "w")))
@@ -440,7 +550,7 @@ int contract_planned(symt_ctx* ctx, const Plan& p, void* workspace, size_t works
     for (int op = 0; op < 3; ++op)
       if (!p.chg[op].empty()) chg[op] = dev + off[op];
   }
-  if (p.fused || p.fused_ua) return do_fused(ctx, p, base, s, chg);
+  if (p.fused || p.fused_ua) return do_fused(ctx, p, base, s, chg, tables);
   void* ual = base;
   void* val = base + symt::round_up(p.ws_u_al, 256);
   void* wal = base + symt::round_up(p.ws_u_al, 256) + symt::round_up(p.ws_v_al, 256);
@@ -465,9 +575,10 @@ int symtensor_contract(symt_ctx* ctx, const char* einsum, const symt_group* grou
   if (!ctx) return ctx_fail(nullptr, SYMT_EINVAL, "context is NULL");
   if (!w) return ctx_fail(ctx, SYMT_EINVAL, "output descriptor is NULL");
   Plan p;
-  int rc = plan_for(ctx, einsum, group, u, v, w, compute, &p);
+  std::shared_ptr<TableCache> tables;
+  int rc = plan_for(ctx, einsum, group, u, v, w, compute, &p, &tables);
   if (rc) return rc;
-  return contract_planned(ctx, p, workspace, workspace_bytes, stream);
+  return contract_planned(ctx, p, workspace, workspace_bytes, stream, tables.get());
 }
 
 int symtensor_contract_static(symt_ctx* ctx, const char* einsum, const symt_group* group,

@@ -315,6 +315,69 @@ void check_bijection(const std::vector<int64_t>& R, const std::vector<int64_t>& 
   for (int64_t e = 0; e < reals; ++e) CHECK(hit[e] == 1, what, e, hit[e]);
 }
 
+// The row-streaming product (K and N at most 64): the index walk of one launch
+// over tables (empty vector: the aligned row-major form).  Every A and B read
+// inside its operand, every C element written exactly once.
+// (`resident`: workgroups the device holds at once; the launcher asks the
+// runtime, the replay tries several)
+void replay_rows(int64_t resident, int64_t batch, int64_t M, int64_t N, int64_t K, const std::vector<int64_t>& ra,
+                 const std::vector<int64_t>& ca, const std::vector<int64_t>& rb, const std::vector<int64_t>& cb,
+                 const std::vector<int64_t>& rc, const std::vector<int64_t>& cc, int64_t a_n, int64_t b_n,
+                 int64_t c_n, int row_groups, bool trans) {
+  const int waves = 4, rows = 16 * row_groups;
+  const int64_t ks = (K + 3) / 4, tn = (N + 15) / 16;
+  const int64_t blocks = (M + rows - 1) / rows;
+  const int64_t want = std::max<int64_t>(1, resident / std::max<int64_t>(batch, 1));
+  const int64_t gx = std::min<int64_t>((blocks + waves - 1) / waves, want);
+  std::vector<uint8_t> written(static_cast<size_t>(c_n), 0);
+  for (int64_t q = 0; q < batch; ++q) {
+    for (int64_t k = 0; k < 4 * ks; ++k)
+      for (int64_t n = 0; n < 16 * tn; ++n) {
+        if (k >= K || n >= N) continue;
+        const int64_t b = rb.empty() ? (q * K + k) * N + n : rb[q * K + k] + cb[q * N + n];
+        CHECK(b >= 0 && b < b_n, "row product B read out of bounds", b, b_n);
+      }
+    for (int64_t x = 0; x < gx; ++x)
+      for (int w = 0; w < waves; ++w)
+        for (int64_t blk = x * waves + w; blk < blocks; blk += gx * waves) {
+          const int64_t m0 = blk * rows;
+          for (int lane = 0; lane < 64; ++lane) {
+            for (int i = 0; i < row_groups; ++i) {
+              const int64_t m = std::min<int64_t>(m0 + i * 16 + (lane & 15), M - 1);
+              const int64_t rbase = ra.empty() ? (q * M + m) * K : ra[q * M + m];
+              for (int64_t st = 0; st < ks; ++st) {
+                const int64_t k = 4 * st + (lane >> 4);
+                if (k >= K) continue;
+                const int64_t a = rbase + (ca.empty() ? k : ca[q * K + k]);
+                CHECK(a >= 0 && a < a_n, "row product A read out of bounds", a, a_n);
+              }
+              // stores: both accumulator row layouts cover rows m0 + 16 i + 0..15
+              // (trans: the lane's row is lane % 16, its columns those rows)
+              for (int r = 0; r < 4; ++r) {
+                const int64_t acc_row = (lane >> 4) + 4 * r;
+                const int64_t row = m0 + i * 16 + (trans ? (lane & 15) : acc_row);
+                if (row >= M) continue;
+                const int64_t crow = rc.empty() ? (q * M + row) * N : rc[q * M + row];
+                for (int64_t j = 0; j < tn; ++j) {
+                  const int64_t col = j * 16 + (trans ? acc_row : (lane & 15));
+                  if (col >= N) continue;
+                  const int64_t c = crow + (cc.empty() ? col : cc[q * N + col]);
+                  CHECK(c >= 0 && c < c_n, "row product C write out of bounds", c, c_n);
+                  if (c >= 0 && c < c_n) {
+                    CHECK(written[c] == 0, "row product C written twice", c, 0);
+                    written[c]++;
+                  }
+                }
+              }
+            }
+          }
+        }
+  }
+  int64_t total = 0;
+  for (uint8_t v : written) total += v;
+  CHECK(total == batch * M * N, "row product C elements not all written", total, batch * M * N);
+}
+
 void check_fused(const Plan& p) {
   if (!(p.fused || p.fused_ua)) return;
   const int G = p.g.size;
@@ -336,6 +399,15 @@ void check_fused(const Plan& p) {
     rb = table(make_offsets(p, 1, true), G);
     cb = table(make_offsets(p, 1, false), G);
     check_bijection(rb, cb, G, p.gk, p.gn, p.V.elems, "V tables not a bijection onto V");
+  }
+  if (p.compute != SYMT_COMPUTE_BF16X3 && p.gk <= 64 && p.gn <= 64) {
+    const std::vector<int64_t> none;
+    const int64_t b_n = p.fused_b ? p.V.elems : G * p.gk * p.gn;   // V in place, or V_al
+    for (int rg : {1, 2})
+      for (int64_t resident : {256, 512, 2048})
+        for (bool trans : {false, true})
+          replay_rows(resident, G, p.M, p.gn, p.gk, ra, ca, p.fused_b ? rb : none, p.fused_b ? cb : none, rc, cc,
+                      p.fused_ua ? G * p.M * p.gk : p.U.elems * cm, b_n, p.W.elems * cm, rg, trans);
   }
   if (p.compute == SYMT_COMPUTE_BF16X3) {
     // register tiles split U in registers along 32-deep K-steps of one run

@@ -498,7 +498,7 @@ RUN_CASES = [
 
 @pytest.mark.parametrize("case", RUN_CASES)
 @pytest.mark.parametrize("compute", ["f64", "f32"])
-@pytest.mark.parametrize("tile", ["", "128x48", "64x96", "128x128"])
+@pytest.mark.parametrize("tile", ["", "128x48", "64x96", "128x128", "rows"])
 def test_fused_product_steps_each_run(P, case, compute, tile, monkeypatch):
     """Run-by-run K-steps: U and V read in place and W written in place whatever the
     run length, within the product's bound of the oracle (as is the three-step
@@ -573,7 +573,7 @@ def _w_col_run(sub, du, dv):
 @pytest.mark.parametrize("case", UA_CASES)
 @pytest.mark.parametrize("compute", ["f64", "f32", "bf16x3"])
 @pytest.mark.parametrize("tile,sk", [("", ""), ("d96x96s2", "0"), ("d96x96s2", "1"), ("d128x64s3", "1"),
-                                     ("128x48", "0"), ("64x96", "0")])
+                                     ("128x48", "0"), ("64x96", "0"), ("rows", "")])
 def test_fused_product_on_aligned_u(P, case, compute, tile, sk, monkeypatch):
     """U's contracted modes leading (or runs that do not suit a global-to-LDS
     tile): U aligned first on global-to-LDS tiles, read K-major in place on
@@ -744,7 +744,7 @@ VIP_CASES = [
 @pytest.mark.parametrize("compute", ["f64", "f32"])
 @pytest.mark.parametrize("tile,sk", [("d96x96s2", "0"), ("d96x96s2", "1"), ("d128x64s3", "0"),
                                      ("d128x64s3", "1"), ("d128x128s2", "1"), ("128x48", "0"),
-                                     ("64x96", "0"), ("128x128", ""), ("", "")])
+                                     ("64x96", "0"), ("128x128", ""), ("rows", ""), ("", "")])
 def test_fused_product_reads_v_in_place(P, case, compute, tile, sk, monkeypatch):
     """Products reading B from V's standard form through its row and column
     tables, on global-to-LDS tiles (stream-K on and off), register tiles and
@@ -793,6 +793,133 @@ def test_fused_product_reads_v_in_place(P, case, compute, tile, sk, monkeypatch)
         w_o = P.output_like(sub, u, v, dtype=dt)
         P.contract_into(sub, u, v_off, w_o, compute)
         assert torch.equal(w_o.data, w_s.data)
+
+
+@pytest.mark.parametrize("compute", ["f64", "f32"])
+def test_row_streaming_product(P, compute, monkeypatch):
+    """The row-streaming product (K and N at most 64): forced on small and
+    ragged shapes (K and N of 1, not multiples of 4 or 16, and 64; one row;
+    many slices) and taken by default on tall ones, within the product's bound
+    of an FP64 matmul and run-to-run identical."""
+    monkeypatch.delenv("SYMT_GEMM_SK", raising=False)
+    cases = [("rows", (1, 1, 1, 1)), ("rows", (3, 5, 3, 7)), ("rows", (2, 33, 64, 64)), ("rows", (5, 100, 17, 1)),
+             ("rows", (1, 16, 32, 4)), ("rows", (7, 61, 48, 48)), ("rows", (300, 3, 8, 16)),
+             ("", (6, 3000, 48, 48)), ("", (1, 40000, 13, 50)), ("", (2, 9000, 64, 33))]
+    for tile, shape in cases:
+        if tile:
+            monkeypatch.setenv("SYMT_GEMM_TILE", tile)
+        else:
+            monkeypatch.delenv("SYMT_GEMM_TILE", raising=False)
+        b, m, k, n = shape
+        say(f"row product {compute} tile={tile or 'default'} {shape}")
+        rng = np.random.default_rng(m * 7 + n + k)
+        dt = torch.float64 if compute == "f64" else torch.float32
+        a = torch.from_numpy(rng.standard_normal((b, m, k))).to(DEV, dt)
+        bb = torch.from_numpy(rng.standard_normal((b, k, n))).to(DEV, dt)
+        C = H.to_np(P.sector_gemm(a, bb, compute))
+        A64, B64 = H.to_np(a).astype(np.float64), H.to_np(bb).astype(np.float64)
+        ref = np.matmul(A64, B64)
+        absb = np.matmul(np.abs(A64), np.abs(B64))
+        fac = 2 * H.gamma(k, H.U64) if compute == "f64" else 1.05 * H.gamma(k, H.U32)
+        assert np.all(np.abs(C - ref) <= fac * absb + 1e-300), (compute, shape)
+        assert np.array_equal(H.to_np(P.sector_gemm(a, bb, compute)), C)
+
+
+ROW_CASES = [
+    # W's rows contiguous (its last modes from U): lanes store along rows
+    ("cASB,bsSB->bcsA", (2, 3), "----", "+---", (6, 16, 2, 4), (4, 2, 2, 4)),
+    ("ak,kb->ba", (2, 3), "--", "-+", (17, 32), (32, 8)),
+    # W's columns contiguous: lanes store along columns
+    ("bcsA,bsSB->cASB", (2, 3), "--+-", "+---", (4, 6, 2, 16), (4, 2, 2, 4)),
+    ("abkl,klij->abij", (4,), "++--", "++--", (3, 5, 4, 4), (4, 4, 2, 6)),
+    # odd K and N
+    ("akl,klb->ab", (3,), "+-+", "-++", (7, 3, 5), (3, 5, 13)),
+]
+
+
+@pytest.mark.parametrize("case", ROW_CASES)
+@pytest.mark.parametrize("compute", ["f64", "f32"])
+def test_row_streaming_product_in_place(P, case, compute, monkeypatch):
+    """The row-streaming product forced on fused contractions (U and V read in
+    place where they can, W written in place, lanes along W's contiguous index):
+    bit-identical to the three-step path on the same kernel (the transposed
+    MFMA forms the same products in the same K order), within the product's
+    bound of the oracle, with and without charge tables."""
+    sub, orders, cu, cv, du, dv = case
+    monkeypatch.setenv("SYMT_GEMM_TILE", "rows")
+    monkeypatch.delenv("SYMT_GEMM_SK", raising=False)
+    rng = np.random.default_rng(seed("rows", sub, orders))
+    g = O.Group(orders)
+    su0 = O.Sym.make(cu, int(rng.integers(g.size)), du, g)
+    sv0 = O.Sym.make(cv, int(rng.integers(g.size)), dv, g)
+    dt = torch.float64 if compute == "f64" else torch.float32
+    for tables in (False, True):
+        su, sv = _with_tables(rng, sub, su0, sv0) if tables else (su0, sv0)
+        say(f"rows in place {sub} G={orders} {compute} tables={tables}")
+        Ru = rng.standard_normal(su.reduced_shape())
+        Rv = rng.standard_normal(sv.reduced_shape())
+        u = _sym_tensor(P, Ru, su, dt)
+        v = _sym_tensor(P, Rv, sv, dt)
+        info = P.plan(sub, u, v, compute)
+        assert info.fused_w == 1
+        w_f = P.output_like(sub, u, v, dtype=dt)
+        w_s = P.output_like(sub, u, v, dtype=dt)
+        P.contract_into(sub, u, v, w_f, compute)
+        P.contract_into(sub, u, v, w_s, compute, steps=True)
+        assert torch.equal(w_f.data, w_s.data)
+        ref, _ = O.contract_blocks(sub, H.to_np(u.data).astype(np.float64), su,
+                                   H.to_np(v.data).astype(np.float64), sv)
+        absref, _ = O.contract_blocks(sub, np.abs(H.to_np(u.data).astype(np.float64)), su,
+                                      np.abs(H.to_np(v.data).astype(np.float64)), sv)
+        k = H.contracted_extent(sub, su)
+        fac = 2 * H.gamma(k, H.U64) if compute == "f64" else 1.05 * H.gamma(k, H.U32) + H.gamma(k, H.U64)
+        assert np.all(np.abs(H.to_np(w_f.data) - ref) <= fac * absref + 1e-300)
+
+
+def test_cached_offset_tables_across_streams_and_alignments(P):
+    """A plan's offset tables are built once on the context (on the stream of
+    its first call) and reused: a first call whose V is not 16-byte aligned
+    (V aligned first, four tables used), then calls reading V in place (six
+    tables) on a second stream, then on the first again, with new data each
+    time, with and without charge tables: every call bit-identical to the
+    three-step path and within the product's bound of the oracle."""
+    sub, orders, cu, cv = "abkl,klij->abij", (4,), "++--", "++--"
+    du, dv = (3, 7, 4, 8), (4, 8, 5, 6)          # shapes no other test plans
+    rng = np.random.default_rng(91)
+    g = O.Group(orders)
+    su0 = O.Sym.make(cu, 1, du, g)
+    sv0 = O.Sym.make(cv, 3, dv, g)
+    side = torch.cuda.Stream(device=DEV)
+    for tables in (False, True):
+        su, sv = _with_tables(rng, sub, su0, sv0) if tables else (su0, sv0)
+        for call, (stream, aligned) in enumerate(((None, False), (side, True), (None, True), (side, False))):
+            say(f"cached tables tables={tables} call={call} side={stream is not None} aligned_v={aligned}")
+            Ru = rng.standard_normal(su.reduced_shape())
+            Rv = rng.standard_normal(sv.reduced_shape())
+            u = _sym_tensor(P, Ru, su)
+            v = _sym_tensor(P, Rv, sv)
+            if not aligned:
+                buf = torch.zeros(v.data.numel() + 1, dtype=torch.float64, device=DEV)
+                buf[1:] = v.data.reshape(-1)
+                v = P.SymTensor(buf[1:].view(v.data.shape), v.signs, v.charge, v.group, v.mode_charges)
+            info = P.plan(sub, u, v, "f64")
+            assert info.fused == 1 and info.fused_v == 1
+            w_f = P.output_like(sub, u, v)
+            w_s = P.output_like(sub, u, v)
+            if stream is not None:
+                stream.wait_stream(torch.cuda.current_stream(DEV))
+                with torch.cuda.stream(stream):
+                    P.contract_into(sub, u, v, w_f, "f64")
+                torch.cuda.current_stream(DEV).wait_stream(stream)
+            else:
+                P.contract_into(sub, u, v, w_f, "f64")
+            P.contract_into(sub, u, v, w_s, "f64", steps=True)
+            torch.cuda.synchronize(DEV)
+            assert torch.equal(w_f.data, w_s.data), call
+            ref, _ = O.contract_blocks(sub, Ru, su, Rv, sv)
+            absref, _ = O.contract_blocks(sub, np.abs(Ru), su, np.abs(Rv), sv)
+            k = H.contracted_extent(sub, su)
+            assert np.all(np.abs(H.to_np(w_f.data) - ref) <= 2 * H.gamma(k, H.U64) * absref + 1e-300), call
 
 
 @pytest.mark.parametrize("tile,sk", [("d128x128s2", "0"), ("d128x96s2", "0"), ("d128x64s3", "0"),
