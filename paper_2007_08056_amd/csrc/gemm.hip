@@ -281,53 +281,49 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
 }
 
 // Sums the `splits` partial tiles of each tile in split order (so the result does
-// not depend on scheduling) and writes the tile, as k_gemm's epilogue would.  One
-// workgroup per tile, threads laid out as in k_gemm.
+// not depend on scheduling) and writes the tile, as k_gemm's epilogue would.
+// Workgroup (tile, chunk) sums one range of the tile's elements: each element
+// starts from zero and adds its splits in order whatever the chunk count.
 template <typename T, int BM, int BN, int WM, int WN, bool FC>
 __global__ __launch_bounds__(64 * WM * WN) void k_split_sum(const T* __restrict__ part, T* __restrict__ C,
                                                             int M, int N, int tiles_m, int tiles_n, int splits,
                                                             const int64_t* __restrict__ rc,
                                                             const int64_t* __restrict__ cc) {
   constexpr int TM = BM / WM / 16, TN = BN / WN / 16;
-  using Acc = typename Mfma<T>::Acc;
+  constexpr int E = BM * BN;
+  constexpr int NT = 64 * WM * WN;
+  constexpr int PER_WAVE = TM * TN * 4 * 64;
   const int64_t tile = blockIdx.x;
   int64_t q;
   int tm, tn;
   tile_coords(tile, tiles_m, tiles_n, q, tm, tn);
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int wm0 = (wave / WN) * (BM / WM);
-  const int wn0 = (wave % WN) * (BN / WN);
-  Acc acc[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = Acc{};
-  for (int sp = 0; sp < splits; ++sp) {
-    const T* pw = part + (tile * splits + sp) * static_cast<int64_t>(BM * BN) + wave * (TM * TN * 4 * 64) + lane;
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-      for (int j = 0; j < TN; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[i][j][r] += pw[((i * TN + j) * 4 + r) * 64];
-  }
   T* Cq = C + (FC ? 0 : q * static_cast<int64_t>(M) * N);
-  const int m0 = tm * BM, n0 = tn * BN;
-#pragma unroll
-  for (int j = 0; j < TN; ++j) {
-    const int col = n0 + wn0 + j * 16 + (lane & 15);
-    const int64_t ccol = (FC && col < N) ? cc[q * N + col] : col;
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm0 + i * 16 + Mfma<T>::row(lane, r);
-        if (row < M && col < N) {
-          const int64_t crow = FC ? rc[q * M + row] : static_cast<int64_t>(row) * N;
-          Cq[crow + ccol] = acc[i][j][r];
-        }
-      }
+  const T* pt = part + tile * splits * static_cast<int64_t>(E);
+  // workgroup (tile, chunk): the chunk-th of gridDim.y equal ranges of the
+  // tile's elements in accumulator order
+  const int chunks = static_cast<int>(gridDim.y);
+  const int per = (E + chunks - 1) / chunks;
+  const int e0 = static_cast<int>(blockIdx.y) * per;
+  const int e1 = min(E, e0 + per);
+  for (int e = e0 + static_cast<int>(threadIdx.x); e < e1; e += NT) {
+    T acc = T(0);
+#pragma unroll 8
+    for (int sp = 0; sp < splits; ++sp) acc += pt[static_cast<int64_t>(sp) * E + e];
+    // accumulator order: element ((w * TM + i) * TN + j) * 4 + r of lane l at 64 * that + l
+    const int w = e / PER_WAVE;
+    const int rem = e - w * PER_WAVE;
+    const int lane = rem & 63;
+    const int ijr = rem >> 6;
+    const int r = ijr & 3;
+    const int ij = ijr >> 2;
+    const int i = ij / TN, j = ij - (ij / TN) * TN;
+    const int row = tm * BM + (w / WN) * (BM / WM) + i * 16 + Mfma<T>::row(lane, r);
+    const int col = tn * BN + (w % WN) * (BN / WN) + j * 16 + (lane & 15);
+    if (row < M && col < N) {
+      const int64_t crow = FC ? rc[q * M + row] : static_cast<int64_t>(row) * N;
+      const int64_t ccol = FC ? cc[q * N + col] : col;
+      Cq[crow + ccol] = acc;
+    }
   }
 }
 
@@ -917,12 +913,17 @@ hipError_t launch_fp(int vec, int64_t batch, int M, int N, int K, const void* A,
                          N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, splits);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    // a tile's sum over several workgroups (more with more splits), down to
+    // one element per thread
+    const int64_t max_chunks = std::max<int64_t>(1, static_cast<int64_t>(BM) * BN / (64 * WM * WN));
+    const dim3 sgrid(static_cast<unsigned>(ntiles),
+                     static_cast<unsigned>(std::min<int64_t>(max_chunks, std::max(4, splits / 2))));
     if (f)
-      hipLaunchKernelGGL((k_split_sum<T, BM, BN, WM, WN, true>), dim3(static_cast<unsigned>(ntiles)), block, 0, s,
-                         pt, c, M, N, tiles_m, tiles_n, splits, rc, cc);
+      hipLaunchKernelGGL((k_split_sum<T, BM, BN, WM, WN, true>), sgrid, block, 0, s, pt, c, M, N, tiles_m,
+                         tiles_n, splits, rc, cc);
     else
-      hipLaunchKernelGGL((k_split_sum<T, BM, BN, WM, WN, false>), dim3(static_cast<unsigned>(ntiles)), block, 0,
-                         s, pt, c, M, N, tiles_m, tiles_n, splits, rc, cc);
+      hipLaunchKernelGGL((k_split_sum<T, BM, BN, WM, WN, false>), sgrid, block, 0, s, pt, c, M, N, tiles_m,
+                         tiles_n, splits, rc, cc);
     return hipGetLastError();
   }
   const dim3 grid(static_cast<unsigned>(ntiles));

@@ -620,6 +620,9 @@ constexpr FpTile kFpTiles[] = {
 // fetched at staggered K positions, pieces and their fixup); measured on the
 // CCD ladder over Z_8.
 constexpr double kSkEff64 = 0.965, kSkEff32 = 0.80;
+// Resident workgroups per CU that a register tile needs to reach its measured
+// efficiency (the efficiencies above come from launches of many tiles per CU).
+constexpr int64_t kRegSaturation = 3;
 constexpr int kNumFpTiles = sizeof(kFpTiles) / sizeof(kFpTiles[0]);
 }  // namespace
 
@@ -636,6 +639,7 @@ GemmChoice choose_among(int64_t batch, int64_t M, int64_t N, int64_t K, int elem
     return aligned && K % (128 / elem) == 0 && N % (16 / elem) == 0 && (t.bn * elem / 16) % 16 == 0;
   };
   const double per_cu = (elem == 8 ? 78.6e12 : 157.3e12) / 256.0;
+  const bool big = 2.0 * static_cast<double>(batch) * M * N * K >= 1e9;
   GemmChoice best;
   // K and N at most 64: 2 K N flops per 8 (K + N) bytes of A and C, bound by HBM
   // on any tile; the row-streaming product reads A once and keeps B in LDS
@@ -662,7 +666,11 @@ GemmChoice choose_among(int64_t batch, int64_t M, int64_t N, int64_t K, int elem
       double time;
       size_t partial = 0;
       if (!sk) {
-        time = static_cast<double>((tiles + 255) / 256) * t_tile;
+        // register tiles hide their load latency with about three resident
+        // workgroups per CU: fewer tiles than that still take three tiles' time
+        // (on products of a GFLOP and up; below, launches dominate)
+        const int64_t rounds = (tiles + 255) / 256;
+        time = static_cast<double>(t.dma || !big ? rounds : std::max<int64_t>(rounds, kRegSaturation)) * t_tile;
       } else {
         partial = 2 * static_cast<size_t>(std::min(kSkSlots, 256 * t.wgs)) * t.bm * t.bn * elem;
         time = static_cast<double>(tiles) / 256.0 * t_tile / (elem == 8 ? kSkEff64 : kSkEff32) +
@@ -681,10 +689,12 @@ GemmChoice choose_among(int64_t batch, int64_t M, int64_t N, int64_t K, int elem
     // Each run pays a pipeline fill of about two K-steps.
     if (!t.dma && sk_mode != 0) {
       const int64_t nk = (K + 15) / 16;
-      const int64_t sp = std::min<int64_t>({(512 + tiles - 1) / std::max<int64_t>(tiles, 1), nk / 8, 128});
+      const int64_t sp = std::min<int64_t>({(256 * kRegSaturation + tiles - 1) / std::max<int64_t>(tiles, 1),
+                                            nk / 8, 128});
       if (sp > 1) {
         const size_t partial = static_cast<size_t>(tiles * sp) * t.bm * t.bn * elem;
-        const double time = static_cast<double>((tiles * sp + 255) / 256) * t_tile / static_cast<double>(sp) *
+        const int64_t rounds = std::max<int64_t>((tiles * sp + 255) / 256, big ? kRegSaturation : 1);
+        const double time = static_cast<double>(rounds) * t_tile / static_cast<double>(sp) *
                                 (1.0 + 2.0 * static_cast<double>(sp) / static_cast<double>(nk)) +
                             2.0 * static_cast<double>(partial) / 5e12 + 5e-6;
         if (time < best_t) {
