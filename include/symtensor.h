@@ -153,10 +153,13 @@
  *                          tile applies (F64/F32: "128x96", "d96x96s2", ...,
  *                          "rows" = the row-streaming product taken by default
  *                          where K and N are at most 64 and the slices hold at
- *                          least 16384 rows in all;
+ *                          least 16384 rows in all, "tallk" = the long-K
+ *                          product taken by default where M and N are at most
+ *                          64 and K is 1024 or more;
  *                          BF16X3: "b128x128k32", "bd128x256s3", ...); an
  *                          unknown or inapplicable name is ignored.
- *   SYMT_GEMM_SK=0 | 1     0 forbids stream-K and split K; 1 forces stream-K on
+ *   SYMT_GEMM_SK=0 | 1     0 forbids stream-K and split K (the long-K product's
+ *                          ranges included); 1 forces stream-K on
  *                          the global-to-LDS tiles.
  *   SYMT_FUSED_V=0         keeps V aligned in the fused product (info.fused_v = 0).
  *   SYMT_GEMM_GROUP_M=<n>  M-panels per group in the tile order of the wide

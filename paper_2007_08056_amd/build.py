@@ -27,7 +27,7 @@ COMMON = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-mllvm", "-amdgpu-mfma-vgpr-form"]
 
-LIB_SOURCES = ["plan.cpp", "symtensor.cpp", "xform.hip", "gemm.hip", "scratch.hip", "gemm_bf16x3.hip", "gemm_rows.hip"]
+LIB_SOURCES = ["plan.cpp", "symtensor.cpp", "xform.hip", "gemm.hip", "scratch.hip", "gemm_bf16x3.hip", "gemm_rows.hip", "gemm_tallk.hip"]
 # The wide split-bf16 tiles keep their 256 accumulators in AGPRs: built without
 # the VGPR-form flag.
 NO_VGPR_FORM = {"gemm_bf16x3.hip"}

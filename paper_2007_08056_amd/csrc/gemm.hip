@@ -1311,6 +1311,9 @@ hipError_t launch_fp_tile(int idx, int vec, int64_t batch, int M, int N, int K, 
 // Row-streaming product for K and N at most 64 (gemm_rows.hip).
 hipError_t launch_gemm_rows(bool f64, int64_t batch, int M, int N, int K, const void* A, const void* B, void* C,
                             hipStream_t s, const FusedTables* f);
+// Long-K product for M and N at most 64 (gemm_tallk.hip).
+hipError_t launch_gemm_tallk(bool f64, int64_t batch, int M, int N, int K, const void* A, const void* B, void* C,
+                             hipStream_t s, const FusedTables* f, void* part, int ranges);
 
 // Wide split-bf16 tiles with one binary32 accumulator (gemm_bf16x3.hip).
 hipError_t launch_bf16x3_wide(int variant, int64_t batch, int M, int N, int K, const void* A, const void* B,
@@ -1386,6 +1389,19 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
                          (reinterpret_cast<uintptr_t>(B) & 15) == 0 &&
                          (!fused || (fused->vec > 1 && fused->krun == 0 && !fused->at));
     const GemmChoice gc = choose_fp_gemm(batch, M, N, K, f64 ? 8 : 4, aligned);
+    if (gc.tile == kTallKTile) {
+      // without room for the partials (the allocation-free entry point may drop
+      // them) the 128 x 48 register tile runs instead, one workgroup per tile
+      const bool room = part && part_bytes >= gc.partial_bytes;
+      e = room ? launch_gemm_tallk(f64, batch, M, N, K, A, B, C, stream, fused, part, gc.splits)
+          : f64 ? launch_fp_tile<double>(3, vec, batch, M, N, K, A, B, C, stream, fused, nullptr, 0, 1)
+                : launch_fp_tile<float>(3, vec, batch, M, N, K, A, B, C, stream, fused, nullptr, 0, 1);
+      if (e != hipSuccess) {
+        if (err) *err = std::string("sector product launch: ") + hipGetErrorString(e);
+        return SYMT_EHIP;
+      }
+      return SYMT_OK;
+    }
     if ((!gc.sk && gc.splits <= 1) || (reinterpret_cast<uintptr_t>(part) & 15) != 0) part = nullptr;
     e = gc.tile == kRowsTile ? launch_gemm_rows(f64, batch, M, N, K, A, B, C, stream, fused)
         : f64 ? launch_fp_tile<double>(gc.tile, vec, batch, M, N, K, A, B, C, stream, fused, part, part_bytes,

@@ -1,0 +1,240 @@
+// Long-K sector product with a small output (Alg. 2's product step where M and N
+// are both at most 64 and K is long, as in a gradient with respect to a small
+// tensor): C[Q] = A[Q] B[Q], f64 or f32.
+//
+// Such a product reads 8 (M + N) bytes per index of K for 2 M N flops: HBM
+// bound, and with M, N below one 128-row tile, a tiled product would waste most
+// of its MFMA work on padding.  Here workgroup (x, Q) takes the x-th range of K;
+// its four waves take 16-deep groups of that range in turn and load their
+// MFMA operands straight from global memory into registers (A[m][k] for the
+// 16 x 4 operand of each row tile, B[k][n] likewise), one group ahead, with the
+// operands' table entries two groups ahead.  Every wave accumulates the whole
+// M x N output over its groups; the four waves are summed in LDS in wave order
+// and the workgroup's partial goes to `part`.  k_tallk_sum then adds the
+// partials of each output element in range order and writes C, so the result
+// does not depend on scheduling.  v_mfma_f64_16x16x4_f64 / v_mfma_f32_16x16x4_f32.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "gemm_common.hpp"
+#include "plan.hpp"
+
+namespace symt {
+
+namespace {
+
+template <typename T>
+struct TkMfma;
+// Accumulator rows (lane l, item r; column l % 16): f64 l/16 + 4r, f32 4(l/16) + r.
+template <>
+struct TkMfma<double> {
+  using Acc = d4;
+  static __device__ __forceinline__ Acc run(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <>
+struct TkMfma<float> {
+  using Acc = f4;
+  static __device__ __forceinline__ Acc run(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+constexpr int kTkWaves = 4;
+constexpr int kTkGroup = 16;     // K indices per group (four MFMA K-steps)
+
+// TM, TN: 16-row / 16-column tiles of the output (M <= 16 TM, N <= 16 TN).
+// kc: K indices per workgroup (a multiple of kTkGroup); gridDim.x ranges per Q.
+template <typename T, int TM, int TN>
+__global__ __launch_bounds__(64 * kTkWaves) void k_gemm_tallk(
+    const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ part, int M, int N, int K, int kc,
+    const int64_t* __restrict__ ra, const int64_t* __restrict__ ca, const int64_t* __restrict__ rb,
+    const int64_t* __restrict__ cb) {
+  using Acc = typename TkMfma<T>::Acc;
+  constexpr int MP = 16 * TM, NP = 16 * TN;
+  __shared__ T red[MP * NP];
+  const int64_t q = blockIdx.y;
+  const int x = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const int kq = lane >> 4;
+  const int k_begin = x * kc;
+  const int k_end = min(K, k_begin + kc);
+
+  // this lane's operand rows of A (one per row tile) and columns of B (one per
+  // column tile); -1 past M or N
+  int64_t arow[TM], bcol[TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    const int m = 16 * i + (lane & 15);
+    arow[i] = m < M ? (ra ? ra[q * M + m] : (q * M + m) * static_cast<int64_t>(K)) : -1;
+  }
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int n = 16 * j + (lane & 15);
+    bcol[j] = n < N ? (cb ? cb[q * N + n] : static_cast<int64_t>(n)) : -1;
+  }
+  // table entries of the lane's four K indices of a group: A's column offset and
+  // B's row offset (-1 past the range)
+  auto tables = [&](int g0, int64_t (&ak)[4], int64_t (&bk)[4]) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = g0 + 4 * u + kq;
+      const bool ok = k < k_end;
+      ak[u] = ok ? (ca ? ca[q * K + k] : static_cast<int64_t>(k)) : -1;
+      bk[u] = ok ? (rb ? rb[q * K + k] : (q * K + k) * static_cast<int64_t>(N)) : -1;
+    }
+  };
+  auto operands = [&](const int64_t (&ak)[4], const int64_t (&bk)[4], T (&a)[4][TM], T (&b)[4][TN]) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a[u][i] = ak[u] >= 0 && arow[i] >= 0 ? A[arow[i] + ak[u]] : T(0);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) b[u][j] = bk[u] >= 0 && bcol[j] >= 0 ? B[bk[u] + bcol[j]] : T(0);
+    }
+  };
+
+  Acc acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = Acc{};
+  const int gstep = kTkWaves * kTkGroup;
+  int g = k_begin + wave * kTkGroup;
+  if (g < k_end) {
+    T a[4][TM], b[4][TN], an[4][TM], bn[4][TN];
+    int64_t ak[4], bk[4], ak2[4], bk2[4];
+    tables(g, ak, bk);
+    operands(ak, bk, a, b);
+    if (g + gstep < k_end) tables(g + gstep, ak, bk);
+    for (; g < k_end; g += gstep) {
+      const bool more = g + gstep < k_end;
+      if (g + 2 * gstep < k_end) tables(g + 2 * gstep, ak2, bk2);
+      if (more) operands(ak, bk, an, bn);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) acc[i][j] = TkMfma<T>::run(a[u][i], b[u][j], acc[i][j]);
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+          for (int i = 0; i < TM; ++i) a[u][i] = an[u][i];
+#pragma unroll
+          for (int j = 0; j < TN; ++j) b[u][j] = bn[u][j];
+          ak[u] = ak2[u];
+          bk[u] = bk2[u];
+        }
+      }
+    }
+  }
+  // the four waves' sums in wave order, then the workgroup's partial [m][n]
+  for (int w = 0; w < kTkWaves; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int e = (16 * i + TkMfma<T>::row(lane, r)) * NP + 16 * j + (lane & 15);
+            red[e] = w == 0 ? acc[i][j][r] : red[e] + acc[i][j][r];
+          }
+    }
+    __syncthreads();
+  }
+  T* pw = part + (q * gridDim.x + x) * static_cast<int64_t>(M) * N;
+  for (int e = static_cast<int>(threadIdx.x); e < M * N; e += 64 * kTkWaves) {
+    const int m = e / N, n = e - (e / N) * N;
+    pw[e] = red[m * NP + n];
+  }
+}
+
+// C = the sum over ranges, in range order, of the partials (one thread per
+// output element; grid (elements / 256, Q)).
+template <typename T>
+__global__ __launch_bounds__(256) void k_tallk_sum(const T* __restrict__ part, T* __restrict__ C, int M, int N,
+                                                   int ranges, const int64_t* __restrict__ rc,
+                                                   const int64_t* __restrict__ cc) {
+  const int64_t q = blockIdx.y;
+  const int e = static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);
+  if (e >= M * N) return;
+  const int64_t mn = static_cast<int64_t>(M) * N;
+  const T* p = part + q * ranges * mn + e;
+  T acc = T(0);
+#pragma unroll 8
+  for (int x = 0; x < ranges; ++x) acc += p[x * mn];
+  const int m = e / N, n = e - (e / N) * N;
+  const int64_t off = rc ? rc[q * M + m] + cc[q * N + n] : (q * M + m) * static_cast<int64_t>(N) + n;
+  C[off] = acc;
+}
+
+template <typename T, int TM, int TN>
+hipError_t launch_mn(int64_t batch, int M, int N, int K, const T* A, const T* B, T* C, hipStream_t s,
+                     const FusedTables* f, T* part, int ranges, int kc) {
+  const int64_t* ra = f ? f->ra : nullptr;
+  const int64_t* ca = f ? f->ca : nullptr;
+  const int64_t* rb = f ? f->rb : nullptr;
+  const int64_t* cb = f ? f->cb : nullptr;
+  const int64_t* rc = f ? f->rc : nullptr;
+  const int64_t* cc = f ? f->cc : nullptr;
+  hipLaunchKernelGGL((k_gemm_tallk<T, TM, TN>), dim3(static_cast<unsigned>(ranges), static_cast<unsigned>(batch)),
+                     dim3(64 * kTkWaves), 0, s, A, B, part, M, N, K, kc, ra, ca, rb, cb);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_tallk_sum<T>), dim3(static_cast<unsigned>((M * N + 255) / 256), static_cast<unsigned>(batch)),
+                     dim3(256), 0, s, part, C, M, N, ranges, rc, cc);
+  return hipGetLastError();
+}
+
+template <typename T, int TM>
+hipError_t launch_m(int tn, int64_t batch, int M, int N, int K, const T* A, const T* B, T* C, hipStream_t s,
+                    const FusedTables* f, T* part, int ranges, int kc) {
+  switch (tn) {
+    case 1: return launch_mn<T, TM, 1>(batch, M, N, K, A, B, C, s, f, part, ranges, kc);
+    case 2: return launch_mn<T, TM, 2>(batch, M, N, K, A, B, C, s, f, part, ranges, kc);
+    case 3: return launch_mn<T, TM, 3>(batch, M, N, K, A, B, C, s, f, part, ranges, kc);
+    default: return launch_mn<T, TM, 4>(batch, M, N, K, A, B, C, s, f, part, ranges, kc);
+  }
+}
+
+template <typename T>
+hipError_t launch_typed_tallk(int64_t batch, int M, int N, int K, const void* A, const void* B, void* C,
+                              hipStream_t s, const FusedTables* f, void* part, int ranges) {
+  const T* a = static_cast<const T*>(A);
+  const T* b = static_cast<const T*>(B);
+  T* c = static_cast<T*>(C);
+  T* pt = static_cast<T*>(part);
+  const int kc = tallk_range(K, ranges);
+  const int tm = (M + 15) / 16, tn = (N + 15) / 16;
+  switch (tm) {
+    case 1: return launch_m<T, 1>(tn, batch, M, N, K, a, b, c, s, f, pt, ranges, kc);
+    case 2: return launch_m<T, 2>(tn, batch, M, N, K, a, b, c, s, f, pt, ranges, kc);
+    case 3: return launch_m<T, 3>(tn, batch, M, N, K, a, b, c, s, f, pt, ranges, kc);
+    default: return launch_m<T, 4>(tn, batch, M, N, K, a, b, c, s, f, pt, ranges, kc);
+  }
+}
+
+}  // namespace
+
+// C[q] = A[q] B[q] for M, N <= 64 (f64 when f64, else f32) over `ranges` ranges
+// of K per slice (tallk_ranges); `part` holds batch * ranges * M * N partials.
+// f: the operands' offset tables (nullptr or null tables: aligned row-major
+// A [Q][M][K], B [Q][K][N], C [Q][M][N]).  batch <= 65535.
+hipError_t launch_gemm_tallk(bool f64, int64_t batch, int M, int N, int K, const void* A, const void* B, void* C,
+                             hipStream_t s, const FusedTables* f, void* part, int ranges) {
+  if (M < 1 || M > 64 || N < 1 || N > 64 || K < 1 || batch < 1 || batch > 65535 || ranges < 1 || !part)
+    return hipErrorInvalidValue;
+  return f64 ? launch_typed_tallk<double>(batch, M, N, K, A, B, C, s, f, part, ranges)
+             : launch_typed_tallk<float>(batch, M, N, K, A, B, C, s, f, part, ranges);
+}
+
+}  // namespace symt

@@ -644,6 +644,19 @@ GemmChoice choose_among(int64_t batch, int64_t M, int64_t N, int64_t K, int elem
   // K and N at most 64: 2 K N flops per 8 (K + N) bytes of A and C, bound by HBM
   // on any tile; the row-streaming product reads A once and keeps B in LDS
   // (named "rows"; it needs enough rows to spread over the device)
+  // M and N at most 64 with a long K: 2 M N flops per 8 (M + N) bytes, HBM
+  // bound, and most of any 128-wide tile would be padding; the long-K product
+  // splits K over ranges and sums their partials in order (named "tallk")
+  const bool tallk_forced = forced && std::strcmp(forced, "tallk") == 0;
+  if (M >= 1 && M <= 64 && N >= 1 && N <= 64 && K >= 1 && batch >= 1 && batch <= 65535 && K <= INT32_MAX &&
+      (tallk_forced || (!forced && K >= 1024 && sk_mode != 0))) {
+    best.tile = kTallKTile;
+    best.bm = static_cast<int>(M);
+    best.bn = static_cast<int>(N);
+    best.splits = tallk_ranges(batch, K);
+    best.partial_bytes = static_cast<size_t>(batch) * best.splits * M * N * elem;
+    return best;
+  }
   const bool rows_forced = forced && std::strcmp(forced, "rows") == 0;
   if (K >= 1 && K <= 64 && N >= 1 && N <= 64 && batch >= 1 && batch <= 65535 && M >= 1 &&
       (rows_forced || (!forced && batch * M >= 16384))) {

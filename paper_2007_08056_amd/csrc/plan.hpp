@@ -241,6 +241,22 @@ constexpr int kSkSlots = 768;
 // GemmChoice::tile of the row-streaming product (K and N at most 64, many rows):
 // past the tile table.
 constexpr int kRowsTile = 64;
+// GemmChoice::tile of the long-K product with M and N at most 64 (GemmChoice::
+// splits = its K ranges per slice, partial_bytes = their partial outputs).
+constexpr int kTallKTile = 65;
+// K ranges per slice of the long-K product (about two workgroups per CU over
+// all slices, at least 256 K indices each) and the K indices of each range (a
+// multiple of 16, the last range shorter or empty).
+inline int tallk_ranges(int64_t batch, int64_t K) {
+  const int64_t want = (512 + batch - 1) / (batch > 0 ? batch : 1);
+  const int64_t most = (K + 255) / 256;
+  const int64_t r = want < most ? want : most;
+  return static_cast<int>(r < 1 ? 1 : r);
+}
+inline int tallk_range(int64_t K, int ranges) {
+  const int64_t per = (K + ranges - 1) / ranges;
+  return static_cast<int>((per + 15) / 16 * 16);
+}
 // Fewest K-iterations a stream-K workgroup takes on (bounds the pieces per tile).
 constexpr int kSkMinIters = 4;
 GemmChoice choose_fp_gemm(int64_t batch, int64_t M, int64_t N, int64_t K, int elem, bool aligned);

@@ -378,6 +378,65 @@ void replay_rows(int64_t resident, int64_t batch, int64_t M, int64_t N, int64_t 
   CHECK(total == batch * M * N, "row product C elements not all written", total, batch * M * N);
 }
 
+// The long-K product (M and N at most 64): the index walk of its two launches.
+// Every K index multiplied exactly once per slice, every A and B read inside its
+// operand, partials inside their buffer, every C element written exactly once.
+void replay_tallk(int64_t batch, int64_t M, int64_t N, int64_t K, const std::vector<int64_t>& ra,
+                  const std::vector<int64_t>& ca, const std::vector<int64_t>& rb, const std::vector<int64_t>& cb,
+                  const std::vector<int64_t>& rc, const std::vector<int64_t>& cc, int64_t a_n, int64_t b_n,
+                  int64_t c_n) {
+  const int ranges = tallk_ranges(batch, K);
+  const int kc = tallk_range(K, ranges);
+  CHECK(kc % 16 == 0 && static_cast<int64_t>(kc) * ranges >= K, "long-K ranges do not cover K", kc, ranges);
+  const int64_t part_n = batch * ranges * M * N;
+  std::vector<uint8_t> written(static_cast<size_t>(c_n), 0);
+  std::vector<uint8_t> part_w(static_cast<size_t>(part_n), 0);
+  const int64_t tm = (M + 15) / 16, tn = (N + 15) / 16;
+  for (int64_t q = 0; q < batch; ++q) {
+    std::vector<uint8_t> cover(static_cast<size_t>(K), 0);
+    for (int x = 0; x < ranges; ++x) {
+      const int64_t k_begin = static_cast<int64_t>(x) * kc, k_end = std::min<int64_t>(K, k_begin + kc);
+      for (int w = 0; w < 4; ++w)
+        for (int64_t g = k_begin + w * 16; g < k_end; g += 64)
+          for (int lane = 0; lane < 64; ++lane)
+            for (int u = 0; u < 4; ++u) {
+              const int64_t k = g + 4 * u + (lane >> 4);
+              if (k >= k_end) continue;
+              if ((lane & 15) == 0) cover[k]++;   // one lane per K index and row tile
+              const int64_t ak = ca.empty() ? k : ca[q * K + k];
+              const int64_t bk = rb.empty() ? (q * K + k) * N : rb[q * K + k];
+              for (int64_t i = 0; i < tm; ++i) {
+                const int64_t m = 16 * i + (lane & 15);
+                if (m >= M) continue;
+                const int64_t a = (ra.empty() ? (q * M + m) * K : ra[q * M + m]) + ak;
+                CHECK(a >= 0 && a < a_n, "long-K A read out of bounds", a, a_n);
+              }
+              for (int64_t j = 0; j < tn; ++j) {
+                const int64_t n = 16 * j + (lane & 15);
+                if (n >= N) continue;
+                const int64_t b = bk + (cb.empty() ? n : cb[q * N + n]);
+                CHECK(b >= 0 && b < b_n, "long-K B read out of bounds", b, b_n);
+              }
+            }
+      for (int64_t e = 0; e < M * N; ++e) {
+        const int64_t pe = (q * ranges + x) * M * N + e;
+        CHECK(pe >= 0 && pe < part_n && part_w[pe] == 0, "long-K partial out of bounds or twice", pe, part_n);
+        if (pe >= 0 && pe < part_n) part_w[pe]++;
+      }
+    }
+    for (int64_t k = 0; k < K; ++k) CHECK(cover[k] == 1, "long-K index not multiplied once", k, cover[k]);
+    for (int64_t e = 0; e < M * N; ++e) {
+      const int64_t m = e / N, n = e % N;
+      const int64_t c = rc.empty() ? (q * M + m) * N + n : rc[q * M + m] + cc[q * N + n];
+      CHECK(c >= 0 && c < c_n, "long-K C write out of bounds", c, c_n);
+      if (c >= 0 && c < c_n) {
+        CHECK(written[c] == 0, "long-K C written twice", c, 0);
+        written[c]++;
+      }
+    }
+  }
+}
+
 void check_fused(const Plan& p) {
   if (!(p.fused || p.fused_ua)) return;
   const int G = p.g.size;
@@ -399,6 +458,12 @@ void check_fused(const Plan& p) {
     rb = table(make_offsets(p, 1, true), G);
     cb = table(make_offsets(p, 1, false), G);
     check_bijection(rb, cb, G, p.gk, p.gn, p.V.elems, "V tables not a bijection onto V");
+  }
+  if (p.compute != SYMT_COMPUTE_BF16X3 && p.M <= 64 && p.gn <= 64) {
+    const std::vector<int64_t> none;
+    const int64_t b_n = p.fused_b ? p.V.elems : G * p.gk * p.gn;
+    replay_tallk(G, p.M, p.gn, p.gk, ra, ca, p.fused_b ? rb : none, p.fused_b ? cb : none, rc, cc,
+                 p.fused_ua ? G * p.M * p.gk : p.U.elems * cm, b_n, p.W.elems * cm);
   }
   if (p.compute != SYMT_COMPUTE_BF16X3 && p.gk <= 64 && p.gn <= 64) {
     const std::vector<int64_t> none;

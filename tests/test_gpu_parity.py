@@ -825,6 +825,36 @@ def test_row_streaming_product(P, compute, monkeypatch):
         assert np.array_equal(H.to_np(P.sector_gemm(a, bb, compute)), C)
 
 
+@pytest.mark.parametrize("compute", ["f64", "f32"])
+def test_long_k_product(P, compute, monkeypatch):
+    """The long-K product (M and N at most 64): forced on small and ragged shapes
+    (M, N of 1 and 64, K of 3 and not a multiple of 16, one and many slices)
+    and taken by default on long K, within the product's bound of an FP64
+    matmul and run-to-run identical (ranges summed in order)."""
+    monkeypatch.delenv("SYMT_GEMM_SK", raising=False)
+    cases = [("tallk", (1, 1, 1, 1)), ("tallk", (2, 16, 3, 16)), ("tallk", (3, 17, 5000, 33)),
+             ("tallk", (2, 64, 1030, 64)), ("tallk", (1, 5, 4097, 1)), ("tallk", (700, 3, 40, 2)),
+             ("", (6, 48, 20000, 48)), ("", (1, 64, 300000, 64)), ("", (2, 9, 1024, 50))]
+    for tile, shape in cases:
+        if tile:
+            monkeypatch.setenv("SYMT_GEMM_TILE", tile)
+        else:
+            monkeypatch.delenv("SYMT_GEMM_TILE", raising=False)
+        b, m, k, n = shape
+        say(f"long-K product {compute} tile={tile or 'default'} {shape}")
+        rng = np.random.default_rng(m * 5 + n + k)
+        dt = torch.float64 if compute == "f64" else torch.float32
+        a = torch.from_numpy(rng.standard_normal((b, m, k))).to(DEV, dt)
+        bb = torch.from_numpy(rng.standard_normal((b, k, n))).to(DEV, dt)
+        C = H.to_np(P.sector_gemm(a, bb, compute))
+        A64, B64 = H.to_np(a).astype(np.float64), H.to_np(bb).astype(np.float64)
+        ref = np.matmul(A64, B64)
+        absb = np.matmul(np.abs(A64), np.abs(B64))
+        fac = 2 * H.gamma(k, H.U64) if compute == "f64" else 1.05 * H.gamma(k, H.U32)
+        assert np.all(np.abs(C - ref) <= fac * absb + 1e-300), (compute, shape)
+        assert np.array_equal(H.to_np(P.sector_gemm(a, bb, compute)), C)
+
+
 ROW_CASES = [
     # W's rows contiguous (its last modes from U): lanes store along rows
     ("cASB,bsSB->bcsA", (2, 3), "----", "+---", (6, 16, 2, 4), (4, 2, 2, 4)),
@@ -837,16 +867,25 @@ ROW_CASES = [
 ]
 
 
-@pytest.mark.parametrize("case", ROW_CASES)
+# Long K with M and N at most 64 (a gradient with respect to a small operand).
+TALLK_CASES = [
+    ("bcsA,cASB->bsSB", (2, 3), "--+-", "----", (4, 16, 2, 16), (16, 16, 2, 4)),
+    ("ak,kb->ab", (5,), "+-", "++", (7, 3000), (3000, 9)),
+    ("klab,klc->abc", (3,), "++-+", "--+", (40, 30, 2, 3), (40, 30, 5)),
+]
+
+
+@pytest.mark.parametrize("case", [("rows", c) for c in ROW_CASES] + [("tallk", c) for c in TALLK_CASES])
 @pytest.mark.parametrize("compute", ["f64", "f32"])
-def test_row_streaming_product_in_place(P, case, compute, monkeypatch):
-    """The row-streaming product forced on fused contractions (U and V read in
-    place where they can, W written in place, lanes along W's contiguous index):
+def test_short_products_in_place(P, case, compute, monkeypatch):
+    """The row-streaming product (K, N <= 64) and the long-K product (M, N <=
+    64) forced on fused contractions (U and V read in place where they can, W
+    written in place; row-streaming lanes along W's contiguous index):
     bit-identical to the three-step path on the same kernel (the transposed
     MFMA forms the same products in the same K order), within the product's
     bound of the oracle, with and without charge tables."""
-    sub, orders, cu, cv, du, dv = case
-    monkeypatch.setenv("SYMT_GEMM_TILE", "rows")
+    tile, (sub, orders, cu, cv, du, dv) = case
+    monkeypatch.setenv("SYMT_GEMM_TILE", tile)
     monkeypatch.delenv("SYMT_GEMM_SK", raising=False)
     rng = np.random.default_rng(seed("rows", sub, orders))
     g = O.Group(orders)
@@ -855,7 +894,7 @@ def test_row_streaming_product_in_place(P, case, compute, monkeypatch):
     dt = torch.float64 if compute == "f64" else torch.float32
     for tables in (False, True):
         su, sv = _with_tables(rng, sub, su0, sv0) if tables else (su0, sv0)
-        say(f"rows in place {sub} G={orders} {compute} tables={tables}")
+        say(f"{tile} in place {sub} G={orders} {compute} tables={tables}")
         Ru = rng.standard_normal(su.reduced_shape())
         Rv = rng.standard_normal(sv.reduced_shape())
         u = _sym_tensor(P, Ru, su, dt)
