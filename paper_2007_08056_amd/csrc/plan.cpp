@@ -1046,7 +1046,7 @@ XformParams make_xform(const Plan& p, int operand, bool to_aligned, int in_bytes
     x.run_chunk = x.run_len > 16384 ? 8192 : std::max<int64_t>(x.run_len, 1);
     x.run_tiles = (x.run_len + x.run_chunk - 1) / x.run_chunk;
     // rows per workgroup: about 64 KB of source each (short runs take many rows,
-    // moved 256 at a time), so the per-workgroup block arithmetic stays small
+    // moved 1024 at a time), so the per-workgroup block arithmetic stays small
     int64_t rpt = std::max<int64_t>(1, 65536 / std::max<int64_t>(1, x.run_chunk * in_bytes));
     rpt = std::max<int64_t>(rpt, 256 / lanes);
     rpt = std::min<int64_t>(rpt, 4096);

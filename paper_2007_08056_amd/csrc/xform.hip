@@ -62,8 +62,9 @@ __device__ __forceinline__ void store_vec(void* dst, int64_t off, int64_t plane,
 template <typename Tin, int OUT, int V>
 __global__ __launch_bounds__(256) void k_xform_copy(const Tin* __restrict__ src,
                                                     void* __restrict__ dst, const XformParams p) {
-  __shared__ int64_t soff[256];
-  __shared__ int64_t doff[256];
+  constexpr int kRows = 1024;                    // rows whose offsets sit in LDS at once
+  __shared__ int64_t soff[kRows];
+  __shared__ int64_t doff[kRows];
   const int64_t wg = blockIdx.x;
   const int64_t blk = wg / p.tiles_per_block;
   const int64_t tile = wg - blk * p.tiles_per_block;
@@ -77,15 +78,15 @@ __global__ __launch_bounds__(256) void k_xform_copy(const Tin* __restrict__ src,
   if (!live && !p.to_aligned) return;
   const int64_t src_base = p.to_aligned ? sb : ab;
   const int64_t dst_base = p.to_aligned ? ab : sb;
-  // this workgroup's rows [r_begin, r_end), moved 256 at a time (their offsets in LDS)
+  // this workgroup's rows [r_begin, r_end), moved kRows at a time (their offsets in LDS)
   const int64_t r_begin = row_tile * p.rows_per_tile;
   const int64_t r_end = r_begin + p.rows_per_tile < p.rows ? r_begin + p.rows_per_tile : p.rows;
   const int lane = threadIdx.x & (p.lanes_per_row - 1);
   const int sub = threadIdx.x >> p.lanes_log2;
   const int rpp = blockDim.x >> p.lanes_log2;
   const int64_t step = static_cast<int64_t>(p.lanes_per_row) * V;
-  for (int64_t r0 = r_begin; r0 < r_end; r0 += 256) {
-  const int nr = static_cast<int>(r_end - r0 < 256 ? r_end - r0 : 256);
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += kRows) {
+  const int nr = static_cast<int>(r_end - r0 < kRows ? r_end - r0 : kRows);
   if (r0 > r_begin) __syncthreads();             // the previous rows' offsets are no longer read
   for (int r = threadIdx.x; r < nr; r += blockDim.x) {
     int64_t rem = r0 + r, so = 0, dof = 0;
@@ -100,23 +101,51 @@ __global__ __launch_bounds__(256) void k_xform_copy(const Tin* __restrict__ src,
     doff[r] = dst_base + dof;
   }
   __syncthreads();
-  for (int r = sub; r < nr; r += rpp) {
-    const int64_t s0 = soff[r], d0 = doff[r];
-    for (int64_t c = c_begin + static_cast<int64_t>(lane) * V; c < c_end; c += step) {
-      double x[V];
-      if constexpr (V == 1) {
-        x[0] = live ? static_cast<double>(src[s0 + c * p.run_ss]) : 0.0;
-        store_vec<OUT, 1>(dst, d0 + c * p.run_ds, p.plane, x);
+  // Four loads go out before their stores (a load waits for nothing but its
+  // own data): four rows at a time where each lane holds at most one vector of
+  // a row, else four vectors of one row at a time.
+  auto load = [&](int64_t s0, int64_t c, double (&x)[V]) {
+    if constexpr (V == 1) {
+      x[0] = live ? static_cast<double>(src[s0 + c * p.run_ss]) : 0.0;
+    } else {
+      if (live) {
+        const VecT<Tin, V> in = *reinterpret_cast<const VecT<Tin, V>*>(src + s0 + c);
+#pragma unroll
+        for (int i = 0; i < V; ++i) x[i] = static_cast<double>(in.v[i]);
       } else {
-        if (live) {
-          const VecT<Tin, V> in = *reinterpret_cast<const VecT<Tin, V>*>(src + s0 + c);
 #pragma unroll
-          for (int i = 0; i < V; ++i) x[i] = static_cast<double>(in.v[i]);
-        } else {
+        for (int i = 0; i < V; ++i) x[i] = 0.0;
+      }
+    }
+  };
+  auto store = [&](int64_t d0, int64_t c, const double (&x)[V]) {
+    store_vec<OUT, V>(dst, d0 + (V == 1 ? c * p.run_ds : c), p.plane, x);
+  };
+  constexpr int U = 4;
+  const int64_t c0 = c_begin + static_cast<int64_t>(lane) * V;
+  if (c_end - c_begin <= step) {
+    if (c0 < c_end) {
+      for (int r = sub; r < nr; r += U * rpp) {
+        double x[U][V];
 #pragma unroll
-          for (int i = 0; i < V; ++i) x[i] = 0.0;
-        }
-        store_vec<OUT, V>(dst, d0 + c, p.plane, x);
+        for (int u = 0; u < U; ++u)
+          if (r + u * rpp < nr) load(soff[r + u * rpp], c0, x[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (r + u * rpp < nr) store(doff[r + u * rpp], c0, x[u]);
+      }
+    }
+  } else {
+    for (int r = sub; r < nr; r += rpp) {
+      const int64_t s0 = soff[r], d0 = doff[r];
+      for (int64_t c = c0; c < c_end; c += U * step) {
+        double x[U][V];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (c + u * step < c_end) load(s0, c + u * step, x[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (c + u * step < c_end) store(d0, c + u * step, x[u]);
       }
     }
   }
@@ -176,8 +205,17 @@ __global__ __launch_bounds__(256) void k_xform_transpose(const Tin* __restrict__
   const int x = t & 63;
   const int y = t >> 6;
   if (x < na) {
+    // all sixteen of this thread's loads go out before the first LDS write
     const int64_t sx = so + a_src[x];
-    for (int j = y; j < nb; j += 4) tile[j][x] = live ? static_cast<double>(src[sx + b_src[j]]) : 0.0;
+    double v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int j = y + 4 * k;
+      v[k] = live && j < nb ? static_cast<double>(src[sx + b_src[j]]) : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      if (y + 4 * k < nb) tile[y + 4 * k][x] = v[k];
   }
   __syncthreads();
   if (x < nb) {

@@ -137,7 +137,7 @@ void replay_xform(const XformParams& x, int64_t src_n, int64_t dst_n, bool dst_s
       const int64_t c_end = std::min(c_begin + x.run_chunk, x.run_len);
       const int64_t r0 = row_tile * x.rows_per_tile;
       const int nr = static_cast<int>(std::min<int64_t>(x.rows - r0, x.rows_per_tile));
-      // (the kernel moves them 256 at a time through its LDS row table)
+      // (the kernel moves them 1024 at a time through its LDS row table)
       CHECK(nr >= 1, "copy tile without rows", nr, x.rows);
       const int V = x.vec;
       CHECK(c_begin % V == 0, "vector chunk start", c_begin, V);
