@@ -300,7 +300,10 @@ int symtensor_workspace_size(const char* einsum, const symt_group* group, const 
  * sub-buffers, in that order), or for the fused product V_al and the offset
  * tables; then, where the product runs stream-K (see symtensor_sector_gemm),
  * the pieces of the tiles it cuts; then, with non-identity charge tables,
- * their device copies.
+ * their device copies.  With BF16X3 the workspace's U_al and V_al planes hold
+ * K at a pitch rounded up to a multiple of 8 (the pad cleared to zero), so
+ * any contracted extent works; the standalone symtensor_align layouts keep K
+ * unpadded.
  * w->data must not overlap u->data, v->data or the workspace, and u->data and
  * v->data must not overlap the workspace (SYMT_EALIAS).
  * Storage dtypes: SYMT_COMPUTE_F64 takes any mix of F64/F32 operands
@@ -357,9 +360,11 @@ int symtensor_unalign(symt_ctx* ctx, const char* einsum, const symt_group* group
  * set of persistent workgroups takes equal shares of all tiles' K-iterations,
  * so the last wave of tiles no longer idles most of the device; tiles cut
  * between two workgroups are stored here as pieces and summed afterwards in K
- * order (the result does not depend on scheduling).  With a NULL or smaller
- * workspace the product runs one workgroup per tile.  The two launches differ
- * only in floating-point summation order. */
+ * order (the result does not depend on scheduling).  It also holds split-K
+ * partial tiles and the long-K product's range partials (m, n <= 64).  With a
+ * NULL or smaller workspace the product runs one workgroup per tile.  The
+ * launches differ only in floating-point summation order.  BF16X3 needs k a
+ * multiple of 8 here (SYMT_EUNSUPPORTED otherwise). */
 int symtensor_sector_gemm(symt_ctx* ctx, int32_t compute, int64_t batch, int64_t m, int64_t k,
                           int64_t n, const void* a, const void* b, void* c, void* workspace,
                           size_t workspace_bytes, void* stream);

@@ -441,6 +441,10 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   // complex: the real representation doubles the contracted and output columns
   p->gk = p->cplx ? 2 * p->Kd : p->Kd;
   p->gn = p->cplx ? 2 * p->N : p->N;
+  // the split-bf16 products read K in 16-byte chunks of 8: the contraction's
+  // workspace planes take a zero pad up to a multiple of 8 (the standalone
+  // aligned layouts keep K unpadded)
+  p->kpad = compute == SYMT_COMPUTE_BF16X3 ? (p->gk + 7) / 8 * 8 : p->gk;
   if (p->M > INT32_MAX || p->gn > INT32_MAX || p->gk > INT32_MAX)
     return fail(err, SYMT_EUNSUPPORTED, "aligned matrix dimension above 2^31-1");
   p->flops = 2.0 * static_cast<double>(p->nq) * static_cast<double>(p->M) * static_cast<double>(p->gk) *
@@ -458,8 +462,8 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   p->bytes_v_al = ea * static_cast<size_t>(av);
   p->bytes_w_al = ec * static_cast<size_t>(aw);
   const size_t G = static_cast<size_t>(p->g.size), nq = static_cast<size_t>(p->nq);
-  p->ws_u_al = p->bytes_u_al / G * nq;
-  p->ws_v_al = p->bytes_v_al / G * nq;
+  p->ws_u_al = ea * static_cast<size_t>(p->M) * static_cast<size_t>(p->kpad) * nq;
+  p->ws_v_al = ea * static_cast<size_t>(p->kpad) * static_cast<size_t>(p->gn) * nq;
   p->ws_w_al = p->bytes_w_al / G * nq;
   p->workspace = round_up(p->ws_u_al, 256) + round_up(p->ws_v_al, 256) + round_up(p->ws_w_al, 256);
 
@@ -904,10 +908,14 @@ XformParams make_xform(const Plan& p, int operand, bool to_aligned, int in_bytes
   for (int i = 0; i < C.count; ++i) nC *= X.dims[C.pos[i]];
   const int64_t rows_tot = x.gpow_row * nR * row_mult, cols_tot = x.gpow_col * nC * cm;
   const AlignedLayout lay = aligned_layout(p.compute, operand);
-  x.q_stride = rows_tot * cols_tot;
-  x.plane = (x.q_full ? static_cast<int64_t>(G) : nslices) * rows_tot * cols_tot;
-  const int64_t row_unit = lay == kRowMajor ? cols_tot : 1;   // aligned stride of one real row
-  const int64_t col_unit = lay == kRowMajor ? 1 : rows_tot;   // aligned stride of one real column
+  // the contraction's split-bf16 planes: K (U's columns, V's rows) at pitch kpad
+  const bool pad = slice_only && p.compute == SYMT_COMPUTE_BF16X3 && operand < 2 && p.kpad != p.gk;
+  const int64_t rows_pitch = pad && operand == 1 ? p.kpad : rows_tot;
+  const int64_t cols_pitch = pad && operand == 0 ? p.kpad : cols_tot;
+  x.q_stride = rows_pitch * cols_pitch;
+  x.plane = (x.q_full ? static_cast<int64_t>(G) : nslices) * x.q_stride;
+  const int64_t row_unit = lay == kRowMajor ? cols_pitch : 1;   // aligned stride of one real row
+  const int64_t col_unit = lay == kRowMajor ? 1 : rows_pitch;   // aligned stride of one real column
   x.rs_stride = nR * row_mult * row_unit;
   x.cs_stride = nC * cm * col_unit;
   x.to_aligned = to_aligned ? 1 : 0;

@@ -169,6 +169,8 @@ struct Plan {
   bool cplx = false;                // complex operands: the product runs on C's real representation
   bool subgroups = false;           // some mode has fewer than |G| sectors
   int64_t gk = 0, gn = 0;           // the real product's K and N (2 Kd, 2 N when complex)
+  int64_t kpad = 0;                 // split-bf16: K pitch of the contraction's workspace
+                                    // planes (gk rounded up to 8; the pad is zero), else gk
   OperandDesc U, V, W;
   bool has_w = false;
   int32_t w_sign[kMaxOrder];        // derived

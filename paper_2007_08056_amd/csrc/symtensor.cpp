@@ -170,6 +170,17 @@ int do_unalign(symt_ctx* ctx, const Plan& p, const void* wal, hipStream_t s, boo
   return rc ? ctx_fail(ctx, rc, err) : SYMT_OK;
 }
 
+// Split-bf16 planes with K padded to a multiple of 8 (kpad): clear them before
+// the transforms fill their first gk columns, so the pad multiplies as zero.
+int clear_k_pad(symt_ctx* ctx, const Plan& p, void* ual, void* val, hipStream_t s) {
+  if (p.compute != SYMT_COMPUTE_BF16X3 || p.kpad == p.gk) return SYMT_OK;
+  std::string err;
+  int rc = SYMT_OK;
+  if (ual && p.ws_u_al > 0) rc = symt::launch_zero(ual, p.ws_u_al, s, &err);
+  if (rc == SYMT_OK && val && p.ws_v_al > 0) rc = symt::launch_zero(val, p.ws_v_al, s, &err);
+  return rc ? ctx_fail(ctx, rc, err) : SYMT_OK;
+}
+
 int do_gemm(symt_ctx* ctx, int compute, int64_t batch, int64_t m, int64_t k, int64_t n,
             const void* a, const void* b, void* c, hipStream_t s,
             const symt::FusedTables* fused = nullptr, void* part = nullptr, size_t part_bytes = 0,
@@ -302,6 +313,7 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
   }
   if (tlock.owns_lock()) tlock.unlock();
   if (rc_) return ctx_fail(ctx, rc_, err);
+  if (p.fused_ua && (rc_ = clear_k_pad(ctx, p, ual, fb ? nullptr : val, s))) return rc_;
   if (p.fused_ua && (rc_ = do_align(ctx, p, 0, ual, s, true, chg[0]))) return rc_;
   if (!fb && (rc_ = do_align(ctx, p, 1, val, s, true, chg[1]))) return rc_;
   symt::FusedTables f{ra, ca, rc, cc, vec};
@@ -319,7 +331,8 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
     f.cb = cb;
     f.ldb = p.ldb;
   }
-  return do_gemm(ctx, p.compute, p.g.size, p.M, p.gk, p.gn, p.fused_ua ? ual : p.U.data, fb ? p.V.data : val,
+  return do_gemm(ctx, p.compute, p.g.size, p.M, p.fused_ua ? p.kpad : p.gk, p.gn, p.fused_ua ? ual : p.U.data,
+                 fb ? p.V.data : val,
                  p.W.data, s, &f,
                  p.bytes_partial ? part : nullptr, p.bytes_partial);
 }
@@ -530,9 +543,6 @@ int contract_planned(symt_ctx* ctx, const Plan& p, void* workspace, size_t works
   // the workspace is written (aligned forms, tables, pieces) before u and v are read
   if (overlaps(p.U.data, ub, workspace, p.workspace) || overlaps(p.V.data, vb, workspace, p.workspace))
     return ctx_fail(ctx, SYMT_EALIAS, "an input overlaps the workspace");
-  if (p.compute == SYMT_COMPUTE_BF16X3 && p.gk % 8 != 0)
-    return ctx_fail(ctx, SYMT_EUNSUPPORTED,
-                    "split-bf16 product needs the aligned contracted extent to be a multiple of 8");
   if (p.workspace > 0 && !aligned16(workspace))
     return ctx_fail(ctx, SYMT_EUNSUPPORTED, "workspace must be 16-byte aligned");
   if ((rc = set_device(ctx))) return rc;
@@ -555,11 +565,12 @@ int contract_planned(symt_ctx* ctx, const Plan& p, void* workspace, size_t works
   void* val = base + symt::round_up(p.ws_u_al, 256);
   void* wal = base + symt::round_up(p.ws_u_al, 256) + symt::round_up(p.ws_v_al, 256);
   char* part = static_cast<char*>(wal) + symt::round_up(p.ws_w_al, 256);
+  if ((rc = clear_k_pad(ctx, p, ual, val, s))) return rc;
   if ((rc = do_align(ctx, p, 0, ual, s, true, chg[0]))) return rc;
   if ((rc = do_align(ctx, p, 1, val, s, true, chg[1]))) return rc;
   // the workspace holds the nq live slices in order: one batched product of them
   // (none live: no block of W is reached, and the unalign step clears W)
-  if (p.nq > 0 && (rc = do_gemm(ctx, p.compute, p.nq, p.M, p.gk, p.gn, ual, val, wal, s, nullptr,
+  if (p.nq > 0 && (rc = do_gemm(ctx, p.compute, p.nq, p.M, p.kpad, p.gn, ual, val, wal, s, nullptr,
                                 p.bytes_partial ? part : nullptr, p.bytes_partial)))
     return rc;
   if ((rc = do_unalign(ctx, p, wal, s, true, chg[2]))) return rc;

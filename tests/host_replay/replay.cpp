@@ -260,7 +260,11 @@ void check_transforms(const Plan& p) {
           x.vec = 1;     // operands that are not 16-byte aligned
         }
         const int64_t nsl = slice_only ? p.nq : G;
-        const int64_t al_n = nsl * per_slice;
+        // the contraction's split-bf16 planes hold K at pitch kpad (pad unwritten)
+        const bool kpad = slice_only && kind == 2 && op < 2 && p.kpad != p.gk;
+        const int64_t slice_n = kpad ? (op == 0 ? p.M * p.kpad : p.kpad * p.gn) : per_slice;
+        const int64_t al_n = nsl * slice_n;
+        CHECK(x.plane == al_n || !split, "hi-to-lo plane distance", x.plane, al_n);
         if (to_al) {
           std::vector<uint8_t> written(static_cast<size_t>(al_n) * (split ? 2 : 1), 0);
           std::vector<uint8_t> read(static_cast<size_t>(reals), 0);
@@ -275,7 +279,7 @@ void check_transforms(const Plan& p) {
           }
           if (p.cplx && op == 1) replay_cplx_rows(p, nsl, al_n, written, lo, hi);
           for (int64_t d = 0; d < al_n; ++d) {
-            const uint8_t want = d >= lo && d < hi ? 1 : 0;
+            const uint8_t want = d >= lo && d < hi && !(kpad && d % p.kpad >= p.gk) ? 1 : 0;
             CHECK(written[d] == want, "aligned element not written exactly once", d, written[d]);
             if (split) CHECK(written[d + al_n] == want, "lo plane element not written exactly once", d, written[d + al_n]);
           }

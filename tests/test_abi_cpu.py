@@ -196,7 +196,8 @@ def test_workspace_sizes_per_compute_mode():
     # three steps: U_al | V_al | W_al
     assert sizes["f64", True] == r(8 * eu) + r(8 * ev) + r(8 * ew)
     assert sizes["f32", True] == r(4 * eu) + r(4 * ev) + r(4 * ew)
-    assert sizes["bf16x3", True] == r(4 * eu) + r(4 * ev) + r(8 * ew)
+    # split-bf16 planes hold K (36 per Q here) at a pitch rounded up to 8: 40
+    assert sizes["bf16x3", True] == r(4 * 4 * 36 * 40) + r(4 * 4 * 40 * 16) + r(8 * ew)
     # fused (the contracted block of 9 is stepped on its own; U and V read in place):
     # V_al, then row and column tables of U, W and V (M = K = 36, N = 16 per Q)
     tables = lambda rows, cols: r(8 * 4 * rows) + r(8 * 4 * cols)  # noqa: E731
@@ -221,7 +222,8 @@ def test_workspace_sizes_per_compute_mode():
     v4 = _desc("++--", 0, (3, 3, 4, 4))
     info = _plan("abcd,cdij->abij", 4, u, v4, compute=L.COMPUTE["bf16x3"])[1]
     assert info.fused == 0 and info.fused_w == 1
-    assert info.workspace_bytes == r(4 * eu) + r(4 * 4 ** 3 * 144) + tables(36, 36) + tables(36, 64)
+    # (planes at K pitch 40: U 36 x 40, V 64 x 40 per Q)
+    assert info.workspace_bytes == r(4 * 4 * 36 * 40) + r(4 * 4 * 64 * 40) + tables(36, 36) + tables(36, 64)
 
 
 def test_status_strings():

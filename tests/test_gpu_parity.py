@@ -275,8 +275,6 @@ def test_contract_random_vs_oracle(P, case):
         vv = _sym_tensor(P, Rv, sv)
         for compute in ("f64", "f32", "bf16x3"):
             info = P.plan(sub, u, vv, compute)
-            if compute == "bf16x3" and info.k % 8:
-                continue
             w = P.output_like(sub, u, vv)
             P.contract_into(sub, u, vv, w, compute)
             got = H.to_np(w.data)
@@ -1017,8 +1015,6 @@ def test_contract_with_charge_tables_vs_oracle(P, case):
         u, v = _sym_tensor(P, Ru, su), _sym_tensor(P, Rv, sv)
         for compute in ("f64", "f32", "bf16x3"):
             info = P.plan(sub, u, v, compute)
-            if compute == "bf16x3" and info.k % 8:
-                continue
             w = P.output_like(sub, u, v)
             assert w.mode_charges == sw.charges
             P.contract_into(sub, u, v, w, compute)
@@ -1106,8 +1102,6 @@ def test_degenerate_contractions_vs_oracle(P, sub, orders):
         assert P.plan(sub, u, v).flops == O.flop_count(sub, su, sv)
         for compute in ("f64", "f32", "bf16x3"):
             info = P.plan(sub, u, v, compute)
-            if compute == "bf16x3" and info.k % 8:
-                continue
             w = P.output_like(sub, u, v)
             w.data.fill_(7.0)                      # every element must be overwritten
             assert w.signs == sw.sign_string() and w.charge == sw.charge
@@ -1153,8 +1147,6 @@ def test_u1_emulation_vs_dense_u1_einsum(P, sub):
         k = P.plan(sub, u, v).k + int(np.prod([d for m, d in zip(sub.split(",")[0], c["Tu"].shape)
                                                  if m in sub.split(",")[1].split("->")[0]]))
         for compute in ("f64", "f32", "bf16x3"):
-            if compute == "bf16x3" and P.plan(sub, u, v, compute).k % 8:
-                continue
             w = P.output_like(sub, u, v)
             w.data.fill_(7.0)
             P.contract_into(sub, u, v, w, compute)
@@ -1276,8 +1268,6 @@ def test_subgroup_contractions_vs_oracle(P, G, s, t, v):
         assert (info.m, info.k, info.n) == (M, K, N) and (info.fused == 0 or not has_sub)
         dead = H.dead_stored_tuples(sw)
         for compute in ("f64", "f32", "bf16x3"):
-            if compute == "bf16x3" and K % 8:
-                continue
             w = P.output_like(sub, u, v_)
             assert w.sectors == sw.sectors
             w.data.fill_(7.0)

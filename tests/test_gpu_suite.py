@@ -74,8 +74,6 @@ def test_suite_small_vs_oracle(P, SG, label):
         dt = torch.float64 if compute == "f64" else torch.float32
         u, v = _tensor(P, SG, wl, "U", dt), _tensor(P, SG, wl, "V", dt)
         info = P.plan(st.einsum, u, v, compute)
-        if compute == "bf16x3" and info.k % 8:
-            continue
         say(f"suite {label} small {compute}: batch {info.group_size} m {info.m} k {info.k} n {info.n}")
         w = P.output_like(st.einsum, u, v, dtype=torch.float64)
         P.contract_into(st.einsum, u, v, w, compute)
@@ -108,9 +106,6 @@ def _full_sampled_three_precisions(P, SG, wl, label, count, seed_):
         dt = torch.float64 if compute == "f64" else torch.float32
         u, v = _tensor(P, SG, wl, "U", dt), _tensor(P, SG, wl, "V", dt)
         info = P.plan(st.einsum, u, v, compute)
-        if compute == "bf16x3" and info.k % 8:
-            say(f"{label} full {compute}: skipped (contracted extent {info.k} is not a multiple of 8)")
-            continue
         w = P.output_like(st.einsum, u, v, dtype=torch.float64)
         say(f"{label} full {compute}: batch {info.group_size} m {info.m} k {info.k} n {info.n}, "
             f"{info.flops / 1e9:.1f} GFLOP, fused {info.fused}")
@@ -155,8 +150,6 @@ def _check_small(P, SG, wl, label):
         dt = torch.float64 if compute == "f64" else torch.float32
         u, v = _tensor(P, SG, wl, "U", dt), _tensor(P, SG, wl, "V", dt)
         info = P.plan(st.einsum, u, v, compute)
-        if compute == "bf16x3" and info.k % 8:
-            continue
         say(f"{label} small {compute}: batch {info.group_size} m {info.m} k {info.k} n {info.n}")
         w = P.output_like(st.einsum, u, v, dtype=torch.float64)
         P.contract_into(st.einsum, u, v, w, compute)
