@@ -57,16 +57,19 @@
  *   accumulation (two accumulators) and a binary64 sum of the two at the end.
  *
  * COMPLEX OPERANDS (Sec. 2.2 allows tensors over C).  u, v and w are all
- * complex (SYMT_C128 / SYMT_C64) or all real, else SYMT_EDTYPE; compute F64
- * or F32 (BF16X3: SYMT_EDTYPE).  The product runs on the real representation
- * of C: with Kd and N the complex extents,
+ * complex (SYMT_C128 / SYMT_C64) or all real, else SYMT_EDTYPE; any compute
+ * mode.  The product runs on the real representation of C: with Kd and N the
+ * complex extents,
  *   U_al  real (|G|, M, 2 Kd): the (re, im) pair of column k at 2k, 2k + 1;
  *   V_al  real (|G|, 2 Kd, 2 N): row 2k holds (re, im) of V's row k, row
- *         2k + 1 holds (-im, re), pairs at columns 2n, 2n + 1;
+ *         2k + 1 holds (-im, re), pairs at columns 2n, 2n + 1 (BF16X3: the
+ *         hi and lo planes of the same real matrix stored (|G|, 2 N, 2 Kd),
+ *         the split of -im being minus the split of im);
  *   W_al  real (|G|, M, 2 N): (re, im) of W's column n at 2n, 2n + 1;
  * so the real product U_al V_al is the complex one.  symt_plan_info reports
  * this real product (k = 2 Kd, n = 2 N, flops = 8 |G| M Kd N).  The fused
- * product (below) reads u's and writes w's (re, im) pairs as reals.
+ * product (below) reads u's and writes w's (re, im) pairs as reals (F64 and
+ * F32; BF16X3 runs complex contractions in three steps).
  *
  * EMPTY MODE GROUPS (s, t or v = 0; Sec. 2.1's deltas with an empty sum).  One
  * delta then fixes Q on its own: v = 0 (an outer product) gives Q = 0 and

@@ -253,8 +253,6 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   p->cplx = is_complex(p->U.dtype);
   if (is_complex(p->V.dtype) != p->cplx)
     return fail(err, SYMT_EDTYPE, "u and v must both be complex or both be real");
-  if (p->cplx && compute == SYMT_COMPUTE_BF16X3)
-    return fail(err, SYMT_EDTYPE, "complex operands take compute F64 or F32");
   if ((rc = read_charges(u, p->g, &p->chg[0], "u", err))) return rc;
   if ((rc = read_charges(v, p->g, &p->chg[1], "v", err))) return rc;
   if (p->U.n != static_cast<int>(tu.size()) || p->V.n != static_cast<int>(tv.size()))
@@ -546,7 +544,7 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
                 (!w || p->W.dtype == (p->cplx ? want : w_want) ||
                  (compute == SYMT_COMPUTE_BF16X3 && p->W.dtype == SYMT_F32)) &&
                 p->M > 0 && p->N > 0 && p->Kd > 0 && p->U.elems > 0 &&
-                (compute != SYMT_COMPUTE_BF16X3 || w_run >= 16);
+                (compute != SYMT_COMPUTE_BF16X3 || (w_run >= 16 && !p->cplx));
   if (p->fused || p->fused_ua) {
     const size_t G = static_cast<size_t>(p->g.size);
     p->bytes_tables = round_up(8 * G * p->M, 256) * 2 + round_up(8 * G * p->gk, 256) +

@@ -27,6 +27,8 @@ int launch_put_i32(int32_t* dst, const int32_t* src, int64_t n, hipStream_t stre
 int launch_zero(void* ptr, size_t bytes, hipStream_t stream, std::string* err);
 int launch_cplx_rows(void* v, bool f64, int64_t slices, int64_t rows, int64_t pairs, hipStream_t stream,
                      std::string* err);
+int launch_cplx_rows_planes(void* v, int64_t plane, int64_t slices, int64_t rows, int64_t pairs, int64_t kp,
+                            hipStream_t stream, std::string* err);
 int scratch_setup(int device, std::string* err);
 void* scratch_device_ptr(int device);
 }  // namespace symt
@@ -142,7 +144,10 @@ int do_align(symt_ctx* ctx, const Plan& p, int operand, void* dst, hipStream_t s
     if (r == SYMT_OK && p.cplx && operand == 1) {
       // complex V: the odd real rows of the real representation of C
       const int64_t slices = slice_only ? p.nq : p.g.size;
-      r = symt::launch_cplx_rows(dst, p.compute == SYMT_COMPUTE_F64, slices, p.Kd, p.N, s, &err);
+      if (p.compute == SYMT_COMPUTE_BF16X3)
+        r = symt::launch_cplx_rows_planes(dst, x.plane, slices, p.Kd, p.N, slice_only ? p.kpad : p.gk, s, &err);
+      else
+        r = symt::launch_cplx_rows(dst, p.compute == SYMT_COMPUTE_F64, slices, p.Kd, p.N, s, &err);
     }
     return r;
   });

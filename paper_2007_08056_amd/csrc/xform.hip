@@ -280,6 +280,31 @@ __global__ __launch_bounds__(256) void k_cplx_rows(T* __restrict__ v, int64_t sl
   }
 }
 
+// The same for split-bf16 V planes, stored K fastest ([slice][real column][K
+// pitch kp]): real row 2k + 1 of column pair (2n, 2n + 1) holds (-im, re) of
+// row 2k, in the hi plane at v and the lo plane at v + plane.  Negation only
+// flips the sign bit, so the pair is the split of (-im, re) exactly.
+__global__ __launch_bounds__(256) void k_cplx_rows_planes(uint16_t* __restrict__ v, int64_t plane, int64_t slices,
+                                                          int64_t rows, int64_t pairs, int64_t kp) {
+  const int64_t total = slices * pairs * rows;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int64_t k = i % rows;
+    const int64_t t = i / rows;
+    const int64_t n = t % pairs;
+    const int64_t sl = t / pairs;
+    const int64_t re = (sl * 2 * pairs + 2 * n) * kp + 2 * k;    // (2k, 2n)
+    const int64_t im = re + kp;                                   // (2k, 2n + 1)
+#pragma unroll
+    for (int pl = 0; pl < 2; ++pl) {
+      uint16_t* b = v + pl * plane;
+      const uint16_t r = b[re], m = b[im];
+      b[re + 1] = static_cast<uint16_t>(m ^ 0x8000u);              // (2k + 1, 2n) = -im
+      b[im + 1] = r;                                              // (2k + 1, 2n + 1) = re
+    }
+  }
+}
+
 // A few KB of host data (charge tables) written into device memory from kernel
 // arguments: stream-ordered, with no host buffer that must outlive the call.
 struct I32Chunk {
@@ -319,6 +344,22 @@ int launch_cplx_rows(void* v, bool f64, int64_t slices, int64_t rows, int64_t pa
   else
     hipLaunchKernelGGL(k_cplx_rows<float>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream,
                        static_cast<float*>(v), slices, rows, pairs);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    if (err) *err = std::string("complex rows launch: ") + hipGetErrorString(e);
+    return SYMT_EHIP;
+  }
+  return SYMT_OK;
+}
+
+int launch_cplx_rows_planes(void* v, int64_t plane, int64_t slices, int64_t rows, int64_t pairs, int64_t kp,
+                            hipStream_t stream, std::string* err) {
+  const int64_t total = slices * rows * pairs;
+  if (total == 0) return SYMT_OK;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_cplx_rows_planes, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream,
+                     static_cast<uint16_t*>(v), plane, slices, rows, pairs, kp);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     if (err) *err = std::string("complex rows launch: ") + hipGetErrorString(e);

@@ -217,6 +217,25 @@ void aligned_dims(const Plan& p, int op, int64_t& rows, int64_t& cols) {
 // k_cplx_rows over a complex V_al of `nsl` slices: row 2r + 1 from row 2r.
 // Outside [lo, hi) (slices a standalone transform cleared instead of moving)
 // it rewrites zeros: only its bounds are checked there.
+// Split-bf16 planes (planes: true) store the real V K fastest at pitch kp:
+// k_cplx_rows_planes fills (2k + 1, 2n) and (2k + 1, 2n + 1) of both planes.
+void replay_cplx_rows_planes(const Plan& p, int64_t nsl, int64_t al_n, int64_t kp, std::vector<uint8_t>& written,
+                             int64_t lo, int64_t hi) {
+  const int64_t pairs = p.N;
+  for (int64_t i = 0; i < nsl * pairs * p.Kd; ++i) {
+    const int64_t k = i % p.Kd, t = i / p.Kd, n = t % pairs, sl = t / pairs;
+    const int64_t re = (sl * 2 * pairs + 2 * n) * kp + 2 * k, im = re + kp;
+    CHECK(re >= 0 && im + 1 < al_n, "complex plane row out of bounds", im + 1, al_n);
+    if (re < 0 || im + 1 >= al_n || re < lo || re >= hi) continue;
+    CHECK(written[re] == 1 && written[im] == 1, "complex plane row from an unwritten even row", re, 0);
+    for (int64_t e : {re + 1, im + 1})
+      for (int64_t pl = 0; pl < 2; ++pl) {
+        CHECK(written[e + pl * al_n] == 0, "complex plane row written twice", e, pl);
+        written[e + pl * al_n]++;
+      }
+  }
+}
+
 void replay_cplx_rows(const Plan& p, int64_t nsl, int64_t al_n, std::vector<uint8_t>& written, int64_t lo,
                       int64_t hi) {
   const int64_t pairs = p.N;
@@ -277,7 +296,12 @@ void check_transforms(const Plan& p) {
             lo = static_cast<int64_t>(p.q_pin) * per_slice;
             hi = lo + per_slice;
           }
-          if (p.cplx && op == 1) replay_cplx_rows(p, nsl, al_n, written, lo, hi);
+          if (p.cplx && op == 1) {
+            if (kind == 2)
+              replay_cplx_rows_planes(p, nsl, al_n, kpad ? p.kpad : p.gk, written, lo, hi);
+            else
+              replay_cplx_rows(p, nsl, al_n, written, lo, hi);
+          }
           for (int64_t d = 0; d < al_n; ++d) {
             const uint8_t want = d >= lo && d < hi && !(kpad && d % p.kpad >= p.gk) ? 1 : 0;
             CHECK(written[d] == want, "aligned element not written exactly once", d, written[d]);
@@ -728,7 +752,7 @@ bool random_case(Rng& rng, Case& c, bool allow_tables, bool allow_sub, bool allo
   c.v.dtype = cplx ? (rng.coin() ? SYMT_C128 : SYMT_C64) : (rng.coin() ? SYMT_F64 : SYMT_F32);
   c.u.bind();
   c.v.bind();
-  const int cmp = cplx ? rng.below(2) : rng.below(3);
+  const int cmp = rng.below(3);
   symt_plan_info info;
   std::string err;
   Plan pl;
@@ -745,7 +769,7 @@ bool random_case(Rng& rng, Case& c, bool allow_tables, bool allow_sub, bool allo
     if (sub) c.w.sectors.push_back(hs[m]);
   }
   const int wt = rng.below(3);
-  c.w.dtype = cplx ? (cmp == 0 ? SYMT_C128 : SYMT_C64)
+  c.w.dtype = cplx ? (cmp == 1 ? SYMT_C64 : SYMT_C128)
                    : (wt == 0 ? SYMT_F64 : wt == 1 ? SYMT_F32 : (cmp == 1 ? SYMT_F32 : SYMT_F64));
   c.w.bind();
   c.compute = cmp;

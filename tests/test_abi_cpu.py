@@ -318,9 +318,14 @@ def test_complex_planning():
     assert info.fused == 1          # one contracted mode: a single run of 2 x 5 reals
     rc32, info32 = _plan("ak,kb->ab", G, u, v, compute=1)
     assert rc32 == 0 and info32.bytes_v_al == 4 * G * 10 * 12
-    # all complex or all real; no split-bf16 product for complex operands
+    # all complex or all real; split-bf16 takes complex operands in three steps
+    # (planes K fastest, the K pitch rounded up to 8 in the workspace: 10 -> 16)
     assert _plan("ak,kb->ab", G, u, _desc("+-", 2, (5, 6)))[0] == L.SYMT_EDTYPE
-    assert _plan("ak,kb->ab", G, u, v, compute=2)[0] == L.SYMT_EDTYPE
+    rcb, infob = _plan("ak,kb->ab", G, u, v, compute=2)
+    assert rcb == 0 and infob.fused == 0 and infob.fused_w == 0
+    assert infob.bytes_u_al == 4 * G * 3 * 10 and infob.bytes_v_al == 4 * G * 10 * 12
+    r = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    assert infob.workspace_bytes == r(4 * G * 3 * 16) + r(4 * G * 16 * 12) + r(8 * G * 3 * 12)
     sig = info.w_signs.decode()
     assert _plan("ak,kb->ab", G, u, v, _desc(sig, info.w_charge, (3, 6), L.SYMT_C128))[0] == 0
     assert _plan("ak,kb->ab", G, u, v, _desc(sig, info.w_charge, (3, 6)))[0] == L.SYMT_EDTYPE

@@ -1185,19 +1185,18 @@ def test_complex_contractions_vs_oracle(P, orders, s, t, v):
         info = P.plan(sub, u, v_)
         assert info.flops == 4 * O.flop_count(sub, su, sv)      # 8 real flops per complex multiply-add
         k = info.k                                              # real terms per output component
-        for compute in ("f64", "f32"):
+        for compute in ("f64", "f32", "bf16x3"):
             w = P.output_like(sub, u, v_)
             assert w.data.dtype == torch.complex128
             w.data.fill_(7.0 + 7.0j)
             P.contract_into(sub, u, v_, w, compute)
             got = H.to_np(w.data)
-            # each component is a real sum of 2 K terms bounded by |u||v| (Cauchy-Schwarz)
+            # each component is a real sum of 2 K terms bounded by |u||v| (Cauchy-Schwarz);
+            # split-bf16 and f32 round the inputs to binary32 first
             for part in (np.real, np.imag):
                 assert np.all(np.abs(part(got) - part(ref)) <= H.bound_factor(compute, k) * absref + 1e-300), compute
             if compute == "f64":
                 assert H.rel_err(got, ref) <= 1e-12 or np.max(np.abs(ref)) == 0
-        with pytest.raises(Exception):
-            P.contract_into(sub, u, v_, P.output_like(sub, u, v_), "bf16x3")
         if not with_tables:
             Ual, Val = O.align_u(sub, Ru, su, sv), O.align_v(sub, Rv, su, sv)
             bu = torch.full((Ual.shape[0], Ual.shape[1], 2 * Ual.shape[2]), float("nan"), dtype=torch.float64, device=DEV)
@@ -1214,6 +1213,33 @@ def test_complex_contractions_vs_oracle(P, orders, s, t, v):
             w.data.fill_(3.0)
             P.unalign(sub, u, v_, w, torch.from_numpy(np.ascontiguousarray(Wal).view(np.float64)).to(DEV), "f64")
             assert np.array_equal(H.to_np(w.data), ref_w)
+
+
+def test_complex_split_bf16_on_global_to_lds_tiles(P):
+    """Complex operands under split-bf16 at a size that takes the global-to-LDS
+    tiles (M >= 256, N >= 512 reals) with a contracted extent that is not a
+    multiple of 8 (77 complex = 154 reals, padded to 160): within the product's
+    bound of the oracle, componentwise."""
+    rng = np.random.default_rng(seed(("cplx-bf16", 77)))
+    g = O.Group((4,))
+    sub = "ak,kb->ab"
+    su, sv = O.Sym.make("+-", 1, (300, 77), g), O.Sym.make("++", 3, (77, 300), g)
+    Ru, Rv = _cplx(rng, su.reduced_shape()), _cplx(rng, sv.reduced_shape())
+    u, v = _sym_tensor(P, Ru, su, torch.complex128), _sym_tensor(P, Rv, sv, torch.complex128)
+    info = P.plan(sub, u, v, "bf16x3")
+    assert (info.m, info.k, info.n) == (300, 154, 600) and info.fused == 0
+    say("complex split-bf16 ak,kb->ab G=4 (300 x 77 x 300)")
+    w = P.output_like(sub, u, v)
+    w.data.fill_(7.0 + 7.0j)
+    P.contract_into(sub, u, v, w, "bf16x3")
+    got = H.to_np(w.data)
+    # the oracle on binary32-rounded inputs (the split starts from binary32)
+    R32u = Ru.real.astype(np.float32) + 1j * Ru.imag.astype(np.float32)
+    R32v = Rv.real.astype(np.float32) + 1j * Rv.imag.astype(np.float32)
+    ref, _ = O.contract_blocks(sub, R32u.astype(np.complex128), su, R32v.astype(np.complex128), sv)
+    absref, _ = O.contract_blocks(sub, np.abs(Ru), su, np.abs(Rv), sv)
+    for part in (np.real, np.imag):
+        assert np.all(np.abs(part(got) - part(ref)) <= H.bound_factor("bf16x3", info.k) * absref + 1e-300)
 
 
 @pytest.mark.parametrize("orders,s,t,v", [((3,), 1, 1, 1), ((2, 2), 2, 1, 1), ((4,), 1, 1, 0)])
