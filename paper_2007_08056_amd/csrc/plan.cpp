@@ -968,6 +968,37 @@ XformParams make_xform(const Plan& p, int operand, bool to_aligned, int in_bytes
   }
   if (run < 0 && a == b) run = a;
   x.mode = run >= 0 ? 0 : 1;
+  x.tr_write = 0;
+  if (run >= 0 && md > 1 && msize[run] < 16) {
+    // A short common run (under 16 elements): the tiled transpose with its A side
+    // (source-fastest dims, 64 elements) written in destination order moves
+    // longer contiguous pieces where the A side nests in the destination too
+    // (a source [A][S][B] into a destination [S][A][B]: runs of A x B, not B).
+    int by2[kMaxDims];
+    for (int d = 0; d < md; ++d) by2[d] = d;
+    std::sort(by2, by2 + md, [&](int l, int r) { return ss[l] < ss[r]; });
+    int64_t rng[kMaxDims] = {}, pa = 1;
+    int na = 0;
+    for (int i = 0; i < md && pa < 64; ++i) {
+      const int d = by2[i];
+      rng[d] = std::min<int64_t>(msize[d], (64 + pa - 1) / pa);
+      pa *= msize[d];
+      ++na;
+    }
+    std::sort(by2, by2 + md, [&](int l, int r) { return ds[l] < ds[r]; });
+    int64_t wrun = 1;
+    for (int i = 0; i < md; ++i) {
+      const int d = by2[i];
+      if (rng[d] == 0 || ds[d] != wrun) break;
+      wrun *= rng[d];
+      if (rng[d] < msize[d]) break;
+    }
+    if (na < md && wrun >= 16 && wrun >= 2 * msize[run]) {
+      x.mode = 1;
+      x.tr_write = 1;
+      run = -1;
+    }
+  }
   bool in_tile[kMaxDims] = {};
   x.na = x.nb = 0;
   x.run = run;

@@ -84,6 +84,9 @@ struct XformParams {
   int32_t lanes_log2;
   int32_t vec;                      // elements per thread access along the run (1, 2, 4)
   int32_t tiles_run, tiles_t;       // transpose: tiles along run and tdim
+  int32_t tr_write;                 // transpose: lanes write the tile's A side in
+                                    // destination order (A holds the destination's
+                                    // fastest dims; B's are strided)
   const int32_t* chg;               // device charge tables of the operand, or nullptr (identity)
 };
 

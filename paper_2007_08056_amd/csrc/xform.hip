@@ -172,6 +172,7 @@ __global__ __launch_bounds__(256) void k_xform_transpose(const Tin* __restrict__
                                                          const XformParams p) {
   __shared__ double tile[64][65];
   __shared__ int64_t a_src[64], a_dst[64], b_src[64], b_dst[64];
+  __shared__ int perm[64];                        // tr_write: A elements in destination order
   const int64_t wg = blockIdx.x;
   const int64_t blk = wg / p.tiles_per_block;
   int64_t rem = wg - blk * p.tiles_per_block;
@@ -204,6 +205,12 @@ __global__ __launch_bounds__(256) void k_xform_transpose(const Tin* __restrict__
   __syncthreads();
   const int x = t & 63;
   const int y = t >> 6;
+  if (p.tr_write && t < na) {
+    // rank of this A element by destination offset (ties by index): a permutation
+    int rk = 0;
+    for (int u = 0; u < na; ++u) rk += a_dst[u] < a_dst[t] || (a_dst[u] == a_dst[t] && u < t);
+    perm[rk] = t;
+  }
   if (x < na) {
     // all sixteen of this thread's loads go out before the first LDS write
     const int64_t sx = so + a_src[x];
@@ -218,7 +225,17 @@ __global__ __launch_bounds__(256) void k_xform_transpose(const Tin* __restrict__
       if (y + 4 * k < nb) tile[y + 4 * k][x] = v[k];
   }
   __syncthreads();
-  if (x < nb) {
+  if (p.tr_write) {
+    // lanes along the A side in destination order, B rows in turn
+    if (x < na) {
+      const int ae = perm[x];
+      const int64_t da = dof + a_dst[ae];
+      for (int j = y; j < nb; j += 4) {
+        double v[1] = {tile[j][ae]};
+        store_vec<OUT, 1>(dst, da + b_dst[j], p.plane, v);
+      }
+    }
+  } else if (x < nb) {
     const int64_t dx = dof + b_dst[x];
     for (int j = y; j < na; j += 4) {
       double v[1] = {tile[x][j]};

@@ -192,6 +192,22 @@ void replay_xform(const XformParams& x, int64_t src_n, int64_t dst_n, bool dst_s
           d += c * ds[k];
         }
       };
+      if (x.tr_write) {
+        // the kernel ranks the A elements by destination offset: a permutation
+        std::vector<int64_t> adst(static_cast<size_t>(na));
+        for (int ia = 0; ia < na; ++ia) {
+          int64_t as;
+          offs(a0 + ia, x.na, x.asize, x.ass, x.ads, as, adst[ia]);
+        }
+        std::vector<int> seen(static_cast<size_t>(na), 0);
+        for (int t = 0; t < na; ++t) {
+          int rk = 0;
+          for (int u = 0; u < na; ++u) rk += adst[u] < adst[t] || (adst[u] == adst[t] && u < t);
+          CHECK(rk >= 0 && rk < na, "transpose write rank out of range", rk, na);
+          if (rk >= 0 && rk < na) seen[rk]++;
+        }
+        for (int r = 0; r < na; ++r) CHECK(seen[r] == 1, "transpose write ranks not a permutation", r, seen[r]);
+      }
       for (int ia = 0; ia < na; ++ia) {
         int64_t as, ad;
         offs(a0 + ia, x.na, x.asize, x.ass, x.ads, as, ad);
