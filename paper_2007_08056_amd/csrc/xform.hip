@@ -65,11 +65,13 @@ __global__ __launch_bounds__(256) void k_xform_copy(const Tin* __restrict__ src,
   constexpr int kRows = 1024;                    // rows whose offsets sit in LDS at once
   __shared__ int64_t soff[kRows];
   __shared__ int64_t doff[kRows];
-  const int64_t wg = blockIdx.x;
-  const int64_t blk = wg / p.tiles_per_block;
-  const int64_t tile = wg - blk * p.tiles_per_block;
-  const int64_t row_tile = tile / p.run_tiles;
-  const int64_t c_begin = (tile - row_tile * p.run_tiles) * p.run_chunk;
+  // (the launch has at most 2^31 - 1 workgroups: 32-bit workgroup arithmetic)
+  const int wg = static_cast<int>(blockIdx.x);
+  const int tpb = static_cast<int>(p.tiles_per_block), rt = static_cast<int>(p.run_tiles);
+  const int blk = wg / tpb;
+  const int tile = wg - blk * tpb;
+  const int row_tile = tile / rt;
+  const int64_t c_begin = static_cast<int64_t>(tile - row_tile * rt) * p.run_chunk;
   const int64_t c_end = c_begin + p.run_chunk < p.run_len ? c_begin + p.run_chunk : p.run_len;
   int64_t sb, ab;
   // a block that does not exist (subgroup modes): its aligned block is zero,
@@ -89,14 +91,9 @@ __global__ __launch_bounds__(256) void k_xform_copy(const Tin* __restrict__ src,
   const int nr = static_cast<int>(r_end - r0 < kRows ? r_end - r0 : kRows);
   if (r0 > r_begin) __syncthreads();             // the previous rows' offsets are no longer read
   for (int r = threadIdx.x; r < nr; r += blockDim.x) {
-    int64_t rem = r0 + r, so = 0, dof = 0;
-    for (int i = p.nbatch - 1; i >= 0; --i) {
-      const int64_t qd = rem / p.bsize[i];
-      const int64_t d = rem - qd * p.bsize[i];
-      rem = qd;
-      so += d * p.bss[i];
-      dof += d * p.bds[i];
-    }
+    int64_t so = 0, dof = 0;
+    if (p.rows <= INT32_MAX) batch_offsets<int32_t>(p, static_cast<int32_t>(r0 + r), so, dof);
+    else batch_offsets<int64_t>(p, r0 + r, so, dof);
     soff[r] = src_base + so;
     doff[r] = dst_base + dof;
   }
@@ -152,17 +149,20 @@ __global__ __launch_bounds__(256) void k_xform_copy(const Tin* __restrict__ src,
   }
 }
 
-// Offsets (source, destination) of entry i of a mixed-radix tile index.
-__device__ __forceinline__ void tile_offsets(int64_t i, int n, const int64_t* size, const int64_t* ss,
+// Offsets (source, destination) of entry i of a mixed-radix tile index (I: the
+// index type, 32-bit where the tile's index range fits).
+template <typename I>
+__device__ __forceinline__ void tile_offsets(I i, int n, const int64_t* size, const int64_t* ss,
                                              const int64_t* ds, int64_t& so, int64_t& dof) {
   so = 0;
   dof = 0;
   for (int k = 0; k < n; ++k) {
-    const int64_t q = i / size[k];
-    const int64_t c = i - q * size[k];
+    const I sz = static_cast<I>(size[k]);
+    const I q = i / sz;
+    const I c = i - q * sz;
     i = q;
-    so += c * ss[k];
-    dof += c * ds[k];
+    so += static_cast<int64_t>(c) * ss[k];
+    dof += static_cast<int64_t>(c) * ds[k];
   }
 }
 
@@ -173,34 +173,36 @@ __global__ __launch_bounds__(256) void k_xform_transpose(const Tin* __restrict__
   __shared__ double tile[64][65];
   __shared__ int64_t a_src[64], a_dst[64], b_src[64], b_dst[64];
   __shared__ int perm[64];                        // tr_write: A elements in destination order
-  const int64_t wg = blockIdx.x;
-  const int64_t blk = wg / p.tiles_per_block;
-  int64_t rem = wg - blk * p.tiles_per_block;
-  const int64_t tb = rem % p.tiles_t;
+  // (the launch has at most 2^31 - 1 workgroups: 32-bit workgroup arithmetic)
+  const int wg = static_cast<int>(blockIdx.x);
+  const int tpb = static_cast<int>(p.tiles_per_block);
+  const int blk = wg / tpb;
+  int rem = wg - blk * tpb;
+  const int tb = rem % p.tiles_t;
   rem /= p.tiles_t;
-  const int64_t ta = rem % p.tiles_run;
-  int64_t row = rem / p.tiles_run;
+  const int ta = rem % p.tiles_run;
+  const int row = rem / p.tiles_run;
   int64_t sb, ab;
   const bool live = block_bases(p, blk, sb, ab);
   if (!live && !p.to_aligned) return;             // as in k_xform_copy
   int64_t so = p.to_aligned ? sb : ab;
   int64_t dof = p.to_aligned ? ab : sb;
-  for (int i = p.nbatch - 1; i >= 0; --i) {
-    const int64_t qd = row / p.bsize[i];
-    const int64_t d = row - qd * p.bsize[i];
-    row = qd;
-    so += d * p.bss[i];
-    dof += d * p.bds[i];
-  }
-  const int64_t a0 = ta * 64, b0 = tb * 64;
+  batch_offsets<int32_t>(p, row, so, dof);
+  const int64_t a0 = static_cast<int64_t>(ta) * 64, b0 = static_cast<int64_t>(tb) * 64;
   const int na = static_cast<int>(p.run_len - a0 < 64 ? p.run_len - a0 : 64);
   const int nb = static_cast<int>(p.t_len - b0 < 64 ? p.t_len - b0 : 64);
   const int t = threadIdx.x;
   if (t < 64) {
-    if (t < na) tile_offsets(a0 + t, p.na, p.asize, p.ass, p.ads, a_src[t], a_dst[t]);
+    if (t < na) {
+      if (p.run_len <= INT32_MAX) tile_offsets<int32_t>(static_cast<int32_t>(a0 + t), p.na, p.asize, p.ass, p.ads, a_src[t], a_dst[t]);
+      else tile_offsets<int64_t>(a0 + t, p.na, p.asize, p.ass, p.ads, a_src[t], a_dst[t]);
+    }
   } else if (t < 128) {
     const int u = t - 64;
-    if (u < nb) tile_offsets(b0 + u, p.nb, p.tsize, p.tss, p.tds, b_src[u], b_dst[u]);
+    if (u < nb) {
+      if (p.t_len <= INT32_MAX) tile_offsets<int32_t>(static_cast<int32_t>(b0 + u), p.nb, p.tsize, p.tss, p.tds, b_src[u], b_dst[u]);
+      else tile_offsets<int64_t>(b0 + u, p.nb, p.tsize, p.tss, p.tds, b_src[u], b_dst[u]);
+    }
   }
   __syncthreads();
   const int x = t & 63;

@@ -86,14 +86,17 @@ __host__ __device__ inline bool fill_sectors(const GroupDesc& g, const SectorGro
 
 // Aligned block index -> (standard-form element offset, aligned element
 // offset); false when the block does not exist (its aligned block is zero).
-__host__ __device__ inline bool block_bases(const XformParams& p, int64_t blk, int64_t& std_base,
-                                            int64_t& al_base) {
-  const int64_t cs = blk % p.gpow_col;
-  const int64_t t = blk / p.gpow_col;
-  const int64_t rs = t % p.gpow_row;
-  const int64_t slice = t / p.gpow_row;
+// (I: the index type of the block arithmetic, 32-bit where the block count fits)
+template <typename I>
+__host__ __device__ inline bool block_bases_t(const XformParams& p, I blk, int64_t& std_base, int64_t& al_base) {
+  const I gc = static_cast<I>(p.gpow_col), gr = static_cast<I>(p.gpow_row);
+  const I cs = blk % gc;
+  const I t = blk / gc;
+  const I rs = t % gr;
+  const I slice = t / gr;
   const int q = p.q0 + p.q_step * static_cast<int>(slice);
-  al_base = (p.q_full ? q : slice) * p.q_stride + rs * p.rs_stride + cs * p.cs_stride;
+  al_base = static_cast<int64_t>(p.q_full ? q : slice) * p.q_stride + static_cast<int64_t>(rs) * p.rs_stride +
+            static_cast<int64_t>(cs) * p.cs_stride;
   int S[kMaxOrder];
   std_base = 0;
   if (!fill_sectors(p.g, p.row, rs, q, S, p.chg) || !fill_sectors(p.g, p.col, cs, q, S, p.chg)) return false;
@@ -101,6 +104,25 @@ __host__ __device__ inline bool block_bases(const XformParams& p, int64_t blk, i
   for (int m = 0; m < p.order - 1; ++m) sb = sb * p.hs[m] + S[m];
   std_base = sb * p.blk_elems;
   return true;
+}
+__host__ __device__ inline bool block_bases(const XformParams& p, int64_t blk, int64_t& std_base,
+                                            int64_t& al_base) {
+  if (p.nblocks <= INT32_MAX) return block_bases_t<int32_t>(p, static_cast<int32_t>(blk), std_base, al_base);
+  return block_bases_t<int64_t>(p, blk, std_base, al_base);
+}
+
+// Source and destination offsets of batch row `row` (mixed radix over the batch
+// dims, the last one fastest), added to so / dof.
+template <typename I>
+__host__ __device__ inline void batch_offsets(const XformParams& p, I row, int64_t& so, int64_t& dof) {
+  for (int i = p.nbatch - 1; i >= 0; --i) {
+    const I b = static_cast<I>(p.bsize[i]);
+    const I qd = row / b;
+    const I d = row - qd * b;
+    row = qd;
+    so += static_cast<int64_t>(d) * p.bss[i];
+    dof += static_cast<int64_t>(d) * p.bds[i];
+  }
 }
 
 // Entry i of an offset table for auxiliary sector q: the group's stored sectors
