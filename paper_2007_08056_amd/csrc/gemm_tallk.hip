@@ -50,14 +50,22 @@ constexpr int kTkGroup = 16;     // K indices per group (four MFMA K-steps)
 
 // TM, TN: 16-row / 16-column tiles of the output (M <= 16 TM, N <= 16 TN).
 // kc: K indices per workgroup (a multiple of kTkGroup); gridDim.x ranges per Q.
-template <typename T, int TM, int TN>
+// KL (A's K index contiguous in runs of 16 or more): each lane loads A along K
+// (a group's 16 K indices of one row are one 128-byte line, 4 rows per load)
+// into a per-wave LDS slab, and the MFMA operands are read back from it;
+// otherwise lanes load A in the MFMA operand layout (16 rows x 4 K indices).
+template <typename T, int TM, int TN, bool KL>
 __global__ __launch_bounds__(64 * kTkWaves) void k_gemm_tallk(
     const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ part, int M, int N, int K, int kc,
     const int64_t* __restrict__ ra, const int64_t* __restrict__ ca, const int64_t* __restrict__ rb,
     const int64_t* __restrict__ cb) {
   using Acc = typename TkMfma<T>::Acc;
   constexpr int MP = 16 * TM, NP = 16 * TN;
+  constexpr int LDA = kTkGroup + 1;               // slab row pitch (odd: no bank conflicts)
+  constexpr int AL = KL ? 4 * TM : 1;             // A values per lane per group (K lanes)
+  constexpr int AM = KL ? 1 : TM;                 // A operand registers kept across groups
   __shared__ T red[MP * NP];
+  __shared__ T slab[KL ? kTkWaves : 1][KL ? MP * LDA : 1];
   const int64_t q = blockIdx.y;
   const int x = blockIdx.x;
   const int lane = threadIdx.x & 63;
@@ -68,10 +76,12 @@ __global__ __launch_bounds__(64 * kTkWaves) void k_gemm_tallk(
 
   // this lane's operand rows of A (one per row tile) and columns of B (one per
   // column tile); -1 past M or N
-  int64_t arow[TM], bcol[TN];
+  // (K lanes: rows (lane >> 4) + 4 j, j < 4 TM)
+  constexpr int NA = KL ? 4 * TM : TM;
+  int64_t arow[NA], bcol[TN];
 #pragma unroll
-  for (int i = 0; i < TM; ++i) {
-    const int m = 16 * i + (lane & 15);
+  for (int i = 0; i < NA; ++i) {
+    const int m = KL ? (lane >> 4) + 4 * i : 16 * i + (lane & 15);
     arow[i] = m < M ? (ra ? ra[q * M + m] : (q * M + m) * static_cast<int64_t>(K)) : -1;
   }
 #pragma unroll
@@ -81,23 +91,36 @@ __global__ __launch_bounds__(64 * kTkWaves) void k_gemm_tallk(
   }
   // table entries of the lane's four K indices of a group: A's column offset and
   // B's row offset (-1 past the range)
+  // (K lanes: ak[0] is A's column offset of the lane's K index g0 + lane % 16)
   auto tables = [&](int g0, int64_t (&ak)[4], int64_t (&bk)[4]) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int k = g0 + 4 * u + kq;
       const bool ok = k < k_end;
-      ak[u] = ok ? (ca ? ca[q * K + k] : static_cast<int64_t>(k)) : -1;
+      if (!KL) ak[u] = ok ? (ca ? ca[q * K + k] : static_cast<int64_t>(k)) : -1;
       bk[u] = ok ? (rb ? rb[q * K + k] : (q * K + k) * static_cast<int64_t>(N)) : -1;
     }
+    if (KL) {
+      const int k = g0 + (lane & 15);
+      ak[0] = k < k_end ? (ca ? ca[q * K + k] : static_cast<int64_t>(k)) : -1;
+    }
   };
-  auto operands = [&](const int64_t (&ak)[4], const int64_t (&bk)[4], T (&a)[4][TM], T (&b)[4][TN]) {
+  // the next group's operands: A (in the MFMA layout, or along K) and B
+  auto operands = [&](const int64_t (&ak)[4], const int64_t (&bk)[4], T (&a)[4][AM], T (&al)[AL],
+                      T (&b)[4][TN]) {
+    if constexpr (KL) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+      for (int i = 0; i < AL; ++i) al[i] = ak[0] >= 0 && arow[i] >= 0 ? A[arow[i] + ak[0]] : T(0);
+    } else {
 #pragma unroll
-      for (int i = 0; i < TM; ++i) a[u][i] = ak[u] >= 0 && arow[i] >= 0 ? A[arow[i] + ak[u]] : T(0);
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int i = 0; i < TM; ++i) a[u][i] = ak[u] >= 0 && arow[i] >= 0 ? A[arow[i] + ak[u]] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int j = 0; j < TN; ++j) b[u][j] = bk[u] >= 0 && bcol[j] >= 0 ? B[bk[u] + bcol[j]] : T(0);
-    }
   };
 
   Acc acc[TM][TN];
@@ -108,30 +131,51 @@ __global__ __launch_bounds__(64 * kTkWaves) void k_gemm_tallk(
   const int gstep = kTkWaves * kTkGroup;
   int g = k_begin + wave * kTkGroup;
   if (g < k_end) {
-    T a[4][TM], b[4][TN], an[4][TM], bn[4][TN];
+    T a[4][AM], b[4][TN], an[4][AM], bn[4][TN], al[AL], aln[AL];
     int64_t ak[4], bk[4], ak2[4], bk2[4];
     tables(g, ak, bk);
-    operands(ak, bk, a, b);
+    operands(ak, bk, a, al, b);
     if (g + gstep < k_end) tables(g + gstep, ak, bk);
     for (; g < k_end; g += gstep) {
       const bool more = g + gstep < k_end;
       if (g + 2 * gstep < k_end) tables(g + 2 * gstep, ak2, bk2);
-      if (more) operands(ak, bk, an, bn);
+      if (more) operands(ak, bk, an, aln, bn);
+      if constexpr (KL) {
+        // this group's A through the wave's slab into the MFMA layout
+        T* sl = slab[wave];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+        for (int i = 0; i < AL; ++i) sl[((lane >> 4) + 4 * i) * LDA + (lane & 15)] = al[i];
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-          for (int j = 0; j < TN; ++j) acc[i][j] = TkMfma<T>::run(a[u][i], b[u][j], acc[i][j]);
+          for (int i = 0; i < TM; ++i) {
+            const T av = sl[(16 * i + (lane & 15)) * LDA + 4 * u + kq];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = TkMfma<T>::run(av, b[u][j], acc[i][j]);
+          }
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = TkMfma<T>::run(a[u][i], b[u][j], acc[i][j]);
+      }
       if (more) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
+          if constexpr (!KL) {
 #pragma unroll
-          for (int i = 0; i < TM; ++i) a[u][i] = an[u][i];
+            for (int i = 0; i < TM; ++i) a[u][i] = an[u][i];
+          }
 #pragma unroll
           for (int j = 0; j < TN; ++j) b[u][j] = bn[u][j];
           ak[u] = ak2[u];
           bk[u] = bk2[u];
+        }
+        if constexpr (KL) {
+#pragma unroll
+          for (int i = 0; i < AL; ++i) al[i] = aln[i];
         }
       }
     }
@@ -180,14 +224,22 @@ __global__ __launch_bounds__(256) void k_tallk_sum(const T* __restrict__ part, T
 template <typename T, int TM, int TN>
 hipError_t launch_mn(int64_t batch, int M, int N, int K, const T* A, const T* B, T* C, hipStream_t s,
                      const FusedTables* f, T* part, int ranges, int kc) {
+  // A's K index contiguous (the aligned form, or a hint from the plan): loads
+  // along K, binary32 only (binary64 would hold one wave per SIMD: 263 registers)
+  const bool kl = sizeof(T) == 4 && (!f || !f->ra || f->a_klanes);
   const int64_t* ra = f ? f->ra : nullptr;
   const int64_t* ca = f ? f->ca : nullptr;
   const int64_t* rb = f ? f->rb : nullptr;
   const int64_t* cb = f ? f->cb : nullptr;
   const int64_t* rc = f ? f->rc : nullptr;
   const int64_t* cc = f ? f->cc : nullptr;
-  hipLaunchKernelGGL((k_gemm_tallk<T, TM, TN>), dim3(static_cast<unsigned>(ranges), static_cast<unsigned>(batch)),
-                     dim3(64 * kTkWaves), 0, s, A, B, part, M, N, K, kc, ra, ca, rb, cb);
+  const dim3 grid(static_cast<unsigned>(ranges), static_cast<unsigned>(batch));
+  if (kl)
+    hipLaunchKernelGGL((k_gemm_tallk<T, TM, TN, true>), grid, dim3(64 * kTkWaves), 0, s, A, B, part, M, N, K, kc,
+                       ra, ca, rb, cb);
+  else
+    hipLaunchKernelGGL((k_gemm_tallk<T, TM, TN, false>), grid, dim3(64 * kTkWaves), 0, s, A, B, part, M, N, K,
+                       kc, ra, ca, rb, cb);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_tallk_sum<T>), dim3(static_cast<unsigned>((M * N + 255) / 256), static_cast<unsigned>(batch)),

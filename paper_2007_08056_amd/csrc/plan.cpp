@@ -476,6 +476,14 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
                            : (compute == SYMT_COMPUTE_F64 ? SYMT_F64 : SYMT_F32);
   bool trailing_k = true;
   for (int i = 0; i < p->v; ++i) trailing_k = trailing_k && p->posK_u[i] == p->U.n - p->v + i;
+  {
+    // U's contracted modes from its fastest one down, while they nest (a contiguous K run)
+    int64_t st[kMaxOrder];
+    int64_t a = 1;
+    for (int m = p->U.n - 1; m >= 0; --m) { st[m] = a; a *= p->U.dims[m]; }
+    p->u_k_run = 1;
+    for (int i = p->v - 1; i >= 0 && st[p->posK_u[i]] == p->u_k_run; --i) p->u_k_run *= p->U.dims[p->posK_u[i]];
+  }
   // A single run (one contracted mode, or every contracted sector fixed) holds
   // any K-step; the product masks the steps past its end.
   const int64_t run = (p->cplx ? 2 : 1) * p->nK;

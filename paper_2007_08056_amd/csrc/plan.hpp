@@ -143,6 +143,7 @@ struct FusedTables {
   int32_t c_bytes = 8;              // split-bf16 products: W's element size (8 binary64, 4 binary32)
   int32_t at = 0;                   // 1: A loaded K-major from U (register tiles)
   int32_t c_trans = 0;              // 1: W's rows are its contiguous index (row-streaming product)
+  int32_t a_klanes = 0;             // 1: U's K index runs contiguous for 16 or more (long-K product)
 };
 
 struct OperandDesc {
@@ -197,6 +198,7 @@ struct Plan {
   // W's contiguous runs at its end: of its output modes from V (columns of the
   // product) and of those from U (rows); one of them is 1
   int64_t w_col_run = 1, w_row_run = 1;
+  int64_t u_k_run = 1;              // U's contiguous run of its contracted index (in elements)
   // fused with K runs that do not hold whole K-steps: the register tiles step each
   // run on its own (krun = the run length; 0 = plain K-steps)
   int32_t krun = 0;

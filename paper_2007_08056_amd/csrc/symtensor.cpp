@@ -331,6 +331,9 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
   // W written in place with its rows contiguous (and not its columns): the
   // row-streaming product stores lanes along rows
   f.c_trans = !p.cplx && p.w_row_run >= 16 && p.w_col_run < 8 ? 1 : 0;
+  // U's K index contiguous (U_al, or runs of 16 and more in U): the long-K
+  // product loads A along K
+  f.a_klanes = p.fused_ua || p.u_k_run >= 16 ? 1 : 0;
   if (fb) {
     f.rb = rb;
     f.cb = cb;

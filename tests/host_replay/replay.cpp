@@ -455,6 +455,18 @@ void replay_tallk(int64_t batch, int64_t M, int64_t N, int64_t K, const std::vec
                 const int64_t a = (ra.empty() ? (q * M + m) * K : ra[q * M + m]) + ak;
                 CHECK(a >= 0 && a < a_n, "long-K A read out of bounds", a, a_n);
               }
+              // A along K (rows (lane / 16) + 4 j, K index g + lane % 16), once per group
+              if (u == 0) {
+                const int64_t kk = g + (lane & 15);
+                if (kk < k_end)
+                  for (int64_t j = 0; j < 4 * tm; ++j) {
+                    const int64_t m = (lane >> 4) + 4 * j;
+                    if (m >= M) continue;
+                    const int64_t a = (ra.empty() ? (q * M + m) * K : ra[q * M + m]) + (ca.empty() ? kk : ca[q * K + kk]);
+                    CHECK(a >= 0 && a < a_n, "long-K A read along K out of bounds", a, a_n);
+                    CHECK(m < 16 * tm, "long-K slab row past the tile", m, 16 * tm);
+                  }
+              }
               for (int64_t j = 0; j < tn; ++j) {
                 const int64_t n = 16 * j + (lane & 15);
                 if (n >= N) continue;
