@@ -92,7 +92,8 @@
  * sector group).  symtensor_contract uses this when compute is F64 or F32, u is
  * stored in the compute type (complex: its complex counterpart), w too, no mode
  * is a subgroup mode, every Q slice is live and u's last v modes are exactly its
- * contracted modes (or see K-major A below).  It builds the offset tables of U and W in the workspace
+ * contracted modes (or see K-major A below).  It builds the offset tables of U and W (once per
+ * cached plan, on the context; see Execution and ownership; else in the workspace)
  * and runs one product that reads A straight from u's standard form and writes
  * C straight into w's, so U_al and W_al are never materialised
  * (info.fused = 1).  A K run (u's contracted block, in reals) that holds whole
