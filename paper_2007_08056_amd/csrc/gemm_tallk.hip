@@ -12,7 +12,9 @@
 // M x N output over its groups; the four waves are summed in LDS in wave order
 // and the workgroup's partial goes to `part`.  k_tallk_sum then adds the
 // partials of each output element in range order and writes C, so the result
-// does not depend on scheduling.  v_mfma_f64_16x16x4_f64 / v_mfma_f32_16x16x4_f32.
+// does not depend on scheduling.  Where the operands hold whole 16-deep groups
+// (k_gemm_tallk_dma below) the groups stream through LDS instead, in the same
+// order.  v_mfma_f64_16x16x4_f64 / v_mfma_f32_16x16x4_f32.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -202,6 +204,186 @@ __global__ __launch_bounds__(64 * kTkWaves) void k_gemm_tallk(
   }
 }
 
+// Global-to-LDS variant, where every 16-deep group of K lies in one contiguous
+// run of A's rows and one affine run of B's rows, and B's columns come in whole
+// 16-byte chunks: each wave streams its own groups (the same groups, in the same
+// order, as above, so both variants give the same bits) through a private
+// S-stage LDS ring with global_load_lds_dwordx4 (A: the group's 16 K values of
+// each row, 128 or 64 bytes; B: the group's 16 rows in 16-byte chunks), so a
+// group costs no staging registers and S - 1 groups stay in flight per wave.
+// The waves never wait on each other until the final sum.
+// LDS slots: A (r, p) holds chunk p ^ tk_aswz(r) of row r, B (k, p) holds chunk
+// p ^ tk_bswz(k); with these the MFMA operand reads hit distinct banks.  Rows
+// past M and chunks past N are clamped on load and never stored.
+template <typename T>
+__device__ __forceinline__ int tk_aswz(int r) {
+  if constexpr (sizeof(T) == 8) return (r >> 1) & 7;     // 8 chunks per 128-byte row
+  else return (r >> 2) & 3;                              // 4 chunks per 64-byte row
+}
+template <typename T, int NP>
+__device__ __forceinline__ int tk_bswz(int k) {
+  constexpr int row_bytes = NP * static_cast<int>(sizeof(T));
+  if constexpr (sizeof(T) == 8) return row_bytes % 256 == 0 ? (k & 1) << 3 : 0;
+  else if constexpr (row_bytes % 256 == 0) return (k & 3) << 2;
+  else if constexpr (row_bytes % 256 == 128) return ((k >> 1) & 1) << 2;
+  else return 0;
+}
+
+template <typename T, int TM, int TN>
+struct TkDma {
+  static constexpr int E = static_cast<int>(sizeof(T));
+  static constexpr int VE = 16 / E;                        // elements per 16-byte chunk
+  static constexpr int GK = kTkGroup;                      // K indices per group
+  static constexpr int CPR = GK / VE;                      // A chunks per row and group
+  static constexpr int MP = 16 * TM, NP = 16 * TN;
+  static constexpr int BCH = NP / VE;                      // chunks per B row
+  static constexpr int A_LOADS = MP * CPR / 64, B_LOADS = GK * BCH / 64;
+  static constexpr int LOADS = A_LOADS + B_LOADS;
+  static constexpr int A_BYTES = MP * GK * E;
+  static constexpr int STAGE = A_BYTES + GK * NP * E;
+  static constexpr int LDS = 160 * 1024;
+  static constexpr int S = LDS / (kTkWaves * STAGE) >= 4 ? 4 : LDS / (kTkWaves * STAGE) >= 3 ? 3 : 2;
+  static_assert(A_LOADS * 64 == MP * CPR && B_LOADS * 64 == GK * BCH, "loads must fill whole waves");
+  static_assert(kTkWaves * S * STAGE <= LDS && (S - 1) * LOADS < 64, "ring");
+  static_assert(MP * NP * E <= kTkWaves * S * STAGE, "sum space");
+};
+
+// vmcnt <= n LOADS-sized groups of loads (n < 4)
+template <int LOADS>
+__device__ __forceinline__ void tk_wait_groups(int n) {
+  switch (n) {
+    case 0: wait_vmcnt<0>(); break;
+    case 1: wait_vmcnt<LOADS>(); break;
+    case 2: wait_vmcnt<2 * LOADS < 64 ? 2 * LOADS : 0>(); break;
+    default: wait_vmcnt<3 * LOADS < 64 ? 3 * LOADS : 0>(); break;
+  }
+}
+
+template <typename T, int TM, int TN>
+__global__ __launch_bounds__(64 * kTkWaves) void k_gemm_tallk_dma(
+    const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ part, int M, int N, int K, int kc,
+    const int64_t* __restrict__ ra, const int64_t* __restrict__ ca, const int64_t* __restrict__ rb,
+    const int64_t* __restrict__ cb, int64_t ldb) {
+  using D = TkDma<T, TM, TN>;
+  using Acc = typename TkMfma<T>::Acc;
+  constexpr int VE = D::VE, GK = D::GK, CPR = D::CPR, MP = D::MP, NP = D::NP, BCH = D::BCH, S = D::S;
+  constexpr int A_LOADS = D::A_LOADS, B_LOADS = D::B_LOADS, LOADS = D::LOADS, STAGE = D::STAGE;
+  constexpr int A_BYTES = D::A_BYTES;
+  __shared__ __attribute__((aligned(16))) char smem[kTkWaves * S * STAGE];
+  const int64_t q = blockIdx.y;
+  const int x = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const int k_begin = x * kc;
+  const int k_end = min(K, k_begin + kc);
+  char* ring = smem + wave * S * STAGE;
+
+  // this lane's load sources, fixed across groups: A row base + chunk, B row k of
+  // a group + column chunk
+  int64_t a_src[A_LOADS], b_src[B_LOADS];
+#pragma unroll
+  for (int i = 0; i < A_LOADS; ++i) {
+    const int slot = i * 64 + lane;
+    const int r = slot / CPR, c = (slot % CPR) ^ tk_aswz<T>(r);
+    const int gr = min(r, M - 1);
+    a_src[i] = (ra ? ra[q * M + gr] : (q * M + gr) * static_cast<int64_t>(K)) + c * VE;
+  }
+#pragma unroll
+  for (int i = 0; i < B_LOADS; ++i) {
+    const int slot = i * 64 + lane;
+    const int k = slot / BCH, c = (slot % BCH) ^ tk_bswz<T, NP>(k);
+    const int gn = min(c * VE, N - VE);
+    b_src[i] = k * ldb + (cb ? cb[q * N + gn] : static_cast<int64_t>(gn));
+  }
+  // a group's A column offset and B row offset (wave-uniform)
+  auto acol_of = [&](int g) { return ca ? ca[q * K + g] : static_cast<int64_t>(g); };
+  auto brow_of = [&](int g) { return rb ? rb[q * K + g] : (q * K + g) * static_cast<int64_t>(N); };
+  auto issue = [&](int stage, int64_t acol, int64_t brow) {
+    char* base = ring + stage * STAGE;
+#pragma unroll
+    for (int i = 0; i < A_LOADS; ++i) lds_dma16(A + a_src[i] + acol, base + i * 1024);
+#pragma unroll
+    for (int i = 0; i < B_LOADS; ++i) lds_dma16(B + b_src[i] + brow, base + A_BYTES + i * 1024);
+  };
+
+  Acc acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = Acc{};
+  const int g0 = k_begin + wave * GK;
+  const int gstep = kTkWaves * GK;
+  const int ng = g0 < k_end ? (k_end - g0 + gstep - 1) / gstep : 0;
+#pragma unroll
+  for (int s = 0; s < S - 1; ++s)
+    if (s < ng) issue(s, acol_of(g0 + s * gstep), brow_of(g0 + s * gstep));
+  // table entries of the next group to issue, fetched one iteration ahead
+  int64_t acol_n = 0, brow_n = 0;
+  if (S - 1 < ng) {
+    acol_n = acol_of(g0 + (S - 1) * gstep);
+    brow_n = brow_of(g0 + (S - 1) * gstep);
+  }
+  for (int it = 0; it < ng; ++it) {
+    // the stage refilled next was read by the previous group's operand loads
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0), vmcnt and expcnt untouched
+    const int nxt = it + S - 1;
+    if (nxt < ng) {
+      issue(nxt % S, acol_n, brow_n);
+      if (nxt + 1 < ng) {
+        acol_n = acol_of(g0 + (nxt + 1) * gstep);
+        brow_n = brow_of(g0 + (nxt + 1) * gstep);
+      }
+    }
+    tk_wait_groups<LOADS>(min(ng - 1, nxt) - it);
+    asm volatile("" ::: "memory");        // the operand reads below stay after the wait
+    const char* base = ring + (it % S) * STAGE;
+    const T* As = reinterpret_cast<const T*>(base);
+    const T* Bs = reinterpret_cast<const T*>(base + A_BYTES);
+#pragma unroll
+    for (int kk = 0; kk < GK; kk += 4) {
+      const int k = kk + (lane >> 4);
+      T a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int m = 16 * i + (lane & 15);
+        a[i] = As[m * GK + ((k / VE) ^ tk_aswz<T>(m)) * VE + k % VE];
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int n = 16 * j + (lane & 15);
+        b[j] = Bs[k * NP + ((n / VE) ^ tk_bswz<T, NP>(k)) * VE + n % VE];
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = TkMfma<T>::run(a[i], b[j], acc[i][j]);
+    }
+  }
+  // the four waves' sums in wave order (over the rings, once every wave is done
+  // with its own), then the workgroup's partial [m][n]
+  T* red = reinterpret_cast<T*>(smem);
+  __syncthreads();
+  for (int w = 0; w < kTkWaves; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int e = (16 * i + TkMfma<T>::row(lane, r)) * NP + 16 * j + (lane & 15);
+            red[e] = w == 0 ? acc[i][j][r] : red[e] + acc[i][j][r];
+          }
+    }
+    __syncthreads();
+  }
+  T* pw = part + (q * gridDim.x + x) * static_cast<int64_t>(M) * N;
+  for (int e = static_cast<int>(threadIdx.x); e < M * N; e += 64 * kTkWaves) {
+    const int m = e / N, n = e - (e / N) * N;
+    pw[e] = red[m * NP + n];
+  }
+}
+
 // C = the sum over ranges, in range order, of the partials (one thread per
 // output element; grid (elements / 256, Q)).
 template <typename T>
@@ -234,7 +416,16 @@ hipError_t launch_mn(int64_t batch, int M, int N, int K, const T* A, const T* B,
   const int64_t* rc = f ? f->rc : nullptr;
   const int64_t* cc = f ? f->cc : nullptr;
   const dim3 grid(static_cast<unsigned>(ranges), static_cast<unsigned>(batch));
-  if (kl)
+  // whole 16-deep groups of K in A's runs and B's affine K-steps, 16-byte
+  // chunks of B's columns, 16-byte aligned operands: the global-to-LDS variant
+  constexpr int GK = TkDma<T, TM, TN>::GK, VE = TkDma<T, TM, TN>::VE;
+  const bool dma = K % GK == 0 && N % VE == 0 &&
+                   ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15) == 0 &&
+                   (!f || (!f->ra && !f->rb) || f->k_groups);
+  if (dma) {
+    hipLaunchKernelGGL((k_gemm_tallk_dma<T, TM, TN>), grid, dim3(64 * kTkWaves), 0, s, A, B, part, M, N, K, kc,
+                       ra, ca, rb, cb, f && f->rb ? f->ldb : static_cast<int64_t>(N));
+  } else if (kl)
     hipLaunchKernelGGL((k_gemm_tallk<T, TM, TN, true>), grid, dim3(64 * kTkWaves), 0, s, A, B, part, M, N, K, kc,
                        ra, ca, rb, cb);
   else

@@ -733,6 +733,16 @@ GemmChoice choose_among(int64_t batch, int64_t M, int64_t N, int64_t K, int elem
 }
 }  // namespace
 
+bool tallk_groups(const Plan& p) {
+  if (p.cplx || (p.compute != SYMT_COMPUTE_F64 && p.compute != SYMT_COMPUTE_F32)) return false;
+  const int64_t elem = p.compute == SYMT_COMPUTE_F64 ? 8 : 4;
+  const int64_t group = 16, ve = 16 / elem;
+  // (U's K order ends with its trailing contracted modes: u_k_run of them are contiguous)
+  const bool a_ok = p.fused_ua ? p.kpad % group == 0 : p.fused && p.u_k_run % group == 0;
+  const bool b_ok = p.fused_b ? p.nK % group == 0 && p.fused_b_chunks : p.gn % ve == 0;
+  return a_ok && b_ok;
+}
+
 // SYMT_GEMM_TILE=<name> restricts the choice to one tile (ignored where it does
 // not apply); SYMT_GEMM_SK=0 forbids stream-K and split K, 1 forces stream-K on
 // the DMA tiles.

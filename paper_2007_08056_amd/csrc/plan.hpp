@@ -144,6 +144,8 @@ struct FusedTables {
   int32_t at = 0;                   // 1: A loaded K-major from U (register tiles)
   int32_t c_trans = 0;              // 1: W's rows are its contiguous index (row-streaming product)
   int32_t a_klanes = 0;             // 1: U's K index runs contiguous for 16 or more (long-K product)
+  int32_t k_groups = 0;             // 1: every 16-deep group of K lies in one run of A's rows and one
+                                    //    affine run of B's rows, B's columns in 16-byte chunks (long-K)
 };
 
 struct OperandDesc {
@@ -251,11 +253,12 @@ constexpr int kRowsTile = 64;
 // GemmChoice::tile of the long-K product with M and N at most 64 (GemmChoice::
 // splits = its K ranges per slice, partial_bytes = their partial outputs).
 constexpr int kTallKTile = 65;
-// K ranges per slice of the long-K product (about two workgroups per CU over
-// all slices, at least 256 K indices each) and the K indices of each range (a
+// K ranges per slice of the long-K product (at most two workgroups per CU over
+// all slices, so that whole rounds of one or two resident workgroups per CU
+// cover them; at least 256 K indices each) and the K indices of each range (a
 // multiple of 16, the last range shorter or empty).
 inline int tallk_ranges(int64_t batch, int64_t K) {
-  const int64_t want = (512 + batch - 1) / (batch > 0 ? batch : 1);
+  const int64_t want = 512 / (batch > 0 ? batch : 1);
   const int64_t most = (K + 255) / 256;
   const int64_t r = want < most ? want : most;
   return static_cast<int>(r < 1 ? 1 : r);
@@ -264,6 +267,11 @@ inline int tallk_range(int64_t K, int ranges) {
   const int64_t per = (K + ranges - 1) / ranges;
   return static_cast<int>((per + 15) / 16 * 16);
 }
+// Whether the fused product's operands hold the long-K product's 16-deep groups
+// of K (FusedTables::k_groups): A's K runs (U_al rows, or U's trailing
+// contracted run) and V's contracted runs are whole groups, V's columns whole
+// 16-byte chunks (V in place) or V_al's rows a whole number of chunks.
+bool tallk_groups(const Plan& p);
 // Fewest K-iterations a stream-K workgroup takes on (bounds the pieces per tile).
 constexpr int kSkMinIters = 4;
 GemmChoice choose_fp_gemm(int64_t batch, int64_t M, int64_t N, int64_t K, int elem, bool aligned);

@@ -334,6 +334,7 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
   // U's K index contiguous (U_al, or runs of 16 and more in U): the long-K
   // product loads A along K
   f.a_klanes = p.fused_ua || p.u_k_run >= 16 ? 1 : 0;
+  f.k_groups = symt::tallk_groups(p) ? 1 : 0;
   if (fb) {
     f.rb = rb;
     f.cb = cb;

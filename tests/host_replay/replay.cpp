@@ -493,6 +493,84 @@ void replay_tallk(int64_t batch, int64_t M, int64_t N, int64_t K, const std::vec
   }
 }
 
+// The long-K product's global-to-LDS variant (taken where tallk_groups holds):
+// each wave's 16-deep groups of K through its LDS ring.  Checks that every group of
+// K lies in one contiguous run of A's rows and one affine run of B's rows, that
+// B's 16-byte column chunks are contiguous, every load is 16-byte aligned and
+// inside its operand, every K index is multiplied once, and that the swizzled
+// LDS slots hand each MFMA operand read the element it stands for.
+int tk_bswz_host(int elem, int np, int k) {
+  const int row_bytes = np * elem;
+  if (elem == 8) return row_bytes % 256 == 0 ? (k & 1) << 3 : 0;
+  if (row_bytes % 256 == 0) return (k & 3) << 2;
+  if (row_bytes % 256 == 128) return ((k >> 1) & 1) << 2;
+  return 0;
+}
+
+int64_t g_tallk_dma = 0;   // plans whose long-K product takes the global-to-LDS variant
+
+void replay_tallk_dma(int elem, int64_t batch, int64_t M, int64_t N, int64_t K, const std::vector<int64_t>& ra,
+                      const std::vector<int64_t>& ca, const std::vector<int64_t>& rb, const std::vector<int64_t>& cb,
+                      int64_t ldb, int64_t a_n, int64_t b_n) {
+  const int VE = 16 / elem, GK = 16, CPR = GK / VE;
+  auto aswz = [&](int r) { return elem == 8 ? (r >> 1) & 7 : (r >> 2) & 3; };
+  if (K % GK != 0 || N % VE != 0) return;   // the launcher keeps the register variant
+  ++g_tallk_dma;
+  const int tm = static_cast<int>((M + 15) / 16), tn = static_cast<int>((N + 15) / 16);
+  const int MP = 16 * tm, NP = 16 * tn, BCH = NP / VE;
+  const int ranges = tallk_ranges(batch, K);
+  const int kc = tallk_range(K, ranges);
+  for (int64_t q = 0; q < batch; ++q) {
+    std::vector<uint8_t> cover(static_cast<size_t>(K), 0);
+    for (int x = 0; x < ranges; ++x) {
+      const int64_t k_begin = static_cast<int64_t>(x) * kc, k_end = std::min<int64_t>(K, k_begin + kc);
+      for (int w = 0; w < 4; ++w)
+        for (int64_t g = k_begin + w * GK; g < k_end; g += 4 * GK) {
+          CHECK(g + GK <= k_end, "long-K group past its range", g, k_end);
+          const int64_t acol = ca.empty() ? g : ca[q * K + g];
+          const int64_t brow = rb.empty() ? (q * K + g) * N : rb[q * K + g];
+          for (int j = 0; j < GK; ++j) {
+            cover[g + j]++;
+            if (!ca.empty()) CHECK(ca[q * K + g + j] == acol + j, "long-K A group not contiguous", g, j);
+            if (!rb.empty()) CHECK(rb[q * K + g + j] == brow + j * ldb, "long-K B group not affine", g, j);
+          }
+          // LDS labels: A slot (r, pos) holds row min(r, M - 1), K chunk pos ^ aswz(r)
+          std::vector<int64_t> lab_a(static_cast<size_t>(MP) * GK), lab_b(static_cast<size_t>(GK) * NP);
+          for (int slot = 0; slot < MP * CPR; ++slot) {
+            const int r = slot / CPR, c = (slot % CPR) ^ aswz(r);
+            CHECK(c >= 0 && c < CPR, "long-K A swizzle past the row", c, CPR);
+            const int64_t gr = std::min<int64_t>(r, M - 1);
+            const int64_t a = (ra.empty() ? (q * M + gr) * K : ra[q * M + gr]) + c * VE + acol;
+            CHECK(a % VE == 0 && a >= 0 && a + VE <= a_n, "long-K A chunk misaligned or out of bounds", a, a_n);
+            for (int e = 0; e < VE; ++e) lab_a[slot * VE + e] = gr * GK + c * VE + e;
+          }
+          for (int slot = 0; slot < GK * BCH; ++slot) {
+            const int k = slot / BCH, c = (slot % BCH) ^ tk_bswz_host(elem, NP, k);
+            CHECK(c >= 0 && c < BCH, "long-K B swizzle past the row", c, BCH);
+            const int64_t gn = std::min<int64_t>(static_cast<int64_t>(c) * VE, N - VE);
+            if (!cb.empty())
+              for (int e = 1; e < VE; ++e)
+                CHECK(cb[q * N + gn + e] == cb[q * N + gn] + e, "long-K B chunk not contiguous", gn, e);
+            const int64_t b = brow + k * ldb + (cb.empty() ? gn : cb[q * N + gn]);
+            CHECK(b % VE == 0 && b >= 0 && b + VE <= b_n, "long-K B chunk misaligned or out of bounds", b, b_n);
+            for (int e = 0; e < VE; ++e) lab_b[slot * VE + e] = k * NP + gn + e;
+          }
+          for (int m = 0; m < M; ++m)
+            for (int k = 0; k < GK; ++k) {
+              const int idx = m * GK + ((k / VE) ^ aswz(m)) * VE + k % VE;
+              CHECK(lab_a[idx] == static_cast<int64_t>(m) * GK + k, "long-K A operand read from the wrong slot", m, k);
+            }
+          for (int k = 0; k < GK; ++k)
+            for (int n = 0; n < N; ++n) {
+              const int idx = k * NP + ((n / VE) ^ tk_bswz_host(elem, NP, k)) * VE + n % VE;
+              CHECK(lab_b[idx] == static_cast<int64_t>(k) * NP + n, "long-K B operand read from the wrong slot", k, n);
+            }
+        }
+    }
+    for (int64_t k = 0; k < K; ++k) CHECK(cover[k] == 1, "long-K group index not multiplied once", k, cover[k]);
+  }
+}
+
 void check_fused(const Plan& p) {
   if (!(p.fused || p.fused_ua)) return;
   const int G = p.g.size;
@@ -520,6 +598,10 @@ void check_fused(const Plan& p) {
     const int64_t b_n = p.fused_b ? p.V.elems : G * p.gk * p.gn;
     replay_tallk(G, p.M, p.gn, p.gk, ra, ca, p.fused_b ? rb : none, p.fused_b ? cb : none, rc, cc,
                  p.fused_ua ? G * p.M * p.gk : p.U.elems * cm, b_n, p.W.elems * cm);
+    if (tallk_groups(p))
+      replay_tallk_dma(p.compute == SYMT_COMPUTE_F64 ? 8 : 4, G, p.M, p.gn, p.fused_ua ? p.kpad : p.gk, ra, ca,
+                       p.fused_b ? rb : none, p.fused_b ? cb : none, p.fused_b ? p.ldb : p.gn,
+                       p.fused_ua ? G * p.M * p.kpad : p.U.elems * cm, b_n);
   }
   if (p.compute != SYMT_COMPUTE_BF16X3 && p.gk <= 64 && p.gn <= 64) {
     const std::vector<int64_t> none;
@@ -846,6 +928,9 @@ void workload_cases() {
       {"abc,asA->bcsA", 6, "---", "++-", {8, 4, 8}, {8, 2, 8}},
       {"bcsA,bsSB->cASB", 6, "--+-", "+---", {4, 8, 2, 8}, {4, 2, 2, 4}},
       {"cASB,cSC->ABC", 6, "----", "++-", {8, 8, 2, 4}, {8, 2, 8}},
+      // the chain's gradient with respect to W: a long-K product whose K runs (A)
+      // hold whole 16-deep groups
+      {"bcsA,cASB->bsSB", 6, "--+-", "----", {2, 8, 2, 16}, {8, 16, 2, 2}},
       {"opij,opkm->ijmk", 8, "++--", "--++", {3, 3, 4, 4}, {3, 3, 4, 2}},
       {"ijk,klm->ijlm", 5, "++-", "++-", {7, 10, 7}, {7, 1, 7}},
   };
@@ -927,7 +1012,8 @@ int main(int argc, char** argv) {
     for (int sp : {2, 3, 8, 64, 128})
       for (int nk : {8, 16, 17, 100, 185193})
         check_split_k(tiles, sp, nk, tiles * sp * 128 * 128, 128 * 128);
-  std::printf("host replay: %d random contractions + workload shapes, %lld checks, %d failures\n", done,
-              static_cast<long long>(g_checks), g_failures);
+  std::printf("host replay: %d random contractions + workload shapes, %lld checks (%lld global-to-LDS long-K"
+              " plans), %d failures\n", done, static_cast<long long>(g_checks), static_cast<long long>(g_tallk_dma),
+              g_failures);
   return g_failures == 0 ? 0 : 1;
 }

@@ -853,6 +853,34 @@ def test_long_k_product(P, compute, monkeypatch):
         assert np.array_equal(H.to_np(P.sector_gemm(a, bb, compute)), C)
 
 
+@pytest.mark.parametrize("compute", ["f64", "f32"])
+def test_long_k_lds_variant(P, compute, monkeypatch):
+    """The long-K product's global-to-LDS variant (K in whole 16-deep groups,
+    N in whole 16-byte chunks): within the product's bound of an FP64 matmul on
+    ragged M and N (rows and chunks clamped), one group, more slices than
+    ranges, every LDS swizzle of B (rows of 32, 36, 48 and 64 columns), and
+    run-to-run identical.  (Its bits equal the register variant's: see the
+    in-place long-K cases, whose fused and three-step paths take different
+    variants.)"""
+    monkeypatch.setenv("SYMT_GEMM_TILE", "tallk")
+    monkeypatch.delenv("SYMT_GEMM_SK", raising=False)
+    dt = torch.float64 if compute == "f64" else torch.float32
+    for shape in [(6, 48, 20000, 48), (2, 1, 512, 4), (5, 33, 1600, 20), (3, 64, 4096, 64),
+                  (1, 64, 16, 64), (700, 3, 48, 4), (2, 17, 2048, 36), (4, 48, 3072, 32)]:
+        b, m, k, n = shape
+        say(f"long-K global-to-LDS {compute} {shape}")
+        rng = np.random.default_rng(m * 7 + n + k)
+        a = torch.from_numpy(rng.standard_normal((b, m, k))).to(DEV, dt)
+        bb = torch.from_numpy(rng.standard_normal((b, k, n))).to(DEV, dt)
+        C = H.to_np(P.sector_gemm(a, bb, compute))
+        A64, B64 = H.to_np(a).astype(np.float64), H.to_np(bb).astype(np.float64)
+        ref = np.matmul(A64, B64)
+        absb = np.matmul(np.abs(A64), np.abs(B64))
+        fac = 2 * H.gamma(k, H.U64) if compute == "f64" else 1.05 * H.gamma(k, H.U32)
+        assert np.all(np.abs(C - ref) <= fac * absb + 1e-300), (compute, shape)
+        assert np.array_equal(H.to_np(P.sector_gemm(a, bb, compute)), C)
+
+
 ROW_CASES = [
     # W's rows contiguous (its last modes from U): lanes store along rows
     ("cASB,bsSB->bcsA", (2, 3), "----", "+---", (6, 16, 2, 4), (4, 2, 2, 4)),
@@ -867,9 +895,14 @@ ROW_CASES = [
 
 # Long K with M and N at most 64 (a gradient with respect to a small operand).
 TALLK_CASES = [
+    # (K in whole 16-deep groups of U's and V's runs: the global-to-LDS variant on both paths)
     ("bcsA,cASB->bsSB", (2, 3), "--+-", "----", (4, 16, 2, 16), (16, 16, 2, 4)),
     ("ak,kb->ab", (5,), "+-", "++", (7, 3000), (3000, 9)),
     ("klab,klc->abc", (3,), "++-+", "--+", (40, 30, 2, 3), (40, 30, 5)),
+    # U's contracted modes lead: the register variant in place, the global-to-LDS
+    # variant on U_al (three steps); the two must give the same bits
+    ("klab,klc->abc", (3,), "++-+", "--+", (40, 32, 2, 4), (40, 32, 4)),
+    ("ak,kb->ab", (5,), "+-", "++", (7, 3200), (3200, 10)),
 ]
 
 
