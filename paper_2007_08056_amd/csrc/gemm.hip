@@ -493,6 +493,66 @@ __device__ __forceinline__ void store_tile(T* __restrict__ C, int M, int N, int6
   }
 }
 
+// W's offset-table entries of this thread's rows and columns of a tile, loaded
+// before the tile's K loop (so their latency hides behind it) and used by
+// store_tile_tab.  rows4: W's rows come in contiguous, 16-byte aligned runs of
+// a multiple of 4 elements; a binary32 lane then holds 4 consecutive rows of one
+// column (rows 4(l/16) .. +3) and writes them with one 16-byte store.
+template <int TM, int TN>
+struct CTab {
+  int64_t row[TM][4];
+  int64_t col[TN];
+};
+
+template <typename T, int BM, int BN, int WM, int WN, int TM, int TN>
+__device__ __forceinline__ void load_ctab(CTab<TM, TN>& t, int M, int N, int64_t q, int m0, int n0,
+                                          const int64_t* __restrict__ rc, const int64_t* __restrict__ cc) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wm0 = (wave / WN) * (BM / WM);
+  const int wn0 = (wave % WN) * (BN / WN);
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int col = n0 + wn0 + j * 16 + (lane & 15);
+    t.col[j] = col < N ? cc[q * N + col] : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = m0 + wm0 + i * 16 + Mfma<T>::row(lane, r);
+      t.row[i][r] = row < M ? rc[q * M + row] : 0;
+    }
+}
+
+template <typename T, int BM, int BN, int WM, int WN, int TM, int TN, typename Acc>
+__device__ __forceinline__ void store_tile_tab(T* __restrict__ C, int M, int N, int m0, int n0,
+                                               const CTab<TM, TN>& t, bool rows4, const Acc (&acc)[TM][TN]) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wm0 = (wave / WN) * (BM / WM);
+  const int wn0 = (wave % WN) * (BN / WN);
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int col = n0 + wn0 + j * 16 + (lane & 15);
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      if constexpr (sizeof(T) == 4) {
+        const int row0 = m0 + wm0 + i * 16 + Mfma<T>::row(lane, 0);
+        if (rows4 && row0 + 3 < M) {
+          if (col < N) *reinterpret_cast<f4*>(C + t.row[i][0] + t.col[j]) = acc[i][j];
+          continue;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm0 + i * 16 + Mfma<T>::row(lane, r);
+        if (row < M && col < N) C[t.row[i][r] + t.col[j]] = acc[i][j][r];
+      }
+    }
+  }
+}
+
 // Piece of a cut tile in accumulator order: element ((wave*TM + i)*TN + j)*4 + r
 // of lane l sits at 64 * that + l, so stores and the fixup's loads coalesce.
 template <int TM, int TN, typename T, typename Acc>
@@ -525,7 +585,7 @@ __global__ __launch_bounds__(64 * WM * WN, (kDmaWavesPerSimd<BM, BN, S>)) void k
     int tiles_m, int tiles_n, int64_t ntiles, const int64_t* __restrict__ ra,
     const int64_t* __restrict__ ca, const int64_t* __restrict__ rc, const int64_t* __restrict__ cc,
     const int64_t* __restrict__ rb, const int64_t* __restrict__ cb, int64_t ldb,
-    T* __restrict__ part, int ts) {
+    T* __restrict__ part, int ts, int c_rows4) {
   using D = DmaTile<T, BM, BN, WM, WN, S>;
   constexpr int TM = D::TM, TN = D::TN;
   __shared__ __attribute__((aligned(1024))) char smem[S * D::STAGE];
@@ -540,9 +600,17 @@ __global__ __launch_bounds__(64 * WM * WN, (kDmaWavesPerSimd<BM, BN, S>)) void k
     for (int i = 0; i < TM; ++i)
 #pragma unroll
       for (int j = 0; j < TN; ++j) acc[i][j] = typename D::Acc{};
+    // W's table entries ahead of the K loop where registers allow (the binary64
+    // 128-wide tiles keep their two waves per SIMD without them)
+    constexpr bool kTabAhead = FC && (sizeof(T) == 4 || BM * BN <= 96 * 96);
+    CTab<TM, TN> ct;
+    if constexpr (kTabAhead) load_ctab<T, BM, BN, WM, WN, TM, TN>(ct, M, N, q, tm * BM, tn * BN, rc, cc);
     dma_tile_accumulate<T, BM, BN, WM, WN, S, FA, FB>(A, B, M, N, K, q, tm * BM, tn * BN, 0, nk, ra, ca,
                                                       rb, cb, ldb, smem, acc);
-    store_tile<T, BM, BN, WM, WN, TM, TN, FC>(C, M, N, q, tm * BM, tn * BN, rc, cc, acc);
+    if constexpr (kTabAhead)
+      store_tile_tab<T, BM, BN, WM, WN, TM, TN>(C, M, N, tm * BM, tn * BN, ct, c_rows4 != 0, acc);
+    else
+      store_tile<T, BM, BN, WM, WN, TM, TN, FC>(C, M, N, q, tm * BM, tn * BN, rc, cc, acc);
   } else {
     const SkSlot sl = sk_slot(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x), ts);
     const int team = sl.team, member = sl.member, nteam = sl.nteam;
@@ -1203,15 +1271,16 @@ hipError_t launch_dma_kernel(int mode, dim3 grid, dim3 block, hipStream_t s, con
   const int64_t* rb = f ? f->rb : nullptr;
   const int64_t* cb = f ? f->cb : nullptr;
   const int64_t ldb = f ? f->ldb : 0;
+  const int rows4 = f && f->c_rows4 && (reinterpret_cast<uintptr_t>(c) & 15) == 0 ? 1 : 0;
   if (mode == 2)
     hipLaunchKernelGGL((k_gemm_dma<T, BM, BN, WM, WN, S, true, true, true, SK>), grid, block, 0, s, a, b, c, M,
-                       N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, rb, cb, ldb, pt, ts);
+                       N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, rb, cb, ldb, pt, ts, rows4);
   else if (mode == 1)
     hipLaunchKernelGGL((k_gemm_dma<T, BM, BN, WM, WN, S, true, false, true, SK>), grid, block, 0, s, a, b, c, M,
-                       N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, rb, cb, ldb, pt, ts);
+                       N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, rb, cb, ldb, pt, ts, rows4);
   else
     hipLaunchKernelGGL((k_gemm_dma<T, BM, BN, WM, WN, S, false, false, false, SK>), grid, block, 0, s, a, b, c,
-                       M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, rb, cb, ldb, pt, ts);
+                       M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, rb, cb, ldb, pt, ts, rows4);
   return hipGetLastError();
 }
 

@@ -144,6 +144,7 @@ struct FusedTables {
   int32_t at = 0;                   // 1: A loaded K-major from U (register tiles)
   int32_t c_trans = 0;              // 1: W's rows are its contiguous index (row-streaming product)
   int32_t a_klanes = 0;             // 1: U's K index runs contiguous for 16 or more (long-K product)
+  int32_t c_rows4 = 0;              // 1: W's rows in contiguous runs of a multiple of 4 elements
   int32_t k_groups = 0;             // 1: every 16-deep group of K lies in one run of A's rows and one
                                     //    affine run of B's rows, B's columns in 16-byte chunks (long-K)
 };

@@ -335,6 +335,8 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
   // product loads A along K
   f.a_klanes = p.fused_ua || p.u_k_run >= 16 ? 1 : 0;
   f.k_groups = symt::tallk_groups(p) ? 1 : 0;
+  // W's rows contiguous in runs of 4k elements: binary32 tiles store 4 rows per lane
+  f.c_rows4 = !p.cplx && p.w_row_run % 4 == 0 ? 1 : 0;
   if (fb) {
     f.rb = rb;
     f.cb = cb;

@@ -588,6 +588,16 @@ void check_fused(const Plan& p) {
   rc = table(make_offsets(p, 2, true), G);
   cc = table(make_offsets(p, 2, false), G);
   check_bijection(rc, cc, G, p.M, p.gn, p.W.elems * cm, "W tables not a bijection onto W");
+  if (!p.cplx && p.w_row_run % 4 == 0) {
+    // binary32 tiles store 4 consecutive rows of a column with one 16-byte store
+    for (int q = 0; q < G; ++q)
+      for (int64_t m = 0; m + 3 < p.M; m += 4) {
+        for (int t = 1; t < 4; ++t)
+          CHECK(rc[q * p.M + m + t] == rc[q * p.M + m] + t, "W rows not in runs of 4", m, t);
+        for (int64_t n = 0; n < p.gn; ++n)
+          CHECK((rc[q * p.M + m] + cc[q * p.gn + n]) % 4 == 0, "W run of 4 rows not 16-byte aligned", m, n);
+      }
+  }
   if (p.fused_b) {
     rb = table(make_offsets(p, 1, true), G);
     cb = table(make_offsets(p, 1, false), G);
