@@ -509,26 +509,10 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
                        !choose_fp_gemm(p->g.size, p->M, p->gn, p->gk, static_cast<int>(ea), true).dma;
   // U's contracted modes are not its last ones: where the product runs on register
   // tiles anyway, A is loaded K-major straight from U (row k of a K-step at its own
-  // column-table entry, M chunks along U's other modes), as B is from V.  Where
-  // U's last modes hold no whole 16-byte chunk along M, those loads are single
-  // elements at a stride: on register-tile products of a GFLOP and more,
-  // aligning U first (one streaming transform) and running the aligned product
-  // costs less.  (The row-streaming and long-K products read U through its
-  // tables whatever its layout.)
-  bool at_chunks = false;
-  {
-    int64_t st[kMaxOrder];
-    int64_t a = 1;
-    for (int m = p->U.n - 1; m >= 0; --m) { st[m] = a; a *= p->U.dims[m]; }
-    int64_t i_run = 1;
-    for (int i = p->s - 1; i >= 0 && st[p->posI_u[i]] == i_run; --i) i_run *= p->U.dims[p->posI_u[i]];
-    at_chunks = !p->cplx && i_run % (16 / static_cast<int64_t>(ea)) == 0;
-  }
-  const bool at_big = 2.0 * static_cast<double>(p->nq) * p->M * p->gn * p->gk >= 1e9;
-  const GemmChoice at_gc = choose_fp_gemm(p->g.size, p->M, p->gn, p->gk, static_cast<int>(ea), true);
-  const bool at_tables = at_gc.tile == kTallKTile || at_gc.tile == kRowsTile;
+  // column-table entry, M chunks along U's other modes), as B is from V.
   const bool at_ok = !trailing_k && compute != SYMT_COMPUTE_BF16X3 && p->U.dtype == want &&
-                     (!w || p->W.dtype == want) && (at_chunks || !at_big || at_tables) && !at_gc.dma;
+                     (!w || p->W.dtype == want) &&
+                     !choose_fp_gemm(p->g.size, p->M, p->gn, p->gk, static_cast<int>(ea), true).dma;
   p->fused = !force_steps && !p->subgroups && p->nq == p->g.size &&
              (((fp_ok || bf_ok || stepped) && trailing_k) || at_ok) &&
              p->M > 0 && p->N > 0 && p->Kd > 0 && p->U.elems > 0;
@@ -1075,23 +1059,6 @@ XformParams make_xform(const Plan& p, int operand, bool to_aligned, int in_bytes
     }
     x.run_len = pa;
     x.t_len = pb;
-    // The destination's fastest dim on the A side, small, with B's fastest dim
-    // right above it (a source [c][A][S][B] into [A][B][c][S]): writing lanes
-    // along B alone would leave gaps of that dim's size; lanes take (B, that
-    // dim) pairs instead and write whole runs.
-    x.pair_w = x.pair_ad = 0;
-    if (!x.tr_write && x.nb > 0) {
-      int64_t ad = 1;
-      for (int i = 0; i < x.na; ++i) {
-        const int64_t w = x.asize[i];
-        if (x.ads[i] == 1 && (w == 2 || w == 4 || w == 8 || w == 16) && 64 % (ad * w) == 0 && x.tds[0] == w) {
-          x.pair_w = static_cast<int32_t>(w);
-          x.pair_ad = static_cast<int32_t>(ad);
-          break;
-        }
-        ad *= x.asize[i];
-      }
-    }
   }
   // Batch dims: the rest, ordered so that the last one has the smallest dst stride.
   int order_idx[kMaxDims];
