@@ -115,11 +115,13 @@
  * (or K stepped run by run): then two more tables let the product read B from
  * v's standard form as well (info.fused_v = 1) and no aligned form is written
  * at all.  Where u's contracted modes are not its last ones, u and w are real
- * and in the compute type and the product runs on register-staged tiles, A is
+ * and in the compute type and the product runs on register-staged tiles, or on
+ * 128-row global-to-LDS tiles with u's trailing output modes in whole 16-byte
+ * chunks (and u 16-byte aligned; else a register-staged tile takes over), A is
  * loaded K-major straight from u (each row of a K-step from its own table
  * entry, chunks along u's other modes), with the same values in the same order
- * (info.fused = 1).  Where u does not qualify otherwise (global-to-LDS shapes,
- * or runs that suit neither stepping), compute is F64 or F32, the operands
+ * (info.fused = 1).  Where u does not qualify otherwise (other global-to-LDS
+ * shapes, or runs that suit neither stepping), compute is F64 or F32, the operands
  * are real, w is in the compute type, no mode is a subgroup mode and every Q
  * slice is live, u alone is aligned first and the same product reads U_al
  * through affine tables (info.fused = 0, info.fused_w = 1); with BF16X3, u and

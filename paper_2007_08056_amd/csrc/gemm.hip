@@ -306,10 +306,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_split_sum(const T* __restrict_
   const int e0 = static_cast<int>(blockIdx.y) * per;
   const int e1 = min(E, e0 + per);
   for (int e = e0 + static_cast<int>(threadIdx.x); e < e1; e += NT) {
-    T acc = T(0);
-#pragma unroll 8
-    for (int sp = 0; sp < splits; ++sp) acc += pt[static_cast<int64_t>(sp) * E + e];
     // accumulator order: element ((w * TM + i) * TN + j) * 4 + r of lane l at 64 * that + l
+    // (W's table entries requested before the partials are read)
     const int w = e / PER_WAVE;
     const int rem = e - w * PER_WAVE;
     const int lane = rem & 63;
@@ -319,11 +317,13 @@ __global__ __launch_bounds__(64 * WM * WN) void k_split_sum(const T* __restrict_
     const int i = ij / TN, j = ij - (ij / TN) * TN;
     const int row = tm * BM + (w / WN) * (BM / WM) + i * 16 + Mfma<T>::row(lane, r);
     const int col = tn * BN + (w % WN) * (BN / WN) + j * 16 + (lane & 15);
-    if (row < M && col < N) {
-      const int64_t crow = FC ? rc[q * M + row] : static_cast<int64_t>(row) * N;
-      const int64_t ccol = FC ? cc[q * N + col] : col;
-      Cq[crow + ccol] = acc;
-    }
+    const bool in = row < M && col < N;
+    const int64_t crow = FC ? (in ? rc[q * M + row] : 0) : static_cast<int64_t>(row) * N;
+    const int64_t ccol = FC ? (in ? cc[q * N + col] : 0) : col;
+    T acc = T(0);
+#pragma unroll 8
+    for (int sp = 0; sp < splits; ++sp) acc += pt[static_cast<int64_t>(sp) * E + e];
+    if (in) Cq[crow + ccol] = acc;
   }
 }
 
@@ -364,7 +364,11 @@ struct DmaTile {
 // FB: B is V's standard form, row k0 + k of a K-step at rb[q*K + k0] + k * ldb
 // and 16-byte column chunk n at cb[q*N + n] (every K-step inside one affine run
 // of rows, every chunk inside one contiguous run of columns).
-template <typename T, int BM, int BN, int WM, int WN, int S, bool FA, bool FB>
+// AT (with FA): A is K-major in U, element (m, k) at ra[q*M + m] + ca[q*K + k] with
+// 16-byte chunks along M; its tile is staged like B's (row k of a K-step at its
+// own table entry, one wave-uniform entry per row and load) and read back in the
+// MFMA layout from [k][m].
+template <typename T, int BM, int BN, int WM, int WN, int S, bool FA, bool FB, bool AT = false>
 __device__ __forceinline__ void dma_tile_accumulate(
     const T* __restrict__ A, const T* __restrict__ B, int M, int N, int K, int64_t q, int m0, int n0,
     int kt0, int kt1, const int64_t* __restrict__ ra, const int64_t* __restrict__ ca,
@@ -385,15 +389,44 @@ __device__ __forceinline__ void dma_tile_accumulate(
   const int wn0 = (wave % WN) * (BN / WN);
 
   // Global source of each of this thread's loads (row base, chunk), fixed across K-steps.
+  // (K-major A: slot (k, position) of a K-step holds M chunk position ^ ((k & 1) << 3),
+  // the lane's M offset fixed, the row offset of k from the step's table entries)
+  constexpr int ACH = BM / VE;                    // K-major A: chunks per K row
+  static_assert(!AT || (FA && (ACH == 32 || ACH == 64)), "K-major A needs 32 or 64 chunks per row");
   int64_t a_src[A_LOADS];
   int a_chunk[A_LOADS];
 #pragma unroll
   for (int i = 0; i < A_LOADS; ++i) {
     const int slot = tid + i * NT;                // A slot = row * 8 + position
-    const int r = slot >> 3, c = slot & 7;
-    const int gr = min(m0 + r, M - 1);
-    a_src[i] = FA ? ra[q * M + gr] : static_cast<int64_t>(gr) * K;
-    a_chunk[i] = c ^ ((r >> 1) & 7);
+    if constexpr (AT) {
+      const int k = slot / ACH, c = slot % ACH;
+      const int gm = min(m0 + (c ^ ((k & 1) << 3)) * VE, M - VE);
+      a_src[i] = ra[q * M + gm];
+      a_chunk[i] = 0;
+    } else {
+      const int r = slot >> 3, c = slot & 7;
+      const int gr = min(m0 + r, M - 1);
+      a_src[i] = FA ? ra[q * M + gr] : static_cast<int64_t>(gr) * K;
+      a_chunk[i] = c ^ ((r >> 1) & 7);
+    }
+  }
+  // K-major A: the row offsets of this thread's K rows of step kt (wave-uniform
+  // for 64 chunks per row; two per wave, split by lane half, for 32), one step ahead
+  auto at_rows = [&](int kt, int64_t (&rows)[A_LOADS]) {
+    const int64_t* tab = ca + q * K + static_cast<int64_t>(kt) * BK;
+#pragma unroll
+    for (int i = 0; i < A_LOADS; ++i) {
+      if constexpr (ACH == 64) {
+        rows[i] = tab[wave + i * (NT / 64)];
+      } else {
+        const int64_t r0 = tab[2 * wave + i * (NT / 32)], r1 = tab[2 * wave + 1 + i * (NT / 32)];
+        rows[i] = (lane & 32) ? r1 : r0;
+      }
+    }
+  };
+  int64_t arow_next[AT ? A_LOADS : 1];
+  if constexpr (AT) {
+    if (kt0 < kt1) at_rows(kt0, arow_next);
   }
   int64_t b_src[B_LOADS];
 #pragma unroll
@@ -406,12 +439,17 @@ __device__ __forceinline__ void dma_tile_accumulate(
   }
   // Fused A (B): column (row) offset of each K-step, fetched one issue ahead so
   // its latency hides behind the previous step's products.
-  int64_t acol_next = FA && kt0 < kt1 ? ca[q * K + static_cast<int64_t>(kt0) * BK] : 0;
+  int64_t acol_next = FA && !AT && kt0 < kt1 ? ca[q * K + static_cast<int64_t>(kt0) * BK] : 0;
   int64_t brow_next = FB && kt0 < kt1 ? rb[q * K + static_cast<int64_t>(kt0) * BK] : 0;
   auto issue = [&](int kt, int stage) {
     const int k0 = kt * BK;
     int64_t acol = k0;
-    if constexpr (FA) {
+    int64_t arow[AT ? A_LOADS : 1];
+    if constexpr (AT) {
+#pragma unroll
+      for (int i = 0; i < A_LOADS; ++i) arow[i] = arow_next[i];
+      if (kt + 1 < kt1) at_rows(kt + 1, arow_next);
+    } else if constexpr (FA) {
       acol = acol_next;
       if (kt + 1 < kt1) acol_next = ca[q * K + static_cast<int64_t>(kt + 1) * BK];
     }
@@ -422,8 +460,12 @@ __device__ __forceinline__ void dma_tile_accumulate(
     }
     char* base = smem + stage * STAGE;
 #pragma unroll
-    for (int i = 0; i < A_LOADS; ++i)
-      lds_dma16(Aq + a_src[i] + acol + a_chunk[i] * VE, base + (i * NT + wave * 64) * 16);
+    for (int i = 0; i < A_LOADS; ++i) {
+      if constexpr (AT)
+        lds_dma16(Aq + arow[i] + a_src[i], base + (i * NT + wave * 64) * 16);
+      else
+        lds_dma16(Aq + a_src[i] + acol + a_chunk[i] * VE, base + (i * NT + wave * 64) * 16);
+    }
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i)
       lds_dma16(Bq + b_src[i] + brow, base + BM * 128 + (i * NT + wave * 64) * 16);
@@ -451,7 +493,10 @@ __device__ __forceinline__ void dma_tile_accumulate(
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
         const int m = wm0 + i * 16 + (lane & 15);
-        a[i] = As[m * BK + ((k / VE) ^ ((m >> 1) & 7)) * VE + k % VE];
+        if constexpr (AT)
+          a[i] = As[k * BM + ((m / VE) ^ ((k & 1) << 3)) * VE + m % VE];
+        else
+          a[i] = As[m * BK + ((k / VE) ^ ((m >> 1) & 7)) * VE + k % VE];
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
@@ -579,7 +624,7 @@ __device__ __forceinline__ void store_piece(T* __restrict__ piece, const Acc (&a
 template <int BM, int BN, int S>
 constexpr int kDmaWavesPerSimd = (S == 2 && BM * BN <= 96 * 96) ? 3 : 1;
 
-template <typename T, int BM, int BN, int WM, int WN, int S, bool FA, bool FB, bool FC, bool SK>
+template <typename T, int BM, int BN, int WM, int WN, int S, bool FA, bool FB, bool FC, bool SK, bool AT = false>
 __global__ __launch_bounds__(64 * WM * WN, (kDmaWavesPerSimd<BM, BN, S>)) void k_gemm_dma(
     const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C, int M, int N, int K,
     int tiles_m, int tiles_n, int64_t ntiles, const int64_t* __restrict__ ra,
@@ -605,8 +650,8 @@ __global__ __launch_bounds__(64 * WM * WN, (kDmaWavesPerSimd<BM, BN, S>)) void k
     constexpr bool kTabAhead = FC && (sizeof(T) == 4 || BM * BN <= 96 * 96);
     CTab<TM, TN> ct;
     if constexpr (kTabAhead) load_ctab<T, BM, BN, WM, WN, TM, TN>(ct, M, N, q, tm * BM, tn * BN, rc, cc);
-    dma_tile_accumulate<T, BM, BN, WM, WN, S, FA, FB>(A, B, M, N, K, q, tm * BM, tn * BN, 0, nk, ra, ca,
-                                                      rb, cb, ldb, smem, acc);
+    dma_tile_accumulate<T, BM, BN, WM, WN, S, FA, FB, AT>(A, B, M, N, K, q, tm * BM, tn * BN, 0, nk, ra, ca,
+                                                          rb, cb, ldb, smem, acc);
     if constexpr (kTabAhead)
       store_tile_tab<T, BM, BN, WM, WN, TM, TN>(C, M, N, tm * BM, tn * BN, ct, c_rows4 != 0, acc);
     else
@@ -632,11 +677,18 @@ __global__ __launch_bounds__(64 * WM * WN, (kDmaWavesPerSimd<BM, BN, S>)) void k
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = typename D::Acc{};
-      dma_tile_accumulate<T, BM, BN, WM, WN, S, FA, FB>(A, B, M, N, K, q, tm * BM, tn * BN, kt0, kt1, ra,
-                                                        ca, rb, cb, ldb, smem, acc);
-      if (kt0 == 0 && kt1 == nk)
-        store_tile<T, BM, BN, WM, WN, TM, TN, FC>(C, M, N, q, tm * BM, tn * BN, rc, cc, acc);
-      else
+      dma_tile_accumulate<T, BM, BN, WM, WN, S, FA, FB, AT>(A, B, M, N, K, q, tm * BM, tn * BN, kt0, kt1, ra,
+                                                            ca, rb, cb, ldb, smem, acc);
+      if (kt0 == 0 && kt1 == nk) {
+        if constexpr (FC) {
+          // W's table entries all requested before the first store
+          CTab<TM, TN> ct;
+          load_ctab<T, BM, BN, WM, WN, TM, TN>(ct, M, N, q, tm * BM, tn * BN, rc, cc);
+          store_tile_tab<T, BM, BN, WM, WN, TM, TN>(C, M, N, tm * BM, tn * BN, ct, c_rows4 != 0, acc);
+        } else {
+          store_tile<T, BM, BN, WM, WN, TM, TN, false>(C, M, N, q, tm * BM, tn * BN, rc, cc, acc);
+        }
+      } else
         store_piece<TM, TN>(part + sk_piece(team, member, ts, grp, first) * (BM * BN), acc);
       it += kt1 - kt0;
     }
@@ -689,7 +741,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_sk_fixup(
   const int e0 = static_cast<int>(blockIdx.y) * per;
   const int e1 = min(E, e0 + per);
   // accumulator order: element ((w * TM + i) * TN + j) * 4 + r of lane l at 64 * that + l
-  auto store = [&](int e, T v) {
+  // destination of element e of the tile (accumulator order), -1 past M or N;
+  // W's table entries are requested before the pieces are read
+  auto dest = [&](int e) -> int64_t {
     const int w = e / PER_WAVE;
     const int rem = e - w * PER_WAVE;
     const int lane = rem & 63;
@@ -699,18 +753,21 @@ __global__ __launch_bounds__(64 * WM * WN) void k_sk_fixup(
     const int i = ij / TN, j = ij - (ij / TN) * TN;
     const int row = tm * BM + (w / WN) * (BM / WM) + i * 16 + Mfma<T>::row(lane, r);
     const int col = tn * BN + (w % WN) * (BN / WN) + j * 16 + (lane & 15);
-    if (row < M && col < N) {
-      const int64_t crow = FC ? rc[q * M + row] : static_cast<int64_t>(row) * N;
-      const int64_t ccol = FC ? cc[q * N + col] : col;
-      Cq[crow + ccol] = v;
-    }
+    if (row >= M || col >= N) return -1;
+    const int64_t crow = FC ? rc[q * M + row] : static_cast<int64_t>(row) * N;
+    const int64_t ccol = FC ? cc[q * N + col] : col;
+    return crow + ccol;
   };
   constexpr int NT = 64 * WM * WN;
   constexpr int U = 4;                            // elements in flight per thread
   for (int e = e0 + static_cast<int>(threadIdx.x); e < e1; e += U * NT) {
     T acc[U];
+    int64_t dst[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) acc[u] = T(0);
+    for (int u = 0; u < U; ++u) {
+      acc[u] = T(0);
+      dst[u] = e + u * NT < e1 ? dest(e + u * NT) : -1;
+    }
     if (listed) {
 #pragma unroll 4
       for (int k = 0; k < static_cast<int>(n_teams); ++k) {
@@ -734,7 +791,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_sk_fixup(
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (e + u * NT < e1) store(e + u * NT, acc[u]);
+      if (dst[u] >= 0) Cq[dst[u]] = acc[u];
   }
 }
 
@@ -1257,8 +1314,9 @@ int device_cus() {
 }
 
 // Fused mode of a global-to-LDS product: 0 aligned operands, 1 A read from U and
-// C written to W in place, 2 B read from V in place as well.
-inline int dma_mode(const FusedTables* f) { return !f ? 0 : f->rb ? 2 : 1; }
+// C written to W in place, 2 B read from V in place as well; 3 and 4: as 1 and 2
+// with A K-major in U (128-row tiles only).
+inline int dma_mode(const FusedTables* f) { return !f ? 0 : (f->rb ? 2 : 1) + (f->at ? 2 : 0); }
 
 template <typename T, int BM, int BN, int WM, int WN, int S, bool SK>
 hipError_t launch_dma_kernel(int mode, dim3 grid, dim3 block, hipStream_t s, const T* a, const T* b, T* c,
@@ -1272,6 +1330,20 @@ hipError_t launch_dma_kernel(int mode, dim3 grid, dim3 block, hipStream_t s, con
   const int64_t* cb = f ? f->cb : nullptr;
   const int64_t ldb = f ? f->ldb : 0;
   const int rows4 = f && f->c_rows4 && (reinterpret_cast<uintptr_t>(c) & 15) == 0 ? 1 : 0;
+  if constexpr (BM == 128) {
+    if (mode == 4) {
+      hipLaunchKernelGGL((k_gemm_dma<T, BM, BN, WM, WN, S, true, true, true, SK, true>), grid, block, 0, s, a, b, c,
+                         M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, rb, cb, ldb, pt, ts, rows4);
+      return hipGetLastError();
+    }
+    if (mode == 3) {
+      hipLaunchKernelGGL((k_gemm_dma<T, BM, BN, WM, WN, S, true, false, true, SK, true>), grid, block, 0, s, a, b,
+                         c, M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, rb, cb, ldb, pt, ts, rows4);
+      return hipGetLastError();
+    }
+  } else {
+    if (mode > 2) return hipErrorInvalidValue;   // K-major A takes 128-row tiles only
+  }
   if (mode == 2)
     hipLaunchKernelGGL((k_gemm_dma<T, BM, BN, WM, WN, S, true, true, true, SK>), grid, block, 0, s, a, b, c, M,
                        N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, rb, cb, ldb, pt, ts, rows4);
@@ -1306,12 +1378,13 @@ hipError_t launch_dma(int64_t batch, int M, int N, int K, const void* A, const v
   int P = 0, ts = 1;
   if (part) {
     // resident workgroups per CU of this instantiation (per fused mode), cached
-    static std::atomic<int> occupancy[3];
+    static std::atomic<int> occupancy[5];
     int occ = occupancy[mode].load(std::memory_order_relaxed);
     if (occ == 0) {
-      auto kern = mode == 2   ? k_gemm_dma<T, BM, BN, WM, WN, S, true, true, true, true>
-                  : mode == 1 ? k_gemm_dma<T, BM, BN, WM, WN, S, true, false, true, true>
-                              : k_gemm_dma<T, BM, BN, WM, WN, S, false, false, false, true>;
+      // (the K-major forms have the same LDS and about the same registers)
+      auto kern = mode % 2 == 0 && mode > 0 ? k_gemm_dma<T, BM, BN, WM, WN, S, true, true, true, true>
+                  : mode > 0              ? k_gemm_dma<T, BM, BN, WM, WN, S, true, false, true, true>
+                                          : k_gemm_dma<T, BM, BN, WM, WN, S, false, false, false, true>;
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64 * WM * WN, 0) != hipSuccess || occ < 1)
         occ = 1;
       occupancy[mode].store(occ, std::memory_order_relaxed);
@@ -1453,11 +1526,13 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
     const bool f64 = compute == SYMT_COMPUTE_F64;
     const int vw = f64 ? 2 : 4;
     const int vec = (K % vw == 0 && N % vw == 0) ? vw : 1;
-    // K stepped run by run (fused->krun) and K-major A (fused->at) need the register tiles
+    // K stepped run by run (fused->krun) needs the register tiles; K-major A
+    // (fused->at) with 16-byte chunks takes the 128-row global-to-LDS tiles too
+    const bool a_kmajor = fused && fused->at;
     const bool aligned = (reinterpret_cast<uintptr_t>(A) & 15) == 0 &&
                          (reinterpret_cast<uintptr_t>(B) & 15) == 0 &&
-                         (!fused || (fused->vec > 1 && fused->krun == 0 && !fused->at));
-    const GemmChoice gc = choose_fp_gemm(batch, M, N, K, f64 ? 8 : 4, aligned);
+                         (!fused || (fused->vec > 1 && fused->krun == 0));
+    const GemmChoice gc = choose_fp_gemm(batch, M, N, K, f64 ? 8 : 4, aligned, a_kmajor);
     if (gc.tile == kTallKTile) {
       // without room for the partials (the allocation-free entry point may drop
       // them) the 128 x 48 register tile runs instead, one workgroup per tile

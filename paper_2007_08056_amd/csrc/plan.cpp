@@ -507,18 +507,12 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
                        (!w || p->W.dtype == want) && p->nK <= INT32_MAX && p->nK > 0 &&
                        p->gk % p->nK == 0 &&
                        !choose_fp_gemm(p->g.size, p->M, p->gn, p->gk, static_cast<int>(ea), true).dma;
-  // U's contracted modes are not its last ones: where the product runs on register
-  // tiles anyway, A is loaded K-major straight from U (row k of a K-step at its own
-  // column-table entry, M chunks along U's other modes), as B is from V.
-  const bool at_ok = !trailing_k && compute != SYMT_COMPUTE_BF16X3 && p->U.dtype == want &&
-                     (!w || p->W.dtype == want) &&
-                     !choose_fp_gemm(p->g.size, p->M, p->gn, p->gk, static_cast<int>(ea), true).dma;
-  p->fused = !force_steps && !p->subgroups && p->nq == p->g.size &&
-             (((fp_ok || bf_ok || stepped) && trailing_k) || at_ok) &&
-             p->M > 0 && p->N > 0 && p->Kd > 0 && p->U.elems > 0;
-  p->a_trans = p->fused && !trailing_k;
-  p->krun = p->fused && stepped ? static_cast<int32_t>(p->nK) : 0;
-  if (p->a_trans) {
+  // U's contracted modes are not its last ones: A is loaded K-major straight from U
+  // (row k of a K-step at its own column-table entry, M chunks along U's other
+  // modes), as B is from V: on register tiles, and on the 128-row global-to-LDS
+  // tiles where U's last modes hold whole 16-byte chunks along M.
+  bool a_chunks = false;
+  {
     // contiguous run of U's output modes at its end (16-byte loads along M)
     int64_t st[kMaxOrder];
     int64_t a = 1;
@@ -526,8 +520,23 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
     int64_t i_run = 1;
     for (int i = p->s - 1; i >= 0 && st[p->posI_u[i]] == i_run; --i) i_run *= p->U.dims[p->posI_u[i]];
     // (complex: pairs interleave, one-element loads)
-    p->a_chunks = !p->cplx && i_run % (16 / static_cast<int64_t>(ea)) == 0;
+    a_chunks = !p->cplx && i_run % (16 / static_cast<int64_t>(ea)) == 0;
   }
+  // (where the model's global-to-LDS tile is a 96-row one, which cannot read
+  // K-major A, a 128-row one replaces it only for a U large enough that aligning
+  // it would cost more than the other tile: 64 MiB; else U is aligned first)
+  const GemmChoice g_any = choose_fp_gemm(p->g.size, p->M, p->gn, p->gk, static_cast<int>(ea), true);
+  const GemmChoice g_at = choose_fp_gemm(p->g.size, p->M, p->gn, p->gk, static_cast<int>(ea), true, true);
+  const bool at_dma = g_at.dma && a_chunks &&
+                      (g_at.tile == g_any.tile || static_cast<double>(ea) * p->U.elems >= 64.0 * (1 << 20));
+  const bool at_ok = !trailing_k && compute != SYMT_COMPUTE_BF16X3 && p->U.dtype == want &&
+                     (!w || p->W.dtype == want) && (!g_any.dma || at_dma);
+  p->fused = !force_steps && !p->subgroups && p->nq == p->g.size &&
+             (((fp_ok || bf_ok || stepped) && trailing_k) || at_ok) &&
+             p->M > 0 && p->N > 0 && p->Kd > 0 && p->U.elems > 0;
+  p->a_trans = p->fused && !trailing_k;
+  p->krun = p->fused && stepped ? static_cast<int32_t>(p->nK) : 0;
+  if (p->a_trans) p->a_chunks = a_chunks;
   // Otherwise, for W in the compute type (complex: its complex counterpart), U
   // alone is aligned and the same product reads U_al through affine tables (in
   // reals), V in place where it can, and writes W in place.
@@ -580,7 +589,7 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   // Room for stream-K pieces when the model would pick it on 16-byte aligned operands.
   if (compute != SYMT_COMPUTE_BF16X3 && p->nq > 0 && p->M > 0 && p->gn > 0 && p->gk > 0) {
     const GemmChoice gc = choose_fp_gemm(p->nq, p->M, p->gn, p->gk,
-                                         compute == SYMT_COMPUTE_F64 ? 8 : 4, true);
+                                         compute == SYMT_COMPUTE_F64 ? 8 : 4, true, p->a_trans);
     p->bytes_partial = gc.partial_bytes;
     p->workspace += round_up(p->bytes_partial, 256);
   }
@@ -643,10 +652,11 @@ constexpr int kNumFpTiles = sizeof(kFpTiles) / sizeof(kFpTiles[0]);
 // fills (~1.5 us each), and one more launch (~5 us).
 namespace {
 GemmChoice choose_among(int64_t batch, int64_t M, int64_t N, int64_t K, int elem, bool aligned,
-                        const char* forced, int sk_mode) {
+                        const char* forced, int sk_mode, bool a_kmajor) {
   auto usable = [&](const FpTile& t) {
     if (!t.dma) return true;
-    return aligned && K % (128 / elem) == 0 && N % (16 / elem) == 0 && (t.bn * elem / 16) % 16 == 0;
+    return aligned && K % (128 / elem) == 0 && N % (16 / elem) == 0 && (t.bn * elem / 16) % 16 == 0 &&
+           (!a_kmajor || (t.bm == 128 && M % (16 / elem) == 0));
   };
   const double per_cu = (elem == 8 ? 78.6e12 : 157.3e12) / 256.0;
   const bool big = 2.0 * static_cast<double>(batch) * M * N * K >= 1e9;
@@ -746,12 +756,13 @@ bool tallk_groups(const Plan& p) {
 // SYMT_GEMM_TILE=<name> restricts the choice to one tile (ignored where it does
 // not apply); SYMT_GEMM_SK=0 forbids stream-K and split K, 1 forces stream-K on
 // the DMA tiles.
-GemmChoice choose_fp_gemm(int64_t batch, int64_t M, int64_t N, int64_t K, int elem, bool aligned) {
+GemmChoice choose_fp_gemm(int64_t batch, int64_t M, int64_t N, int64_t K, int elem, bool aligned,
+                          bool a_kmajor) {
   const char* forced = std::getenv("SYMT_GEMM_TILE");
   const char* sk_env = std::getenv("SYMT_GEMM_SK");
   const int sk_mode = sk_env ? std::atoi(sk_env) : -1;
-  GemmChoice g = choose_among(batch, M, N, K, elem, aligned, forced, sk_mode);
-  if (g.tile < 0) g = choose_among(batch, M, N, K, elem, aligned, nullptr, sk_mode);
+  GemmChoice g = choose_among(batch, M, N, K, elem, aligned, forced, sk_mode, a_kmajor);
+  if (g.tile < 0) g = choose_among(batch, M, N, K, elem, aligned, nullptr, sk_mode, a_kmajor);
   return g;
 }
 

@@ -275,7 +275,9 @@ inline int tallk_range(int64_t K, int ranges) {
 bool tallk_groups(const Plan& p);
 // Fewest K-iterations a stream-K workgroup takes on (bounds the pieces per tile).
 constexpr int kSkMinIters = 4;
-GemmChoice choose_fp_gemm(int64_t batch, int64_t M, int64_t N, int64_t K, int elem, bool aligned);
+// a_kmajor: A is read K-major from U (global-to-LDS tiles of 128 rows only).
+GemmChoice choose_fp_gemm(int64_t batch, int64_t M, int64_t N, int64_t K, int elem, bool aligned,
+                          bool a_kmajor = false);
 // Split-bf16 product: whether the launcher runs register-staged tiles on this
 // shape (else global-to-LDS ones), and which of the fused product's three
 // register tiles it takes (0: 128 x 64, 1: 128 x 128, 2: 128 x 256, 3: 128 x 96).

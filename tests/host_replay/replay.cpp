@@ -508,6 +508,7 @@ int tk_bswz_host(int elem, int np, int k) {
 }
 
 int64_t g_tallk_dma = 0;   // plans whose long-K product takes the global-to-LDS variant
+int64_t g_at_dma = 0;      // plans whose product can read K-major A on global-to-LDS tiles
 
 void replay_tallk_dma(int elem, int64_t batch, int64_t M, int64_t N, int64_t K, const std::vector<int64_t>& ra,
                       const std::vector<int64_t>& ca, const std::vector<int64_t>& rb, const std::vector<int64_t>& cb,
@@ -634,7 +635,7 @@ void check_fused(const Plan& p) {
   const int BK = kFpBK;
   const int spr = p.krun > 0 ? (p.krun + BK - 1) / BK : 0;
   const int64_t nk_all = p.krun > 0 ? p.gk / p.krun * spr : (p.gk + BK - 1) / BK;
-  const GemmChoice gc = choose_fp_gemm(G, p.M, p.gn, p.gk, p.compute == SYMT_COMPUTE_F64 ? 8 : 4, true);
+  const GemmChoice gc = choose_fp_gemm(G, p.M, p.gn, p.gk, p.compute == SYMT_COMPUTE_F64 ? 8 : 4, true, p.a_trans);
   for (int q = 0; q < G; ++q)
     for (int64_t kt = 0; kt < nk_all; ++kt) {
       int64_t k0, kv;
@@ -682,6 +683,40 @@ void check_fused(const Plan& p) {
           CHECK(ra[q * p.M + m + j] == ra[q * p.M + m] + j, "K-major A chunk not contiguous", m, j);
         CHECK(ra[q * p.M + m] % vw == 0, "K-major A chunk misaligned", m, q);
       }
+  const int64_t bkd = 128 / (p.compute == SYMT_COMPUTE_F64 ? 8 : 4);
+  if (p.a_trans && gc.dma) {
+    CHECK(gc.bm == 128 && p.a_chunks, "K-major A on a DMA tile that is not 128 rows or has no chunks", gc.bm,
+          p.a_chunks);
+    CHECK(p.gk % bkd == 0 && p.M % vw == 0, "K-major A DMA tile with a partial step or chunk", p.gk, p.M);
+  }
+  if (p.a_trans && p.a_chunks && p.gk % bkd == 0 && p.M % vw == 0) {
+    // K-major A on a global-to-LDS tile (the model's choice, or a forced tile):
+    // 16-byte chunks along M at every K row's table entry, inside U; the swizzled
+    // slots (k, position) hold chunk position ^ ((k & 1) << 3) and the operand
+    // reads find element (k, m) there
+    ++g_at_dma;
+    const int64_t u_n = p.U.elems * cm;
+    for (int q = 0; q < G; ++q)
+      for (int64_t k = 0; k < p.gk; ++k) {
+        CHECK(ca[q * p.gk + k] % vw == 0, "K-major A row misaligned", k, q);
+        for (int64_t m = 0; m + vw <= p.M; m += vw) {
+          const int64_t a = ca[q * p.gk + k] + ra[q * p.M + m];
+          CHECK(a >= 0 && a + vw <= u_n, "K-major A chunk outside U", a, u_n);
+        }
+      }
+    const int ach = 128 / vw;
+    std::vector<int> lab(static_cast<size_t>(bkd) * 128, -1);
+    for (int slot = 0; slot < bkd * ach; ++slot) {
+      const int k = slot / ach, c = (slot % ach) ^ ((k & 1) << 3);
+      CHECK(c >= 0 && c < ach, "K-major A swizzle past the row", c, ach);
+      for (int e = 0; e < vw; ++e) lab[static_cast<size_t>(slot) * vw + e] = k * 128 + c * vw + e;
+    }
+    for (int k = 0; k < bkd; ++k)
+      for (int m = 0; m < 128; ++m) {
+        const int idx = k * 128 + ((m / vw) ^ ((k & 1) << 3)) * vw + m % vw;
+        CHECK(lab[idx] == k * 128 + m, "K-major A operand read from the wrong slot", k, m);
+      }
+  }
   if (p.fused_b && gc.dma && p.krun == 0)
     CHECK(p.fused_b_chunks, "V in place on a DMA tile without whole column chunks", p.gn, p.ldb);
   if (p.fused_b && p.fused_b_chunks)
@@ -1023,7 +1058,8 @@ int main(int argc, char** argv) {
       for (int nk : {8, 16, 17, 100, 185193})
         check_split_k(tiles, sp, nk, tiles * sp * 128 * 128, 128 * 128);
   std::printf("host replay: %d random contractions + workload shapes, %lld checks (%lld global-to-LDS long-K"
-              " plans), %d failures\n", done, static_cast<long long>(g_checks), static_cast<long long>(g_tallk_dma),
-              g_failures);
+              " plans, %lld with K-major A for global-to-LDS tiles), %d failures\n", done,
+              static_cast<long long>(g_checks), static_cast<long long>(g_tallk_dma),
+              static_cast<long long>(g_at_dma), g_failures);
   return g_failures == 0 ? 0 : 1;
 }
