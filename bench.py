@@ -153,9 +153,10 @@ def time_workload(P, SG, wl, compute, steps, warmup, grad=False, cplx=False):
 
     With grad, the backward of every step is two contractions of the forward's
     size (dU and dV), so the step does three times the forward's flops.
-    Warm-up runs at least `warmup` steps and at least 50 ms (clocks ramp up
-    after host-side idle); the figure is the median of three timed batches of
-    at least `steps` steps and 10 ms each.
+    Warm-up runs at least `warmup` steps and at least 0.5 s (the device's clocks
+    ramp up over tens of milliseconds after host-side idle: a bond-128 chain
+    step runs about 15% longer in its first 30 ms of work); the figure is the
+    median of three timed batches of at least `steps` steps and 50 ms each.
     """
     import torch
     dt = torch.float64 if compute == "f64" else torch.float32
@@ -186,11 +187,11 @@ def time_workload(P, SG, wl, compute, steps, warmup, grad=False, cplx=False):
         torch.cuda.synchronize()
         return time.perf_counter() - t0
     n, spent = 0, 0.0
-    while n < warmup or spent < 0.05:
+    while n < warmup or spent < 0.5:
         spent += run(1)
         n += 1
     per = spent / n
-    batch = max(steps, int(0.01 / max(per, 1e-6)) + 1)
+    batch = max(steps, int(0.05 / max(per, 1e-6)) + 1)
     ms = sorted(run(batch) * 1e3 / batch for _ in range(3))[1]
     return {"ms_per_step": round(ms, 4), "tflops": round(flops / (ms * 1e-3) / 1e12, 2),
             "flops_per_step": flops, "steps_per_batch": batch}
