@@ -66,13 +66,19 @@ constexpr int row_groups() {
 // TR: the MFMA computes the transposed tile (B^T A^T), so that each lane's
 // accumulators hold one row of C and a store instruction writes 16 consecutive
 // rows (for a W whose rows, not columns, are its contiguous index).
-template <typename T, int KS, int TN, bool TR>
-__global__ __launch_bounds__(64 * kRowWaves) void k_gemm_rows(
+// RV > 1 (A's rows contiguous in aligned runs of RV, as where U's output modes
+// trail: A read K-major): lane r of a 16 x RV-row group loads rows RV r ..
+// RV r + RV - 1 of one K index with one 16-byte load and feeds them to RV
+// MFMAs, whose output row p then stands for row RV p + t of the group.
+template <typename T, int KS, int TN, bool TR, int RV = 1>
+__global__ __launch_bounds__(64 * kRowWaves, (RV > 1 ? 2 : 1)) void k_gemm_rows(
     const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C, int M, int N, int K,
     const int64_t* __restrict__ ra, const int64_t* __restrict__ ca, const int64_t* __restrict__ rb,
     const int64_t* __restrict__ cb, const int64_t* __restrict__ rc, const int64_t* __restrict__ cc) {
   using Acc = typename RowMfma<T>::Acc;
-  constexpr int kRowGroups = row_groups<T, KS, TN>();
+  static_assert(RV == 1 || (!TR && RV * sizeof(T) == 16), "row vectors: 16 bytes, lanes along columns");
+  constexpr int kRowGroups = RV > 1 ? 1 : row_groups<T, KS, TN>();
+  constexpr int NG = kRowGroups * RV;            // 16-row MFMA groups per block
   constexpr int KP = 4 * KS;
   constexpr int NP = 16 * TN;
   // B rows padded so that the four k-rows of one operand read start 16 * sizeof(T)
@@ -111,35 +117,43 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_gemm_rows(
       ccol[j][r] = col < N ? (cc ? cc[q * N + col] : static_cast<int64_t>(col)) : -1;
     }
   const int kq = lane >> 4;                      // k index within each K-step
-  const int64_t blocks = (M + 16 * kRowGroups - 1) / (16 * kRowGroups);
+  const int64_t blocks = (M + 16 * NG - 1) / (16 * NG);
   const int64_t step = static_cast<int64_t>(gridDim.x) * kRowWaves;
   // Row offsets of block b's A rows (this lane's row of each 16-row group) and
   // of its C rows (this lane's accumulator rows; -1 past M).
   auto a_rows = [&](int64_t b, int64_t (&rbase)[kRowGroups]) {
 #pragma unroll
     for (int i = 0; i < kRowGroups; ++i) {
-      const int m = min(static_cast<int>(b * 16 * kRowGroups) + i * 16 + (lane & 15), M - 1);
+      const int m = min(static_cast<int>(b * 16 * NG) + i * 16 * RV + RV * (lane & 15), M - RV);
       rbase[i] = ra ? ra[q * M + m] : (q * M + m) * static_cast<int64_t>(K);
     }
   };
   constexpr int NR = TR ? 1 : 4;                 // C rows per lane and row group
-  auto c_rows = [&](int64_t b, int64_t (&crow)[kRowGroups][NR]) {
+  auto c_rows = [&](int64_t b, int64_t (&crow)[NG][NR]) {
 #pragma unroll
-    for (int i = 0; i < kRowGroups; ++i)
+    for (int g = 0; g < NG; ++g)
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        const int row = static_cast<int>(b * 16 * kRowGroups) + i * 16 + (TR ? (lane & 15) : RowMfma<T>::row(lane, r));
-        crow[i][r] = row < M ? (rc ? rc[q * M + row] : (q * M + row) * static_cast<int64_t>(N)) : -1;
+        const int i = g / RV, t = g % RV;
+        const int row = static_cast<int>(b * 16 * NG) + i * 16 * RV +
+                        (TR ? (lane & 15) : RV * RowMfma<T>::row(lane, r) + t);
+        crow[g][r] = row < M ? (rc ? rc[q * M + row] : (q * M + row) * static_cast<int64_t>(N)) : -1;
       }
   };
-  // A: lane (r, kq) of group i holds A[m0 + 16 i + r][4 s + kq] for every step s
-  auto load_a = [&](const int64_t (&rbase)[kRowGroups], T (&a)[kRowGroups][KS]) {
+  // A: lane (r, kq) of group i holds A[m0 + 16 RV i + RV r + t][4 s + kq], t < RV, for every step s
+  using AV = VecT<T, RV>;
+  auto load_a = [&](const int64_t (&rbase)[kRowGroups], AV (&a)[kRowGroups][KS]) {
 #pragma unroll
     for (int i = 0; i < kRowGroups; ++i)
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
         const int k = 4 * s + kq;
-        a[i][s] = k < K ? A[rbase[i] + cols_a[k]] : T(0);
+        if (k < K) {
+          a[i][s] = *reinterpret_cast<const AV*>(A + rbase[i] + cols_a[k]);
+        } else {
+#pragma unroll
+          for (int t = 0; t < RV; ++t) a[i][s].v[t] = T(0);
+        }
       }
   };
   int64_t blk = static_cast<int64_t>(blockIdx.x) * kRowWaves + wave;
@@ -147,42 +161,44 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_gemm_rows(
   // Loads run ahead: A one block ahead, its row offsets two blocks ahead, and
   // each block's C row offsets before its products, so no table read waits on
   // the critical path (the loads complete in issue order).
-  T a[kRowGroups][KS], an[kRowGroups][KS];
+  AV a[kRowGroups][KS], an[kRowGroups][KS];
   int64_t r1[kRowGroups], r2[kRowGroups];
   a_rows(blk, r1);
   load_a(r1, a);
   if (blk + step < blocks) a_rows(blk + step, r1);
   for (; blk < blocks; blk += step) {
-    int64_t crow[kRowGroups][NR];
+    int64_t crow[NG][NR];
     c_rows(blk, crow);
     const bool more = blk + step < blocks;
     if (blk + 2 * step < blocks) a_rows(blk + 2 * step, r2);
     if (more) load_a(r1, an);
-    Acc acc[kRowGroups][TN];
+    Acc acc[NG][TN];
 #pragma unroll
-    for (int i = 0; i < kRowGroups; ++i)
+    for (int g = 0; g < NG; ++g)
 #pragma unroll
-      for (int j = 0; j < TN; ++j) acc[i][j] = Acc{};
+      for (int j = 0; j < TN; ++j) acc[g][j] = Acc{};
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const T b = Bs[4 * s + kq][j * 16 + (lane & 15)];
 #pragma unroll
-        for (int i = 0; i < kRowGroups; ++i)
-          acc[i][j] = TR ? RowMfma<T>::run(b, a[i][s], acc[i][j]) : RowMfma<T>::run(a[i][s], b, acc[i][j]);
+        for (int g = 0; g < NG; ++g) {
+          const T av = a[g / RV][s].v[g % RV];
+          acc[g][j] = TR ? RowMfma<T>::run(b, av, acc[g][j]) : RowMfma<T>::run(av, b, acc[g][j]);
+        }
       }
     }
 #pragma unroll
-    for (int i = 0; i < kRowGroups; ++i)
+    for (int g = 0; g < NG; ++g)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t cr = crow[i][TR ? 0 : r];
+        const int64_t cr = crow[g][TR ? 0 : r];
         if (cr < 0) continue;
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
           const int64_t cc_ = ccol[j][TR ? r : 0];
-          if (cc_ >= 0) C[cr + cc_] = acc[i][j][r];
+          if (cc_ >= 0) C[cr + cc_] = acc[g][j][r];
         }
       }
     if (more) {
@@ -196,7 +212,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_gemm_rows(
   }
 }
 
-template <typename T, int KS, int TN, bool TR>
+template <typename T, int KS, int TN, bool TR, int RV>
 hipError_t launch_ks_tn(int64_t batch, int M, int N, int K, const T* A, const T* B, T* C, hipStream_t s,
                         const FusedTables* f) {
   const int64_t* ra = f ? f->ra : nullptr;
@@ -210,7 +226,7 @@ hipError_t launch_ks_tn(int64_t batch, int M, int N, int K, const T* A, const T*
   // loads in flight
   static const int resident = [] {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm_rows<T, KS, TN, TR>, 64 * kRowWaves, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm_rows<T, KS, TN, TR, RV>, 64 * kRowWaves, 0) !=
             hipSuccess ||
         per_cu < 1) {
       (void)hipGetLastError();
@@ -218,23 +234,36 @@ hipError_t launch_ks_tn(int64_t batch, int M, int N, int K, const T* A, const T*
     }
     return per_cu * 256;
   }();
-  constexpr int rows = 16 * row_groups<T, KS, TN>();
+  constexpr int rows = RV > 1 ? 16 * RV : 16 * row_groups<T, KS, TN>();
   const int64_t blocks = (M + rows - 1) / rows;
   const int64_t want = std::max<int64_t>(1, resident / std::max<int64_t>(batch, 1));
   const unsigned gx = static_cast<unsigned>(std::min<int64_t>((blocks + kRowWaves - 1) / kRowWaves, want));
-  hipLaunchKernelGGL((k_gemm_rows<T, KS, TN, TR>), dim3(gx, static_cast<unsigned>(batch)), dim3(64 * kRowWaves), 0,
-                     s, A, B, C, M, N, K, ra, ca, rb, cb, rc, cc);
+  hipLaunchKernelGGL((k_gemm_rows<T, KS, TN, TR, RV>), dim3(gx, static_cast<unsigned>(batch)), dim3(64 * kRowWaves),
+                     0, s, A, B, C, M, N, K, ra, ca, rb, cb, rc, cc);
   return hipGetLastError();
 }
 
 template <typename T, int KS, bool TR>
 hipError_t launch_ks(int tn, int64_t batch, int M, int N, int K, const T* A, const T* B, T* C, hipStream_t s,
                      const FusedTables* f) {
+  // K-major A whose output-mode runs hold 16-byte chunks (f->vec > 1 then): row
+  // vectors, binary32 only (four rows per load; binary64's pairs measured no faster)
+  constexpr int VE = static_cast<int>(16 / sizeof(T));
+  if constexpr (!TR && sizeof(T) == 4) {
+    if (f && f->at && f->vec > 1 && M % VE == 0) {
+      switch (tn) {
+        case 1: return launch_ks_tn<T, KS, 1, TR, VE>(batch, M, N, K, A, B, C, s, f);
+        case 2: return launch_ks_tn<T, KS, 2, TR, VE>(batch, M, N, K, A, B, C, s, f);
+        case 3: return launch_ks_tn<T, KS, 3, TR, VE>(batch, M, N, K, A, B, C, s, f);
+        default: return launch_ks_tn<T, KS, 4, TR, VE>(batch, M, N, K, A, B, C, s, f);
+      }
+    }
+  }
   switch (tn) {
-    case 1: return launch_ks_tn<T, KS, 1, TR>(batch, M, N, K, A, B, C, s, f);
-    case 2: return launch_ks_tn<T, KS, 2, TR>(batch, M, N, K, A, B, C, s, f);
-    case 3: return launch_ks_tn<T, KS, 3, TR>(batch, M, N, K, A, B, C, s, f);
-    default: return launch_ks_tn<T, KS, 4, TR>(batch, M, N, K, A, B, C, s, f);
+    case 1: return launch_ks_tn<T, KS, 1, TR, 1>(batch, M, N, K, A, B, C, s, f);
+    case 2: return launch_ks_tn<T, KS, 2, TR, 1>(batch, M, N, K, A, B, C, s, f);
+    case 3: return launch_ks_tn<T, KS, 3, TR, 1>(batch, M, N, K, A, B, C, s, f);
+    default: return launch_ks_tn<T, KS, 4, TR, 1>(batch, M, N, K, A, B, C, s, f);
   }
 }
 

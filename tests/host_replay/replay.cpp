@@ -367,8 +367,10 @@ void check_bijection(const std::vector<int64_t>& R, const std::vector<int64_t>& 
 void replay_rows(int64_t resident, int64_t batch, int64_t M, int64_t N, int64_t K, const std::vector<int64_t>& ra,
                  const std::vector<int64_t>& ca, const std::vector<int64_t>& rb, const std::vector<int64_t>& cb,
                  const std::vector<int64_t>& rc, const std::vector<int64_t>& cc, int64_t a_n, int64_t b_n,
-                 int64_t c_n, int row_groups, bool trans) {
-  const int waves = 4, rows = 16 * row_groups;
+                 int64_t c_n, int row_groups, bool trans, int rv = 1) {
+  // (rv > 1: lane r of a 16 rv-row group loads rows rv r .. rv r + rv - 1 of one K
+  // index with one vector load; MFMA output row p of vector element t is row rv p + t)
+  const int waves = 4, rows = 16 * row_groups * rv;
   const int64_t ks = (K + 3) / 4, tn = (N + 15) / 16;
   const int64_t blocks = (M + rows - 1) / rows;
   const int64_t want = std::max<int64_t>(1, resident / std::max<int64_t>(batch, 1));
@@ -386,20 +388,28 @@ void replay_rows(int64_t resident, int64_t batch, int64_t M, int64_t N, int64_t 
         for (int64_t blk = x * waves + w; blk < blocks; blk += gx * waves) {
           const int64_t m0 = blk * rows;
           for (int lane = 0; lane < 64; ++lane) {
-            for (int i = 0; i < row_groups; ++i) {
-              const int64_t m = std::min<int64_t>(m0 + i * 16 + (lane & 15), M - 1);
+            for (int g = 0; g < row_groups * rv; ++g) {
+              const int i = g / rv, t = g % rv;
+              const int64_t m = std::min<int64_t>(m0 + i * 16 * rv + rv * (lane & 15), M - rv);
               const int64_t rbase = ra.empty() ? (q * M + m) * K : ra[q * M + m];
-              for (int64_t st = 0; st < ks; ++st) {
+              if (rv > 1 && t == 0) {
+                CHECK(M % rv == 0 && rbase % rv == 0, "row vector of A misaligned", m, rbase);
+                for (int u = 1; u < rv; ++u)
+                  CHECK(ra[q * M + m + u] == rbase + u, "row vector of A not contiguous", m, u);
+              }
+              for (int64_t st = 0; st < ks && t == 0; ++st) {
                 const int64_t k = 4 * st + (lane >> 4);
                 if (k >= K) continue;
                 const int64_t a = rbase + (ca.empty() ? k : ca[q * K + k]);
-                CHECK(a >= 0 && a < a_n, "row product A read out of bounds", a, a_n);
+                CHECK(a >= 0 && a + rv <= a_n, "row product A read out of bounds", a, a_n);
+                CHECK(a % rv == 0, "row vector load of A misaligned", a, rv);
               }
               // stores: both accumulator row layouts cover rows m0 + 16 i + 0..15
-              // (trans: the lane's row is lane % 16, its columns those rows)
+              // (trans: the lane's row is lane % 16, its columns those rows; rv > 1:
+              // MFMA output row p of vector element t is row rv p + t)
               for (int r = 0; r < 4; ++r) {
                 const int64_t acc_row = (lane >> 4) + 4 * r;
-                const int64_t row = m0 + i * 16 + (trans ? (lane & 15) : acc_row);
+                const int64_t row = m0 + i * 16 * rv + (trans ? (lane & 15) : rv * acc_row + t);
                 if (row >= M) continue;
                 const int64_t crow = rc.empty() ? (q * M + row) * N : rc[q * M + row];
                 for (int64_t j = 0; j < tn; ++j) {
@@ -509,6 +519,7 @@ int tk_bswz_host(int elem, int np, int k) {
 
 int64_t g_tallk_dma = 0;   // plans whose long-K product takes the global-to-LDS variant
 int64_t g_at_dma = 0;      // plans whose product can read K-major A on global-to-LDS tiles
+int64_t g_row_vec = 0;     // plans whose row-streaming product loads row vectors of K-major A
 
 void replay_tallk_dma(int elem, int64_t batch, int64_t M, int64_t N, int64_t K, const std::vector<int64_t>& ra,
                       const std::vector<int64_t>& ca, const std::vector<int64_t>& rb, const std::vector<int64_t>& cb,
@@ -622,6 +633,14 @@ void check_fused(const Plan& p) {
         for (bool trans : {false, true})
           replay_rows(resident, G, p.M, p.gn, p.gk, ra, ca, p.fused_b ? rb : none, p.fused_b ? cb : none, rc, cc,
                       p.fused_ua ? G * p.M * p.gk : p.U.elems * cm, b_n, p.W.elems * cm, rg, trans);
+    // binary32 K-major A with 16-byte chunks along M: row vectors of 4 (one row group)
+    const int vwr = 4;
+    if (p.compute == SYMT_COMPUTE_F32 && p.a_trans && p.a_chunks && p.M % vwr == 0) {
+      ++g_row_vec;
+      for (int64_t resident : {256, 2048})
+        replay_rows(resident, G, p.M, p.gn, p.gk, ra, ca, p.fused_b ? rb : none, p.fused_b ? cb : none, rc, cc,
+                    p.U.elems * cm, b_n, p.W.elems * cm, 1, false, vwr);
+    }
   }
   if (p.compute == SYMT_COMPUTE_BF16X3) {
     // register tiles split U in registers along 32-deep K-steps of one run
@@ -1058,8 +1077,8 @@ int main(int argc, char** argv) {
       for (int nk : {8, 16, 17, 100, 185193})
         check_split_k(tiles, sp, nk, tiles * sp * 128 * 128, 128 * 128);
   std::printf("host replay: %d random contractions + workload shapes, %lld checks (%lld global-to-LDS long-K"
-              " plans, %lld with K-major A for global-to-LDS tiles), %d failures\n", done,
+              " plans, %lld with K-major A for global-to-LDS tiles, %lld with row vectors), %d failures\n", done,
               static_cast<long long>(g_checks), static_cast<long long>(g_tallk_dma),
-              static_cast<long long>(g_at_dma), g_failures);
+              static_cast<long long>(g_at_dma), static_cast<long long>(g_row_vec), g_failures);
   return g_failures == 0 ? 0 : 1;
 }
