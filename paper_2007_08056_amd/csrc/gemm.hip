@@ -74,8 +74,11 @@ struct Mfma<float> {
 // AT (with FA): A is loaded K-major, as B is: row k0 + r of a K-step at
 // ca[q*K + k0 + r] (any layout of U's contracted modes), V-wide chunks of M at
 // ra[q*M + m] (contiguous runs of U's other modes); the LDS tile is [k][m].
+// ATK (with AT): U's other modes hold no such chunks but its contracted modes
+// end in runs of V: lanes load V consecutive K indices of one row m
+// (ra[q*M + m] + ca[q*K + k] .. + V - 1) and write them down the [k][m] tile.
 template <typename T, int BM, int BN, int BK, int WM, int WN, int V, bool FA, bool FC, bool SPLIT = false,
-          bool AT = false>
+          bool AT = false, bool ATK = false>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
                                                        const T* __restrict__ B,
                                                        T* __restrict__ C, int M, int N, int K,
@@ -131,11 +134,12 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
 
   // Fused A: the standard-form offset of each of this thread's tile rows (AT:
   // of the M chunk it loads in every K-step).
+  static_assert(!ATK || (AT && BK % V == 0), "K vectors of A need K-major A and whole vectors per step");
   int64_t arow[LA];
 #pragma unroll
   for (int i = 0; i < LA; ++i) {
     const int e = (tid + i * NT) * V;
-    const int gr = m0 + (AT ? e % BM : e / BK);
+    const int gr = m0 + (AT && !ATK ? e % BM : e / BK);
     arow[i] = (FA && e < BM * BK && gr < M) ? ra[q * M + gr] : static_cast<int64_t>(gr) * K;
   }
 
@@ -168,7 +172,14 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
       const int e = (tid + i * NT) * V;              // element index inside the BM x BK tile
-      if constexpr (AT) {                            // [k][m]: row r of the step, M chunk c
+      if constexpr (ATK) {                           // row m, K vector c of the step
+        const int m = e / BK, c = e % BK;
+        if (e < BM * BK && m0 + m < M && c < kv)
+          ra_[i] = *reinterpret_cast<const VecT<T, V>*>(Aq + ca[q * K + k0 + c] + arow[i]);
+        else
+#pragma unroll
+          for (int j = 0; j < V; ++j) ra_[i].v[j] = T(0);
+      } else if constexpr (AT) {                     // [k][m]: row r of the step, M chunk c
         const int r = e / BM, c = e % BM;
         if (e < BM * BK && m0 + c < M && r < kv)
           ra_[i] = *reinterpret_cast<const VecT<T, V>*>(Aq + ca[q * K + k0 + r] + arow[i]);
@@ -201,7 +212,11 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(const T* __restrict__ A,
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
       const int e = (tid + i * NT) * V;
-      if constexpr (AT) {
+      if constexpr (ATK) {
+        if (e < BM * BK)
+#pragma unroll
+          for (int j = 0; j < V; ++j) AsT[buf][e % BK + j][e / BK] = ra_[i].v[j];
+      } else if constexpr (AT) {
         if (e < BM * BK) *reinterpret_cast<VecT<T, V>*>(&AsT[buf][e / BM][e % BM]) = ra_[i];
       } else {
         if (e < BM * BK) *reinterpret_cast<VecT<T, V>*>(&As[buf][e / BK][e % BK]) = ra_[i];
@@ -1011,6 +1026,8 @@ hipError_t launch_fp(int vec, int64_t batch, int M, int N, int K, const void* A,
   const int64_t* cc = f ? f->cc : nullptr;
   // one vector width for A and B loads: K and N (and for the fused loads, U's runs) must allow it
   const bool fv = vec > 1 && (!f || f->vec > 1);
+  // K-major A without M chunks, its contracted modes ending in runs of the vector width
+  const bool kv = vec > 1 && f && f->at && !fv && f->a_kvec;
   // split-K only where the workspace holds every partial tile
   if (splits > 1 && (!part || static_cast<size_t>(ntiles) * splits * BM * BN * sizeof(T) > part_bytes)) splits = 1;
   if (splits > 1) {
@@ -1019,6 +1036,10 @@ hipError_t launch_fp(int vec, int64_t batch, int M, int N, int K, const void* A,
     if (f && f->at && fv)
       hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, VV, true, true, true, true>), grid, block, 0, s, a, b, c,
                          M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, splits, f->rb, f->cb, f->ldb,
+                         f->krun);
+    else if (kv)
+      hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, VV, true, true, true, true, true>), grid, block, 0, s, a, b,
+                         c, M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, splits, f->rb, f->cb, f->ldb,
                          f->krun);
     else if (f && f->at)
       hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, 1, true, true, true, true>), grid, block, 0, s, a, b, c,
@@ -1055,6 +1076,10 @@ hipError_t launch_fp(int vec, int64_t batch, int M, int N, int K, const void* A,
   if (f && f->at && fv) {
     hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, VV, true, true, false, true>), grid, block, 0, s, a, b, c,
                        M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, nullptr, 1, f->rb, f->cb, f->ldb, f->krun);
+  } else if (kv) {
+    hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, VV, true, true, false, true, true>), grid, block, 0, s, a, b,
+                       c, M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, nullptr, 1, f->rb, f->cb, f->ldb,
+                       f->krun);
   } else if (f && f->at) {
     hipLaunchKernelGGL((k_gemm<T, BM, BN, BK, WM, WN, 1, true, true, false, true>), grid, block, 0, s, a, b, c,
                        M, N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, nullptr, 1, f->rb, f->cb, f->ldb, f->krun);

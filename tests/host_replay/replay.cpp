@@ -520,6 +520,7 @@ int tk_bswz_host(int elem, int np, int k) {
 int64_t g_tallk_dma = 0;   // plans whose long-K product takes the global-to-LDS variant
 int64_t g_at_dma = 0;      // plans whose product can read K-major A on global-to-LDS tiles
 int64_t g_row_vec = 0;     // plans whose row-streaming product loads row vectors of K-major A
+int64_t g_a_kvec = 0;      // plans whose register tiles load K vectors of K-major A
 
 void replay_tallk_dma(int elem, int64_t batch, int64_t M, int64_t N, int64_t K, const std::vector<int64_t>& ra,
                       const std::vector<int64_t>& ca, const std::vector<int64_t>& rb, const std::vector<int64_t>& cb,
@@ -695,6 +696,18 @@ void check_fused(const Plan& p) {
       for (int64_t m = 0; m < p.M; ++m)
         for (int64_t k = 0; k < p.gk; k += vw)
           CHECK((ra[q * p.M + m] + ca[q * p.gk + k]) % vw == 0, "vector A load misaligned", m, k);
+  if (p.a_trans && !p.a_chunks && !p.cplx && p.u_k_run % vw == 0 && p.gk % vw == 0) {
+    // K-major A without M chunks on register tiles: 16-byte loads along U's trailing
+    // contracted run (rows m, K indices k .. k + vw - 1 at ra(m) + ca(k) + 0 ..)
+    ++g_a_kvec;
+    for (int q = 0; q < G; ++q)
+      for (int64_t k = 0; k < p.gk; k += vw) {
+        for (int j = 1; j < vw; ++j)
+          CHECK(ca[q * p.gk + k + j] == ca[q * p.gk + k] + j, "K vector of A not contiguous", k, j);
+        for (int64_t m = 0; m < p.M; ++m)
+          CHECK((ra[q * p.M + m] + ca[q * p.gk + k]) % vw == 0, "K vector of A misaligned", m, k);
+      }
+  }
   if (p.a_trans && p.a_chunks)
     for (int q = 0; q < G; ++q)
       for (int64_t m = 0; m < p.M; m += vw) {
@@ -1077,8 +1090,9 @@ int main(int argc, char** argv) {
       for (int nk : {8, 16, 17, 100, 185193})
         check_split_k(tiles, sp, nk, tiles * sp * 128 * 128, 128 * 128);
   std::printf("host replay: %d random contractions + workload shapes, %lld checks (%lld global-to-LDS long-K"
-              " plans, %lld with K-major A for global-to-LDS tiles, %lld with row vectors), %d failures\n", done,
-              static_cast<long long>(g_checks), static_cast<long long>(g_tallk_dma),
-              static_cast<long long>(g_at_dma), static_cast<long long>(g_row_vec), g_failures);
+              " plans, %lld with K-major A for global-to-LDS tiles, %lld with row vectors, %lld with K vectors of K-major"
+              " A), %d failures\n", done, static_cast<long long>(g_checks), static_cast<long long>(g_tallk_dma),
+              static_cast<long long>(g_at_dma), static_cast<long long>(g_row_vec), static_cast<long long>(g_a_kvec),
+              g_failures);
   return g_failures == 0 ? 0 : 1;
 }

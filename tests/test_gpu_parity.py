@@ -550,6 +550,8 @@ UA_CASES = [
     ("klab,klij->abij", (2,), "--++", "++--", (4, 8, 16, 16), (4, 8, 16, 16)),  # 512 x 64 x 512
     # the chain's E' = T2 A: M chunks of 4 (B) under a strided K (c, S)
     ("cASB,cSC->ABC", (2, 3), "----", "++-", (8, 8, 2, 4), (8, 2, 8)),
+    # the chain's dA = T2 dE': no M chunks (S strided), K = (A, B) ending in runs of 4 (B)
+    ("cASB,ABC->cSC", (2, 3), "----", "---", (8, 8, 2, 4), (8, 4, 8)),
 ]
 
 
