@@ -16,8 +16,9 @@
 // Operands are addressed through separable offset tables, so the same kernel
 // reads A from U's standard form (row offsets ra, column offsets ca, any
 // layout of U's modes), B from V's (rb, cb) and writes C into W's (rc, cc);
-// a null table stands for the aligned row-major form.  K is summed in order,
-// four indices per MFMA (v_mfma_f64_16x16x4_f64, v_mfma_f32_16x16x4_f32).
+// a null table stands for the aligned row-major form.  K is summed four
+// indices per MFMA (v_mfma_f64_16x16x4_f64, v_mfma_f32_16x16x4_f32): in order in
+// binary64, in a fixed order within groups of 16 in binary32 (see below).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -70,7 +71,12 @@ constexpr int row_groups() {
 // trail: A read K-major): lane r of a 16 x RV-row group loads rows RV r ..
 // RV r + RV - 1 of one K index with one 16-byte load and feeds them to RV
 // MFMAs, whose output row p then stands for row RV p + t of the group.
-template <typename T, int KS, int TN, bool TR, int RV = 1>
+// Binary32 steps through K in groups of 16: K-step 4 u + t takes index
+// 16 u + 4 kq + t at lane group kq (the same sums as 4 s + kq, permuted within
+// each group, in every variant); KV = 4 (A's K index contiguous in aligned
+// runs of 4): lane (r, kq) loads the four indices 16 u + 4 kq .. + 3 of its row
+// with one 16-byte load for K-steps 4 u .. 4 u + 3.
+template <typename T, int KS, int TN, bool TR, int RV = 1, int KV = 1>
 __global__ __launch_bounds__(64 * kRowWaves, (RV > 1 ? 2 : 1)) void k_gemm_rows(
     const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C, int M, int N, int K,
     const int64_t* __restrict__ ra, const int64_t* __restrict__ ca, const int64_t* __restrict__ rb,
@@ -141,20 +147,42 @@ __global__ __launch_bounds__(64 * kRowWaves, (RV > 1 ? 2 : 1)) void k_gemm_rows(
       }
   };
   // A: lane (r, kq) of group i holds A[m0 + 16 RV i + RV r + t][4 s + kq], t < RV, for every step s
+  static_assert(KV == 1 || (RV == 1 && KV * sizeof(T) == 16 && KS % KV == 0), "K vectors: 16 bytes");
+  // K index of (step s, lane group kq): binary64 4 s + kq; binary32 16 (s / 4) + 4 kq + s % 4
+  constexpr int KO = sizeof(T) == 4 ? 4 : 1;
+  static_assert(KS % KO == 0, "whole groups of K-steps");
+  auto kidx = [&](int s) { return KO > 1 ? 4 * KO * (s / KO) + KO * kq + s % KO : 4 * s + kq; };
   using AV = VecT<T, RV>;
   auto load_a = [&](const int64_t (&rbase)[kRowGroups], AV (&a)[kRowGroups][KS]) {
 #pragma unroll
-    for (int i = 0; i < kRowGroups; ++i)
+    for (int i = 0; i < kRowGroups; ++i) {
+      if constexpr (KV > 1) {
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const int k = 4 * s + kq;
-        if (k < K) {
-          a[i][s] = *reinterpret_cast<const AV*>(A + rbase[i] + cols_a[k]);
-        } else {
+        for (int u = 0; u < KS / KV; ++u) {
+          const int k = kidx(KV * u);
+          VecT<T, KV> x;
+          if (k < K) {
+            x = *reinterpret_cast<const VecT<T, KV>*>(A + rbase[i] + cols_a[k]);
+          } else {
 #pragma unroll
-          for (int t = 0; t < RV; ++t) a[i][s].v[t] = T(0);
+            for (int t = 0; t < KV; ++t) x.v[t] = T(0);
+          }
+#pragma unroll
+          for (int t = 0; t < KV; ++t) a[i][KV * u + t].v[0] = x.v[t];
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const int k = kidx(s);
+          if (k < K) {
+            a[i][s] = *reinterpret_cast<const AV*>(A + rbase[i] + cols_a[k]);
+          } else {
+#pragma unroll
+            for (int t = 0; t < RV; ++t) a[i][s].v[t] = T(0);
+          }
         }
       }
+    }
   };
   int64_t blk = static_cast<int64_t>(blockIdx.x) * kRowWaves + wave;
   if (blk >= blocks) return;
@@ -181,7 +209,7 @@ __global__ __launch_bounds__(64 * kRowWaves, (RV > 1 ? 2 : 1)) void k_gemm_rows(
     for (int s = 0; s < KS; ++s) {
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
-        const T b = Bs[4 * s + kq][j * 16 + (lane & 15)];
+        const T b = Bs[kidx(s)][j * 16 + (lane & 15)];
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
           const T av = a[g / RV][s].v[g % RV];
@@ -212,7 +240,7 @@ __global__ __launch_bounds__(64 * kRowWaves, (RV > 1 ? 2 : 1)) void k_gemm_rows(
   }
 }
 
-template <typename T, int KS, int TN, bool TR, int RV>
+template <typename T, int KS, int TN, bool TR, int RV, int KV = 1>
 hipError_t launch_ks_tn(int64_t batch, int M, int N, int K, const T* A, const T* B, T* C, hipStream_t s,
                         const FusedTables* f) {
   const int64_t* ra = f ? f->ra : nullptr;
@@ -226,7 +254,7 @@ hipError_t launch_ks_tn(int64_t batch, int M, int N, int K, const T* A, const T*
   // loads in flight
   static const int resident = [] {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm_rows<T, KS, TN, TR, RV>, 64 * kRowWaves, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm_rows<T, KS, TN, TR, RV, KV>, 64 * kRowWaves, 0) !=
             hipSuccess ||
         per_cu < 1) {
       (void)hipGetLastError();
@@ -238,7 +266,7 @@ hipError_t launch_ks_tn(int64_t batch, int M, int N, int K, const T* A, const T*
   const int64_t blocks = (M + rows - 1) / rows;
   const int64_t want = std::max<int64_t>(1, resident / std::max<int64_t>(batch, 1));
   const unsigned gx = static_cast<unsigned>(std::min<int64_t>((blocks + kRowWaves - 1) / kRowWaves, want));
-  hipLaunchKernelGGL((k_gemm_rows<T, KS, TN, TR, RV>), dim3(gx, static_cast<unsigned>(batch)), dim3(64 * kRowWaves),
+  hipLaunchKernelGGL((k_gemm_rows<T, KS, TN, TR, RV, KV>), dim3(gx, static_cast<unsigned>(batch)), dim3(64 * kRowWaves),
                      0, s, A, B, C, M, N, K, ra, ca, rb, cb, rc, cc);
   return hipGetLastError();
 }
@@ -256,6 +284,19 @@ hipError_t launch_ks(int tn, int64_t batch, int M, int N, int K, const T* A, con
         case 2: return launch_ks_tn<T, KS, 2, TR, VE>(batch, M, N, K, A, B, C, s, f);
         case 3: return launch_ks_tn<T, KS, 3, TR, VE>(batch, M, N, K, A, B, C, s, f);
         default: return launch_ks_tn<T, KS, 4, TR, VE>(batch, M, N, K, A, B, C, s, f);
+      }
+    }
+  }
+  // A's K index contiguous in aligned runs of 16 bytes (U_al, or U's trailing
+  // contracted block: f->vec > 1 then): K vectors, binary32 only
+  if constexpr (sizeof(T) == 4 && KS % VE == 0) {
+    if ((!f || (!f->at && f->vec > 1 && f->krun == 0)) && K % VE == 0 &&
+        (reinterpret_cast<uintptr_t>(A) & 15) == 0) {
+      switch (tn) {
+        case 1: return launch_ks_tn<T, KS, 1, TR, 1, VE>(batch, M, N, K, A, B, C, s, f);
+        case 2: return launch_ks_tn<T, KS, 2, TR, 1, VE>(batch, M, N, K, A, B, C, s, f);
+        case 3: return launch_ks_tn<T, KS, 3, TR, 1, VE>(batch, M, N, K, A, B, C, s, f);
+        default: return launch_ks_tn<T, KS, 4, TR, 1, VE>(batch, M, N, K, A, B, C, s, f);
       }
     }
   }

@@ -367,7 +367,7 @@ void check_bijection(const std::vector<int64_t>& R, const std::vector<int64_t>& 
 void replay_rows(int64_t resident, int64_t batch, int64_t M, int64_t N, int64_t K, const std::vector<int64_t>& ra,
                  const std::vector<int64_t>& ca, const std::vector<int64_t>& rb, const std::vector<int64_t>& cb,
                  const std::vector<int64_t>& rc, const std::vector<int64_t>& cc, int64_t a_n, int64_t b_n,
-                 int64_t c_n, int row_groups, bool trans, int rv = 1) {
+                 int64_t c_n, int row_groups, bool trans, int rv = 1, int kv = 1, int ko = 1) {
   // (rv > 1: lane r of a 16 rv-row group loads rows rv r .. rv r + rv - 1 of one K
   // index with one vector load; MFMA output row p of vector element t is row rv p + t)
   const int waves = 4, rows = 16 * row_groups * rv;
@@ -398,11 +398,16 @@ void replay_rows(int64_t resident, int64_t batch, int64_t M, int64_t N, int64_t 
                   CHECK(ra[q * M + m + u] == rbase + u, "row vector of A not contiguous", m, u);
               }
               for (int64_t st = 0; st < ks && t == 0; ++st) {
-                const int64_t k = 4 * st + (lane >> 4);
+                // (kv > 1: one vector of kv K indices per group of kv steps)
+                // (ko > 1: binary32's K order, 4 ko (st / ko) + ko kq + st % ko)
+                if (kv > 1 && st % kv != 0) continue;
+                const int64_t k = ko > 1 ? 4 * ko * (st / ko) + ko * (lane >> 4) + st % ko : 4 * st + (lane >> 4);
                 if (k >= K) continue;
                 const int64_t a = rbase + (ca.empty() ? k : ca[q * K + k]);
-                CHECK(a >= 0 && a + rv <= a_n, "row product A read out of bounds", a, a_n);
-                CHECK(a % rv == 0, "row vector load of A misaligned", a, rv);
+                CHECK(a >= 0 && a + rv * kv <= a_n, "row product A read out of bounds", a, a_n);
+                CHECK(a % (rv * kv) == 0, "vector load of A misaligned", a, rv * kv);
+                for (int j = 1; j < kv && !ca.empty(); ++j)
+                  CHECK(ca[q * K + k + j] == ca[q * K + k] + j, "K vector of A not contiguous", k, j);
               }
               // stores: both accumulator row layouts cover rows m0 + 16 i + 0..15
               // (trans: the lane's row is lane % 16, its columns those rows; rv > 1:
@@ -521,6 +526,7 @@ int64_t g_tallk_dma = 0;   // plans whose long-K product takes the global-to-LDS
 int64_t g_at_dma = 0;      // plans whose product can read K-major A on global-to-LDS tiles
 int64_t g_row_vec = 0;     // plans whose row-streaming product loads row vectors of K-major A
 int64_t g_a_kvec = 0;      // plans whose register tiles load K vectors of K-major A
+int64_t g_k_vec = 0;       // plans whose row-streaming product loads K vectors of A
 
 void replay_tallk_dma(int elem, int64_t batch, int64_t M, int64_t N, int64_t K, const std::vector<int64_t>& ra,
                       const std::vector<int64_t>& ca, const std::vector<int64_t>& rb, const std::vector<int64_t>& cb,
@@ -633,14 +639,23 @@ void check_fused(const Plan& p) {
       for (int64_t resident : {256, 512, 2048})
         for (bool trans : {false, true})
           replay_rows(resident, G, p.M, p.gn, p.gk, ra, ca, p.fused_b ? rb : none, p.fused_b ? cb : none, rc, cc,
-                      p.fused_ua ? G * p.M * p.gk : p.U.elems * cm, b_n, p.W.elems * cm, rg, trans);
+                      p.fused_ua ? G * p.M * p.gk : p.U.elems * cm, b_n, p.W.elems * cm, rg, trans, 1, 1,
+                      p.compute == SYMT_COMPUTE_F32 ? 4 : 1);
+    // binary32 A with its K index contiguous in aligned runs of 4: K vectors
+    const int64_t krun_a = p.fused_ua ? p.gk : p.nK;
+    if (p.compute == SYMT_COMPUTE_F32 && !p.a_trans && !p.cplx && p.krun == 0 && krun_a % 4 == 0 && p.gk % 4 == 0) {
+      ++g_k_vec;
+      for (bool trans : {false, true})
+        replay_rows(512, G, p.M, p.gn, p.gk, ra, ca, p.fused_b ? rb : none, p.fused_b ? cb : none, rc, cc,
+                    p.fused_ua ? G * p.M * p.gk : p.U.elems * cm, b_n, p.W.elems * cm, 2, trans, 1, 4, 4);
+    }
     // binary32 K-major A with 16-byte chunks along M: row vectors of 4 (one row group)
     const int vwr = 4;
     if (p.compute == SYMT_COMPUTE_F32 && p.a_trans && p.a_chunks && p.M % vwr == 0) {
       ++g_row_vec;
       for (int64_t resident : {256, 2048})
         replay_rows(resident, G, p.M, p.gn, p.gk, ra, ca, p.fused_b ? rb : none, p.fused_b ? cb : none, rc, cc,
-                    p.U.elems * cm, b_n, p.W.elems * cm, 1, false, vwr);
+                    p.U.elems * cm, b_n, p.W.elems * cm, 1, false, vwr, 1, 4);
     }
   }
   if (p.compute == SYMT_COMPUTE_BF16X3) {
@@ -1091,8 +1106,8 @@ int main(int argc, char** argv) {
         check_split_k(tiles, sp, nk, tiles * sp * 128 * 128, 128 * 128);
   std::printf("host replay: %d random contractions + workload shapes, %lld checks (%lld global-to-LDS long-K"
               " plans, %lld with K-major A for global-to-LDS tiles, %lld with row vectors, %lld with K vectors of K-major"
-              " A), %d failures\n", done, static_cast<long long>(g_checks), static_cast<long long>(g_tallk_dma),
-              static_cast<long long>(g_at_dma), static_cast<long long>(g_row_vec), static_cast<long long>(g_a_kvec),
-              g_failures);
+              " A, %lld with K vectors on rows), %d failures\n", done, static_cast<long long>(g_checks),
+              static_cast<long long>(g_tallk_dma), static_cast<long long>(g_at_dma), static_cast<long long>(g_row_vec),
+              static_cast<long long>(g_a_kvec), static_cast<long long>(g_k_vec), g_failures);
   return g_failures == 0 ? 0 : 1;
 }
