@@ -288,9 +288,9 @@ hipError_t launch_ks(int tn, int64_t batch, int M, int N, int K, const T* A, con
     }
   }
   // A's K index contiguous in aligned runs of 16 bytes (U_al, or U's trailing
-  // contracted block: f->vec > 1 then): K vectors, binary32 only
+  // contracted block): K vectors, binary32 only
   if constexpr (sizeof(T) == 4 && KS % VE == 0) {
-    if ((!f || (!f->at && f->vec > 1 && f->krun == 0)) && K % VE == 0 &&
+    if ((!f || !f->ra || f->a_krow) && K % VE == 0 &&
         (reinterpret_cast<uintptr_t>(A) & 15) == 0) {
       switch (tn) {
         case 1: return launch_ks_tn<T, KS, 1, TR, 1, VE>(batch, M, N, K, A, B, C, s, f);

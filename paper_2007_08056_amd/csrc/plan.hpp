@@ -147,6 +147,7 @@ struct FusedTables {
   int32_t c_rows4 = 0;              // 1: W's rows in contiguous runs of a multiple of 4 elements
   int32_t a_kvec = 0;               // 1 (K-major A without M chunks): U 16-byte aligned, its contracted
                                     //    modes ending in runs of 16 bytes, B's loads vectors too
+  int32_t a_krow = 0;               // 1 (A not K-major): A's K index contiguous in 16-byte aligned runs
   int32_t k_groups = 0;             // 1: every 16-deep group of K lies in one run of A's rows and one
                                     //    affine run of B's rows, B's columns in 16-byte chunks (long-K)
 };

@@ -338,6 +338,10 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
   // W's rows contiguous in runs of 4k elements: binary32 tiles store 4 rows per lane
   f.c_rows4 = !p.cplx && p.w_row_run % 4 == 0 ? 1 : 0;
   // K-major A without M chunks: 16-byte loads along U's trailing contracted run instead
+  // A not K-major, its K runs whole 16-byte vectors (whatever B's layout)
+  // (K stepped run by run is the register tiles' concern; the row-streaming
+  // product reads each K index through its own table entry)
+  f.a_krow = !p.a_trans && !p.cplx && (p.fused_ua || aligned16(p.U.data)) && run % vw == 0 ? 1 : 0;
   f.a_kvec = p.a_trans && !p.cplx && !p.a_chunks && aligned16(p.U.data) && p.u_k_run % vw == 0 &&
                      (!fb || (aligned16(p.V.data) && p.fused_b_chunks))
                  ? 1

@@ -643,7 +643,7 @@ void check_fused(const Plan& p) {
                       p.compute == SYMT_COMPUTE_F32 ? 4 : 1);
     // binary32 A with its K index contiguous in aligned runs of 4: K vectors
     const int64_t krun_a = p.fused_ua ? p.gk : p.nK;
-    if (p.compute == SYMT_COMPUTE_F32 && !p.a_trans && !p.cplx && p.krun == 0 && krun_a % 4 == 0 && p.gk % 4 == 0) {
+    if (p.compute == SYMT_COMPUTE_F32 && !p.a_trans && !p.cplx && krun_a % 4 == 0 && p.gk % 4 == 0) {
       ++g_k_vec;
       for (bool trans : {false, true})
         replay_rows(512, G, p.M, p.gn, p.gk, ra, ca, p.fused_b ? rb : none, p.fused_b ? cb : none, rc, cc,
