@@ -1059,11 +1059,10 @@ hipError_t launch_fp(int vec, int64_t batch, int M, int N, int K, const void* A,
                          N, K, tiles_m, tiles_n, ntiles, ra, ca, rc, cc, pt, splits);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // a tile's sum over several workgroups (more with more splits), down to
-    // one element per thread
+    // a tile's sum over workgroups of one element per thread (every thread's
+    // loads go out together: no second round trip)
     const int64_t max_chunks = std::max<int64_t>(1, static_cast<int64_t>(BM) * BN / (64 * WM * WN));
-    const dim3 sgrid(static_cast<unsigned>(ntiles),
-                     static_cast<unsigned>(std::min<int64_t>(max_chunks, std::max(4, splits / 2))));
+    const dim3 sgrid(static_cast<unsigned>(ntiles), static_cast<unsigned>(max_chunks));
     if (f)
       hipLaunchKernelGGL((k_split_sum<T, BM, BN, WM, WN, true>), sgrid, block, 0, s, pt, c, M, N, tiles_m,
                          tiles_n, splits, rc, cc);
@@ -1429,14 +1428,15 @@ hipError_t launch_dma(int64_t batch, int M, int N, int K, const void* A, const v
                                                                  tiles_m, tiles_n, ntiles, f, pt, ts);
     if (e != hipSuccess) return e;
     // a tile spans about nk / (iterations per team) + 1 teams' pieces: the sum of
-    // a tile goes to at least 4 workgroups (8192 elements each would leave one
-    // workgroup per compute unit waiting on memory), more when the tile has many
+    // a tile goes to enough workgroups that each thread makes one pass of four
+    // elements (their loads in flight together), more when the tile has many
     // pieces, down to one element per thread
     const int64_t per_team = std::max<int64_t>(1, (ntiles / ts) * nk / nteam);
     const int64_t spans = nk / per_team + 1;
     const int64_t max_chunks = std::max<int64_t>(1, static_cast<int64_t>(BM) * BN / (64 * WM * WN));
+    const int64_t one_pass = std::max<int64_t>(1, max_chunks / 4);
     const dim3 fgrid(static_cast<unsigned>(ntiles),
-                     static_cast<unsigned>(std::min<int64_t>(max_chunks, std::max<int64_t>(4, spans))));
+                     static_cast<unsigned>(std::min<int64_t>(max_chunks, std::max<int64_t>(one_pass, spans))));
     if (f)
       hipLaunchKernelGGL((k_sk_fixup<T, BM, BN, WM, WN, true>), fgrid, block, 0, s, pt, c, M, N, nk, tiles_m,
                          tiles_n, ntiles, ts, nteam, rc, cc);
