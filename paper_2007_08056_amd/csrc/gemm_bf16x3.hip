@@ -18,6 +18,14 @@
 // rows of 64 bytes whose four chunks are XOR-swizzled by ((row >> 1) & 3), so
 // the fragment reads of 8 consecutive rows fall on distinct banks.  Rows past M
 // or N are clamped on load and never stored; K must be a multiple of 32.
+//
+// IL: the planes interleaved by K-steps ([Q][row][K / 32][hi 32 | lo 32], the
+// layout the contraction's transforms write for these tiles).  A row's K-step
+// is then one whole 128-byte line instead of two half lines 32 K-steps of
+// planes apart, which halves the lines each workgroup has in flight per K-step
+// (the kernel is bound by those line requests, not by HBM bytes).  The stage
+// keeps each row's 128 bytes together, its eight 16-byte chunks XOR-swizzled
+// by (row & 7).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -31,7 +39,7 @@ namespace symt {
 
 namespace {
 
-template <int BM, int BN, int WM, int WN, int S, bool FC, typename TC>
+template <int BM, int BN, int WM, int WN, int S, bool FC, typename TC, bool IL>
 __global__ __launch_bounds__(64 * WM * WN, 1) void k_bf16x3_wide(
     const uint16_t* __restrict__ Ahi, const uint16_t* __restrict__ Alo, const uint16_t* __restrict__ Bhi,
     const uint16_t* __restrict__ Blo, TC* __restrict__ C, int M, int N, int K, int tiles_m, int tiles_n,
@@ -60,33 +68,45 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void k_bf16x3_wide(
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm0 = (wave / WN) * (BM / WM);
   const int wn0 = (wave % WN) * (BN / WN);
-  const int64_t offA = q * static_cast<int64_t>(M) * K;
-  const int64_t offB = q * static_cast<int64_t>(N) * K;
+  const int64_t offA = q * static_cast<int64_t>(M) * K * (IL ? 2 : 1);
+  const int64_t offB = q * static_cast<int64_t>(N) * K * (IL ? 2 : 1);
 
   // Load slot s = tid + i * NT covers [plane][row][chunk]; LDS position c of row
-  // r holds global chunk c ^ ((r >> 1) & 3).
+  // r holds global chunk c ^ ((r >> 1) & 3).  IL: slot s covers [row][chunk of
+  // 8] and position c of row r holds chunk c ^ (r & 7) of the row's K-step
+  // (chunks 0-3 hi, 4-7 lo).
   const uint16_t* a_src[A_LOADS];
 #pragma unroll
   for (int i = 0; i < A_LOADS; ++i) {
     const int slot = tid + i * NT;
-    const int plane = slot / (BM * 4);
-    const int rem = slot - plane * (BM * 4);
-    const int r = rem >> 2, c = rem & 3;
-    const int gr = min(m0 + r, M - 1);
-    a_src[i] = (plane ? Alo : Ahi) + offA + static_cast<int64_t>(gr) * K + (c ^ ((r >> 1) & 3)) * 8;
+    if constexpr (IL) {
+      const int r = slot >> 3;
+      a_src[i] = Ahi + offA + static_cast<int64_t>(min(m0 + r, M - 1)) * 2 * K + ((slot & 7) ^ (r & 7)) * 8;
+    } else {
+      const int plane = slot / (BM * 4);
+      const int rem = slot - plane * (BM * 4);
+      const int r = rem >> 2, c = rem & 3;
+      const int gr = min(m0 + r, M - 1);
+      a_src[i] = (plane ? Alo : Ahi) + offA + static_cast<int64_t>(gr) * K + (c ^ ((r >> 1) & 3)) * 8;
+    }
   }
   const uint16_t* b_src[B_LOADS];
 #pragma unroll
   for (int i = 0; i < B_LOADS; ++i) {
     const int slot = tid + i * NT;
-    const int plane = slot / (BN * 4);
-    const int rem = slot - plane * (BN * 4);
-    const int r = rem >> 2, c = rem & 3;
-    const int gr = min(n0 + r, N - 1);
-    b_src[i] = (plane ? Blo : Bhi) + offB + static_cast<int64_t>(gr) * K + (c ^ ((r >> 1) & 3)) * 8;
+    if constexpr (IL) {
+      const int r = slot >> 3;
+      b_src[i] = Bhi + offB + static_cast<int64_t>(min(n0 + r, N - 1)) * 2 * K + ((slot & 7) ^ (r & 7)) * 8;
+    } else {
+      const int plane = slot / (BN * 4);
+      const int rem = slot - plane * (BN * 4);
+      const int r = rem >> 2, c = rem & 3;
+      const int gr = min(n0 + r, N - 1);
+      b_src[i] = (plane ? Blo : Bhi) + offB + static_cast<int64_t>(gr) * K + (c ^ ((r >> 1) & 3)) * 8;
+    }
   }
   auto issue = [&](int kt, int stage) {
-    const int k0 = kt * BK;
+    const int k0 = kt * (IL ? 2 * BK : BK);
     char* base = smem + stage * STAGE;
 #pragma unroll
     for (int i = 0; i < A_LOADS; ++i) lds_dma16(a_src[i] + k0, base + (i * NT + wave * 64) * 16);
@@ -118,16 +138,18 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void k_bf16x3_wide(
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
       const int r = wm0 + i * 16 + (lane & 15);
-      const int off = r * 64 + ((kc ^ ((r >> 1) & 3)) << 4);
+      const int off = IL ? r * 128 + ((kc ^ (r & 7)) << 4) : r * 64 + ((kc ^ ((r >> 1) & 3)) << 4);
+      const int off_lo = IL ? r * 128 + (((4 + kc) ^ (r & 7)) << 4) : PA + off;
       ah[i] = *reinterpret_cast<const bf8*>(base + off);
-      al[i] = *reinterpret_cast<const bf8*>(base + PA + off);
+      al[i] = *reinterpret_cast<const bf8*>(base + off_lo);
     }
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
       const int r = wn0 + j * 16 + (lane & 15);
-      const int off = 2 * PA + r * 64 + ((kc ^ ((r >> 1) & 3)) << 4);
+      const int off = 2 * PA + (IL ? r * 128 + ((kc ^ (r & 7)) << 4) : r * 64 + ((kc ^ ((r >> 1) & 3)) << 4));
+      const int off_lo = IL ? 2 * PA + r * 128 + (((4 + kc) ^ (r & 7)) << 4) : PB + off;
       const bf8 bh = *reinterpret_cast<const bf8*>(base + off);
-      const bf8 bl = *reinterpret_cast<const bf8*>(base + PB + off);
+      const bf8 bl = *reinterpret_cast<const bf8*>(base + off_lo);
       // consecutive MFMAs update different accumulators (no dependent back-to-back pairs)
 #pragma unroll
       for (int i = 0; i < TM; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
@@ -157,7 +179,7 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void k_bf16x3_wide(
   }
 }
 
-template <int BM, int BN, int WM, int WN, int S>
+template <int BM, int BN, int WM, int WN, int S, bool IL>
 hipError_t launch_wide(int64_t batch, int M, int N, int K, const void* A, const void* B, void* C, hipStream_t s,
                        int64_t pa, int64_t pb, const int64_t* rc, const int64_t* cc, int c_bytes) {
   const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
@@ -173,13 +195,13 @@ hipError_t launch_wide(int64_t batch, int M, int N, int K, const void* A, const 
   int gm = gm_env ? std::atoi(gm_env) : 8;
   if (gm < 1) gm = 1;
   if (rc && c_bytes == 4)
-    hipLaunchKernelGGL((k_bf16x3_wide<BM, BN, WM, WN, S, true, float>), grid, block, 0, s, a, a + pa, b, b + pb,
+    hipLaunchKernelGGL((k_bf16x3_wide<BM, BN, WM, WN, S, true, float, IL>), grid, block, 0, s, a, a + pa, b, b + pb,
                        static_cast<float*>(C), M, N, K, tiles_m, tiles_n, ntiles, rc, cc, gm);
   else if (rc)
-    hipLaunchKernelGGL((k_bf16x3_wide<BM, BN, WM, WN, S, true, double>), grid, block, 0, s, a, a + pa, b, b + pb,
+    hipLaunchKernelGGL((k_bf16x3_wide<BM, BN, WM, WN, S, true, double, IL>), grid, block, 0, s, a, a + pa, b, b + pb,
                        static_cast<double*>(C), M, N, K, tiles_m, tiles_n, ntiles, rc, cc, gm);
   else
-    hipLaunchKernelGGL((k_bf16x3_wide<BM, BN, WM, WN, S, false, double>), grid, block, 0, s, a, a + pa, b,
+    hipLaunchKernelGGL((k_bf16x3_wide<BM, BN, WM, WN, S, false, double, IL>), grid, block, 0, s, a, a + pa, b,
                        b + pb, static_cast<double*>(C), M, N, K, tiles_m, tiles_n, ntiles, rc, cc, gm);
   return hipGetLastError();
 }
@@ -188,13 +210,17 @@ hipError_t launch_wide(int64_t batch, int M, int N, int K, const void* A, const 
 
 // Wide split-bf16 tiles: 0 = 256 x 256 (4 waves of 128 x 128, two LDS stages),
 // 1 = 256 x 128 (4 waves of 128 x 64, three stages).  pa / pb: elements from
-// each hi plane to its lo plane; rc / cc: W's offset tables (nullptr: C is the
-// aligned W, binary64).  Needs K % 32 == 0 and 16-byte aligned planes.
+// each hi plane to its lo plane (unused with il); rc / cc: W's offset tables
+// (nullptr: C is the aligned W, binary64); il: planes interleaved by K-steps.
+// Needs K % 32 == 0 and 16-byte aligned planes.
 hipError_t launch_bf16x3_wide(int variant, int64_t batch, int M, int N, int K, const void* A, const void* B,
                               void* C, hipStream_t s, int64_t pa, int64_t pb, const int64_t* rc,
-                              const int64_t* cc, int c_bytes) {
-  if (variant == 1) return launch_wide<256, 128, 2, 2, 3>(batch, M, N, K, A, B, C, s, pa, pb, rc, cc, c_bytes);
-  return launch_wide<256, 256, 2, 2, 2>(batch, M, N, K, A, B, C, s, pa, pb, rc, cc, c_bytes);
+                              const int64_t* cc, int c_bytes, bool il) {
+  if (il)
+    return variant == 1 ? launch_wide<256, 128, 2, 2, 3, true>(batch, M, N, K, A, B, C, s, pa, pb, rc, cc, c_bytes)
+                        : launch_wide<256, 256, 2, 2, 2, true>(batch, M, N, K, A, B, C, s, pa, pb, rc, cc, c_bytes);
+  if (variant == 1) return launch_wide<256, 128, 2, 2, 3, false>(batch, M, N, K, A, B, C, s, pa, pb, rc, cc, c_bytes);
+  return launch_wide<256, 256, 2, 2, 2, false>(batch, M, N, K, A, B, C, s, pa, pb, rc, cc, c_bytes);
 }
 
 }  // namespace symt

@@ -583,6 +583,18 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
     p->bytes_tables += round_up(8 * G * p->gk, 256) + round_up(8 * G * p->gn, 256);
     p->workspace = (p->fused_ua ? round_up(p->ws_u_al, 256) : 0) + round_up(p->ws_v_al, 256) + p->bytes_tables;
   }
+  // ---- split-bf16 planes interleaved by K-steps where the wide tiles multiply
+  // both aligned operands (the launcher's own pick, or a forced wide tile);
+  // SYMT_BF16_IL=0 keeps the plane-after-plane layout (tuning and tests)
+  if (compute == SYMT_COMPUTE_BF16X3 && !p->cplx && !p->fused && !p->fused_b && p->nq > 0 && p->M > 0 &&
+      p->gn > 0 && p->kpad % 32 == 0) {
+    const char* tile_env = std::getenv("SYMT_GEMM_TILE");
+    const std::string tile = tile_env ? tile_env : "";
+    const char* il_env = std::getenv("SYMT_BF16_IL");
+    const bool wide = tile.empty() ? bf16x3_wide_tile(p->nq, p->M, p->gn) >= 0
+                                   : tile == "bw256x256s2" || tile == "bw256x128s3";
+    p->bf16_il = wide && !(il_env && std::atoi(il_env) == 0);
+  }
   if (p->charges) {
     p->bytes_charges = 4 * 2 * static_cast<size_t>(p->g.size) * (p->U.n + p->V.n + p->W.n);
   }
@@ -941,6 +953,10 @@ XformParams make_xform(const Plan& p, int operand, bool to_aligned, int in_bytes
   const int64_t cols_pitch = pad && operand == 0 ? p.kpad : cols_tot;
   x.q_stride = rows_pitch * cols_pitch;
   x.plane = (x.q_full ? static_cast<int64_t>(G) : nslices) * x.q_stride;
+  // the contraction's planes interleaved by K-steps (K fastest in both operands'
+  // planes, its pitch a multiple of 32)
+  x.il = out_is_split && slice_only && operand < 2 && p.bf16_il ? 1 : 0;
+  if (x.il) x.plane = 32;
   const int64_t row_unit = lay == kRowMajor ? cols_pitch : 1;   // aligned stride of one real row
   const int64_t col_unit = lay == kRowMajor ? 1 : rows_pitch;   // aligned stride of one real column
   x.rs_stride = nR * row_mult * row_unit;

@@ -59,6 +59,8 @@ struct XformParams {
   int64_t blk_elems;                // elements per block (product of inner dims)
   int64_t q_stride, rs_stride, cs_stride;  // aligned block base = Q*q + Rs*rs + Cs*cs
   int64_t plane;                    // elements between the hi and lo bf16 planes
+  int32_t il;                       // split-bf16 destination interleaved by 32-deep K-steps:
+                                    // hi of aligned offset o at 2 o - o % 32, lo `plane` (32) after
   int32_t to_aligned;               // 1: standard -> aligned, 0: aligned -> standard
   // inner dims after merging; src / dst strides already oriented by direction
   int32_t mode;                     // 0 copy (one run dim), 1 tiled transpose
@@ -190,6 +192,10 @@ struct Plan {
   // fused product on U_al: U's contracted modes are not its last ones (or its runs
   // do not suit the product's tiles), so U is aligned first; B and C as when fused
   bool fused_ua = false;
+  // split-bf16 workspace planes interleaved by 32-deep K-steps (a row's hi and lo
+  // halves of one K-step share a 128-byte line): both operands aligned and the
+  // product on the wide tiles
+  bool bf16_il = false;
   // fused with A loaded K-major (U's contracted modes are not its last ones): row k
   // of a K-step at ca(Q, k), M chunks at ra(Q, m); a_chunks: U's other modes come
   // in runs of whole 16-byte chunks (vector loads along M)

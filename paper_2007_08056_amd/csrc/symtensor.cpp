@@ -21,7 +21,7 @@ int launch_xform(const XformParams& p, bool in_f64, int out, const void* src, vo
 int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t n, const void* A,
                        const void* B, void* C, hipStream_t stream, std::string* err,
                        const FusedTables* fused = nullptr, void* part = nullptr,
-                       size_t part_bytes = 0, int64_t plane_a = 0, int64_t plane_b = 0);
+                       size_t part_bytes = 0, int64_t plane_a = 0, int64_t plane_b = 0, bool il = false);
 int launch_offsets(const OffsetBatch& batch, hipStream_t stream, std::string* err);
 int launch_put_i32(int32_t* dst, const int32_t* src, int64_t n, hipStream_t stream, std::string* err);
 int launch_zero(void* ptr, size_t bytes, hipStream_t stream, std::string* err);
@@ -189,11 +189,11 @@ int clear_k_pad(symt_ctx* ctx, const Plan& p, void* ual, void* val, hipStream_t 
 int do_gemm(symt_ctx* ctx, int compute, int64_t batch, int64_t m, int64_t k, int64_t n,
             const void* a, const void* b, void* c, hipStream_t s,
             const symt::FusedTables* fused = nullptr, void* part = nullptr, size_t part_bytes = 0,
-            int64_t plane_a = 0, int64_t plane_b = 0) {
+            int64_t plane_a = 0, int64_t plane_b = 0, bool il = false) {
   std::string err;
   const int rc = timed(ctx, 2, s, [&] {
     return symt::launch_sector_gemm(compute, batch, m, k, n, a, b, c, s, &err, fused, part, part_bytes,
-                                    plane_a, plane_b);
+                                    plane_a, plane_b, il);
   });
   return rc ? ctx_fail(ctx, rc, err) : SYMT_OK;
 }
@@ -354,7 +354,7 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
   return do_gemm(ctx, p.compute, p.g.size, p.M, p.fused_ua ? p.kpad : p.gk, p.gn, p.fused_ua ? ual : p.U.data,
                  fb ? p.V.data : val,
                  p.W.data, s, &f,
-                 p.bytes_partial ? part : nullptr, p.bytes_partial);
+                 p.bytes_partial ? part : nullptr, p.bytes_partial, 0, 0, p.bf16_il);
 }
 
 // Cache key of a planning request: the einsum, group, compute mode, every
@@ -403,7 +403,7 @@ std::string plan_key(const char* einsum, const symt_group* group, const symt_ten
   if (!key_tensor(k, u, static_cast<int>(G)) || !key_tensor(k, v, static_cast<int>(G)) ||
       !key_tensor(k, w, static_cast<int>(G)))
     return {};
-  for (const char* var : {"SYMT_FUSED_V", "SYMT_GEMM_TILE", "SYMT_GEMM_SK"}) {
+  for (const char* var : {"SYMT_FUSED_V", "SYMT_GEMM_TILE", "SYMT_GEMM_SK", "SYMT_BF16_IL"}) {
     const char* val = std::getenv(var);
     k.push_back('|');
     if (val) k.append(val);
@@ -591,7 +591,7 @@ int contract_planned(symt_ctx* ctx, const Plan& p, void* workspace, size_t works
   // the workspace holds the nq live slices in order: one batched product of them
   // (none live: no block of W is reached, and the unalign step clears W)
   if (p.nq > 0 && (rc = do_gemm(ctx, p.compute, p.nq, p.M, p.kpad, p.gn, ual, val, wal, s, nullptr,
-                                p.bytes_partial ? part : nullptr, p.bytes_partial)))
+                                p.bytes_partial ? part : nullptr, p.bytes_partial, 0, 0, p.bf16_il)))
     return rc;
   if ((rc = do_unalign(ctx, p, wal, s, true, chg[2]))) return rc;
   return SYMT_OK;

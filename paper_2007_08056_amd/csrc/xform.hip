@@ -36,9 +36,11 @@ struct alignas(sizeof(T) * V) VecT {
   T v[V];
 };
 
-// OUT: 0 -> f64, 1 -> f32, 2 -> bf16 hi plane at off, lo plane at off + plane.
+// OUT: 0 -> f64, 1 -> f32, 2 -> bf16 hi plane at off, lo plane at off + plane;
+// il: the planes interleaved by 32-deep K-steps (hi at 2 off - off % 32; the V
+// elements of one store stay inside one K-step).
 template <int OUT, int V>
-__device__ __forceinline__ void store_vec(void* dst, int64_t off, int64_t plane, const double (&x)[V]) {
+__device__ __forceinline__ void store_vec(void* dst, int64_t off, int64_t plane, const double (&x)[V], int il = 0) {
   if constexpr (OUT == 0) {
     VecT<double, V> o;
 #pragma unroll
@@ -54,6 +56,7 @@ __device__ __forceinline__ void store_vec(void* dst, int64_t off, int64_t plane,
 #pragma unroll
     for (int i = 0; i < V; ++i) bf16_split(x[i], h.v[i], l.v[i]);
     uint16_t* d = static_cast<uint16_t*>(dst);
+    if (il) off = 2 * off - (off & 31);
     *reinterpret_cast<VecT<uint16_t, V>*>(d + off) = h;
     *reinterpret_cast<VecT<uint16_t, V>*>(d + off + plane) = l;
   }
@@ -116,7 +119,7 @@ __global__ __launch_bounds__(256) void k_xform_copy(const Tin* __restrict__ src,
     }
   };
   auto store = [&](int64_t d0, int64_t c, const double (&x)[V]) {
-    store_vec<OUT, V>(dst, d0 + (V == 1 ? c * p.run_ds : c), p.plane, x);
+    store_vec<OUT, V>(dst, d0 + (V == 1 ? c * p.run_ds : c), p.plane, x, p.il);
   };
   constexpr int U = 4;
   const int64_t c0 = c_begin + static_cast<int64_t>(lane) * V;
@@ -234,14 +237,14 @@ __global__ __launch_bounds__(256) void k_xform_transpose(const Tin* __restrict__
       const int64_t da = dof + a_dst[ae];
       for (int j = y; j < nb; j += 4) {
         double v[1] = {tile[j][ae]};
-        store_vec<OUT, 1>(dst, da + b_dst[j], p.plane, v);
+        store_vec<OUT, 1>(dst, da + b_dst[j], p.plane, v, p.il);
       }
     }
   } else if (x < nb) {
     const int64_t dx = dof + b_dst[x];
     for (int j = y; j < na; j += 4) {
       double v[1] = {tile[x][j]};
-      store_vec<OUT, 1>(dst, dx + a_dst[j], p.plane, v);
+      store_vec<OUT, 1>(dst, dx + a_dst[j], p.plane, v, p.il);
     }
   }
 }

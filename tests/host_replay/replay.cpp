@@ -39,6 +39,7 @@ namespace {
 
 int g_failures = 0;
 int64_t g_checks = 0;
+int64_t g_bf16_il = 0;     // transforms writing split-bf16 planes interleaved by K-steps
 std::string g_case;
 
 void fail(const char* what, long long a = 0, long long b = 0) {
@@ -108,6 +109,17 @@ void replay_xform(const XformParams& x, int64_t src_n, int64_t dst_n, bool dst_s
   auto write = [&](int64_t d) {
     CHECK(d >= 0 && d < dst_n, "destination out of bounds", d, dst_n);
     if (d < 0 || d >= dst_n) return;
+    if (dst_split && x.il) {
+      // planes interleaved by 32-deep K-steps: hi at 2 d - d % 32, lo 32 after
+      const int64_t h = 2 * d - (d & 31), e = h + x.plane;
+      CHECK(x.plane == 32, "interleaved hi-to-lo distance", x.plane, 32);
+      CHECK(h >= 0 && e < 2 * dst_n, "interleaved plane element out of bounds", e, 2 * dst_n);
+      if (h < 0 || e >= 2 * dst_n) return;
+      CHECK(written[h] == 0 && written[e] == 0, "interleaved plane element written twice", h, 0);
+      written[h]++;
+      written[e]++;
+      return;
+    }
     CHECK(written[d] == 0, "destination written twice", d, 0);
     written[d]++;
     if (dst_split) {
@@ -299,7 +311,11 @@ void check_transforms(const Plan& p) {
         const bool kpad = slice_only && kind == 2 && op < 2 && p.kpad != p.gk;
         const int64_t slice_n = kpad ? (op == 0 ? p.M * p.kpad : p.kpad * p.gn) : per_slice;
         const int64_t al_n = nsl * slice_n;
-        CHECK(x.plane == al_n || !split, "hi-to-lo plane distance", x.plane, al_n);
+        CHECK(x.plane == al_n || !split || x.il, "hi-to-lo plane distance", x.plane, al_n);
+        // interleaved planes: the contraction's own aligned operands, K a whole number of K-steps
+        CHECK(!x.il || (split && slice_only && op < 2 && p.bf16_il && !p.cplx && p.kpad % 32 == 0),
+              "interleaved planes outside the wide split-bf16 product", op, p.kpad);
+        if (x.il && !scalar) ++g_bf16_il;
         if (to_al) {
           std::vector<uint8_t> written(static_cast<size_t>(al_n) * (split ? 2 : 1), 0);
           std::vector<uint8_t> read(static_cast<size_t>(reals), 0);
@@ -320,8 +336,9 @@ void check_transforms(const Plan& p) {
           }
           for (int64_t d = 0; d < al_n; ++d) {
             const uint8_t want = d >= lo && d < hi && !(kpad && d % p.kpad >= p.gk) ? 1 : 0;
-            CHECK(written[d] == want, "aligned element not written exactly once", d, written[d]);
-            if (split) CHECK(written[d + al_n] == want, "lo plane element not written exactly once", d, written[d + al_n]);
+            const int64_t h = x.il ? 2 * d - (d & 31) : d, e = x.il ? h + 32 : d + al_n;
+            CHECK(written[h] == want, "aligned element not written exactly once", d, written[h]);
+            if (split) CHECK(written[e] == want, "lo plane element not written exactly once", d, written[e]);
           }
         } else {
           std::vector<uint8_t> written(static_cast<size_t>(reals), 0);
@@ -981,7 +998,7 @@ bool random_case(Rng& rng, Case& c, bool allow_tables, bool allow_sub, bool allo
 
 int64_t elems_of(const Plan& p) { return p.U.elems + p.V.elems + p.W.elems; }
 
-void run_case(const Case& c, bool steps) {
+void run_case_once(const Case& c, bool steps) {
   Plan p;
   std::string err;
   const int rc = make_plan(c.einsum.c_str(), &c.g, &c.u.t, &c.v.t, &c.w.t, c.compute | (steps ? kForceSteps : 0),
@@ -1004,6 +1021,17 @@ void run_case(const Case& c, bool steps) {
     check_split_k(tiles, gc.splits, nk_all, static_cast<int64_t>(p.bytes_partial / elem),
                   static_cast<int64_t>(gc.bm) * gc.bn);
   }
+}
+
+// Split-bf16 contractions once more on a forced wide tile (one of the two in
+// turn): their aligned planes are then interleaved by K-steps wherever K allows.
+void run_case(const Case& c, bool steps) {
+  run_case_once(c, steps);
+  if (c.compute != SYMT_COMPUTE_BF16X3) return;
+  static int turn = 0;
+  setenv("SYMT_GEMM_TILE", (turn++ & 1) ? "bw256x128s3" : "bw256x256s2", 1);
+  run_case_once(c, steps);
+  unsetenv("SYMT_GEMM_TILE");
 }
 
 // The workloads' own shapes (small enough to walk element by element).
@@ -1106,8 +1134,9 @@ int main(int argc, char** argv) {
         check_split_k(tiles, sp, nk, tiles * sp * 128 * 128, 128 * 128);
   std::printf("host replay: %d random contractions + workload shapes, %lld checks (%lld global-to-LDS long-K"
               " plans, %lld with K-major A for global-to-LDS tiles, %lld with row vectors, %lld with K vectors of K-major"
-              " A, %lld with K vectors on rows), %d failures\n", done, static_cast<long long>(g_checks),
+              " A, %lld with K vectors on rows, %lld interleaved split-bf16 plane transforms), %d failures\n", done, static_cast<long long>(g_checks),
               static_cast<long long>(g_tallk_dma), static_cast<long long>(g_at_dma), static_cast<long long>(g_row_vec),
-              static_cast<long long>(g_a_kvec), static_cast<long long>(g_k_vec), g_failures);
+              static_cast<long long>(g_a_kvec), static_cast<long long>(g_k_vec), static_cast<long long>(g_bf16_il),
+              g_failures);
   return g_failures == 0 ? 0 : 1;
 }

@@ -738,6 +738,47 @@ def test_fused_split_bf16_product(P, case, udt, tile, monkeypatch):
     assert torch.equal(w32_f.data, w_s.data.to(torch.float32))
 
 
+# split-bf16 contractions on the wide tiles: the aligned planes interleaved by
+# 32-deep K-steps (K = 32 and 64; M and N ragged against the 256-row tiles)
+IL_CASES = [
+    ("abcd,cdij->abij", (8,), "++--", "++--", (3, 5, 2, 2), (2, 2, 4, 9)),
+    ("abkl,klij->abij", (4,), "++--", "++--", (9, 8, 4, 4), (4, 4, 5, 13)),
+]
+
+
+@pytest.mark.parametrize("case", IL_CASES)
+@pytest.mark.parametrize("tile", ["bw256x256s2", "bw256x128s3"])
+@pytest.mark.parametrize("steps", [False, True])
+def test_interleaved_split_bf16_planes(P, case, tile, steps, monkeypatch):
+    """Split-bf16 planes interleaved by K-steps (U aligned first, or the three-step
+    path): bit-identical to the plane-after-plane layout on the same wide tile
+    (the same sums in the same order), and within the split-bf16 bound of the
+    oracle."""
+    sub, orders, cu, cv, du, dv = case
+    monkeypatch.setenv("SYMT_GEMM_TILE", tile)
+    monkeypatch.delenv("SYMT_BF16_IL", raising=False)
+    rng = np.random.default_rng(sum(du) * 7 + len(sub))
+    g = O.Group(orders)
+    su = O.Sym.make(cu, int(rng.integers(g.size)), du, g)
+    sv = O.Sym.make(cv, int(rng.integers(g.size)), dv, g)
+    say(f"interleaved split-bf16 planes {sub} G={orders} tile={tile} steps={steps}")
+    u = _sym_tensor(P, rng.standard_normal(su.reduced_shape()), su, torch.float64)
+    v = _sym_tensor(P, rng.standard_normal(sv.reduced_shape()), sv, torch.float64)
+    info = P.plan(sub, u, v, "bf16x3")
+    assert info.k % 32 == 0 and info.fused == 0
+    w_il = P.output_like(sub, u, v, dtype=torch.float64)
+    P.contract_into(sub, u, v, w_il, "bf16x3", steps=steps)
+    monkeypatch.setenv("SYMT_BF16_IL", "0")
+    w_pp = P.output_like(sub, u, v, dtype=torch.float64)
+    P.contract_into(sub, u, v, w_pp, "bf16x3", steps=steps)
+    assert torch.equal(w_il.data, w_pp.data)
+    U64, V64 = H.to_np(u.data), H.to_np(v.data)
+    ref, _ = O.contract_blocks(sub, U64, su, V64, sv)
+    absref, _ = O.contract_blocks(sub, np.abs(U64), su, np.abs(V64), sv)
+    k = H.contracted_extent(sub, su)
+    assert np.all(np.abs(H.to_np(w_il.data) - ref) <= H.bound_factor("bf16x3", k) * absref + 1e-300)
+
+
 # V read in place: contracted modes first in V, in U's K order; K runs of 32
 # rows; V's trailing output run a multiple of 16 bytes (f64; the last case's run
 # of 6 is not for f32)

@@ -13,6 +13,7 @@ destination element and exact coverage.  Any failure, or any sanitizer report,
 fails the test.
 """
 import os
+import re
 import shutil
 import subprocess
 
@@ -41,3 +42,6 @@ def test_host_replay_under_sanitizers(tmp_path):
     print(r.stdout)
     assert r.returncode == 0, r.stdout + r.stderr[-4000:]
     assert "0 failures" in r.stdout
+    # the interleaved split-bf16 planes (forced wide tiles) were walked too
+    m = re.search(r"(\d+) interleaved split-bf16 plane transforms", r.stdout)
+    assert m and int(m.group(1)) > 0, r.stdout
