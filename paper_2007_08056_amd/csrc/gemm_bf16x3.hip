@@ -7,11 +7,13 @@
 // (BM/WM) x (BN/WN) block of 16 x 16 MFMA tiles (v_mfma_f32_16x16x32_bf16) and
 // keeps ONE binary32 accumulator per output element, into which it adds
 // Ahi*Bhi, Ahi*Blo and Alo*Bhi.  One accumulator (rather than one for hi*hi and
-// one for the cross terms) halves the accumulator registers, so each wave can
-// hold a 128 x 128 block: every 16-byte operand fragment read from LDS then
-// feeds 24 MFMAs instead of 12, which is what keeps the product off the LDS
-// bandwidth limit.  The accumulators live in AGPRs, so this file is compiled
-// without the VGPR-form flag of the other product kernels.
+// one for the cross terms) halves the accumulator registers, so a wave can hold
+// a 128 x 64 block in half a SIMD's registers: the 256 x 256 tile runs eight
+// waves, two per SIMD, so that one wave's MFMAs cover the other's wait at the
+// K-step barrier and on its fragment reads (the four-wave form, one 128 x 128
+// block per wave, left the matrix pipes idle there: 0.53 against 0.59 of the
+// bf16 peak on the Z_16 ladder's product).  The accumulators live in AGPRs, so
+// this file is compiled without the VGPR-form flag of the other product kernels.
 //
 // K-steps are 32 deep (one MFMA); each stage of the LDS ring holds one K-step
 // of the four planes, loaded with global_load_lds (16 bytes per lane) into
@@ -208,7 +210,7 @@ hipError_t launch_wide(int64_t batch, int M, int N, int K, const void* A, const 
 
 }  // namespace
 
-// Wide split-bf16 tiles: 0 = 256 x 256 (4 waves of 128 x 128, two LDS stages),
+// Wide split-bf16 tiles: 0 = 256 x 256 (8 waves of 128 x 64, two LDS stages),
 // 1 = 256 x 128 (4 waves of 128 x 64, three stages).  pa / pb: elements from
 // each hi plane to its lo plane (unused with il); rc / cc: W's offset tables
 // (nullptr: C is the aligned W, binary64); il: planes interleaved by K-steps.
@@ -218,9 +220,9 @@ hipError_t launch_bf16x3_wide(int variant, int64_t batch, int M, int N, int K, c
                               const int64_t* cc, int c_bytes, bool il) {
   if (il)
     return variant == 1 ? launch_wide<256, 128, 2, 2, 3, true>(batch, M, N, K, A, B, C, s, pa, pb, rc, cc, c_bytes)
-                        : launch_wide<256, 256, 2, 2, 2, true>(batch, M, N, K, A, B, C, s, pa, pb, rc, cc, c_bytes);
+                        : launch_wide<256, 256, 2, 4, 2, true>(batch, M, N, K, A, B, C, s, pa, pb, rc, cc, c_bytes);
   if (variant == 1) return launch_wide<256, 128, 2, 2, 3, false>(batch, M, N, K, A, B, C, s, pa, pb, rc, cc, c_bytes);
-  return launch_wide<256, 256, 2, 2, 2, false>(batch, M, N, K, A, B, C, s, pa, pb, rc, cc, c_bytes);
+  return launch_wide<256, 256, 2, 4, 2, false>(batch, M, N, K, A, B, C, s, pa, pb, rc, cc, c_bytes);
 }
 
 }  // namespace symt
