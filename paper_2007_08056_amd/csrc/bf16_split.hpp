@@ -9,11 +9,10 @@
 
 namespace symt {
 
-// bfloat16 by round-to-nearest-even on the binary32 bit pattern (finite inputs).
+// bfloat16 rounded to nearest even: the gfx950 conversion (v_cvt_pk_bf16_f32),
+// the same instruction the wide product uses when it splits U in registers.
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return static_cast<uint16_t>(u >> 16);
+  return __builtin_bit_cast(uint16_t, static_cast<__bf16>(x));
 }
 __device__ __forceinline__ float bf16_as_f32(uint16_t h) {
   return __uint_as_float(static_cast<uint32_t>(h) << 16);

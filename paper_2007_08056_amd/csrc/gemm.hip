@@ -1485,7 +1485,7 @@ hipError_t launch_gemm_tallk(bool f64, int64_t batch, int M, int N, int K, const
 // Wide split-bf16 tiles with one binary32 accumulator (gemm_bf16x3.hip).
 hipError_t launch_bf16x3_wide(int variant, int64_t batch, int M, int N, int K, const void* A, const void* B,
                               void* C, hipStream_t s, int64_t pa, int64_t pb, const int64_t* rc,
-                              const int64_t* cc, int c_bytes, bool il);
+                              const int64_t* cc, int c_bytes, bool il, const int64_t* ra, const int64_t* ca);
 
 // plane_a / plane_b (split-bf16 only): elements from a hi plane to its lo
 // plane, 0 for the packed layout (batch * m * k, batch * n * k).  il
@@ -1516,13 +1516,16 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
     const int64_t* wcc = fused ? fused->cc : nullptr;
     const int wcb = fused ? fused->c_bytes : 8;           // W's element size
     if (il) {
-      // the planner interleaves the planes only where a wide tile runs
+      // the planner interleaves the planes only where a wide tile runs; with U's
+      // tables (fused->ra) the 256 x 256 tile reads A as binary32 U in place
       const int wv = f == "bw256x128s3" ? 1 : f == "bw256x256s2" ? 0 : f.empty() ? bf16x3_wide_tile(batch, M, N) : -1;
-      if (!dma_ok || wv < 0 || (fused && fused->ra)) {
+      const bool fa = fused && fused->ra;
+      if (!dma_ok || wv < 0 || (fa && (wv != 0 || fused->a_bytes != 4 || !fused->ca || !wrc))) {
         if (err) *err = "interleaved split-bf16 planes need a wide tile and whole 32-deep K-steps";
         return SYMT_EUNSUPPORTED;
       }
-      e = launch_bf16x3_wide(wv, batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb, true);
+      e = launch_bf16x3_wide(wv, batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb, true,
+                             fa ? fused->ra : nullptr, fa ? fused->ca : nullptr);
     } else if (fused && fused->ra) {
       // register tiles only (the planner fuses where the launcher would pick one)
       if (!bf16x3_register_tile(M, N, K) || K % 32 != 0) {
@@ -1534,8 +1537,8 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
           : t == 2 ? launch_bf16x3_fused<128, 256, 32, 2, 4>(batch, M, N, K, A, B, C, stream, pb, fused)
           : t == 3 ? launch_bf16x3_fused<128, 96, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pb, fused)
                    : launch_bf16x3_fused<128, 128, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pb, fused);
-    } else if (f == "bw256x256s2" && dma_ok) e = launch_bf16x3_wide(0, batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb, false);
-    else if (f == "bw256x128s3" && dma_ok) e = launch_bf16x3_wide(1, batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb, false);
+    } else if (f == "bw256x256s2" && dma_ok) e = launch_bf16x3_wide(0, batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb, false, nullptr, nullptr);
+    else if (f == "bw256x128s3" && dma_ok) e = launch_bf16x3_wide(1, batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb, false, nullptr, nullptr);
     else if (f == "bd256x128s3" && dma_ok) e = launch_bf16x3_dma<256, 128, 4, 2, 3>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
     else if (f == "bd128x256s3" && dma_ok) e = launch_bf16x3_dma<128, 256, 2, 4, 3>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
     else if (f == "b128x128k64") e = launch_bf16x3<128, 128, 64, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
@@ -1546,7 +1549,8 @@ int launch_sector_gemm(int compute, int64_t batch, int64_t m, int64_t k, int64_t
     else if (f == "b128x96k32") e = launch_bf16x3<128, 96, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
     else if (f == "b64x64k32") e = launch_bf16x3<64, 64, 32, 2, 2>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
     else if (dma_ok && f.empty() && bf16x3_wide_tile(batch, M, N) >= 0)
-      e = launch_bf16x3_wide(bf16x3_wide_tile(batch, M, N), batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb, false);
+      e = launch_bf16x3_wide(bf16x3_wide_tile(batch, M, N), batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb, false,
+                             nullptr, nullptr);
     else if (dma_ok && f.empty() && M >= 256 && N >= 512)
       e = launch_bf16x3_dma<128, 256, 2, 4, 3>(batch, M, N, K, A, B, C, stream, pa, pb, wrc, wcc, wcb);
     else if (N <= 64)

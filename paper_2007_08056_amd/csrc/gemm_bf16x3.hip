@@ -28,12 +28,22 @@
 // (the kernel is bound by those line requests, not by HBM bytes).  The stage
 // keeps each row's 128 bytes together, its eight 16-byte chunks XOR-swizzled
 // by (row & 7).
+//
+// FA: A read in place from U's standard form (binary32, runs of 4 along K at
+// 16-byte aligned offsets ra(Q, m) + ca(Q, k)) and split into hi/lo when the
+// fragments are read, as the transforms split it (bf16_split): the stage holds
+// each row's 32 binary32 values (128 bytes, the interleaved planes' size), its
+// eight 16-byte chunks XOR-swizzled by (row & 7); a K-step's column offsets are
+// fetched one step ahead of its loads.  This drops the pass that would put U on
+// planes (a read and a write of U) for 24 conversions and subtractions per
+// fragment (the 64 x 128 wave blocks read half the A fragments of 128 x 64).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 #include <cstdlib>
 #include <type_traits>
 
+#include "bf16_split.hpp"
 #include "gemm_common.hpp"
 #include "plan.hpp"
 
@@ -41,11 +51,31 @@ namespace symt {
 
 namespace {
 
-template <int BM, int BN, int WM, int WN, int S, bool FC, typename TC, bool IL>
+typedef float fv4 __attribute__((ext_vector_type(4)));
+typedef float fv8 __attribute__((ext_vector_type(8)));
+typedef uint32_t uv4 __attribute__((ext_vector_type(4)));
+
+// bf16_split of eight binary32 values at once: hi = bf16(x), lo = bf16(x - hi),
+// each by the hardware conversion that bf16_rne is (paired, round to nearest even).
+__device__ __forceinline__ void split8(fv4 x0, fv4 x1, bf8& hi, bf8& lo) {
+  const fv8 x = {x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3]};
+  hi = __builtin_convertvector(x, bf8);
+  const uv4 hb = __builtin_bit_cast(uv4, hi);
+  fv8 hf;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    hf[2 * j] = __uint_as_float(hb[j] << 16);
+    hf[2 * j + 1] = __uint_as_float(hb[j] & 0xFFFF0000u);
+  }
+  lo = __builtin_convertvector(x - hf, bf8);
+}
+
+template <int BM, int BN, int WM, int WN, int S, bool FC, typename TC, bool IL, bool FA>
 __global__ __launch_bounds__(64 * WM * WN, 1) void k_bf16x3_wide(
     const uint16_t* __restrict__ Ahi, const uint16_t* __restrict__ Alo, const uint16_t* __restrict__ Bhi,
     const uint16_t* __restrict__ Blo, TC* __restrict__ C, int M, int N, int K, int tiles_m, int tiles_n,
-    int64_t ntiles, const int64_t* __restrict__ rc, const int64_t* __restrict__ cc, int group_m) {
+    int64_t ntiles, const int64_t* __restrict__ rc, const int64_t* __restrict__ cc, int group_m,
+    const float* __restrict__ U, const int64_t* __restrict__ ra, const int64_t* __restrict__ ca) {
   constexpr int NT = 64 * WM * WN;
   constexpr int BK = 32;
   constexpr int TM = BM / WM / 16;
@@ -58,6 +88,7 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void k_bf16x3_wide(
   static_assert(A_LOADS * NT == BM * 8 && B_LOADS * NT == BN * 8, "loads must divide evenly");
   static_assert(S >= 2 && S * STAGE <= 160 * 1024, "LDS ring");
   static_assert(FC || std::is_same<TC, double>::value, "aligned W is binary64");
+  static_assert(!FA || (IL && S == 2), "A in place: interleaved B planes and two stages");
   __shared__ __attribute__((aligned(1024))) char smem[S * STAGE];
 
   const int64_t tile = xcd_remap(blockIdx.x, ntiles);
@@ -78,10 +109,19 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void k_bf16x3_wide(
   // 8] and position c of row r holds chunk c ^ (r & 7) of the row's K-step
   // (chunks 0-3 hi, 4-7 lo).
   const uint16_t* a_src[A_LOADS];
+  // FA: U's row offset and the in-step K offset (4 x chunk) of each load slot,
+  // and the column offsets of the next K-step to issue
+  const float* a_row[A_LOADS];
+  int a_k[A_LOADS];
+  int64_t a_col[A_LOADS];
 #pragma unroll
   for (int i = 0; i < A_LOADS; ++i) {
     const int slot = tid + i * NT;
-    if constexpr (IL) {
+    if constexpr (FA) {
+      const int r = slot >> 3;
+      a_row[i] = U + ra[q * M + min(m0 + r, M - 1)];
+      a_k[i] = ((slot & 7) ^ (r & 7)) * 4;
+    } else if constexpr (IL) {
       const int r = slot >> 3;
       a_src[i] = Ahi + offA + static_cast<int64_t>(min(m0 + r, M - 1)) * 2 * K + ((slot & 7) ^ (r & 7)) * 8;
     } else {
@@ -107,11 +147,18 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void k_bf16x3_wide(
       b_src[i] = (plane ? Blo : Bhi) + offB + static_cast<int64_t>(gr) * K + (c ^ ((r >> 1) & 3)) * 8;
     }
   }
+  auto fetch_cols = [&](int kt) {
+#pragma unroll
+    for (int i = 0; i < A_LOADS; ++i) a_col[i] = ca[q * K + kt * BK + a_k[i]];
+  };
   auto issue = [&](int kt, int stage) {
     const int k0 = kt * (IL ? 2 * BK : BK);
     char* base = smem + stage * STAGE;
 #pragma unroll
-    for (int i = 0; i < A_LOADS; ++i) lds_dma16(a_src[i] + k0, base + (i * NT + wave * 64) * 16);
+    for (int i = 0; i < A_LOADS; ++i) {
+      if constexpr (FA) lds_dma16(a_row[i] + a_col[i], base + (i * NT + wave * 64) * 16);
+      else lds_dma16(a_src[i] + k0, base + (i * NT + wave * 64) * 16);
+    }
 #pragma unroll
     for (int i = 0; i < B_LOADS; ++i) lds_dma16(b_src[i] + k0, base + 2 * PA + (i * NT + wave * 64) * 16);
   };
@@ -124,9 +171,20 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void k_bf16x3_wide(
 
   const int nk = K / BK;
   const int kc = lane >> 4;                       // operand chunk: k = 8 * kc .. 8 * kc + 7
+  if constexpr (FA) {
+    // (two stages: the loop's wait for nothing outstanding also covers the
+    // column offsets fetched one step ahead)
+    if (nk > 0) {
+      fetch_cols(0);
+      wait_vmcnt<0>();
+      issue(0, 0);
+      if (nk > 1) fetch_cols(1);
+    }
+  } else {
 #pragma unroll
-  for (int s = 0; s < S - 1; ++s)
-    if (s < nk) issue(s, s);
+    for (int s = 0; s < S - 1; ++s)
+      if (s < nk) issue(s, s);
+  }
   for (int kt = 0; kt < nk; ++kt) {
     // step kt has landed once at most (S - 2) later steps' loads are outstanding
     if (kt + S - 2 < nk) wait_vmcnt<(S - 2) * (A_LOADS + B_LOADS)>();
@@ -134,16 +192,27 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void k_bf16x3_wide(
     // a plain barrier: the wait above covers this wave's loads of step kt, and
     // every wave has finished reading the stage that the next issue overwrites
     asm volatile("s_barrier" ::: "memory");
-    if (kt + S - 1 < nk) issue(kt + S - 1, (kt + S - 1) % S);
+    if (kt + S - 1 < nk) {
+      issue(kt + S - 1, (kt + S - 1) % S);
+      if constexpr (FA)
+        if (kt + 2 < nk) fetch_cols(kt + 2);
+    }
     const char* base = smem + (kt % S) * STAGE;
     bf8 ah[TM], al[TM];
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
       const int r = wm0 + i * 16 + (lane & 15);
-      const int off = IL ? r * 128 + ((kc ^ (r & 7)) << 4) : r * 64 + ((kc ^ ((r >> 1) & 3)) << 4);
-      const int off_lo = IL ? r * 128 + (((4 + kc) ^ (r & 7)) << 4) : PA + off;
-      ah[i] = *reinterpret_cast<const bf8*>(base + off);
-      al[i] = *reinterpret_cast<const bf8*>(base + off_lo);
+      if constexpr (FA) {
+        // K 8 kc .. 8 kc + 7 of row r: chunks 2 kc and 2 kc + 1
+        const fv4 x0 = *reinterpret_cast<const fv4*>(base + r * 128 + (((2 * kc) ^ (r & 7)) << 4));
+        const fv4 x1 = *reinterpret_cast<const fv4*>(base + r * 128 + (((2 * kc + 1) ^ (r & 7)) << 4));
+        split8(x0, x1, ah[i], al[i]);
+      } else {
+        const int off = IL ? r * 128 + ((kc ^ (r & 7)) << 4) : r * 64 + ((kc ^ ((r >> 1) & 3)) << 4);
+        const int off_lo = IL ? r * 128 + (((4 + kc) ^ (r & 7)) << 4) : PA + off;
+        ah[i] = *reinterpret_cast<const bf8*>(base + off);
+        al[i] = *reinterpret_cast<const bf8*>(base + off_lo);
+      }
     }
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
@@ -181,13 +250,15 @@ __global__ __launch_bounds__(64 * WM * WN, 1) void k_bf16x3_wide(
   }
 }
 
-template <int BM, int BN, int WM, int WN, int S, bool IL>
+template <int BM, int BN, int WM, int WN, int S, bool IL, bool FA = false>
 hipError_t launch_wide(int64_t batch, int M, int N, int K, const void* A, const void* B, void* C, hipStream_t s,
-                       int64_t pa, int64_t pb, const int64_t* rc, const int64_t* cc, int c_bytes) {
+                       int64_t pa, int64_t pb, const int64_t* rc, const int64_t* cc, int c_bytes,
+                       const int64_t* ra = nullptr, const int64_t* ca = nullptr) {
   const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
   const int64_t ntiles = batch * tiles_m * tiles_n;
   const dim3 grid(static_cast<unsigned>(ntiles)), block(64 * WM * WN);
-  const uint16_t* a = static_cast<const uint16_t*>(A);
+  const uint16_t* a = FA ? nullptr : static_cast<const uint16_t*>(A);
+  const float* u = FA ? static_cast<const float*>(A) : nullptr;
   const uint16_t* b = static_cast<const uint16_t*>(B);
   // M-panels per group of the tile order (each XCD runs a contiguous range of
   // tiles, so the workgroups in flight on one XCD are group_m M-panels by a few
@@ -197,14 +268,16 @@ hipError_t launch_wide(int64_t batch, int M, int N, int K, const void* A, const 
   int gm = gm_env ? std::atoi(gm_env) : 8;
   if (gm < 1) gm = 1;
   if (rc && c_bytes == 4)
-    hipLaunchKernelGGL((k_bf16x3_wide<BM, BN, WM, WN, S, true, float, IL>), grid, block, 0, s, a, a + pa, b, b + pb,
-                       static_cast<float*>(C), M, N, K, tiles_m, tiles_n, ntiles, rc, cc, gm);
+    hipLaunchKernelGGL((k_bf16x3_wide<BM, BN, WM, WN, S, true, float, IL, FA>), grid, block, 0, s, a, a + pa, b, b + pb,
+                       static_cast<float*>(C), M, N, K, tiles_m, tiles_n, ntiles, rc, cc, gm, u, ra, ca);
   else if (rc)
-    hipLaunchKernelGGL((k_bf16x3_wide<BM, BN, WM, WN, S, true, double, IL>), grid, block, 0, s, a, a + pa, b, b + pb,
-                       static_cast<double*>(C), M, N, K, tiles_m, tiles_n, ntiles, rc, cc, gm);
+    hipLaunchKernelGGL((k_bf16x3_wide<BM, BN, WM, WN, S, true, double, IL, FA>), grid, block, 0, s, a, a + pa, b, b + pb,
+                       static_cast<double*>(C), M, N, K, tiles_m, tiles_n, ntiles, rc, cc, gm, u, ra, ca);
+  else if constexpr (!FA)
+    hipLaunchKernelGGL((k_bf16x3_wide<BM, BN, WM, WN, S, false, double, IL, false>), grid, block, 0, s, a, a + pa, b,
+                       b + pb, static_cast<double*>(C), M, N, K, tiles_m, tiles_n, ntiles, rc, cc, gm, u, ra, ca);
   else
-    hipLaunchKernelGGL((k_bf16x3_wide<BM, BN, WM, WN, S, false, double, IL>), grid, block, 0, s, a, a + pa, b,
-                       b + pb, static_cast<double*>(C), M, N, K, tiles_m, tiles_n, ntiles, rc, cc, gm);
+    return hipErrorInvalidValue;   // A in place writes W in place
   return hipGetLastError();
 }
 
@@ -213,11 +286,18 @@ hipError_t launch_wide(int64_t batch, int M, int N, int K, const void* A, const 
 // Wide split-bf16 tiles: 0 = 256 x 256 (8 waves of 128 x 64, two LDS stages),
 // 1 = 256 x 128 (4 waves of 128 x 64, three stages).  pa / pb: elements from
 // each hi plane to its lo plane (unused with il); rc / cc: W's offset tables
-// (nullptr: C is the aligned W, binary64); il: planes interleaved by K-steps.
-// Needs K % 32 == 0 and 16-byte aligned planes.
+// (nullptr: C is the aligned W, binary64); il: planes interleaved by K-steps;
+// ra / ca (with il, variant 0 and W's tables): A is U's standard form in
+// binary32, read through these tables (FA above).  Needs K % 32 == 0 and
+// 16-byte aligned planes.
 hipError_t launch_bf16x3_wide(int variant, int64_t batch, int M, int N, int K, const void* A, const void* B,
                               void* C, hipStream_t s, int64_t pa, int64_t pb, const int64_t* rc,
-                              const int64_t* cc, int c_bytes, bool il) {
+                              const int64_t* cc, int c_bytes, bool il, const int64_t* ra, const int64_t* ca) {
+  // A in place (binary32 U through ra / ca): the 256 x 256 tile with 64 x 128 wave blocks
+  if (ra && ca) {
+    if (!il || variant != 0 || !rc) return hipErrorInvalidValue;
+    return launch_wide<256, 256, 4, 2, 2, true, true>(batch, M, N, K, A, B, C, s, pa, pb, rc, cc, c_bytes, ra, ca);
+  }
   if (il)
     return variant == 1 ? launch_wide<256, 128, 2, 2, 3, true>(batch, M, N, K, A, B, C, s, pa, pb, rc, cc, c_bytes)
                         : launch_wide<256, 256, 2, 4, 2, true>(batch, M, N, K, A, B, C, s, pa, pb, rc, cc, c_bytes);

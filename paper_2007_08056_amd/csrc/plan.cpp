@@ -594,6 +594,10 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
     const bool wide = tile.empty() ? bf16x3_wide_tile(p->nq, p->M, p->gn) >= 0
                                    : tile == "bw256x256s2" || tile == "bw256x128s3";
     p->bf16_il = wide && !(il_env && std::atoi(il_env) == 0);
+    const char* fa_env = std::getenv("SYMT_BF16_FA");
+    const bool wide256 = tile.empty() ? bf16x3_wide_tile(p->nq, p->M, p->gn) == 0 : tile == "bw256x256s2";
+    p->bf16_wide_fa = p->bf16_il && wide256 && p->fused_ua && p->U.dtype == SYMT_F32 && trailing_k &&
+                      p->nK % 4 == 0 && p->gk == p->kpad && !(fa_env && std::atoi(fa_env) == 0);
   }
   if (p->charges) {
     p->bytes_charges = 4 * 2 * static_cast<size_t>(p->g.size) * (p->U.n + p->V.n + p->W.n);

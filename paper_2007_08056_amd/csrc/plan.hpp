@@ -196,6 +196,10 @@ struct Plan {
   // halves of one K-step share a 128-byte line): both operands aligned and the
   // product on the wide tiles
   bool bf16_il = false;
+  // ... and U (binary32, its contracted modes last in runs of 4) read in place by
+  // the 256 x 256 wide tile, split when its fragments are read (where U is
+  // 16-byte aligned; else U is aligned first as for fused_ua)
+  bool bf16_wide_fa = false;
   // fused with A loaded K-major (U's contracted modes are not its last ones): row k
   // of a K-step at ca(Q, k), M chunks at ra(Q, m); a_chunks: U's other modes come
   // in runs of whole 16-byte chunks (vector loads along M)

@@ -300,7 +300,7 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
       int64_t total = 0;
       b.n = n_build;
       for (int t = 0; t < b.n; ++t) {
-        if (p.fused_ua && ops[t] == 0)   // U_al: row m at (q M + m) gk, column k at k
+        if (p.fused_ua && ops[t] == 0 && !p.bf16_wide_fa)   // U_al: row m at (q M + m) gk, column k at k
           b.t[t] = t == 0 ? symt::affine_offsets(p, p.M, p.M * p.gk, p.gk) : symt::affine_offsets(p, p.gk, 0, 1);
         else
           b.t[t] = symt::make_offsets(p, ops[t], t % 2 == 0);
@@ -318,13 +318,16 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
   }
   if (tlock.owns_lock()) tlock.unlock();
   if (rc_) return ctx_fail(ctx, rc_, err);
+  // split-bf16 on the 256 x 256 wide tile: binary32 U read in place (16-byte aligned)
+  const bool wide_fa = p.bf16_wide_fa && aligned16(p.U.data);
   if (p.fused_ua && (rc_ = clear_k_pad(ctx, p, ual, fb ? nullptr : val, s))) return rc_;
-  if (p.fused_ua && (rc_ = do_align(ctx, p, 0, ual, s, true, chg[0]))) return rc_;
+  if (p.fused_ua && !wide_fa && (rc_ = do_align(ctx, p, 0, ual, s, true, chg[0]))) return rc_;
   if (!fb && (rc_ = do_align(ctx, p, 1, val, s, true, chg[1]))) return rc_;
   symt::FusedTables f{ra, ca, rc, cc, vec};
   // split-bf16 on aligned U: A and B come from the hi/lo planes, only W's tables apply
-  if (p.fused_ua && p.compute == SYMT_COMPUTE_BF16X3) f.ra = f.ca = nullptr;
-  f.a_bytes = static_cast<int32_t>(p.fused_ua ? (p.compute == SYMT_COMPUTE_F64 ? 8 : 4) : elem_bytes(p.U.dtype));
+  if (p.fused_ua && p.compute == SYMT_COMPUTE_BF16X3 && !wide_fa) f.ra = f.ca = nullptr;
+  f.a_bytes = static_cast<int32_t>(p.fused_ua && !wide_fa ? (p.compute == SYMT_COMPUTE_F64 ? 8 : 4)
+                                                            : elem_bytes(p.U.dtype));
   f.krun = p.krun;
   f.at = p.a_trans ? 1 : 0;
   f.c_bytes = static_cast<int32_t>(elem_bytes(p.W.dtype));
@@ -351,7 +354,8 @@ int do_fused(symt_ctx* ctx, const Plan& p, char* base, hipStream_t s, const int3
     f.cb = cb;
     f.ldb = p.ldb;
   }
-  return do_gemm(ctx, p.compute, p.g.size, p.M, p.fused_ua ? p.kpad : p.gk, p.gn, p.fused_ua ? ual : p.U.data,
+  return do_gemm(ctx, p.compute, p.g.size, p.M, p.fused_ua ? p.kpad : p.gk, p.gn,
+                 p.fused_ua && !wide_fa ? ual : p.U.data,
                  fb ? p.V.data : val,
                  p.W.data, s, &f,
                  p.bytes_partial ? part : nullptr, p.bytes_partial, 0, 0, p.bf16_il);
@@ -403,7 +407,7 @@ std::string plan_key(const char* einsum, const symt_group* group, const symt_ten
   if (!key_tensor(k, u, static_cast<int>(G)) || !key_tensor(k, v, static_cast<int>(G)) ||
       !key_tensor(k, w, static_cast<int>(G)))
     return {};
-  for (const char* var : {"SYMT_FUSED_V", "SYMT_GEMM_TILE", "SYMT_GEMM_SK", "SYMT_BF16_IL"}) {
+  for (const char* var : {"SYMT_FUSED_V", "SYMT_GEMM_TILE", "SYMT_GEMM_SK", "SYMT_BF16_IL", "SYMT_BF16_FA"}) {
     const char* val = std::getenv(var);
     k.push_back('|');
     if (val) k.append(val);

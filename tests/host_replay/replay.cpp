@@ -40,6 +40,7 @@ namespace {
 int g_failures = 0;
 int64_t g_checks = 0;
 int64_t g_bf16_il = 0;     // transforms writing split-bf16 planes interleaved by K-steps
+int64_t g_bf16_fa = 0;     // split-bf16 plans whose wide tile reads binary32 U in place
 std::string g_case;
 
 void fail(const char* what, long long a = 0, long long b = 0) {
@@ -624,6 +625,25 @@ void check_fused(const Plan& p) {
   rc = table(make_offsets(p, 2, true), G);
   cc = table(make_offsets(p, 2, false), G);
   check_bijection(rc, cc, G, p.M, p.gn, p.W.elems * cm, "W tables not a bijection onto W");
+  if (p.bf16_wide_fa) {
+    // the wide split-bf16 tile reading binary32 U in place: one 16-byte load per
+    // run of 4 along K, at ra(Q, m) + ca(Q, k) for k a multiple of 4
+    ++g_bf16_fa;
+    CHECK(p.fused_ua && p.bf16_il && !p.cplx && p.U.dtype == SYMT_F32 && p.gk % 32 == 0 && p.gk == p.kpad,
+          "wide split-bf16 in place outside its conditions", p.gk, p.kpad);
+    const std::vector<int64_t> ua = table(make_offsets(p, 0, true), G), uc = table(make_offsets(p, 0, false), G);
+    check_bijection(ua, uc, G, p.M, p.gk, p.U.elems, "U tables (wide split-bf16 in place) not a bijection onto U");
+    for (int q = 0; q < G; ++q)
+      for (int64_t k = 0; k + 3 < p.gk; k += 4) {
+        const int64_t c0 = uc[q * p.gk + k];
+        for (int i = 1; i < 4; ++i) CHECK(uc[q * p.gk + k + i] == c0 + i, "U's K run of 4 not contiguous", k, i);
+        for (int64_t m = 0; m < p.M; ++m) {
+          const int64_t off = ua[q * p.M + m] + c0;
+          CHECK(off % 4 == 0, "U run of 4 not 16-byte aligned", m, k);
+          CHECK(off >= 0 && off + 4 <= p.U.elems, "U run of 4 out of bounds", off, p.U.elems);
+        }
+      }
+  }
   if (!p.cplx && p.w_row_run % 4 == 0) {
     // binary32 tiles store 4 consecutive rows of a column with one 16-byte store
     for (int q = 0; q < G; ++q)
@@ -1023,14 +1043,16 @@ void run_case_once(const Case& c, bool steps) {
   }
 }
 
-// Split-bf16 contractions once more on a forced wide tile (one of the two in
-// turn): their aligned planes are then interleaved by K-steps wherever K allows.
+// Split-bf16 contractions once more on each forced wide tile: their aligned
+// planes are then interleaved by K-steps wherever K allows, and the 256 x 256
+// tile reads a binary32 U in place where its runs allow.
 void run_case(const Case& c, bool steps) {
   run_case_once(c, steps);
   if (c.compute != SYMT_COMPUTE_BF16X3) return;
-  static int turn = 0;
-  setenv("SYMT_GEMM_TILE", (turn++ & 1) ? "bw256x128s3" : "bw256x256s2", 1);
-  run_case_once(c, steps);
+  for (const char* tile : {"bw256x256s2", "bw256x128s3"}) {
+    setenv("SYMT_GEMM_TILE", tile, 1);
+    run_case_once(c, steps);
+  }
   unsetenv("SYMT_GEMM_TILE");
 }
 
@@ -1052,6 +1074,10 @@ void workload_cases() {
       // hold whole 16-deep groups
       {"bcsA,cASB->bsSB", 6, "--+-", "----", {2, 8, 2, 16}, {8, 16, 2, 2}},
       {"opij,opkm->ijmk", 8, "++--", "--++", {3, 3, 4, 4}, {3, 3, 4, 2}},
+      // the ladder's form with K a whole number of 32-deep steps and U's runs of 4
+      // and 16 (split-bf16 on the wide tiles, U in place)
+      {"abcd,cdij->abij", 8, "++--", "++--", {3, 5, 2, 2}, {2, 2, 4, 9}},
+      {"abkl,klij->abij", 4, "++--", "++--", {9, 8, 4, 4}, {4, 4, 5, 13}},
       {"ijk,klm->ijlm", 5, "++-", "++-", {7, 10, 7}, {7, 1, 7}},
   };
   for (const W& w : ws) {
@@ -1134,9 +1160,10 @@ int main(int argc, char** argv) {
         check_split_k(tiles, sp, nk, tiles * sp * 128 * 128, 128 * 128);
   std::printf("host replay: %d random contractions + workload shapes, %lld checks (%lld global-to-LDS long-K"
               " plans, %lld with K-major A for global-to-LDS tiles, %lld with row vectors, %lld with K vectors of K-major"
-              " A, %lld with K vectors on rows, %lld interleaved split-bf16 plane transforms), %d failures\n", done, static_cast<long long>(g_checks),
+              " A, %lld with K vectors on rows, %lld interleaved split-bf16 plane transforms, %lld split-bf16 plans reading U"
+              " in place on the wide tile), %d failures\n", done, static_cast<long long>(g_checks),
               static_cast<long long>(g_tallk_dma), static_cast<long long>(g_at_dma), static_cast<long long>(g_row_vec),
               static_cast<long long>(g_a_kvec), static_cast<long long>(g_k_vec), static_cast<long long>(g_bf16_il),
-              g_failures);
+              static_cast<long long>(g_bf16_fa), g_failures);
   return g_failures == 0 ? 0 : 1;
 }

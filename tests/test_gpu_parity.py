@@ -779,6 +779,51 @@ def test_interleaved_split_bf16_planes(P, case, tile, steps, monkeypatch):
     assert np.all(np.abs(H.to_np(w_il.data) - ref) <= H.bound_factor("bf16x3", k) * absref + 1e-300)
 
 
+@pytest.mark.parametrize("case", IL_CASES)
+@pytest.mark.parametrize("wdt", ["f64", "f32"])
+def test_wide_split_bf16_reads_u_in_place(P, case, wdt, monkeypatch):
+    """The 256 x 256 wide split-bf16 tile reading binary32 U in place (split into
+    hi/lo as its fragments are read): bit-identical to the three-step path (U on
+    interleaved planes), to the same contraction with U at an odd element offset
+    (aligned first) and with the in-place read switched off, and within the
+    split-bf16 bound of the oracle."""
+    sub, orders, cu, cv, du, dv = case
+    monkeypatch.setenv("SYMT_GEMM_TILE", "bw256x256s2")
+    monkeypatch.delenv("SYMT_BF16_IL", raising=False)
+    monkeypatch.delenv("SYMT_BF16_FA", raising=False)
+    rng = np.random.default_rng(sum(dv) * 11 + len(wdt))
+    g = O.Group(orders)
+    su = O.Sym.make(cu, int(rng.integers(g.size)), du, g)
+    sv = O.Sym.make(cv, int(rng.integers(g.size)), dv, g)
+    say(f"wide split-bf16 U in place {sub} G={orders} w={wdt}")
+    u = _sym_tensor(P, rng.standard_normal(su.reduced_shape()), su, torch.float32)
+    v = _sym_tensor(P, rng.standard_normal(sv.reduced_shape()), sv, torch.float32)
+    wt = torch.float64 if wdt == "f64" else torch.float32
+    w_fa = P.output_like(sub, u, v, dtype=wt)
+    P.contract_into(sub, u, v, w_fa, "bf16x3")
+    w_st = P.output_like(sub, u, v, dtype=wt)
+    P.contract_into(sub, u, v, w_st, "bf16x3", steps=True)
+    assert torch.equal(w_fa.data, w_st.data)
+    buf = torch.zeros(u.data.numel() + 1, dtype=torch.float32, device=DEV)
+    buf[1:] = u.data.reshape(-1)
+    u_off = P.SymTensor(buf[1:].view(u.data.shape), u.signs, u.charge, u.group)
+    w_o = P.output_like(sub, u, v, dtype=wt)
+    P.contract_into(sub, u_off, v, w_o, "bf16x3")
+    assert torch.equal(w_o.data, w_st.data)
+    monkeypatch.setenv("SYMT_BF16_FA", "0")
+    w_pl = P.output_like(sub, u, v, dtype=wt)
+    P.contract_into(sub, u, v, w_pl, "bf16x3")
+    assert torch.equal(w_pl.data, w_st.data)
+    U64, V64 = H.to_np(u.data).astype(np.float64), H.to_np(v.data).astype(np.float64)
+    ref, _ = O.contract_blocks(sub, U64, su, V64, sv)
+    absref, _ = O.contract_blocks(sub, np.abs(U64), su, np.abs(V64), sv)
+    k = H.contracted_extent(sub, su)
+    w64 = H.to_np(w_fa.data).astype(np.float64)
+    # (a binary32 W adds one rounding of each sum)
+    extra = 0.0 if wdt == "f64" else H.U32
+    assert np.all(np.abs(w64 - ref) <= H.bound_factor("bf16x3", k) * absref + extra * np.abs(ref) + 1e-300)
+
+
 # V read in place: contracted modes first in V, in U's K order; K runs of 32
 # rows; V's trailing output run a multiple of 16 bytes (f64; the last case's run
 # of 6 is not for f32)

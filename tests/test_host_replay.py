@@ -45,3 +45,5 @@ def test_host_replay_under_sanitizers(tmp_path):
     # the interleaved split-bf16 planes (forced wide tiles) were walked too
     m = re.search(r"(\d+) interleaved split-bf16 plane transforms", r.stdout)
     assert m and int(m.group(1)) > 0, r.stdout
+    m = re.search(r"(\d+) split-bf16 plans reading U in place", r.stdout)
+    assert m and int(m.group(1)) > 0, r.stdout
