@@ -126,9 +126,14 @@
  * slice is live, u alone is aligned first and the same product reads U_al
  * through affine tables (info.fused = 0, info.fused_w = 1); with BF16X3, u and
  * v go to their hi/lo planes and only w is written in place, where w (binary64
- * or binary32) takes its product columns in contiguous runs of 16 or more.  The workspace holds
- * U_al in that case, then V_al (used when v is not read in place) and the
- * tables.  Where K-steps are the three-step path's, results are identical in
+ * or binary32) takes its product columns in contiguous runs of 16 or more.  On
+ * the wide split-bf16 tiles (products from 256 x 256 with K a multiple of 32)
+ * the planes are interleaved by 32-deep K-steps, and a binary32 u whose
+ * contracted modes are its last ones, in runs of 4 or more elements per block,
+ * 16-byte aligned, is read in place by the 256 x 256 tile and split in
+ * registers (same bits as its planes).  The workspace holds
+ * U_al in that case (left unused when u is read in place), then V_al (used when
+ * v is not read in place) and the tables.  Where K-steps are the three-step path's, results are identical in
  * value to it: the product sums in the same order.
  *
  * Execution and ownership.  Every device buffer the caller names (operand
@@ -170,6 +175,10 @@
  *   SYMT_FUSED_V=0         keeps V aligned in the fused product (info.fused_v = 0).
  *   SYMT_GEMM_GROUP_M=<n>  M-panels per group in the tile order of the wide
  *                          split-bf16 tiles (default 8).
+ *   SYMT_BF16_IL=0         keeps the wide split-bf16 tiles' planes one after the
+ *                          other (not interleaved by K-steps).
+ *   SYMT_BF16_FA=0         keeps u on planes for the 256 x 256 wide split-bf16
+ *                          tile (not read in place).
  */
 #ifndef SYMTENSOR_H
 #define SYMTENSOR_H
