@@ -17,9 +17,13 @@ __device__ __forceinline__ uint16_t bf16_rne(float x) {
 __device__ __forceinline__ float bf16_as_f32(uint16_t h) {
   return __uint_as_float(static_cast<uint32_t>(h) << 16);
 }
-// x is taken in binary32 first (a binary64 input is rounded to nearest).
+// x is taken in binary32 first (a binary64 input is rounded to nearest).  The
+// empty asm keeps that binary32 value: the compiler would otherwise fold the two
+// conversions into one rounding of the binary64 value to bfloat16, which can
+// differ by one unit in hi.
 __device__ __forceinline__ void bf16_split(double x, uint16_t& hi, uint16_t& lo) {
-  const float f = static_cast<float>(x);
+  float f = static_cast<float>(x);
+  asm("" : "+v"(f));
   hi = bf16_rne(f);
   lo = bf16_rne(f - bf16_as_f32(hi));
 }
