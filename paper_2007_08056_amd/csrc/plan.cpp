@@ -443,6 +443,16 @@ int make_plan(const char* einsum, const symt_group* group, const symt_tensor* u,
   // workspace planes take a zero pad up to a multiple of 8 (the standalone
   // aligned layouts keep K unpadded)
   p->kpad = compute == SYMT_COMPUTE_BF16X3 ? (p->gk + 7) / 8 * 8 : p->gk;
+  // ... and up to a multiple of 32 where a wide tile multiplies them (32-deep
+  // K-steps), if that adds at most an eighth of K
+  if (compute == SYMT_COMPUTE_BF16X3 && p->kpad % 32 != 0 && p->nq > 0 && p->M > 0 && p->gn > 0) {
+    const char* tile_env = std::getenv("SYMT_GEMM_TILE");
+    const std::string tile = tile_env ? tile_env : "";
+    const int64_t k32 = (p->gk + 31) / 32 * 32;
+    const bool wide = tile.empty() ? bf16x3_wide_tile(p->nq, p->M, p->gn) >= 0
+                                   : tile == "bw256x256s2" || tile == "bw256x128s3";
+    if (wide && 8 * (k32 - p->gk) <= p->gk) p->kpad = k32;
+  }
   if (p->M > INT32_MAX || p->gn > INT32_MAX || p->gk > INT32_MAX)
     return fail(err, SYMT_EUNSUPPORTED, "aligned matrix dimension above 2^31-1");
   p->flops = 2.0 * static_cast<double>(p->nq) * static_cast<double>(p->M) * static_cast<double>(p->gk) *

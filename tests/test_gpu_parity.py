@@ -824,6 +824,36 @@ def test_wide_split_bf16_reads_u_in_place(P, case, wdt, monkeypatch):
     assert np.all(np.abs(w64 - ref) <= H.bound_factor("bf16x3", k) * absref + extra * np.abs(ref) + 1e-300)
 
 
+@pytest.mark.parametrize("steps", [False, True])
+@pytest.mark.parametrize("tile", ["bw256x256s2", "bw256x128s3"])
+def test_wide_split_bf16_pads_k_to_whole_steps(P, steps, tile, monkeypatch):
+    """K = 280 on a wide split-bf16 tile: the planes take a zero pad to 288 (whole
+    32-deep K-steps, interleaved) instead of leaving the wide tiles out; the
+    U-aligned-first and three-step paths give the same bits, within the
+    oracle's bound."""
+    sub, orders, cu, cv, du, dv = "ak,kb->ab", (5,), "+-", "++", (300, 280), (280, 260)
+    monkeypatch.setenv("SYMT_GEMM_TILE", tile)
+    monkeypatch.delenv("SYMT_BF16_IL", raising=False)
+    rng = np.random.default_rng(280 + len(tile))
+    g = O.Group(orders)
+    su = O.Sym.make(cu, int(rng.integers(g.size)), du, g)
+    sv = O.Sym.make(cv, int(rng.integers(g.size)), dv, g)
+    say(f"wide split-bf16 K pad {sub} tile={tile} steps={steps}")
+    u = _sym_tensor(P, rng.standard_normal(su.reduced_shape()), su, torch.float64)
+    v = _sym_tensor(P, rng.standard_normal(sv.reduced_shape()), sv, torch.float64)
+    assert P.plan(sub, u, v, "bf16x3").k == 280
+    w = P.output_like(sub, u, v, dtype=torch.float64)
+    P.contract_into(sub, u, v, w, "bf16x3", steps=steps)
+    w_other = P.output_like(sub, u, v, dtype=torch.float64)
+    P.contract_into(sub, u, v, w_other, "bf16x3", steps=not steps)
+    assert torch.equal(w.data, w_other.data)
+    U64, V64 = H.to_np(u.data), H.to_np(v.data)
+    ref, _ = O.contract_blocks(sub, U64, su, V64, sv)
+    absref, _ = O.contract_blocks(sub, np.abs(U64), su, np.abs(V64), sv)
+    k = H.contracted_extent(sub, su)
+    assert np.all(np.abs(H.to_np(w.data) - ref) <= H.bound_factor("bf16x3", k) * absref + 1e-300)
+
+
 # V read in place: contracted modes first in V, in U's K order; K runs of 32
 # rows; V's trailing output run a multiple of 16 bytes (f64; the last case's run
 # of 6 is not for f32)
