@@ -174,10 +174,16 @@ def time_workload(P, SG, wl, compute, steps, warmup, grad=False, cplx=False):
 
     def step():
         cur = dict(t)
+        if grad:
+            # each step's gradients are its own (as a training step that clears
+            # them to None): no add of the previous step's into them
+            for x in t.values():
+                x.data.grad = None
         for st in wl.steps:
             cur[st.w] = P.einsum(st.einsum, cur[st.u], cur[st.v], compute)
         if grad:
-            (cur[wl.output].data * cur["R"].data).sum().backward()
+            # L = <E', R> as one dot product (its backward: one scaled copy of R)
+            torch.dot(cur[wl.output].data.reshape(-1), cur["R"].data.reshape(-1)).backward()
 
     def run(n):
         torch.cuda.synchronize()
