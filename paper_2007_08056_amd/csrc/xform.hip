@@ -240,29 +240,6 @@ __global__ __launch_bounds__(256) void k_xform_transpose(const Tin* __restrict__
         store_vec<OUT, 1>(dst, da + b_dst[j], p.plane, v, p.il);
       }
     }
-  } else if constexpr (OUT == 2) {
-    // bf16 planes: two destination-adjacent B elements per lane where they nest
-    // (32 lanes along B, 8 rows of A at a time), one 4-byte store per plane
-    const int xp = 2 * (t & 31), yp = t >> 5;
-    if (xp < nb) {
-      const bool two = xp + 1 < nb;
-      const bool pair = two && b_dst[xp + 1] == b_dst[xp] + 1 && (p.plane & 1) == 0;
-      const int64_t d0 = dof + b_dst[xp], d1 = dof + (two ? b_dst[xp + 1] : 0);
-      for (int j = yp; j < na; j += 8) {
-        const int64_t d = d0 + a_dst[j];
-        if (pair && (d & 1) == 0) {
-          const double v[2] = {tile[xp][j], tile[xp + 1][j]};
-          store_vec<OUT, 2>(dst, d, p.plane, v, p.il);
-        } else {
-          const double v0[1] = {tile[xp][j]};
-          store_vec<OUT, 1>(dst, d, p.plane, v0, p.il);
-          if (two) {
-            const double v1[1] = {tile[xp + 1][j]};
-            store_vec<OUT, 1>(dst, d1 + a_dst[j], p.plane, v1, p.il);
-          }
-        }
-      }
-    }
   } else if (x < nb) {
     const int64_t dx = dof + b_dst[x];
     for (int j = y; j < na; j += 4) {
