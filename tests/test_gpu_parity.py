@@ -1215,6 +1215,33 @@ def test_charge_tables_fused_path_and_gradient(P):
     assert H.rel_err(H.to_np(vd.grad), gv_ref) <= 1e-12
 
 
+@pytest.mark.parametrize("tile", ["bw256x256s2", "bw256x128s3"])
+def test_charge_tables_on_wide_split_bf16_tiles(P, tile, monkeypatch):
+    """Charge tables with the wide split-bf16 tiles: U (binary32) read in place on the
+    256 x 256 tile, or aligned onto interleaved planes on the 256 x 128 one; the same
+    bits as the three-step path, within the oracle's bound."""
+    monkeypatch.setenv("SYMT_GEMM_TILE", tile)
+    rng = np.random.default_rng(47 + len(tile))
+    g = O.Group((8,))
+    sub = "abcd,cdij->abij"
+    su0 = O.Sym.make("++--", 3, (3, 5, 2, 2), g)
+    sv0 = O.Sym.make("++--", 5, (2, 2, 4, 9), g)
+    su, sv = _with_tables(rng, sub, su0, sv0)
+    say(f"charge tables on wide split-bf16 tile {tile}")
+    Ru, Rv = rng.standard_normal(su.reduced_shape()), rng.standard_normal(sv.reduced_shape())
+    u, v = _sym_tensor(P, Ru, su, torch.float32), _sym_tensor(P, Rv, sv, torch.float32)
+    w = P.output_like(sub, u, v, dtype=torch.float64)
+    P.contract_into(sub, u, v, w, "bf16x3")
+    ws = P.output_like(sub, u, v, dtype=torch.float64)
+    P.contract_into(sub, u, v, ws, "bf16x3", steps=True)
+    assert torch.equal(w.data, ws.data)
+    U64, V64 = H.to_np(u.data).astype(np.float64), H.to_np(v.data).astype(np.float64)
+    ref, _ = O.contract_blocks(sub, U64, su, V64, sv)
+    absref, _ = O.contract_blocks(sub, np.abs(U64), su, np.abs(V64), sv)
+    k = H.contracted_extent(sub, su)
+    assert np.all(np.abs(H.to_np(w.data) - ref) <= H.bound_factor("bf16x3", k) * absref + 1e-300)
+
+
 def test_charge_tables_rejected_by_standalone_align(P):
     rng = np.random.default_rng(3)
     g = O.Group((3,))
